@@ -1,0 +1,117 @@
+"""Element matrices, load vectors, global assembly and essential BCs (oracle; test infrastructure only).
+
+Definitions followed:
+
+* Diffusion (stiffness) entries A_ij = int grad phi_j . grad phi_i, with a
+  coefficient kappa inside the integral -- "Finite Element Abstractions",
+  eq. (abstract forms) and the matrix definition before eq. (linear system).
+  Mapped to the reference element with quadrature (the same change of
+  variables as the mass-matrix equations of "High-Order Partial Assembly"):
+      K_E[i, j] = sum_k alpha_k kappa_k det J_k (J_k^{-T} ghat_i) . (J_k^{-T} ghat_j).
+  The quadrature-point factor alpha kappa det J J^{-1} J^{-T} is computed with a
+  matrix inverse (numpy.linalg.inv), not with the adjugate form of the paper's
+  2D setup listing ("GPU Acceleration"), which is what the test pins it against.
+* Mass M_E = B^t D_E B, (D_E)_kk = alpha_k det J(xhat_k) rho(Phi(xhat_k)) --
+  "High-Order Partial Assembly", mass-matrix equations.
+* Load b_i = int f phi_i -- eq. (abstract forms), the b_i definition.
+* Global operator A = sum_E G_E^t A_E G_E (dense element matrices scattered into
+  a sparse matrix; "Operator Decomposition" with P = identity).
+* Essential BC: the "further modifications" of FormLinearSystem ("Finite Element
+  Linear Systems") are not spelled out; the reading used is symmetric elimination:
+  zero the boundary rows and columns, unit diagonal, b_G = g, b_I -= A_IG g.
+
+Pins (tests/test_oracle_forms.py): closed-form 1D element matrices on affine
+cubes, volume = 1^T M 1, K 1 = 0, SPD with nullity 1 before BC, the paper's 2D
+setup formula, linear patch test, O(h^{p+1}) L2 convergence.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .basis import tensor_basis, tensor_points, tensor_weights
+from .geometry import map_points
+from .quadrature import gauss_legendre, gauss_lobatto
+
+
+def quadrature_points(q1d):
+    """Tensor Gauss-Legendre points [Q^3, 3] and weights [Q^3] on [0,1]^3 (x fastest)."""
+    x, w = gauss_legendre(q1d)
+    return tensor_points(x), tensor_weights(w)
+
+
+def qpoint_diffusion_operator(J, weight, coeff=1.0):
+    """alpha * coeff * det J * J^{-1} J^{-T} for Jacobians J[..., d, d] (any d)."""
+    J = np.asarray(J, dtype=np.float64)
+    Jinv = np.linalg.inv(J)
+    det = np.linalg.det(J)
+    scale = np.asarray(weight) * np.asarray(coeff) * det
+    return scale[..., None, None] * np.einsum("...ab,...cb->...ac", Jinv, Jinv)
+
+
+def _jacobians(mesh, q1d):
+    pts, w = quadrature_points(q1d)
+    x, J = map_points(mesh, pts)
+    det = np.linalg.det(J)
+    if np.any(det <= 0.0):
+        bad = int(np.nonzero((det <= 0.0).any(axis=1))[0][0])
+        raise ValueError(f"non-positive Jacobian determinant in element {bad}")
+    return pts, w, x, J, det
+
+
+def element_stiffness(mesh, p, q1d, coeff=None):
+    """Dense element diffusion matrices [E, D^3, D^3]; coeff is None, scalar or [E, Q^3]."""
+    pts, w, _, J, _ = _jacobians(mesh, q1d)
+    _, grad = tensor_basis(gauss_lobatto(p + 1), pts)                  # [3, Q^3, D^3]
+    c = 1.0 if coeff is None else coeff
+    Dq = qpoint_diffusion_operator(J, w[None, :], c)                   # [E, Q^3, 3, 3]
+    return np.einsum("aqi,eqab,bqj->eij", grad, Dq, grad, optimize=True)
+
+
+def element_mass(mesh, p, q1d, coeff=None):
+    """Dense element mass matrices [E, D^3, D^3]."""
+    pts, w, _, _, det = _jacobians(mesh, q1d)
+    val, _ = tensor_basis(gauss_lobatto(p + 1), pts)                   # [Q^3, D^3]
+    c = 1.0 if coeff is None else coeff
+    d = w[None, :] * det * c
+    return np.einsum("qi,eq,qj->eij", val, d, val, optimize=True)
+
+
+def element_load(mesh, p, q1d, f):
+    """Element load vectors [E, D^3] for b_i = int f phi_i.
+
+    ``f`` is a callable on physical points [E, Q^3, 3] or an array [E, Q^3].
+    """
+    pts, w, x, _, det = _jacobians(mesh, q1d)
+    val, _ = tensor_basis(gauss_lobatto(p + 1), pts)
+    fq = f(x) if callable(f) else np.asarray(f)
+    return np.einsum("qi,eq->ei", val, w[None, :] * det * fq)
+
+
+def assemble(space, elmats):
+    """Global CSR sum_E G_E^t A_E G_E (duplicates summed)."""
+    E, nd, _ = elmats.shape
+    rows = np.repeat(space.elem_dofs, nd, axis=1).ravel()
+    cols = np.tile(space.elem_dofs, (1, nd)).ravel()
+    A = sp.coo_matrix((elmats.ravel(), (rows, cols)), shape=(space.ndofs, space.ndofs))
+    return A.tocsr()
+
+
+def assemble_vector(space, elvecs):
+    """Global vector sum_E G_E^t v_E."""
+    return np.bincount(space.elem_dofs.ravel(), weights=np.asarray(elvecs).ravel(),
+                       minlength=space.ndofs)
+
+
+def constrain(A, b, boundary_mask, g=None):
+    """Symmetric elimination of essential dofs with a unit diagonal.
+
+    Returns (A_c, b_c) with A_c[G, :] = A_c[:, G] = 0 except A_c[G, G] = I,
+    b_c[G] = g and b_c[I] = b[I] - A[I, G] g.
+    """
+    n = A.shape[0]
+    bmask = np.asarray(boundary_mask, dtype=bool)
+    gvec = np.zeros(n) if g is None else np.asarray(g, dtype=np.float64)
+    keep = sp.diags((~bmask).astype(np.float64))
+    Ac = (keep @ A @ keep + sp.diags(bmask.astype(np.float64))).tocsr()
+    bc = np.asarray(b, dtype=np.float64) - A @ np.where(bmask, gvec, 0.0)
+    bc[bmask] = gvec[bmask]
+    return Ac, bc

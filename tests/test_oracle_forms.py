@@ -1,0 +1,234 @@
+"""Pins for the oracle's element matrices, assembly and boundary treatment (CPU only).
+
+What fixes the expected values here is not the oracle's own code:
+* exact 1D integrals of Lagrange polynomials built from a Vandermonde solve and
+  integrated symbolically (numpy.polynomial), tensorised with Kronecker products;
+* textbook 1D P1/P2 element matrices;
+* the energy identity for linear functions, u^T K v = (c . d) * vol(E), which
+  holds on any element whose map lies in the discrete space;
+* the paper's 2D diffusion setup formula (adjugate form, "GPU Acceleration");
+* volume = 1^T M 1 = 1 on the unit cube, K 1 = 0, the spectrum by brute force.
+A few mutation tests show that plausible mistakes fail these pins.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle
+import synth
+from oracle import forms
+from oracle.forms import assemble_vector
+from oracle.quadrature import gauss_lobatto
+
+
+def _lagrange_polys(nodes):
+    """Lagrange polynomials via a Vandermonde solve (independent of the oracle)."""
+    n = len(nodes)
+    V = np.vander(nodes, n, increasing=True)
+    C = np.linalg.solve(V, np.eye(n))
+    return [np.polynomial.Polynomial(C[:, j]) for j in range(n)]
+
+
+def _exact_1d(p):
+    """Exact 1D matrices on [0,1]: mass, stiffness, and C[i,j] = int phi_i' phi_j."""
+    L = _lagrange_polys(gauss_lobatto(p + 1))
+    def integ(poly):
+        P = poly.integ()
+        return P(1.0) - P(0.0)
+    M = np.array([[integ(a * b) for b in L] for a in L])
+    K = np.array([[integ(a.deriv() * b.deriv()) for b in L] for a in L])
+    C = np.array([[integ(a.deriv() * b) for b in L] for a in L])
+    return M, K, C
+
+
+def _kron3(t1, t2, t3):
+    # lexicographic dof index i1 + D*(i2 + D*i3): the first axis varies fastest
+    return np.kron(t3, np.kron(t2, t1))
+
+
+def _single_element(A=None, c=None):
+    verts = synth.HEX_CORNERS.astype(np.float64)
+    if A is not None:
+        verts = verts @ np.asarray(A).T + (0 if c is None else np.asarray(c))
+    return {"vertices": verts, "hex": np.arange(8)[None, :], "geom_order": 1, "geom_nodes": None}
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_unit_cube_element_matrices_exact(p):
+    M1, K1, _ = _exact_1d(p)
+    mesh = _single_element()
+    Me = forms.element_mass(mesh, p, p + 2)[0]
+    Ke = forms.element_stiffness(mesh, p, p + 2)[0]
+    np.testing.assert_allclose(Me, _kron3(M1, M1, M1), atol=1e-14)
+    expected_K = _kron3(K1, M1, M1) + _kron3(M1, K1, M1) + _kron3(M1, M1, K1)
+    np.testing.assert_allclose(Ke, expected_K, atol=1e-13)
+
+
+def test_textbook_1d_matrices():
+    M1, K1, _ = _exact_1d(1)
+    np.testing.assert_allclose(M1, [[1 / 3, 1 / 6], [1 / 6, 1 / 3]], atol=1e-15)
+    np.testing.assert_allclose(K1, [[1, -1], [-1, 1]], atol=1e-14)
+    M2, K2, _ = _exact_1d(2)
+    np.testing.assert_allclose(M2, np.array([[4, 2, -1], [2, 16, 2], [-1, 2, 4]]) / 30, atol=1e-14)
+    np.testing.assert_allclose(K2, np.array([[7, -8, 1], [-8, 16, -8], [1, -8, 7]]) / 3, atol=1e-13)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_affine_element_stiffness_exact(p):
+    """General affine map: K = det A * sum_ab (A^-1 A^-T)_ab S_ab, S from exact 1D integrals."""
+    rng = np.random.default_rng(3 + p)
+    A = np.eye(3) + 0.3 * rng.normal(size=(3, 3))
+    assert np.linalg.det(A) > 0
+    M1, K1, C1 = _exact_1d(p)
+    Ainv = np.linalg.inv(A)
+    G = Ainv @ Ainv.T
+    Kexp = np.zeros(((p + 1) ** 3,) * 2)
+    for a in range(3):
+        for b in range(3):
+            t = []
+            for d in range(3):
+                if d == a and d == b:
+                    t.append(K1)
+                elif d == a:
+                    t.append(C1)
+                elif d == b:
+                    t.append(C1.T)
+                else:
+                    t.append(M1)
+            Kexp += G[a, b] * _kron3(*t)
+    Kexp *= np.linalg.det(A)
+    Ke = forms.element_stiffness(_single_element(A, [0.2, -0.1, 0.4]), p, p + 2)[0]
+    np.testing.assert_allclose(Ke, Kexp, atol=1e-12 * np.abs(Kexp).max())
+
+
+def _linear_energy_check(mesh, p, q1d, coeff=None):
+    s = oracle.H1Space(mesh, p)
+    K = oracle.assemble(s, forms.element_stiffness(mesh, p, q1d, coeff))
+    pts, w = forms.quadrature_points(q1d)
+    _, J = oracle.map_points(mesh, pts)
+    wdet = w[None, :] * np.linalg.det(J) * (1.0 if coeff is None else coeff)
+    X = s.dof_coordinates()
+    rng = np.random.default_rng(11)
+    c, d = rng.normal(size=3), rng.normal(size=3)
+    u, v = X @ c, X @ d
+    return v @ (K @ u), np.dot(c, d) * wdet.sum()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_linear_energy_identity_jittered(p):
+    mesh = synth.hex_lattice(3, 0.1, seed=2)
+    got, want = _linear_energy_check(mesh, p, p + 2)
+    assert abs(got - want) < 1e-12 * abs(want)
+
+
+def test_linear_energy_identity_with_coefficient():
+    mesh = synth.hex_lattice(2, 0.1, seed=4)
+    kappa = synth.lognormal_iid(8, 5, 1.0, seed=3)
+    got, want = _linear_energy_check(mesh, 3, 5, kappa)
+    assert abs(got - want) < 1e-12 * abs(want)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_linear_energy_identity_q2_warped(p):
+    mesh = synth.q2_warped_lattice(2, 0.05)
+    got, want = _linear_energy_check(mesh, p, p + 2)
+    assert abs(got - want) < 1e-12 * abs(want)
+
+
+def test_paper_2d_setup_formula():
+    """2D quadrature-point operator vs the adjugate form of the paper's listing."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        J = np.eye(2) + 0.4 * rng.normal(size=(2, 2))
+        if np.linalg.det(J) <= 0:
+            J[:, 0] *= -1
+        W, alpha = rng.uniform(0.1, 1.0), rng.uniform(0.5, 2.0)
+        J11, J21, J12, J22 = J[0, 0], J[1, 0], J[0, 1], J[1, 1]
+        c = alpha * W / (J11 * J22 - J21 * J12)
+        Y0 = c * (J12 * J12 + J22 * J22)
+        Y1 = -c * (J12 * J11 + J22 * J21)
+        Y2 = c * (J11 * J11 + J21 * J21)
+        D = forms.qpoint_diffusion_operator(J, W, alpha)
+        np.testing.assert_allclose([D[0, 0], D[0, 1], D[1, 0], D[1, 1]], [Y0, Y1, Y1, Y2], rtol=1e-13)
+
+
+@pytest.mark.parametrize("mesh_kind", ["jitter", "q2"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_volume_and_constants(mesh_kind, p):
+    mesh = synth.hex_lattice(3, 0.1, seed=1) if mesh_kind == "jitter" else synth.q2_warped_lattice(3)
+    q1d = max(p + 2, 4)
+    s = oracle.H1Space(mesh, p)
+    M = oracle.assemble(s, forms.element_mass(mesh, p, q1d))
+    K = oracle.assemble(s, forms.element_stiffness(mesh, p, q1d))
+    one = np.ones(s.ndofs)
+    assert abs(one @ (M @ one) - 1.0) < 1e-13
+    assert np.abs(K @ one).max() < 1e-12
+    # load of f = 1 integrates to the volume; of f = x to 1/2
+    b1 = assemble_vector(s, forms.element_load(mesh, p, q1d, lambda x: np.ones(x.shape[:-1])))
+    bx = assemble_vector(s, forms.element_load(mesh, p, q1d, lambda x: x[..., 0]))
+    assert abs(b1.sum() - 1.0) < 1e-13
+    assert abs(bx.sum() - 0.5) < 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_spectrum_brute_force(p):
+    mesh = synth.hex_lattice(2, 0.1, seed=9)
+    s = oracle.H1Space(mesh, p)
+    K = oracle.assemble(s, forms.element_stiffness(mesh, p, p + 2)).toarray()
+    M = oracle.assemble(s, forms.element_mass(mesh, p, p + 2)).toarray()
+    assert np.abs(K - K.T).max() < 1e-13
+    ev = np.linalg.eigvalsh(K)
+    assert abs(ev[0]) < 1e-12 * ev[-1] and ev[1] > 1e-6 * ev[-1]      # nullity exactly 1
+    assert np.linalg.eigvalsh(M)[0] > 0
+    Kc, _ = oracle.constrain(oracle.assemble(s, forms.element_stiffness(mesh, p, p + 2)),
+                             np.zeros(s.ndofs), s.boundary)
+    assert np.linalg.eigvalsh(Kc.toarray())[0] > 0
+
+
+@pytest.mark.parametrize("case", [("jitter", 1), ("jitter", 2), ("q2", 2), ("q2", 3)])
+def test_linear_patch(case):
+    kind, p = case
+    mesh = synth.hex_lattice(3, 0.1, seed=6) if kind == "jitter" else synth.q2_warped_lattice(2)
+    s = oracle.H1Space(mesh, p)
+    K = oracle.assemble(s, forms.element_stiffness(mesh, p, p + 2))
+    X = s.dof_coordinates()
+    g = synth.linear_patch(X)
+    Kc, bc = oracle.constrain(K, np.zeros(s.ndofs), s.boundary, g)
+    x = spla.spsolve(Kc.tocsc(), bc)
+    assert np.abs(x - g).max() < 1e-11
+
+
+@pytest.mark.parametrize("p,ns", [(1, (4, 8, 16)), (2, (2, 4, 8)), (3, (2, 4, 8))])
+def test_l2_convergence_rate(p, ns):
+    errs = []
+    for n in ns:
+        mesh = synth.hex_lattice(n, 0.1, seed=7)
+        s = oracle.H1Space(mesh, p)
+        K = oracle.assemble(s, forms.element_stiffness(mesh, p, p + 2))
+        b = assemble_vector(s, forms.element_load(mesh, p, p + 2, synth.sine_source))
+        Kc, bc = oracle.constrain(K, b, s.boundary)
+        x = spla.spsolve(Kc.tocsc(), bc)
+        errs.append(oracle.l2_error(s, x, synth.sine_solution))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert abs(rates[-1] - (p + 1)) < 0.3, rates
+
+
+# ---- mutation tests: plausible mistakes must fail the pins above ----------------
+
+def test_mutant_transposed_metric_fails(monkeypatch):
+    orig = forms.qpoint_diffusion_operator
+
+    def transposed(J, weight, coeff=1.0):
+        return orig(np.swapaxes(J, -1, -2), weight, coeff)
+    monkeypatch.setattr(forms, "qpoint_diffusion_operator", transposed)
+    mesh = synth.hex_lattice(2, 0.1, seed=2)
+    got, want = _linear_energy_check(mesh, 2, 4)
+    assert abs(got - want) > 1e-6 * abs(want)
+
+
+def test_mutant_short_quadrature_fails():
+    # integrating the unit-cube stiffness with too few points breaks the exact pin
+    M1, K1, _ = _exact_1d(3)
+    Ke = forms.element_stiffness(_single_element(), 3, 2)[0]
+    expected_K = _kron3(K1, M1, M1) + _kron3(M1, K1, M1) + _kron3(M1, M1, K1)
+    assert np.abs(Ke - expected_K).max() > 1e-6
