@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the partial-assembly diffusion apply (FP64) on one MI355X.
+
+Workload (the scale sweep): unit-cube hexahedral lattices sized to ~1e7 dofs for
+each order p = 1..8, interior vertices jittered by up to 5% of h (seed 2),
+trilinear geometry, coefficient kappa = exp(N(0,1)) i.i.d. per element and
+quadrature point (seed 3), Gauss rule with q1d = p + 2, essential dofs on the
+whole boundary.  One step = one diffusion apply y = A x at every order of the
+sweep; `value` = sum_p ndofs_p / sum_p t_p in GDOF/s (every dof, boundary
+included).  The mass apply and Jacobi-PCG time-to-1e-8 are reported beside it.
+All inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6
+
+METRIC = "PA diffusion apply GDOF/s (p=1–8); CG time-to-1e-8, chosen vs plain FP64"
+
+
+def lattice_size(p: int, target_dofs: float) -> int:
+    return max(1, int(round((target_dofs ** (1.0 / 3.0) - 1.0) / p)))
+
+
+def algorithmic_bytes(kind: str, p: int, ne: int, ndofs: int) -> int:
+    """x read + y written + stored D + int32 element->dof map, per apply."""
+    q = p + 2
+    d_bytes = (48 if kind == "diffusion" else 8) * ne * q ** 3
+    return 8 * ndofs + 8 * ndofs + d_bytes + 4 * ne * (p + 1) ** 3
+
+
+def algorithmic_flops(kind: str, p: int, ne: int) -> int:
+    D, Q = p + 1, p + 2
+    if kind == "diffusion":
+        per = 2 * (2 * (2 * D ** 3 * Q + 3 * D * D * Q * Q + 3 * D * Q ** 3)) + 18 * Q ** 3
+    else:
+        per = 2 * (2 * (D ** 3 * Q + D * D * Q * Q + D * Q ** 3)) + Q ** 3
+    return per * ne
+
+
+def setup_problem(P, torch, p, target, scatter):
+    import synth
+    n = lattice_size(p, target)
+    mesh = synth.hex_lattice(n, 0.05, seed=2)
+    ne = mesh["hex"].shape[0]
+    kappa = torch.as_tensor(synth.lognormal_iid(ne, p + 2, 1.0, seed=3), device="cuda")
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    del mesh
+    qd = S.qdata(P.DIFFUSION, coeff=kappa)
+    qm = S.qdata(P.MASS, coeff=kappa)
+    del kappa
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(100 + p)
+    x = torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=gen)
+    return {
+        "p": p, "n": n, "space": S, "ne": S.nelem, "ndofs": S.ndofs,
+        "diff": P.Operator(S, P.DIFFUSION, qd, scatter=scatter),
+        "mass": P.Operator(S, P.MASS, qm, scatter=scatter),
+        "x": x, "y": torch.empty_like(x),
+    }
+
+
+def time_applies(torch, probs, kind, steps, warmup):
+    """Per-order mean apply time (s) from HIP events on the launch stream."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        for pr in probs:
+            pr[kind].apply(pr["x"], pr["y"])
+    torch.cuda.synchronize()
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in probs] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        for i, pr in enumerate(probs):
+            evs[s][i][0].record(stream)
+            pr[kind].apply(pr["x"], pr["y"])
+            evs[s][i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(steps)) / steps / 1e3
+           for i in range(len(probs))]
+    return per, wall
+
+
+def cpu_baseline(orders, budget_s=20.0):
+    """The oracle's apply (assembled CSR matvec) on reduced meshes of the same recipe."""
+    import numpy as np
+
+    import oracle
+    import synth
+    from oracle import forms
+    t_start = time.perf_counter()
+    sizes = {p: (2e5 if p <= 2 else 1e5 if p <= 4 else 4e4) for p in orders}
+    tot_n, tot_t, parts, t_asm = 0.0, 0.0, [], 0.0
+    per_order_budget = budget_s / max(1, len(orders))
+    for p in orders:
+        n = lattice_size(p, sizes[p])
+        mesh = synth.hex_lattice(n, 0.05, seed=2)
+        kappa = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 1.0, seed=3)
+        ta = time.perf_counter()
+        sp = oracle.H1Space(mesh, p)
+        K = oracle.assemble(sp, forms.element_stiffness(mesh, p, p + 2, kappa))
+        Kc, _ = oracle.constrain(K, np.zeros(sp.ndofs), sp.boundary)
+        t_asm += time.perf_counter() - ta
+        x = np.random.default_rng(p).normal(size=sp.ndofs)
+        y = Kc @ x
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            y = Kc @ x
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > min(1.0, per_order_budget / 4) and reps >= 3:
+                break
+        t_apply = el / reps
+        tot_n += sp.ndofs
+        tot_t += t_apply
+        parts.append(f"p{p}:{sp.ndofs}dofs:{sp.ndofs / t_apply / 1e9:.4f}GDOF/s")
+        del y
+    return {
+        "value": round(tot_n / tot_t / 1e9, 5), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+        "sample": ("oracle CSR matvec (scipy, single thread) of the assembled constrained "
+                   "diffusion matrix, one apply per order, on reduced lattices of the same "
+                   "recipe: " + ", ".join(parts) +
+                   f"; oracle assembly {t_asm:.1f}s; leg total "
+                   f"{time.perf_counter() - t_start:.1f}s on {os.cpu_count()} host cpus"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--orders", default="1,2,3,4,5,6,7,8")
+    ap.add_argument("--target-dofs", type=float, default=1e7)
+    ap.add_argument("--scatter", choices=["atomic", "evec"], default="atomic")
+    ap.add_argument("--cg-orders", default="3", help="orders for the Jacobi-PCG solve ('' = none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mass", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1911_09220_amd import pafem as P
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    orders = [int(v) for v in args.orders.split(",") if v]
+    t_setup = time.perf_counter()
+    probs = []
+    for p in orders:
+        probs.append(setup_problem(P, torch, p, args.target_dofs, args.scatter))
+        print(f"# setup p={p}: {probs[-1]['ndofs']} dofs, {probs[-1]['ne']} elements",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+
+    per, wall = time_applies(torch, probs, "diff", args.steps, args.warmup)
+    total_dofs = sum(pr["ndofs"] for pr in probs)
+    step_s = sum(per)
+    value = total_dofs / step_s / 1e9
+    per_p = {}
+    for pr, t in zip(probs, per):
+        by = algorithmic_bytes("diffusion", pr["p"], pr["ne"], pr["ndofs"])
+        fl = algorithmic_flops("diffusion", pr["p"], pr["ne"])
+        per_p[str(pr["p"])] = {
+            "ndofs": pr["ndofs"], "elements": pr["ne"], "ms": round(t * 1e3, 4),
+            "gdofs": round(pr["ndofs"] / t / 1e9, 3),
+            "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4),
+            "fp64_frac": round(fl / t / 1e12 / FP64_PEAK_TFLOPS, 4),
+        }
+    mass = {}
+    if not args.no_mass:
+        mper, _ = time_applies(torch, probs, "mass", max(3, args.steps // 2), 1)
+        for pr, t in zip(probs, mper):
+            by = algorithmic_bytes("mass", pr["p"], pr["ne"], pr["ndofs"])
+            mass[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
+                                  "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
+
+    # dominant kernel: the order whose apply takes the longest
+    k = max(range(len(probs)), key=lambda i: per[i])
+    dom = probs[k]
+    by = algorithmic_bytes("diffusion", dom["p"], dom["ne"], dom["ndofs"])
+    achieved = by / per[k] / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"pa_apply_kernel diffusion p={dom['p']} q1d={dom['p'] + 2} f64 "
+                          f"({args.scatter} scatter, with its y-init kernel)",
+                "bytes_per_launch": by}
+
+    cg = {}
+    for p in [int(v) for v in args.cg_orders.split(",") if v]:
+        pr = next((q for q in probs if q["p"] == p), None)
+        if pr is None:
+            continue
+        b = pr["space"].linear_form(P.SOURCE_SINE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        diag = pr["diff"].diagonal()
+        torch.cuda.synchronize()
+        t_diag = time.perf_counter() - t0
+        xs, info = pr["diff"].pcg(b, diag=diag, rel_tol=1e-8, max_iter=20000, history=False)
+        cg[str(p)] = {"solver": "jacobi-pcg f64", "iters": info["iters"],
+                      "seconds": round(info["seconds"], 4), "status": info["status"],
+                      "true_rel_res": info["true_rel_res"], "diag_seconds": round(t_diag, 4),
+                      "ms_per_iter": round(1e3 * info["seconds"] / max(1, info["iters"]), 4)}
+        del xs, b, diag
+
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GDOF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_s * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"scale sweep: unit-cube hex lattices of ~{args.target_dofs:.0e} "
+                               f"dofs for p={args.orders}, 5% vertex jitter, lognormal kappa "
+                               f"(sigma=1) per quadrature point, q1d=p+2, Dirichlet boundary",
+                   "orders": orders, "scatter": args.scatter, "per_p": per_p,
+                   "mass_apply": mass, "setup_seconds": round(t_setup, 1),
+                   "timed_wall_seconds": round(wall, 4)},
+        "roofline": roofline,
+        "cg_time_to_1e-8": cg,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(orders)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

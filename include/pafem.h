@@ -1,0 +1,237 @@
+/*
+ * pafem.h -- C ABI of the MI355X partial-assembly finite element library.
+ *
+ * The library computes the matrix-free ("partially assembled") action of H1
+ * diffusion and mass operators on unstructured hexahedral meshes,
+ *      y = G^t B^t D B G x,
+ * where G is the element restriction (global dofs -> element dofs), B the
+ * basis evaluation at quadrature points (applied by sum factorization with 1D
+ * tables), and D the stored quadrature-point operator.  Notation and the
+ * factorization follow the MFEM paper (arXiv:1911.09220), sections
+ * "Operator Decomposition" and "High-Order Partial Assembly"; the problem is
+ * the weak form of "Finite Element Abstractions": find u_h in V_h with
+ * a(u_h, v_h) = l(v_h) for all v_h, a(u,v) = int kappa grad u . grad v,
+ * l(v) = int f v, with essential (Dirichlet) boundary conditions imposed as
+ * in FormLinearSystem ("Finite Element Linear Systems").
+ *
+ * Conventions (every call):
+ *  - Return value: PAFEM_OK (0) or a negative status; a message describing the
+ *    last error of the calling thread is available from pafem_last_error().
+ *    No C++ exception crosses this boundary.
+ *  - Handles (mesh, space, op) are host objects owned by the library; release
+ *    them with the matching *_destroy call.  Destroying a space or mesh that an
+ *    op still references is undefined.
+ *  - "device" pointers are HIP device memory owned by the caller (typically
+ *    torch tensors); the library never frees caller memory and never
+ *    allocates device memory itself.  Scratch memory comes from caller
+ *    workspaces whose size is queried first.
+ *  - stream is a hipStream_t (NULL = default stream).  Calls are asynchronous
+ *    on that stream unless marked SYNCHRONOUS.  An asynchronous HIP failure is
+ *    reported as PAFEM_EHIP by a later synchronous call.
+ *  - Reference element [0,1]^3.  Element dofs are lexicographic
+ *    i = i1 + D1*(i2 + D1*i3), D1 = p+1, nodes at Gauss-Lobatto points.
+ *    Quadrature points are tensor Gauss-Legendre points, lexicographic
+ *    q = q1 + Q*(q2 + Q*q3), Q = q1d.
+ *  - Hex connectivity: 8 vertex indices per element in the usual order, bottom
+ *    face (0,0,0) (1,0,0) (1,1,0) (0,1,0), then the top face in the same order.
+ */
+#ifndef PAFEM_H
+#define PAFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pafem_status;
+
+#define PAFEM_OK 0
+#define PAFEM_EINVAL (-1)       /* invalid argument: null pointer, bad index, bad mesh, det J <= 0 */
+#define PAFEM_ESHAPE (-2)       /* buffer or workspace too small, size mismatch */
+#define PAFEM_EUNSUPPORTED (-3) /* order / q1d / dtype / kind combination not built */
+#define PAFEM_EHIP (-4)         /* HIP runtime error (launch, copy, asynchronous fault) */
+#define PAFEM_ENOTCONV (-5)     /* solver stopped at max_iter before reaching the tolerance */
+#define PAFEM_EBREAKDOWN (-6)   /* CG breakdown: p.Ap <= 0 or a non-finite scalar */
+
+/* Operator kinds ("High-Order Partial Assembly": mass; "Finite Element
+ * Abstractions": diffusion). */
+#define PAFEM_MASS 0
+#define PAFEM_DIFFUSION 1
+
+/* Storage types. */
+#define PAFEM_F64 0
+#define PAFEM_F32 1
+#define PAFEM_BF16 2
+
+/* Space creation flags. */
+#define PAFEM_SPACE_RENUMBER 1 /* number dofs by first touch in element order (locality);
+                                  default is vertices, edges, faces, interiors */
+
+/* Operator flags. */
+#define PAFEM_OP_CONSTRAINED 1  /* eliminate essential dofs: y_b = x_b on boundary dofs and
+                                   boundary columns dropped (symmetric elimination) */
+#define PAFEM_OP_SCATTER_EVEC 2 /* G^t by writing element vectors and gathering them per dof
+                                   through the transposed element->dof map: deterministic,
+                                   needs a workspace.  Default: hardware FP atomics. */
+
+/* Built-in sources for pafem_linear_form. */
+#define PAFEM_SOURCE_ARRAY 0 /* f given at quadrature points, device [E][Q^3] f64 */
+#define PAFEM_SOURCE_CONST 1 /* f = scale */
+#define PAFEM_SOURCE_SINE 2  /* f = scale * 3 pi^2 sin(pi x) sin(pi y) sin(pi z) */
+
+/* Preconditioners for pafem_pcg_solve. */
+#define PAFEM_PRECOND_NONE 0
+#define PAFEM_PRECOND_JACOBI 1
+
+typedef struct pafem_mesh_s* pafem_mesh;
+typedef struct pafem_space_s* pafem_space;
+typedef struct pafem_op_s* pafem_op;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* pafem_last_error(void);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t pafem_version(void);
+
+/* ---------------------------------------------------------------- mesh --- */
+
+/* Conforming hexahedral mesh ("Meshes / Conforming Meshes").  Host call.
+ *  nv, xyz:        vertex count and coordinates, host [nv][3] f64 (copied).
+ *  ne, hex8:       element count and connectivity, host [ne][8] int64 (copied).
+ *  geom_order:     1 = trilinear map from the vertices; 2 = quadratic map from
+ *                  27 nodes per element (the nodal mesh description).
+ *  geom_nodes:     NULL for geom_order 1; host [ne][27][3] f64 lexicographic
+ *                  nodes at reference positions {0,1/2,1}^3 for geom_order 2.
+ * Errors: EINVAL on null pointers, nv/ne <= 0, an index outside [0,nv), or an
+ * element repeating a vertex. */
+pafem_status pafem_mesh_create_hex(int64_t nv, const double* xyz, int64_t ne,
+                                   const int64_t* hex8, int32_t geom_order,
+                                   const double* geom_nodes, pafem_mesh* out);
+void pafem_mesh_destroy(pafem_mesh mesh);
+
+/* --------------------------------------------------------------- space --- */
+
+/* Order-p H1 space with nodal Lagrange basis at Gauss-Lobatto points
+ * ("Finite Element Discretization"): builds the element->dof map G with
+ * orientation-consistent edge and face dofs, the essential (boundary) dof
+ * set -- every dof on a face that belongs to one element only -- and the
+ * transposed map used by the deterministic scatter.  Host call.
+ *  order: 1..8.  flags: PAFEM_SPACE_RENUMBER or 0.
+ * Errors: EUNSUPPORTED for order outside 1..8; EINVAL on a non-conforming mesh
+ * (a face shared by more than two elements). */
+pafem_status pafem_space_create_h1(pafem_mesh mesh, int32_t order, int32_t flags,
+                                   pafem_space* out);
+void pafem_space_destroy(pafem_space space);
+
+/* Sizes: global dofs, elements, dofs per element ((p+1)^3), essential dofs. */
+pafem_status pafem_space_info(pafem_space space, int64_t* ndofs, int64_t* nelem,
+                              int32_t* dofs_per_elem, int64_t* nbdr);
+
+/* Host copies: dof node coordinates [ndofs][3] f64; essential dof indices
+ * [nbdr] int32 ascending; element->dof map [nelem][(p+1)^3] int32. */
+pafem_status pafem_space_dof_coords(pafem_space space, double* xyz);
+pafem_status pafem_space_boundary_dofs(pafem_space space, int32_t* idx);
+pafem_status pafem_space_elem_dofs(pafem_space space, int32_t* gmap);
+
+/* Device image of the space (element->dof map, geometry nodes, transposed map,
+ * boundary mask, 1D tables).  Query the size, allocate a device buffer of at
+ * least that many bytes (256-byte aligned), then upload.  The buffer must stay
+ * alive and unmodified while the space is used.  pafem_space_upload is
+ * SYNCHRONOUS.  Errors: ESHAPE if nbytes is too small. */
+pafem_status pafem_space_device_bytes(pafem_space space, size_t* nbytes);
+pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbytes,
+                                void* stream);
+
+/* ------------------------------------------------------ quadrature data --- */
+
+/* Number of stored values of the quadrature-point operator D
+ * ("High-Order Partial Assembly": storing only D):
+ *   mass:      E * Q^3       D_q = alpha_q det J_q rho_q
+ *   diffusion: E * 6 * Q^3   D_q = alpha_q kappa_q det J_q J_q^{-1} J_q^{-T},
+ *                            symmetric, components (00,01,02,11,12,22),
+ *                            layout [E][6][Q^3].
+ * Errors: EUNSUPPORTED if q1d is not one of the built rules (q1d = p+2). */
+pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int64_t* nvalues);
+
+/* PA setup: geometric factors (Jacobian of the element map at every
+ * quadrature point) and D, written as f64 to device `qdata`.
+ *  coeff: device [E][Q^3] f64 coefficient (kappa or rho) or NULL for 1.
+ *  coeff_scale: multiplies the coefficient.
+ * SYNCHRONOUS: returns EINVAL naming the first element with det J <= 0. */
+pafem_status pafem_qdata_assemble(pafem_space space, int32_t kind, int32_t q1d,
+                                  const double* coeff, double coeff_scale,
+                                  double* qdata, void* stream);
+
+/* ------------------------------------------------------------ operator --- */
+
+/* Operator y = G^t B^t D B G x on the space, reading `qdata` (device, layout
+ * of pafem_qdata_size, f64).  flags: PAFEM_OP_* bits.  Host call; the op
+ * keeps the qdata pointer. */
+pafem_status pafem_op_create(pafem_space space, int32_t kind, int32_t q1d,
+                             const void* qdata, int32_t qdata_dtype, int32_t flags,
+                             pafem_op* out);
+void pafem_op_destroy(pafem_op op);
+
+/* Workspace bytes needed by pafem_op_apply / pafem_op_diagonal (0 if none). */
+pafem_status pafem_op_workspace_bytes(pafem_op op, size_t* nbytes);
+
+/* y = A x on device vectors of length ndofs (f64).  x and y must not alias.
+ * With PAFEM_OP_CONSTRAINED, y_b = x_b on essential dofs and the essential
+ * columns are dropped.  Asynchronous. */
+pafem_status pafem_op_apply(pafem_op op, const double* x, double* y, void* work,
+                            size_t work_bytes, void* stream);
+
+/* diag[ndofs] = diagonal of the operator (1 on essential dofs if constrained),
+ * by sum factorization with products of the 1D tables.  Asynchronous. */
+pafem_status pafem_op_diagonal(pafem_op op, double* diag, void* work, size_t work_bytes,
+                               void* stream);
+
+/* b[ndofs] = int f phi_i ("Finite Element Abstractions", l(v)), zero on
+ * essential dofs.  f per `source` (PAFEM_SOURCE_*), f_qp used only for
+ * PAFEM_SOURCE_ARRAY.  work >= E*(p+1)^3*8 bytes.  Asynchronous. */
+pafem_status pafem_linear_form(pafem_space space, int32_t q1d, int32_t source,
+                               const double* f_qp, double scale, double* b, void* work,
+                               size_t work_bytes, void* stream);
+
+/* -------------------------------------------------------------- solver --- */
+
+typedef struct {
+  double rel_tol;       /* stop when ||r_k||_2 <= rel_tol * ||b||_2 (recursive residual) */
+  int32_t max_iter;     /* iteration cap (the paper's ex1p uses 2000) */
+  int32_t precond;      /* PAFEM_PRECOND_* */
+  int32_t check_every;  /* host reads the convergence flag every this many iterations */
+  int32_t zero_guess;   /* 1: start from x = 0 (x is overwritten); 0: start from x */
+  double* res_hist;     /* optional host array of ||r_k||/||b||, k = 0..iters */
+  int32_t res_hist_cap; /* its capacity */
+} pafem_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* CG iterations performed */
+  int32_t converged;    /* 1 if the tolerance was met */
+  double rel_res;       /* final recursive ||r||/||b|| */
+  double true_rel_res;  /* ||b - A x|| / ||b|| recomputed at exit */
+  double seconds;       /* wall time of the call */
+} pafem_solve_result;
+
+/* Workspace bytes for pafem_pcg_solve on this op with at most max_iter
+ * iterations (three dof vectors, reduction partials, the residual history and
+ * the operator's own workspace). */
+pafem_status pafem_pcg_workspace_bytes(pafem_op op, int32_t max_iter, size_t* nbytes);
+
+/* Preconditioned CG ("Scalable Linear Solvers", CGSolver on the PA operator;
+ * Jacobi preconditioner z = r / diag).  Vectors are device f64 [ndofs]; diag
+ * may be NULL for PAFEM_PRECOND_NONE.  All vector work and the dot products
+ * run on the device; the host reads a convergence flag every check_every
+ * iterations.  SYNCHRONOUS.  Returns ENOTCONV at max_iter, EBREAKDOWN on
+ * p.Ap <= 0 or a non-finite scalar (result filled in either case). */
+pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, double* x,
+                             void* work, size_t work_bytes, const pafem_solve_opts* opts,
+                             pafem_solve_result* result, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAFEM_H */

@@ -57,22 +57,43 @@ def _jacobians(mesh, q1d):
     return pts, w, x, J, det
 
 
+def _chunks(E, per_elem_bytes, budget=256 << 20):
+    step = max(1, int(budget // max(per_elem_bytes, 1)))
+    for a in range(0, E, step):
+        yield slice(a, min(E, a + step))
+
+
 def element_stiffness(mesh, p, q1d, coeff=None):
-    """Dense element diffusion matrices [E, D^3, D^3]; coeff is None, scalar or [E, Q^3]."""
+    """Dense element diffusion matrices [E, D^3, D^3]; coeff is None, scalar or [E, Q^3].
+
+    K_E = sum_q ghat(q)^T Dq ghat(q), evaluated as one matrix product per element:
+    with Ghat = [ghat_1; ghat_2; ghat_3] of shape [3 Q^3, D^3] and H = Dq applied
+    pointwise to Ghat, K_E = Ghat^T H.
+    """
     pts, w, _, J, _ = _jacobians(mesh, q1d)
     _, grad = tensor_basis(gauss_lobatto(p + 1), pts)                  # [3, Q^3, D^3]
     c = 1.0 if coeff is None else coeff
     Dq = qpoint_diffusion_operator(J, w[None, :], c)                   # [E, Q^3, 3, 3]
-    return np.einsum("aqi,eqab,bqj->eij", grad, Dq, grad, optimize=True)
+    E, nq, nd = J.shape[0], grad.shape[1], grad.shape[2]
+    gflat = grad.reshape(3 * nq, nd)
+    out = np.empty((E, nd, nd))
+    for sl in _chunks(E, 8 * 3 * nq * nd):
+        H = np.einsum("eqab,bqj->eaqj", Dq[sl], grad).reshape(-1, 3 * nq, nd)
+        out[sl] = np.matmul(gflat.T[None], H)
+    return out
 
 
 def element_mass(mesh, p, q1d, coeff=None):
-    """Dense element mass matrices [E, D^3, D^3]."""
+    """Dense element mass matrices [E, D^3, D^3]: M_E = B^t diag(alpha det J rho) B."""
     pts, w, _, _, det = _jacobians(mesh, q1d)
     val, _ = tensor_basis(gauss_lobatto(p + 1), pts)                   # [Q^3, D^3]
     c = 1.0 if coeff is None else coeff
     d = w[None, :] * det * c
-    return np.einsum("qi,eq,qj->eij", val, d, val, optimize=True)
+    E, nd = det.shape[0], val.shape[1]
+    out = np.empty((E, nd, nd))
+    for sl in _chunks(E, 8 * val.size):
+        out[sl] = np.matmul(val.T[None], d[sl][:, :, None] * val[None])
+    return out
 
 
 def element_load(mesh, p, q1d, f):

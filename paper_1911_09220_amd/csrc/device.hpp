@@ -1,0 +1,67 @@
+// Device-side helpers for gfx950 (CDNA4, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pafem {
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, one L2 each
+
+// Workgroups are dispatched round-robin over the XCDs (block b runs on XCD b % 8).
+// Remap so that each XCD works on one contiguous range of tiles: neighbouring
+// element tiles share dofs, and keeping them on one die keeps the shared x/y
+// lines in one L2.  Bijective for any grid size.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int xcd = bid % kNumXcd, idx = bid / kNumXcd;
+  const int base = nblocks / kNumXcd, rem = nblocks % kNumXcd;
+  return xcd * base + min(xcd, rem) + idx;
+}
+
+// bfloat16 storage as raw 16-bit patterns (round-to-nearest-even on conversion).
+struct bf16 {
+  uint16_t bits;
+};
+__device__ __host__ __forceinline__ float bf16_to_float(bf16 h) {
+  union {
+    uint32_t u;
+    float f;
+  } v;
+  v.u = uint32_t(h.bits) << 16;
+  return v.f;
+}
+
+template <typename TC, typename TD>
+__device__ __forceinline__ TC load_value(const TD* p) {
+  return TC(__builtin_nontemporal_load(p));
+}
+template <>
+__device__ __forceinline__ float load_value<float, bf16>(const bf16* p) {
+  const uint16_t raw = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p));
+  return bf16_to_float(bf16{raw});
+}
+
+// Sum over the 64 lanes of a wave (butterfly: every lane ends with the total,
+// fixed association order, so results are reproducible run to run).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Deterministic block sum; `scratch` holds blockDim.x / 64 doubles in LDS.
+// Returns the total in every thread.  Contains __syncthreads().
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  v = wave_sum(v);
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += scratch[w];
+  __syncthreads();
+  return t;
+}
+
+}  // namespace pafem

@@ -1,0 +1,102 @@
+// Internal declarations shared by the host code and the kernel launchers of
+// the partial-assembly library.  Not part of the public C ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "pafem.h"
+
+namespace pafem {
+
+constexpr int kMaxOrder = 8;
+constexpr int kMaxQ1d = 12;  // 1D tables are built for every q1d in [1, kMaxQ1d]
+
+// Thrown inside the library and turned into a status at the C boundary.
+struct Error : std::runtime_error {
+  pafem_status code;
+  Error(pafem_status c, const std::string& msg) : std::runtime_error(msg), code(c) {}
+};
+
+inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// ---- 1D tables (tables.cpp) -------------------------------------------------
+// Gauss-Legendre rule on [0,1]: points and weights, ascending.
+void gauss_legendre_01(int q, double* x, double* w);
+// Gauss-Lobatto points on [0,1], ascending, n >= 2.
+void gauss_lobatto_01(int n, double* x);
+// Lagrange basis on `nodes` (n of them): B[k*n+j] = phi_j(pts[k]),
+// G[k*n+j] = phi_j'(pts[k]).
+void lagrange_tables(int n, const double* nodes, int npts, const double* pts, double* B,
+                     double* G);
+
+// Per-q1d table block, in doubles: pts[Q] wts[Q] B[Q*D] G[Q*D] Bg[Q*NG] Gg[Q*NG]
+// (D = basis dofs per direction, NG = geometry nodes per direction).
+inline size_t table_block_doubles(int Q, int D, int NG) {
+  return size_t(2 * Q + 2 * Q * D + 2 * Q * NG);
+}
+inline size_t table_offset_doubles(int Q, int D, int NG) {
+  size_t off = 0;
+  for (int q = 1; q < Q; ++q) off += table_block_doubles(q, D, NG);
+  return off;
+}
+std::vector<double> build_tables(int p, int ng);
+
+// ---- device image of a space -------------------------------------------------
+struct DevSpace {
+  const int32_t* gmap = nullptr;   // [ne][D^3], essential dofs stored as ~g
+  const double* gnodes = nullptr;  // [ne][NG^3][3]
+  const uint8_t* bmask = nullptr;  // [ndofs] 1 on essential dofs
+  const int32_t* toff = nullptr;   // [ndofs+1] transposed map offsets
+  const int32_t* tidx = nullptr;   // [ne*D^3] element-vector entries per dof (ascending)
+  const double* tables = nullptr;  // 1D tables for q1d = 1..kMaxQ1d
+  int32_t* status = nullptr;       // [64] small device status words
+  int64_t ne = 0, ndofs = 0;
+  int p = 0, ng = 0;
+};
+
+struct Mesh {
+  int64_t nv = 0, ne = 0;
+  std::vector<double> xyz;     // [nv][3]
+  std::vector<int64_t> hex;    // [ne][8]
+  int geom_order = 1;
+  std::vector<double> gnodes;  // [ne][27][3] for geom_order 2
+};
+
+struct Space {
+  const Mesh* mesh = nullptr;
+  int p = 0, D1 = 0, dpe = 0, ng = 0;
+  int64_t ne = 0, ndofs = 0;
+  std::vector<int32_t> gmap;      // [ne][dpe] dof ids
+  std::vector<uint8_t> bmask;     // [ndofs]
+  std::vector<int32_t> bdr;       // essential dofs ascending
+  std::vector<double> ref_nodes;  // Gauss-Lobatto nodes [D1]
+  std::vector<double> tables;     // build_tables(p, ng)
+  // device image (caller-owned buffer)
+  void* dev_buf = nullptr;
+  size_t dev_bytes = 0;
+  DevSpace dev;
+  bool uploaded = false;
+};
+
+// space.cpp
+Space* build_space(const Mesh* mesh, int order, int flags);
+void space_dof_coords(const Space& s, double* xyz);
+void space_device_layout(const Space& s, size_t* offsets /*[8]*/, size_t* total);
+// host copies of every device array, in upload order
+void space_pack(const Space& s, std::vector<int32_t>& gmap_enc, std::vector<double>& gnodes,
+                std::vector<int32_t>& toff, std::vector<int32_t>& tidx);
+
+struct Op {
+  const Space* space = nullptr;
+  int kind = PAFEM_DIFFUSION;
+  int q1d = 0;
+  const void* qdata = nullptr;
+  int qdtype = PAFEM_F64;
+  int flags = 0;
+};
+
+}  // namespace pafem

@@ -1,0 +1,327 @@
+// Setup kernels: geometric factors + quadrature data (PA setup), the linear
+// form, the operator diagonal, and the transposed element restriction G^t.
+//
+// These run once per solve, so they are written for clarity with runtime sizes
+// (one workgroup per element, dynamic LDS).  All arithmetic is FP64.
+#include <climits>
+
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace pafem {
+
+namespace {
+
+#define HIP_LAUNCH_CHECK()                                                        \
+  do {                                                                            \
+    hipError_t err_ = hipGetLastError();                                          \
+    if (err_ != hipSuccess)                                                       \
+      throw Error(PAFEM_EHIP, std::string("kernel launch: ") + hipGetErrorString(err_)); \
+  } while (0)
+
+struct TabView {
+  const double *pts, *wts, *B, *G, *Bg, *Gg;
+};
+
+TabView tab_view(const DevSpace& sp, int Q) {
+  const int D = sp.p + 1, NG = sp.ng;
+  const double* t = sp.tables + table_offset_doubles(Q, D, NG);
+  TabView v;
+  v.pts = t;
+  v.wts = t + Q;
+  v.B = t + 2 * Q;
+  v.G = v.B + Q * D;
+  v.Bg = v.G + Q * D;
+  v.Gg = v.Bg + Q * NG;
+  return v;
+}
+
+// Jacobian J_ab = d x_a / d xhat_b of the element map at quadrature point q, from
+// the element's geometry nodes X[k][3] and the 1D geometry tables Bg, Gg [Q][NG].
+__device__ void element_jacobian(int q, int Q, int NG, const double* X, const double* Bg,
+                                 const double* Gg, double J[3][3], double x[3]) {
+  const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
+  for (int a = 0; a < 3; ++a) {
+    x[a] = 0.0;
+    for (int b = 0; b < 3; ++b) J[a][b] = 0.0;
+  }
+  for (int k3 = 0; k3 < NG; ++k3)
+    for (int k2 = 0; k2 < NG; ++k2)
+      for (int k1 = 0; k1 < NG; ++k1) {
+        const double b1 = Bg[q1 * NG + k1], g1 = Gg[q1 * NG + k1];
+        const double b2 = Bg[q2 * NG + k2], g2 = Gg[q2 * NG + k2];
+        const double b3 = Bg[q3 * NG + k3], g3 = Gg[q3 * NG + k3];
+        const double w = b1 * b2 * b3;
+        const double d0 = g1 * b2 * b3, d1 = b1 * g2 * b3, d2 = b1 * b2 * g3;
+        const double* Xk = X + 3 * (k1 + NG * (k2 + NG * k3));
+        for (int a = 0; a < 3; ++a) {
+          x[a] += w * Xk[a];
+          J[a][0] += Xk[a] * d0;
+          J[a][1] += Xk[a] * d1;
+          J[a][2] += Xk[a] * d2;
+        }
+      }
+}
+
+__global__ void qdata_kernel(const double* __restrict__ gnodes, int NG, TabView tv, int Q,
+                             int kind, const double* __restrict__ coeff, double scale,
+                             double* __restrict__ qd, int32_t* status) {
+  extern __shared__ double smem[];
+  const int e = blockIdx.x;
+  const int NN = NG * NG * NG, QQQ = Q * Q * Q;
+  double* sX = smem;
+  double* sBg = sX + 3 * NN;
+  double* sGg = sBg + Q * NG;
+  for (int i = threadIdx.x; i < 3 * NN; i += blockDim.x) sX[i] = gnodes[size_t(e) * 3 * NN + i];
+  for (int i = threadIdx.x; i < Q * NG; i += blockDim.x) {
+    sBg[i] = tv.Bg[i];
+    sGg[i] = tv.Gg[i];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < QQQ; q += blockDim.x) {
+    double J[3][3], x[3];
+    element_jacobian(q, Q, NG, sX, sBg, sGg, J, x);
+    // adjugate A = det(J) J^{-1}
+    const double A00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double A01 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    const double A02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    const double A10 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double A11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    const double A12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    const double A20 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double A21 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    const double A22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * A00 + J[0][1] * A10 + J[0][2] * A20;
+    if (!(det > 0.0)) atomicMin(&status[0], e);
+    const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
+    const double w = tv.wts[q1] * tv.wts[q2] * tv.wts[q3];
+    const double c = scale * (coeff ? coeff[size_t(e) * QQQ + q] : 1.0);
+    if (kind == PAFEM_MASS) {
+      qd[size_t(e) * QQQ + q] = w * c * det;
+    } else {
+      // alpha kappa det J J^{-1} J^{-T} = alpha kappa A A^T / det J
+      const double f = w * c / det;
+      double* o = qd + size_t(e) * 6 * QQQ + q;
+      o[0 * QQQ] = f * (A00 * A00 + A01 * A01 + A02 * A02);
+      o[1 * QQQ] = f * (A00 * A10 + A01 * A11 + A02 * A12);
+      o[2 * QQQ] = f * (A00 * A20 + A01 * A21 + A02 * A22);
+      o[3 * QQQ] = f * (A10 * A10 + A11 * A11 + A12 * A12);
+      o[4 * QQQ] = f * (A10 * A20 + A11 * A21 + A12 * A22);
+      o[5 * QQQ] = f * (A20 * A20 + A21 * A21 + A22 * A22);
+    }
+  }
+}
+
+// out[i1,i2,i3] (+)= factor * sum_q T1[q1,i1] T2[q2,i2] T3[q3,i3] in[q1,q2,q3] by three
+// one-axis contractions through LDS (sum factorization of B^t).
+__device__ void contract_to_dofs(int Q, int D, const double* in, double* t1, double* t2,
+                                 double* out, const double* T1, const double* T2,
+                                 const double* T3, double factor, bool accumulate) {
+  const int nt = blockDim.x, tid = threadIdx.x;
+  for (int idx = tid; idx < Q * Q * D; idx += nt) {
+    const int i1 = idx % D, q23 = idx / D;
+    double s = 0.0;
+    for (int q1 = 0; q1 < Q; ++q1) s += T1[q1 * D + i1] * in[q23 * Q + q1];
+    t1[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < Q * D * D; idx += nt) {
+    const int i1 = idx % D, i2 = (idx / D) % D, q3 = idx / (D * D);
+    double s = 0.0;
+    for (int q2 = 0; q2 < Q; ++q2) s += T2[q2 * D + i2] * t1[(q3 * Q + q2) * D + i1];
+    t2[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < D * D * D; idx += nt) {
+    const int i1 = idx % D, i2 = (idx / D) % D, i3 = idx / (D * D);
+    double s = 0.0;
+    for (int q3 = 0; q3 < Q; ++q3) s += T3[q3 * D + i3] * t2[(q3 * D + i2) * D + i1];
+    out[idx] = (accumulate ? out[idx] : 0.0) + factor * s;
+  }
+  __syncthreads();
+}
+
+__global__ void linear_form_kernel(const double* __restrict__ gnodes, int NG, TabView tv, int Q,
+                                   int D, int source, const double* __restrict__ fqp,
+                                   double scale, double* __restrict__ ye) {
+  extern __shared__ double smem[];
+  const int e = blockIdx.x;
+  const int NN = NG * NG * NG, QQQ = Q * Q * Q, DDD = D * D * D;
+  double* sX = smem;
+  double* sBg = sX + 3 * NN;
+  double* sGg = sBg + Q * NG;
+  double* sB = sGg + Q * NG;
+  double* sF = sB + Q * D;
+  double* t1 = sF + QQQ;
+  double* t2 = t1 + Q * Q * D;
+  double* out = t2 + Q * D * D;
+  for (int i = threadIdx.x; i < 3 * NN; i += blockDim.x) sX[i] = gnodes[size_t(e) * 3 * NN + i];
+  for (int i = threadIdx.x; i < Q * NG; i += blockDim.x) {
+    sBg[i] = tv.Bg[i];
+    sGg[i] = tv.Gg[i];
+  }
+  for (int i = threadIdx.x; i < Q * D; i += blockDim.x) sB[i] = tv.B[i];
+  __syncthreads();
+  const double pi = 3.14159265358979323846;
+  for (int q = threadIdx.x; q < QQQ; q += blockDim.x) {
+    double J[3][3], x[3];
+    element_jacobian(q, Q, NG, sX, sBg, sGg, J, x);
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
+    const double w = tv.wts[q1] * tv.wts[q2] * tv.wts[q3];
+    double f;
+    if (source == PAFEM_SOURCE_ARRAY)
+      f = scale * fqp[size_t(e) * QQQ + q];
+    else if (source == PAFEM_SOURCE_CONST)
+      f = scale;
+    else
+      f = scale * 3.0 * pi * pi * sin(pi * x[0]) * sin(pi * x[1]) * sin(pi * x[2]);
+    sF[q] = w * det * f;
+  }
+  __syncthreads();
+  contract_to_dofs(Q, D, sF, t1, t2, out, sB, sB, sB, 1.0, false);
+  for (int i = threadIdx.x; i < DDD; i += blockDim.x) ye[size_t(e) * DDD + i] = out[i];
+}
+
+__global__ void diagonal_kernel(TabView tv, int Q, int D, int kind,
+                                const double* __restrict__ qd, double* __restrict__ ye) {
+  extern __shared__ double smem[];
+  const int e = blockIdx.x;
+  const int QQQ = Q * Q * Q, DDD = D * D * D, QD = Q * D;
+  double* sBB = smem;      // B o B
+  double* sGG = sBB + QD;  // G o G
+  double* sBG = sGG + QD;  // B o G
+  double* sF = sBG + QD;
+  double* t1 = sF + QQQ;
+  double* t2 = t1 + Q * Q * D;
+  double* out = t2 + Q * D * D;
+  for (int i = threadIdx.x; i < QD; i += blockDim.x) {
+    const double b = tv.B[i], g = tv.G[i];
+    sBB[i] = b * b;
+    sGG[i] = g * g;
+    sBG[i] = b * g;
+  }
+  __syncthreads();
+  if (kind == PAFEM_MASS) {
+    for (int q = threadIdx.x; q < QQQ; q += blockDim.x) sF[q] = qd[size_t(e) * QQQ + q];
+    __syncthreads();
+    contract_to_dofs(Q, D, sF, t1, t2, out, sBB, sBB, sBB, 1.0, false);
+  } else {
+    // diag_i = sum_q sum_ab D_ab(q) d_a phi_i(q) d_b phi_i(q); d_a phi_i is a product of
+    // G in direction a and B in the others, so each (a,b) term is a tensor
+    // contraction with elementwise products of the 1D tables.
+    int comp = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = a; b < 3; ++b, ++comp) {
+        for (int q = threadIdx.x; q < QQQ; q += blockDim.x)
+          sF[q] = qd[(size_t(e) * 6 + comp) * QQQ + q];
+        __syncthreads();
+        const double* T[3];
+        for (int d = 0; d < 3; ++d) {
+          const int hits = (d == a) + (d == b);
+          T[d] = hits == 2 ? sGG : (hits == 1 ? sBG : sBB);
+        }
+        contract_to_dofs(Q, D, sF, t1, t2, out, T[0], T[1], T[2], a == b ? 1.0 : 2.0, comp > 0);
+      }
+  }
+  for (int i = threadIdx.x; i < DDD; i += blockDim.x) ye[size_t(e) * DDD + i] = out[i];
+}
+
+template <typename T>
+__global__ void evec_gather_kernel(const int32_t* __restrict__ toff,
+                                   const int32_t* __restrict__ tidx,
+                                   const uint8_t* __restrict__ bmask, const T* __restrict__ ye,
+                                   const T* __restrict__ x, int bc_mode, T bc_value,
+                                   T* __restrict__ y, int64_t n) {
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n;
+       g += int64_t(gridDim.x) * blockDim.x) {
+    if (bc_mode != 0 && bmask[g]) {
+      y[g] = (bc_mode == 1) ? x[g] : bc_value;
+      continue;
+    }
+    T s = T(0);
+    const int32_t k1 = toff[g + 1];
+    for (int32_t k = toff[g]; k < k1; ++k) s += ye[tidx[k]];
+    y[g] = s;
+  }
+}
+
+template <typename T>
+__global__ void scatter_init_kernel(const uint8_t* __restrict__ bmask, const T* __restrict__ x,
+                                    int constrained, T* __restrict__ y, int64_t n) {
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n;
+       g += int64_t(gridDim.x) * blockDim.x)
+    y[g] = (constrained && bmask[g]) ? x[g] : T(0);
+}
+
+int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g > (1 << 20)) g = 1 << 20;
+  return int(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+void launch_qdata(const DevSpace& sp, int kind, int q1d, const double* coeff, double scale,
+                  double* qd, hipStream_t st) {
+  const TabView tv = tab_view(sp, q1d);
+  const int NN = sp.ng * sp.ng * sp.ng;
+  const size_t lds = sizeof(double) * (3 * NN + 2 * q1d * sp.ng);
+  hipLaunchKernelGGL(qdata_kernel, dim3(unsigned(sp.ne)), dim3(256), lds, st, sp.gnodes, sp.ng,
+                     tv, q1d, kind, coeff, scale, qd, sp.status);
+  HIP_LAUNCH_CHECK();
+}
+
+void launch_linear_form_evec(const DevSpace& sp, int q1d, int source, const double* fqp,
+                             double scale, double* ye, hipStream_t st) {
+  const TabView tv = tab_view(sp, q1d);
+  const int NN = sp.ng * sp.ng * sp.ng, Q = q1d, D = sp.p + 1;
+  const size_t lds = sizeof(double) * (3 * NN + 2 * Q * sp.ng + Q * D + Q * Q * Q + Q * Q * D +
+                                       Q * D * D + D * D * D);
+  hipLaunchKernelGGL(linear_form_kernel, dim3(unsigned(sp.ne)), dim3(256), lds, st, sp.gnodes,
+                     sp.ng, tv, Q, D, source, fqp, scale, ye);
+  HIP_LAUNCH_CHECK();
+}
+
+void launch_diagonal_evec(const DevSpace& sp, int kind, int q1d, const double* qd, double* ye,
+                          hipStream_t st) {
+  const TabView tv = tab_view(sp, q1d);
+  const int Q = q1d, D = sp.p + 1;
+  const size_t lds =
+      sizeof(double) * (3 * Q * D + Q * Q * Q + Q * Q * D + Q * D * D + D * D * D);
+  hipLaunchKernelGGL(diagonal_kernel, dim3(unsigned(sp.ne)), dim3(256), lds, st, tv, Q, D, kind,
+                     qd, ye);
+  HIP_LAUNCH_CHECK();
+}
+
+void launch_evec_gather(const DevSpace& sp, const double* ye, const double* x, int bc_mode,
+                        double bc_value, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(evec_gather_kernel<double>, dim3(grid_for(sp.ndofs, 256)), dim3(256), 0, st,
+                     sp.toff, sp.tidx, sp.bmask, ye, x, bc_mode, bc_value, y, sp.ndofs);
+  HIP_LAUNCH_CHECK();
+}
+
+void launch_evec_gather_f32(const DevSpace& sp, const float* ye, const float* x, int bc_mode,
+                            float* y, hipStream_t st) {
+  hipLaunchKernelGGL(evec_gather_kernel<float>, dim3(grid_for(sp.ndofs, 256)), dim3(256), 0, st,
+                     sp.toff, sp.tidx, sp.bmask, ye, x, bc_mode, 0.0f, y, sp.ndofs);
+  HIP_LAUNCH_CHECK();
+}
+
+void launch_scatter_init(const DevSpace& sp, const double* x, bool constrained, double* y,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(scatter_init_kernel<double>, dim3(grid_for(sp.ndofs, 256)), dim3(256), 0, st,
+                     sp.bmask, x, int(constrained), y, sp.ndofs);
+  HIP_LAUNCH_CHECK();
+}
+
+void launch_scatter_init_f32(const DevSpace& sp, const float* x, bool constrained, float* y,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(scatter_init_kernel<float>, dim3(grid_for(sp.ndofs, 256)), dim3(256), 0, st,
+                     sp.bmask, x, int(constrained), y, sp.ndofs);
+  HIP_LAUNCH_CHECK();
+}
+
+}  // namespace pafem

@@ -1,0 +1,40 @@
+// Host-callable kernel launchers (implemented in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "internal.hpp"
+
+namespace pafem {
+
+// ---- setup (k_setup.hip) ----
+// status[0] must hold INT32_MAX on entry; receives the smallest element with det J <= 0.
+void launch_qdata(const DevSpace& sp, int kind, int q1d, const double* coeff, double scale,
+                  double* qd, hipStream_t st);
+// element vectors of the linear form into ye [ne][D^3]
+void launch_linear_form_evec(const DevSpace& sp, int q1d, int source, const double* fqp,
+                             double scale, double* ye, hipStream_t st);
+// element diagonals into ye [ne][D^3]
+void launch_diagonal_evec(const DevSpace& sp, int kind, int q1d, const double* qd,
+                          double* ye, hipStream_t st);
+// y[g] = sum of element-vector entries of dof g; essential dofs per bc_mode:
+// 0 plain sum, 1 y = x (x required), 2 y = bc_value
+void launch_evec_gather(const DevSpace& sp, const double* ye, const double* x, int bc_mode,
+                        double bc_value, double* y, hipStream_t st);
+void launch_evec_gather_f32(const DevSpace& sp, const float* ye, const float* x, int bc_mode,
+                            float* y, hipStream_t st);
+// y = x on essential dofs (constrained) and 0 elsewhere: start of an atomic scatter
+void launch_scatter_init(const DevSpace& sp, const double* x, bool constrained, double* y,
+                         hipStream_t st);
+void launch_scatter_init_f32(const DevSpace& sp, const float* x, bool constrained, float* y,
+                             hipStream_t st);
+
+// ---- apply (k_apply.hip) ----
+// Fused G -> B -> D -> B^t -> G^t.  evec: write element vectors to `out`
+// [ne][D^3] instead of atomically adding into the dof vector `out`.
+// Returns false if (p, q1d, dtype) is not instantiated.
+bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool constrained,
+                     bool evec, const void* qd, const void* x, void* out, int vdtype,
+                     hipStream_t st);
+
+}  // namespace pafem

@@ -1,0 +1,358 @@
+// Mesh topology and the H1 finite element space (host).
+//
+// Builds the element restriction G of "Operator Decomposition" as an
+// element->dof table in lexicographic local order.  Global numbering follows
+// "Finite Element Spaces": vertex dofs, then edge dofs (each edge traversed
+// in a fixed direction), then face dofs (each face in a fixed orientation),
+// then element interiors.  The fixed direction of an edge runs from its
+// smaller to its larger vertex id; the fixed frame of a face has its origin at
+// the face's smallest vertex id, first axis towards the adjacent corner with
+// the smaller id.  Every element maps its local edge/face nodes into that frame,
+// which is the orientation permutation of "Finite Elements"
+// (FiniteElementCollection).
+//
+// Edges and faces are matched by bucketing them by their smallest vertex and
+// comparing within buckets (no hashing).  A face seen once is a boundary face;
+// every dof on a boundary face is essential.
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace pafem {
+
+namespace {
+
+// lexicographic corner c = cx + 2 cy + 4 cz -> slot in the usual hex vertex order
+constexpr int kLexToSlot[8] = {0, 1, 3, 2, 4, 5, 7, 6};
+
+struct ElemCorners {
+  int64_t v[8];
+};
+
+inline ElemCorners corners_of(const Mesh& m, int64_t e) {
+  ElemCorners c;
+  for (int k = 0; k < 8; ++k) c.v[k] = m.hex[size_t(e) * 8 + kLexToSlot[k]];
+  return c;
+}
+
+// 12 edges: (axis, low corner) pairs with bit `axis` of the corner clear
+struct EdgeSlot {
+  int axis, c0;
+};
+std::array<EdgeSlot, 12> edge_slots() {
+  std::array<EdgeSlot, 12> out{};
+  int k = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 8; ++c)
+      if (!((c >> a) & 1)) out[k++] = {a, c};
+  return out;
+}
+
+// 6 faces: axis a, side s; corners with bit a == s
+struct FaceSlot {
+  int axis, side, c[4];
+};
+std::array<FaceSlot, 6> face_slots() {
+  std::array<FaceSlot, 6> out{};
+  int k = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s) {
+      FaceSlot f{a, s, {0, 0, 0, 0}};
+      int n = 0;
+      for (int c = 0; c < 8; ++c)
+        if (((c >> a) & 1) == s) f.c[n++] = c;
+      out[k++] = f;
+    }
+  return out;
+}
+
+// Match items (edges or faces) that carry the same sorted vertex key.  Items are
+// bucketed by their first (smallest) key entry.  rep[i] = smallest item index
+// with the same key; count[i] = multiplicity of the key.
+template <int K>
+void match_keys(const std::vector<std::array<int64_t, K>>& keys, int64_t nv,
+                std::vector<int64_t>& rep, std::vector<int32_t>& mult) {
+  const size_t n = keys.size();
+  std::vector<int64_t> off(size_t(nv) + 1, 0);
+  for (size_t i = 0; i < n; ++i) off[size_t(keys[i][0]) + 1]++;
+  for (int64_t v = 0; v < nv; ++v) off[v + 1] += off[v];
+  std::vector<int64_t> items(n);
+  {
+    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+    for (size_t i = 0; i < n; ++i) items[fill[size_t(keys[i][0])]++] = int64_t(i);
+  }
+  rep.assign(n, -1);
+  mult.assign(n, 0);
+  for (int64_t v = 0; v < nv; ++v) {
+    for (int64_t a = off[v]; a < off[v + 1]; ++a) {
+      const int64_t i = items[a];
+      if (rep[i] >= 0) continue;
+      rep[i] = i;
+      int32_t m = 1;
+      for (int64_t b = a + 1; b < off[v + 1]; ++b) {
+        const int64_t j = items[b];
+        if (rep[j] < 0 && keys[j] == keys[i]) {
+          rep[j] = i;
+          ++m;
+        }
+      }
+      mult[i] = m;
+    }
+  }
+  for (size_t i = 0; i < n; ++i) mult[i] = mult[size_t(rep[i])];
+}
+
+}  // namespace
+
+Space* build_space(const Mesh* mesh, int order, int flags) {
+  if (order < 1 || order > kMaxOrder)
+    throw Error(PAFEM_EUNSUPPORTED, "order must be in 1..8, got " + std::to_string(order));
+  const Mesh& m = *mesh;
+  const int p = order, D1 = p + 1, dpe = D1 * D1 * D1;
+  const int64_t ne = m.ne;
+  auto* s = new Space();
+  s->mesh = mesh;
+  s->p = p;
+  s->D1 = D1;
+  s->dpe = dpe;
+  s->ne = ne;
+  s->ng = (m.geom_order == 2) ? 3 : 2;
+  s->ref_nodes.resize(D1);
+  gauss_lobatto_01(D1, s->ref_nodes.data());
+
+  // ---- faces: always needed (boundary detection) -------------------------
+  const auto fs = face_slots();
+  std::vector<std::array<int64_t, 4>> fkeys(size_t(ne) * 6);
+  for (int64_t e = 0; e < ne; ++e) {
+    const ElemCorners c = corners_of(m, e);
+    for (int f = 0; f < 6; ++f) {
+      std::array<int64_t, 4> k = {c.v[fs[f].c[0]], c.v[fs[f].c[1]], c.v[fs[f].c[2]],
+                                  c.v[fs[f].c[3]]};
+      std::sort(k.begin(), k.end());
+      fkeys[size_t(e) * 6 + f] = k;
+    }
+  }
+  std::vector<int64_t> frep;
+  std::vector<int32_t> fmult;
+  match_keys<4>(fkeys, m.nv, frep, fmult);
+  for (size_t i = 0; i < fmult.size(); ++i)
+    if (fmult[i] > 2) {
+      delete s;
+      throw Error(PAFEM_EINVAL, "non-conforming mesh: face shared by more than two elements "
+                                "(element " + std::to_string(i / 6) + ")");
+    }
+  fkeys.clear();
+  fkeys.shrink_to_fit();
+
+  // ---- numbering of vertices, edges, faces, interiors ---------------------
+  std::vector<int32_t> vdof(size_t(m.nv), -1);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int k = 0; k < 8; ++k) vdof[size_t(m.hex[size_t(e) * 8 + k])] = 0;
+  int64_t next = 0;
+  for (int64_t v = 0; v < m.nv; ++v)
+    if (vdof[v] == 0) vdof[v] = int32_t(next++);
+
+  const auto es = edge_slots();
+  std::vector<int64_t> erep;
+  std::vector<int32_t> eid, fid;
+  int64_t n_edges = 0, n_faces = 0;
+  if (p >= 2) {
+    std::vector<std::array<int64_t, 2>> ekeys(size_t(ne) * 12);
+    for (int64_t e = 0; e < ne; ++e) {
+      const ElemCorners c = corners_of(m, e);
+      for (int k = 0; k < 12; ++k) {
+        int64_t a = c.v[es[k].c0], b = c.v[es[k].c0 | (1 << es[k].axis)];
+        ekeys[size_t(e) * 12 + k] = {std::min(a, b), std::max(a, b)};
+      }
+    }
+    std::vector<int32_t> emult;
+    match_keys<2>(ekeys, m.nv, erep, emult);
+    eid.assign(erep.size(), -1);
+    for (size_t i = 0; i < erep.size(); ++i)
+      eid[i] = (erep[i] == int64_t(i)) ? int32_t(n_edges++) : eid[size_t(erep[i])];
+    fid.assign(frep.size(), -1);
+    for (size_t i = 0; i < frep.size(); ++i)
+      fid[i] = (frep[i] == int64_t(i)) ? int32_t(n_faces++) : fid[size_t(frep[i])];
+  }
+  const int64_t nvd = next;
+  const int64_t ebase = nvd;
+  const int64_t fbase = ebase + n_edges * (p - 1);
+  const int64_t ibase = fbase + n_faces * int64_t(p - 1) * (p - 1);
+  const int64_t ndofs = ibase + ne * int64_t(p - 1) * (p - 1) * (p - 1);
+  if (ndofs >= (int64_t(1) << 31) - 1 || ne * int64_t(dpe) >= (int64_t(1) << 31) - 1) {
+    delete s;
+    throw Error(PAFEM_EINVAL, "problem too large for 32-bit dof indices");
+  }
+  s->ndofs = ndofs;
+
+  // local (axis, low corner) -> edge slot index
+  int edge_slot_of[3][8];
+  for (int k = 0; k < 12; ++k) edge_slot_of[es[k].axis][es[k].c0] = k;
+
+  s->gmap.assign(size_t(ne) * dpe, 0);
+  s->bmask.assign(size_t(ndofs), 0);
+  for (int64_t e = 0; e < ne; ++e) {
+    const ElemCorners c = corners_of(m, e);
+    int32_t* g = s->gmap.data() + size_t(e) * dpe;
+    for (int i3 = 0; i3 < D1; ++i3)
+      for (int i2 = 0; i2 < D1; ++i2)
+        for (int i1 = 0; i1 < D1; ++i1) {
+          const int idx[3] = {i1, i2, i3};
+          int nb = 0;
+          for (int a = 0; a < 3; ++a) nb += (idx[a] == 0 || idx[a] == p);
+          int64_t dof = -1;
+          if (nb == 3) {
+            int cc = (i1 == p) | ((i2 == p) << 1) | ((i3 == p) << 2);
+            dof = vdof[size_t(c.v[cc])];
+          } else if (nb == 2) {
+            int a = (idx[0] != 0 && idx[0] != p) ? 0 : (idx[1] != 0 && idx[1] != p) ? 1 : 2;
+            int c0 = 0;
+            for (int b = 0; b < 3; ++b)
+              if (b != a && idx[b] == p) c0 |= (1 << b);
+            const int k = edge_slot_of[a][c0];
+            const int64_t va = c.v[c0], vb = c.v[c0 | (1 << a)];
+            const int t = idx[a];
+            const int tc = (va < vb) ? t : p - t;
+            dof = ebase + int64_t(eid[size_t(e) * 12 + k]) * (p - 1) + (tc - 1);
+          } else if (nb == 1) {
+            int a = (idx[0] == 0 || idx[0] == p) ? 0 : (idx[1] == 0 || idx[1] == p) ? 1 : 2;
+            const int side = (idx[a] == p);
+            const int f = 2 * a + side;
+            const int b0 = (a == 0) ? 1 : 0, b1 = (a == 2) ? 1 : 2;
+            // origin: face corner with the smallest vertex id
+            int O = fs[f].c[0];
+            for (int q = 1; q < 4; ++q)
+              if (c.v[fs[f].c[q]] < c.v[O]) O = fs[f].c[q];
+            const int n0 = O ^ (1 << b0), n1 = O ^ (1 << b1);
+            int au, av;
+            if (c.v[n0] < c.v[n1]) {
+              au = b0;
+              av = b1;
+            } else {
+              au = b1;
+              av = b0;
+            }
+            const int cu = ((O >> au) & 1) ? p - idx[au] : idx[au];
+            const int cv = ((O >> av) & 1) ? p - idx[av] : idx[av];
+            dof = fbase + int64_t(fid[size_t(e) * 6 + f]) * (p - 1) * (p - 1) + (cu - 1) +
+                  int64_t(p - 1) * (cv - 1);
+          } else {
+            dof = ibase + e * int64_t(p - 1) * (p - 1) * (p - 1) + (i1 - 1) +
+                  int64_t(p - 1) * ((i2 - 1) + int64_t(p - 1) * (i3 - 1));
+          }
+          g[i1 + D1 * (i2 + D1 * i3)] = int32_t(dof);
+        }
+    // essential dofs: all nodes of faces that belong to this element only
+    for (int f = 0; f < 6; ++f) {
+      if (fmult[size_t(e) * 6 + f] != 1) continue;
+      const int a = fs[f].axis, v = fs[f].side ? p : 0;
+      for (int i3 = 0; i3 < D1; ++i3)
+        for (int i2 = 0; i2 < D1; ++i2)
+          for (int i1 = 0; i1 < D1; ++i1) {
+            const int idx[3] = {i1, i2, i3};
+            if (idx[a] == v) s->bmask[size_t(g[i1 + D1 * (i2 + D1 * i3)])] = 1;
+          }
+    }
+  }
+
+  if (flags & PAFEM_SPACE_RENUMBER) {
+    std::vector<int32_t> perm(size_t(ndofs), -1);
+    int32_t nn = 0;
+    for (auto& d : s->gmap) {
+      if (perm[size_t(d)] < 0) perm[size_t(d)] = nn++;
+      d = perm[size_t(d)];
+    }
+    std::vector<uint8_t> bm(static_cast<size_t>(ndofs), 0);
+    for (int64_t d = 0; d < ndofs; ++d) bm[size_t(perm[d])] = s->bmask[size_t(d)];
+    s->bmask.swap(bm);
+  }
+  for (int64_t d = 0; d < ndofs; ++d)
+    if (s->bmask[size_t(d)]) s->bdr.push_back(int32_t(d));
+  s->tables = build_tables(p, s->ng);
+  return s;
+}
+
+void space_dof_coords(const Space& s, double* xyz) {
+  const Mesh& m = *s.mesh;
+  const int D1 = s.D1, ng = s.ng;
+  // geometry basis (linear or quadratic Lagrange on equispaced nodes) at the
+  // Gauss-Lobatto nodes
+  std::vector<double> gn(ng), Bg(size_t(D1) * ng), Gg(size_t(D1) * ng);
+  for (int i = 0; i < ng; ++i) gn[i] = double(i) / (ng - 1);
+  lagrange_tables(ng, gn.data(), D1, s.ref_nodes.data(), Bg.data(), Gg.data());
+  const int nn = ng * ng * ng;
+  std::vector<double> X(size_t(nn) * 3);
+  for (int64_t e = 0; e < s.ne; ++e) {
+    if (m.geom_order == 2) {
+      std::memcpy(X.data(), m.gnodes.data() + size_t(e) * 27 * 3, sizeof(double) * 81);
+    } else {
+      const ElemCorners c = corners_of(m, e);
+      for (int k = 0; k < 8; ++k)
+        for (int a = 0; a < 3; ++a) X[k * 3 + a] = m.xyz[size_t(c.v[k]) * 3 + a];
+    }
+    const int32_t* g = s.gmap.data() + size_t(e) * s.dpe;
+    for (int i3 = 0; i3 < D1; ++i3)
+      for (int i2 = 0; i2 < D1; ++i2)
+        for (int i1 = 0; i1 < D1; ++i1) {
+          double x[3] = {0, 0, 0};
+          for (int k3 = 0; k3 < ng; ++k3)
+            for (int k2 = 0; k2 < ng; ++k2)
+              for (int k1 = 0; k1 < ng; ++k1) {
+                const double w = Bg[i1 * ng + k1] * Bg[i2 * ng + k2] * Bg[i3 * ng + k3];
+                const int k = k1 + ng * (k2 + ng * k3);
+                for (int a = 0; a < 3; ++a) x[a] += w * X[k * 3 + a];
+              }
+          const int32_t d = g[i1 + D1 * (i2 + D1 * i3)];
+          for (int a = 0; a < 3; ++a) xyz[size_t(d) * 3 + a] = x[a];
+        }
+  }
+}
+
+void space_device_layout(const Space& s, size_t* off, size_t* total) {
+  const size_t nn = size_t(s.ng) * s.ng * s.ng;
+  size_t o = 0;
+  off[0] = o; o += align256(sizeof(int32_t) * size_t(s.ne) * s.dpe);        // gmap
+  off[1] = o; o += align256(sizeof(double) * size_t(s.ne) * nn * 3);        // gnodes
+  off[2] = o; o += align256(size_t(s.ndofs));                               // bmask
+  off[3] = o; o += align256(sizeof(int32_t) * size_t(s.ndofs + 1));         // toff
+  off[4] = o; o += align256(sizeof(int32_t) * size_t(s.ne) * s.dpe);        // tidx
+  off[5] = o; o += align256(sizeof(double) * s.tables.size());              // tables
+  off[6] = o; o += align256(sizeof(int32_t) * 64);                          // status
+  off[7] = o;
+  *total = o;
+}
+
+void space_pack(const Space& s, std::vector<int32_t>& gmap_enc, std::vector<double>& gnodes,
+                std::vector<int32_t>& toff, std::vector<int32_t>& tidx) {
+  const Mesh& m = *s.mesh;
+  const size_t n = size_t(s.ne) * s.dpe;
+  gmap_enc.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    const int32_t d = s.gmap[i];
+    gmap_enc[i] = s.bmask[size_t(d)] ? ~d : d;
+  }
+  const int nn = s.ng * s.ng * s.ng;
+  gnodes.resize(size_t(s.ne) * nn * 3);
+  for (int64_t e = 0; e < s.ne; ++e) {
+    double* X = gnodes.data() + size_t(e) * nn * 3;
+    if (m.geom_order == 2) {
+      std::memcpy(X, m.gnodes.data() + size_t(e) * 81, sizeof(double) * 81);
+    } else {
+      const ElemCorners c = corners_of(m, e);
+      for (int k = 0; k < 8; ++k)
+        for (int a = 0; a < 3; ++a) X[k * 3 + a] = m.xyz[size_t(c.v[k]) * 3 + a];
+    }
+  }
+  // transposed map: for each dof, its element-vector entries in ascending order
+  toff.assign(size_t(s.ndofs) + 1, 0);
+  for (size_t i = 0; i < n; ++i) toff[size_t(s.gmap[i]) + 1]++;
+  for (int64_t d = 0; d < s.ndofs; ++d) toff[size_t(d) + 1] += toff[size_t(d)];
+  tidx.resize(n);
+  std::vector<int32_t> fill(toff.begin(), toff.end() - 1);
+  for (size_t i = 0; i < n; ++i) tidx[size_t(fill[size_t(s.gmap[i])]++)] = int32_t(i);
+}
+
+}  // namespace pafem

@@ -1,0 +1,336 @@
+"""Thin ctypes binding of libpafem.so (argument marshalling only).
+
+Every function named ``pafem_*`` here calls the C entry point of the same name
+declared in ``include/pafem.h``; device buffers are torch tensors on the GPU
+and the stream is torch's current stream.  The classes below only hold handles
+and the caller-owned device buffers the C calls need.  No computation happens in
+Python: if the library is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpafem.so")
+
+MASS, DIFFUSION = 0, 1
+F64, F32, BF16 = 0, 1, 2
+SPACE_RENUMBER = 1
+OP_CONSTRAINED, OP_SCATTER_EVEC = 1, 2
+SOURCE_ARRAY, SOURCE_CONST, SOURCE_SINE = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
+STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EUNSUPPORTED", -4: "EHIP",
+          -5: "ENOTCONV", -6: "EBREAKDOWN"}
+
+
+class PafemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rel_tol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32),
+                ("check_every", C.c_int32), ("zero_guess", C.c_int32),
+                ("res_hist", C.POINTER(C.c_double)), ("res_hist_cap", C.c_int32)]
+
+
+class SolveResult(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double), ("seconds", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    sig = {
+        "pafem_last_error": (C.c_char_p, []),
+        "pafem_version": (I32, []),
+        "pafem_mesh_create_hex": (I32, [I64, P, I64, P, I32, P, C.POINTER(P)]),
+        "pafem_mesh_destroy": (None, [P]),
+        "pafem_space_create_h1": (I32, [P, I32, I32, C.POINTER(P)]),
+        "pafem_space_destroy": (None, [P]),
+        "pafem_space_info": (I32, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32),
+                                   C.POINTER(I64)]),
+        "pafem_space_dof_coords": (I32, [P, P]),
+        "pafem_space_boundary_dofs": (I32, [P, P]),
+        "pafem_space_elem_dofs": (I32, [P, P]),
+        "pafem_space_device_bytes": (I32, [P, C.POINTER(SZ)]),
+        "pafem_space_upload": (I32, [P, P, SZ, P]),
+        "pafem_qdata_size": (I32, [P, I32, I32, C.POINTER(I64)]),
+        "pafem_qdata_assemble": (I32, [P, I32, I32, P, D, P, P]),
+        "pafem_op_create": (I32, [P, I32, I32, P, I32, I32, C.POINTER(P)]),
+        "pafem_op_destroy": (None, [P]),
+        "pafem_op_workspace_bytes": (I32, [P, C.POINTER(SZ)]),
+        "pafem_op_apply": (I32, [P, P, P, P, SZ, P]),
+        "pafem_op_diagonal": (I32, [P, P, P, SZ, P]),
+        "pafem_linear_form": (I32, [P, I32, I32, P, D, P, P, SZ, P]),
+        "pafem_pcg_workspace_bytes": (I32, [P, I32, C.POINTER(SZ)]),
+        "pafem_pcg_solve": (I32, [P, P, P, P, P, SZ, C.POINTER(SolveOpts),
+                                  C.POINTER(SolveResult), P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != 0:
+        raise PafemError(rc, lib.pafem_last_error().decode())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _device_bytes(nbytes, device="cuda"):
+    import torch
+    # 256-byte aligned: torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ---- thin wrappers with the C names -------------------------------------------------
+
+def pafem_version():
+    return lib.pafem_version()
+
+
+def pafem_mesh_create_hex(vertices, hexes, geom_order=1, geom_nodes=None):
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    h = np.ascontiguousarray(hexes, dtype=np.int64)
+    g = None if geom_nodes is None else np.ascontiguousarray(geom_nodes, dtype=np.float64)
+    out = C.c_void_p()
+    _check(lib.pafem_mesh_create_hex(v.shape[0], _np_ptr(v), h.shape[0], _np_ptr(h),
+                                     int(geom_order), None if g is None else _np_ptr(g),
+                                     C.byref(out)))
+    return out
+
+
+def pafem_space_create_h1(mesh, order, flags=0):
+    out = C.c_void_p()
+    _check(lib.pafem_space_create_h1(mesh, int(order), int(flags), C.byref(out)))
+    return out
+
+
+def pafem_space_info(space):
+    nd, ne, nb = C.c_int64(), C.c_int64(), C.c_int64()
+    dpe = C.c_int32()
+    _check(lib.pafem_space_info(space, C.byref(nd), C.byref(ne), C.byref(dpe), C.byref(nb)))
+    return nd.value, ne.value, dpe.value, nb.value
+
+
+def pafem_space_device_bytes(space):
+    n = C.c_size_t()
+    _check(lib.pafem_space_device_bytes(space, C.byref(n)))
+    return n.value
+
+
+def pafem_space_upload(space, buf):
+    _check(lib.pafem_space_upload(space, _ptr(buf), buf.numel() * buf.element_size(), _stream()))
+
+
+def pafem_qdata_size(space, kind, q1d):
+    n = C.c_int64()
+    _check(lib.pafem_qdata_size(space, int(kind), int(q1d), C.byref(n)))
+    return n.value
+
+
+def pafem_qdata_assemble(space, kind, q1d, coeff, scale, qdata):
+    _check(lib.pafem_qdata_assemble(space, int(kind), int(q1d), _ptr(coeff), float(scale),
+                                    _ptr(qdata), _stream()))
+
+
+def pafem_op_create(space, kind, q1d, qdata, qdata_dtype, flags):
+    out = C.c_void_p()
+    _check(lib.pafem_op_create(space, int(kind), int(q1d), _ptr(qdata), int(qdata_dtype),
+                               int(flags), C.byref(out)))
+    return out
+
+
+def pafem_op_workspace_bytes(op):
+    n = C.c_size_t()
+    _check(lib.pafem_op_workspace_bytes(op, C.byref(n)))
+    return n.value
+
+
+def pafem_op_apply(op, x, y, work):
+    _check(lib.pafem_op_apply(op, _ptr(x), _ptr(y), _ptr(work),
+                              0 if work is None else work.numel(), _stream()))
+
+
+def pafem_op_diagonal(op, diag, work):
+    _check(lib.pafem_op_diagonal(op, _ptr(diag), _ptr(work), work.numel(), _stream()))
+
+
+def pafem_linear_form(space, q1d, source, f_qp, scale, b, work):
+    _check(lib.pafem_linear_form(space, int(q1d), int(source), _ptr(f_qp), float(scale),
+                                 _ptr(b), _ptr(work), work.numel(), _stream()))
+
+
+def pafem_pcg_workspace_bytes(op, max_iter):
+    n = C.c_size_t()
+    _check(lib.pafem_pcg_workspace_bytes(op, int(max_iter), C.byref(n)))
+    return n.value
+
+
+def pafem_pcg_solve(op, diag, b, x, work, opts: SolveOpts):
+    res = SolveResult()
+    rc = lib.pafem_pcg_solve(op, _ptr(diag), _ptr(b), _ptr(x), _ptr(work), work.numel(),
+                             C.byref(opts), C.byref(res), _stream())
+    return rc, res
+
+
+# ---- handle-owning conveniences -----------------------------------------------------
+
+class Mesh:
+    def __init__(self, vertices, hexes, geom_order=1, geom_nodes=None):
+        self.handle = pafem_mesh_create_hex(vertices, hexes, geom_order, geom_nodes)
+
+    @classmethod
+    def from_dict(cls, m):
+        return cls(m["vertices"], m["hex"], m.get("geom_order", 1), m.get("geom_nodes"))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.pafem_mesh_destroy(self.handle)
+            self.handle = None
+
+
+class Space:
+    """H1 space of order p; uploads its device image on construction."""
+
+    def __init__(self, mesh: Mesh, order: int, renumber: bool = False, device="cuda"):
+        self.mesh = mesh  # keeps the mesh alive
+        self.p = int(order)
+        self.handle = pafem_space_create_h1(mesh.handle, order, SPACE_RENUMBER if renumber else 0)
+        self.ndofs, self.nelem, self.dofs_per_elem, self.nbdr = pafem_space_info(self.handle)
+        self.device = device
+        self.buf = None
+        if device is not None:
+            self.buf = _device_bytes(pafem_space_device_bytes(self.handle), device)
+            pafem_space_upload(self.handle, self.buf)
+
+    def dof_coords(self):
+        out = np.empty((self.ndofs, 3))
+        _check(lib.pafem_space_dof_coords(self.handle, _np_ptr(out)))
+        return out
+
+    def boundary_dofs(self):
+        out = np.empty(self.nbdr, dtype=np.int32)
+        _check(lib.pafem_space_boundary_dofs(self.handle, _np_ptr(out)))
+        return out
+
+    def elem_dofs(self):
+        out = np.empty((self.nelem, self.dofs_per_elem), dtype=np.int32)
+        _check(lib.pafem_space_elem_dofs(self.handle, _np_ptr(out)))
+        return out
+
+    def _check_qp_array(self, a, q1d, name):
+        if a is None:
+            return
+        need = self.nelem * q1d ** 3
+        if a.numel() != need or a.dtype != __import__("torch").float64 or not a.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 array of {need} values")
+
+    def qdata(self, kind, q1d=None, coeff=None, scale=1.0):
+        import torch
+        q1d = self.p + 2 if q1d is None else q1d
+        self._check_qp_array(coeff, q1d, "coeff")
+        qd = torch.empty(pafem_qdata_size(self.handle, kind, q1d), dtype=torch.float64,
+                         device=self.device)
+        pafem_qdata_assemble(self.handle, kind, q1d, coeff, scale, qd)
+        return qd
+
+    def linear_form(self, source=SOURCE_SINE, q1d=None, f_qp=None, scale=1.0):
+        import torch
+        q1d = self.p + 2 if q1d is None else q1d
+        self._check_qp_array(f_qp, q1d, "f_qp")
+        b = torch.empty(self.ndofs, dtype=torch.float64, device=self.device)
+        work = _device_bytes(self.nelem * self.dofs_per_elem * 8, self.device)
+        pafem_linear_form(self.handle, q1d, source, f_qp, scale, b, work)
+        return b
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.pafem_space_destroy(self.handle)
+            self.handle = None
+
+
+class Operator:
+    """y = A x for the PA mass or diffusion operator on a Space."""
+
+    def __init__(self, space: Space, kind, qdata, q1d=None, constrained=True,
+                 scatter="atomic", qdata_dtype=F64):
+        self.space, self.kind, self.qdata = space, kind, qdata
+        self.q1d = space.p + 2 if q1d is None else q1d
+        flags = (OP_CONSTRAINED if constrained else 0) | (OP_SCATTER_EVEC if scatter == "evec" else 0)
+        self.handle = pafem_op_create(space.handle, kind, self.q1d, qdata, qdata_dtype, flags)
+        self.work = _device_bytes(pafem_op_workspace_bytes(self.handle), space.device)
+
+    def _check_vec(self, v, name):
+        if v.numel() != self.space.ndofs or not v.is_contiguous() or not v.is_cuda:
+            raise ValueError(f"{name} must be a contiguous device vector of {self.space.ndofs}")
+
+    def apply(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        self._check_vec(x, "x")
+        self._check_vec(y, "y")
+        pafem_op_apply(self.handle, x, y, self.work)
+        return y
+
+    def diagonal(self):
+        import torch
+        d = torch.empty(self.space.ndofs, dtype=torch.float64, device=self.space.device)
+        pafem_op_diagonal(self.handle, d, self.work)
+        return d
+
+    def pcg(self, b, x=None, diag=None, rel_tol=1e-10, max_iter=2000, precond=PRECOND_JACOBI,
+            check_every=8, history=True):
+        import torch
+        if precond == PRECOND_JACOBI and diag is None:
+            diag = self.diagonal()
+        zero = x is None
+        if x is None:
+            x = torch.zeros_like(b)
+        for v, nm in ((b, "b"), (x, "x")) + (((diag, "diag"),) if diag is not None else ()):
+            self._check_vec(v, nm)
+        work = _device_bytes(pafem_pcg_workspace_bytes(self.handle, max_iter), self.space.device)
+        hist = np.zeros(max_iter + 1) if history else None
+        opts = SolveOpts(float(rel_tol), int(max_iter), int(precond), int(check_every), int(zero),
+                         None if hist is None else hist.ctypes.data_as(C.POINTER(C.c_double)),
+                         0 if hist is None else hist.size)
+        rc, res = pafem_pcg_solve(self.handle, diag if precond == PRECOND_JACOBI else None,
+                                  b, x, work, opts)
+        if rc not in (0, -5, -6):
+            _check(rc)
+        info = {"status": STATUS.get(rc, rc), "iters": res.iters, "converged": bool(res.converged),
+                "rel_res": res.rel_res, "true_rel_res": res.true_rel_res, "seconds": res.seconds}
+        if hist is not None:
+            info["history"] = hist[: res.iters + 1].copy()
+        return x, info
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.pafem_op_destroy(self.handle)
+            self.handle = None

@@ -52,20 +52,20 @@ def _corner_permutations() -> np.ndarray:
 CUBE_ROTATIONS = _corner_permutations()  # [24, 8]
 
 
-def hex_lattice(n: int, jitter: float = 0.0, seed: int = 0,
+def hex_lattice(n, jitter: float = 0.0, seed: int = 0,
                 rotate_seed: int | None = None) -> dict:
-    """Unit-cube lattice of n^3 hexahedra.
+    """Unit-cube lattice of nx*ny*nz hexahedra (n is an int or a 3-tuple).
 
     Interior vertices are displaced by ``jitter * h * u`` with ``u`` uniform in the
-    unit ball (h = 1/n), using ``numpy.random.default_rng(seed)``.  With
+    unit ball (h = 1/max(n)), using ``numpy.random.default_rng(seed)``.  With
     ``rotate_seed`` every element's vertex list is re-labelled by a random proper
     rotation of the cube (same geometry, different local orientation).
     Elements are numbered lexicographically (x fastest).
     """
-    n = int(n)
-    m = n + 1
-    g = np.arange(m, dtype=np.float64) / n
-    vz, vy, vx = np.meshgrid(g, g, g, indexing="ij")
+    nx, ny, nz = (int(n),) * 3 if np.isscalar(n) else tuple(int(v) for v in n)
+    mx, my, mz = nx + 1, ny + 1, nz + 1
+    vz, vy, vx = np.meshgrid(np.arange(mz) / nz, np.arange(my) / ny, np.arange(mx) / nx,
+                             indexing="ij")
     verts = np.stack([vx.ravel(), vy.ravel(), vz.ravel()], axis=1)
     if jitter > 0.0:
         rng = np.random.default_rng(seed)
@@ -73,22 +73,32 @@ def hex_lattice(n: int, jitter: float = 0.0, seed: int = 0,
         d = rng.normal(size=(nv, 3))
         d /= np.linalg.norm(d, axis=1, keepdims=True)
         r = rng.uniform(size=(nv, 1)) ** (1.0 / 3.0)
-        disp = jitter * (1.0 / n) * r * d
+        disp = jitter * (1.0 / max(nx, ny, nz)) * r * d
         ix = np.arange(nv)
-        i0, i1, i2 = ix % m, (ix // m) % m, ix // (m * m)
-        interior = (i0 > 0) & (i0 < n) & (i1 > 0) & (i1 < n) & (i2 > 0) & (i2 < n)
+        i0, i1, i2 = ix % mx, (ix // mx) % my, ix // (mx * my)
+        interior = (i0 > 0) & (i0 < nx) & (i1 > 0) & (i1 < ny) & (i2 > 0) & (i2 < nz)
         verts[interior] += disp[interior]
-    ez, ey, ex = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
-    hexes = np.empty((n ** 3, 8), dtype=np.int64)
+    hexes = np.empty((nx * ny * nz, 8), dtype=np.int64)
     for s, (cx, cy, cz) in enumerate(HEX_CORNERS):
-        hexes[:, s] = (ex + cx) + m * ((ey + cy) + m * (ez + cz))
+        hexes[:, s] = (ex + cx) + mx * ((ey + cy) + my * (ez + cz))
     if rotate_seed is not None:
         rng = np.random.default_rng(rotate_seed)
         pick = rng.integers(0, 24, size=hexes.shape[0])
         perms = CUBE_ROTATIONS[pick]
         hexes = np.take_along_axis(hexes, perms, axis=1)
-    return {"vertices": verts, "hex": hexes, "n": n, "geom_order": 1, "geom_nodes": None}
+    return {"vertices": verts, "hex": hexes, "n": (nx, ny, nz), "geom_order": 1,
+            "geom_nodes": None}
+
+
+def sub_mesh(mesh: dict, elems) -> dict:
+    """The mesh restricted to the listed elements (vertex array kept whole)."""
+    out = dict(mesh)
+    out["hex"] = mesh["hex"][elems]
+    if mesh.get("geom_nodes") is not None:
+        out["geom_nodes"] = mesh["geom_nodes"][elems]
+    return out
 
 
 def warp_sine(points: np.ndarray, amp: float) -> np.ndarray:

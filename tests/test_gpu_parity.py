@@ -1,0 +1,186 @@
+"""GPU parity of the HIP path against the CPU oracle (through the C ABI).
+
+Inputs are seeded synthetic meshes; input vectors are pseudo-random values keyed
+by dof position (``synth.hash_normal``), so each side evaluates them on its own
+dof coordinates and no input crosses from the GPU path to the oracle.  Results
+are compared after matching dofs by position.  Bar: FP64 relative error
+<= 1e-12 (norm-wise) for applies, diagonals and load vectors.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._common import OracleProblem, match_by_coords, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1911_09220_amd import pafem as P  # noqa: E402  (must load: no fallback)
+
+TOL = 1e-12
+
+# per order: lattice shape spanning several element tiles with a ragged last tile
+SHAPES = {1: (5, 5, 5), 2: (5, 4, 3), 3: (4, 4, 4), 4: (3, 3, 3), 5: (3, 3, 2),
+          6: (3, 2, 2), 7: (2, 2, 2), 8: (3, 1, 1)}
+
+
+def _cuda(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _setup(mesh, p, coeff=None, renumber=False):
+    S = P.Space(P.Mesh.from_dict(mesh), p, renumber=renumber)
+    c = None if coeff is None else _cuda(coeff)
+    return S, S.dof_coords(), c
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "evec"])
+@pytest.mark.parametrize("p", range(1, 9))
+def test_diffusion_apply(p, scatter):
+    mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=p, rotate_seed=100 + p)
+    kappa = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 1.0, seed=7)
+    S, X, kc = _setup(mesh, p, kappa, renumber=(p % 2 == 0))
+    op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kc), scatter=scatter)
+    y = op.apply(_cuda(synth.hash_normal(X, seed=p))).cpu().numpy()
+    ref = OracleProblem(mesh, p, coeff=kappa)
+    y_ref = ref.Kc @ synth.hash_normal(ref.coords, seed=p)
+    perm = match_by_coords(X, ref.coords)
+    err = rel_err(y, y_ref[perm])
+    print(f"diffusion p={p} {scatter}: rel err {err:.2e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_mass_apply(p):
+    mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=20 + p)
+    rho = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 1.0, seed=8)
+    S, X, rc = _setup(mesh, p, rho)
+    for scatter in ("atomic", "evec"):
+        op = P.Operator(S, P.MASS, S.qdata(P.MASS, coeff=rc), scatter=scatter)
+        y = op.apply(_cuda(synth.hash_normal(X, seed=3))).cpu().numpy()
+        ref = OracleProblem(mesh, p, rho=rho)
+        y_ref = ref.Mc @ synth.hash_normal(ref.coords, seed=3)
+        perm = match_by_coords(X, ref.coords)
+        assert rel_err(y, y_ref[perm]) <= TOL
+
+
+@pytest.mark.parametrize("kind", [P.DIFFUSION, P.MASS])
+@pytest.mark.parametrize("p,shape", [(1, (2, 2, 2)), (2, (2, 2, 1)), (3, (2, 1, 1)), (5, (1, 1, 1))])
+def test_brute_force_columns(kind, p, shape):
+    """A e_j for every unit vector rebuilds the oracle's assembled constrained matrix."""
+    mesh = synth.hex_lattice(shape, 0.15, seed=5, rotate_seed=6)
+    S, X, _ = _setup(mesh, p)
+    op = P.Operator(S, kind, S.qdata(kind))
+    n = S.ndofs
+    A = np.empty((n, n))
+    e = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for j in range(n):
+        e.zero_()
+        e[j] = 1.0
+        A[:, j] = op.apply(e).cpu().numpy()
+    ref = OracleProblem(mesh, p)
+    Aref = (ref.Kc if kind == P.DIFFUSION else ref.Mc).toarray()
+    perm = match_by_coords(X, ref.coords)
+    Aref = Aref[np.ix_(perm, perm)]
+    assert np.abs(A - Aref).max() <= TOL * np.abs(Aref).max()
+    assert np.abs(A - A.T).max() <= TOL * np.abs(A).max()
+
+
+@pytest.mark.parametrize("p", [2, 3, 6])
+def test_quadratic_geometry(p):
+    mesh = synth.q2_warped_lattice(2, 0.05)
+    S, X, _ = _setup(mesh, p)
+    op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION))
+    y = op.apply(_cuda(synth.hash_normal(X, seed=11))).cpu().numpy()
+    ref = OracleProblem(mesh, p)
+    perm = match_by_coords(X, ref.coords)
+    assert rel_err(y, (ref.Kc @ synth.hash_normal(ref.coords, seed=11))[perm]) <= TOL
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 8])
+def test_diagonal(p):
+    mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=30 + p, rotate_seed=31)
+    kappa = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 1.0, seed=9)
+    S, X, kc = _setup(mesh, p, kappa)
+    ref = OracleProblem(mesh, p, coeff=kappa, rho=kappa)
+    perm = match_by_coords(X, ref.coords)
+    for kind, A in ((P.DIFFUSION, ref.Kc), (P.MASS, ref.Mc)):
+        op = P.Operator(S, kind, S.qdata(kind, coeff=kc))
+        d = op.diagonal().cpu().numpy()
+        assert rel_err(d, A.diagonal()[perm]) <= TOL
+
+
+@pytest.mark.parametrize("p", [1, 3, 6])
+def test_linear_form(p):
+    mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=40 + p)
+    S, X, _ = _setup(mesh, p)
+    ref = OracleProblem(mesh, p)
+    perm = match_by_coords(X, ref.coords)
+    b = S.linear_form(P.SOURCE_SINE).cpu().numpy()
+    assert rel_err(b, ref.load(synth.sine_source)[perm]) <= TOL
+    b1 = S.linear_form(P.SOURCE_CONST, scale=2.5).cpu().numpy()
+    assert rel_err(b1, ref.load(lambda x: np.full(x.shape[:-1], 2.5))[perm]) <= TOL
+    fq = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 0.5, seed=12)
+    b2 = S.linear_form(P.SOURCE_ARRAY, f_qp=_cuda(fq)).cpu().numpy()
+    assert rel_err(b2, ref.load(fq)[perm]) <= TOL
+
+
+def test_unconstrained_invariants():
+    """Without BC: 1^T M 1 = volume = 1 and the diffusion operator annihilates constants."""
+    mesh = synth.hex_lattice(4, 0.1, seed=2)
+    S, X, _ = _setup(mesh, 3)
+    one = torch.ones(S.ndofs, dtype=torch.float64, device="cuda")
+    M = P.Operator(S, P.MASS, S.qdata(P.MASS), constrained=False)
+    K = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION), constrained=False)
+    assert abs(float(torch.dot(one, M.apply(one))) - 1.0) < 1e-13
+    assert float(K.apply(one).abs().max()) < 1e-12
+
+
+def test_evec_scatter_is_bitwise_reproducible():
+    mesh = synth.hex_lattice(6, 0.1, seed=1)
+    S, X, _ = _setup(mesh, 3)
+    op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION), scatter="evec")
+    x = _cuda(synth.hash_normal(X, seed=1))
+    y1, y2 = op.apply(x), op.apply(x)
+    assert torch.equal(y1, y2)
+
+
+def test_inverted_element_rejected():
+    mesh = synth.hex_lattice(2)
+    h = mesh["hex"].copy()
+    h[3] = h[3][[4, 5, 6, 7, 0, 1, 2, 3]]          # mirror: det J < 0 everywhere
+    S = P.Space(P.Mesh(mesh["vertices"], h), 2)
+    with pytest.raises(P.PafemError) as ei:
+        S.qdata(P.DIFFUSION)
+    assert ei.value.code == -1 and "element 3" in str(ei.value)
+
+
+def test_small_poisson_solve():
+    """Unit cube 8^3, 10% jitter, p = 2, f from the sine solution, Jacobi-PCG."""
+    mesh = synth.hex_lattice(8, 0.1, seed=1)
+    S, X, _ = _setup(mesh, 2)
+    assert S.ndofs == 4913
+    op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION))
+    b = S.linear_form(P.SOURCE_SINE)
+    x, info = op.pcg(b, rel_tol=1e-13, max_iter=2000)
+    assert info["status"] == "OK" and info["converged"]
+    assert info["true_rel_res"] < 1e-12
+    ref = OracleProblem(mesh, 2)
+    perm = match_by_coords(X, ref.coords)
+    bref = ref.load(synth.sine_source)
+    assert rel_err(b.cpu().numpy(), bref[perm]) <= TOL
+    import scipy.sparse.linalg as spla
+    xd = spla.spsolve(ref.Kc.tocsc(), bref)
+    err = rel_err(x.cpu().numpy(), xd[perm])
+    print(f"poisson: iters {info['iters']} solution rel err vs direct {err:.2e}")
+    assert err < 1e-11
+    # same iteration history as the oracle's PCG up to roundoff
+    r = oracle.pcg(ref.Kc, bref, ref.Kc.diagonal(), tol=1e-13)
+    assert abs(r["iters"] - info["iters"]) <= 2
+    hist = info["history"]
+    assert np.allclose(hist[:20], r["history"][:20], rtol=1e-8)
+    assert oracle.l2_error(ref.space, x.cpu().numpy()[np.argsort(perm)], synth.sine_solution) < 1e-3

@@ -1,0 +1,92 @@
+"""CPU tests of the C-ABI library's host logic (no GPU calls).
+
+* every symbol declared in include/pafem.h is exported by libpafem.so;
+* the element->dof map, essential dofs and dof coordinates built by the C++
+  host code agree exactly (integer for integer) with the oracle's independent
+  numbering after matching dofs by position, including randomly rotated element
+  vertex lists and the quadratic geometry;
+* error statuses for bad input.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._common import match_by_coords
+
+pafem = pytest.importorskip("paper_1911_09220_amd.pafem",
+                            reason="libpafem.so not built (run __graft_entry__.build())")
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "pafem.h")
+
+
+def test_header_symbols_exported():
+    text = open(HEADER).read()
+    names = set(re.findall(r"\b(pafem_[a-z0-9_]+)\s*\(", text))
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(pafem.lib, n), f"{n} declared in pafem.h but not exported"
+
+
+@pytest.mark.parametrize("case", [
+    ("lattice", 1, False), ("lattice", 2, False), ("lattice", 3, True), ("lattice", 4, False),
+    ("rotated", 2, False), ("rotated", 3, False), ("rotated", 5, True), ("q2", 2, False),
+    ("q2", 3, True), ("rotated", 8, False)])
+def test_element_dof_map_matches_oracle(case):
+    kind, p, renumber = case
+    if kind == "lattice":
+        mesh = synth.hex_lattice(3, 0.1, seed=3)
+    elif kind == "rotated":
+        mesh = synth.hex_lattice(3, 0.1, seed=4, rotate_seed=17)
+    else:
+        mesh = synth.q2_warped_lattice(2)
+    sp = pafem.Space(pafem.Mesh.from_dict(mesh), p, renumber=renumber, device=None)
+    ref = oracle.H1Space(mesh, p)
+    assert sp.ndofs == ref.ndofs and sp.nelem == mesh["hex"].shape[0]
+    assert sp.dofs_per_elem == (p + 1) ** 3
+    X = sp.dof_coords()
+    perm = match_by_coords(X, ref.dof_coordinates())      # lib dof i <-> oracle dof perm[i]
+    assert len(np.unique(perm)) == sp.ndofs
+    gmap = sp.elem_dofs()
+    np.testing.assert_array_equal(perm[gmap], ref.elem_dofs)
+    bd = np.zeros(sp.ndofs, dtype=bool)
+    bd[sp.boundary_dofs()] = True
+    np.testing.assert_array_equal(bd, ref.boundary[perm])
+    assert sp.nbdr == ref.boundary.sum()
+
+
+def test_default_numbering_order():
+    """Vertex dofs first, then edges, faces, interiors (the paper's global order)."""
+    mesh = synth.hex_lattice(2, 0.0)
+    sp = pafem.Space(pafem.Mesh.from_dict(mesh), 3, device=None)
+    ref = oracle.H1Space(mesh, 3)
+    perm = match_by_coords(sp.dof_coords(), ref.dof_coordinates())
+    cls = ref.dof_class[perm]              # class of lib dof i
+    assert np.all(np.diff(cls) >= 0)
+
+
+def test_bad_inputs():
+    mesh = synth.hex_lattice(2)
+    bad = mesh["hex"].copy()
+    bad[0, 0] = 10_000
+    with pytest.raises(pafem.PafemError) as ei:
+        pafem.Mesh(mesh["vertices"], bad)
+    assert ei.value.code == -1
+    rep = mesh["hex"].copy()
+    rep[1, 3] = rep[1, 0]
+    with pytest.raises(pafem.PafemError):
+        pafem.Mesh(mesh["vertices"], rep)
+    m = pafem.Mesh.from_dict(mesh)
+    with pytest.raises(pafem.PafemError) as ei:
+        pafem.Space(m, 9, device=None)
+    assert ei.value.code == -3
+    # three elements on one face: not conforming
+    h = np.concatenate([mesh["hex"], mesh["hex"][:1]], axis=0)
+    with pytest.raises(pafem.PafemError) as ei:
+        pafem.Space(pafem.Mesh(mesh["vertices"], h), 1, device=None)
+    assert ei.value.code == -1
+    with pytest.raises(pafem.PafemError):
+        pafem.Mesh(mesh["vertices"], mesh["hex"], geom_order=2)   # nodes missing
