@@ -101,7 +101,7 @@ def cpu_baseline(orders, budget_s=20.0):
     import synth
     from oracle import forms
     t_start = time.perf_counter()
-    sizes = {p: (2e5 if p <= 2 else 1e5 if p <= 4 else 4e4) for p in orders}
+    sizes = {p: (1e5 if p <= 2 else 5e4 if p <= 4 else 2e4) for p in orders}
     tot_n, tot_t, parts, t_asm = 0.0, 0.0, [], 0.0
     per_order_budget = budget_s / max(1, len(orders))
     for p in orders:
