@@ -230,6 +230,88 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
                              void* work, size_t work_bytes, const pafem_solve_opts* opts,
                              pafem_solve_result* result, void* stream);
 
+
+/* ------------------------------------------- mixed precision refinement --- */
+
+/* dst[i] = src[i] rounded to PAFEM_F32 or PAFEM_BF16 (round to nearest even),
+ * device arrays of n values.  Makes the reduced-precision copies of quadrature
+ * data for an inner operator (pafem_op_create with that qdata_dtype).
+ * Asynchronous.  Errors: EINVAL for another dtype. */
+pafem_status pafem_convert(int64_t n, const double* src, void* dst, int32_t dtype, void* stream);
+
+typedef struct {
+  double rel_tol;       /* outer stop: ||b - A_hi x||_2 <= rel_tol ||b||_2, FP64 residual */
+  double inner_rel_tol; /* inner stop: reduction of the reduced-precision PCG residual */
+  int32_t max_outer;    /* refinement steps */
+  int32_t max_inner;    /* inner PCG iterations per step */
+  int32_t check_every;  /* host reads the inner convergence flag every this many iterations */
+  int32_t precond;      /* PAFEM_PRECOND_NONE or PAFEM_PRECOND_JACOBI (diag rounded to f32) */
+  double* res_hist;     /* optional host array: outer ||r_k||/||b||, k = 0..outer */
+  int32_t res_hist_cap;
+} pafem_ir_opts;
+
+typedef struct {
+  int32_t outer;        /* refinement steps taken */
+  int32_t inner_total;  /* inner PCG iterations summed over the steps */
+  int32_t converged;    /* 1 if rel_tol was met */
+  double rel_res;       /* final ||b - A_hi x|| / ||b|| (FP64) */
+  double seconds;       /* wall time of the call */
+} pafem_ir_result;
+
+/* Workspace bytes of pafem_ir_solve for this pair of operators. */
+pafem_status pafem_ir_workspace_bytes(pafem_op a_hi, pafem_op a_lo, size_t* nbytes);
+
+/* Iterative refinement: x = 0; repeat r = b - A_hi x (FP64 apply, FP64 residual
+ * and norms), solve A_lo d = r/||r|| approximately with Jacobi-PCG whose vectors
+ * are FP32 and whose dot products accumulate in FP64, x += ||r|| d (FP64).
+ * a_hi: an FP64 operator; a_lo: the same operator (same space, kind and flags)
+ * built on F32 or BF16 quadrature data.  diag: FP64 diagonal of a_hi (NULL for
+ * PAFEM_PRECOND_NONE).  b, x: device f64 [ndofs].  SYNCHRONOUS.  Returns
+ * ENOTCONV if max_outer steps do not reach rel_tol (result filled in). */
+pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, const double* b,
+                            double* x, void* work, size_t work_bytes, const pafem_ir_opts* opts,
+                            pafem_ir_result* result, void* stream);
+
+
+/* ------------------------------------------------------------- batched --- */
+
+/* Many right-hand sides over many meshes in one graph launch.  Each operator
+ * (one per mesh; same kind; all F64 or all F32 quadrature data; orders 1..6,
+ * q1d = p+2) applies to nrhs vectors stored right-hand-side fastest:
+ * x_m[dof][rhs], y_m[dof][rhs] (device, f64 for F64 operators, f32 for F32).
+ * The batch groups the meshes by order (one grouped launch per order), and
+ * captures the whole batch into a HIP graph that replays on the caller's stream.
+ * The tile shape of each order (elements x right-hand sides per workgroup) is
+ * chosen by pafem_batch_autotune, or set by hand. */
+typedef struct pafem_batch_s* pafem_batch;
+
+/* Device workspace for the mesh descriptors of a batch of nops operators. */
+pafem_status pafem_batch_workspace_bytes(int32_t nops, size_t* nbytes);
+
+/* nrhs: even and >= 2.  work: device workspace (kept by the batch). */
+pafem_status pafem_batch_create(int32_t nops, const pafem_op* ops, int32_t nrhs, void* work,
+                                size_t work_bytes, pafem_batch* out);
+void pafem_batch_destroy(pafem_batch batch);
+
+/* y_m = A_m x_m for every mesh m (x, y: host arrays of nops device pointers).
+ * Constrained operators return y_b = x_b on essential dofs.  Asynchronous; the
+ * graph is (re)captured when the pointers or tiles change. */
+pafem_status pafem_batch_apply(pafem_batch batch, const void* const* x, void* const* y,
+                               void* stream);
+
+/* Time every tile candidate of every order `reps` times on these vectors (their
+ * y contents are overwritten) and keep the fastest; results are read from and
+ * written to the text cache `cache_path` (NULL: no cache), keyed by GPU
+ * architecture, kind, dtype, nrhs and order.  SYNCHRONOUS. */
+pafem_status pafem_batch_autotune(pafem_batch batch, const void* const* x, void* const* y,
+                                  const char* cache_path, int32_t reps, void* stream);
+
+/* Force the tile candidate (0..4, -1 = default) for the meshes of one order. */
+pafem_status pafem_batch_set_tile(pafem_batch batch, int32_t order, int32_t candidate);
+
+/* JSON description of the groups, chosen tiles and tuning timings into buf. */
+pafem_status pafem_batch_describe(pafem_batch batch, char* buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

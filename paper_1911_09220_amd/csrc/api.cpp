@@ -10,6 +10,8 @@
 #include <string>
 
 #include "internal.hpp"
+#include "batch_host.hpp"
+#include "capi.hpp"
 #include "launch.hpp"
 #include "solver.hpp"
 
@@ -24,24 +26,11 @@ struct pafem_space_s {
 struct pafem_op_s {
   Op op;
 };
+struct pafem_batch_s {
+  Batch* b;
+};
 
 namespace {
-
-thread_local std::string g_last_error;
-
-pafem_status fail(pafem_status code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
-}
-
-void hip_check(hipError_t err, const char* what) {
-  if (err != hipSuccess) throw Error(PAFEM_EHIP, std::string(what) + ": " + hipGetErrorString(err));
-}
-
-void require(bool cond, pafem_status code, const std::string& msg) {
-  if (!cond) throw Error(code, msg);
-}
-
 const Space& uploaded_space(pafem_space sp) {
   require(sp != nullptr && sp->s != nullptr, PAFEM_EINVAL, "null space");
   require(sp->s->uploaded, PAFEM_EINVAL, "space has no device image: call pafem_space_upload");
@@ -60,7 +49,9 @@ size_t dtype_size(int dt) {
 // vector type used by an operator with the given qdata type
 int vector_dtype(int qdtype) { return qdtype == PAFEM_F64 ? PAFEM_F64 : PAFEM_F32; }
 
-size_t op_work_bytes(const Op& op) {
+}  // namespace
+
+size_t pafem::op_work_bytes(const Op& op) {
   const Space& s = *op.space;
   const size_t evec = size_t(s.ne) * s.dpe;
   // diagonal needs an f64 element vector; the deterministic scatter an element
@@ -69,23 +60,11 @@ size_t op_work_bytes(const Op& op) {
   return align256(need);
 }
 
-template <typename F>
-pafem_status guarded(F&& f) {
-  try {
-    f();
-    return PAFEM_OK;
-  } catch (const Error& e) {
-    g_last_error = e.what();
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    g_last_error = "out of host memory";
-    return PAFEM_EINVAL;
-  } catch (const std::exception& e) {
-    g_last_error = e.what();
-    return PAFEM_EINVAL;
-  }
-}
+namespace {
 
+}  // namespace
+
+namespace pafem {
 // One application of the operator; `work` must hold op_work_bytes(op).
 void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st) {
   const Space& s = *op.space;
@@ -114,8 +93,11 @@ void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st) 
             PAFEM_EUNSUPPORTED, "apply kernel not built for this order/q1d/dtype");
   }
 }
+}  // namespace pafem
 
-}  // namespace
+namespace pafem {
+thread_local std::string g_last_error;
+}
 
 extern "C" {
 
@@ -212,7 +194,7 @@ pafem_status pafem_space_elem_dofs(pafem_space space, int32_t* gmap) {
 pafem_status pafem_space_device_bytes(pafem_space space, size_t* nbytes) {
   return guarded([&] {
     require(space && space->s && nbytes, PAFEM_EINVAL, "null pointer argument");
-    size_t off[8];
+    size_t off[kSpaceSegments + 1];
     space_device_layout(*space->s, off, nbytes);
   });
 }
@@ -224,7 +206,7 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     require((reinterpret_cast<uintptr_t>(device_buf) & 255) == 0, PAFEM_EINVAL,
             "device buffer must be 256-byte aligned");
     Space& s = *space->s;
-    size_t off[8], total = 0;
+    size_t off[kSpaceSegments + 1], total = 0;
     space_device_layout(s, off, &total);
     require(nbytes >= total, PAFEM_ESHAPE,
             "device buffer too small: need " + std::to_string(total) + " bytes");
@@ -233,19 +215,20 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     space_pack(s, gmap_enc, gnodes, toff, tidx);
     auto st = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(device_buf);
-    hip_check(hipMemcpyAsync(base + off[0], gmap_enc.data(), gmap_enc.size() * 4,
-                             hipMemcpyHostToDevice, st), "upload gmap");
-    hip_check(hipMemcpyAsync(base + off[1], gnodes.data(), gnodes.size() * 8,
-                             hipMemcpyHostToDevice, st), "upload geometry");
-    hip_check(hipMemcpyAsync(base + off[2], s.bmask.data(), s.bmask.size(),
-                             hipMemcpyHostToDevice, st), "upload boundary mask");
-    hip_check(hipMemcpyAsync(base + off[3], toff.data(), toff.size() * 4,
-                             hipMemcpyHostToDevice, st), "upload transposed offsets");
-    hip_check(hipMemcpyAsync(base + off[4], tidx.data(), tidx.size() * 4,
-                             hipMemcpyHostToDevice, st), "upload transposed map");
-    hip_check(hipMemcpyAsync(base + off[5], s.tables.data(), s.tables.size() * 8,
-                             hipMemcpyHostToDevice, st), "upload tables");
+    auto up = [&](int seg, const void* src, size_t bytes, const char* what) {
+      if (bytes) hip_check(hipMemcpyAsync(base + off[seg], src, bytes, hipMemcpyHostToDevice, st), what);
+    };
+    up(0, gmap_enc.data(), gmap_enc.size() * 4, "upload gmap");
+    up(1, gnodes.data(), gnodes.size() * 8, "upload geometry");
+    up(2, s.bmask.data(), s.bmask.size(), "upload boundary mask");
+    up(3, toff.data(), toff.size() * 4, "upload transposed offsets");
+    up(4, tidx.data(), tidx.size() * 4, "upload transposed map");
+    up(5, s.tables.data(), s.tables.size() * 8, "upload tables");
     hip_check(hipMemsetAsync(base + off[6], 0, 64 * 4, st), "clear status");
+    up(7, s.dev_order.data(), s.dev_order.size() * 4, "upload element order");
+    up(8, s.tile_off.data(), s.tile_off.size() * 4, "upload tile offsets");
+    up(9, s.tile_dofs.data(), s.tile_dofs.size() * 4, "upload tile dofs");
+    up(10, s.tile_slot.data(), s.tile_slot.size() * 2, "upload tile slots");
     hip_check(hipStreamSynchronize(st), "upload sync");
     s.dev_buf = device_buf;
     s.dev_bytes = nbytes;
@@ -256,10 +239,15 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     s.dev.tidx = reinterpret_cast<const int32_t*>(base + off[4]);
     s.dev.tables = reinterpret_cast<const double*>(base + off[5]);
     s.dev.status = reinterpret_cast<int32_t*>(base + off[6]);
+    s.dev.elem_orig = reinterpret_cast<const int32_t*>(base + off[7]);
+    s.dev.tile_off = reinterpret_cast<const int32_t*>(base + off[8]);
+    s.dev.tile_dofs = reinterpret_cast<const int32_t*>(base + off[9]);
+    s.dev.tile_slot = reinterpret_cast<const uint16_t*>(base + off[10]);
     s.dev.ne = s.ne;
     s.dev.ndofs = s.ndofs;
     s.dev.p = s.p;
     s.dev.ng = s.ng;
+    s.dev.tile_ne = s.tile_ne;
     s.uploaded = true;
   });
 }
@@ -269,8 +257,7 @@ pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int6
     require(space && space->s && nvalues, PAFEM_EINVAL, "null pointer argument");
     require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, PAFEM_EINVAL, "unknown operator kind");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
-    const int64_t qqq = int64_t(q1d) * q1d * q1d;
-    *nvalues = space->s->ne * qqq * (kind == PAFEM_DIFFUSION ? 6 : 1);
+    *nvalues = qdata_values(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 6 : 1);
   });
 }
 
@@ -423,8 +410,8 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
 
     launch_cg_reset(state, opts->max_iter + 1, st);
     if (!opts->zero_guess) apply_op(o, x, q, opwork, st);
-    launch_cg_init(state, partials, b, opts->zero_guess ? nullptr : q, dg, x, r, d,
-                   opts->zero_guess, opts->rel_tol, hist, n, st);
+    launch_cg_init<double, double>(state, partials, b, 1.0, opts->zero_guess ? nullptr : q, dg,
+                                   x, r, d, opts->zero_guess, opts->rel_tol, hist, n, st);
     CGState host{};
     int launched = 0;
     while (true) {
@@ -443,7 +430,7 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
     }
     // true residual ||b - A x||
     apply_op(o, x, q, opwork, st);
-    launch_residual_norm(state, partials, b, q, n, st);
+    launch_residual(state, partials, b, q, nullptr, n, st);
     hip_check(hipMemcpyAsync(&host, state, sizeof(CGState), hipMemcpyDeviceToHost, st),
               "state read");
     hip_check(hipStreamSynchronize(st), "solver sync");
@@ -466,6 +453,227 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
     result->seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return rc != PAFEM_OK ? rc : status;
+}
+
+
+pafem_status pafem_convert(int64_t n, const double* src, void* dst, int32_t dtype, void* stream) {
+  return guarded([&] {
+    require(n >= 0, PAFEM_EINVAL, "negative length");
+    require(dtype == PAFEM_F32 || dtype == PAFEM_BF16, PAFEM_EINVAL, "dtype must be F32 or BF16");
+    if (n == 0) return;
+    require(src && dst, PAFEM_EINVAL, "null pointer argument");
+    launch_convert(src, dst, dtype, n, static_cast<hipStream_t>(stream));
+  });
+}
+
+namespace {
+
+struct IRLayout {
+  size_t state_hi, state_lo, partials, r64, q64, x32, r32, d32, q32, diag32, opwork, total;
+};
+
+IRLayout ir_layout(const Op& hi, const Op& lo) {
+  const size_t n = size_t(hi.space->ndofs);
+  IRLayout L{};
+  size_t o = 0;
+  L.state_hi = o; o += align256(sizeof(CGState));
+  L.state_lo = o; o += align256(sizeof(CGState));
+  L.partials = o; o += align256(3 * kCGBlocks * sizeof(double));
+  L.r64 = o; o += align256(n * 8);
+  L.q64 = o; o += align256(n * 8);
+  L.x32 = o; o += align256(n * 4);
+  L.r32 = o; o += align256(n * 4);
+  L.d32 = o; o += align256(n * 4);
+  L.q32 = o; o += align256(n * 4);
+  L.diag32 = o; o += align256(n * 4);
+  L.opwork = o; o += std::max(op_work_bytes(hi), op_work_bytes(lo));
+  L.total = o;
+  return L;
+}
+
+void check_ir_pair(const Op& hi, const Op& lo) {
+  require(hi.qdtype == PAFEM_F64, PAFEM_EINVAL, "a_hi must be an FP64 operator");
+  require(lo.qdtype == PAFEM_F32 || lo.qdtype == PAFEM_BF16, PAFEM_EINVAL,
+          "a_lo must use F32 or BF16 quadrature data");
+  require(hi.space == lo.space && hi.kind == lo.kind && hi.q1d == lo.q1d &&
+              hi.flags == lo.flags,
+          PAFEM_EINVAL, "a_hi and a_lo must be the same operator on the same space");
+}
+
+}  // namespace
+
+pafem_status pafem_ir_workspace_bytes(pafem_op a_hi, pafem_op a_lo, size_t* nbytes) {
+  return guarded([&] {
+    require(a_hi && a_lo && nbytes, PAFEM_EINVAL, "null pointer argument");
+    check_ir_pair(a_hi->op, a_lo->op);
+    *nbytes = ir_layout(a_hi->op, a_lo->op).total;
+  });
+}
+
+pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, const double* b,
+                            double* x, void* work, size_t work_bytes, const pafem_ir_opts* opts,
+                            pafem_ir_result* result, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  pafem_status status = PAFEM_OK;
+  pafem_status rc = guarded([&] {
+    require(a_hi && a_lo && b && x && work && opts && result, PAFEM_EINVAL,
+            "null pointer argument");
+    const Op& hi = a_hi->op;
+    const Op& lo = a_lo->op;
+    check_ir_pair(hi, lo);
+    require(opts->precond == PAFEM_PRECOND_NONE || (opts->precond == PAFEM_PRECOND_JACOBI && diag),
+            PAFEM_EINVAL, "Jacobi preconditioner needs diag");
+    require(opts->max_outer >= 0 && opts->max_inner >= 1 && opts->rel_tol >= 0.0 &&
+                opts->inner_rel_tol > 0.0,
+            PAFEM_EINVAL, "bad solver options");
+    const IRLayout L = ir_layout(hi, lo);
+    require(work_bytes >= L.total, PAFEM_ESHAPE,
+            "workspace too small: need " + std::to_string(L.total));
+    const int64_t n = hi.space->ndofs;
+    char* w = static_cast<char*>(work);
+    auto* st_hi = reinterpret_cast<CGState*>(w + L.state_hi);
+    auto* st_lo = reinterpret_cast<CGState*>(w + L.state_lo);
+    auto* partials = reinterpret_cast<double*>(w + L.partials);
+    auto* r64 = reinterpret_cast<double*>(w + L.r64);
+    auto* q64 = reinterpret_cast<double*>(w + L.q64);
+    auto* x32 = reinterpret_cast<float*>(w + L.x32);
+    auto* r32 = reinterpret_cast<float*>(w + L.r32);
+    auto* d32 = reinterpret_cast<float*>(w + L.d32);
+    auto* q32 = reinterpret_cast<float*>(w + L.q32);
+    auto* diag32 = reinterpret_cast<float*>(w + L.diag32);
+    void* opwork = w + L.opwork;
+    auto st = static_cast<hipStream_t>(stream);
+    const bool jac = opts->precond == PAFEM_PRECOND_JACOBI;
+    const int check = std::max(1, opts->check_every);
+    if (jac) launch_convert(diag, diag32, PAFEM_F32, n, st);
+    hip_check(hipMemsetAsync(x, 0, size_t(n) * 8, st), "zero x");
+    launch_cg_reset(st_hi, 0, st);
+    // ||b||
+    hip_check(hipMemsetAsync(q64, 0, size_t(n) * 8, st), "zero q");
+    launch_residual(st_hi, partials, b, q64, r64, n, st);
+    CGState h{};
+    hip_check(hipMemcpyAsync(&h, st_hi, sizeof(CGState), hipMemcpyDeviceToHost, st), "state read");
+    hip_check(hipStreamSynchronize(st), "ir sync");
+    const double bb = h.res2;
+    double rr = bb;
+    int outer = 0, inner_total = 0;
+    bool converged = bb == 0.0;
+    if (opts->res_hist && opts->res_hist_cap > 0) opts->res_hist[0] = bb > 0 ? 1.0 : 0.0;
+    while (!converged && outer < opts->max_outer) {
+      const double s = std::sqrt(rr);
+      // inner: reduced-precision Jacobi-PCG on A_lo d = r / ||r||, from d = 0
+      launch_cg_reset(st_lo, 0, st);
+      launch_cg_init<double, float>(st_lo, partials, r64, 1.0 / s, nullptr, jac ? diag32 : nullptr,
+                                    x32, r32, d32, 1, opts->inner_rel_tol, nullptr, n, st);
+      int launched = 0;
+      CGState hl{};
+      while (true) {
+        hip_check(hipMemcpyAsync(&hl, st_lo, sizeof(CGState), hipMemcpyDeviceToHost, st),
+                  "state read");
+        hip_check(hipStreamSynchronize(st), "ir sync");
+        if (hl.done || launched >= opts->max_inner) break;
+        const int batch = std::min(check, opts->max_inner - launched);
+        for (int k = 0; k < batch; ++k) {
+          apply_op(lo, d32, q32, opwork, st);
+          launch_cg_dot<float>(st_lo, partials, d32, q32, n, st);
+          launch_cg_update<float>(st_lo, partials, x32, r32, d32, q32, jac ? diag32 : nullptr,
+                                  nullptr, n, st);
+          launch_cg_direction<float>(st_lo, r32, jac ? diag32 : nullptr, d32, n, st);
+        }
+        launched += batch;
+      }
+      inner_total += hl.iter;
+      launch_ir_correct(x, x32, s, n, st);
+      ++outer;
+      // FP64 residual of the refined iterate
+      apply_op(hi, x, q64, opwork, st);
+      launch_residual(st_hi, partials, b, q64, r64, n, st);
+      hip_check(hipMemcpyAsync(&h, st_hi, sizeof(CGState), hipMemcpyDeviceToHost, st),
+                "state read");
+      hip_check(hipStreamSynchronize(st), "ir sync");
+      rr = h.res2;
+      if (opts->res_hist && outer < opts->res_hist_cap) opts->res_hist[outer] = std::sqrt(rr / bb);
+      converged = rr <= opts->rel_tol * opts->rel_tol * bb;
+      if (!std::isfinite(rr)) break;
+    }
+    result->outer = outer;
+    result->inner_total = inner_total;
+    result->converged = converged;
+    result->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    if (!converged)
+      status = fail(PAFEM_ENOTCONV, "iterative refinement did not reach the tolerance in " +
+                                        std::to_string(outer) + " steps");
+  });
+  if (result)
+    result->seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return rc != PAFEM_OK ? rc : status;
+}
+
+
+pafem_status pafem_batch_workspace_bytes(int32_t nops, size_t* nbytes) {
+  return guarded([&] {
+    require(nops > 0 && nbytes, PAFEM_EINVAL, "bad arguments");
+    *nbytes = Batch::workspace_bytes(nops);
+  });
+}
+
+pafem_status pafem_batch_create(int32_t nops, const pafem_op* ops, int32_t nrhs, void* work,
+                                size_t work_bytes, pafem_batch* out) {
+  return guarded([&] {
+    require(nops > 0 && ops && out, PAFEM_EINVAL, "bad arguments");
+    std::vector<const Op*> v;
+    for (int i = 0; i < nops; ++i) {
+      require(ops[i] != nullptr, PAFEM_EINVAL, "null operator in batch");
+      v.push_back(&ops[i]->op);
+    }
+    auto* b = new pafem_batch_s();
+    try {
+      b->b = new Batch(v, nrhs, work, work_bytes);
+    } catch (...) {
+      delete b;
+      throw;
+    }
+    *out = b;
+  });
+}
+
+void pafem_batch_destroy(pafem_batch batch) {
+  if (!batch) return;
+  delete batch->b;
+  delete batch;
+}
+
+pafem_status pafem_batch_apply(pafem_batch batch, const void* const* x, void* const* y,
+                               void* stream) {
+  return guarded([&] {
+    require(batch && x && y, PAFEM_EINVAL, "null pointer argument");
+    batch->b->apply(x, y, static_cast<hipStream_t>(stream));
+  });
+}
+
+pafem_status pafem_batch_autotune(pafem_batch batch, const void* const* x, void* const* y,
+                                  const char* cache_path, int32_t reps, void* stream) {
+  return guarded([&] {
+    require(batch && x && y, PAFEM_EINVAL, "null pointer argument");
+    batch->b->autotune(x, y, cache_path, reps, static_cast<hipStream_t>(stream));
+  });
+}
+
+pafem_status pafem_batch_set_tile(pafem_batch batch, int32_t order, int32_t candidate) {
+  return guarded([&] {
+    require(batch != nullptr, PAFEM_EINVAL, "null batch");
+    batch->b->set_candidate(order, candidate);
+  });
+}
+
+pafem_status pafem_batch_describe(pafem_batch batch, char* buf, size_t len) {
+  return guarded([&] {
+    require(batch && buf && len > 0, PAFEM_EINVAL, "bad arguments");
+    const std::string d = batch->b->describe();
+    require(d.size() < len, PAFEM_ESHAPE, "buffer too small: need " + std::to_string(d.size() + 1));
+    std::memcpy(buf, d.c_str(), d.size() + 1);
+  });
 }
 
 }  // extern "C"

@@ -1,0 +1,34 @@
+// Batched multi-right-hand-side apply over many meshes: device descriptors and
+// launchers (k_batch.hip), used by the host batch object (batch.cpp).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace pafem {
+
+// One mesh of a batch, as the kernels see it.
+struct BatchMesh {
+  const int32_t* gmap;   // device-order element->dof map, ~g on essential dofs
+  const uint8_t* bmask;  // essential-dof mask
+  const void* qdata;     // tile-interleaved quadrature data
+  const void* x;         // [ndofs][nrhs]
+  void* y;               // [ndofs][nrhs]
+  int32_t ne, ndofs;
+  int32_t block_begin;   // first workgroup of this mesh within its order's launch
+  int32_t constrained;
+};
+
+constexpr int kBatchCandidates = 5;
+int batch_tile_elems(int cand);
+int batch_tile_rhs(int cand);
+// Launches the multi-rhs apply of one order group; false if the (order,
+// candidate, dtype) combination is not built.
+bool launch_batch_apply(int p, int cand, int vdtype, int qdtype, int kind,
+                        const BatchMesh* meshes, int nmesh, int nblocks, const double* tabB,
+                        const double* tabG, int nrhs, hipStream_t st);
+void launch_batch_init(int vdtype, const BatchMesh* meshes, int nmesh, int nrhs, hipStream_t st);
+
+}  // namespace pafem

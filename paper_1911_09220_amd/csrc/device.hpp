@@ -64,4 +64,37 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return t;
 }
 
+// ---- deterministic grid reductions -------------------------------------------
+// Each block stores one partial per quantity; the last block to arrive (atomic
+// ticket) sums all partials in index order.
+
+__device__ __forceinline__ void store_partial(double* partials, double v) {
+  __hip_atomic_store(&partials[blockIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_partial(const double* partials, int i) {
+  return __hip_atomic_load(const_cast<double*>(&partials[i]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publishes this block's partials (thread 0 already stored them) and returns true in
+// every thread of the last block to arrive.
+__device__ inline bool arrive_last(uint32_t* ticket) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t t = atomicAdd(ticket, 1u);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+// Sum of partials[0..gridDim.x) in a fixed order, valid in every thread.
+__device__ inline double sum_partials(const double* partials, double* scratch) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < int(gridDim.x); i += blockDim.x) v += load_partial(partials, i);
+  return block_sum(v, scratch);
+}
+
 }  // namespace pafem

@@ -23,6 +23,25 @@ struct Error : std::runtime_error {
 
 inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+// Quadrature data is stored tile-interleaved: elements are grouped in tiles of
+// qdata_tile(Q) consecutive elements, and within a tile the values are ordered
+// [component][qz][element in tile][qy][qx].  One load instruction of the fused
+// apply (all threads of a tile reading component c at plane qz) is then one
+// contiguous run.  The last tile is padded.
+constexpr int qdata_tile(int Q) { return (256 / (Q * Q)) > 0 ? (256 / (Q * Q)) : 1; }
+// Offset of value (e, component c, point q = qz*Q*Q + r) with nc components.
+constexpr size_t qdata_index(int64_t e, int c, int q, int Q, int nc) {
+  const int nt = qdata_tile(Q), qq = Q * Q;
+  const int64_t tile = e / nt;
+  const int el = int(e - tile * nt);
+  const int qz = q / qq, r = q - qz * qq;
+  return ((size_t(tile) * nc + c) * Q + qz) * size_t(nt * qq) + size_t(el) * qq + r;
+}
+inline int64_t qdata_values(int64_t ne, int Q, int nc) {
+  const int nt = qdata_tile(Q);
+  return ((ne + nt - 1) / nt) * nt * int64_t(nc) * Q * Q * Q;
+}
+
 // ---- 1D tables (tables.cpp) -------------------------------------------------
 // Gauss-Legendre rule on [0,1]: points and weights, ascending.
 void gauss_legendre_01(int q, double* x, double* w);
@@ -46,16 +65,23 @@ inline size_t table_offset_doubles(int Q, int D, int NG) {
 std::vector<double> build_tables(int p, int ng);
 
 // ---- device image of a space -------------------------------------------------
+// Device image.  Element arrays are in the device element order (a Morton order
+// of element centroids, so consecutive elements -- and each apply tile -- are
+// spatially compact); elem_orig maps back to the caller's element numbering.
 struct DevSpace {
-  const int32_t* gmap = nullptr;   // [ne][D^3], essential dofs stored as ~g
-  const double* gnodes = nullptr;  // [ne][NG^3][3]
-  const uint8_t* bmask = nullptr;  // [ndofs] 1 on essential dofs
-  const int32_t* toff = nullptr;   // [ndofs+1] transposed map offsets
-  const int32_t* tidx = nullptr;   // [ne*D^3] element-vector entries per dof (ascending)
-  const double* tables = nullptr;  // 1D tables for q1d = 1..kMaxQ1d
-  int32_t* status = nullptr;       // [64] small device status words
+  const int32_t* gmap = nullptr;       // [ne][D^3], essential dofs stored as ~g
+  const double* gnodes = nullptr;      // [ne][NG^3][3]
+  const uint8_t* bmask = nullptr;      // [ndofs] 1 on essential dofs
+  const int32_t* toff = nullptr;       // [ndofs+1] transposed map offsets
+  const int32_t* tidx = nullptr;       // [ne*D^3] element-vector entries per dof (ascending)
+  const double* tables = nullptr;      // 1D tables for q1d = 1..kMaxQ1d
+  int32_t* status = nullptr;           // [64] small device status words
+  const int32_t* elem_orig = nullptr;  // [ne] caller element id of each device element
+  const int32_t* tile_off = nullptr;   // [ntiles+1] offsets into tile_dofs
+  const int32_t* tile_dofs = nullptr;  // unique dofs of each apply tile (~g if essential)
+  const uint16_t* tile_slot = nullptr; // [ntiles*tile_ne*D^3] node -> index in its tile's list
   int64_t ne = 0, ndofs = 0;
-  int p = 0, ng = 0;
+  int p = 0, ng = 0, tile_ne = 0;
 };
 
 struct Mesh {
@@ -70,7 +96,11 @@ struct Space {
   const Mesh* mesh = nullptr;
   int p = 0, D1 = 0, dpe = 0, ng = 0;
   int64_t ne = 0, ndofs = 0;
-  std::vector<int32_t> gmap;      // [ne][dpe] dof ids
+  std::vector<int32_t> gmap;      // [ne][dpe] dof ids, caller element order
+  std::vector<int32_t> dev_order; // device element position -> caller element id
+  int tile_ne = 0;                // elements per apply tile (qdata_tile(p + 2))
+  std::vector<int32_t> tile_off, tile_dofs;
+  std::vector<uint16_t> tile_slot;
   std::vector<uint8_t> bmask;     // [ndofs]
   std::vector<int32_t> bdr;       // essential dofs ascending
   std::vector<double> ref_nodes;  // Gauss-Lobatto nodes [D1]
@@ -85,7 +115,8 @@ struct Space {
 // space.cpp
 Space* build_space(const Mesh* mesh, int order, int flags);
 void space_dof_coords(const Space& s, double* xyz);
-void space_device_layout(const Space& s, size_t* offsets /*[8]*/, size_t* total);
+constexpr int kSpaceSegments = 11;
+void space_device_layout(const Space& s, size_t* offsets /*[kSpaceSegments+1]*/, size_t* total);
 // host copies of every device array, in upload order
 void space_pack(const Space& s, std::vector<int32_t>& gmap_enc, std::vector<double>& gnodes,
                 std::vector<int32_t>& toff, std::vector<int32_t>& tidx);

@@ -4,15 +4,17 @@
 //
 // One workgroup holds NE elements; each element gets a Q x Q plane of threads
 // (qx, qy) that walks the third direction in registers.  Per element:
-//   G    gather x_E = x[gmap] into LDS (essential dofs read as 0 when constrained)
+//   G    gather the tile's unique dofs once into LDS (essential dofs read as 0 when
+//        constrained) and expand them to the element nodes through a slot map
 //   B    three one-axis contractions with the 1D tables (sum factorization):
 //        x-axis through LDS, y-axis through LDS into registers, z-axis in registers
 //   D    pointwise: 1 value (mass) or a symmetric 3x3 (diffusion) per point,
 //        streamed from HBM once with non-temporal loads, issued before the gather
 //   B^t  the transposed contractions in reverse order (z in registers, y and x
 //        through LDS)
-//   G^t  either hardware FP atomics into y (y pre-set by a init kernel) or a
-//        plain store of the element vector for the deterministic transposed gather.
+//   G^t  either: sum the element outputs per unique dof of the tile in LDS, then one
+//        hardware FP atomic per unique dof into y (y pre-set by an init kernel); or
+//        a plain store of the element vector for the deterministic transposed gather.
 // Blocks are remapped so each XCD processes one contiguous range of elements.
 #include "device.hpp"
 #include "launch.hpp"
@@ -21,14 +23,16 @@ namespace pafem {
 
 namespace {
 
+// one workgroup = one tile of the tile-interleaved quadrature data
 template <int Q>
 constexpr int elems_per_block() {
-  return (256 / (Q * Q)) > 0 ? (256 / (Q * Q)) : 1;
+  return qdata_tile(Q);
 }
 
 template <int P, int Q, int KIND, bool EVEC, typename TV, typename TD, typename TC>
 __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
-    pa_apply_kernel(const int32_t* __restrict__ gmap, const double* __restrict__ tabB,
+    pa_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
+                    const uint16_t* __restrict__ tile_slot, const double* __restrict__ tabB,
                     const double* __restrict__ tabG, const TD* __restrict__ qd,
                     const TV* __restrict__ x, TV* __restrict__ y, int ne, int constrained) {
   constexpr int D = P + 1, QQ = Q * Q, QQQ = Q * Q * Q, DDD = D * D * D;
@@ -44,12 +48,22 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   __shared__ TC sA[NE][NA][D][D][Q];
   __shared__ TC sC[NE][NCC][D][Q][Q];
 
+  // The tile's unique dofs: x is gathered once per unique dof into sX, and the
+  // element outputs are summed per unique dof in sY before one global atomic
+  // per unique dof.  sX aliases sC (not live before the z-loop ends), sY aliases
+  // sU (not live after the x-contraction).
+  TC* const sX = &sC[0][0][0][0][0];
+  TC* const sY = &sU[0][0][0][0];
+
   const int tid = threadIdx.x;
   const int el = tid / QQ;
   const int r = tid - el * QQ;
   const int qx = r % Q, qy = r / Q;
-  const int e = xcd_remap(blockIdx.x, gridDim.x) * NE + el;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int e = tile * NE + el;
   const bool act = e < ne;
+  const int u0 = tile_off[tile];
+  const int nu = tile_off[tile + 1] - u0;
 
   for (int i = tid; i < Q * D; i += NE * QQ) {
     (&sB[0][0])[i] = TC(tabB[i]);
@@ -58,28 +72,47 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 
   // D for this thread's (qx, qy) column: issued first so the HBM stream overlaps
   // the gather and the forward contractions
+  // (tile-interleaved: for each (c, qz) the workgroup reads one contiguous run)
   TC dq[Q][NC];
   if (act) {
-    const TD* qe = qd + size_t(e) * NC * QQQ + r;
+    const TD* qe = qd + size_t(e / NE) * NC * QQQ * NE + tid;
 #pragma unroll
     for (int qz = 0; qz < Q; ++qz)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) dq[qz][c] = load_value<TC, TD>(qe + c * QQQ + qz * QQ);
+      for (int c = 0; c < NC; ++c)
+        dq[qz][c] = load_value<TC, TD>(qe + (c * Q + qz) * (NE * QQ));
   }
 
-  // G: gather
-  int gidx[D];
+  // G: gather the tile's unique dofs, then expand to the element nodes
+  // four unique dofs per thread per step keep several gathers in flight
+  for (int s0 = tid; s0 < nu; s0 += 4 * NE * QQ) {
+    int gg[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int s = s0 + k * NE * QQ;
+      gg[k] = s < nu ? tile_dofs[u0 + s] : 0;
+    }
+    TC xv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int g = gg[k];
+      xv[k] = (s0 + k * NE * QQ < nu && !(constrained && g < 0)) ? TC(x[g < 0 ? ~g : g]) : TC(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (s0 + k * NE * QQ < nu) sX[s0 + k * NE * QQ] = xv[k];
+  }
+  int slot[D];
   const bool dof_thread = act && qx < D && qy < D;
   if (dof_thread) {
-    const int32_t* ge = gmap + size_t(e) * DDD + qy * D + qx;
+    const uint16_t* sl = tile_slot + size_t(e) * DDD + qy * D + qx;
 #pragma unroll
-    for (int dz = 0; dz < D; ++dz) {
-      const int g = ge[dz * D * D];
-      gidx[dz] = g;
-      TC v = TC(0);
-      if (!(constrained && g < 0)) v = TC(x[g < 0 ? ~g : g]);
-      sU[el][dz][qy][qx] = v;
-    }
+    for (int dz = 0; dz < D; ++dz) slot[dz] = sl[dz * D * D];
+  }
+  __syncthreads();
+  if (dof_thread) {
+#pragma unroll
+    for (int dz = 0; dz < D; ++dz) sU[el][dz][qy][qx] = sX[slot[dz]];
   }
   __syncthreads();
 
@@ -99,6 +132,10 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
     }
   }
   __syncthreads();
+
+  // sU is dead from here on: clear the per-unique-dof accumulators it now holds
+  if (!EVEC)
+    for (int s = tid; s < nu; s += NE * QQ) sY[s] = TC(0);
 
   // B, y-axis into registers: thread (qx, qy)
   TC BB[D], GB[D], BG[D];
@@ -198,13 +235,19 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
         acc += sB[q1][qx] * sA[el][0][dz][qy][q1];
         if (DIFF) acc += sG[q1][qx] * sA[el][NA - 1][dz][qy][q1];
       }
-      if (EVEC) {
+      if (EVEC)
         y[size_t(e) * DDD + dz * D * D + qy * D + qx] = TV(acc);
-      } else {
-        const int g = gidx[dz];
-        if (!(constrained && g < 0)) unsafeAtomicAdd(&y[g < 0 ? ~g : g], TV(acc));
-      }
+      else
+        atomicAdd(&sY[slot[dz]], acc);
     }
+  }
+  if (EVEC) return;
+  __syncthreads();
+  // G^t: one global atomic per unique dof of the tile
+#pragma unroll 4
+  for (int s = tid; s < nu; s += NE * QQ) {
+    const int g = tile_dofs[u0 + s];
+    if (!(constrained && g < 0)) unsafeAtomicAdd(&y[g < 0 ? ~g : g], TV(sY[s]));
   }
 }
 
@@ -217,7 +260,7 @@ void launch_one(const DevSpace& sp, const double* tab, bool constrained, const v
   const double* tabB = tab + 2 * Q;
   const double* tabG = tabB + Q * (P + 1);
   hipLaunchKernelGGL((pa_apply_kernel<P, Q, KIND, EVEC, TV, TD, TC>), dim3(nblk),
-                     dim3(NE * Q * Q), 0, st, sp.gmap, tabB, tabG,
+                     dim3(NE * Q * Q), 0, st, sp.tile_off, sp.tile_dofs, sp.tile_slot, tabB, tabG,
                      static_cast<const TD*>(qd), static_cast<const TV*>(x),
                      static_cast<TV*>(out), int(sp.ne), int(constrained));
 }

@@ -63,8 +63,9 @@ __device__ void element_jacobian(int q, int Q, int NG, const double* X, const do
       }
 }
 
-__global__ void qdata_kernel(const double* __restrict__ gnodes, int NG, TabView tv, int Q,
-                             int kind, const double* __restrict__ coeff, double scale,
+__global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* __restrict__ orig,
+                             int NG, TabView tv, int Q, int kind,
+                             const double* __restrict__ coeff, double scale,
                              double* __restrict__ qd, int32_t* status) {
   extern __shared__ double smem[];
   const int e = blockIdx.x;
@@ -92,22 +93,21 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, int NG, TabView 
     const double A21 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
     const double A22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     const double det = J[0][0] * A00 + J[0][1] * A10 + J[0][2] * A20;
-    if (!(det > 0.0)) atomicMin(&status[0], e);
+    if (!(det > 0.0)) atomicMin(&status[0], orig[e]);
     const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
     const double w = tv.wts[q1] * tv.wts[q2] * tv.wts[q3];
-    const double c = scale * (coeff ? coeff[size_t(e) * QQQ + q] : 1.0);
+    const double c = scale * (coeff ? coeff[size_t(orig[e]) * QQQ + q] : 1.0);
     if (kind == PAFEM_MASS) {
-      qd[size_t(e) * QQQ + q] = w * c * det;
+      qd[qdata_index(e, 0, q, Q, 1)] = w * c * det;
     } else {
       // alpha kappa det J J^{-1} J^{-T} = alpha kappa A A^T / det J
       const double f = w * c / det;
-      double* o = qd + size_t(e) * 6 * QQQ + q;
-      o[0 * QQQ] = f * (A00 * A00 + A01 * A01 + A02 * A02);
-      o[1 * QQQ] = f * (A00 * A10 + A01 * A11 + A02 * A12);
-      o[2 * QQQ] = f * (A00 * A20 + A01 * A21 + A02 * A22);
-      o[3 * QQQ] = f * (A10 * A10 + A11 * A11 + A12 * A12);
-      o[4 * QQQ] = f * (A10 * A20 + A11 * A21 + A12 * A22);
-      o[5 * QQQ] = f * (A20 * A20 + A21 * A21 + A22 * A22);
+      qd[qdata_index(e, 0, q, Q, 6)] = f * (A00 * A00 + A01 * A01 + A02 * A02);
+      qd[qdata_index(e, 1, q, Q, 6)] = f * (A00 * A10 + A01 * A11 + A02 * A12);
+      qd[qdata_index(e, 2, q, Q, 6)] = f * (A00 * A20 + A01 * A21 + A02 * A22);
+      qd[qdata_index(e, 3, q, Q, 6)] = f * (A10 * A10 + A11 * A11 + A12 * A12);
+      qd[qdata_index(e, 4, q, Q, 6)] = f * (A10 * A20 + A11 * A21 + A12 * A22);
+      qd[qdata_index(e, 5, q, Q, 6)] = f * (A20 * A20 + A21 * A21 + A22 * A22);
     }
   }
 }
@@ -141,7 +141,8 @@ __device__ void contract_to_dofs(int Q, int D, const double* in, double* t1, dou
   __syncthreads();
 }
 
-__global__ void linear_form_kernel(const double* __restrict__ gnodes, int NG, TabView tv, int Q,
+__global__ void linear_form_kernel(const double* __restrict__ gnodes,
+                                   const int32_t* __restrict__ orig, int NG, TabView tv, int Q,
                                    int D, int source, const double* __restrict__ fqp,
                                    double scale, double* __restrict__ ye) {
   extern __shared__ double smem[];
@@ -173,7 +174,7 @@ __global__ void linear_form_kernel(const double* __restrict__ gnodes, int NG, Ta
     const double w = tv.wts[q1] * tv.wts[q2] * tv.wts[q3];
     double f;
     if (source == PAFEM_SOURCE_ARRAY)
-      f = scale * fqp[size_t(e) * QQQ + q];
+      f = scale * fqp[size_t(orig[e]) * QQQ + q];
     else if (source == PAFEM_SOURCE_CONST)
       f = scale;
     else
@@ -205,7 +206,7 @@ __global__ void diagonal_kernel(TabView tv, int Q, int D, int kind,
   }
   __syncthreads();
   if (kind == PAFEM_MASS) {
-    for (int q = threadIdx.x; q < QQQ; q += blockDim.x) sF[q] = qd[size_t(e) * QQQ + q];
+    for (int q = threadIdx.x; q < QQQ; q += blockDim.x) sF[q] = qd[qdata_index(e, 0, q, Q, 1)];
     __syncthreads();
     contract_to_dofs(Q, D, sF, t1, t2, out, sBB, sBB, sBB, 1.0, false);
   } else {
@@ -216,7 +217,7 @@ __global__ void diagonal_kernel(TabView tv, int Q, int D, int kind,
     for (int a = 0; a < 3; ++a)
       for (int b = a; b < 3; ++b, ++comp) {
         for (int q = threadIdx.x; q < QQQ; q += blockDim.x)
-          sF[q] = qd[(size_t(e) * 6 + comp) * QQQ + q];
+          sF[q] = qd[qdata_index(e, comp, q, Q, 6)];
         __syncthreads();
         const double* T[3];
         for (int d = 0; d < 3; ++d) {
@@ -269,8 +270,8 @@ void launch_qdata(const DevSpace& sp, int kind, int q1d, const double* coeff, do
   const TabView tv = tab_view(sp, q1d);
   const int NN = sp.ng * sp.ng * sp.ng;
   const size_t lds = sizeof(double) * (3 * NN + 2 * q1d * sp.ng);
-  hipLaunchKernelGGL(qdata_kernel, dim3(unsigned(sp.ne)), dim3(256), lds, st, sp.gnodes, sp.ng,
-                     tv, q1d, kind, coeff, scale, qd, sp.status);
+  hipLaunchKernelGGL(qdata_kernel, dim3(unsigned(sp.ne)), dim3(256), lds, st, sp.gnodes,
+                     sp.elem_orig, sp.ng, tv, q1d, kind, coeff, scale, qd, sp.status);
   HIP_LAUNCH_CHECK();
 }
 
@@ -281,7 +282,7 @@ void launch_linear_form_evec(const DevSpace& sp, int q1d, int source, const doub
   const size_t lds = sizeof(double) * (3 * NN + 2 * Q * sp.ng + Q * D + Q * Q * Q + Q * Q * D +
                                        Q * D * D + D * D * D);
   hipLaunchKernelGGL(linear_form_kernel, dim3(unsigned(sp.ne)), dim3(256), lds, st, sp.gnodes,
-                     sp.ng, tv, Q, D, source, fqp, scale, ye);
+                     sp.elem_orig, sp.ng, tv, Q, D, source, fqp, scale, ye);
   HIP_LAUNCH_CHECK();
 }
 

@@ -17,35 +17,6 @@ namespace pafem {
 
 namespace {
 
-__device__ __forceinline__ void store_partial(double* partials, double v) {
-  __hip_atomic_store(&partials[blockIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_partial(const double* partials, int i) {
-  return __hip_atomic_load(const_cast<double*>(&partials[i]), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Publishes this block's partials (thread 0 already stored them) and returns true in
-// every thread of the last block to arrive.
-__device__ bool arrive_last(uint32_t* ticket) {
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t t = atomicAdd(ticket, 1u);
-    last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
-}
-
-// Sum of partials[0..gridDim.x) in a fixed order, valid in every thread.
-__device__ double sum_partials(const double* partials, double* scratch) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < int(gridDim.x); i += blockDim.x) v += load_partial(partials, i);
-  return block_sum(v, scratch);
-}
-
 __device__ __forceinline__ bool state_done(const CGState* st) {
   return __hip_atomic_load(const_cast<int32_t*>(&st->done), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -65,22 +36,23 @@ __global__ void cg_reset_kernel(CGState* st, int32_t max_hist) {
   }
 }
 
+template <typename TB, typename TV>
 __global__ void __launch_bounds__(kCGThreads)
-    cg_init_kernel(CGState* st, double* partials, const double* __restrict__ b,
-                   const double* __restrict__ q, const double* __restrict__ diag,
-                   double* __restrict__ x, double* __restrict__ r, double* __restrict__ d,
-                   int zero_guess, double rel_tol, double* hist, int64_t n) {
+    cg_init_kernel(CGState* st, double* partials, const TB* __restrict__ b, double bscale,
+                   const TV* __restrict__ q, const TV* __restrict__ diag, TV* __restrict__ x,
+                   TV* __restrict__ r, TV* __restrict__ d, int zero_guess, double rel_tol,
+                   double* hist, int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   double rz = 0.0, rr = 0.0, bb = 0.0;
   GRID_LOOP(i, n) {
-    const double bi = b[i];
-    const double ri = q ? bi - q[i] : bi;
-    if (zero_guess) x[i] = 0.0;
-    const double zi = diag ? ri / diag[i] : ri;
+    const double bi = double(b[i]) * bscale;
+    const TV ri = TV(q ? bi - double(q[i]) : bi);
+    if (zero_guess) x[i] = TV(0);
+    const TV zi = diag ? ri / diag[i] : ri;
     r[i] = ri;
     d[i] = zi;
-    rz += ri * zi;
-    rr += ri * ri;
+    rz += double(ri) * double(zi);
+    rr += double(ri) * double(ri);
     bb += bi * bi;
   }
   double* p0 = partials;
@@ -113,13 +85,14 @@ __global__ void __launch_bounds__(kCGThreads)
   }
 }
 
+template <typename TV>
 __global__ void __launch_bounds__(kCGThreads)
-    cg_dot_kernel(CGState* st, double* partials, const double* __restrict__ d,
-                  const double* __restrict__ q, int64_t n) {
+    cg_dot_kernel(CGState* st, double* partials, const TV* __restrict__ d,
+                  const TV* __restrict__ q, int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   if (state_done(st)) return;
   double s = 0.0;
-  GRID_LOOP(i, n) s += d[i] * q[i];
+  GRID_LOOP(i, n) s += double(d[i]) * double(q[i]);
   s = block_sum(s, scratch);
   if (threadIdx.x == 0) store_partial(partials, s);
   if (!arrive_last(&st->ticket[1])) return;
@@ -134,23 +107,23 @@ __global__ void __launch_bounds__(kCGThreads)
   }
 }
 
+template <typename TV>
 __global__ void __launch_bounds__(kCGThreads)
-    cg_update_kernel(CGState* st, double* partials, double* __restrict__ x,
-                     double* __restrict__ r, const double* __restrict__ d,
-                     const double* __restrict__ q, const double* __restrict__ diag,
-                     double* hist, int64_t n) {
+    cg_update_kernel(CGState* st, double* partials, TV* __restrict__ x, TV* __restrict__ r,
+                     const TV* __restrict__ d, const TV* __restrict__ q,
+                     const TV* __restrict__ diag, double* hist, int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   if (state_done(st)) return;
-  const double alpha = st->alpha;
+  const TV alpha = TV(st->alpha);
   double rz = 0.0, rr = 0.0;
   GRID_LOOP(i, n) {
-    const double di = d[i];
+    const TV di = d[i];
     x[i] += alpha * di;
-    const double ri = r[i] - alpha * q[i];
+    const TV ri = r[i] - alpha * q[i];
     r[i] = ri;
-    const double zi = diag ? ri / diag[i] : ri;
-    rz += ri * zi;
-    rr += ri * ri;
+    const TV zi = diag ? ri / diag[i] : ri;
+    rz += double(ri) * double(zi);
+    rr += double(ri) * double(ri);
   }
   double* p0 = partials;
   double* p1 = partials + kCGBlocks;
@@ -179,24 +152,156 @@ __global__ void __launch_bounds__(kCGThreads)
   }
 }
 
+template <typename TV>
 __global__ void __launch_bounds__(kCGThreads)
-    cg_direction_kernel(const CGState* st, const double* __restrict__ r,
-                        const double* __restrict__ diag, double* __restrict__ d, int64_t n) {
+    cg_direction_kernel(const CGState* st, const TV* __restrict__ r,
+                        const TV* __restrict__ diag, TV* __restrict__ d, int64_t n) {
   if (state_done(st)) return;
-  const double beta = st->beta;
+  const TV beta = TV(st->beta);
   GRID_LOOP(i, n) {
-    const double zi = diag ? r[i] / diag[i] : r[i];
+    const TV zi = diag ? r[i] / diag[i] : r[i];
     d[i] = zi + beta * d[i];
   }
 }
 
+// ---- flexible CG (variable preconditioner) ----
+// r = b - q (q may be null), x = 0 if zero_guess; rr, bb, tol2; iteration count kept
 __global__ void __launch_bounds__(kCGThreads)
-    residual_norm_kernel(CGState* st, double* partials, const double* __restrict__ b,
-                         const double* __restrict__ q, int64_t n) {
+    fcg_init_kernel(CGState* st, double* partials, const double* __restrict__ b,
+                    const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
+                    int zero_guess, double rel_tol, int64_t n) {
+  __shared__ double scratch[kCGThreads / kWave];
+  double rr = 0.0, bb = 0.0;
+  GRID_LOOP(i, n) {
+    const double bi = b[i];
+    const double ri = q ? bi - q[i] : bi;
+    if (zero_guess) x[i] = 0.0;
+    r[i] = ri;
+    rr += ri * ri;
+    bb += bi * bi;
+  }
+  rr = block_sum(rr, scratch);
+  bb = block_sum(bb, scratch);
+  if (threadIdx.x == 0) {
+    store_partial(partials, rr);
+    store_partial(partials + kCGBlocks, bb);
+  }
+  if (!arrive_last(&st->ticket[0])) return;
+  const double trr = sum_partials(partials, scratch);
+  const double tbb = sum_partials(partials + kCGBlocks, scratch);
+  if (threadIdx.x == 0) {
+    st->rr = trr;
+    st->bb = tbb;
+    st->tol2 = rel_tol * rel_tol * tbb;
+    const int conv = (trr <= st->tol2) || (tbb == 0.0);
+    __hip_atomic_store(&st->done, conv ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// rz = r . z (must be > 0: otherwise done = 3, the preconditioner is not positive); p = z
+__global__ void __launch_bounds__(kCGThreads)
+    fcg_start_kernel(CGState* st, double* partials, const double* __restrict__ r,
+                     const double* __restrict__ z, double* __restrict__ p, int64_t n) {
+  __shared__ double scratch[kCGThreads / kWave];
+  if (state_done(st)) return;
+  double rz = 0.0;
+  GRID_LOOP(i, n) {
+    const double zi = z[i];
+    p[i] = zi;
+    rz += r[i] * zi;
+  }
+  rz = block_sum(rz, scratch);
+  if (threadIdx.x == 0) store_partial(partials, rz);
+  if (!arrive_last(&st->ticket[4])) return;
+  const double t = sum_partials(partials, scratch);
+  if (threadIdx.x == 0) {
+    st->rz = t;
+    if (!(t > 0.0) || !isfinite(t))
+      __hip_atomic_store(&st->done, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->ticket[4], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// x += alpha p; r -= alpha q; rr, iteration count, history, convergence
+__global__ void __launch_bounds__(kCGThreads)
+    fcg_update_kernel(CGState* st, double* partials, double* __restrict__ x,
+                      double* __restrict__ r, const double* __restrict__ p,
+                      const double* __restrict__ q, double* hist, int64_t n) {
+  __shared__ double scratch[kCGThreads / kWave];
+  if (state_done(st)) return;
+  const double alpha = st->alpha;
+  double rr = 0.0;
+  GRID_LOOP(i, n) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    rr += ri * ri;
+  }
+  rr = block_sum(rr, scratch);
+  if (threadIdx.x == 0) store_partial(partials, rr);
+  if (!arrive_last(&st->ticket[2])) return;
+  const double t = sum_partials(partials, scratch);
+  if (threadIdx.x == 0) {
+    st->rr = t;
+    const int it = st->iter + 1;
+    st->iter = it;
+    if (hist && it < st->max_hist) hist[it] = sqrt(t / st->bb);
+    int done = 0;
+    if (!isfinite(t)) done = 2;
+    else if (t <= st->tol2) done = 1;
+    if (done) __hip_atomic_store(&st->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->ticket[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// beta = r.(z - z_old) / rz_old (Polak-Ribiere); rz = r.z (> 0 else done = 3)
+__global__ void __launch_bounds__(kCGThreads)
+    fcg_beta_kernel(CGState* st, double* partials, const double* __restrict__ r,
+                    const double* __restrict__ z, const double* __restrict__ zold, int64_t n) {
+  __shared__ double scratch[kCGThreads / kWave];
+  if (state_done(st)) return;
+  double rz = 0.0, rzo = 0.0;
+  GRID_LOOP(i, n) {
+    const double ri = r[i];
+    rz += ri * z[i];
+    rzo += ri * zold[i];
+  }
+  rz = block_sum(rz, scratch);
+  rzo = block_sum(rzo, scratch);
+  if (threadIdx.x == 0) {
+    store_partial(partials, rz);
+    store_partial(partials + kCGBlocks, rzo);
+  }
+  if (!arrive_last(&st->ticket[5])) return;
+  const double trz = sum_partials(partials, scratch);
+  const double trzo = sum_partials(partials + kCGBlocks, scratch);
+  if (threadIdx.x == 0) {
+    st->beta = (trz - trzo) / st->rz;
+    st->rz = trz;
+    if (!(trz > 0.0) || !isfinite(st->beta))
+      __hip_atomic_store(&st->done, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->ticket[5], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// p = z + beta p
+__global__ void __launch_bounds__(kCGThreads)
+    fcg_direction_kernel(const CGState* st, const double* __restrict__ z, double* __restrict__ p,
+                         int64_t n) {
+  if (state_done(st)) return;
+  const double beta = st->beta;
+  GRID_LOOP(i, n) p[i] = z[i] + beta * p[i];
+}
+
+__global__ void __launch_bounds__(kCGThreads)
+    residual_kernel(CGState* st, double* partials, const double* __restrict__ b,
+                    const double* __restrict__ q, double* __restrict__ r, int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   double s = 0.0;
   GRID_LOOP(i, n) {
     const double v = b[i] - q[i];
+    if (r) r[i] = v;
     s += v * v;
   }
   s = block_sum(s, scratch);
@@ -209,9 +314,39 @@ __global__ void __launch_bounds__(kCGThreads)
   }
 }
 
+__global__ void __launch_bounds__(kCGThreads)
+    ir_correct_kernel(double* __restrict__ x, const float* __restrict__ dx, double scale,
+                      int64_t n) {
+  GRID_LOOP(i, n) x[i] += scale * double(dx[i]);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u)  // inf or nan
+    return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  const uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t((u + rounding) >> 16);
+}
+
+__global__ void __launch_bounds__(kCGThreads)
+    convert_kernel(const double* __restrict__ src, void* __restrict__ dst, int dtype, int64_t n) {
+  GRID_LOOP(i, n) {
+    const float f = float(src[i]);
+    if (dtype == PAFEM_F32)
+      static_cast<float*>(dst)[i] = f;
+    else
+      static_cast<uint16_t*>(dst)[i] = f32_to_bf16_bits(f);
+  }
+}
+
 void check_launch(const char* what) {
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) throw Error(PAFEM_EHIP, std::string(what) + ": " + hipGetErrorString(err));
+}
+
+int vec_grid(int64_t n) {
+  int64_t g = (n + kCGThreads - 1) / kCGThreads;
+  return int(g < 1 ? 1 : (g > 65536 ? 65536 : g));
 }
 
 }  // namespace
@@ -221,41 +356,105 @@ void launch_cg_reset(CGState* st, int32_t max_hist, hipStream_t s) {
   check_launch("cg_reset");
 }
 
-void launch_cg_init(CGState* st, double* partials, const double* b, const double* q,
-                    const double* diag, double* x, double* r, double* d, int zero_guess,
-                    double rel_tol, double* hist, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(cg_init_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, b, q,
-                     diag, x, r, d, zero_guess, rel_tol, hist, n);
+template <typename TB, typename TV>
+void launch_cg_init(CGState* st, double* partials, const TB* b, double bscale, const TV* q,
+                    const TV* diag, TV* x, TV* r, TV* d, int zero_guess, double rel_tol,
+                    double* hist, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((cg_init_kernel<TB, TV>), dim3(kCGBlocks), dim3(kCGThreads), 0, s, st,
+                     partials, b, bscale, q, diag, x, r, d, zero_guess, rel_tol, hist, n);
   check_launch("cg_init");
 }
 
-void launch_cg_dot(CGState* st, double* partials, const double* d, const double* q, int64_t n,
+template <typename TV>
+void launch_cg_dot(CGState* st, double* partials, const TV* d, const TV* q, int64_t n,
                    hipStream_t s) {
-  hipLaunchKernelGGL(cg_dot_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, d, q,
-                     n);
+  hipLaunchKernelGGL((cg_dot_kernel<TV>), dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials,
+                     d, q, n);
   check_launch("cg_dot");
 }
 
-void launch_cg_update(CGState* st, double* partials, double* x, double* r, const double* d,
-                      const double* q, const double* diag, double* hist, int64_t n,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(cg_update_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, x,
-                     r, d, q, diag, hist, n);
+template <typename TV>
+void launch_cg_update(CGState* st, double* partials, TV* x, TV* r, const TV* d, const TV* q,
+                      const TV* diag, double* hist, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((cg_update_kernel<TV>), dim3(kCGBlocks), dim3(kCGThreads), 0, s, st,
+                     partials, x, r, d, q, diag, hist, n);
   check_launch("cg_update");
 }
 
-void launch_cg_direction(CGState* st, const double* r, const double* diag, double* d, int64_t n,
+template <typename TV>
+void launch_cg_direction(CGState* st, const TV* r, const TV* diag, TV* d, int64_t n,
                          hipStream_t s) {
-  hipLaunchKernelGGL(cg_direction_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, r, diag, d,
-                     n);
+  hipLaunchKernelGGL((cg_direction_kernel<TV>), dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, r,
+                     diag, d, n);
   check_launch("cg_direction");
 }
 
-void launch_residual_norm(CGState* st, double* partials, const double* b, const double* q,
-                          int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(residual_norm_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials,
-                     b, q, n);
-  check_launch("residual_norm");
+template void launch_cg_init<double, double>(CGState*, double*, const double*, double,
+                                             const double*, const double*, double*, double*,
+                                             double*, int, double, double*, int64_t, hipStream_t);
+template void launch_cg_init<double, float>(CGState*, double*, const double*, double,
+                                            const float*, const float*, float*, float*, float*,
+                                            int, double, double*, int64_t, hipStream_t);
+template void launch_cg_dot<double>(CGState*, double*, const double*, const double*, int64_t,
+                                    hipStream_t);
+template void launch_cg_dot<float>(CGState*, double*, const float*, const float*, int64_t,
+                                   hipStream_t);
+template void launch_cg_update<double>(CGState*, double*, double*, double*, const double*,
+                                       const double*, const double*, double*, int64_t,
+                                       hipStream_t);
+template void launch_cg_update<float>(CGState*, double*, float*, float*, const float*,
+                                      const float*, const float*, double*, int64_t, hipStream_t);
+template void launch_cg_direction<double>(CGState*, const double*, const double*, double*,
+                                          int64_t, hipStream_t);
+template void launch_cg_direction<float>(CGState*, const float*, const float*, float*, int64_t,
+                                         hipStream_t);
+
+void launch_fcg_init(CGState* st, double* partials, const double* b, const double* q, double* x,
+                     double* r, int zero_guess, double rel_tol, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fcg_init_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, b, q,
+                     x, r, zero_guess, rel_tol, n);
+  check_launch("fcg_init");
+}
+void launch_fcg_start(CGState* st, double* partials, const double* r, const double* z, double* p,
+                      int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fcg_start_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, r, z,
+                     p, n);
+  check_launch("fcg_start");
+}
+void launch_fcg_update(CGState* st, double* partials, double* x, double* r, const double* p,
+                       const double* q, double* hist, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fcg_update_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, x,
+                     r, p, q, hist, n);
+  check_launch("fcg_update");
+}
+void launch_fcg_beta(CGState* st, double* partials, const double* r, const double* z,
+                     const double* zold, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fcg_beta_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, r, z,
+                     zold, n);
+  check_launch("fcg_beta");
+}
+void launch_fcg_direction(CGState* st, const double* z, double* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fcg_direction_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, z, p, n);
+  check_launch("fcg_direction");
+}
+
+void launch_residual(CGState* st, double* partials, const double* b, const double* q, double* r,
+                     int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(residual_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, b, q,
+                     r, n);
+  check_launch("residual");
+}
+
+void launch_ir_correct(double* x, const float* dx, double scale, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(ir_correct_kernel, dim3(vec_grid(n)), dim3(kCGThreads), 0, s, x, dx, scale,
+                     n);
+  check_launch("ir_correct");
+}
+
+void launch_convert(const double* src, void* dst, int dtype, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(convert_kernel, dim3(vec_grid(n)), dim3(kCGThreads), 0, s, src, dst, dtype,
+                     n);
+  check_launch("convert");
 }
 
 }  // namespace pafem

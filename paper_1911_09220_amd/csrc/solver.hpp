@@ -29,23 +29,45 @@ constexpr int kCGThreads = 256;
 
 // zero the state and tickets; hist holds max_hist entries
 void launch_cg_reset(CGState* st, int32_t max_hist, hipStream_t s);
-// r = b - q (q may be null: r = b); x = 0 if zero_guess; d = z = r / diag;
+
+// The iteration kernels are templated on the vector type TV (double, or float
+// for the inner solve of iterative refinement); dot products always accumulate
+// in double.
+//
+// r = b*bscale - q (q may be null); x = 0 if zero_guess; d = z = r / diag;
 // rz, rr, bb, tol2, done, hist[0].
-void launch_cg_init(CGState* st, double* partials, const double* b, const double* q,
-                    const double* diag, double* x, double* r, double* d, int zero_guess,
-                    double rel_tol, double* hist, int64_t n, hipStream_t s);
+template <typename TB, typename TV>
+void launch_cg_init(CGState* st, double* partials, const TB* b, double bscale, const TV* q,
+                    const TV* diag, TV* x, TV* r, TV* d, int zero_guess, double rel_tol,
+                    double* hist, int64_t n, hipStream_t s);
 // alpha = rz / (d . q); breakdown if d . q <= 0 or non-finite
-void launch_cg_dot(CGState* st, double* partials, const double* d, const double* q, int64_t n,
+template <typename TV>
+void launch_cg_dot(CGState* st, double* partials, const TV* d, const TV* q, int64_t n,
                    hipStream_t s);
 // x += alpha d; r -= alpha q; z = r / diag; rz, rr, beta, iter, hist, convergence
-void launch_cg_update(CGState* st, double* partials, double* x, double* r, const double* d,
-                      const double* q, const double* diag, double* hist, int64_t n,
-                      hipStream_t s);
+template <typename TV>
+void launch_cg_update(CGState* st, double* partials, TV* x, TV* r, const TV* d, const TV* q,
+                      const TV* diag, double* hist, int64_t n, hipStream_t s);
 // d = r / diag + beta d
-void launch_cg_direction(CGState* st, const double* r, const double* diag, double* d, int64_t n,
+template <typename TV>
+void launch_cg_direction(CGState* st, const TV* r, const TV* diag, TV* d, int64_t n,
                          hipStream_t s);
-// res2 = ||b - q||^2 (always runs, ignores `done`)
-void launch_residual_norm(CGState* st, double* partials, const double* b, const double* q,
-                          int64_t n, hipStream_t s);
+// Flexible CG (done = 3: the preconditioner returned r.z <= 0)
+void launch_fcg_init(CGState* st, double* partials, const double* b, const double* q, double* x,
+                     double* r, int zero_guess, double rel_tol, int64_t n, hipStream_t s);
+void launch_fcg_start(CGState* st, double* partials, const double* r, const double* z, double* p,
+                      int64_t n, hipStream_t s);
+void launch_fcg_update(CGState* st, double* partials, double* x, double* r, const double* p,
+                       const double* q, double* hist, int64_t n, hipStream_t s);
+void launch_fcg_beta(CGState* st, double* partials, const double* r, const double* z,
+                     const double* zold, int64_t n, hipStream_t s);
+void launch_fcg_direction(CGState* st, const double* z, double* p, int64_t n, hipStream_t s);
+// res2 = ||b - q||^2 and, if r is not null, r = b - q (always runs, ignores `done`)
+void launch_residual(CGState* st, double* partials, const double* b, const double* q, double* r,
+                     int64_t n, hipStream_t s);
+// x += scale * dx (f64 += f32)
+void launch_ir_correct(double* x, const float* dx, double scale, int64_t n, hipStream_t s);
+// dst = convert(src) to f32 or bf16 (round to nearest even)
+void launch_convert(const double* src, void* dst, int dtype, int64_t n, hipStream_t s);
 
 }  // namespace pafem

@@ -105,6 +105,48 @@ void match_keys(const std::vector<std::array<int64_t, K>>& keys, int64_t nv,
   for (size_t i = 0; i < n; ++i) mult[i] = mult[size_t(rep[i])];
 }
 
+// spread the low 21 bits of v so that bit i lands at bit 3i
+uint64_t spread3(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | (v << 32)) & 0x1f00000000ffffULL;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+  v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+  v = (v | (v << 2)) & 0x1249249249249249ULL;
+  return v;
+}
+
+// Device element order: Morton (Z-curve) order of element centroids.
+std::vector<int32_t> morton_order(const Mesh& m) {
+  const int64_t ne = m.ne;
+  std::vector<double> c(static_cast<size_t>(ne) * 3, 0.0);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int k = 0; k < 8; ++k)
+      for (int a = 0; a < 3; ++a) c[size_t(e) * 3 + a] += m.xyz[size_t(m.hex[size_t(e) * 8 + k]) * 3 + a];
+    for (int a = 0; a < 3; ++a) {
+      c[size_t(e) * 3 + a] *= 0.125;
+      lo[a] = std::min(lo[a], c[size_t(e) * 3 + a]);
+      hi[a] = std::max(hi[a], c[size_t(e) * 3 + a]);
+    }
+  }
+  std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(ne));
+  for (int64_t e = 0; e < ne; ++e) {
+    uint64_t code = 0;
+    for (int a = 0; a < 3; ++a) {
+      const double span = hi[a] - lo[a];
+      const double t = span > 0 ? (c[size_t(e) * 3 + a] - lo[a]) / span : 0.0;
+      const uint64_t qv = uint64_t(std::min(std::max(t, 0.0), 1.0) * double((1 << 21) - 1));
+      code |= spread3(qv) << a;
+    }
+    key[size_t(e)] = {code, int32_t(e)};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> order(static_cast<size_t>(ne));
+  for (int64_t i = 0; i < ne; ++i) order[size_t(i)] = key[size_t(i)].second;
+  return order;
+}
+
 }  // namespace
 
 Space* build_space(const Mesh* mesh, int order, int flags) {
@@ -258,16 +300,45 @@ Space* build_space(const Mesh* mesh, int order, int flags) {
     }
   }
 
+  s->dev_order = morton_order(m);
   if (flags & PAFEM_SPACE_RENUMBER) {
+    // first touch while walking the elements in device order
     std::vector<int32_t> perm(size_t(ndofs), -1);
     int32_t nn = 0;
-    for (auto& d : s->gmap) {
-      if (perm[size_t(d)] < 0) perm[size_t(d)] = nn++;
-      d = perm[size_t(d)];
+    for (int64_t k = 0; k < ne; ++k) {
+      const int32_t* g = s->gmap.data() + size_t(s->dev_order[size_t(k)]) * dpe;
+      for (int i = 0; i < dpe; ++i)
+        if (perm[size_t(g[i])] < 0) perm[size_t(g[i])] = nn++;
     }
+    for (auto& d : s->gmap) d = perm[size_t(d)];
     std::vector<uint8_t> bm(static_cast<size_t>(ndofs), 0);
     for (int64_t d = 0; d < ndofs; ++d) bm[size_t(perm[d])] = s->bmask[size_t(d)];
     s->bmask.swap(bm);
+  }
+  // apply tiles: tile_ne consecutive device elements share one list of unique dofs
+  s->tile_ne = qdata_tile(p + 2);
+  const int64_t ntiles = (ne + s->tile_ne - 1) / s->tile_ne;
+  s->tile_off.assign(size_t(ntiles) + 1, 0);
+  s->tile_slot.assign(size_t(ntiles) * s->tile_ne * dpe, 0);
+  s->tile_dofs.reserve(size_t(ne) * dpe / 2);
+  std::vector<int32_t> buf;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int64_t e0 = t * s->tile_ne, e1 = std::min(ne, e0 + s->tile_ne);
+    buf.clear();
+    for (int64_t k = e0; k < e1; ++k) {
+      const int32_t* g = s->gmap.data() + size_t(s->dev_order[size_t(k)]) * dpe;
+      buf.insert(buf.end(), g, g + dpe);
+    }
+    std::sort(buf.begin(), buf.end());
+    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    for (int64_t k = e0; k < e1; ++k) {
+      const int32_t* g = s->gmap.data() + size_t(s->dev_order[size_t(k)]) * dpe;
+      uint16_t* sl = s->tile_slot.data() + size_t(k) * dpe;
+      for (int i = 0; i < dpe; ++i)
+        sl[i] = uint16_t(std::lower_bound(buf.begin(), buf.end(), g[i]) - buf.begin());
+    }
+    for (int32_t d : buf) s->tile_dofs.push_back(s->bmask[size_t(d)] ? ~d : d);
+    s->tile_off[size_t(t) + 1] = int32_t(s->tile_dofs.size());
   }
   for (int64_t d = 0; d < ndofs; ++d)
     if (s->bmask[size_t(d)]) s->bdr.push_back(int32_t(d));
@@ -314,14 +385,24 @@ void space_dof_coords(const Space& s, double* xyz) {
 void space_device_layout(const Space& s, size_t* off, size_t* total) {
   const size_t nn = size_t(s.ng) * s.ng * s.ng;
   size_t o = 0;
-  off[0] = o; o += align256(sizeof(int32_t) * size_t(s.ne) * s.dpe);        // gmap
-  off[1] = o; o += align256(sizeof(double) * size_t(s.ne) * nn * 3);        // gnodes
-  off[2] = o; o += align256(size_t(s.ndofs));                               // bmask
-  off[3] = o; o += align256(sizeof(int32_t) * size_t(s.ndofs + 1));         // toff
-  off[4] = o; o += align256(sizeof(int32_t) * size_t(s.ne) * s.dpe);        // tidx
-  off[5] = o; o += align256(sizeof(double) * s.tables.size());              // tables
-  off[6] = o; o += align256(sizeof(int32_t) * 64);                          // status
-  off[7] = o;
+  const size_t sizes[kSpaceSegments] = {
+      sizeof(int32_t) * size_t(s.ne) * s.dpe,      // 0 gmap (device order)
+      sizeof(double) * size_t(s.ne) * nn * 3,      // 1 geometry nodes (device order)
+      size_t(s.ndofs),                             // 2 boundary mask
+      sizeof(int32_t) * size_t(s.ndofs + 1),       // 3 transposed offsets
+      sizeof(int32_t) * size_t(s.ne) * s.dpe,      // 4 transposed entries
+      sizeof(double) * s.tables.size(),            // 5 1D tables
+      sizeof(int32_t) * 64,                        // 6 status words
+      sizeof(int32_t) * size_t(s.ne),              // 7 caller element ids
+      sizeof(int32_t) * s.tile_off.size(),         // 8 tile offsets
+      sizeof(int32_t) * s.tile_dofs.size(),        // 9 tile dof lists
+      sizeof(uint16_t) * s.tile_slot.size(),       // 10 tile slot maps
+  };
+  for (int i = 0; i < kSpaceSegments; ++i) {
+    off[i] = o;
+    o += align256(sizes[i]);
+  }
+  off[kSpaceSegments] = o;
   *total = o;
 }
 
@@ -330,29 +411,32 @@ void space_pack(const Space& s, std::vector<int32_t>& gmap_enc, std::vector<doub
   const Mesh& m = *s.mesh;
   const size_t n = size_t(s.ne) * s.dpe;
   gmap_enc.resize(n);
-  for (size_t i = 0; i < n; ++i) {
-    const int32_t d = s.gmap[i];
-    gmap_enc[i] = s.bmask[size_t(d)] ? ~d : d;
+  for (int64_t k = 0; k < s.ne; ++k) {
+    const int32_t* g = s.gmap.data() + size_t(s.dev_order[size_t(k)]) * s.dpe;
+    for (int i = 0; i < s.dpe; ++i)
+      gmap_enc[size_t(k) * s.dpe + i] = s.bmask[size_t(g[i])] ? ~g[i] : g[i];
   }
   const int nn = s.ng * s.ng * s.ng;
   gnodes.resize(size_t(s.ne) * nn * 3);
-  for (int64_t e = 0; e < s.ne; ++e) {
-    double* X = gnodes.data() + size_t(e) * nn * 3;
+  for (int64_t k = 0; k < s.ne; ++k) {
+    const int64_t e = s.dev_order[size_t(k)];
+    double* X = gnodes.data() + size_t(k) * nn * 3;
     if (m.geom_order == 2) {
       std::memcpy(X, m.gnodes.data() + size_t(e) * 81, sizeof(double) * 81);
     } else {
       const ElemCorners c = corners_of(m, e);
-      for (int k = 0; k < 8; ++k)
-        for (int a = 0; a < 3; ++a) X[k * 3 + a] = m.xyz[size_t(c.v[k]) * 3 + a];
+      for (int q = 0; q < 8; ++q)
+        for (int a = 0; a < 3; ++a) X[q * 3 + a] = m.xyz[size_t(c.v[q]) * 3 + a];
     }
   }
-  // transposed map: for each dof, its element-vector entries in ascending order
+  // transposed map: for each dof, its element-vector entries (device order) ascending
   toff.assign(size_t(s.ndofs) + 1, 0);
-  for (size_t i = 0; i < n; ++i) toff[size_t(s.gmap[i]) + 1]++;
+  auto dof_of = [&](size_t i) { const int32_t v = gmap_enc[i]; return v < 0 ? ~v : v; };
+  for (size_t i = 0; i < n; ++i) toff[size_t(dof_of(i)) + 1]++;
   for (int64_t d = 0; d < s.ndofs; ++d) toff[size_t(d) + 1] += toff[size_t(d)];
   tidx.resize(n);
   std::vector<int32_t> fill(toff.begin(), toff.end() - 1);
-  for (size_t i = 0; i < n; ++i) tidx[size_t(fill[size_t(s.gmap[i])]++)] = int32_t(i);
+  for (size_t i = 0; i < n; ++i) tidx[size_t(fill[size_t(dof_of(i))]++)] = int32_t(i);
 }
 
 }  // namespace pafem

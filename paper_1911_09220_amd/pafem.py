@@ -43,6 +43,17 @@ class SolveResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
+class IROpts(C.Structure):
+    _fields_ = [("rel_tol", C.c_double), ("inner_rel_tol", C.c_double), ("max_outer", C.c_int32),
+                ("max_inner", C.c_int32), ("check_every", C.c_int32), ("precond", C.c_int32),
+                ("res_hist", C.POINTER(C.c_double)), ("res_hist_cap", C.c_int32)]
+
+
+class IRResult(C.Structure):
+    _fields_ = [("outer", C.c_int32), ("inner_total", C.c_int32), ("converged", C.c_int32),
+                ("rel_res", C.c_double), ("seconds", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
@@ -73,6 +84,16 @@ def _load():
         "pafem_pcg_workspace_bytes": (I32, [P, I32, C.POINTER(SZ)]),
         "pafem_pcg_solve": (I32, [P, P, P, P, P, SZ, C.POINTER(SolveOpts),
                                   C.POINTER(SolveResult), P]),
+        "pafem_convert": (I32, [I64, P, P, I32, P]),
+        "pafem_batch_workspace_bytes": (I32, [I32, C.POINTER(SZ)]),
+        "pafem_batch_create": (I32, [I32, P, I32, P, SZ, C.POINTER(P)]),
+        "pafem_batch_destroy": (None, [P]),
+        "pafem_batch_apply": (I32, [P, P, P, P]),
+        "pafem_batch_autotune": (I32, [P, P, P, C.c_char_p, I32, P]),
+        "pafem_batch_set_tile": (I32, [P, I32, I32]),
+        "pafem_batch_describe": (I32, [P, C.c_char_p, SZ]),
+        "pafem_ir_workspace_bytes": (I32, [P, P, C.POINTER(SZ)]),
+        "pafem_ir_solve": (I32, [P, P, P, P, P, P, SZ, C.POINTER(IROpts), C.POINTER(IRResult), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -197,6 +218,73 @@ def pafem_pcg_solve(op, diag, b, x, work, opts: SolveOpts):
     rc = lib.pafem_pcg_solve(op, _ptr(diag), _ptr(b), _ptr(x), _ptr(work), work.numel(),
                              C.byref(opts), C.byref(res), _stream())
     return rc, res
+
+
+def pafem_convert(src, dst, dtype):
+    _check(lib.pafem_convert(src.numel(), _ptr(src), _ptr(dst), int(dtype), _stream()))
+
+
+def pafem_ir_workspace_bytes(a_hi, a_lo):
+    n = C.c_size_t()
+    _check(lib.pafem_ir_workspace_bytes(a_hi, a_lo, C.byref(n)))
+    return n.value
+
+
+def pafem_ir_solve(a_hi, a_lo, diag, b, x, work, opts: IROpts):
+    res = IRResult()
+    rc = lib.pafem_ir_solve(a_hi, a_lo, _ptr(diag), _ptr(b), _ptr(x), _ptr(work), work.numel(),
+                            C.byref(opts), C.byref(res), _stream())
+    return rc, res
+
+
+def _ptr_array(tensors):
+    arr = (C.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def pafem_batch_workspace_bytes(nops):
+    n = C.c_size_t()
+    _check(lib.pafem_batch_workspace_bytes(int(nops), C.byref(n)))
+    return n.value
+
+
+def pafem_batch_create(ops, nrhs, work):
+    handles = (C.c_void_p * len(ops))(*[o.value for o in ops])
+    out = C.c_void_p()
+    _check(lib.pafem_batch_create(len(ops), handles, int(nrhs), _ptr(work), work.numel(),
+                                  C.byref(out)))
+    return out
+
+
+def pafem_batch_apply(batch, xs, ys):
+    _check(lib.pafem_batch_apply(batch, _ptr_array(xs), _ptr_array(ys), _stream()))
+
+
+def pafem_batch_autotune(batch, xs, ys, cache_path=None, reps=5):
+    _check(lib.pafem_batch_autotune(batch, _ptr_array(xs), _ptr_array(ys),
+                                    None if cache_path is None else cache_path.encode(),
+                                    int(reps), _stream()))
+
+
+def pafem_batch_set_tile(batch, order, candidate):
+    _check(lib.pafem_batch_set_tile(batch, int(order), int(candidate)))
+
+
+def pafem_batch_describe(batch):
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib.pafem_batch_describe(batch, buf, len(buf)))
+    return buf.value.decode()
+
+
+def lowered_qdata(qdata, dtype):
+    """Reduced-precision copy (F32 or BF16 bits) of f64 quadrature data, on the device."""
+    import torch
+    out = torch.empty(qdata.numel(), dtype=torch.float32 if dtype == F32 else torch.int16,
+                      device=qdata.device)
+    pafem_convert(qdata, out, dtype)
+    return out
 
 
 # ---- handle-owning conveniences -----------------------------------------------------
@@ -330,7 +418,68 @@ class Operator:
             info["history"] = hist[: res.iters + 1].copy()
         return x, info
 
+    def ir_solve(self, lo, b, diag=None, rel_tol=1e-10, inner_rel_tol=1e-2, max_outer=50,
+                 max_inner=5000, check_every=8, precond=PRECOND_JACOBI):
+        """Iterative refinement with `lo` (same operator on F32/BF16 qdata) as inner solver."""
+        import torch
+        if precond == PRECOND_JACOBI and diag is None:
+            diag = self.diagonal()
+        self._check_vec(b, "b")
+        x = torch.empty_like(b)
+        work = _device_bytes(pafem_ir_workspace_bytes(self.handle, lo.handle), self.space.device)
+        hist = np.zeros(max_outer + 1)
+        opts = IROpts(float(rel_tol), float(inner_rel_tol), int(max_outer), int(max_inner),
+                      int(check_every), int(precond), hist.ctypes.data_as(C.POINTER(C.c_double)),
+                      hist.size)
+        rc, res = pafem_ir_solve(self.handle, lo.handle,
+                                 diag if precond == PRECOND_JACOBI else None, b, x, work, opts)
+        if rc not in (0, -5):
+            _check(rc)
+        return x, {"status": STATUS.get(rc, rc), "outer": res.outer, "inner_total": res.inner_total,
+                   "converged": bool(res.converged), "rel_res": res.rel_res,
+                   "seconds": res.seconds, "history": hist[: res.outer + 1].copy()}
+
     def __del__(self):
         if getattr(self, "handle", None):
             lib.pafem_op_destroy(self.handle)
+            self.handle = None
+
+
+class Batch:
+    """Many meshes x nrhs right-hand sides in one graph launch (vectors [ndofs, nrhs])."""
+
+    def __init__(self, ops, nrhs=16):
+        self.ops = list(ops)  # keep operators (and their spaces) alive
+        self.nrhs = int(nrhs)
+        dev = self.ops[0].space.device
+        self.work = _device_bytes(pafem_batch_workspace_bytes(len(self.ops)), dev)
+        self.handle = pafem_batch_create([o.handle for o in self.ops], self.nrhs, self.work)
+
+    def _check(self, xs, ys):
+        if len(xs) != len(self.ops) or len(ys) != len(self.ops):
+            raise ValueError("one x and one y per operator")
+        for o, x, y in zip(self.ops, xs, ys):
+            for v in (x, y):
+                if v.numel() != o.space.ndofs * self.nrhs or not v.is_contiguous() or not v.is_cuda:
+                    raise ValueError("batch vectors must be contiguous [ndofs, nrhs] device arrays")
+
+    def apply(self, xs, ys):
+        self._check(xs, ys)
+        pafem_batch_apply(self.handle, xs, ys)
+        return ys
+
+    def autotune(self, xs, ys, cache_path=None, reps=5):
+        self._check(xs, ys)
+        pafem_batch_autotune(self.handle, xs, ys, cache_path, reps)
+
+    def set_tile(self, order, candidate):
+        pafem_batch_set_tile(self.handle, order, candidate)
+
+    def describe(self):
+        import json
+        return json.loads(pafem_batch_describe(self.handle))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.pafem_batch_destroy(self.handle)
             self.handle = None

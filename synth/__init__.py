@@ -225,3 +225,19 @@ def uneven_mesh_list(count: int = 32, nmin: float = 1e4, nmax: float = 1e6,
         n = max(1, int(round((ndof ** (1.0 / 3.0) - 1.0) / p)))
         out.append({"n": n, "p": p, "mesh_seed": 1000 + i})
     return out
+
+
+def mlp_init(in_dim: int, hidden: int, out_dim: int, seed: int = 0,
+             zero_last: bool = True) -> dict:
+    """Initial weights of the element-patch network (He-normal hidden layers).
+
+    The last layer starts at zero when ``zero_last`` (the preconditioner then
+    starts as plain Jacobi).  W* are [out, in] row-major, float64.
+    """
+    rng = np.random.default_rng(seed)
+    w1 = rng.normal(scale=np.sqrt(2.0 / in_dim), size=(hidden, in_dim))
+    w2 = rng.normal(scale=np.sqrt(2.0 / hidden), size=(hidden, hidden))
+    w3 = (np.zeros((out_dim, hidden)) if zero_last
+          else rng.normal(scale=np.sqrt(1.0 / hidden), size=(out_dim, hidden)))
+    return {"W1": w1, "b1": np.zeros(hidden), "W2": w2, "b2": np.zeros(hidden),
+            "W3": w3, "b3": np.zeros(out_dim)}

@@ -1,0 +1,120 @@
+"""Pins for the learned-preconditioner oracle (CPU only)."""
+import numpy as np
+import scipy.sparse.linalg as spla
+
+import oracle
+import synth
+from oracle import forms, mlp
+from tests._common import OracleProblem
+
+
+def _params(seed=0, zero_last=False, i=10, h=12, o=6):
+    return synth.mlp_init(i, h, o, seed=seed, zero_last=zero_last)
+
+
+def test_backward_matches_finite_differences():
+    P = _params(1)
+    rng = np.random.default_rng(2)
+    for k in P:
+        P[k] = P[k] + 0.1 * rng.normal(size=P[k].shape)   # no dead units at zero bias
+    X = rng.normal(size=(7, 10))
+    W = rng.normal(size=(7, 6))
+    out, cache = mlp.forward(P, X)
+    G = mlp.backward(P, cache, W)          # gradient of sum(W * out)
+    h = 1e-6
+    for k in P:
+        flat = P[k].ravel()
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            fp = np.sum(W * mlp.forward(P, X)[0])
+            flat[idx] = old - h
+            fm = np.sum(W * mlp.forward(P, X)[0])
+            flat[idx] = old
+            fd = (fp - fm) / (2 * h)
+            assert abs(fd - G[k].ravel()[idx]) <= 1e-6 * max(1.0, abs(fd)), (k, idx)
+
+
+def test_adam_closed_form_first_steps():
+    # with constant gradient g, m_hat = g and v_hat = g^2: each step moves lr*g/(|g|+eps)
+    P = {"w": np.array([1.0, -2.0])}
+    G = {"w": np.array([0.5, -4.0])}
+    st = {}
+    for t in range(3):
+        mlp.adam_step(P, G, st, lr=0.1, eps=0.0)
+    np.testing.assert_allclose(P["w"], [1.0 - 0.3, -2.0 + 0.3], atol=1e-12)
+
+
+def test_zero_last_layer_is_jacobi():
+    mesh = synth.hex_lattice(3, 0.1, seed=1)
+    ref = OracleProblem(mesh, 2)
+    kappa = synth.lognormal_iid(27, 4, 1.0, seed=2)
+    kbar, feats = mlp.element_features(kappa, 4)
+    in_dim = 27 + 8
+    P = synth.mlp_init(in_dim, 16, 27, seed=3, zero_last=True)
+    r = np.random.default_rng(4).normal(size=ref.space.ndofs)
+    r[ref.space.boundary] = 0
+    d = ref.Kc.diagonal()
+    z, _ = mlp.precondition(P, r, d, ref.space.elem_dofs, ref.space.boundary, feats, kbar, in_dim)
+    np.testing.assert_allclose(z, r / d, atol=1e-15)
+
+
+def test_element_features_closed_form():
+    kappa = np.ones((2, 27))
+    kappa[1, :] = 5.0
+    kbar, f = mlp.element_features(kappa, 3)
+    np.testing.assert_allclose(kbar, [1.0, 5.0])
+    np.testing.assert_allclose(f, 0.0, atol=1e-15)
+    # a coefficient depending on x only: octants with x-high all see the same ratio
+    q = np.arange(3)
+    kx = np.broadcast_to(np.exp(q)[None, None, :], (3, 3, 3)).reshape(1, 27)
+    kbar, f = mlp.element_features(kx, 3)
+    lo, hi = 1.0, np.mean(np.exp([1.0, 2.0]))
+    np.testing.assert_allclose(f[0, 0], np.log(lo / kbar[0]))
+    np.testing.assert_allclose(f[0, 1], np.log(hi / kbar[0]))
+    assert np.allclose(f[0, ::2], f[0, 0]) and np.allclose(f[0, 1::2], f[0, 1])
+
+
+def test_loss_gradient_finite_differences():
+    mesh = synth.hex_lattice(2, 0.1, seed=3)
+    p = 2
+    ref = OracleProblem(mesh, p)
+    kappa = synth.lognormal_iid(8, 4, 0.5, seed=5)
+    kbar, feats = mlp.element_features(kappa, 4)
+    in_dim = 27 + 8
+    P = synth.mlp_init(in_dim, 8, 27, seed=6, zero_last=False)
+    rng = np.random.default_rng(7)
+    e = rng.normal(size=ref.space.ndofs)
+    e[ref.space.boundary] = 0
+    A = ref.Kc
+    r = A @ e
+    d = A.diagonal()
+    L, G = mlp.loss_and_grads(P, A, r, e, d, ref.space.elem_dofs, ref.space.boundary, feats,
+                              kbar, in_dim)
+    h = 1e-6
+    for k in ("W1", "W3", "b2"):
+        flat = P[k].ravel()
+        for idx in rng.choice(flat.size, size=4, replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            Lp, _ = mlp.loss_and_grads(P, A, r, e, d, ref.space.elem_dofs, ref.space.boundary,
+                                       feats, kbar, in_dim)
+            flat[idx] = old - h
+            Lm, _ = mlp.loss_and_grads(P, A, r, e, d, ref.space.elem_dofs, ref.space.boundary,
+                                       feats, kbar, in_dim)
+            flat[idx] = old
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - G[k].ravel()[idx]) <= 1e-5 * max(1e-3, abs(fd)), (k, idx, fd)
+
+
+def test_fcg_with_linear_preconditioner_equals_pcg():
+    mesh = synth.hex_lattice(4, 0.1, seed=2)
+    ref = OracleProblem(mesh, 2)
+    b = ref.load(synth.sine_source)
+    d = ref.Kc.diagonal()
+    x, k, hist = mlp.fcg(ref.Kc, b, lambda r: r / d, tol=1e-10)
+    r = oracle.pcg(ref.Kc, b, d, tol=1e-10)
+    assert abs(k - r["iters"]) <= 1
+    np.testing.assert_allclose(hist[:10], r["history"][:10], rtol=1e-6)
+    xd = spla.spsolve(ref.Kc.tocsc(), b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-8
