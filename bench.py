@@ -137,6 +137,137 @@ def cpu_baseline(orders, budget_s=20.0):
     }
 
 
+def bench_mixed(P, torch, n=45, p=6, tol=1e-8):
+    """Quadratic warped mesh, p = 6: FP64 Jacobi-PCG vs FP32/BF16-inner refinement."""
+    import synth
+    mesh = synth.q2_warped_lattice(n, 0.05)
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    del mesh
+    qd = S.qdata(P.DIFFUSION)
+    hi = P.Operator(S, P.DIFFUSION, qd)
+    b = S.linear_form(P.SOURCE_SINE)
+    diag = hi.diagonal()
+    out = {"ndofs": S.ndofs, "elements": S.nelem, "order": p, "tol": tol}
+    x64, i64 = hi.pcg(b, diag=diag, rel_tol=tol, max_iter=20000, history=False)
+    out["fp64_pcg"] = {"seconds": round(i64["seconds"], 4), "iters": i64["iters"],
+                       "true_rel_res": i64["true_rel_res"]}
+    for name, dt in (("fp32", P.F32), ("bf16", P.BF16)):
+        lo = P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, dt), qdata_dtype=dt)
+        x, info = hi.ir_solve(lo, b, diag=diag, rel_tol=tol, inner_rel_tol=1e-2, max_outer=40,
+                              max_inner=20000)
+        err = float((x - x64).norm() / x64.norm())
+        # reduced-precision apply error on one vector, against the FP64 apply
+        v = b / b.norm()
+        ea = float((lo.apply(v.float()).double() - hi.apply(v)).norm() / hi.apply(v).norm())
+        out[f"ir_{name}"] = {"seconds": round(info["seconds"], 4), "outer": info["outer"],
+                             "inner_iters": info["inner_total"], "rel_res": info["rel_res"],
+                             "solution_rel_diff_vs_fp64_pcg": err, "apply_rel_err": ea,
+                             "speedup_vs_fp64": round(i64["seconds"] / info["seconds"], 3)}
+        del lo
+    return out
+
+
+def bench_batched(P, torch, nrhs=16, reps=20, tune_cache=None):
+    """32 uneven meshes (1e4..1e6 dofs, p = 2..6), nrhs right-hand sides, one graph launch."""
+    import synth
+    specs = synth.uneven_mesh_list(32)
+    out = {"meshes": len(specs), "nrhs": nrhs}
+    ops64, ops32, x64, y64, x32, y32 = [], [], [], [], [], []
+    total = 0
+    for i, sp in enumerate(specs):
+        mesh = synth.hex_lattice(sp["n"], 0.05, seed=sp["mesh_seed"])
+        S = P.Space(P.Mesh.from_dict(mesh), sp["p"])
+        qd = S.qdata(P.DIFFUSION)
+        ops64.append(P.Operator(S, P.DIFFUSION, qd))
+        ops32.append(P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, P.F32), qdata_dtype=P.F32))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(5000 + i)
+        x = torch.randn(S.ndofs, nrhs, dtype=torch.float64, device="cuda", generator=g)
+        x64.append(x)
+        y64.append(torch.empty_like(x))
+        x32.append(x.float())
+        y32.append(torch.empty_like(x32[-1]))
+        total += S.ndofs
+    out["total_dofs"] = total
+    for name, ops, xs, ys in (("f64", ops64, x64, y64), ("f32", ops32, x32, y32)):
+        B = P.Batch(ops, nrhs)
+        res = {}
+        for mode in ("default", "autotuned"):
+            if mode == "autotuned":
+                B.autotune(xs, ys, cache_path=tune_cache, reps=5)
+            B.apply(xs, ys)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                B.apply(xs, ys)
+            b.record()
+            torch.cuda.synchronize()
+            t = a.elapsed_time(b) / reps / 1e3
+            res[mode] = {"ms": round(t * 1e3, 4), "gdofs_rhs": round(total * nrhs / t / 1e9, 3)}
+        res["tiles"] = B.describe()["groups"]
+        out[name] = res
+    return out
+
+
+def bench_learned(P, torch, n_train=16, n_test=64, p=3, fields=20, heldout=2, steps=1500,
+                  tol=1e-8):
+    """GRF lognormal coefficient (contrast 1e3, correlation 0.1): learned FCG vs Jacobi-PCG."""
+    import synth
+    from paper_1911_09220_amd import learned as L
+    t0 = time.perf_counter()
+    mesh = synth.hex_lattice(n_train, 0.05, seed=21)
+    E = mesh["hex"].shape[0]
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    pts = synth.lattice_quadrature_points(n_train, p + 2)
+    samples = []
+    for f in range(fields):
+        kappa = torch.as_tensor(synth.grf_lognormal(pts, 0.1, 1e3, seed=1000 + f),
+                                device="cuda").reshape(E, -1).contiguous()
+        op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kappa))
+        diag = op.diagonal()
+        feats = P.learned_features(S, kappa)
+        b = S.linear_form(P.SOURCE_SINE)
+        for r, e in L.jacobi_pairs(op, b, diag):
+            samples.append((op, feats, diag, r, e))
+    t_pairs = time.perf_counter() - t0
+    test_mesh = synth.hex_lattice(n_test, 0.05, seed=22)
+    Et = test_mesh["hex"].shape[0]
+    St = P.Space(P.Mesh.from_dict(test_mesh), p)
+    del test_mesh
+    net = P.Net(p, hidden=128, max_rows=max(E, Et), max_train_rows=E)
+    net.set_params(synth.mlp_init(net.in_dim, 128, net.out_dim, seed=23, zero_last=True))
+    t1 = time.perf_counter()
+    losses = L.train(net, samples, steps=steps, lr=2e-3, decay_every=max(1, steps // 3))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    out = {"order": p, "train_mesh": n_train, "train_fields": fields, "pairs": len(samples),
+           "train_steps": steps, "pair_seconds": round(t_pairs, 2),
+           "train_seconds": round(t_train, 2),
+           "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
+           "test_mesh": n_test, "test_ndofs": St.ndofs, "tol": tol, "heldout": []}
+    pts_t = synth.lattice_quadrature_points(n_test, p + 2)
+    for f in range(heldout):
+        kappa = torch.as_tensor(synth.grf_lognormal(pts_t, 0.1, 1e3, seed=2000 + f),
+                                device="cuda").reshape(Et, -1).contiguous()
+        op = P.Operator(St, P.DIFFUSION, St.qdata(P.DIFFUSION, coeff=kappa))
+        diag = op.diagonal()
+        feats = P.learned_features(St, kappa)
+        b = St.linear_form(P.SOURCE_SINE)
+        _, ij = op.pcg(b, diag=diag, rel_tol=tol, max_iter=20000, history=False)
+        _, il = P.fcg_solve(op, b, diag, net=net, feats=feats, rel_tol=tol, max_iter=20000,
+                            history=False)
+        out["heldout"].append({
+            "field": 2000 + f,
+            "jacobi_pcg": {"seconds": round(ij["seconds"], 4), "iters": ij["iters"],
+                           "true_rel_res": ij["true_rel_res"]},
+            "learned_fcg": {"seconds": round(il["seconds"], 4), "iters": il["iters"],
+                            "true_rel_res": il["true_rel_res"], "fell_back": il["fell_back"]},
+            "speedup": round(ij["seconds"] / il["seconds"], 3)})
+        del op, diag, feats, b, kappa
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +279,10 @@ def main():
     ap.add_argument("--cg-orders", default="3", help="orders for the Jacobi-PCG solve ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mass", action="store_true")
+    ap.add_argument("--forms", default="mixed,batched,learned",
+                    help="solver forms to measure beside the sweep ('' = none)")
+    ap.add_argument("--learned-fields", type=int, default=20)
+    ap.add_argument("--learned-steps", type=int, default=1500)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -234,6 +369,22 @@ def main():
         "roofline": roofline,
         "cg_time_to_1e-8": cg,
     }
+    forms = [f for f in args.forms.split(",") if f]
+    # free the sweep's device memory before the solver forms
+    dom = pr = None
+    probs.clear()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if "mixed" in forms:
+        print("# mixed precision", file=sys.stderr, flush=True)
+        out["mixed_precision"] = bench_mixed(P, torch)
+    if "batched" in forms:
+        print("# batched", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(P, torch)
+    if "learned" in forms:
+        print("# learned", file=sys.stderr, flush=True)
+        out["learned"] = bench_learned(P, torch, fields=args.learned_fields,
+                                       steps=args.learned_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(orders)
     print(json.dumps(out), flush=True)

@@ -312,6 +312,85 @@ pafem_status pafem_batch_set_tile(pafem_batch batch, int32_t order, int32_t cand
 /* JSON description of the groups, chosen tiles and tuning timings into buf. */
 pafem_status pafem_batch_describe(pafem_batch batch, char* buf, size_t len);
 
+
+/* ------------------------------------------- learned element preconditioner --- */
+
+/* A small network N on element patches (BF16 weights and activations, FP32
+ * accumulation on matrix cores, FP32 master weights and Adam) defines the
+ * preconditioner
+ *     z = r / diag + G^t( w * (s_E / kbar_E) * N([r_E / s_E, f_E]) ),
+ * s_E = ||r_E||, kbar_E the element mean of the coefficient, f_E the 8 octant
+ * log-ratios of the coefficient, w = 1 / (element nodes sharing the dof), z = 0
+ * on essential dofs.  N: in -> hidden (relu) -> hidden (relu) -> out with
+ * in = roundup16((p+1)^3 + 8), out = roundup16((p+1)^3).  Parameters (FP32):
+ * W1 [hidden][in], b1, W2 [hidden][hidden], b2, W3 [out][hidden], b3.
+ * Not in the paper: an addition to CG on partially assembled operators.  Built
+ * for orders 1..4. */
+typedef struct pafem_net_s* pafem_net;
+
+/* Device storage of a network that runs on up to max_rows element patches and
+ * trains on up to max_train_rows. */
+pafem_status pafem_net_storage_bytes(int32_t order, int32_t hidden, int64_t max_rows,
+                                     int64_t max_train_rows, size_t* nbytes);
+pafem_status pafem_net_create(int32_t order, int32_t hidden, int64_t max_rows,
+                              int64_t max_train_rows, void* storage, size_t nbytes,
+                              pafem_net* out);
+void pafem_net_destroy(pafem_net net);
+pafem_status pafem_net_dims(pafem_net net, int32_t* in_dim, int32_t* hidden, int32_t* out_dim,
+                            int64_t* nparams);
+/* Host FP32 parameters in, or out; set also clears the Adam state.  SYNCHRONOUS. */
+pafem_status pafem_net_set_params(pafem_net net, const float* host_params, void* stream);
+pafem_status pafem_net_get_params(pafem_net net, float* host_params, void* stream);
+/* Gradients of the last backward pass (host FP32).  SYNCHRONOUS. */
+pafem_status pafem_net_get_grads(pafem_net net, float* host_grads, void* stream);
+/* out [rows][out] f32 = N(x), x device bf16 [rows][in]. */
+pafem_status pafem_net_forward(pafem_net net, const uint16_t* x, float* out, int64_t rows,
+                               void* stream);
+/* Gradients of sum(dout * N(x)) w.r.t. the parameters, kept in the network;
+ * dout device bf16 [rows][out]. */
+pafem_status pafem_net_backward(pafem_net net, const uint16_t* x, const uint16_t* dout,
+                                int64_t rows, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the kept gradients. */
+pafem_status pafem_net_adam_step(pafem_net net, float lr, void* stream);
+
+/* feats [E][9] f32 per element (kbar, 8 octant log-ratios) from the coefficient
+ * kappa [E][q1d^3] f64 (device; NULL: constant 1). */
+pafem_status pafem_learned_features(pafem_space space, const double* kappa, int32_t q1d,
+                                    float* feats, void* stream);
+/* Workspace of pafem_learned_precond / pafem_learned_loss_grad on this op. */
+pafem_status pafem_learned_workspace_bytes(pafem_op op, size_t* nbytes);
+/* z = M(r) as above (device f64 vectors). */
+pafem_status pafem_learned_precond(pafem_net net, pafem_op op, const float* feats,
+                                   const double* diag, const double* r, double* z, void* work,
+                                   size_t work_bytes, void* stream);
+/* Training loss on a pair (r, e) with A e = r:
+ *     L = ||A (e - M(r))||^2_{D^-1} / ||r||^2_{D^-1},
+ * written to the device scalar *loss (may be NULL); its parameter gradients are
+ * kept in the network for pafem_net_adam_step. */
+pafem_status pafem_learned_loss_grad(pafem_net net, pafem_op op, const float* feats,
+                                     const double* diag, const double* r, const double* e,
+                                     double* loss, void* work, size_t work_bytes, void* stream);
+
+typedef struct {
+  int32_t iters;          /* iterations (across a fallback restart) */
+  int32_t converged;
+  int32_t fell_back;      /* 1 if the learned preconditioner was abandoned for Jacobi */
+  int32_t fallback_iter;  /* iteration at which it was abandoned (-1: never) */
+  double rel_res;
+  double true_rel_res;
+  double seconds;
+} pafem_fcg_result;
+
+pafem_status pafem_fcg_workspace_bytes(pafem_op op, int32_t max_iter, size_t* nbytes);
+/* Flexible CG (Polak-Ribiere beta) with the learned preconditioner (net != NULL)
+ * or Jacobi (net == NULL).  If r.z <= 0, a non-finite scalar or a residual
+ * growth by 1e6 appears with the network, it restarts from the current iterate
+ * with Jacobi (result->fell_back).  opts->precond is ignored.  SYNCHRONOUS. */
+pafem_status pafem_fcg_solve(pafem_op op, pafem_net net, const float* feats, const double* diag,
+                             const double* b, double* x, void* work, size_t work_bytes,
+                             const pafem_solve_opts* opts, pafem_fcg_result* result,
+                             void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,11 +92,14 @@ def multiplicity(elem_dofs, ndofs):
 
 
 def precondition(P, r, diag, elem_dofs, boundary, feats, kbar, in_dim):
+    """z = M(r).  Only the first (p+1)^3 network outputs are used (one per element node)."""
     X, s = patch_inputs(r, elem_dofs, feats, in_dim)
     out, cache = forward(P, X)
+    nd = elem_dofs.shape[1]
     m = multiplicity(elem_dofs, r.size)
     scale = (s / kbar)[:, None]
-    contrib = np.bincount(elem_dofs.ravel(), weights=(scale * out).ravel(), minlength=r.size)
+    contrib = np.bincount(elem_dofs.ravel(), weights=(scale * out[:, :nd]).ravel(),
+                          minlength=r.size)
     z = r / diag + contrib / m
     z[boundary] = 0.0
     return z, (X, s, cache, m, scale)
@@ -110,7 +113,9 @@ def loss_and_grads(P, A, r, e, diag, elem_dofs, boundary, feats, kbar, in_dim):
     L = (u @ (u / diag)) / rn
     dz = -2.0 * (A @ (u / diag)) / rn
     dz[boundary] = 0.0
-    dout = scale * (dz / m)[elem_dofs]
+    nd = elem_dofs.shape[1]
+    dout = np.zeros((elem_dofs.shape[0], P["W3"].shape[0]))
+    dout[:, :nd] = scale * (dz / m)[elem_dofs]
     return L, backward(P, cache, dout)
 
 

@@ -17,18 +17,10 @@
 
 using namespace pafem;
 
-struct pafem_mesh_s {
-  Mesh m;
-};
-struct pafem_space_s {
-  Space* s;
-};
-struct pafem_op_s {
-  Op op;
-};
 struct pafem_batch_s {
   Batch* b;
 };
+
 
 namespace {
 const Space& uploaded_space(pafem_space sp) {

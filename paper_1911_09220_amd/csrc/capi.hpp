@@ -50,3 +50,14 @@ size_t op_work_bytes(const Op& op);
 void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st);
 
 }  // namespace pafem
+
+// Opaque handle types of the C ABI.
+struct pafem_mesh_s {
+  pafem::Mesh m;
+};
+struct pafem_space_s {
+  pafem::Space* s;
+};
+struct pafem_op_s {
+  pafem::Op op;
+};

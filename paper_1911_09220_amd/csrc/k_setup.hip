@@ -252,6 +252,7 @@ __global__ void evec_gather_kernel(const int32_t* __restrict__ toff,
 template <typename T>
 __global__ void scatter_init_kernel(const uint8_t* __restrict__ bmask, const T* __restrict__ x,
                                     int constrained, T* __restrict__ y, int64_t n) {
+#pragma unroll 4
   for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n;
        g += int64_t(gridDim.x) * blockDim.x)
     y[g] = (constrained && bmask[g]) ? x[g] : T(0);

@@ -22,7 +22,9 @@ __device__ __forceinline__ bool state_done(const CGState* st) {
                            __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
+// grid-stride loop, unrolled so each thread keeps several independent loads in flight
 #define GRID_LOOP(i, n)                                                        \
+  _Pragma("unroll 4")                                                          \
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < (n);    \
        i += int64_t(gridDim.x) * blockDim.x)
 
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__(kCGThreads)
 __global__ void __launch_bounds__(kCGThreads)
     fcg_init_kernel(CGState* st, double* partials, const double* __restrict__ b,
                     const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
-                    int zero_guess, double rel_tol, int64_t n) {
+                    int zero_guess, double rel_tol, double* hist, int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   double rr = 0.0, bb = 0.0;
   GRID_LOOP(i, n) {
@@ -194,6 +196,7 @@ __global__ void __launch_bounds__(kCGThreads)
     st->bb = tbb;
     st->tol2 = rel_tol * rel_tol * tbb;
     const int conv = (trr <= st->tol2) || (tbb == 0.0);
+    if (hist && st->max_hist > 0) hist[0] = tbb > 0.0 ? sqrt(trr / tbb) : 0.0;
     __hip_atomic_store(&st->done, conv ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&st->ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -410,9 +413,10 @@ template void launch_cg_direction<float>(CGState*, const float*, const float*, f
                                          hipStream_t);
 
 void launch_fcg_init(CGState* st, double* partials, const double* b, const double* q, double* x,
-                     double* r, int zero_guess, double rel_tol, int64_t n, hipStream_t s) {
+                     double* r, int zero_guess, double rel_tol, double* hist, int64_t n,
+                     hipStream_t s) {
   hipLaunchKernelGGL(fcg_init_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, b, q,
-                     x, r, zero_guess, rel_tol, n);
+                     x, r, zero_guess, rel_tol, hist, n);
   check_launch("fcg_init");
 }
 void launch_fcg_start(CGState* st, double* partials, const double* r, const double* z, double* p,

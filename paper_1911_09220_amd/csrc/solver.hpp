@@ -54,7 +54,8 @@ void launch_cg_direction(CGState* st, const TV* r, const TV* diag, TV* d, int64_
                          hipStream_t s);
 // Flexible CG (done = 3: the preconditioner returned r.z <= 0)
 void launch_fcg_init(CGState* st, double* partials, const double* b, const double* q, double* x,
-                     double* r, int zero_guess, double rel_tol, int64_t n, hipStream_t s);
+                     double* r, int zero_guess, double rel_tol, double* hist, int64_t n,
+                     hipStream_t s);
 void launch_fcg_start(CGState* st, double* partials, const double* r, const double* z, double* p,
                       int64_t n, hipStream_t s);
 void launch_fcg_update(CGState* st, double* partials, double* x, double* r, const double* p,

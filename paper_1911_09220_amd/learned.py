@@ -1,0 +1,52 @@
+"""Training orchestration for the learned element preconditioner.
+
+Only sequencing lives here; every computation is a library call:
+* pairs (r_k, e_k = x* - x_k) come from plain Jacobi-PCG runs (pafem_pcg_solve)
+  stopped after k iterations, x* from a run to a tight tolerance;
+* each training step is pafem_learned_loss_grad (preconditioner forward, the
+  A-weighted error loss, backward through the operator and the network) followed
+  by pafem_net_adam_step.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import pafem as P
+
+
+def jacobi_pairs(op, b, diag, stops=(2, 5, 10, 20, 40, 80), tight=1e-12, max_iter=20000):
+    """[(r_k, e_k)] for the listed iteration counts of Jacobi-PCG from x0 = 0."""
+    xstar, info = op.pcg(b, diag=diag, rel_tol=tight, max_iter=max_iter, history=False)
+    pairs = []
+    for k in stops:
+        if k >= info["iters"]:
+            break
+        xk, _ = op.pcg(b, diag=diag, rel_tol=0.0, max_iter=k, history=False)
+        ek = xstar - xk
+        rk = op.apply(ek)
+        pairs.append((rk, ek))
+    return pairs
+
+
+def train(net, samples, steps=500, lr=2e-3, lr_decay=0.5, decay_every=200, seed=0, log_every=0):
+    """Adam on the loss of randomly drawn samples.
+
+    samples: list of (op, feats, diag, r, e).  Returns the per-step losses (host).
+    """
+    import torch
+    rng = np.random.default_rng(seed)
+    works = {}
+    loss_dev = torch.zeros(steps, dtype=torch.float64, device=samples[0][3].device)
+    cur_lr = lr
+    for t in range(steps):
+        if decay_every and t and t % decay_every == 0:
+            cur_lr *= lr_decay
+        op, feats, diag, r, e = samples[int(rng.integers(len(samples)))]
+        w = works.get(id(op))
+        if w is None:
+            w = works[id(op)] = P._learned_work(op)
+        P.learned_loss_grad(net, op, feats, diag, r, e, loss=loss_dev[t:t + 1], work=w)
+        net.adam_step(cur_lr)
+        if log_every and (t + 1) % log_every == 0:
+            print(f"step {t + 1}: loss {float(loss_dev[t]):.4f}", flush=True)
+    return loss_dev.cpu().numpy()

@@ -54,6 +54,12 @@ class IRResult(C.Structure):
                 ("rel_res", C.c_double), ("seconds", C.c_double)]
 
 
+class FCGResult(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("fell_back", C.c_int32),
+                ("fallback_iter", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double), ("seconds", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
@@ -92,6 +98,24 @@ def _load():
         "pafem_batch_autotune": (I32, [P, P, P, C.c_char_p, I32, P]),
         "pafem_batch_set_tile": (I32, [P, I32, I32]),
         "pafem_batch_describe": (I32, [P, C.c_char_p, SZ]),
+        "pafem_net_storage_bytes": (I32, [I32, I32, I64, I64, C.POINTER(SZ)]),
+        "pafem_net_create": (I32, [I32, I32, I64, I64, P, SZ, C.POINTER(P)]),
+        "pafem_net_destroy": (None, [P]),
+        "pafem_net_dims": (I32, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
+                                 C.POINTER(I64)]),
+        "pafem_net_set_params": (I32, [P, P, P]),
+        "pafem_net_get_params": (I32, [P, P, P]),
+        "pafem_net_get_grads": (I32, [P, P, P]),
+        "pafem_net_forward": (I32, [P, P, P, I64, P]),
+        "pafem_net_backward": (I32, [P, P, P, I64, P]),
+        "pafem_net_adam_step": (I32, [P, C.c_float, P]),
+        "pafem_learned_features": (I32, [P, P, I32, P, P]),
+        "pafem_learned_workspace_bytes": (I32, [P, C.POINTER(SZ)]),
+        "pafem_learned_precond": (I32, [P, P, P, P, P, P, P, SZ, P]),
+        "pafem_learned_loss_grad": (I32, [P, P, P, P, P, P, P, P, SZ, P]),
+        "pafem_fcg_workspace_bytes": (I32, [P, I32, C.POINTER(SZ)]),
+        "pafem_fcg_solve": (I32, [P, P, P, P, P, P, P, SZ, C.POINTER(SolveOpts),
+                                  C.POINTER(FCGResult), P]),
         "pafem_ir_workspace_bytes": (I32, [P, P, C.POINTER(SZ)]),
         "pafem_ir_solve": (I32, [P, P, P, P, P, P, SZ, C.POINTER(IROpts), C.POINTER(IRResult), P]),
     }
@@ -483,3 +507,130 @@ class Batch:
         if getattr(self, "handle", None):
             lib.pafem_batch_destroy(self.handle)
             self.handle = None
+
+
+class Net:
+    """Element-patch network (BF16 MFMA kernels, FP32 master weights, Adam)."""
+
+    NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def __init__(self, order, hidden=128, max_rows=1, max_train_rows=0, device="cuda"):
+        n = C.c_size_t()
+        _check(lib.pafem_net_storage_bytes(int(order), int(hidden), int(max_rows),
+                                           int(max_train_rows), C.byref(n)))
+        self.storage = _device_bytes(n.value, device)
+        self.handle = C.c_void_p()
+        _check(lib.pafem_net_create(int(order), int(hidden), int(max_rows), int(max_train_rows),
+                                    _ptr(self.storage), self.storage.numel(),
+                                    C.byref(self.handle)))
+        i, h, o, npar = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib.pafem_net_dims(self.handle, C.byref(i), C.byref(h), C.byref(o), C.byref(npar)))
+        self.in_dim, self.hidden, self.out_dim, self.nparams = i.value, h.value, o.value, npar.value
+        self.order = int(order)
+        self.shapes = {"W1": (self.hidden, self.in_dim), "b1": (self.hidden,),
+                       "W2": (self.hidden, self.hidden), "b2": (self.hidden,),
+                       "W3": (self.out_dim, self.hidden), "b3": (self.out_dim,)}
+
+    def flatten(self, params):
+        return np.concatenate([np.asarray(params[k], dtype=np.float32).reshape(-1)
+                               for k in self.NAMES]).astype(np.float32)
+
+    def unflatten(self, flat):
+        out, o = {}, 0
+        for k in self.NAMES:
+            n = int(np.prod(self.shapes[k]))
+            out[k] = flat[o:o + n].reshape(self.shapes[k]).astype(np.float64)
+            o += n
+        return out
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(params if isinstance(params, np.ndarray) else self.flatten(params),
+                                    dtype=np.float32)
+        assert flat.size == self.nparams
+        _check(lib.pafem_net_set_params(self.handle, _np_ptr(flat), _stream()))
+
+    def get_params(self):
+        flat = np.empty(self.nparams, dtype=np.float32)
+        _check(lib.pafem_net_get_params(self.handle, _np_ptr(flat), _stream()))
+        return self.unflatten(flat)
+
+    def get_grads(self):
+        flat = np.empty(self.nparams, dtype=np.float32)
+        _check(lib.pafem_net_get_grads(self.handle, _np_ptr(flat), _stream()))
+        return self.unflatten(flat)
+
+    def forward(self, x_bf16, rows):
+        import torch
+        out = torch.empty(rows, self.out_dim, dtype=torch.float32, device=x_bf16.device)
+        _check(lib.pafem_net_forward(self.handle, _ptr(x_bf16), _ptr(out), int(rows), _stream()))
+        return out
+
+    def backward(self, x_bf16, dout_bf16, rows):
+        _check(lib.pafem_net_backward(self.handle, _ptr(x_bf16), _ptr(dout_bf16), int(rows),
+                                      _stream()))
+
+    def adam_step(self, lr):
+        _check(lib.pafem_net_adam_step(self.handle, float(lr), _stream()))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.pafem_net_destroy(self.handle)
+            self.handle = None
+
+
+def learned_features(space, kappa=None, q1d=None):
+    import torch
+    q1d = space.p + 2 if q1d is None else q1d
+    space._check_qp_array(kappa, q1d, "kappa")
+    feats = torch.empty(space.nelem, 9, dtype=torch.float32, device=space.device)
+    _check(lib.pafem_learned_features(space.handle, _ptr(kappa), int(q1d), _ptr(feats), _stream()))
+    return feats
+
+
+def _learned_work(op):
+    n = C.c_size_t()
+    _check(lib.pafem_learned_workspace_bytes(op.handle, C.byref(n)))
+    return _device_bytes(n.value, op.space.device)
+
+
+def learned_precond(net, op, feats, diag, r, work=None):
+    import torch
+    z = torch.empty_like(r)
+    work = _learned_work(op) if work is None else work
+    _check(lib.pafem_learned_precond(net.handle, op.handle, _ptr(feats), _ptr(diag), _ptr(r),
+                                     _ptr(z), _ptr(work), work.numel(), _stream()))
+    return z
+
+
+def learned_loss_grad(net, op, feats, diag, r, e, loss=None, work=None):
+    import torch
+    loss = torch.zeros(1, dtype=torch.float64, device=r.device) if loss is None else loss
+    work = _learned_work(op) if work is None else work
+    _check(lib.pafem_learned_loss_grad(net.handle, op.handle, _ptr(feats), _ptr(diag), _ptr(r),
+                                       _ptr(e), _ptr(loss), _ptr(work), work.numel(), _stream()))
+    return loss
+
+
+def fcg_solve(op, b, diag, net=None, feats=None, rel_tol=1e-8, max_iter=2000, check_every=8,
+              history=True):
+    import torch
+    x = torch.zeros_like(b)
+    n = C.c_size_t()
+    _check(lib.pafem_fcg_workspace_bytes(op.handle, int(max_iter), C.byref(n)))
+    work = _device_bytes(n.value, op.space.device)
+    hist = np.zeros(max_iter + 1) if history else None
+    opts = SolveOpts(float(rel_tol), int(max_iter), 0, int(check_every), 1,
+                     None if hist is None else hist.ctypes.data_as(C.POINTER(C.c_double)),
+                     0 if hist is None else hist.size)
+    res = FCGResult()
+    rc = lib.pafem_fcg_solve(op.handle, None if net is None else net.handle, _ptr(feats),
+                             _ptr(diag), _ptr(b), _ptr(x), _ptr(work), work.numel(),
+                             C.byref(opts), C.byref(res), _stream())
+    if rc not in (0, -5, -6):
+        _check(rc)
+    info = {"status": STATUS.get(rc, rc), "iters": res.iters, "converged": bool(res.converged),
+            "fell_back": bool(res.fell_back), "fallback_iter": res.fallback_iter,
+            "rel_res": res.rel_res, "true_rel_res": res.true_rel_res, "seconds": res.seconds}
+    if hist is not None:
+        info["history"] = hist[: res.iters + 1].copy()
+    return x, info

@@ -1,0 +1,194 @@
+"""Learned element preconditioner on the GPU: BF16 MFMA network kernels against the
+FP64 NumPy oracle, the preconditioner and its training loss/gradients against the
+oracle, flexible CG, the Jacobi fallback, and training.
+
+Bars (BF16 weights and activations, FP32 accumulation): forward outputs and loss
+within 3e-2 relative of the FP64 oracle on the same bf16-rounded weights and
+inputs; gradients with cosine >= 0.999 and relative error <= 5e-2.  The gradient
+bar follows from the arithmetic: the first-layer gradient passes through three
+bf16 roundings (the output gradient and the two back-propagated activations,
+2^-8 relative each) and through ReLU masks whose near-zero pre-activations can
+flip sign between BF16/FP32 and FP64 evaluation.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import mlp as omlp
+from oracle.precision import bf16_bits_to_f64, to_bf16_bits
+from tests._common import OracleProblem, match_by_coords, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1911_09220_amd import learned as L  # noqa: E402
+from paper_1911_09220_amd import pafem as P  # noqa: E402
+
+
+def _bf16(a):
+    return bf16_bits_to_f64(to_bf16_bits(a))
+
+
+def _rounded(params):
+    """Weights as the GPU sees them: bf16 matrices, fp32 biases."""
+    out = {}
+    for k, v in params.items():
+        out[k] = _bf16(v) if k.startswith("W") else v.astype(np.float32).astype(np.float64)
+    return out
+
+
+def _cos(a, b):
+    return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def _params(net, seed, zero_last=False):
+    p = synth.mlp_init(net.in_dim, net.hidden, net.out_dim, seed=seed, zero_last=zero_last)
+    rng = np.random.default_rng(seed + 1)
+    for k in ("b1", "b2", "b3"):
+        p[k] = 0.05 * rng.normal(size=p[k].shape)
+    return p
+
+
+def test_network_forward_backward_vs_oracle():
+    rows = 300
+    net = P.Net(3, hidden=64, max_rows=rows, max_train_rows=rows)
+    params = _params(net, 3)
+    net.set_params(params)
+    rng = np.random.default_rng(4)
+    xbits = to_bf16_bits(rng.normal(size=(rows, net.in_dim)))
+    dbits = to_bf16_bits(rng.normal(size=(rows, net.out_dim)))
+    xd = torch.as_tensor(xbits.view(np.int16), device="cuda").contiguous()
+    dd = torch.as_tensor(dbits.view(np.int16), device="cuda").contiguous()
+    out = net.forward(xd, rows).cpu().numpy()
+    pr = _rounded(params)
+    ref, cache = omlp.forward(pr, bf16_bits_to_f64(xbits))
+    assert rel_err(out, ref) <= 3e-2
+    net.backward(xd, dd, rows)
+    g = net.get_grads()
+    gr = omlp.backward(pr, cache, bf16_bits_to_f64(dbits))
+    for k in net.NAMES:
+        c, e = _cos(g[k], gr[k]), rel_err(g[k], gr[k])
+        print(f"{k}: cosine {c:.5f} rel {e:.2e}")
+        assert c >= 0.999 and e <= 5e-2, k
+
+
+def _small_problem(p=2, n=(3, 3, 2), seed=5):
+    mesh = synth.hex_lattice(n, 0.1, seed=seed, rotate_seed=seed + 1)
+    E = mesh["hex"].shape[0]
+    kappa = synth.lognormal_iid(E, p + 2, 1.0, seed=seed + 2)
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    kc = torch.as_tensor(kappa, device="cuda")
+    op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kc))
+    diag = op.diagonal()
+    feats = P.learned_features(S, kc)
+    ref = OracleProblem(mesh, p, coeff=kappa)
+    return mesh, kappa, S, op, diag, feats, ref
+
+
+def test_zero_last_layer_is_jacobi():
+    mesh, kappa, S, op, diag, feats, ref = _small_problem()
+    net = P.Net(2, hidden=32, max_rows=S.nelem, max_train_rows=S.nelem)
+    net.set_params(_params(net, 6, zero_last=True) | {"b3": np.zeros(net.out_dim)})
+    X = S.dof_coords()
+    r = torch.as_tensor(synth.hash_normal(X, seed=7), device="cuda")
+    r[torch.as_tensor(S.boundary_dofs(), device="cuda").long()] = 0.0
+    z = P.learned_precond(net, op, feats, diag, r)
+    jac = torch.where(diag != 0, r / diag, torch.zeros_like(r))
+    assert float((z - jac).abs().max()) == 0.0
+
+
+def test_preconditioner_and_loss_gradients_vs_oracle():
+    p = 2
+    mesh, kappa, S, op, diag, feats, ref = _small_problem(p)
+    net = P.Net(p, hidden=32, max_rows=S.nelem, max_train_rows=S.nelem)
+    params = _params(net, 8)
+    params["W3"] *= 3.0
+    net.set_params(params)
+    pr = _rounded(params)
+    X = S.dof_coords()
+    perm = match_by_coords(X, ref.coords)
+    bd = ref.space.boundary
+    e_or = synth.hash_normal(ref.coords, seed=9)
+    e_or[bd] = 0.0
+    e_lib = synth.hash_normal(X, seed=9)
+    e_lib[ref.space.boundary[perm]] = 0.0
+    e = torch.as_tensor(e_lib, device="cuda")
+    r = op.apply(e)
+    kbar, f8 = omlp.element_features(kappa, p + 2)
+    in_dim = net.in_dim
+    r_or = ref.Kc @ e_or
+    d_or = ref.Kc.diagonal()
+    z = P.learned_precond(net, op, feats, diag, r).cpu().numpy()
+    z_or, _ = omlp.precondition(pr, r_or, d_or, ref.space.elem_dofs, bd, f8.astype(np.float32),
+                                kbar.astype(np.float32), in_dim)
+    err = rel_err(z, z_or[perm])
+    print(f"preconditioner rel err {err:.2e}")
+    assert err <= 3e-2
+    loss = float(P.learned_loss_grad(net, op, feats, diag, r, e)[0])
+    L_or, G_or = omlp.loss_and_grads(pr, ref.Kc, r_or, e_or, d_or, ref.space.elem_dofs, bd,
+                                     f8.astype(np.float32), kbar.astype(np.float32), in_dim)
+    print(f"loss {loss:.6f} oracle {L_or:.6f}")
+    assert abs(loss - L_or) <= 3e-2 * abs(L_or)
+    g = net.get_grads()
+    for k in net.NAMES:
+        c, er = _cos(g[k], G_or[k]), rel_err(g[k], G_or[k])
+        print(f"{k}: cosine {c:.5f} rel {er:.2e}")
+        assert c >= 0.999 and er <= 5e-2, k
+
+
+def test_fcg_with_jacobi_matches_pcg():
+    mesh, kappa, S, op, diag, feats, ref = _small_problem(2, (6, 6, 6))
+    b = S.linear_form(P.SOURCE_SINE)
+    x1, i1 = op.pcg(b, diag=diag, rel_tol=1e-10)
+    x2, i2 = P.fcg_solve(op, b, diag, rel_tol=1e-10)
+    assert i2["converged"] and abs(i1["iters"] - i2["iters"]) <= 1
+    assert float((x1 - x2).norm() / x1.norm()) < 1e-8
+    perm = match_by_coords(S.dof_coords(), ref.coords)
+    xd = spla.spsolve(ref.Kc.tocsc(), ref.load(synth.sine_source))
+    assert rel_err(x2.cpu().numpy(), xd[perm]) < 1e-8
+
+
+def test_fallback_on_broken_network():
+    mesh, kappa, S, op, diag, feats, ref = _small_problem(2, (5, 5, 5))
+    net = P.Net(2, hidden=32, max_rows=S.nelem, max_train_rows=0)
+    params = _params(net, 10)
+    params["b3"] = np.full(net.out_dim, np.nan)
+    net.set_params(params)
+    b = S.linear_form(P.SOURCE_SINE)
+    x, info = P.fcg_solve(op, b, diag, net=net, feats=feats, rel_tol=1e-10)
+    assert info["fell_back"] and info["converged"] and info["true_rel_res"] < 1e-9
+    perm = match_by_coords(S.dof_coords(), ref.coords)
+    xd = spla.spsolve(ref.Kc.tocsc(), ref.load(synth.sine_source))
+    assert rel_err(x.cpu().numpy(), xd[perm]) < 1e-8
+
+
+def test_training_lowers_loss_and_fcg_converges():
+    p = 3
+    mesh = synth.hex_lattice(6, 0.05, seed=11)
+    E = mesh["hex"].shape[0]
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    net = P.Net(p, hidden=64, max_rows=E, max_train_rows=E)
+    net.set_params(synth.mlp_init(net.in_dim, 64, net.out_dim, seed=12, zero_last=True))
+    samples = []
+    pts = synth.lattice_quadrature_points(6, p + 2)
+    for f in range(4):
+        kappa = torch.as_tensor(synth.grf_lognormal(pts, 0.1, 1e3, seed=1000 + f), device="cuda")
+        kappa = kappa.reshape(E, -1).contiguous()
+        op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kappa))
+        diag = op.diagonal()
+        feats = P.learned_features(S, kappa)
+        b = S.linear_form(P.SOURCE_SINE)
+        for r, e in L.jacobi_pairs(op, b, diag):
+            samples.append((op, feats, diag, r, e))
+    losses = L.train(net, samples, steps=300, lr=2e-3)
+    first, last = losses[:20].mean(), losses[-20:].mean()
+    print(f"loss {first:.4f} -> {last:.4f}")
+    assert np.all(np.isfinite(losses)) and last < first
+    op, feats, diag = samples[0][0], samples[0][1], samples[0][2]
+    b = S.linear_form(P.SOURCE_SINE)
+    x, info = P.fcg_solve(op, b, diag, net=net, feats=feats, rel_tol=1e-8)
+    assert info["converged"] and info["true_rel_res"] < 1e-7
