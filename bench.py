@@ -29,6 +29,37 @@ FP64_PEAK_TFLOPS = 78.6
 METRIC = "PA diffusion apply GDOF/s (p=1–8); CG time-to-1e-8, chosen vs plain FP64"
 
 
+APPLY_SOURCES = ("paper_1911_09220_amd/csrc/k_apply.hip", "paper_1911_09220_amd/csrc/device.hpp",
+                 "paper_1911_09220_amd/csrc/internal.hpp", "paper_1911_09220_amd/csrc/space.cpp")
+
+
+def log(msg: str) -> None:
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
+def apply_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in APPLY_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(p: int):
+    """HBM bytes per launch of the p-order diffusion apply from the committed counter record,
+    or None when the record was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"pa_apply_diffusion_p{p}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != apply_source_hash():
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 def lattice_size(p: int, target_dofs: float) -> int:
     return max(1, int(round((target_dofs ** (1.0 / 3.0) - 1.0) / p)))
 
@@ -151,6 +182,7 @@ def bench_mixed(P, torch, n=45, p=6, tol=1e-8):
     x64, i64 = hi.pcg(b, diag=diag, rel_tol=tol, max_iter=20000, history=False)
     out["fp64_pcg"] = {"seconds": round(i64["seconds"], 4), "iters": i64["iters"],
                        "true_rel_res": i64["true_rel_res"]}
+    log(f"mixed: FP64 PCG {i64['iters']} its {i64['seconds']:.3f} s")
     for name, dt in (("fp32", P.F32), ("bf16", P.BF16)):
         lo = P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, dt), qdata_dtype=dt)
         x, info = hi.ir_solve(lo, b, diag=diag, rel_tol=tol, inner_rel_tol=1e-2, max_outer=40,
@@ -163,6 +195,7 @@ def bench_mixed(P, torch, n=45, p=6, tol=1e-8):
                              "inner_iters": info["inner_total"], "rel_res": info["rel_res"],
                              "solution_rel_diff_vs_fp64_pcg": err, "apply_rel_err": ea,
                              "speedup_vs_fp64": round(i64["seconds"] / info["seconds"], 3)}
+        log(f"mixed: IR {name} {info['outer']} outer {info['inner_total']} inner {info['seconds']:.3f} s")
         del lo
     return out
 
@@ -207,6 +240,7 @@ def bench_batched(P, torch, nrhs=16, reps=20, tune_cache=None):
             res[mode] = {"ms": round(t * 1e3, 4), "gdofs_rhs": round(total * nrhs / t / 1e9, 3)}
         res["tiles"] = B.describe()["groups"]
         out[name] = res
+        log(f"batched: {name} {res['default']['ms']} ms default, {res['autotuned']['ms']} ms tuned")
     return out
 
 
@@ -222,14 +256,15 @@ def bench_learned(P, torch, n_train=16, n_test=64, p=3, fields=20, heldout=2, st
     pts = synth.lattice_quadrature_points(n_train, p + 2)
     samples = []
     for f in range(fields):
-        kappa = torch.as_tensor(synth.grf_lognormal(pts, 0.1, 1e3, seed=1000 + f),
-                                device="cuda").reshape(E, -1).contiguous()
+        kappa = synth.grf_lognormal(pts, 0.1, 1e3, seed=1000 + f,
+                                    device="cuda").reshape(E, -1).contiguous()
         op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kappa))
         diag = op.diagonal()
         feats = P.learned_features(S, kappa)
         b = S.linear_form(P.SOURCE_SINE)
         for r, e in L.jacobi_pairs(op, b, diag):
             samples.append((op, feats, diag, r, e))
+        log(f"learned: field {f + 1}/{fields}, {len(samples)} pairs")
     t_pairs = time.perf_counter() - t0
     test_mesh = synth.hex_lattice(n_test, 0.05, seed=22)
     Et = test_mesh["hex"].shape[0]
@@ -238,7 +273,8 @@ def bench_learned(P, torch, n_train=16, n_test=64, p=3, fields=20, heldout=2, st
     net = P.Net(p, hidden=128, max_rows=max(E, Et), max_train_rows=E)
     net.set_params(synth.mlp_init(net.in_dim, 128, net.out_dim, seed=23, zero_last=True))
     t1 = time.perf_counter()
-    losses = L.train(net, samples, steps=steps, lr=2e-3, decay_every=max(1, steps // 3))
+    losses = L.train(net, samples, steps=steps, lr=2e-3, decay_every=max(1, steps // 3),
+                     log_every=max(1, steps // 5), log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     out = {"order": p, "train_mesh": n_train, "train_fields": fields, "pairs": len(samples),
@@ -248,13 +284,14 @@ def bench_learned(P, torch, n_train=16, n_test=64, p=3, fields=20, heldout=2, st
            "test_mesh": n_test, "test_ndofs": St.ndofs, "tol": tol, "heldout": []}
     pts_t = synth.lattice_quadrature_points(n_test, p + 2)
     for f in range(heldout):
-        kappa = torch.as_tensor(synth.grf_lognormal(pts_t, 0.1, 1e3, seed=2000 + f),
-                                device="cuda").reshape(Et, -1).contiguous()
+        kappa = synth.grf_lognormal(pts_t, 0.1, 1e3, seed=2000 + f,
+                                    device="cuda").reshape(Et, -1).contiguous()
         op = P.Operator(St, P.DIFFUSION, St.qdata(P.DIFFUSION, coeff=kappa))
         diag = op.diagonal()
         feats = P.learned_features(St, kappa)
         b = St.linear_form(P.SOURCE_SINE)
         _, ij = op.pcg(b, diag=diag, rel_tol=tol, max_iter=20000, history=False)
+        log(f"learned: held-out field {f}: Jacobi-PCG {ij['iters']} its {ij['seconds']:.3f} s")
         _, il = P.fcg_solve(op, b, diag, net=net, feats=feats, rel_tol=tol, max_iter=20000,
                             history=False)
         out["heldout"].append({
@@ -264,6 +301,7 @@ def bench_learned(P, torch, n_train=16, n_test=64, p=3, fields=20, heldout=2, st
             "learned_fcg": {"seconds": round(il["seconds"], 4), "iters": il["iters"],
                             "true_rel_res": il["true_rel_res"], "fell_back": il["fell_back"]},
             "speedup": round(ij["seconds"] / il["seconds"], 3)})
+        log(f"learned: held-out field {f}: FCG {il['iters']} its {il['seconds']:.3f} s")
         del op, diag, feats, b, kappa
     return out
 
@@ -332,7 +370,8 @@ def main():
     by = algorithmic_bytes("diffusion", dom["p"], dom["ne"], dom["ndofs"])
     achieved = by / per[k] / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": recorded_traffic(dom["p"]), "source_hash": apply_source_hash(),
                 "kernel": f"pa_apply_kernel diffusion p={dom['p']} q1d={dom['p'] + 2} f64 "
                           f"({args.scatter} scatter, with its y-init kernel)",
                 "bytes_per_launch": by}
@@ -376,13 +415,13 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     if "mixed" in forms:
-        print("# mixed precision", file=sys.stderr, flush=True)
+        log("mixed precision")
         out["mixed_precision"] = bench_mixed(P, torch)
     if "batched" in forms:
-        print("# batched", file=sys.stderr, flush=True)
+        log("batched")
         out["batched"] = bench_batched(P, torch)
     if "learned" in forms:
-        print("# learned", file=sys.stderr, flush=True)
+        log("learned")
         out["learned"] = bench_learned(P, torch, fields=args.learned_fields,
                                        steps=args.learned_steps)
     if not args.no_cpu_baseline:

@@ -2,19 +2,25 @@
 // diffusion on hexahedra ("Operator Decomposition", "High-Order Partial
 // Assembly").
 //
-// One workgroup holds NE elements; each element gets a Q x Q plane of threads
-// (qx, qy) that walks the third direction in registers.  Per element:
+// One workgroup holds NE elements (one tile of the tile-interleaved quadrature
+// data); each element gets Q*Q threads.  Every contraction is done one 1D line per
+// thread: a thread loads the D (or Q) inputs of its line into registers and
+// produces all Q (or D) outputs of that line, so the 1D table entries it multiplies
+// by are the same for every thread of the wave and are read as scalars, and each
+// intermediate value passes through LDS once.  Per element:
 //   G    gather the tile's unique dofs once into LDS (essential dofs read as 0 when
-//        constrained) and expand them to the element nodes through a slot map
-//   B    three one-axis contractions with the 1D tables (sum factorization):
-//        x-axis through LDS, y-axis through LDS into registers, z-axis in registers
-//   D    pointwise: 1 value (mass) or a symmetric 3x3 (diffusion) per point,
-//        streamed from HBM once with non-temporal loads, issued before the gather
-//   B^t  the transposed contractions in reverse order (z in registers, y and x
-//        through LDS)
+//        constrained); a thread owning the x-line (dz, dy) picks its D values
+//        through the tile slot map
+//   B    x-lines (dz, dy) -> y-lines (dz, qx) -> z-lines (qy, qx)
+//   D    pointwise on the z-line: 1 value (mass) or a symmetric 3x3 (diffusion) per
+//        point, streamed from HBM with non-temporal loads issued before the gather
+//   B^t  z-lines (in registers) -> y-lines -> x-lines
 //   G^t  either: sum the element outputs per unique dof of the tile in LDS, then one
 //        hardware FP atomic per unique dof into y (y pre-set by an init kernel); or
 //        a plain store of the element vector for the deterministic transposed gather.
+// All intermediate arrays of an element share one LDS region: every stage writes
+// only entries that the same thread has just read, so a region of 3*Q*Q lines of
+// D values (1*Q*Q for mass) holds them all.
 // Blocks are remapped so each XCD processes one contiguous range of elements.
 #include "device.hpp"
 #include "launch.hpp"
@@ -35,47 +41,43 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
                     const uint16_t* __restrict__ tile_slot, const double* __restrict__ tabB,
                     const double* __restrict__ tabG, const TD* __restrict__ qd,
                     const TV* __restrict__ x, TV* __restrict__ y, int ne, int constrained) {
-  constexpr int D = P + 1, QQ = Q * Q, QQQ = Q * Q * Q, DDD = D * D * D;
+  constexpr int D = P + 1, DD = D * D, QQ = Q * Q, QQQ = Q * Q * Q, DDD = D * D * D;
   constexpr int NE = elems_per_block<Q>();
   constexpr bool DIFF = (KIND == PAFEM_DIFFUSION);
   constexpr int NC = DIFF ? 6 : 1;   // stored values per quadrature point
-  constexpr int NA = DIFF ? 2 : 1;   // x-contraction outputs (B, G)
-  constexpr int NCC = DIFF ? 3 : 1;  // z^t-contraction outputs
+  constexpr int NA = DIFF ? 2 : 1;   // arrays after the x-lines (B and G along x)
+  constexpr int NCC = DIFF ? 3 : 1;  // arrays after the y-lines (one per derivative)
+  // Line stride: odd, so that threads walking consecutive lines hit distinct banks.
+  constexpr int LC = D | 1;
+  constexpr int ELEM = NCC * QQ * LC;
+  static_assert(NA * D <= NCC * Q, "x-line outputs must fit the element region");
 
-  __shared__ TC sB[Q][D];
-  __shared__ TC sG[Q][D];
-  __shared__ TC sU[NE][D][D][D];
-  __shared__ TC sA[NE][NA][D][D][Q];
-  __shared__ TC sC[NE][NCC][D][Q][Q];
-
-  // The tile's unique dofs: x is gathered once per unique dof into sX, and the
-  // element outputs are summed per unique dof in sY before one global atomic
-  // per unique dof.  sX aliases sC (not live before the z-loop ends), sY aliases
-  // sU (not live after the x-contraction).
-  TC* const sX = &sC[0][0][0][0][0];
-  TC* const sY = &sU[0][0][0][0];
+  __shared__ TC sW[NE * ELEM];
+  // The tile's unique dofs: x gathered once per unique dof, later the element
+  // outputs summed per unique dof before one global atomic each.
+  __shared__ TC sX[NE * DDD];
 
   const int tid = threadIdx.x;
   const int el = tid / QQ;
   const int r = tid - el * QQ;
-  const int qx = r % Q, qy = r / Q;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int e = tile * NE + el;
   const bool act = e < ne;
   const int u0 = tile_off[tile];
   const int nu = tile_off[tile + 1] - u0;
+  TC* const W = sW + el * ELEM;
+  // entry (c, qy, qx, dz) of the element region; the x-line outputs (a, dz, dy, qx)
+  // live at c*Q + qy = a*D + dy
+  auto at = [&](int c, int qy, int qx, int dz) -> TC& { return W[((c * Q + qy) * Q + qx) * LC + dz]; };
+  auto bB = [&](int q, int d) -> TC { return TC(tabB[q * D + d]); };
+  auto bG = [&](int q, int d) -> TC { return TC(tabG[q * D + d]); };
 
-  for (int i = tid; i < Q * D; i += NE * QQ) {
-    (&sB[0][0])[i] = TC(tabB[i]);
-    if (DIFF) (&sG[0][0])[i] = TC(tabG[i]);
-  }
-
-  // D for this thread's (qx, qy) column: issued first so the HBM stream overlaps
-  // the gather and the forward contractions
-  // (tile-interleaved: for each (c, qz) the workgroup reads one contiguous run)
+  // D for this thread's z-line (qx, qy) = r: issued first so the HBM stream
+  // overlaps the gather and the forward contractions (tile-interleaved: for each
+  // (c, qz) the workgroup reads one contiguous run)
   TC dq[Q][NC];
   if (act) {
-    const TD* qe = qd + size_t(e / NE) * NC * QQQ * NE + tid;
+    const TD* qe = qd + size_t(tile) * NC * QQQ * NE + tid;
 #pragma unroll
     for (int qz = 0; qz < Q; ++qz)
 #pragma unroll
@@ -83,8 +85,8 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
         dq[qz][c] = load_value<TC, TD>(qe + (c * Q + qz) * (NE * QQ));
   }
 
-  // G: gather the tile's unique dofs, then expand to the element nodes
-  // four unique dofs per thread per step keep several gathers in flight
+  // G: gather the tile's unique dofs; four per thread per step keep several
+  // gathers in flight
   for (int s0 = tid; s0 < nu; s0 += 4 * NE * QQ) {
     int gg[4];
 #pragma unroll
@@ -102,143 +104,175 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
     for (int k = 0; k < 4; ++k)
       if (s0 + k * NE * QQ < nu) sX[s0 + k * NE * QQ] = xv[k];
   }
+  // x-line (dz, dy) = r < D*D: its D slots in the tile's unique dofs
+  const bool xline = act && r < DD;
+  const int xz = r / D, xy = r - (r / D) * D;
   int slot[D];
-  const bool dof_thread = act && qx < D && qy < D;
-  if (dof_thread) {
-    const uint16_t* sl = tile_slot + size_t(e) * DDD + qy * D + qx;
+  if (xline) {
+    const uint16_t* sl = tile_slot + size_t(e) * DDD + r * D;
 #pragma unroll
-    for (int dz = 0; dz < D; ++dz) slot[dz] = sl[dz * D * D];
-  }
-  __syncthreads();
-  if (dof_thread) {
-#pragma unroll
-    for (int dz = 0; dz < D; ++dz) sU[el][dz][qy][qx] = sX[slot[dz]];
+    for (int dx = 0; dx < D; ++dx) slot[dx] = sl[dx];
   }
   __syncthreads();
 
-  // B, x-axis: thread (qx, dy = qy)
-  if (qy < D) {
+  // B along x: thread (dz, dy)
+  if (xline) {
+    TC u[D];
 #pragma unroll
-    for (int dz = 0; dz < D; ++dz) {
+    for (int dx = 0; dx < D; ++dx) u[dx] = sX[slot[dx]];
+#pragma unroll
+    for (int qx = 0; qx < Q; ++qx) {
       TC b = TC(0), g = TC(0);
 #pragma unroll
       for (int dx = 0; dx < D; ++dx) {
-        const TC u = sU[el][dz][qy][dx];
-        b += sB[qx][dx] * u;
-        if (DIFF) g += sG[qx][dx] * u;
+        b += bB(qx, dx) * u[dx];
+        if (DIFF) g += bG(qx, dx) * u[dx];
       }
-      sA[el][0][dz][qy][qx] = b;
-      if (DIFF) sA[el][NA - 1][dz][qy][qx] = g;
+      at(xy / Q, xy % Q, qx, xz) = b;
+      if (DIFF) at((D + xy) / Q, (D + xy) % Q, qx, xz) = g;
     }
   }
   __syncthreads();
 
-  // sU is dead from here on: clear the per-unique-dof accumulators it now holds
+  // sX is dead from here on: clear the per-unique-dof accumulators it now holds
   if (!EVEC)
-    for (int s = tid; s < nu; s += NE * QQ) sY[s] = TC(0);
+    for (int s = tid; s < nu; s += NE * QQ) sX[s] = TC(0);
 
-  // B, y-axis into registers: thread (qx, qy)
-  TC BB[D], GB[D], BG[D];
-#pragma unroll
-  for (int dz = 0; dz < D; ++dz) {
-    TC bb = TC(0), gb = TC(0), bg = TC(0);
+  // B along y: thread (dz, qx) = r < D*Q
+  const bool yline = act && r < D * Q;
+  const int yz = r / Q, yx = r - (r / Q) * Q;
+  if (yline) {
+    TC aB[D], aG[D];
 #pragma unroll
     for (int dy = 0; dy < D; ++dy) {
-      const TC a0 = sA[el][0][dz][dy][qx];
-      const TC by = sB[qy][dy];
-      bb += by * a0;
-      if (DIFF) {
-        const TC a1 = sA[el][NA - 1][dz][dy][qx];
-        gb += by * a1;
-        bg += sG[qy][dy] * a0;
-      }
+      aB[dy] = at(dy / Q, dy % Q, yx, yz);
+      if (DIFF) aG[dy] = at((D + dy) / Q, (D + dy) % Q, yx, yz);
     }
-    BB[dz] = bb;
-    GB[dz] = gb;
-    BG[dz] = bg;
-  }
-
-  // B z-axis, D, B^t z-axis: all in registers
-  TC tBB[D], tGB[D], tBG[D];
 #pragma unroll
-  for (int dz = 0; dz < D; ++dz) tBB[dz] = tGB[dz] = tBG[dz] = TC(0);
+    for (int qy = 0; qy < Q; ++qy) {
+      TC gb = TC(0), bg = TC(0), bb = TC(0);
 #pragma unroll
-  for (int qz = 0; qz < Q; ++qz) {
-    if (DIFF) {
-      TC ux = TC(0), uy = TC(0), uz = TC(0);
-#pragma unroll
-      for (int dz = 0; dz < D; ++dz) {
-        const TC bz = sB[qz][dz], gz = sG[qz][dz];
-        ux += bz * GB[dz];
-        uy += bz * BG[dz];
-        uz += gz * BB[dz];
-      }
-      const TC vx = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
-      const TC vy = dq[qz][1] * ux + dq[qz][3] * uy + dq[qz][4] * uz;
-      const TC vz = dq[qz][2] * ux + dq[qz][4] * uy + dq[qz][5] * uz;
-#pragma unroll
-      for (int dz = 0; dz < D; ++dz) {
-        const TC bz = sB[qz][dz], gz = sG[qz][dz];
-        tGB[dz] += bz * vx;
-        tBG[dz] += bz * vy;
-        tBB[dz] += gz * vz;
-      }
-    } else {
-      TC u = TC(0);
-#pragma unroll
-      for (int dz = 0; dz < D; ++dz) u += sB[qz][dz] * BB[dz];
-      const TC v = dq[qz][0] * u;
-#pragma unroll
-      for (int dz = 0; dz < D; ++dz) tBB[dz] += sB[qz][dz] * v;
-    }
-  }
-#pragma unroll
-  for (int dz = 0; dz < D; ++dz) {
-    if (DIFF) {
-      sC[el][0][dz][qy][qx] = tGB[dz];
-      sC[el][1][dz][qy][qx] = tBG[dz];
-      sC[el][2][dz][qy][qx] = tBB[dz];
-    } else {
-      sC[el][0][dz][qy][qx] = tBB[dz];
-    }
-  }
-  __syncthreads();
-
-  // B^t, y-axis: thread (qx, dy = qy)
-  if (qy < D) {
-#pragma unroll
-    for (int dz = 0; dz < D; ++dz) {
-      TC bx = TC(0), gx = TC(0);
-#pragma unroll
-      for (int q2 = 0; q2 < Q; ++q2) {
-        const TC by = sB[q2][qy];
+      for (int dy = 0; dy < D; ++dy) {
+        bb += bB(qy, dy) * aB[dy];
         if (DIFF) {
-          gx += by * sC[el][0][dz][q2][qx];
-          bx += sG[q2][qy] * sC[el][1][dz][q2][qx] + by * sC[el][2][dz][q2][qx];
-        } else {
-          bx += by * sC[el][0][dz][q2][qx];
+          gb += bB(qy, dy) * aG[dy];
+          bg += bG(qy, dy) * aB[dy];
         }
       }
-      sA[el][0][dz][qy][qx] = bx;
-      if (DIFF) sA[el][NA - 1][dz][qy][qx] = gx;
+      if (DIFF) {
+        at(0, qy, yx, yz) = gb;
+        at(1, qy, yx, yz) = bg;
+        at(2, qy, yx, yz) = bb;
+      } else {
+        at(0, qy, yx, yz) = bb;
+      }
     }
   }
   __syncthreads();
 
-  // B^t, x-axis and G^t: thread (dx = qx, dy = qy)
-  if (dof_thread) {
+  // B along z, D, B^t along z: thread (qy, qx) = r, in registers, written back in place
+  if (act) {
+    const int zy = r / Q, zx = r - (r / Q) * Q;
+    TC c0[D], c1[D], c2[D];
 #pragma unroll
     for (int dz = 0; dz < D; ++dz) {
+      c0[dz] = at(0, zy, zx, dz);
+      if (DIFF) {
+        c1[dz] = at(1, zy, zx, dz);
+        c2[dz] = at(2, zy, zx, dz);
+      }
+    }
+    TC t0[D], t1[D], t2[D];
+#pragma unroll
+    for (int dz = 0; dz < D; ++dz) t0[dz] = t1[dz] = t2[dz] = TC(0);
+#pragma unroll
+    for (int qz = 0; qz < Q; ++qz) {
+      if (DIFF) {
+        TC ux = TC(0), uy = TC(0), uz = TC(0);
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) {
+          ux += bB(qz, dz) * c0[dz];
+          uy += bB(qz, dz) * c1[dz];
+          uz += bG(qz, dz) * c2[dz];
+        }
+        const TC vx = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
+        const TC vy = dq[qz][1] * ux + dq[qz][3] * uy + dq[qz][4] * uz;
+        const TC vz = dq[qz][2] * ux + dq[qz][4] * uy + dq[qz][5] * uz;
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) {
+          t0[dz] += bB(qz, dz) * vx;
+          t1[dz] += bB(qz, dz) * vy;
+          t2[dz] += bG(qz, dz) * vz;
+        }
+      } else {
+        TC u = TC(0);
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) u += bB(qz, dz) * c0[dz];
+        const TC v = dq[qz][0] * u;
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * v;
+      }
+    }
+#pragma unroll
+    for (int dz = 0; dz < D; ++dz) {
+      at(0, zy, zx, dz) = t0[dz];
+      if (DIFF) {
+        at(1, zy, zx, dz) = t1[dz];
+        at(2, zy, zx, dz) = t2[dz];
+      }
+    }
+  }
+  __syncthreads();
+
+  // B^t along y: thread (dz, qx)
+  if (yline) {
+    TC v0[Q], v1[Q], v2[Q];
+#pragma unroll
+    for (int qy = 0; qy < Q; ++qy) {
+      v0[qy] = at(0, qy, yx, yz);
+      if (DIFF) {
+        v1[qy] = at(1, qy, yx, yz);
+        v2[qy] = at(2, qy, yx, yz);
+      }
+    }
+#pragma unroll
+    for (int dy = 0; dy < D; ++dy) {
+      TC b = TC(0), g = TC(0);
+#pragma unroll
+      for (int qy = 0; qy < Q; ++qy) {
+        if (DIFF) {
+          g += bB(qy, dy) * v0[qy];
+          b += bG(qy, dy) * v1[qy] + bB(qy, dy) * v2[qy];
+        } else {
+          b += bB(qy, dy) * v0[qy];
+        }
+      }
+      at(dy / Q, dy % Q, yx, yz) = b;
+      if (DIFF) at((D + dy) / Q, (D + dy) % Q, yx, yz) = g;
+    }
+  }
+  __syncthreads();
+
+  // B^t along x and G^t: thread (dz, dy)
+  if (xline) {
+    TC wB[Q], wG[Q];
+#pragma unroll
+    for (int qx = 0; qx < Q; ++qx) {
+      wB[qx] = at(xy / Q, xy % Q, qx, xz);
+      if (DIFF) wG[qx] = at((D + xy) / Q, (D + xy) % Q, qx, xz);
+    }
+#pragma unroll
+    for (int dx = 0; dx < D; ++dx) {
       TC acc = TC(0);
 #pragma unroll
-      for (int q1 = 0; q1 < Q; ++q1) {
-        acc += sB[q1][qx] * sA[el][0][dz][qy][q1];
-        if (DIFF) acc += sG[q1][qx] * sA[el][NA - 1][dz][qy][q1];
+      for (int qx = 0; qx < Q; ++qx) {
+        acc += bB(qx, dx) * wB[qx];
+        if (DIFF) acc += bG(qx, dx) * wG[qx];
       }
       if (EVEC)
-        y[size_t(e) * DDD + dz * D * D + qy * D + qx] = TV(acc);
+        y[size_t(e) * DDD + r * D + dx] = TV(acc);
       else
-        atomicAdd(&sY[slot[dz]], acc);
+        atomicAdd(&sX[slot[dx]], acc);
     }
   }
   if (EVEC) return;
@@ -247,7 +281,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll 4
   for (int s = tid; s < nu; s += NE * QQ) {
     const int g = tile_dofs[u0 + s];
-    if (!(constrained && g < 0)) unsafeAtomicAdd(&y[g < 0 ? ~g : g], TV(sY[s]));
+    if (!(constrained && g < 0)) unsafeAtomicAdd(&y[g < 0 ? ~g : g], TV(sX[s]));
   }
 }
 

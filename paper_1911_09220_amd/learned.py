@@ -28,7 +28,8 @@ def jacobi_pairs(op, b, diag, stops=(2, 5, 10, 20, 40, 80), tight=1e-12, max_ite
     return pairs
 
 
-def train(net, samples, steps=500, lr=2e-3, lr_decay=0.5, decay_every=200, seed=0, log_every=0):
+def train(net, samples, steps=500, lr=2e-3, lr_decay=0.5, decay_every=200, seed=0, log_every=0,
+          log=print):
     """Adam on the loss of randomly drawn samples.
 
     samples: list of (op, feats, diag, r, e).  Returns the per-step losses (host).
@@ -48,5 +49,5 @@ def train(net, samples, steps=500, lr=2e-3, lr_decay=0.5, decay_every=200, seed=
         P.learned_loss_grad(net, op, feats, diag, r, e, loss=loss_dev[t:t + 1], work=w)
         net.adam_step(cur_lr)
         if log_every and (t + 1) % log_every == 0:
-            print(f"step {t + 1}: loss {float(loss_dev[t]):.4f}", flush=True)
+            log(f"train step {t + 1}: loss {float(loss_dev[t]):.4f}")
     return loss_dev.cpu().numpy()

@@ -149,24 +149,38 @@ def lattice_quadrature_points(n: int, q1d: int) -> np.ndarray:
     return (base[:, None, :] + ref[None, :, :]) / n
 
 
-def grf_lognormal(points: np.ndarray, ell: float = 0.1, contrast: float = 1e3,
-                  seed: int = 0, modes: int = 1024) -> np.ndarray:
+def grf_lognormal(points, ell: float = 0.1, contrast: float = 1e3, seed: int = 0,
+                  modes: int = 1024, device=None):
     """Lognormal field exp(s * g(x)) with g a unit-variance Gaussian field.
 
     g uses random Fourier features of a squared-exponential covariance with
     correlation length ``ell``; s is chosen so max/min of the field over the given
-    points equals ``contrast``.
+    points equals ``contrast``.  With ``device`` (a torch device) the features are
+    evaluated there in float64 and a torch tensor is returned: same frequencies and
+    phases, values equal to the host ones up to the rounding of cos.
     """
     rng = np.random.default_rng(seed)
     omega = rng.normal(scale=1.0 / ell, size=(modes, 3))
     phase = rng.uniform(0.0, 2.0 * np.pi, size=modes)
-    flat = points.reshape(-1, 3)
-    g = np.empty(flat.shape[0])
+    shape = np.asarray(points).shape[:-1] if device is None else tuple(points.shape[:-1])
     step = 1 << 16
-    for a in range(0, flat.shape[0], step):
-        g[a:a + step] = np.sqrt(2.0 / modes) * np.cos(flat[a:a + step] @ omega.T + phase).sum(axis=1)
-    s = np.log(contrast) / (g.max() - g.min())
-    return np.exp(s * g).reshape(points.shape[:-1])
+    if device is None:
+        flat = np.asarray(points).reshape(-1, 3)
+        g = np.empty(flat.shape[0])
+        for a in range(0, flat.shape[0], step):
+            g[a:a + step] = np.sqrt(2.0 / modes) * np.cos(flat[a:a + step] @ omega.T + phase).sum(axis=1)
+        s = np.log(contrast) / (g.max() - g.min())
+        return np.exp(s * g).reshape(shape)
+    import torch
+    flat = torch.as_tensor(np.asarray(points) if not torch.is_tensor(points) else points,
+                           dtype=torch.float64, device=device).reshape(-1, 3)
+    om = torch.as_tensor(omega.T.copy(), device=device)
+    ph = torch.as_tensor(phase, device=device)
+    g = torch.empty(flat.shape[0], dtype=torch.float64, device=device)
+    for a in range(0, flat.shape[0], 1 << 18):
+        g[a:a + (1 << 18)] = np.sqrt(2.0 / modes) * torch.cos(flat[a:a + (1 << 18)] @ om + ph).sum(dim=1)
+    s = np.log(contrast) / float(g.max() - g.min())
+    return torch.exp(s * g).reshape(shape)
 
 
 def _splitmix64(x: np.ndarray) -> np.ndarray:
