@@ -185,17 +185,21 @@ def bench_mixed(P, torch, n=45, p=6, tol=1e-8):
     log(f"mixed: FP64 PCG {i64['iters']} its {i64['seconds']:.3f} s")
     for name, dt in (("fp32", P.F32), ("bf16", P.BF16)):
         lo = P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, dt), qdata_dtype=dt)
-        x, info = hi.ir_solve(lo, b, diag=diag, rel_tol=tol, inner_rel_tol=1e-2, max_outer=40,
-                              max_inner=20000)
-        err = float((x - x64).norm() / x64.norm())
         # reduced-precision apply error on one vector, against the FP64 apply
         v = b / b.norm()
         ea = float((lo.apply(v.float()).double() - hi.apply(v)).norm() / hi.apply(v).norm())
-        out[f"ir_{name}"] = {"seconds": round(info["seconds"], 4), "outer": info["outer"],
-                             "inner_iters": info["inner_total"], "rel_res": info["rel_res"],
-                             "solution_rel_diff_vs_fp64_pcg": err, "apply_rel_err": ea,
-                             "speedup_vs_fp64": round(i64["seconds"] / info["seconds"], 3)}
-        log(f"mixed: IR {name} {info['outer']} outer {info['inner_total']} inner {info['seconds']:.3f} s")
+        for mode, keep in (("", True), ("_restart", False)):
+            x, info = hi.ir_solve(lo, b, diag=diag, rel_tol=tol, inner_rel_tol=1e-2, max_outer=40,
+                                  max_inner=20000, keep_direction=keep)
+            err = float((x - x64).norm() / x64.norm())
+            out[f"ir_{name}{mode}"] = {
+                "seconds": round(info["seconds"], 4), "outer": info["outer"],
+                "inner_iters": info["inner_total"], "rel_res": info["rel_res"],
+                "solution_rel_diff_vs_fp64_pcg": err, "apply_rel_err": ea,
+                "speedup_vs_fp64": round(i64["seconds"] / info["seconds"], 3)}
+            log(f"mixed: IR {name}{mode} {info['outer']} outer {info['inner_total']} inner "
+                f"{info['seconds']:.3f} s")
+            del x
         del lo
     return out
 
@@ -270,8 +274,8 @@ def bench_learned(P, torch, n_train=16, n_test=64, p=3, fields=20, heldout=2, st
     Et = test_mesh["hex"].shape[0]
     St = P.Space(P.Mesh.from_dict(test_mesh), p)
     del test_mesh
-    net = P.Net(p, hidden=128, max_rows=max(E, Et), max_train_rows=E)
-    net.set_params(synth.mlp_init(net.in_dim, 128, net.out_dim, seed=23, zero_last=True))
+    net = P.Net(p, hidden=64, max_rows=max(E, Et), max_train_rows=E)
+    net.set_params(L.initial_params(net, seed=23))
     t1 = time.perf_counter()
     losses = L.train(net, samples, steps=steps, lr=2e-3, decay_every=max(1, steps // 3),
                      log_every=max(1, steps // 5), log=log)

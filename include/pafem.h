@@ -246,6 +246,8 @@ typedef struct {
   int32_t max_inner;    /* inner PCG iterations per step */
   int32_t check_every;  /* host reads the inner convergence flag every this many iterations */
   int32_t precond;      /* PAFEM_PRECOND_NONE or PAFEM_PRECOND_JACOBI (diag rounded to f32) */
+  int32_t keep_direction; /* 1: the inner PCG keeps its search direction across steps
+                             (residual replacement); 0: it restarts from d = 0 each step */
   double* res_hist;     /* optional host array: outer ||r_k||/||b||, k = 0..outer */
   int32_t res_hist_cap;
 } pafem_ir_opts;
@@ -262,8 +264,16 @@ typedef struct {
 pafem_status pafem_ir_workspace_bytes(pafem_op a_hi, pafem_op a_lo, size_t* nbytes);
 
 /* Iterative refinement: x = 0; repeat r = b - A_hi x (FP64 apply, FP64 residual
- * and norms), solve A_lo d = r/||r|| approximately with Jacobi-PCG whose vectors
- * are FP32 and whose dot products accumulate in FP64, x += ||r|| d (FP64).
+ * and norms), solve A_lo d = r/||r|| approximately with Jacobi-PCG, x += ||r|| d
+ * (FP64).  The inner PCG keeps its residual, preconditioned residual and dot
+ * products in FP64; only the reduced-precision apply's input (the search
+ * direction) and output, and the correction d, are FP32 (the Jacobi scaling is
+ * 1/diag rounded to FP32).  With keep_direction the inner PCG is one continuing
+ * iteration whose residual is replaced by the FP64 residual at every step (a
+ * reliable update: the recurrence and its search direction survive, so the inner
+ * iteration count stays close to that of FP64 PCG); a step that ends on max_inner
+ * instead of inner_rel_tol restarts the inner PCG.  One step = one FP64 residual =
+ * one `outer`.
  * a_hi: an FP64 operator; a_lo: the same operator (same space, kind and flags)
  * built on F32 or BF16 quadrature data.  diag: FP64 diagonal of a_hi (NULL for
  * PAFEM_PRECOND_NONE).  b, x: device f64 [ndofs].  SYNCHRONOUS.  Returns

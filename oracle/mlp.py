@@ -1,24 +1,31 @@
-"""Element-patch network, learned preconditioner and flexible CG (oracle; test infrastructure only).
+"""Element network, learned preconditioner and flexible CG (oracle; test infrastructure only).
 
 None of this is in the paper: the learned preconditioner is an addition to the
 paper's CG on partially assembled operators ("Scalable Linear Solvers" notes
 that matrix-free operators need matrix-free preconditioners).  Definitions:
 
 * Network N: x -> W3 relu(W2 relu(W1 x + b1) + b2) + b3.
-* Element input: x_E = [r_E / s_E, f_E, 0...] with s_E = ||r_E||_2 (+tiny) and f_E
-  the log-ratios of the coefficient mean over the 8 octants of the element's
-  quadrature points to the element mean kbar_E.
-* Preconditioner: z = r / diag + G^t( w * (s_E / kbar_E) * N(x_E) ), w = 1/m_g
-  (m_g = number of element nodes sharing dof g); z = 0 on essential dofs.
+* Element input: x_E = [f_E, 0...], f_E the log-ratios of the coefficient mean over
+  the 8 octants of the element's quadrature points to the element mean kbar_E.
+* Element weights: c_E = softplus(N(x_E)) (K values, positive).
+* Preconditioner, with a learned basis V (one (p+1)^3 x K matrix shared by all
+  elements), the element restriction R_E (essential dofs read as 0) and dbar_E the
+  mean of diag over the element's non-essential nodes (1 if it has none):
+      z = r / diag + sum_E R_E^t V diag(c_E / dbar_E) V^t R_E r,   z = 0 on essential dofs.
+  It is linear in r, symmetric, and the correction is positive semidefinite, so
+  z(r) is an SPD preconditioner for any network and basis; dividing by dbar_E
+  makes it invariant to the scale of the coefficient and to the element size.
 * Training loss on a pair (r, e) with A e = r: L = ||A (e - z(r))||^2_{D^-1} /
   ||r||^2_{D^-1} (the error of the correction measured in the norm a local
   preconditioner controls).
 * Adam with bias correction.
 * Flexible CG with the Polak-Ribiere beta, beta = r_new . (z_new - z_old) / (r . z).
 
-Pins (tests/test_oracle_mlp.py): backward against central finite differences,
-Adam against its closed form on a quadratic, a zero last layer reproduces Jacobi,
-and FCG with a linear SPD preconditioner matches PCG.
+Pins (tests/test_oracle_mlp.py): network backward and the loss gradient (network
+and basis) against central finite differences, Adam against its closed form on a
+quadratic, V = 0 reproduces Jacobi, the preconditioner is symmetric with a positive
+semidefinite correction (brute force on a small mesh), and FCG with a linear SPD
+preconditioner matches PCG.
 """
 import numpy as np
 
@@ -76,47 +83,62 @@ def element_features(kappa, q1d):
     return kbar, feats
 
 
-def patch_inputs(r, elem_dofs, feats, in_dim, tiny=1e-300):
-    """Network inputs [E, in_dim] and the element scales s_E."""
-    rE = r[elem_dofs]
-    s = np.sqrt((rE ** 2).sum(axis=1)) + tiny
-    X = np.zeros((rE.shape[0], in_dim))
-    nd = rE.shape[1]
-    X[:, :nd] = rE / s[:, None]
-    X[:, nd:nd + feats.shape[1]] = feats
-    return X, s
+def softplus(a):
+    return np.logaddexp(0.0, a)
 
 
-def multiplicity(elem_dofs, ndofs):
-    return np.bincount(elem_dofs.ravel(), minlength=ndofs).astype(np.float64)
+def sigmoid(a):
+    return 0.5 * (1.0 + np.tanh(0.5 * a))
 
 
-def precondition(P, r, diag, elem_dofs, boundary, feats, kbar, in_dim):
-    """z = M(r).  Only the first (p+1)^3 network outputs are used (one per element node)."""
-    X, s = patch_inputs(r, elem_dofs, feats, in_dim)
-    out, cache = forward(P, X)
-    nd = elem_dofs.shape[1]
-    m = multiplicity(elem_dofs, r.size)
-    scale = (s / kbar)[:, None]
-    contrib = np.bincount(elem_dofs.ravel(), weights=(scale * out[:, :nd]).ravel(),
-                          minlength=r.size)
-    z = r / diag + contrib / m
+def network_inputs(feats, in_dim):
+    """X [E, in_dim] = [f_E, 0...]."""
+    X = np.zeros((feats.shape[0], in_dim))
+    X[:, :feats.shape[1]] = feats
+    return X
+
+
+def diag_mean(diag, elem_dofs, boundary):
+    """dbar_E: mean of diag over the element's non-essential nodes (1 if none)."""
+    inner = ~boundary[elem_dofs]
+    cnt = inner.sum(axis=1)
+    tot = (diag[elem_dofs] * inner).sum(axis=1)
+    return np.where(cnt > 0, tot / np.maximum(cnt, 1), 1.0)
+
+
+def precondition(P, V, r, diag, elem_dofs, boundary, feats, in_dim):
+    """z = M(r) and the intermediates the gradient needs."""
+    X = network_inputs(feats, in_dim)
+    a, cache = forward(P, X)
+    c = softplus(a)
+    dbar = diag_mean(diag, elem_dofs, boundary)
+    rz = np.where(boundary, 0.0, r)
+    rE = rz[elem_dofs]                       # [E, nd]
+    t = rE @ V                               # [E, K]
+    w = c / dbar[:, None]
+    yE = (w * t) @ V.T                       # [E, nd]
+    z = r / diag + np.bincount(elem_dofs.ravel(), weights=yE.ravel(), minlength=r.size)
     z[boundary] = 0.0
-    return z, (X, s, cache, m, scale)
+    return z, (a, cache, c, dbar, rE, t, w)
 
 
-def loss_and_grads(P, A, r, e, diag, elem_dofs, boundary, feats, kbar, in_dim):
-    """Training loss L = ||A(e - z)||^2_{D^-1} / ||r||^2_{D^-1} and its parameter gradients."""
-    z, (X, s, cache, m, scale) = precondition(P, r, diag, elem_dofs, boundary, feats, kbar, in_dim)
+def loss_and_grads(P, V, A, r, e, diag, elem_dofs, boundary, feats, in_dim):
+    """Training loss L = ||A(e - z)||^2_{D^-1} / ||r||^2_{D^-1}; gradients of the network
+    parameters and of the basis V."""
+    z, (a, cache, c, dbar, rE, t, w) = precondition(P, V, r, diag, elem_dofs, boundary, feats,
+                                                    in_dim)
     u = A @ (e - z)
     rn = r @ (r / diag)
     L = (u @ (u / diag)) / rn
-    dz = -2.0 * (A @ (u / diag)) / rn
-    dz[boundary] = 0.0
-    nd = elem_dofs.shape[1]
-    dout = np.zeros((elem_dofs.shape[0], P["W3"].shape[0]))
-    dout[:, :nd] = scale * (dz / m)[elem_dofs]
-    return L, backward(P, cache, dout)
+    g = -2.0 * (A @ (u / diag)) / rn          # dL/dz
+    g[boundary] = 0.0                         # z is pinned to 0 there
+    gE = g[elem_dofs]                         # dL/dy_E
+    s = gE @ V                                # V^t g_E
+    dV = gE.T @ (w * t) + rE.T @ (w * s)
+    dc = s * t / dbar[:, None]
+    G = backward(P, cache, dc * sigmoid(a))
+    G["V"] = dV
+    return L, G
 
 
 def fcg(A, b, precond, tol=1e-8, maxiter=2000):

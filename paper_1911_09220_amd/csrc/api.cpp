@@ -57,15 +57,17 @@ namespace {
 }  // namespace
 
 namespace pafem {
-// One application of the operator; `work` must hold op_work_bytes(op).
-void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st) {
+// One application of the operator; `work` must hold op_work_bytes(op).  dotp (may be
+// null): pa_apply_blocks partial element energies for launch_cg_alpha.
+void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st, double* dotp,
+              bool y_ready) {
   const Space& s = *op.space;
   const bool constrained = op.flags & PAFEM_OP_CONSTRAINED;
   const bool evec = op.flags & PAFEM_OP_SCATTER_EVEC;
   const int vdt = vector_dtype(op.qdtype);
   if (evec) {
     require(launch_pa_apply(s.dev, op.kind, op.q1d, op.qdtype, constrained, true, op.qdata, x,
-                            work, vdt, st),
+                            work, vdt, st, dotp),
             PAFEM_EUNSUPPORTED, "apply kernel not built for this order/q1d/dtype");
     if (vdt == PAFEM_F64)
       launch_evec_gather(s.dev, static_cast<const double*>(work), static_cast<const double*>(x),
@@ -74,14 +76,17 @@ void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st) 
       launch_evec_gather_f32(s.dev, static_cast<const float*>(work), static_cast<const float*>(x),
                              constrained ? 1 : 0, static_cast<float*>(y), st);
   } else {
-    if (vdt == PAFEM_F64)
+    if (y_ready) {
+      // the caller already set y = x on essential dofs (constrained) and 0 elsewhere
+    } else if (vdt == PAFEM_F64) {
       launch_scatter_init(s.dev, static_cast<const double*>(x), constrained,
                           static_cast<double*>(y), st);
-    else
+    } else {
       launch_scatter_init_f32(s.dev, static_cast<const float*>(x), constrained,
                               static_cast<float*>(y), st);
+    }
     require(launch_pa_apply(s.dev, op.kind, op.q1d, op.qdtype, constrained, false, op.qdata, x,
-                            y, vdt, st),
+                            y, vdt, st, dotp),
             PAFEM_EUNSUPPORTED, "apply kernel not built for this order/q1d/dtype");
   }
 }
@@ -95,7 +100,7 @@ extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 100; }
+int32_t pafem_version(void) { return 200; }
 
 pafem_status pafem_mesh_create_hex(int64_t nv, const double* xyz, int64_t ne, const int64_t* hex8,
                                    int32_t geom_order, const double* geom_nodes,
@@ -358,6 +363,7 @@ pafem_status pafem_pcg_workspace_bytes(pafem_op op, int32_t max_iter, size_t* nb
     const size_t n = size_t(op->op.space->ndofs);
     *nbytes = align256(sizeof(CGState)) + align256(3 * kCGBlocks * sizeof(double)) +
               align256((size_t(max_iter) + 1) * sizeof(double)) + 3 * align256(n * 8) +
+              align256(size_t(pa_apply_blocks(op->op.space->dev)) * sizeof(double)) +
               op_work_bytes(op->op);
   });
 }
@@ -396,9 +402,13 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
     w += align256(n * 8);
     auto* q = reinterpret_cast<double*>(w);
     w += align256(n * 8);
+    const int nap = pa_apply_blocks(s.dev);
+    auto* dotp = reinterpret_cast<double*>(w);
+    w += align256(size_t(nap) * sizeof(double));
     void* opwork = w;
     auto st = static_cast<hipStream_t>(stream);
     const int check = std::max(1, opts->check_every);
+    const uint8_t* ess = (o.flags & PAFEM_OP_CONSTRAINED) ? s.dev.bmask : nullptr;
 
     launch_cg_reset(state, opts->max_iter + 1, st);
     if (!opts->zero_guess) apply_op(o, x, q, opwork, st);
@@ -413,8 +423,8 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
       if (host.done || launched >= opts->max_iter) break;
       const int batch = std::min(check, opts->max_iter - launched);
       for (int k = 0; k < batch; ++k) {
-        apply_op(o, d, q, opwork, st);
-        launch_cg_dot(state, partials, d, q, n, st);
+        apply_op(o, d, q, opwork, st, dotp);
+        launch_cg_alpha(state, partials, dotp, nap, ess, d, n, st);
         launch_cg_update(state, partials, x, r, d, q, dg, hist, n, st);
         launch_cg_direction(state, r, dg, d, n, st);
       }
@@ -461,7 +471,7 @@ pafem_status pafem_convert(int64_t n, const double* src, void* dst, int32_t dtyp
 namespace {
 
 struct IRLayout {
-  size_t state_hi, state_lo, partials, r64, q64, x32, r32, d32, q32, diag32, opwork, total;
+  size_t state_hi, state_lo, partials, r64, q64, dx32, d32, q32, dinv32, dotp, opwork, total;
 };
 
 IRLayout ir_layout(const Op& hi, const Op& lo) {
@@ -470,14 +480,14 @@ IRLayout ir_layout(const Op& hi, const Op& lo) {
   size_t o = 0;
   L.state_hi = o; o += align256(sizeof(CGState));
   L.state_lo = o; o += align256(sizeof(CGState));
-  L.partials = o; o += align256(3 * kCGBlocks * sizeof(double));
+  L.partials = o; o += align256(4 * kCGBlocks * sizeof(double));
   L.r64 = o; o += align256(n * 8);
   L.q64 = o; o += align256(n * 8);
-  L.x32 = o; o += align256(n * 4);
-  L.r32 = o; o += align256(n * 4);
+  L.dx32 = o; o += align256(n * 4);
   L.d32 = o; o += align256(n * 4);
   L.q32 = o; o += align256(n * 4);
-  L.diag32 = o; o += align256(n * 4);
+  L.dinv32 = o; o += align256(n * 4);
+  L.dotp = o; o += align256(size_t(pa_apply_blocks(hi.space->dev)) * sizeof(double));
   L.opwork = o; o += std::max(op_work_bytes(hi), op_work_bytes(lo));
   L.total = o;
   return L;
@@ -528,19 +538,22 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
     auto* partials = reinterpret_cast<double*>(w + L.partials);
     auto* r64 = reinterpret_cast<double*>(w + L.r64);
     auto* q64 = reinterpret_cast<double*>(w + L.q64);
-    auto* x32 = reinterpret_cast<float*>(w + L.x32);
-    auto* r32 = reinterpret_cast<float*>(w + L.r32);
+    auto* dx32 = reinterpret_cast<float*>(w + L.dx32);
     auto* d32 = reinterpret_cast<float*>(w + L.d32);
     auto* q32 = reinterpret_cast<float*>(w + L.q32);
-    auto* diag32 = reinterpret_cast<float*>(w + L.diag32);
+    auto* dinv = opts->precond == PAFEM_PRECOND_JACOBI ? reinterpret_cast<float*>(w + L.dinv32)
+                                                       : nullptr;
     void* opwork = w + L.opwork;
+    auto* dotp = reinterpret_cast<double*>(w + L.dotp);
+    const int nap = pa_apply_blocks(hi.space->dev);
+    const uint8_t* ess = (lo.flags & PAFEM_OP_CONSTRAINED) ? hi.space->dev.bmask : nullptr;
     auto st = static_cast<hipStream_t>(stream);
-    const bool jac = opts->precond == PAFEM_PRECOND_JACOBI;
     const int check = std::max(1, opts->check_every);
-    if (jac) launch_convert(diag, diag32, PAFEM_F32, n, st);
+    if (dinv) launch_ir_dinv(diag, dinv, n, st);
     hip_check(hipMemsetAsync(x, 0, size_t(n) * 8, st), "zero x");
     launch_cg_reset(st_hi, 0, st);
-    // ||b||
+    launch_cg_reset(st_lo, 0, st);
+    // r = b, ||b||
     hip_check(hipMemsetAsync(q64, 0, size_t(n) * 8, st), "zero q");
     launch_residual(st_hi, partials, b, q64, r64, n, st);
     CGState h{};
@@ -548,15 +561,16 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
     hip_check(hipStreamSynchronize(st), "ir sync");
     const double bb = h.res2;
     double rr = bb;
-    int outer = 0, inner_total = 0;
+    int outer = 0, inner_total = 0, inner_seen = 0;
     bool converged = bb == 0.0;
     if (opts->res_hist && opts->res_hist_cap > 0) opts->res_hist[0] = bb > 0 ? 1.0 : 0.0;
+    double s = std::sqrt(rr);
+    bool restart = true;  // the inner PCG (re)starts from d = z on r / s
     while (!converged && outer < opts->max_outer) {
-      const double s = std::sqrt(rr);
-      // inner: reduced-precision Jacobi-PCG on A_lo d = r / ||r||, from d = 0
-      launch_cg_reset(st_lo, 0, st);
-      launch_cg_init<double, float>(st_lo, partials, r64, 1.0 / s, nullptr, jac ? diag32 : nullptr,
-                                    x32, r32, d32, 1, opts->inner_rel_tol, nullptr, n, st);
+      if (restart)
+        launch_ir_start(st_lo, partials, r64, s, dinv, d32, dx32, q32, ess, opts->inner_rel_tol,
+                        n, st);
+      // inner: Jacobi-PCG on A_lo dx = r / ||r|| with the reduced-precision apply
       int launched = 0;
       CGState hl{};
       while (true) {
@@ -566,18 +580,19 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
         if (hl.done || launched >= opts->max_inner) break;
         const int batch = std::min(check, opts->max_inner - launched);
         for (int k = 0; k < batch; ++k) {
-          apply_op(lo, d32, q32, opwork, st);
-          launch_cg_dot<float>(st_lo, partials, d32, q32, n, st);
-          launch_cg_update<float>(st_lo, partials, x32, r32, d32, q32, jac ? diag32 : nullptr,
-                                  nullptr, n, st);
-          launch_cg_direction<float>(st_lo, r32, jac ? diag32 : nullptr, d32, n, st);
+          apply_op(lo, d32, q32, opwork, st, dotp, /*y_ready=*/true);
+          launch_cg_alpha<float>(st_lo, partials, dotp, nap, ess, d32, n, st);
+          launch_ir_update(st_lo, partials, dx32, r64, d32, q32, dinv, n, st);
+          launch_ir_direction(st_lo, r64, dinv, d32, q32, ess, n, st);
         }
         launched += batch;
       }
-      inner_total += hl.iter;
-      launch_ir_correct(x, x32, s, n, st);
+      // the inner iteration counter restarts with the inner PCG and continues otherwise
+      inner_total += hl.iter - (restart ? 0 : inner_seen);
+      inner_seen = hl.iter;
+      launch_ir_correct(x, dx32, s, n, st);
       ++outer;
-      // FP64 residual of the refined iterate
+      // FP64 residual of the refined iterate, into the inner residual's buffer
       apply_op(hi, x, q64, opwork, st);
       launch_residual(st_hi, partials, b, q64, r64, n, st);
       hip_check(hipMemcpyAsync(&h, st_hi, sizeof(CGState), hipMemcpyDeviceToHost, st),
@@ -587,6 +602,15 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
       if (opts->res_hist && outer < opts->res_hist_cap) opts->res_hist[outer] = std::sqrt(rr / bb);
       converged = rr <= opts->rel_tol * opts->rel_tol * bb;
       if (!std::isfinite(rr)) break;
+      if (converged) break;
+      const double s_new = std::sqrt(rr);
+      restart = !(opts->keep_direction && hl.done == 1);
+      if (!restart) {
+        launch_ir_replace(st_lo, partials, r64, s_new, dinv, d32, q32, dx32, opts->inner_rel_tol,
+                          n, st);
+        launch_ir_direction(st_lo, r64, dinv, d32, q32, ess, n, st);
+      }
+      s = s_new;
     }
     result->outer = outer;
     result->inner_total = inner_total;

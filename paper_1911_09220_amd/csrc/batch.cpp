@@ -25,25 +25,21 @@ void hipc(hipError_t err, const char* what) {
 }
 
 // largest right-hand-side chunk first: the default before tuning
-int default_candidate(int p, int nrhs) {
-  const int order_pref[] = {2, 1, 0, 4};
-  for (int c : order_pref) {
-    const int nrb = batch_tile_rhs(c);
-    if (nrhs % nrb) continue;
-    if (c == 2 && p > 4) continue;
-    if (c == 1 && p > 5) continue;
-    return c;
-  }
-  return -1;
-}
-
 bool candidate_ok(int p, int cand, int nrhs) {
   if (cand < 0 || cand >= kBatchCandidates) return false;
   if (nrhs % batch_tile_rhs(cand)) return false;
+  // tiles built per order (k_batch.hip): larger ones would exceed the registers
   if (cand == 1 && p > 5) return false;
-  if (cand == 2 && p > 4) return false;
+  if (cand == 2 && p > 3) return false;
   if (cand == 3 && p > 3) return false;
   return true;
+}
+
+int default_candidate(int p, int nrhs) {
+  const int order_pref[] = {2, 1, 0, 4};
+  for (int c : order_pref)
+    if (candidate_ok(p, c, nrhs)) return c;
+  return -1;
 }
 
 std::string arch_name() {

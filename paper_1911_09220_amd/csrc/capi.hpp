@@ -47,7 +47,9 @@ pafem_status guarded(F&& f) {
 // deterministic scatter; also the diagonal's element vector).
 size_t op_work_bytes(const Op& op);
 // y = A x on the op's stream; `work` holds op_work_bytes(op).
-void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st);
+// y_ready: y already holds the apply init (x on essential dofs when constrained, else 0)
+void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st,
+              double* dotp = nullptr, bool y_ready = false);
 
 }  // namespace pafem
 

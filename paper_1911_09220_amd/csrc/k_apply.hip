@@ -18,6 +18,10 @@
 //   G^t  either: sum the element outputs per unique dof of the tile in LDS, then one
 //        hardware FP atomic per unique dof into y (y pre-set by an init kernel); or
 //        a plain store of the element vector for the deterministic transposed gather.
+// With DOT, each workgroup also writes the sum of its elements' energies
+// u_E . (A_E u_E) (u_E the gathered input, essential entries 0 when constrained) to
+// dotp[blockIdx.x], taken at the quadrature points as the sum of (B G u) . D (B G u):
+// the x.Ax of the CG step without another pass over x and y.
 // All intermediate arrays of an element share one LDS region: every stage writes
 // only entries that the same thread has just read, so a region of 3*Q*Q lines of
 // D values (1*Q*Q for mass) holds them all.
@@ -35,12 +39,13 @@ constexpr int elems_per_block() {
   return qdata_tile(Q);
 }
 
-template <int P, int Q, int KIND, bool EVEC, typename TV, typename TD, typename TC>
+template <int P, int Q, int KIND, bool EVEC, bool DOT, typename TV, typename TD, typename TC>
 __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
     pa_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
                     const uint16_t* __restrict__ tile_slot, const double* __restrict__ tabB,
                     const double* __restrict__ tabG, const TD* __restrict__ qd,
-                    const TV* __restrict__ x, TV* __restrict__ y, int ne, int constrained) {
+                    const TV* __restrict__ x, TV* __restrict__ y, double* __restrict__ dotp,
+                    int ne, int constrained) {
   constexpr int D = P + 1, DD = D * D, QQ = Q * Q, QQQ = Q * Q * Q, DDD = D * D * D;
   constexpr int NE = elems_per_block<Q>();
   constexpr bool DIFF = (KIND == PAFEM_DIFFUSION);
@@ -171,6 +176,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   __syncthreads();
 
   // B along z, D, B^t along z: thread (qy, qx) = r, in registers, written back in place
+  double energy = 0.0;  // sum of u . D u over this thread's points (DOT)
   if (act) {
     const int zy = r / Q, zx = r - (r / Q) * Q;
     TC c0[D], c1[D], c2[D];
@@ -198,6 +204,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
         const TC vx = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
         const TC vy = dq[qz][1] * ux + dq[qz][3] * uy + dq[qz][4] * uz;
         const TC vz = dq[qz][2] * ux + dq[qz][4] * uy + dq[qz][5] * uz;
+        if (DOT) energy += double(ux) * double(vx) + double(uy) * double(vy) + double(uz) * double(vz);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
           t0[dz] += bB(qz, dz) * vx;
@@ -209,6 +216,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) u += bB(qz, dz) * c0[dz];
         const TC v = dq[qz][0] * u;
+        if (DOT) energy += double(u) * double(v);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * v;
       }
@@ -275,6 +283,11 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
         atomicAdd(&sX[slot[dx]], acc);
     }
   }
+  if (DOT) {
+    __shared__ double sDot[(elems_per_block<Q>() * Q * Q + kWave - 1) / kWave];
+    energy = block_sum(energy, sDot);
+    if (tid == 0) dotp[blockIdx.x] = energy;
+  }
   if (EVEC) return;
   __syncthreads();
   // G^t: one global atomic per unique dof of the tile
@@ -285,56 +298,66 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   }
 }
 
-template <int P, int KIND, bool EVEC, typename TV, typename TD, typename TC>
+template <int P, int KIND, bool EVEC, bool DOT, typename TV, typename TD, typename TC>
 void launch_one(const DevSpace& sp, const double* tab, bool constrained, const void* qd,
-                const void* x, void* out, hipStream_t st) {
+                const void* x, void* out, double* dotp, hipStream_t st) {
   constexpr int Q = P + 2;
   constexpr int NE = elems_per_block<Q>();
   const int nblk = int((sp.ne + NE - 1) / NE);
   const double* tabB = tab + 2 * Q;
   const double* tabG = tabB + Q * (P + 1);
-  hipLaunchKernelGGL((pa_apply_kernel<P, Q, KIND, EVEC, TV, TD, TC>), dim3(nblk),
+  hipLaunchKernelGGL((pa_apply_kernel<P, Q, KIND, EVEC, DOT, TV, TD, TC>), dim3(nblk),
                      dim3(NE * Q * Q), 0, st, sp.tile_off, sp.tile_dofs, sp.tile_slot, tabB, tabG,
                      static_cast<const TD*>(qd), static_cast<const TV*>(x),
-                     static_cast<TV*>(out), int(sp.ne), int(constrained));
+                     static_cast<TV*>(out), dotp, int(sp.ne), int(constrained));
 }
 
 template <int P, int KIND, typename TV, typename TD, typename TC>
 void launch_mode(const DevSpace& sp, const double* tab, bool constrained, bool evec,
-                 const void* qd, const void* x, void* out, hipStream_t st) {
-  if (evec)
-    launch_one<P, KIND, true, TV, TD, TC>(sp, tab, constrained, qd, x, out, st);
-  else
-    launch_one<P, KIND, false, TV, TD, TC>(sp, tab, constrained, qd, x, out, st);
+                 const void* qd, const void* x, void* out, double* dotp, hipStream_t st) {
+  if (evec) {
+    if (dotp)
+      launch_one<P, KIND, true, true, TV, TD, TC>(sp, tab, constrained, qd, x, out, dotp, st);
+    else
+      launch_one<P, KIND, true, false, TV, TD, TC>(sp, tab, constrained, qd, x, out, dotp, st);
+  } else {
+    if (dotp)
+      launch_one<P, KIND, false, true, TV, TD, TC>(sp, tab, constrained, qd, x, out, dotp, st);
+    else
+      launch_one<P, KIND, false, false, TV, TD, TC>(sp, tab, constrained, qd, x, out, dotp, st);
+  }
 }
 
 template <int P>
 bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, const double* tab,
                   bool constrained, bool evec, const void* qd, const void* x, void* out,
-                  hipStream_t st) {
+                  double* dotp, hipStream_t st) {
+  const bool diff = kind == PAFEM_DIFFUSION;
   if (vdtype == PAFEM_F64 && qdtype == PAFEM_F64) {
-    if (kind == PAFEM_DIFFUSION)
+    if (diff)
       launch_mode<P, PAFEM_DIFFUSION, double, double, double>(sp, tab, constrained, evec, qd, x,
-                                                              out, st);
+                                                              out, dotp, st);
     else
       launch_mode<P, PAFEM_MASS, double, double, double>(sp, tab, constrained, evec, qd, x, out,
-                                                         st);
+                                                         dotp, st);
     return true;
   }
   if (vdtype == PAFEM_F32 && qdtype == PAFEM_F32) {
-    if (kind == PAFEM_DIFFUSION)
+    if (diff)
       launch_mode<P, PAFEM_DIFFUSION, float, float, float>(sp, tab, constrained, evec, qd, x, out,
-                                                           st);
+                                                           dotp, st);
     else
-      launch_mode<P, PAFEM_MASS, float, float, float>(sp, tab, constrained, evec, qd, x, out, st);
+      launch_mode<P, PAFEM_MASS, float, float, float>(sp, tab, constrained, evec, qd, x, out,
+                                                      dotp, st);
     return true;
   }
   if (vdtype == PAFEM_F32 && qdtype == PAFEM_BF16) {
-    if (kind == PAFEM_DIFFUSION)
+    if (diff)
       launch_mode<P, PAFEM_DIFFUSION, float, bf16, float>(sp, tab, constrained, evec, qd, x, out,
-                                                          st);
+                                                          dotp, st);
     else
-      launch_mode<P, PAFEM_MASS, float, bf16, float>(sp, tab, constrained, evec, qd, x, out, st);
+      launch_mode<P, PAFEM_MASS, float, bf16, float>(sp, tab, constrained, evec, qd, x, out, dotp,
+                                                     st);
     return true;
   }
   return false;
@@ -342,23 +365,33 @@ bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, const do
 
 }  // namespace
 
+int pa_apply_blocks(const DevSpace& sp) {
+  return int((sp.ne + qdata_tile(sp.p + 2) - 1) / qdata_tile(sp.p + 2));
+}
+
 bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool constrained,
                      bool evec, const void* qd, const void* x, void* out, int vdtype,
-                     hipStream_t st) {
+                     hipStream_t st, double* dotp) {
   if (q1d != sp.p + 2) return false;
   const double* tab = sp.tables + table_offset_doubles(q1d, sp.p + 1, sp.ng);
   bool ok = false;
+#define PAFEM_ORDER_CASE(P_)                                                                   \
+  case P_:                                                                                     \
+    ok = launch_order<P_>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, dotp, \
+                          st);                                                                 \
+    break;
   switch (sp.p) {
-    case 1: ok = launch_order<1>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, st); break;
-    case 2: ok = launch_order<2>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, st); break;
-    case 3: ok = launch_order<3>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, st); break;
-    case 4: ok = launch_order<4>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, st); break;
-    case 5: ok = launch_order<5>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, st); break;
-    case 6: ok = launch_order<6>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, st); break;
-    case 7: ok = launch_order<7>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, st); break;
-    case 8: ok = launch_order<8>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, st); break;
+    PAFEM_ORDER_CASE(1)
+    PAFEM_ORDER_CASE(2)
+    PAFEM_ORDER_CASE(3)
+    PAFEM_ORDER_CASE(4)
+    PAFEM_ORDER_CASE(5)
+    PAFEM_ORDER_CASE(6)
+    PAFEM_ORDER_CASE(7)
+    PAFEM_ORDER_CASE(8)
     default: ok = false;
   }
+#undef PAFEM_ORDER_CASE
   if (ok) {
     hipError_t err = hipGetLastError();
     if (err != hipSuccess)

@@ -3,13 +3,14 @@
 // Each mesh m holds nrhs vectors stored right-hand-side fastest, X_m[dof][rhs],
 // so the gather of one dof reads one contiguous run of nrhs values.  The
 // partial-assembly stages are those of the single-vector kernel (G, B, D, B^t,
-// G^t; "Operator Decomposition"), applied to NRB right-hand sides at once: the
-// tile of a workgroup is NE elements x NRB right-hand sides, the rhs index is
-// the fastest thread index (coalesced X loads, broadcast D loads, conflict-free
-// LDS), and the quadrature data D of an element is loaded once into registers
-// and reused for every right-hand side.  The workgroup loops over the nrhs/NRB
-// chunks.  All meshes of one order share one grouped launch: a workgroup finds
-// its mesh from a prefix table of tile counts.
+// G^t; "Operator Decomposition"), one 1D line per thread, applied to NRB
+// right-hand sides at once: the tile of a workgroup is NE elements x Q*Q lines x
+// NRB right-hand sides with the rhs index fastest (coalesced X loads and Y
+// atomics, broadcast D loads, conflict-free LDS).  Table entries are the same for
+// every lane and come from scalar loads; the quadrature data D of a z-line is
+// loaded once into registers and reused for every right-hand side.  The
+// workgroup loops over the nrhs/NRB chunks.  All meshes of one order share one
+// grouped launch: a workgroup finds its mesh from a prefix table of tile counts.
 #include "batch.hpp"
 #include "device.hpp"
 
@@ -22,17 +23,14 @@ __global__ void __launch_bounds__(NE * Q * Q * NRB)
     pa_apply_mrhs_kernel(const BatchMesh* __restrict__ meshes, int nmesh,
                          const double* __restrict__ tabB, const double* __restrict__ tabG,
                          int nrhs) {
-  constexpr int D = P + 1, QQ = Q * Q, DDD = D * D * D;
+  constexpr int D = P + 1, DD = D * D, QQ = Q * Q;
   constexpr bool DIFF = (KIND == PAFEM_DIFFUSION);
   constexpr int NC = DIFF ? 6 : 1;
-  constexpr int NA = DIFF ? 2 : 1;
   constexpr int NCC = DIFF ? 3 : 1;
+  constexpr int ELEM = NCC * QQ * D;  // entries of one element region (per rhs)
+  static_assert((DIFF ? 2 : 1) * D <= NCC * Q, "x-line outputs must fit the element region");
 
-  __shared__ TC sB[Q][D];
-  __shared__ TC sG[Q][D];
-  __shared__ TC sU[NE][D][D][D][NRB];
-  __shared__ TC sA[NE][NA][D][D][Q][NRB];
-  __shared__ TC sC[NE][NCC][D][Q][Q][NRB];
+  __shared__ TC sW[NE * ELEM * NRB];
 
   // which mesh and which tile of it
   int m = 0;
@@ -43,18 +41,22 @@ __global__ void __launch_bounds__(NE * Q * Q * NRB)
 
   const int tid = threadIdx.x;
   const int rb = tid % NRB;
-  const int pl = tid / NRB;  // plane thread: (el, qy, qx)
+  const int pl = tid / NRB;  // line thread: (el, r)
   const int el = pl / QQ;
   const int r = pl - el * QQ;
-  const int qx = r % Q, qy = r / Q;
   const int e = tile * NE + el;
   const bool act = e < M.ne;
   const int constrained = M.constrained;
+  TC* const W = sW + el * ELEM * NRB + rb;
+  // entry (c, qy, qx, dz) of this element and rhs; the x-line outputs (a, dz, dy, qx)
+  // live at c*Q + qy = a*D + dy
+  auto at = [&](int c, int qy, int qx, int dz) -> TC& {
+    return W[(((c * Q + qy) * Q + qx) * D + dz) * NRB];
+  };
+  auto bB = [&](int q, int d) -> TC { return TC(tabB[q * D + d]); };
+  auto bG = [&](int q, int d) -> TC { return TC(tabG[q * D + d]); };
 
-  for (int i = tid; i < Q * D; i += NE * QQ * NRB) {
-    (&sB[0][0])[i] = TC(tabB[i]);
-    if (DIFF) (&sG[0][0])[i] = TC(tabG[i]);
-  }
+  // D of this thread's z-line (qy, qx) = r, reused for every chunk of right-hand sides
   TC dq[Q][NC];
   if (act) {
     const TD* qd = static_cast<const TD*>(M.qdata);
@@ -64,140 +66,170 @@ __global__ void __launch_bounds__(NE * Q * Q * NRB)
       for (int c = 0; c < NC; ++c)
         dq[qz][c] = load_value<TC, TD>(qd + qdata_index(e, c, qz * QQ + r, Q, NC));
   }
-  int gidx[D];
-  const bool dof_thread = act && qx < D && qy < D;
-  if (dof_thread) {
-    const int32_t* ge = M.gmap + size_t(e) * DDD + qy * D + qx;
-#pragma unroll
-    for (int dz = 0; dz < D; ++dz) gidx[dz] = ge[dz * D * D];
-  }
+  // x-line (dz, dy) = r < D*D: the dofs of its D nodes (re-read where used: cached)
+  const bool xline = act && r < DD;
+  const int xz = r / D, xy = r - (r / D) * D;
+  const int32_t* __restrict__ gline = M.gmap + size_t(e) * (DD * D) + r * D;
+  const bool yline = act && r < D * Q;
+  const int yz = r / Q, yx = r - (r / Q) * Q;
+  const int zy = r / Q, zx = r - (r / Q) * Q;
   const TV* __restrict__ X = static_cast<const TV*>(M.x);
   TV* __restrict__ Y = static_cast<TV*>(M.y);
 
   for (int r0 = 0; r0 < nrhs; r0 += NRB) {
     const int rr = r0 + rb;
-    // G: gather NRB right-hand sides of every element node
-    if (dof_thread) {
+    // G and B along x: thread (dz, dy)
+    if (xline) {
+      TC u[D];
 #pragma unroll
-      for (int dz = 0; dz < D; ++dz) {
-        const int g = gidx[dz];
-        TC v = TC(0);
-        if (!(constrained && g < 0)) v = TC(X[size_t(g < 0 ? ~g : g) * nrhs + rr]);
-        sU[el][dz][qy][qx][rb] = v;
+      for (int dx = 0; dx < D; ++dx) {
+        const int g = gline[dx];
+        u[dx] = (constrained && g < 0) ? TC(0) : TC(X[size_t(g < 0 ? ~g : g) * nrhs + rr]);
       }
-    }
-    __syncthreads();
-    if (qy < D) {
 #pragma unroll
-      for (int dz = 0; dz < D; ++dz) {
+      for (int qx = 0; qx < Q; ++qx) {
         TC b = TC(0), g = TC(0);
 #pragma unroll
         for (int dx = 0; dx < D; ++dx) {
-          const TC u = sU[el][dz][qy][dx][rb];
-          b += sB[qx][dx] * u;
-          if (DIFF) g += sG[qx][dx] * u;
+          b += bB(qx, dx) * u[dx];
+          if (DIFF) g += bG(qx, dx) * u[dx];
         }
-        sA[el][0][dz][qy][qx][rb] = b;
-        if (DIFF) sA[el][NA - 1][dz][qy][qx][rb] = g;
+        at(xy / Q, xy % Q, qx, xz) = b;
+        if (DIFF) at((D + xy) / Q, (D + xy) % Q, qx, xz) = g;
       }
     }
     __syncthreads();
-    TC BB[D], GB[D], BG[D];
-#pragma unroll
-    for (int dz = 0; dz < D; ++dz) {
-      TC bb = TC(0), gb = TC(0), bg = TC(0);
+    // B along y: thread (dz, qx)
+    if (yline) {
+      TC aB[D], aG[D];
 #pragma unroll
       for (int dy = 0; dy < D; ++dy) {
-        const TC a0 = sA[el][0][dz][dy][qx][rb];
-        const TC by = sB[qy][dy];
-        bb += by * a0;
-        if (DIFF) {
-          gb += by * sA[el][NA - 1][dz][dy][qx][rb];
-          bg += sG[qy][dy] * a0;
-        }
+        aB[dy] = at(dy / Q, dy % Q, yx, yz);
+        if (DIFF) aG[dy] = at((D + dy) / Q, (D + dy) % Q, yx, yz);
       }
-      BB[dz] = bb;
-      GB[dz] = gb;
-      BG[dz] = bg;
-    }
-    TC tBB[D], tGB[D], tBG[D];
 #pragma unroll
-    for (int dz = 0; dz < D; ++dz) tBB[dz] = tGB[dz] = tBG[dz] = TC(0);
+      for (int qy = 0; qy < Q; ++qy) {
+        TC gb = TC(0), bg = TC(0), bb = TC(0);
 #pragma unroll
-    for (int qz = 0; qz < Q; ++qz) {
-      if (DIFF) {
-        TC ux = TC(0), uy = TC(0), uz = TC(0);
-#pragma unroll
-        for (int dz = 0; dz < D; ++dz) {
-          const TC bz = sB[qz][dz], gz = sG[qz][dz];
-          ux += bz * GB[dz];
-          uy += bz * BG[dz];
-          uz += gz * BB[dz];
-        }
-        const TC vx = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
-        const TC vy = dq[qz][1] * ux + dq[qz][3] * uy + dq[qz][4] * uz;
-        const TC vz = dq[qz][2] * ux + dq[qz][4] * uy + dq[qz][5] * uz;
-#pragma unroll
-        for (int dz = 0; dz < D; ++dz) {
-          const TC bz = sB[qz][dz], gz = sG[qz][dz];
-          tGB[dz] += bz * vx;
-          tBG[dz] += bz * vy;
-          tBB[dz] += gz * vz;
-        }
-      } else {
-        TC u = TC(0);
-#pragma unroll
-        for (int dz = 0; dz < D; ++dz) u += sB[qz][dz] * BB[dz];
-        const TC v = dq[qz][0] * u;
-#pragma unroll
-        for (int dz = 0; dz < D; ++dz) tBB[dz] += sB[qz][dz] * v;
-      }
-    }
-#pragma unroll
-    for (int dz = 0; dz < D; ++dz) {
-      if (DIFF) {
-        sC[el][0][dz][qy][qx][rb] = tGB[dz];
-        sC[el][1][dz][qy][qx][rb] = tBG[dz];
-        sC[el][2][dz][qy][qx][rb] = tBB[dz];
-      } else {
-        sC[el][0][dz][qy][qx][rb] = tBB[dz];
-      }
-    }
-    __syncthreads();
-    if (qy < D) {
-#pragma unroll
-      for (int dz = 0; dz < D; ++dz) {
-        TC bx = TC(0), gx = TC(0);
-#pragma unroll
-        for (int q2 = 0; q2 < Q; ++q2) {
-          const TC by = sB[q2][qy];
+        for (int dy = 0; dy < D; ++dy) {
+          bb += bB(qy, dy) * aB[dy];
           if (DIFF) {
-            gx += by * sC[el][0][dz][q2][qx][rb];
-            bx += sG[q2][qy] * sC[el][1][dz][q2][qx][rb] + by * sC[el][2][dz][q2][qx][rb];
-          } else {
-            bx += by * sC[el][0][dz][q2][qx][rb];
+            gb += bB(qy, dy) * aG[dy];
+            bg += bG(qy, dy) * aB[dy];
           }
         }
-        sA[el][0][dz][qy][qx][rb] = bx;
-        if (DIFF) sA[el][NA - 1][dz][qy][qx][rb] = gx;
+        if (DIFF) {
+          at(0, qy, yx, yz) = gb;
+          at(1, qy, yx, yz) = bg;
+          at(2, qy, yx, yz) = bb;
+        } else {
+          at(0, qy, yx, yz) = bb;
+        }
       }
     }
     __syncthreads();
-    if (dof_thread) {
+    // B along z, D, B^t along z: thread (qy, qx), in place
+    if (act) {
+      TC c0[D], c1[D], c2[D];
 #pragma unroll
       for (int dz = 0; dz < D; ++dz) {
+        c0[dz] = at(0, zy, zx, dz);
+        if (DIFF) {
+          c1[dz] = at(1, zy, zx, dz);
+          c2[dz] = at(2, zy, zx, dz);
+        }
+      }
+      TC t0[D], t1[D], t2[D];
+#pragma unroll
+      for (int dz = 0; dz < D; ++dz) t0[dz] = t1[dz] = t2[dz] = TC(0);
+#pragma unroll
+      for (int qz = 0; qz < Q; ++qz) {
+        if (DIFF) {
+          TC ux = TC(0), uy = TC(0), uz = TC(0);
+#pragma unroll
+          for (int dz = 0; dz < D; ++dz) {
+            ux += bB(qz, dz) * c0[dz];
+            uy += bB(qz, dz) * c1[dz];
+            uz += bG(qz, dz) * c2[dz];
+          }
+          const TC vx = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
+          const TC vy = dq[qz][1] * ux + dq[qz][3] * uy + dq[qz][4] * uz;
+          const TC vz = dq[qz][2] * ux + dq[qz][4] * uy + dq[qz][5] * uz;
+#pragma unroll
+          for (int dz = 0; dz < D; ++dz) {
+            t0[dz] += bB(qz, dz) * vx;
+            t1[dz] += bB(qz, dz) * vy;
+            t2[dz] += bG(qz, dz) * vz;
+          }
+        } else {
+          TC u = TC(0);
+#pragma unroll
+          for (int dz = 0; dz < D; ++dz) u += bB(qz, dz) * c0[dz];
+          const TC v = dq[qz][0] * u;
+#pragma unroll
+          for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * v;
+        }
+      }
+#pragma unroll
+      for (int dz = 0; dz < D; ++dz) {
+        at(0, zy, zx, dz) = t0[dz];
+        if (DIFF) {
+          at(1, zy, zx, dz) = t1[dz];
+          at(2, zy, zx, dz) = t2[dz];
+        }
+      }
+    }
+    __syncthreads();
+    // B^t along y: thread (dz, qx)
+    if (yline) {
+      TC v0[Q], v1[Q], v2[Q];
+#pragma unroll
+      for (int qy = 0; qy < Q; ++qy) {
+        v0[qy] = at(0, qy, yx, yz);
+        if (DIFF) {
+          v1[qy] = at(1, qy, yx, yz);
+          v2[qy] = at(2, qy, yx, yz);
+        }
+      }
+#pragma unroll
+      for (int dy = 0; dy < D; ++dy) {
+        TC b = TC(0), g = TC(0);
+#pragma unroll
+        for (int qy = 0; qy < Q; ++qy) {
+          if (DIFF) {
+            g += bB(qy, dy) * v0[qy];
+            b += bG(qy, dy) * v1[qy] + bB(qy, dy) * v2[qy];
+          } else {
+            b += bB(qy, dy) * v0[qy];
+          }
+        }
+        at(dy / Q, dy % Q, yx, yz) = b;
+        if (DIFF) at((D + dy) / Q, (D + dy) % Q, yx, yz) = g;
+      }
+    }
+    __syncthreads();
+    // B^t along x and G^t: thread (dz, dy)
+    if (xline) {
+      TC wB[Q], wG[Q];
+#pragma unroll
+      for (int qx = 0; qx < Q; ++qx) {
+        wB[qx] = at(xy / Q, xy % Q, qx, xz);
+        if (DIFF) wG[qx] = at((D + xy) / Q, (D + xy) % Q, qx, xz);
+      }
+#pragma unroll
+      for (int dx = 0; dx < D; ++dx) {
         TC acc = TC(0);
 #pragma unroll
-        for (int q1 = 0; q1 < Q; ++q1) {
-          acc += sB[q1][qx] * sA[el][0][dz][qy][q1][rb];
-          if (DIFF) acc += sG[q1][qx] * sA[el][NA - 1][dz][qy][q1][rb];
+        for (int qx = 0; qx < Q; ++qx) {
+          acc += bB(qx, dx) * wB[qx];
+          if (DIFF) acc += bG(qx, dx) * wG[qx];
         }
-        const int g = gidx[dz];
+        const int g = gline[dx];
         if (!(constrained && g < 0))
           unsafeAtomicAdd(&Y[size_t(g < 0 ? ~g : g) * nrhs + rr], TV(acc));
       }
     }
-    // the next chunk overwrites sU only after every thread finished this one
+    // the next chunk overwrites the element regions only after every thread is done
     __syncthreads();
   }
 }
@@ -248,7 +280,7 @@ bool launch_tile(int cand, const BatchMesh* meshes, int nmesh, int nblocks, int 
       return true;
     }
   }
-  if constexpr (P <= 4) {
+  if constexpr (P <= 3) {
     if (cand == 2) {
       launch_cfg<P, 1, 16, TV, TD, TC>(meshes, nmesh, nblocks, kind, tabB, tabG, nrhs, st);
       return true;

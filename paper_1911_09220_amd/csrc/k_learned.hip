@@ -1,8 +1,20 @@
-// Element-patch kernels of the learned preconditioner
-//     z = r / diag + G^t( w * (s_E / kbar_E) * N([r_E / s_E, f_E]) ),
-// with s_E = ||r_E||, kbar_E the element mean of the coefficient, f_E the 8
-// octant log-ratios of the coefficient, w = 1 / (number of element nodes that
-// share the dof).  The network N runs on matrix cores (k_mlp.hip).
+// Element kernels of the learned preconditioner
+//     z = r / diag + sum_E R_E^t V diag(c_E / dbar_E) V^t R_E r,   z = 0 on essential dofs,
+// with c_E = softplus(N(f_E)) from the element network N (k_mlp.hip) on the 8 octant
+// log-ratios f_E of the coefficient, V a learned (p+1)^3 x K basis shared by all
+// elements, and dbar_E the mean of diag over the element's non-essential nodes.
+// The correction is positive semidefinite for any network and basis, so z(r) is
+// an SPD preconditioner; the division by dbar_E makes it invariant to the
+// coefficient scale and the element size.
+//
+// The per-iteration part (lowrank_apply) works on the apply tiles: the tile's
+// unique dofs are gathered once into LDS, each element contracts with V^t and V
+// in FP32, the outputs are summed per unique dof in LDS and added with one atomic
+// per unique dof.  The network runs once per operator (lowrank_coeffs).
+#include <math.h>
+
+#include <algorithm>
+
 #include "device.hpp"
 #include "mlp.hpp"
 
@@ -47,87 +59,197 @@ __global__ void patch_features_kernel(const int32_t* __restrict__ orig, const do
   }
 }
 
-// one wave per element: lane i < D^3 owns node i
-__global__ void patch_inputs_kernel(const int32_t* __restrict__ gmap, const double* __restrict__ r,
-                                    const float* __restrict__ feats, int dpe, int in_pad,
-                                    uint16_t* __restrict__ X, float* __restrict__ s, int64_t ne) {
+// X[e] = bf16([f_E (8 log-ratios), 0 ...]), in_pad columns
+__global__ void net_inputs_kernel(const float* __restrict__ feats, int in_pad,
+                                  uint16_t* __restrict__ X, int64_t ne) {
+  const int64_t n = ne * in_pad;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = i / in_pad;
+    const int j = int(i - e * in_pad);
+    X[i] = f2bf(j < 8 ? feats[e * kFeat + 1 + j] : 0.f);
+  }
+}
+
+// One wave per element: c[e][k] = softplus(a[e][k]) and idb[e] = 1 / dbar_E.
+__global__ void lowrank_coeffs_kernel(const int32_t* __restrict__ gmap, const double* __restrict__ diag,
+                                      int dpe, const float* __restrict__ a, int K,
+                                      float* __restrict__ c, float* __restrict__ idb, int64_t ne) {
   const int lane = threadIdx.x % kWave;
   const int64_t e = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) / kWave;
   if (e >= ne) return;
   const int32_t* g = gmap + e * dpe;
-  double ss = 0.0;
+  double sum = 0.0, cnt = 0.0;
   for (int i = lane; i < dpe; i += kWave) {
     const int d = g[i];
-    const double v = r[d < 0 ? ~d : d];
-    ss += v * v;
-  }
-  ss = wave_sum(ss);
-  const double sc = sqrt(ss) + 1e-300;
-  if (lane == 0) s[e] = float(sc);
-  uint16_t* x = X + e * in_pad;
-  for (int i = lane; i < in_pad; i += kWave) {
-    float v = 0.f;
-    if (i < dpe) {
-      const int d = g[i];
-      v = float(r[d < 0 ? ~d : d] / sc);
-    } else if (i < dpe + 8) {
-      v = feats[e * kFeat + 1 + (i - dpe)];
+    if (d >= 0) {
+      sum += diag[d];
+      cnt += 1.0;
     }
-    x[i] = f2bf(v);
+  }
+  sum = wave_sum(sum);
+  cnt = wave_sum(cnt);
+  if (lane == 0) idb[e] = cnt > 0.0 ? float(cnt / sum) : 1.f;
+  for (int k = lane; k < K; k += kWave) {
+    const float x = a[e * K + k];
+    c[e * K + k] = x > 20.f ? x : log1pf(expf(x));
   }
 }
 
-__global__ void patch_outputs_kernel(const float* __restrict__ out, int out_pad, int dpe,
-                                     const float* __restrict__ s, const float* __restrict__ feats,
-                                     double* __restrict__ ye, int64_t ne) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < ne * dpe;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t e = i / dpe;
-    const int k = int(i - e * dpe);
-    ye[i] = double(s[e]) / double(feats[e * kFeat]) * double(out[e * out_pad + k]);
+template <int P, int K>
+struct LowRankShape {
+  static constexpr int D = P + 1, DDD = D * D * D;
+  static constexpr int NE = qdata_tile(P + 2);  // elements per apply tile
+  static constexpr int VK = DDD * K;
+};
+
+// z += sum_E R_E^t V diag(c_E idb_E) V^t R_E r over the non-essential dofs (z holds
+// the Jacobi part on entry).  One workgroup per apply tile.
+template <int P, int K>
+__global__ void __launch_bounds__(256)
+    lowrank_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
+                         const uint16_t* __restrict__ tile_slot, const float* __restrict__ V,
+                         const float* __restrict__ c, const float* __restrict__ idb,
+                         const double* __restrict__ r, double* __restrict__ z, int ne) {
+  using S = LowRankShape<P, K>;
+  constexpr int DDD = S::DDD, NE = S::NE;
+  __shared__ float sV[DDD * K];    // [i][k]
+  __shared__ float sVt[K * DDD];   // [k][i]
+  __shared__ float sU[NE * DDD];   // the tile's unique dofs: r, later the summed outputs
+  __shared__ float sRE[NE * DDD];  // element node values
+  __shared__ float sT[NE * K];
+  __shared__ uint16_t sSlot[NE * DDD];
+  const int tid = threadIdx.x;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int e0 = tile * NE;
+  const int nel = min(NE, ne - e0);
+  const int u0 = tile_off[tile];
+  const int nu = tile_off[tile + 1] - u0;
+  for (int j = tid; j < DDD * K; j += 256) {
+    const float v = V[j];
+    sV[j] = v;
+    sVt[(j % K) * DDD + j / K] = v;
+  }
+  for (int s = tid; s < nu; s += 256) {
+    const int g = tile_dofs[u0 + s];
+    sU[s] = g < 0 ? 0.f : float(r[g]);
+  }
+  for (int j = tid; j < nel * DDD; j += 256) sSlot[j] = tile_slot[size_t(e0) * DDD + j];
+  __syncthreads();
+  for (int j = tid; j < nel * DDD; j += 256) sRE[j] = sU[sSlot[j]];
+  __syncthreads();
+  for (int s = tid; s < nu; s += 256) sU[s] = 0.f;
+  // t = V^t r_E, scaled by c_E / dbar_E
+  for (int j = tid; j < nel * K; j += 256) {
+    const int el = j / K, k = j - el * K;
+    const float* re = sRE + el * DDD;
+    float acc = 0.f;
+#pragma unroll 8
+    for (int i = 0; i < DDD; ++i) acc += sV[i * K + k] * re[i];
+    sT[j] = acc * c[size_t(e0 + el) * K + k] * idb[e0 + el];
+  }
+  __syncthreads();
+  // y_E = V t, summed per unique dof
+  for (int j = tid; j < nel * DDD; j += 256) {
+    const int el = j / DDD, i = j - el * DDD;
+    const float* t = sT + el * K;
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc += sVt[k * DDD + i] * t[k];
+    atomicAdd(&sU[sSlot[j]], acc);
+  }
+  __syncthreads();
+  for (int s = tid; s < nu; s += 256) {
+    const int g = tile_dofs[u0 + s];
+    if (g >= 0) unsafeAtomicAdd(&z[g], double(sU[s]));
   }
 }
 
-__global__ void precond_gather_kernel(const int32_t* __restrict__ toff,
-                                      const int32_t* __restrict__ tidx,
-                                      const uint8_t* __restrict__ bmask,
-                                      const double* __restrict__ ye, const double* __restrict__ r,
-                                      const double* __restrict__ diag, double* __restrict__ z,
-                                      int64_t n) {
-  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n;
-       g += int64_t(gridDim.x) * blockDim.x) {
-    if (bmask[g]) {
-      z[g] = 0.0;
-      continue;
+// Backward of the low-rank term for dL/dz = gscale * g (essential entries are read
+// as 0):
+//   s_E = V^t R_E g,  t_E = V^t R_E r,
+//   dout[e][k] = s_k t_k idb_E sigmoid(a_k)   (bf16, the network's output gradient;
+//                                              sigmoid(a) = 1 - exp(-softplus(a)))
+//   dV = sum_E R_E g (c idb t)^t + R_E r (c idb s)^t,
+// the sum over elements taken in a fixed order: each workgroup walks tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ... and each thread owns fixed entries of
+// dV; part[blockIdx.x] receives the workgroup's partial sum.
+template <int P, int K>
+__global__ void __launch_bounds__(256)
+    lowrank_grad_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
+                        const uint16_t* __restrict__ tile_slot, const float* __restrict__ V,
+                        const float* __restrict__ c, const float* __restrict__ idb,
+                        const double* __restrict__ r, const double* __restrict__ g,
+                        const double* __restrict__ gscale, uint16_t* __restrict__ dout,
+                        float* __restrict__ part, int ne, int ntiles) {
+  using S = LowRankShape<P, K>;
+  constexpr int DDD = S::DDD, NE = S::NE, VK = S::VK;
+  constexpr int OWN = (VK + 255) / 256;
+  __shared__ float sV[DDD * K];
+  __shared__ float sUr[NE * DDD];
+  __shared__ float sUg[NE * DDD];
+  __shared__ float sRE[NE * DDD];
+  __shared__ float sGE[NE * DDD];
+  __shared__ float sA[NE * K];
+  __shared__ float sB[NE * K];
+  const int tid = threadIdx.x;
+  const float gs = float(*gscale);
+  for (int j = tid; j < VK; j += 256) sV[j] = V[j];
+  float acc[OWN];
+#pragma unroll
+  for (int m = 0; m < OWN; ++m) acc[m] = 0.f;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int e0 = tile * NE;
+    const int nel = min(NE, ne - e0);
+    const int u0 = tile_off[tile];
+    const int nu = tile_off[tile + 1] - u0;
+    __syncthreads();  // the previous tile's readers are done
+    for (int s = tid; s < nu; s += 256) {
+      const int d = tile_dofs[u0 + s];
+      sUr[s] = d < 0 ? 0.f : float(r[d]);
+      sUg[s] = d < 0 ? 0.f : float(g[d]) * gs;
     }
-    const int32_t k0 = toff[g], k1 = toff[g + 1];
-    double acc = 0.0;
-    for (int32_t k = k0; k < k1; ++k) acc += ye[tidx[k]];
-    z[g] = r[g] / diag[g] + acc / double(k1 - k0);
-  }
-}
-
-__global__ void patch_output_grad_kernel(const int32_t* __restrict__ gmap,
-                                         const int32_t* __restrict__ toff,
-                                         const double* __restrict__ gz,
-                                         const double* __restrict__ gscale,
-                                         const float* __restrict__ s,
-                                         const float* __restrict__ feats, int dpe, int out_pad,
-                                         uint16_t* __restrict__ dout, int64_t ne) {
-  const double c = gscale ? gscale[0] : 1.0;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < ne * out_pad;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t e = i / out_pad;
-    const int k = int(i - e * out_pad);
-    float v = 0.f;
-    if (k < dpe) {
-      const int d = gmap[e * dpe + k];
-      if (d >= 0) {  // essential dofs carry no correction
-        const double m = double(toff[d + 1] - toff[d]);
-        v = float(c * double(s[e]) / double(feats[e * kFeat]) * gz[d] / m);
+    __syncthreads();
+    for (int j = tid; j < nel * DDD; j += 256) {
+      const int sl = tile_slot[size_t(e0) * DDD + j];
+      sRE[j] = sUr[sl];
+      sGE[j] = sUg[sl];
+    }
+    __syncthreads();
+    for (int j = tid; j < nel * K; j += 256) {
+      const int el = j / K, k = j - el * K;
+      const float* re = sRE + el * DDD;
+      const float* ge = sGE + el * DDD;
+      float t = 0.f, s = 0.f;
+#pragma unroll 8
+      for (int i = 0; i < DDD; ++i) {
+        const float v = sV[i * K + k];
+        t += v * re[i];
+        s += v * ge[i];
+      }
+      const size_t ek = size_t(e0 + el) * K + k;
+      const float ce = c[ek], ib = idb[e0 + el];
+      dout[ek] = f2bf(s * t * ib * (-expm1f(-ce)));
+      sA[j] = ce * ib * t;
+      sB[j] = ce * ib * s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < OWN; ++m) {
+      const int j = tid + 256 * m;
+      if (j < VK) {
+        const int i = j / K, k = j - i * K;
+        float a = acc[m];
+        for (int el = 0; el < nel; ++el)
+          a += sGE[el * DDD + i] * sA[el * K + k] + sRE[el * DDD + i] * sB[el * K + k];
+        acc[m] = a;
       }
     }
-    dout[i] = f2bf(v);
+  }
+#pragma unroll
+  for (int m = 0; m < OWN; ++m) {
+    const int j = tid + 256 * m;
+    if (j < VK) part[size_t(blockIdx.x) * VK + j] = acc[m];
   }
 }
 
@@ -189,6 +311,29 @@ void check(const char* what) {
   if (err != hipSuccess) throw Error(PAFEM_EHIP, std::string(what) + ": " + hipGetErrorString(err));
 }
 
+int ntiles_of(const DevSpace& sp) { return int((sp.ne + sp.tile_ne - 1) / sp.tile_ne); }
+
+template <int P>
+void lowrank_apply_p(const DevSpace& sp, const float* V, const float* c, const float* idb,
+                     const double* r, double* z, hipStream_t st) {
+  if (sp.tile_ne != LowRankShape<P, kLowRank>::NE)
+    throw Error(PAFEM_EINVAL, "low-rank apply: tile size differs from the apply tiles");
+  hipLaunchKernelGGL((lowrank_apply_kernel<P, kLowRank>), dim3(ntiles_of(sp)), dim3(256), 0, st,
+                     sp.tile_off, sp.tile_dofs, sp.tile_slot, V, c, idb, r, z, int(sp.ne));
+}
+
+template <int P>
+void lowrank_grad_p(const DevSpace& sp, const float* V, const float* c, const float* idb,
+                    const double* r, const double* g, const double* gscale, uint16_t* dout,
+                    float* part, hipStream_t st) {
+  if (sp.tile_ne != LowRankShape<P, kLowRank>::NE)
+    throw Error(PAFEM_EINVAL, "low-rank gradient: tile size differs from the apply tiles");
+  const int nt = ntiles_of(sp);
+  hipLaunchKernelGGL((lowrank_grad_kernel<P, kLowRank>), dim3(std::min(nt, kLowRankGradBlocks)),
+                     dim3(256), 0, st, sp.tile_off, sp.tile_dofs, sp.tile_slot, V, c, idb, r, g,
+                     gscale, dout, part, int(sp.ne), nt);
+}
+
 }  // namespace
 
 constexpr int kLossBlocks = 512;
@@ -219,37 +364,47 @@ void launch_patch_features(const DevSpace& sp, const double* kappa, int q1d, flo
   check("patch_features");
 }
 
-void launch_patch_inputs(const DevSpace& sp, const double* r, const float* feats, int in_pad,
-                         uint16_t* X, float* s, hipStream_t st) {
+void launch_net_inputs(const DevSpace& sp, const float* feats, int in_pad, uint16_t* X,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(net_inputs_kernel, dim3(grid_for(sp.ne * in_pad)), dim3(256), 0, st, feats,
+                     in_pad, X, sp.ne);
+  check("net_inputs");
+}
+
+void launch_lowrank_coeffs(const DevSpace& sp, const double* diag, const float* a, float* c,
+                           float* idb, hipStream_t st) {
   const int dpe = (sp.p + 1) * (sp.p + 1) * (sp.p + 1);
   const int64_t threads = sp.ne * kWave;
-  hipLaunchKernelGGL(patch_inputs_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, st,
-                     sp.gmap, r, feats, dpe, in_pad, X, s, sp.ne);
-  check("patch_inputs");
+  hipLaunchKernelGGL(lowrank_coeffs_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0,
+                     st, sp.gmap, diag, dpe, a, kLowRank, c, idb, sp.ne);
+  check("lowrank_coeffs");
 }
 
-void launch_patch_outputs(const DevSpace& sp, const float* out, int out_pad, const float* s,
-                          const float* feats, double* ye, hipStream_t st) {
+void launch_lowrank_apply(const DevSpace& sp, const float* V, const float* c, const float* idb,
+                          const double* r, double* z, hipStream_t st) {
+  switch (sp.p) {
+    case 1: lowrank_apply_p<1>(sp, V, c, idb, r, z, st); break;
+    case 2: lowrank_apply_p<2>(sp, V, c, idb, r, z, st); break;
+    case 3: lowrank_apply_p<3>(sp, V, c, idb, r, z, st); break;
+    case 4: lowrank_apply_p<4>(sp, V, c, idb, r, z, st); break;
+    default: throw Error(PAFEM_EUNSUPPORTED, "learned preconditioner: orders 1..4");
+  }
+  check("lowrank_apply");
+}
+
+void launch_lowrank_grad(const DevSpace& sp, const float* V, const float* c, const float* idb,
+                         const double* r, const double* g, const double* gscale, uint16_t* dout,
+                         float* part, float* gV, hipStream_t st) {
+  switch (sp.p) {
+    case 1: lowrank_grad_p<1>(sp, V, c, idb, r, g, gscale, dout, part, st); break;
+    case 2: lowrank_grad_p<2>(sp, V, c, idb, r, g, gscale, dout, part, st); break;
+    case 3: lowrank_grad_p<3>(sp, V, c, idb, r, g, gscale, dout, part, st); break;
+    case 4: lowrank_grad_p<4>(sp, V, c, idb, r, g, gscale, dout, part, st); break;
+    default: throw Error(PAFEM_EUNSUPPORTED, "learned preconditioner: orders 1..4");
+  }
+  check("lowrank_grad");
   const int dpe = (sp.p + 1) * (sp.p + 1) * (sp.p + 1);
-  hipLaunchKernelGGL(patch_outputs_kernel, dim3(grid_for(sp.ne * dpe)), dim3(256), 0, st, out,
-                     out_pad, dpe, s, feats, ye, sp.ne);
-  check("patch_outputs");
-}
-
-void launch_precond_gather(const DevSpace& sp, const double* ye, const double* r,
-                           const double* diag, double* z, hipStream_t st) {
-  hipLaunchKernelGGL(precond_gather_kernel, dim3(grid_for(sp.ndofs)), dim3(256), 0, st, sp.toff,
-                     sp.tidx, sp.bmask, ye, r, diag, z, sp.ndofs);
-  check("precond_gather");
-}
-
-void launch_patch_output_grad(const DevSpace& sp, const double* g, const double* gscale,
-                              const float* s, const float* feats, int out_pad, uint16_t* dout,
-                              hipStream_t st) {
-  const int dpe = (sp.p + 1) * (sp.p + 1) * (sp.p + 1);
-  hipLaunchKernelGGL(patch_output_grad_kernel, dim3(grid_for(sp.ne * out_pad)), dim3(256), 0, st,
-                     sp.gmap, sp.toff, g, gscale, s, feats, dpe, out_pad, dout, sp.ne);
-  check("patch_output_grad");
+  launch_reduce_parts(part, gV, std::min(ntiles_of(sp), kLowRankGradBlocks), dpe * kLowRank, st);
 }
 
 }  // namespace pafem

@@ -244,6 +244,11 @@ void launch_gemm_wgrad(const uint16_t* Z, const uint16_t* X, float* part, float*
   check("reduce_parts");
 }
 
+void launch_reduce_parts(const float* part, float* out, int nblk, int n, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid1d(n)), dim3(256), 0, st, part, out, nblk, n);
+  check("reduce_parts");
+}
+
 void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float beta1,
                  float beta2, float eps, int step, hipStream_t st) {
   const float c1 = 1.f - powf(beta1, float(step)), c2 = 1.f - powf(beta2, float(step));

@@ -87,23 +87,47 @@ __global__ void __launch_bounds__(kCGThreads)
   }
 }
 
+// alpha = rz / (d . q) with d . q assembled from the apply's per-workgroup element
+// energies plus, for a constrained operator, the essential rows (q_b = d_b there):
+// d . q = sum(epart) + sum over essential b of d_b^2.  The mask is read eight
+// entries at a time; entries at or beyond n are never used.
 template <typename TV>
 __global__ void __launch_bounds__(kCGThreads)
-    cg_dot_kernel(CGState* st, double* partials, const TV* __restrict__ d,
-                  const TV* __restrict__ q, int64_t n) {
+    cg_alpha_kernel(CGState* st, double* partials, const double* __restrict__ epart,
+                    int nepart, const uint8_t* __restrict__ bmask, const TV* __restrict__ d,
+                    int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   if (state_done(st)) return;
+  const int64_t tid = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t nthr = int64_t(gridDim.x) * blockDim.x;
   double s = 0.0;
-  GRID_LOOP(i, n) s += double(d[i]) * double(q[i]);
+  for (int64_t i = tid; i < nepart; i += nthr) s += epart[i];
+  if (bmask) {
+    const int64_t nw = n / 8;
+    const uint64_t* mw = reinterpret_cast<const uint64_t*>(bmask);
+    for (int64_t w = tid; w < nw; w += nthr) {
+      uint64_t m = mw[w];
+      while (m) {
+        const int b = __builtin_ctzll(m) >> 3;
+        const double v = double(d[w * 8 + b]);
+        s += v * v;
+        m &= ~(uint64_t(0xff) << (8 * b));
+      }
+    }
+    for (int64_t i = nw * 8 + tid; i < n; i += nthr)
+      if (bmask[i]) {
+        const double v = double(d[i]);
+        s += v * v;
+      }
+  }
   s = block_sum(s, scratch);
   if (threadIdx.x == 0) store_partial(partials, s);
   if (!arrive_last(&st->ticket[1])) return;
   const double pq = sum_partials(partials, scratch);
   if (threadIdx.x == 0) {
     const double alpha = st->rz / pq;
-    if (!(pq > 0.0) || !isfinite(alpha)) {
+    if (!(pq > 0.0) || !isfinite(alpha))
       __hip_atomic_store(&st->done, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     st->alpha = alpha;
     __hip_atomic_store(&st->ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -323,6 +347,173 @@ __global__ void __launch_bounds__(kCGThreads)
   GRID_LOOP(i, n) x[i] += scale * double(dx[i]);
 }
 
+// ---- inner PCG of iterative refinement --------------------------------------
+// The inner solve of A_lo d = r / s keeps its residual r, the preconditioned
+// residual z and all dot products in FP64; only what the reduced-precision apply
+// reads and writes is FP32: the direction d, its image q = A_lo d and the
+// correction dx accumulated since the last FP64 residual.  dinv is the Jacobi
+// preconditioner 1/diag rounded to FP32 (a preconditioner, not part of the
+// answer); null for none.  Essential rows: q_b = d_b for a constrained operator.
+
+__device__ __forceinline__ double ir_z(const double* r, const float* dinv, int64_t i) {
+  return dinv ? r[i] * double(dinv[i]) : r[i];
+}
+
+// r *= inv_s (r holds the FP64 residual), d = z, dx = 0, q = apply init of d;
+// rz, rr, bb = rr, tol2 = inner_rel_tol^2 rr, iter = 0, done
+__global__ void __launch_bounds__(kCGThreads)
+    ir_start_kernel(CGState* st, double* partials, double* __restrict__ r, double inv_s,
+                    const float* __restrict__ dinv, float* __restrict__ d,
+                    float* __restrict__ dx, float* __restrict__ q,
+                    const uint8_t* __restrict__ ess, double inner_rel_tol, int64_t n) {
+  __shared__ double scratch[kCGThreads / kWave];
+  double rz = 0.0, rr = 0.0;
+  GRID_LOOP(i, n) {
+    const double ri = r[i] * inv_s;
+    r[i] = ri;
+    const double zi = dinv ? ri * double(dinv[i]) : ri;
+    const float di = float(zi);
+    d[i] = di;
+    dx[i] = 0.0f;
+    q[i] = (ess && ess[i]) ? di : 0.0f;
+    rz += ri * zi;
+    rr += ri * ri;
+  }
+  rz = block_sum(rz, scratch);
+  rr = block_sum(rr, scratch);
+  if (threadIdx.x == 0) {
+    store_partial(partials, rz);
+    store_partial(partials + kCGBlocks, rr);
+  }
+  if (!arrive_last(&st->ticket[0])) return;
+  const double trz = sum_partials(partials, scratch);
+  const double trr = sum_partials(partials + kCGBlocks, scratch);
+  if (threadIdx.x == 0) {
+    st->rz = trz;
+    st->rr = trr;
+    st->bb = trr;
+    st->tol2 = inner_rel_tol * inner_rel_tol * trr;
+    st->iter = 0;
+    st->alpha = st->beta = 0.0;
+    const int done = trr > 0.0 ? 0 : 1;
+    __hip_atomic_store(&st->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// dx += alpha d; r -= alpha q (FP64); rz, rr, beta = rz / rz_old, iter, convergence
+__global__ void __launch_bounds__(kCGThreads)
+    ir_update_kernel(CGState* st, double* partials, float* __restrict__ dx,
+                     double* __restrict__ r, const float* __restrict__ d,
+                     const float* __restrict__ q, const float* __restrict__ dinv, int64_t n) {
+  __shared__ double scratch[kCGThreads / kWave];
+  if (state_done(st)) return;
+  const double alpha = st->alpha;
+  const float alpha_f = float(alpha);
+  double rz = 0.0, rr = 0.0;
+  GRID_LOOP(i, n) {
+    dx[i] += alpha_f * d[i];
+    const double ri = r[i] - alpha * double(q[i]);
+    r[i] = ri;
+    const double zi = dinv ? ri * double(dinv[i]) : ri;
+    rz += ri * zi;
+    rr += ri * ri;
+  }
+  rz = block_sum(rz, scratch);
+  rr = block_sum(rr, scratch);
+  if (threadIdx.x == 0) {
+    store_partial(partials, rz);
+    store_partial(partials + kCGBlocks, rr);
+  }
+  if (!arrive_last(&st->ticket[2])) return;
+  const double trz = sum_partials(partials, scratch);
+  const double trr = sum_partials(partials + kCGBlocks, scratch);
+  if (threadIdx.x == 0) {
+    const double beta = trz / st->rz;
+    st->beta = beta;
+    st->rz = trz;
+    st->rr = trr;
+    st->iter = st->iter + 1;
+    int done = 0;
+    if (!isfinite(trr) || !isfinite(beta)) done = 2;
+    else if (trr <= st->tol2) done = 1;
+    if (done) __hip_atomic_store(&st->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->ticket[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// d = z + beta d (stored FP32), q = apply init of the new d
+__global__ void __launch_bounds__(kCGThreads)
+    ir_direction_kernel(const CGState* st, const double* __restrict__ r,
+                        const float* __restrict__ dinv, float* __restrict__ d,
+                        float* __restrict__ q, const uint8_t* __restrict__ ess, int64_t n) {
+  if (state_done(st)) return;
+  const double beta = st->beta;
+  GRID_LOOP(i, n) {
+    const float di = float(ir_z(r, dinv, i) + beta * double(d[i]));
+    d[i] = di;
+    q[i] = (ess && ess[i]) ? di : 0.0f;
+  }
+}
+
+// Residual replacement: r holds the FP64 residual b - A_hi x; scale it by 1/s_new,
+// restart dx, and continue the recurrence with the kept direction d.  The next
+// direction d' = z + beta d is made A_lo-conjugate to d using q = A_lo d of the
+// last step: beta = -(z . q) / (d . q).  Without rounding and operator mismatch this
+// is the usual beta in the new scaling (times s_old / s_new for the kept direction);
+// with a replaced residual it keeps at least the last direction conjugate.
+__global__ void __launch_bounds__(kCGThreads)
+    ir_replace_kernel(CGState* st, double* partials, double* __restrict__ r, double inv_s_new,
+                      const float* __restrict__ dinv, const float* __restrict__ d,
+                      const float* __restrict__ q, float* __restrict__ dx,
+                      double inner_rel_tol, int64_t n) {
+  __shared__ double scratch[kCGThreads / kWave];
+  double rz = 0.0, rr = 0.0, zq = 0.0, dq = 0.0;
+  GRID_LOOP(i, n) {
+    const double ri = r[i] * inv_s_new;
+    r[i] = ri;
+    dx[i] = 0.0f;
+    const double zi = dinv ? ri * double(dinv[i]) : ri;
+    const double qi = double(q[i]);
+    rz += ri * zi;
+    rr += ri * ri;
+    zq += zi * qi;
+    dq += double(d[i]) * qi;
+  }
+  rz = block_sum(rz, scratch);
+  rr = block_sum(rr, scratch);
+  zq = block_sum(zq, scratch);
+  dq = block_sum(dq, scratch);
+  if (threadIdx.x == 0) {
+    store_partial(partials, rz);
+    store_partial(partials + kCGBlocks, rr);
+    store_partial(partials + 2 * kCGBlocks, zq);
+    store_partial(partials + 3 * kCGBlocks, dq);
+  }
+  if (!arrive_last(&st->ticket[6])) return;
+  const double trz = sum_partials(partials, scratch);
+  const double trr = sum_partials(partials + kCGBlocks, scratch);
+  const double tzq = sum_partials(partials + 2 * kCGBlocks, scratch);
+  const double tdq = sum_partials(partials + 3 * kCGBlocks, scratch);
+  if (threadIdx.x == 0) {
+    const double beta = -tzq / tdq;
+    st->beta = beta;
+    st->rz = trz;
+    st->rr = trr;
+    st->bb = trr;
+    st->tol2 = inner_rel_tol * inner_rel_tol * trr;
+    const int done = (isfinite(beta) && trz > 0.0 && tdq > 0.0) ? 0 : 2;
+    __hip_atomic_store(&st->done, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->ticket[6], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// dinv = 1 / diag rounded to FP32
+__global__ void __launch_bounds__(kCGThreads)
+    ir_dinv_kernel(const double* __restrict__ diag, float* __restrict__ dinv, int64_t n) {
+  GRID_LOOP(i, n) dinv[i] = float(1.0 / diag[i]);
+}
+
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
   const uint32_t u = __float_as_uint(f);
   if ((u & 0x7f800000u) == 0x7f800000u)  // inf or nan
@@ -369,11 +560,11 @@ void launch_cg_init(CGState* st, double* partials, const TB* b, double bscale, c
 }
 
 template <typename TV>
-void launch_cg_dot(CGState* st, double* partials, const TV* d, const TV* q, int64_t n,
-                   hipStream_t s) {
-  hipLaunchKernelGGL((cg_dot_kernel<TV>), dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials,
-                     d, q, n);
-  check_launch("cg_dot");
+void launch_cg_alpha(CGState* st, double* partials, const double* epart, int nepart,
+                     const uint8_t* bmask, const TV* d, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((cg_alpha_kernel<TV>), dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials,
+                     epart, nepart, bmask, d, n);
+  check_launch("cg_alpha");
 }
 
 template <typename TV>
@@ -395,22 +586,15 @@ void launch_cg_direction(CGState* st, const TV* r, const TV* diag, TV* d, int64_
 template void launch_cg_init<double, double>(CGState*, double*, const double*, double,
                                              const double*, const double*, double*, double*,
                                              double*, int, double, double*, int64_t, hipStream_t);
-template void launch_cg_init<double, float>(CGState*, double*, const double*, double,
-                                            const float*, const float*, float*, float*, float*,
-                                            int, double, double*, int64_t, hipStream_t);
-template void launch_cg_dot<double>(CGState*, double*, const double*, const double*, int64_t,
-                                    hipStream_t);
-template void launch_cg_dot<float>(CGState*, double*, const float*, const float*, int64_t,
-                                   hipStream_t);
+template void launch_cg_alpha<double>(CGState*, double*, const double*, int, const uint8_t*,
+                                      const double*, int64_t, hipStream_t);
+template void launch_cg_alpha<float>(CGState*, double*, const double*, int, const uint8_t*,
+                                     const float*, int64_t, hipStream_t);
 template void launch_cg_update<double>(CGState*, double*, double*, double*, const double*,
                                        const double*, const double*, double*, int64_t,
                                        hipStream_t);
-template void launch_cg_update<float>(CGState*, double*, float*, float*, const float*,
-                                      const float*, const float*, double*, int64_t, hipStream_t);
 template void launch_cg_direction<double>(CGState*, const double*, const double*, double*,
                                           int64_t, hipStream_t);
-template void launch_cg_direction<float>(CGState*, const float*, const float*, float*, int64_t,
-                                         hipStream_t);
 
 void launch_fcg_init(CGState* st, double* partials, const double* b, const double* q, double* x,
                      double* r, int zero_guess, double rel_tol, double* hist, int64_t n,
@@ -453,6 +637,42 @@ void launch_ir_correct(double* x, const float* dx, double scale, int64_t n, hipS
   hipLaunchKernelGGL(ir_correct_kernel, dim3(vec_grid(n)), dim3(kCGThreads), 0, s, x, dx, scale,
                      n);
   check_launch("ir_correct");
+}
+
+void launch_ir_start(CGState* st, double* partials, double* r, double s, const float* dinv,
+                     float* d, float* dx, float* q, const uint8_t* ess, double inner_rel_tol,
+                     int64_t n, hipStream_t stream) {
+  hipLaunchKernelGGL(ir_start_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, stream, st, partials,
+                     r, 1.0 / s, dinv, d, dx, q, ess, inner_rel_tol, n);
+  check_launch("ir_start");
+}
+
+void launch_ir_update(CGState* st, double* partials, float* dx, double* r, const float* d,
+                      const float* q, const float* dinv, int64_t n, hipStream_t stream) {
+  hipLaunchKernelGGL(ir_update_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, stream, st,
+                     partials, dx, r, d, q, dinv, n);
+  check_launch("ir_update");
+}
+
+void launch_ir_direction(CGState* st, const double* r, const float* dinv, float* d, float* q,
+                         const uint8_t* ess, int64_t n, hipStream_t stream) {
+  hipLaunchKernelGGL(ir_direction_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, stream, st, r,
+                     dinv, d, q, ess, n);
+  check_launch("ir_direction");
+}
+
+void launch_ir_replace(CGState* st, double* partials, double* r, double s_new, const float* dinv,
+                       const float* d, const float* q, float* dx, double inner_rel_tol, int64_t n,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL(ir_replace_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, stream, st,
+                     partials, r, 1.0 / s_new, dinv, d, q, dx, inner_rel_tol, n);
+  check_launch("ir_replace");
+}
+
+void launch_ir_dinv(const double* diag, float* dinv, int64_t n, hipStream_t stream) {
+  hipLaunchKernelGGL(ir_dinv_kernel, dim3(vec_grid(n)), dim3(kCGThreads), 0, stream, diag, dinv,
+                     n);
+  check_launch("ir_dinv");
 }
 
 void launch_convert(const double* src, void* dst, int dtype, int64_t n, hipStream_t s) {

@@ -31,10 +31,13 @@ void launch_scatter_init_f32(const DevSpace& sp, const float* x, bool constraine
 
 // ---- apply (k_apply.hip) ----
 // Fused G -> B -> D -> B^t -> G^t.  evec: write element vectors to `out`
-// [ne][D^3] instead of atomically adding into the dof vector `out`.
+// [ne][D^3] instead of atomically adding into the dof vector `out`.  dotp (may be
+// null): receives pa_apply_blocks(sp) partial sums of the element energies
+// u_E . A_E u_E (essential inputs 0 when constrained), one per workgroup.
 // Returns false if (p, q1d, dtype) is not instantiated.
 bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool constrained,
                      bool evec, const void* qd, const void* x, void* out, int vdtype,
-                     hipStream_t st);
+                     hipStream_t st, double* dotp = nullptr);
+int pa_apply_blocks(const DevSpace& sp);
 
 }  // namespace pafem

@@ -1,7 +1,7 @@
-// Learned element-patch preconditioner: the network object (parameters, Adam
-// state, bf16 copies and activations in one caller-owned device buffer), the
-// preconditioner application, the training loss and its gradient, and flexible
-// CG with a Jacobi fallback.
+// Learned element preconditioner: the network object (parameters -- the element
+// network and the element basis V --, Adam state, bf16 copies and activations in
+// one caller-owned device buffer), the preconditioner application, the training
+// loss and its gradient, and flexible CG with a Jacobi fallback.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "capi.hpp"
+#include "launch.hpp"
 #include "mlp.hpp"
 #include "solver.hpp"
 
@@ -19,17 +20,19 @@ namespace pafem {
 
 namespace {
 
-constexpr int kFeatures = 9;  // per element: kbar + 8 octant log-ratios
 constexpr int kLossPartials = 2 * 512;
+constexpr int kNetIn = 16;  // 8 octant log-ratios, padded to the MFMA K step
 
 int round16(int v) { return (v + 15) / 16 * 16; }
 
 struct NetDims {
   int p = 0, dpe = 0, in = 0, hid = 0, out = 0;
   int64_t nparams = 0;
-  int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+  int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0, oV = 0;
 };
 
+// Parameters, FP32, in this order: W1 [hid][in], b1, W2 [hid][hid], b2,
+// W3 [out][hid], b3 [out], V [(p+1)^3][out]; out = kLowRank.
 NetDims net_dims(int order, int hidden) {
   if (order < 1 || order > 4) throw Error(PAFEM_EUNSUPPORTED, "learned preconditioner: orders 1..4");
   if (hidden < 16 || hidden > 128 || hidden % 16)
@@ -37,22 +40,23 @@ NetDims net_dims(int order, int hidden) {
   NetDims d;
   d.p = order;
   d.dpe = (order + 1) * (order + 1) * (order + 1);
-  d.in = round16(d.dpe + 8);
+  d.in = kNetIn;
   d.hid = hidden;
-  d.out = round16(d.dpe);
+  d.out = kLowRank;
   d.oW1 = 0;
   d.ob1 = d.oW1 + int64_t(d.hid) * d.in;
   d.oW2 = d.ob1 + d.hid;
   d.ob2 = d.oW2 + int64_t(d.hid) * d.hid;
   d.oW3 = d.ob2 + d.hid;
   d.ob3 = d.oW3 + int64_t(d.out) * d.hid;
-  d.nparams = d.ob3 + d.out;
+  d.oV = d.ob3 + d.out;
+  d.nparams = d.oV + int64_t(d.dpe) * d.out;
   return d;
 }
 
 struct NetLayout {
-  size_t params, grads, m, v, w1b, w2b, w2tb, w3b, w3tb, X, H1, H2, O, dO, dZ2, dZ1, s, part,
-      partb, total;
+  size_t params, grads, m, v, w1b, w2b, w2tb, w3b, w3tb, X, H1, H2, O, dO, dZ2, dZ1, part, partb,
+      total;
 };
 
 NetLayout net_layout(const NetDims& d, int64_t rows, int64_t train_rows) {
@@ -80,10 +84,11 @@ NetLayout net_layout(const NetDims& d, int64_t rows, int64_t train_rows) {
   L.dO = take(size_t(train_rows) * d.out * 2);
   L.dZ2 = take(size_t(train_rows) * d.hid * 2);
   L.dZ1 = take(size_t(train_rows) * d.hid * 2);
-  L.s = take(size_t(rows) * 4);
+  // partial weight gradients of the largest layer (N x K of the three GEMMs)
   const size_t nblk = size_t(std::max(1, wgrad_blocks(int(std::max<int64_t>(train_rows, 1)))));
-  L.part = take(nblk * 128 * 256 * 4);
-  L.partb = take(nblk * 128 * 4);
+  const size_t nk = size_t(std::max({d.hid * d.in, d.hid * d.hid, d.out * d.hid}));
+  L.part = take(nblk * nk * 4);
+  L.partb = take(nblk * std::max(d.hid, d.out) * 4);
   L.total = o;
   return L;
 }
@@ -151,7 +156,7 @@ struct Net {
 namespace {
 
 struct LearnedLayout {
-  size_t ye, z, t, u, v, w, partials, ticket, scal, opwork, total;
+  size_t z, t, u, v, w, c, idb, partV, partials, ticket, scal, opwork, total;
 };
 
 LearnedLayout learned_layout(const Op& op) {
@@ -164,12 +169,14 @@ LearnedLayout learned_layout(const Op& op) {
     o += align256(bytes);
     return at;
   };
-  L.ye = take(size_t(s.ne) * s.dpe * 8);
   L.z = take(n * 8);
   L.t = take(n * 8);
   L.u = take(n * 8);
   L.v = take(n * 8);
   L.w = take(n * 8);
+  L.c = take(size_t(s.ne) * kLowRank * 4);
+  L.idb = take(size_t(s.ne) * 4);
+  L.partV = take(size_t(kLowRankGradBlocks) * s.dpe * kLowRank * 4);
   L.partials = take(kLossPartials * 8);
   L.ticket = take(64);
   L.scal = take(64);
@@ -184,18 +191,24 @@ void check_net_op(const Net& net, const Op& op) {
   require(op.space->ne <= net.rows, PAFEM_ESHAPE, "mesh has more elements than the network rows");
 }
 
-// z = M(r) with the network (ye in work)
-void learned_apply(const Net& net, const Op& op, const float* feats, const double* diag,
-                   const double* r, double* z, char* work, const LearnedLayout& W,
-                   hipStream_t st) {
+// Element weights for this operator and the current parameters: the network on
+// the element features, then c = softplus(output) and 1 / dbar_E.
+void learned_setup(const Net& net, const Op& op, const float* feats, const double* diag,
+                   char* work, const LearnedLayout& W, hipStream_t st) {
   const DevSpace& sp = op.space->dev;
-  launch_patch_inputs(sp, r, feats, net.d.in, net.at<uint16_t>(net.L.X), net.at<float>(net.L.s),
-                      st);
+  launch_net_inputs(sp, feats, net.d.in, net.at<uint16_t>(net.L.X), st);
   net.forward(net.at<uint16_t>(net.L.X), sp.ne, st);
-  double* ye = reinterpret_cast<double*>(work + W.ye);
-  launch_patch_outputs(sp, net.at<float>(net.L.O), net.d.out, net.at<float>(net.L.s), feats, ye,
-                       st);
-  launch_precond_gather(sp, ye, r, diag, z, st);
+  launch_lowrank_coeffs(sp, diag, net.at<float>(net.L.O), reinterpret_cast<float*>(work + W.c),
+                        reinterpret_cast<float*>(work + W.idb), st);
+}
+
+// z = M(r) with the element weights of the last learned_setup
+void learned_apply(const Net& net, const Op& op, const double* diag, const double* r, double* z,
+                   char* work, const LearnedLayout& W, hipStream_t st) {
+  const DevSpace& sp = op.space->dev;
+  launch_jacobi(sp, r, diag, z, st);
+  launch_lowrank_apply(sp, net.params() + net.d.oV, reinterpret_cast<const float*>(work + W.c),
+                       reinterpret_cast<const float*>(work + W.idb), r, z, st);
 }
 
 }  // namespace
@@ -330,7 +343,9 @@ void learned_precond(const Net& net, const Op& op, const float* feats, const dou
   check_net_op(net, op);
   const LearnedLayout W = learned_layout(op);
   require(work && work_bytes >= W.total, PAFEM_ESHAPE, "workspace too small");
-  learned_apply(net, op, feats, diag, r, z, static_cast<char*>(work), W, st);
+  char* w = static_cast<char*>(work);
+  learned_setup(net, op, feats, diag, w, W, st);
+  learned_apply(net, op, diag, r, z, w, W, st);
 }
 
 void learned_loss_grad(Net& net, const Op& op, const float* feats, const double* diag,
@@ -351,14 +366,18 @@ void learned_loss_grad(Net& net, const Op& op, const float* feats, const double*
   auto* partials = reinterpret_cast<double*>(w + W.partials);
   auto* ticket = reinterpret_cast<uint32_t*>(w + W.ticket);
   auto* scal = reinterpret_cast<double*>(w + W.scal);
-  learned_apply(net, op, feats, diag, r, z, w, W, st);
+  learned_setup(net, op, feats, diag, w, W, st);
+  learned_apply(net, op, diag, r, z, w, W, st);
   launch_diff(e, z, t, sp.ndofs, st);
   apply_op(op, t, u, w + W.opwork, st);
   hip_check(hipMemsetAsync(ticket, 0, 4, st), "loss ticket");
   launch_loss(sp, u, r, diag, v, partials, ticket, scal, st);
   apply_op(op, v, g, w + W.opwork, st);
-  launch_patch_output_grad(sp, g, scal + 1, net.at<float>(net.L.s), feats, net.d.out,
-                           net.at<uint16_t>(net.L.dO), st);
+  // dL/dz = scal[1] * g; the basis gradient goes straight into the gradient vector
+  launch_lowrank_grad(sp, net.params() + net.d.oV, reinterpret_cast<const float*>(w + W.c),
+                      reinterpret_cast<const float*>(w + W.idb), r, g, scal + 1,
+                      net.at<uint16_t>(net.L.dO), reinterpret_cast<float*>(w + W.partV),
+                      net.grads() + net.d.oV, st);
   net.backward(net.at<uint16_t>(net.L.X), net.at<uint16_t>(net.L.dO), sp.ne, st);
   if (loss) hip_check(hipMemcpyAsync(loss, scal, 8, hipMemcpyDeviceToDevice, st), "loss copy");
 }
@@ -366,7 +385,7 @@ void learned_loss_grad(Net& net, const Op& op, const float* feats, const double*
 // ---- flexible CG ---------------------------------------------------------------
 
 struct FCGLayout {
-  size_t state, partials, hist, r, z, zold, p, q, learned, total;
+  size_t state, partials, hist, r, z, zold, p, q, dotp, learned, total;
 };
 
 FCGLayout fcg_layout(const Op& op, int max_iter) {
@@ -386,6 +405,7 @@ FCGLayout fcg_layout(const Op& op, int max_iter) {
   L.zold = take(n * 8);
   L.p = take(n * 8);
   L.q = take(n * 8);
+  L.dotp = take(size_t(pa_apply_blocks(op.space->dev)) * sizeof(double));
   L.learned = take(learned_layout(op).total);
   L.total = o;
   return L;
@@ -415,6 +435,9 @@ pafem_status fcg_solve(const Op& op, Net* net, const float* feats, const double*
   auto* zold = reinterpret_cast<double*>(w + L.zold);
   auto* p = reinterpret_cast<double*>(w + L.p);
   auto* q = reinterpret_cast<double*>(w + L.q);
+  auto* dotp = reinterpret_cast<double*>(w + L.dotp);
+  const int nap = pa_apply_blocks(op.space->dev);
+  const uint8_t* ess = (op.flags & PAFEM_OP_CONSTRAINED) ? op.space->dev.bmask : nullptr;
   char* lw = w + L.learned;
   const LearnedLayout LW = learned_layout(op);
   const DevSpace& sp = op.space->dev;
@@ -423,9 +446,10 @@ pafem_status fcg_solve(const Op& op, Net* net, const float* feats, const double*
   res = pafem_fcg_result{};
   res.fallback_iter = -1;
 
+  if (use_net) learned_setup(*net, op, feats, diag, lw, LW, st);
   auto precond = [&](const double* rr, double* zz) {
     if (use_net)
-      learned_apply(*net, op, feats, diag, rr, zz, lw, LW, st);
+      learned_apply(*net, op, diag, rr, zz, lw, LW, st);
     else
       launch_jacobi(sp, rr, diag, zz, st);
   };
@@ -463,8 +487,8 @@ pafem_status fcg_solve(const Op& op, Net* net, const float* feats, const double*
     if (launched >= opts.max_iter || h.iter >= opts.max_iter) break;
     const int batch = std::min(check, opts.max_iter - launched);
     for (int k = 0; k < batch; ++k) {
-      apply_op(op, p, q, lw + LW.opwork, st);
-      launch_cg_dot<double>(state, partials, p, q, n, st);
+      apply_op(op, p, q, lw + LW.opwork, st, dotp);
+      launch_cg_alpha<double>(state, partials, dotp, nap, ess, p, n, st);
       launch_fcg_update(state, partials, x, r, p, q, hist, n, st);
       precond(r, zold);  // new z into the spare buffer
       launch_fcg_beta(state, partials, r, zold, z, n, st);

@@ -27,24 +27,31 @@ void launch_cast_weights(const float* W, uint16_t* Wb, uint16_t* Wtb, int rows, 
                          hipStream_t st);
 void launch_f32_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t st);
 
+// part [nblk][n] -> out[n], summed over blocks in index order
+void launch_reduce_parts(const float* part, float* out, int nblk, int n, hipStream_t st);
+
 // ---- learned preconditioner (k_learned.hip) ----
+constexpr int kLowRank = 16;            // columns of the learned element basis V
+constexpr int kLowRankGradBlocks = 256;  // workgroups of the basis-gradient reduction
+
 // feats[e] = {kbar_e, 8 octant log-ratios} per device element, from kappa [E][Q^3]
 // in caller element order (NULL: kbar = 1, ratios 0).
 void launch_patch_features(const DevSpace& sp, const double* kappa, int q1d, float* feats,
                            hipStream_t st);
-// X[e] = bf16([r_E / s_e, ratios, 0...]) and s[e] = ||r_E||
-void launch_patch_inputs(const DevSpace& sp, const double* r, const float* feats, int in_pad,
-                         uint16_t* X, float* s, hipStream_t st);
-// ye[e][i] = (s_e / kbar_e) out[e][i]
-void launch_patch_outputs(const DevSpace& sp, const float* out, int out_pad, const float* s,
-                          const float* feats, double* ye, hipStream_t st);
-// z = r / diag + (sum of ye over the dof's element nodes) / multiplicity; 0 on essential dofs
-void launch_precond_gather(const DevSpace& sp, const double* ye, const double* r,
-                           const double* diag, double* z, hipStream_t st);
-// dout[e][i] = (s_e / kbar_e) * g[dof] / multiplicity(dof) * gscale[0], as bf16 [E][out_pad]
-void launch_patch_output_grad(const DevSpace& sp, const double* g, const double* gscale,
-                              const float* s, const float* feats, int out_pad, uint16_t* dout,
-                              hipStream_t st);
+// X[e] = bf16([8 log-ratios, 0...]), in_pad columns
+void launch_net_inputs(const DevSpace& sp, const float* feats, int in_pad, uint16_t* X,
+                       hipStream_t st);
+// c[e][k] = softplus(a[e][k]) (a: network output [E][kLowRank]); idb[e] = 1 / dbar_E
+void launch_lowrank_coeffs(const DevSpace& sp, const double* diag, const float* a, float* c,
+                           float* idb, hipStream_t st);
+// z += sum_E R_E^t V diag(c_E idb_E) V^t R_E r on non-essential dofs; V [(p+1)^3][kLowRank]
+void launch_lowrank_apply(const DevSpace& sp, const float* V, const float* c, const float* idb,
+                          const double* r, double* z, hipStream_t st);
+// For dL/dz = gscale[0] * g: network output gradient dout (bf16 [E][kLowRank]) and the
+// basis gradient gV [(p+1)^3][kLowRank]; part holds kLowRankGradBlocks * (p+1)^3 * kLowRank floats
+void launch_lowrank_grad(const DevSpace& sp, const float* V, const float* c, const float* idb,
+                         const double* r, const double* g, const double* gscale, uint16_t* dout,
+                         float* part, float* gV, hipStream_t st);
 
 // t = a - b
 void launch_diff(const double* a, const double* b, double* t, int64_t n, hipStream_t st);

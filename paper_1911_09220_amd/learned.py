@@ -1,6 +1,7 @@
 """Training orchestration for the learned element preconditioner.
 
-Only sequencing lives here; every computation is a library call:
+Only sequencing and the initial parameters live here; every computation is a
+library call:
 * pairs (r_k, e_k = x* - x_k) come from plain Jacobi-PCG runs (pafem_pcg_solve)
   stopped after k iterations, x* from a run to a tight tolerance;
 * each training step is pafem_learned_loss_grad (preconditioner forward, the
@@ -12,6 +13,19 @@ from __future__ import annotations
 import numpy as np
 
 from . import pafem as P
+
+
+def initial_params(net, seed=0, bias=-3.0):
+    """Starting point: He-normal hidden layers, a zero last layer whose bias makes
+    every element weight softplus(bias) (small: the preconditioner starts close to
+    Jacobi), and a random basis with unit expected column norm."""
+    rng = np.random.default_rng(seed)
+    h, i, o = net.hidden, net.in_dim, net.out_dim
+    nd = (net.order + 1) ** 3
+    return {"W1": rng.normal(scale=np.sqrt(2.0 / i), size=(h, i)), "b1": np.zeros(h),
+            "W2": rng.normal(scale=np.sqrt(2.0 / h), size=(h, h)), "b2": np.zeros(h),
+            "W3": np.zeros((o, h)), "b3": np.full(o, bias),
+            "V": rng.normal(scale=1.0 / np.sqrt(nd), size=(nd, o))}
 
 
 def jacobi_pairs(op, b, diag, stops=(2, 5, 10, 20, 40, 80), tight=1e-12, max_iter=20000):

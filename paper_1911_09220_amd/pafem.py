@@ -46,7 +46,8 @@ class SolveResult(C.Structure):
 class IROpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("inner_rel_tol", C.c_double), ("max_outer", C.c_int32),
                 ("max_inner", C.c_int32), ("check_every", C.c_int32), ("precond", C.c_int32),
-                ("res_hist", C.POINTER(C.c_double)), ("res_hist_cap", C.c_int32)]
+                ("keep_direction", C.c_int32), ("res_hist", C.POINTER(C.c_double)),
+                ("res_hist_cap", C.c_int32)]
 
 
 class IRResult(C.Structure):
@@ -58,6 +59,9 @@ class FCGResult(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("fell_back", C.c_int32),
                 ("fallback_iter", C.c_int32), ("rel_res", C.c_double),
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
+
+
+ABI_VERSION = 200  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -123,6 +127,9 @@ def _load():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.pafem_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {lib.pafem_version()}, this binding "
+                          f"expects {ABI_VERSION}; rebuild with __graft_entry__.build()")
     return lib
 
 
@@ -443,8 +450,11 @@ class Operator:
         return x, info
 
     def ir_solve(self, lo, b, diag=None, rel_tol=1e-10, inner_rel_tol=1e-2, max_outer=50,
-                 max_inner=5000, check_every=8, precond=PRECOND_JACOBI):
-        """Iterative refinement with `lo` (same operator on F32/BF16 qdata) as inner solver."""
+                 max_inner=5000, check_every=8, precond=PRECOND_JACOBI, keep_direction=True):
+        """Iterative refinement with `lo` (same operator on F32/BF16 qdata) as inner solver.
+
+        keep_direction: the inner PCG continues across steps with its residual replaced
+        by the FP64 one (reliable update); False restarts it at every step."""
         import torch
         if precond == PRECOND_JACOBI and diag is None:
             diag = self.diagonal()
@@ -453,8 +463,8 @@ class Operator:
         work = _device_bytes(pafem_ir_workspace_bytes(self.handle, lo.handle), self.space.device)
         hist = np.zeros(max_outer + 1)
         opts = IROpts(float(rel_tol), float(inner_rel_tol), int(max_outer), int(max_inner),
-                      int(check_every), int(precond), hist.ctypes.data_as(C.POINTER(C.c_double)),
-                      hist.size)
+                      int(check_every), int(precond), int(bool(keep_direction)),
+                      hist.ctypes.data_as(C.POINTER(C.c_double)), hist.size)
         rc, res = pafem_ir_solve(self.handle, lo.handle,
                                  diag if precond == PRECOND_JACOBI else None, b, x, work, opts)
         if rc not in (0, -5):
@@ -510,9 +520,10 @@ class Batch:
 
 
 class Net:
-    """Element-patch network (BF16 MFMA kernels, FP32 master weights, Adam)."""
+    """Learned element preconditioner parameters: the element network (BF16 MFMA
+    kernels, FP32 master weights) and the element basis V [(p+1)^3, out_dim]; Adam."""
 
-    NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+    NAMES = ("W1", "b1", "W2", "b2", "W3", "b3", "V")
 
     def __init__(self, order, hidden=128, max_rows=1, max_train_rows=0, device="cuda"):
         n = C.c_size_t()
@@ -529,7 +540,8 @@ class Net:
         self.order = int(order)
         self.shapes = {"W1": (self.hidden, self.in_dim), "b1": (self.hidden,),
                        "W2": (self.hidden, self.hidden), "b2": (self.hidden,),
-                       "W3": (self.out_dim, self.hidden), "b3": (self.out_dim,)}
+                       "W3": (self.out_dim, self.hidden), "b3": (self.out_dim,),
+                       "V": ((self.order + 1) ** 3, self.out_dim)}
 
     def flatten(self, params):
         return np.concatenate([np.asarray(params[k], dtype=np.float32).reshape(-1)

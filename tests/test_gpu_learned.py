@@ -1,6 +1,7 @@
 """Learned element preconditioner on the GPU: BF16 MFMA network kernels against the
-FP64 NumPy oracle, the preconditioner and its training loss/gradients against the
-oracle, flexible CG, the Jacobi fallback, and training.
+FP64 NumPy oracle, the preconditioner and its training loss/gradients (network and
+element basis) against the oracle, flexible CG, the Jacobi fallback, and training
+with its gain over Jacobi on a held-out coefficient field.
 
 Bars (BF16 weights and activations, FP32 accumulation): forward outputs and loss
 within 3e-2 relative of the FP64 oracle on the same bf16-rounded weights and
@@ -34,11 +35,15 @@ def _bf16(a):
 
 
 def _rounded(params):
-    """Weights as the GPU sees them: bf16 matrices, fp32 biases."""
+    """Parameters as the GPU sees them: bf16 network matrices, fp32 biases and basis."""
     out = {}
     for k, v in params.items():
         out[k] = _bf16(v) if k.startswith("W") else v.astype(np.float32).astype(np.float64)
     return out
+
+
+def _net_only(params):
+    return {k: v for k, v in params.items() if k != "V"}
 
 
 def _cos(a, b):
@@ -50,6 +55,8 @@ def _params(net, seed, zero_last=False):
     rng = np.random.default_rng(seed + 1)
     for k in ("b1", "b2", "b3"):
         p[k] = 0.05 * rng.normal(size=p[k].shape)
+    nd = (net.order + 1) ** 3
+    p["V"] = rng.normal(size=(nd, net.out_dim)) / np.sqrt(nd)
     return p
 
 
@@ -64,13 +71,13 @@ def test_network_forward_backward_vs_oracle():
     xd = torch.as_tensor(xbits.view(np.int16), device="cuda").contiguous()
     dd = torch.as_tensor(dbits.view(np.int16), device="cuda").contiguous()
     out = net.forward(xd, rows).cpu().numpy()
-    pr = _rounded(params)
+    pr = _net_only(_rounded(params))
     ref, cache = omlp.forward(pr, bf16_bits_to_f64(xbits))
     assert rel_err(out, ref) <= 3e-2
     net.backward(xd, dd, rows)
     g = net.get_grads()
     gr = omlp.backward(pr, cache, bf16_bits_to_f64(dbits))
-    for k in net.NAMES:
+    for k in pr:
         c, e = _cos(g[k], gr[k]), rel_err(g[k], gr[k])
         print(f"{k}: cosine {c:.5f} rel {e:.2e}")
         assert c >= 0.999 and e <= 5e-2, k
@@ -89,15 +96,19 @@ def _small_problem(p=2, n=(3, 3, 2), seed=5):
     return mesh, kappa, S, op, diag, feats, ref
 
 
-def test_zero_last_layer_is_jacobi():
+def test_zero_basis_is_jacobi():
     mesh, kappa, S, op, diag, feats, ref = _small_problem()
     net = P.Net(2, hidden=32, max_rows=S.nelem, max_train_rows=S.nelem)
-    net.set_params(_params(net, 6, zero_last=True) | {"b3": np.zeros(net.out_dim)})
+    params = _params(net, 6)
+    params["V"][:] = 0.0
+    net.set_params(params)
     X = S.dof_coords()
     r = torch.as_tensor(synth.hash_normal(X, seed=7), device="cuda")
-    r[torch.as_tensor(S.boundary_dofs(), device="cuda").long()] = 0.0
+    bd = torch.as_tensor(S.boundary_dofs(), device="cuda").long()
+    r[bd] = 0.0
     z = P.learned_precond(net, op, feats, diag, r)
-    jac = torch.where(diag != 0, r / diag, torch.zeros_like(r))
+    jac = r / diag
+    jac[bd] = 0.0
     assert float((z - jac).abs().max()) == 0.0
 
 
@@ -118,19 +129,21 @@ def test_preconditioner_and_loss_gradients_vs_oracle():
     e_lib[ref.space.boundary[perm]] = 0.0
     e = torch.as_tensor(e_lib, device="cuda")
     r = op.apply(e)
-    kbar, f8 = omlp.element_features(kappa, p + 2)
-    in_dim = net.in_dim
+    _, f8 = omlp.element_features(kappa, p + 2)
+    f8 = _bf16(f8.astype(np.float32).astype(np.float64))     # the GPU's network inputs
     r_or = ref.Kc @ e_or
     d_or = ref.Kc.diagonal()
+    net_p = _net_only(pr)
     z = P.learned_precond(net, op, feats, diag, r).cpu().numpy()
-    z_or, _ = omlp.precondition(pr, r_or, d_or, ref.space.elem_dofs, bd, f8.astype(np.float32),
-                                kbar.astype(np.float32), in_dim)
+    z_or, _ = omlp.precondition(net_p, pr["V"], r_or, d_or, ref.space.elem_dofs, bd, f8,
+                                net.in_dim)
     err = rel_err(z, z_or[perm])
-    print(f"preconditioner rel err {err:.2e}")
-    assert err <= 3e-2
+    jac_gap = rel_err(z_or, np.where(bd, 0.0, r_or / d_or))
+    print(f"preconditioner rel err {err:.2e} (correction is {jac_gap:.2e} of z)")
+    assert err <= 3e-2 * max(jac_gap, 1e-3) + 1e-12
     loss = float(P.learned_loss_grad(net, op, feats, diag, r, e)[0])
-    L_or, G_or = omlp.loss_and_grads(pr, ref.Kc, r_or, e_or, d_or, ref.space.elem_dofs, bd,
-                                     f8.astype(np.float32), kbar.astype(np.float32), in_dim)
+    L_or, G_or = omlp.loss_and_grads(net_p, pr["V"], ref.Kc, r_or, e_or, d_or,
+                                     ref.space.elem_dofs, bd, f8, net.in_dim)
     print(f"loss {loss:.6f} oracle {L_or:.6f}")
     assert abs(loss - L_or) <= 3e-2 * abs(L_or)
     g = net.get_grads()
@@ -166,29 +179,41 @@ def test_fallback_on_broken_network():
     assert rel_err(x.cpu().numpy(), xd[perm]) < 1e-8
 
 
-def test_training_lowers_loss_and_fcg_converges():
-    p = 3
-    mesh = synth.hex_lattice(6, 0.05, seed=11)
+def test_training_gains_over_jacobi():
+    """Train on pairs from Jacobi-PCG runs on seeded coefficient fields, then solve
+    with a held-out field: the trained preconditioner needs clearly fewer FCG
+    iterations than Jacobi-PCG, and the solution matches the oracle's."""
+    p, n = 3, 8
+    mesh = synth.hex_lattice(n, 0.05, seed=11)
     E = mesh["hex"].shape[0]
     S = P.Space(P.Mesh.from_dict(mesh), p)
     net = P.Net(p, hidden=64, max_rows=E, max_train_rows=E)
-    net.set_params(synth.mlp_init(net.in_dim, 64, net.out_dim, seed=12, zero_last=True))
+    net.set_params(L.initial_params(net, seed=12))
+    pts = synth.lattice_quadrature_points(n, p + 2)
+
+    def problem(seed):
+        kappa = synth.grf_lognormal(pts, 0.1, 1e3, seed=seed, device="cuda").reshape(E, -1)
+        op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kappa.contiguous()))
+        return kappa, op, op.diagonal(), P.learned_features(S, kappa.contiguous())
+
     samples = []
-    pts = synth.lattice_quadrature_points(6, p + 2)
-    for f in range(4):
-        kappa = torch.as_tensor(synth.grf_lognormal(pts, 0.1, 1e3, seed=1000 + f), device="cuda")
-        kappa = kappa.reshape(E, -1).contiguous()
-        op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kappa))
-        diag = op.diagonal()
-        feats = P.learned_features(S, kappa)
+    for f in range(6):
+        _, op, diag, feats = problem(1000 + f)
         b = S.linear_form(P.SOURCE_SINE)
         for r, e in L.jacobi_pairs(op, b, diag):
             samples.append((op, feats, diag, r, e))
-    losses = L.train(net, samples, steps=300, lr=2e-3)
-    first, last = losses[:20].mean(), losses[-20:].mean()
-    print(f"loss {first:.4f} -> {last:.4f}")
+    losses = L.train(net, samples, steps=800, lr=2e-3, decay_every=300)
+    first, last = losses[:50].mean(), losses[-50:].mean()
     assert np.all(np.isfinite(losses)) and last < first
-    op, feats, diag = samples[0][0], samples[0][1], samples[0][2]
+    kappa, op, diag, feats = problem(2000)
     b = S.linear_form(P.SOURCE_SINE)
-    x, info = P.fcg_solve(op, b, diag, net=net, feats=feats, rel_tol=1e-8)
-    assert info["converged"] and info["true_rel_res"] < 1e-7
+    _, ij = op.pcg(b, diag=diag, rel_tol=1e-8)
+    x, il = P.fcg_solve(op, b, diag, net=net, feats=feats, rel_tol=1e-8)
+    print(f"loss {first:.4f} -> {last:.4f}; held-out: Jacobi-PCG {ij['iters']} its, "
+          f"learned FCG {il['iters']} its")
+    assert il["converged"] and not il["fell_back"] and il["true_rel_res"] < 1e-7
+    assert il["iters"] <= 0.85 * ij["iters"]
+    ref = OracleProblem(mesh, p, coeff=kappa.cpu().numpy())
+    perm = match_by_coords(S.dof_coords(), ref.coords)
+    xd = spla.spsolve(ref.Kc.tocsc(), ref.load(synth.sine_source))
+    assert rel_err(x.cpu().numpy(), xd[perm]) < 1e-6

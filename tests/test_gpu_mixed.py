@@ -58,9 +58,10 @@ def test_reduced_precision_apply(p, dtype, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("keep", [True, False], ids=["reliable", "restart"])
 @pytest.mark.parametrize("dtype", [P.F32, P.BF16])
 @pytest.mark.parametrize("case", ["poisson", "q2"])
-def test_iterative_refinement(case, dtype):
+def test_iterative_refinement(case, dtype, keep):
     if case == "poisson":
         mesh, p = synth.hex_lattice(8, 0.1, seed=1), 2
     else:
@@ -71,7 +72,7 @@ def test_iterative_refinement(case, dtype):
     hi = P.Operator(S, P.DIFFUSION, qd)
     lo = P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, dtype), qdata_dtype=dtype)
     b = S.linear_form(P.SOURCE_SINE)
-    x, info = hi.ir_solve(lo, b, rel_tol=1e-10, inner_rel_tol=1e-2)
+    x, info = hi.ir_solve(lo, b, rel_tol=1e-10, inner_rel_tol=1e-2, keep_direction=keep)
     assert info["status"] == "OK" and info["converged"] and info["rel_res"] <= 1e-10
     # the residual history is monotone and the reported residual is the FP64 one
     h = info["history"]
@@ -82,7 +83,7 @@ def test_iterative_refinement(case, dtype):
     perm = match_by_coords(X, ref.coords)
     xd = spla.spsolve(ref.Kc.tocsc(), ref.load(synth.sine_source))
     err = rel_err(x.cpu().numpy(), xd[perm])
-    print(f"{case} {'f32' if dtype == P.F32 else 'bf16'}: {info['outer']} steps, "
+    print(f"{case} {'f32' if dtype == P.F32 else 'bf16'} keep={keep}: {info['outer']} steps, "
           f"{info['inner_total']} inner its, solution rel err vs oracle {err:.2e}")
     assert err <= 1e-8
 
@@ -97,3 +98,31 @@ def test_refinement_reports_nonconvergence():
     x, info = hi.ir_solve(lo, b, rel_tol=1e-14, max_outer=1)
     assert info["status"] == "ENOTCONV" and info["outer"] == 1 and not info["converged"]
     assert info["rel_res"] < 1e-1
+
+
+@pytest.mark.parametrize("dtype", [P.F32, P.BF16])
+def test_reliable_update_keeps_pcg_iteration_count(dtype):
+    """With an FP32 apply, keeping the inner direction across residual replacements
+    keeps the total inner iteration count near FP64 Jacobi-PCG's (a restart every
+    step loses the Krylov space and needs more).  With a BF16 operator (apply error
+    ~4e-3) both strategies must converge to the same solution; their counts are
+    reported."""
+    mesh, p = synth.hex_lattice(12, 0.1, seed=3), 3
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    kappa = torch.as_tensor(synth.lognormal_iid(S.nelem, p + 2, 1.0, seed=4), device="cuda")
+    qd = S.qdata(P.DIFFUSION, coeff=kappa)
+    hi = P.Operator(S, P.DIFFUSION, qd)
+    lo = P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, dtype), qdata_dtype=dtype)
+    b = S.linear_form(P.SOURCE_SINE)
+    diag = hi.diagonal()
+    x64, i64 = hi.pcg(b, diag=diag, rel_tol=1e-8)
+    xk, keep = hi.ir_solve(lo, b, diag=diag, rel_tol=1e-8, keep_direction=True)
+    xr, rest = hi.ir_solve(lo, b, diag=diag, rel_tol=1e-8, keep_direction=False)
+    print(f"FP64 PCG {i64['iters']} its; reliable {keep['inner_total']} inner / {keep['outer']} "
+          f"steps; restart {rest['inner_total']} inner / {rest['outer']} steps")
+    assert keep["converged"] and rest["converged"]
+    if dtype == P.F32:
+        assert keep["inner_total"] <= 1.15 * i64["iters"] + 10
+        assert keep["inner_total"] < rest["inner_total"]
+    assert float((xk - xr).norm() / xr.norm()) < 1e-6
+    assert float((xk - x64).norm() / x64.norm()) < 1e-6

@@ -184,3 +184,26 @@ def test_small_poisson_solve():
     hist = info["history"]
     assert np.allclose(hist[:20], r["history"][:20], rtol=1e-8)
     assert oracle.l2_error(ref.space, x.cpu().numpy()[np.argsort(perm)], synth.sine_solution) < 1e-3
+
+
+def test_pcg_from_a_guess_with_boundary_values():
+    """A starting guess that is nonzero on essential dofs makes the first directions
+    nonzero there: the step length must include those rows (q_b = d_b).  The
+    iteration history follows the oracle's PCG from the same guess."""
+    mesh = synth.hex_lattice(6, 0.1, seed=2)
+    S, X, _ = _setup(mesh, 2)
+    op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION))
+    b = S.linear_form(P.SOURCE_SINE)
+    ref = OracleProblem(mesh, 2)
+    perm = match_by_coords(X, ref.coords)
+    x0_or = synth.hash_normal(ref.coords, seed=31)
+    x0 = torch.as_tensor(synth.hash_normal(X, seed=31), device="cuda")
+    assert float(x0[torch.as_tensor(S.boundary_dofs(), device="cuda").long()].abs().max()) > 0
+    x, info = op.pcg(b, x=x0.clone(), rel_tol=1e-12, max_iter=2000)
+    assert info["status"] == "OK" and info["converged"]
+    bref = ref.load(synth.sine_source)
+    r = oracle.pcg(ref.Kc, bref, ref.Kc.diagonal(), tol=1e-12, x0=x0_or)
+    print(f"guess: iters {info['iters']} oracle {r['iters']}")
+    assert abs(r["iters"] - info["iters"]) <= 2
+    assert np.allclose(info["history"][:20], r["history"][:20], rtol=1e-8)
+    assert rel_err(x.cpu().numpy(), r["x"][perm]) < 1e-10

@@ -45,18 +45,66 @@ def test_adam_closed_form_first_steps():
     np.testing.assert_allclose(P["w"], [1.0 - 0.3, -2.0 + 0.3], atol=1e-12)
 
 
-def test_zero_last_layer_is_jacobi():
-    mesh = synth.hex_lattice(3, 0.1, seed=1)
-    ref = OracleProblem(mesh, 2)
-    kappa = synth.lognormal_iid(27, 4, 1.0, seed=2)
-    kbar, feats = mlp.element_features(kappa, 4)
-    in_dim = 27 + 8
-    P = synth.mlp_init(in_dim, 16, 27, seed=3, zero_last=True)
+def _small(seed=1, n=3, p=2):
+    mesh = synth.hex_lattice(n, 0.1, seed=seed)
+    ref = OracleProblem(mesh, p)
+    E = mesh["hex"].shape[0]
+    kappa = synth.lognormal_iid(E, p + 2, 1.0, seed=seed + 1)
+    kbar, feats = mlp.element_features(kappa, p + 2)
+    nd = (p + 1) ** 3
+    P = synth.mlp_init(16, 16, 16, seed=seed + 2, zero_last=False)
+    V = np.random.default_rng(seed + 3).normal(size=(nd, 16)) / 4.0
+    return ref, feats, P, V
+
+
+def test_zero_basis_is_jacobi():
+    ref, feats, P, V = _small()
     r = np.random.default_rng(4).normal(size=ref.space.ndofs)
-    r[ref.space.boundary] = 0
     d = ref.Kc.diagonal()
-    z, _ = mlp.precondition(P, r, d, ref.space.elem_dofs, ref.space.boundary, feats, kbar, in_dim)
-    np.testing.assert_allclose(z, r / d, atol=1e-15)
+    z, _ = mlp.precondition(P, 0.0 * V, r, d, ref.space.elem_dofs, ref.space.boundary, feats, 16)
+    want = r / d
+    want[ref.space.boundary] = 0.0
+    np.testing.assert_allclose(z, want, atol=1e-15)
+
+
+def test_preconditioner_is_symmetric_with_psd_correction():
+    """Brute force: the matrix of r -> z(r) on the free dofs."""
+    ref, feats, P, V = _small(seed=5, n=2)
+    d = ref.Kc.diagonal()
+    free = np.flatnonzero(~ref.space.boundary)
+    M = np.empty((free.size, free.size))
+    for j, g in enumerate(free):
+        r = np.zeros(ref.space.ndofs)
+        r[g] = 1.0
+        z, _ = mlp.precondition(P, V, r, d, ref.space.elem_dofs, ref.space.boundary, feats, 16)
+        M[:, j] = z[free]
+    np.testing.assert_allclose(M, M.T, atol=1e-12 * np.abs(M).max())
+    corr = M - np.diag(1.0 / d[free])
+    ev = np.linalg.eigvalsh(0.5 * (corr + corr.T))
+    assert ev.min() >= -1e-12 * ev.max() and ev.max() > 0
+    # the correction has rank at most K per element
+    assert np.linalg.matrix_rank(corr, tol=1e-10 * ev.max()) <= 16 * ref.space.elem_dofs.shape[0]
+
+
+def test_preconditioner_scales_with_the_operator():
+    """Scaling A by alpha scales z by 1/alpha (dbar and diag scale together); the
+    log-ratio features do not change when the coefficient is scaled."""
+    ref, feats, P, V = _small(seed=7)
+    d = ref.Kc.diagonal()
+    r = np.random.default_rng(8).normal(size=ref.space.ndofs)
+    z1, _ = mlp.precondition(P, V, r, d, ref.space.elem_dofs, ref.space.boundary, feats, 16)
+    z2, _ = mlp.precondition(P, V, r, 250.0 * d, ref.space.elem_dofs, ref.space.boundary, feats, 16)
+    np.testing.assert_allclose(250.0 * z2, z1, rtol=1e-13, atol=1e-15)
+    kappa = synth.lognormal_iid(4, 3, 1.0, seed=9)
+    np.testing.assert_allclose(mlp.element_features(37.0 * kappa, 3)[1],
+                               mlp.element_features(kappa, 3)[1], atol=1e-13)
+
+
+def test_diag_mean_closed_form():
+    ed = np.array([[0, 1, 2, 3], [2, 3, 4, 5], [4, 5, 4, 5]])
+    bd = np.array([True, False, False, False, True, True])
+    d = np.array([10.0, 1.0, 2.0, 3.0, 20.0, 30.0])
+    np.testing.assert_allclose(mlp.diag_mean(d, ed, bd), [2.0, 2.5, 1.0])
 
 
 def test_element_features_closed_form():
@@ -76,32 +124,27 @@ def test_element_features_closed_form():
 
 
 def test_loss_gradient_finite_differences():
-    mesh = synth.hex_lattice(2, 0.1, seed=3)
-    p = 2
-    ref = OracleProblem(mesh, p)
-    kappa = synth.lognormal_iid(8, 4, 0.5, seed=5)
-    kbar, feats = mlp.element_features(kappa, 4)
-    in_dim = 27 + 8
-    P = synth.mlp_init(in_dim, 8, 27, seed=6, zero_last=False)
+    ref, feats, P, V = _small(seed=3, n=2)
     rng = np.random.default_rng(7)
+    for k in P:
+        P[k] = P[k] + 0.1 * rng.normal(size=P[k].shape)   # no dead units at zero bias
     e = rng.normal(size=ref.space.ndofs)
     e[ref.space.boundary] = 0
     A = ref.Kc
     r = A @ e
     d = A.diagonal()
-    L, G = mlp.loss_and_grads(P, A, r, e, d, ref.space.elem_dofs, ref.space.boundary, feats,
-                              kbar, in_dim)
+    args = (A, r, e, d, ref.space.elem_dofs, ref.space.boundary, feats, 16)
+    L, G = mlp.loss_and_grads(P, V, *args)
     h = 1e-6
-    for k in ("W1", "W3", "b2"):
-        flat = P[k].ravel()
+    params = dict(P, V=V)
+    for k in ("W1", "W3", "b2", "b3", "V"):
+        flat = params[k].ravel()
         for idx in rng.choice(flat.size, size=4, replace=False):
             old = flat[idx]
             flat[idx] = old + h
-            Lp, _ = mlp.loss_and_grads(P, A, r, e, d, ref.space.elem_dofs, ref.space.boundary,
-                                       feats, kbar, in_dim)
+            Lp, _ = mlp.loss_and_grads(P, V, *args)
             flat[idx] = old - h
-            Lm, _ = mlp.loss_and_grads(P, A, r, e, d, ref.space.elem_dofs, ref.space.boundary,
-                                       feats, kbar, in_dim)
+            Lm, _ = mlp.loss_and_grads(P, V, *args)
             flat[idx] = old
             fd = (Lp - Lm) / (2 * h)
             assert abs(fd - G[k].ravel()[idx]) <= 1e-5 * max(1e-3, abs(fd)), (k, idx, fd)
