@@ -248,52 +248,49 @@ def bench_batched(P, torch, nrhs=16, reps=20, tune_cache=None):
     return out
 
 
-def bench_learned(P, torch, n_train=16, n_test=64, p=3, fields=20, heldout=2, steps=1500,
-                  tol=1e-8):
-    """GRF lognormal coefficient (contrast 1e3, correlation 0.1): learned FCG vs Jacobi-PCG."""
+def bench_learned(P, torch, n=64, p=3, fields=20, heldout=3, steps=1500, tol=1e-8,
+                  stops=(2, 5, 10, 20, 40, 80, 160, 320, 640)):
+    """64^3 p = 3 lattice, GRF lognormal coefficient (contrast 1e3, correlation 0.1): the
+    learned element preconditioner is trained on pairs from Jacobi-PCG runs on seeded
+    training fields of this mesh, then FCG with it is timed against Jacobi-PCG on held-out
+    fields."""
     import synth
     from paper_1911_09220_amd import learned as L
     t0 = time.perf_counter()
-    mesh = synth.hex_lattice(n_train, 0.05, seed=21)
+    mesh = synth.hex_lattice(n, 0.05, seed=22)
     E = mesh["hex"].shape[0]
     S = P.Space(P.Mesh.from_dict(mesh), p)
-    pts = synth.lattice_quadrature_points(n_train, p + 2)
-    samples = []
-    for f in range(fields):
-        kappa = synth.grf_lognormal(pts, 0.1, 1e3, seed=1000 + f,
-                                    device="cuda").reshape(E, -1).contiguous()
+    del mesh
+    pts = synth.lattice_quadrature_points(n, p + 2)
+
+    def field(seed):
+        kappa = synth.grf_lognormal(pts, 0.1, 1e3, seed=seed, device="cuda").reshape(E, -1)
+        kappa = kappa.contiguous()
         op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kappa))
-        diag = op.diagonal()
-        feats = P.learned_features(S, kappa)
-        b = S.linear_form(P.SOURCE_SINE)
-        for r, e in L.jacobi_pairs(op, b, diag):
+        return op, op.diagonal(), P.learned_features(S, kappa)
+
+    samples = []
+    b = S.linear_form(P.SOURCE_SINE)
+    for f in range(fields):
+        op, diag, feats = field(1000 + f)
+        for r, e in L.jacobi_pairs(op, b, diag, stops=stops):
             samples.append((op, feats, diag, r, e))
-        log(f"learned: field {f + 1}/{fields}, {len(samples)} pairs")
+        log(f"learned: training field {f + 1}/{fields}, {len(samples)} pairs")
     t_pairs = time.perf_counter() - t0
-    test_mesh = synth.hex_lattice(n_test, 0.05, seed=22)
-    Et = test_mesh["hex"].shape[0]
-    St = P.Space(P.Mesh.from_dict(test_mesh), p)
-    del test_mesh
-    net = P.Net(p, hidden=64, max_rows=max(E, Et), max_train_rows=E)
+    net = P.Net(p, hidden=64, max_rows=E, max_train_rows=E)
     net.set_params(L.initial_params(net, seed=23))
     t1 = time.perf_counter()
     losses = L.train(net, samples, steps=steps, lr=2e-3, decay_every=max(1, steps // 3),
                      log_every=max(1, steps // 5), log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    out = {"order": p, "train_mesh": n_train, "train_fields": fields, "pairs": len(samples),
-           "train_steps": steps, "pair_seconds": round(t_pairs, 2),
-           "train_seconds": round(t_train, 2),
-           "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
-           "test_mesh": n_test, "test_ndofs": St.ndofs, "tol": tol, "heldout": []}
-    pts_t = synth.lattice_quadrature_points(n_test, p + 2)
+    del samples
+    out = {"order": p, "mesh": n, "ndofs": S.ndofs, "train_fields": fields,
+           "pair_stops": list(stops), "train_steps": steps, "pair_seconds": round(t_pairs, 2),
+           "train_seconds": round(t_train, 2), "loss_first": float(losses[:50].mean()),
+           "loss_last": float(losses[-50:].mean()), "tol": tol, "heldout": []}
     for f in range(heldout):
-        kappa = synth.grf_lognormal(pts_t, 0.1, 1e3, seed=2000 + f,
-                                    device="cuda").reshape(Et, -1).contiguous()
-        op = P.Operator(St, P.DIFFUSION, St.qdata(P.DIFFUSION, coeff=kappa))
-        diag = op.diagonal()
-        feats = P.learned_features(St, kappa)
-        b = St.linear_form(P.SOURCE_SINE)
+        op, diag, feats = field(2000 + f)
         _, ij = op.pcg(b, diag=diag, rel_tol=tol, max_iter=20000, history=False)
         log(f"learned: held-out field {f}: Jacobi-PCG {ij['iters']} its {ij['seconds']:.3f} s")
         _, il = P.fcg_solve(op, b, diag, net=net, feats=feats, rel_tol=tol, max_iter=20000,
@@ -306,7 +303,7 @@ def bench_learned(P, torch, n_train=16, n_test=64, p=3, fields=20, heldout=2, st
                             "true_rel_res": il["true_rel_res"], "fell_back": il["fell_back"]},
             "speedup": round(ij["seconds"] / il["seconds"], 3)})
         log(f"learned: held-out field {f}: FCG {il['iters']} its {il['seconds']:.3f} s")
-        del op, diag, feats, b, kappa
+        del op, diag, feats
     return out
 
 

@@ -226,6 +226,8 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     up(8, s.tile_off.data(), s.tile_off.size() * 4, "upload tile offsets");
     up(9, s.tile_dofs.data(), s.tile_dofs.size() * 4, "upload tile dofs");
     up(10, s.tile_slot.data(), s.tile_slot.size() * 2, "upload tile slots");
+    const std::vector<float> tables32(s.tables.begin(), s.tables.end());
+    up(11, tables32.data(), tables32.size() * 4, "upload FP32 tables");
     hip_check(hipStreamSynchronize(st), "upload sync");
     s.dev_buf = device_buf;
     s.dev_bytes = nbytes;
@@ -240,6 +242,7 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     s.dev.tile_off = reinterpret_cast<const int32_t*>(base + off[8]);
     s.dev.tile_dofs = reinterpret_cast<const int32_t*>(base + off[9]);
     s.dev.tile_slot = reinterpret_cast<const uint16_t*>(base + off[10]);
+    s.dev.tables32 = reinterpret_cast<const float*>(base + off[11]);
     s.dev.ne = s.ne;
     s.dev.ndofs = s.ndofs;
     s.dev.p = s.p;
@@ -471,7 +474,7 @@ pafem_status pafem_convert(int64_t n, const double* src, void* dst, int32_t dtyp
 namespace {
 
 struct IRLayout {
-  size_t state_hi, state_lo, partials, r64, q64, dx32, d32, q32, dinv32, dotp, opwork, total;
+  size_t state_hi, state_lo, partials, r64, q64, d32, q32, dinv32, dotp, opwork, total;
 };
 
 IRLayout ir_layout(const Op& hi, const Op& lo) {
@@ -483,7 +486,6 @@ IRLayout ir_layout(const Op& hi, const Op& lo) {
   L.partials = o; o += align256(4 * kCGBlocks * sizeof(double));
   L.r64 = o; o += align256(n * 8);
   L.q64 = o; o += align256(n * 8);
-  L.dx32 = o; o += align256(n * 4);
   L.d32 = o; o += align256(n * 4);
   L.q32 = o; o += align256(n * 4);
   L.dinv32 = o; o += align256(n * 4);
@@ -538,7 +540,6 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
     auto* partials = reinterpret_cast<double*>(w + L.partials);
     auto* r64 = reinterpret_cast<double*>(w + L.r64);
     auto* q64 = reinterpret_cast<double*>(w + L.q64);
-    auto* dx32 = reinterpret_cast<float*>(w + L.dx32);
     auto* d32 = reinterpret_cast<float*>(w + L.d32);
     auto* q32 = reinterpret_cast<float*>(w + L.q32);
     auto* dinv = opts->precond == PAFEM_PRECOND_JACOBI ? reinterpret_cast<float*>(w + L.dinv32)
@@ -568,9 +569,8 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
     bool restart = true;  // the inner PCG (re)starts from d = z on r / s
     while (!converged && outer < opts->max_outer) {
       if (restart)
-        launch_ir_start(st_lo, partials, r64, s, dinv, d32, dx32, q32, ess, opts->inner_rel_tol,
-                        n, st);
-      // inner: Jacobi-PCG on A_lo dx = r / ||r|| with the reduced-precision apply
+        launch_ir_start(st_lo, partials, r64, s, dinv, d32, q32, ess, opts->inner_rel_tol, n, st);
+      // inner: Jacobi-PCG on A_lo d = r / ||r|| with the reduced-precision apply, x += ||r|| d
       int launched = 0;
       CGState hl{};
       while (true) {
@@ -582,7 +582,7 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
         for (int k = 0; k < batch; ++k) {
           apply_op(lo, d32, q32, opwork, st, dotp, /*y_ready=*/true);
           launch_cg_alpha<float>(st_lo, partials, dotp, nap, ess, d32, n, st);
-          launch_ir_update(st_lo, partials, dx32, r64, d32, q32, dinv, n, st);
+          launch_ir_update(st_lo, partials, x, s, r64, d32, q32, dinv, n, st);
           launch_ir_direction(st_lo, r64, dinv, d32, q32, ess, n, st);
         }
         launched += batch;
@@ -590,7 +590,6 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
       // the inner iteration counter restarts with the inner PCG and continues otherwise
       inner_total += hl.iter - (restart ? 0 : inner_seen);
       inner_seen = hl.iter;
-      launch_ir_correct(x, dx32, s, n, st);
       ++outer;
       // FP64 residual of the refined iterate, into the inner residual's buffer
       apply_op(hi, x, q64, opwork, st);
@@ -606,8 +605,7 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
       const double s_new = std::sqrt(rr);
       restart = !(opts->keep_direction && hl.done == 1);
       if (!restart) {
-        launch_ir_replace(st_lo, partials, r64, s_new, dinv, d32, q32, dx32, opts->inner_rel_tol,
-                          n, st);
+        launch_ir_replace(st_lo, partials, r64, s_new, dinv, d32, q32, opts->inner_rel_tol, n, st);
         launch_ir_direction(st_lo, r64, dinv, d32, q32, ess, n, st);
       }
       s = s_new;

@@ -146,11 +146,12 @@ void Batch::launch_group(const Group& g, hipStream_t st) const {
   const Op* o = ops[order[g.first]];
   const DevSpace& sp = o->space->dev;
   const int Q = g.p + 2, D = g.p + 1;
-  const double* tab = sp.tables + table_offset_doubles(Q, D, sp.ng);
-  const double* tabB = tab + 2 * Q;
-  const double* tabG = tabB + Q * D;
+  // the 1D tables B (then G) of this order, in the compute precision
+  const size_t off = table_offset_doubles(Q, D, sp.ng) + 2 * Q;
+  const void* tabB = vdtype == PAFEM_F64 ? static_cast<const void*>(sp.tables + off)
+                                         : static_cast<const void*>(sp.tables32 + off);
   if (!launch_batch_apply(g.p, g.cand, vdtype, qdtype, kind, d_meshes + g.first, g.count,
-                          group_blocks(g), tabB, tabG, nrhs, st))
+                          group_blocks(g), tabB, nrhs, st))
     throw Error(PAFEM_EUNSUPPORTED, "batched kernel not built for order " + std::to_string(g.p));
 }
 

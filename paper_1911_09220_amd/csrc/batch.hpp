@@ -26,9 +26,10 @@ int batch_tile_elems(int cand);
 int batch_tile_rhs(int cand);
 // Launches the multi-rhs apply of one order group; false if the (order,
 // candidate, dtype) combination is not built.
+// tabB: the order's 1D B table followed by its G table, in the vector dtype
 bool launch_batch_apply(int p, int cand, int vdtype, int qdtype, int kind,
-                        const BatchMesh* meshes, int nmesh, int nblocks, const double* tabB,
-                        const double* tabG, int nrhs, hipStream_t st);
+                        const BatchMesh* meshes, int nmesh, int nblocks, const void* tabB,
+                        int nrhs, hipStream_t st);
 void launch_batch_init(int vdtype, const BatchMesh* meshes, int nmesh, int nrhs, hipStream_t st);
 
 }  // namespace pafem

@@ -75,6 +75,7 @@ struct DevSpace {
   const int32_t* toff = nullptr;       // [ndofs+1] transposed map offsets
   const int32_t* tidx = nullptr;       // [ne*D^3] element-vector entries per dof (ascending)
   const double* tables = nullptr;      // 1D tables for q1d = 1..kMaxQ1d
+  const float* tables32 = nullptr;     // the same tables rounded to FP32 (FP32 kernels)
   int32_t* status = nullptr;           // [64] small device status words
   const int32_t* elem_orig = nullptr;  // [ne] caller element id of each device element
   const int32_t* tile_off = nullptr;   // [ntiles+1] offsets into tile_dofs
@@ -115,7 +116,7 @@ struct Space {
 // space.cpp
 Space* build_space(const Mesh* mesh, int order, int flags);
 void space_dof_coords(const Space& s, double* xyz);
-constexpr int kSpaceSegments = 11;
+constexpr int kSpaceSegments = 12;
 void space_device_layout(const Space& s, size_t* offsets /*[kSpaceSegments+1]*/, size_t* total);
 // host copies of every device array, in upload order
 void space_pack(const Space& s, std::vector<int32_t>& gmap_enc, std::vector<double>& gnodes,

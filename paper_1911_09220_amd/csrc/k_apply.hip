@@ -42,8 +42,8 @@ constexpr int elems_per_block() {
 template <int P, int Q, int KIND, bool EVEC, bool DOT, typename TV, typename TD, typename TC>
 __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
     pa_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
-                    const uint16_t* __restrict__ tile_slot, const double* __restrict__ tabB,
-                    const double* __restrict__ tabG, const TD* __restrict__ qd,
+                    const uint16_t* __restrict__ tile_slot, const TC* __restrict__ tabB,
+                    const TC* __restrict__ tabG, const TD* __restrict__ qd,
                     const TV* __restrict__ x, TV* __restrict__ y, double* __restrict__ dotp,
                     int ne, int constrained) {
   constexpr int D = P + 1, DD = D * D, QQ = Q * Q, QQQ = Q * Q * Q, DDD = D * D * D;
@@ -74,8 +74,8 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   // entry (c, qy, qx, dz) of the element region; the x-line outputs (a, dz, dy, qx)
   // live at c*Q + qy = a*D + dy
   auto at = [&](int c, int qy, int qx, int dz) -> TC& { return W[((c * Q + qy) * Q + qx) * LC + dz]; };
-  auto bB = [&](int q, int d) -> TC { return TC(tabB[q * D + d]); };
-  auto bG = [&](int q, int d) -> TC { return TC(tabG[q * D + d]); };
+  auto bB = [&](int q, int d) -> TC { return tabB[q * D + d]; };
+  auto bG = [&](int q, int d) -> TC { return tabG[q * D + d]; };
 
   // D for this thread's z-line (qx, qy) = r: issued first so the HBM stream
   // overlaps the gather and the forward contractions (tile-interleaved: for each
@@ -298,14 +298,26 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   }
 }
 
+// the 1D tables in the compute precision
+template <typename TC>
+const TC* table_block(const DevSpace& sp, int q1d);
+template <>
+const double* table_block<double>(const DevSpace& sp, int q1d) {
+  return sp.tables + table_offset_doubles(q1d, sp.p + 1, sp.ng);
+}
+template <>
+const float* table_block<float>(const DevSpace& sp, int q1d) {
+  return sp.tables32 + table_offset_doubles(q1d, sp.p + 1, sp.ng);
+}
+
 template <int P, int KIND, bool EVEC, bool DOT, typename TV, typename TD, typename TC>
-void launch_one(const DevSpace& sp, const double* tab, bool constrained, const void* qd,
-                const void* x, void* out, double* dotp, hipStream_t st) {
+void launch_one(const DevSpace& sp, bool constrained, const void* qd, const void* x, void* out,
+                double* dotp, hipStream_t st) {
   constexpr int Q = P + 2;
   constexpr int NE = elems_per_block<Q>();
   const int nblk = int((sp.ne + NE - 1) / NE);
-  const double* tabB = tab + 2 * Q;
-  const double* tabG = tabB + Q * (P + 1);
+  const TC* tabB = table_block<TC>(sp, Q) + 2 * Q;
+  const TC* tabG = tabB + Q * (P + 1);
   hipLaunchKernelGGL((pa_apply_kernel<P, Q, KIND, EVEC, DOT, TV, TD, TC>), dim3(nblk),
                      dim3(NE * Q * Q), 0, st, sp.tile_off, sp.tile_dofs, sp.tile_slot, tabB, tabG,
                      static_cast<const TD*>(qd), static_cast<const TV*>(x),
@@ -313,51 +325,45 @@ void launch_one(const DevSpace& sp, const double* tab, bool constrained, const v
 }
 
 template <int P, int KIND, typename TV, typename TD, typename TC>
-void launch_mode(const DevSpace& sp, const double* tab, bool constrained, bool evec,
-                 const void* qd, const void* x, void* out, double* dotp, hipStream_t st) {
+void launch_mode(const DevSpace& sp, bool constrained, bool evec, const void* qd, const void* x,
+                 void* out, double* dotp, hipStream_t st) {
   if (evec) {
     if (dotp)
-      launch_one<P, KIND, true, true, TV, TD, TC>(sp, tab, constrained, qd, x, out, dotp, st);
+      launch_one<P, KIND, true, true, TV, TD, TC>(sp, constrained, qd, x, out, dotp, st);
     else
-      launch_one<P, KIND, true, false, TV, TD, TC>(sp, tab, constrained, qd, x, out, dotp, st);
+      launch_one<P, KIND, true, false, TV, TD, TC>(sp, constrained, qd, x, out, dotp, st);
   } else {
     if (dotp)
-      launch_one<P, KIND, false, true, TV, TD, TC>(sp, tab, constrained, qd, x, out, dotp, st);
+      launch_one<P, KIND, false, true, TV, TD, TC>(sp, constrained, qd, x, out, dotp, st);
     else
-      launch_one<P, KIND, false, false, TV, TD, TC>(sp, tab, constrained, qd, x, out, dotp, st);
+      launch_one<P, KIND, false, false, TV, TD, TC>(sp, constrained, qd, x, out, dotp, st);
   }
 }
 
 template <int P>
-bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, const double* tab,
-                  bool constrained, bool evec, const void* qd, const void* x, void* out,
-                  double* dotp, hipStream_t st) {
+bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, bool constrained,
+                  bool evec, const void* qd, const void* x, void* out, double* dotp,
+                  hipStream_t st) {
   const bool diff = kind == PAFEM_DIFFUSION;
   if (vdtype == PAFEM_F64 && qdtype == PAFEM_F64) {
     if (diff)
-      launch_mode<P, PAFEM_DIFFUSION, double, double, double>(sp, tab, constrained, evec, qd, x,
-                                                              out, dotp, st);
+      launch_mode<P, PAFEM_DIFFUSION, double, double, double>(sp, constrained, evec, qd, x, out, dotp, st);
     else
-      launch_mode<P, PAFEM_MASS, double, double, double>(sp, tab, constrained, evec, qd, x, out,
-                                                         dotp, st);
+      launch_mode<P, PAFEM_MASS, double, double, double>(sp, constrained, evec, qd, x, out, dotp, st);
     return true;
   }
   if (vdtype == PAFEM_F32 && qdtype == PAFEM_F32) {
     if (diff)
-      launch_mode<P, PAFEM_DIFFUSION, float, float, float>(sp, tab, constrained, evec, qd, x, out,
-                                                           dotp, st);
+      launch_mode<P, PAFEM_DIFFUSION, float, float, float>(sp, constrained, evec, qd, x, out, dotp, st);
     else
-      launch_mode<P, PAFEM_MASS, float, float, float>(sp, tab, constrained, evec, qd, x, out,
-                                                      dotp, st);
+      launch_mode<P, PAFEM_MASS, float, float, float>(sp, constrained, evec, qd, x, out, dotp, st);
     return true;
   }
   if (vdtype == PAFEM_F32 && qdtype == PAFEM_BF16) {
     if (diff)
-      launch_mode<P, PAFEM_DIFFUSION, float, bf16, float>(sp, tab, constrained, evec, qd, x, out,
-                                                          dotp, st);
+      launch_mode<P, PAFEM_DIFFUSION, float, bf16, float>(sp, constrained, evec, qd, x, out, dotp, st);
     else
-      launch_mode<P, PAFEM_MASS, float, bf16, float>(sp, tab, constrained, evec, qd, x, out, dotp,
-                                                     st);
+      launch_mode<P, PAFEM_MASS, float, bf16, float>(sp, constrained, evec, qd, x, out, dotp, st);
     return true;
   }
   return false;
@@ -373,12 +379,10 @@ bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool con
                      bool evec, const void* qd, const void* x, void* out, int vdtype,
                      hipStream_t st, double* dotp) {
   if (q1d != sp.p + 2) return false;
-  const double* tab = sp.tables + table_offset_doubles(q1d, sp.p + 1, sp.ng);
   bool ok = false;
 #define PAFEM_ORDER_CASE(P_)                                                                   \
   case P_:                                                                                     \
-    ok = launch_order<P_>(sp, kind, qdtype, vdtype, tab, constrained, evec, qd, x, out, dotp, \
-                          st);                                                                 \
+    ok = launch_order<P_>(sp, kind, qdtype, vdtype, constrained, evec, qd, x, out, dotp, st); \
     break;
   switch (sp.p) {
     PAFEM_ORDER_CASE(1)

@@ -21,8 +21,7 @@ namespace {
 template <int P, int Q, int NE, int NRB, int KIND, typename TV, typename TD, typename TC>
 __global__ void __launch_bounds__(NE * Q * Q * NRB)
     pa_apply_mrhs_kernel(const BatchMesh* __restrict__ meshes, int nmesh,
-                         const double* __restrict__ tabB, const double* __restrict__ tabG,
-                         int nrhs) {
+                         const TC* __restrict__ tabB, const TC* __restrict__ tabG, int nrhs) {
   constexpr int D = P + 1, DD = D * D, QQ = Q * Q;
   constexpr bool DIFF = (KIND == PAFEM_DIFFUSION);
   constexpr int NC = DIFF ? 6 : 1;
@@ -53,8 +52,8 @@ __global__ void __launch_bounds__(NE * Q * Q * NRB)
   auto at = [&](int c, int qy, int qx, int dz) -> TC& {
     return W[(((c * Q + qy) * Q + qx) * D + dz) * NRB];
   };
-  auto bB = [&](int q, int d) -> TC { return TC(tabB[q * D + d]); };
-  auto bG = [&](int q, int d) -> TC { return TC(tabG[q * D + d]); };
+  auto bB = [&](int q, int d) -> TC { return tabB[q * D + d]; };
+  auto bG = [&](int q, int d) -> TC { return tabG[q * D + d]; };
 
   // D of this thread's z-line (qy, qx) = r, reused for every chunk of right-hand sides
   TC dq[Q][NC];
@@ -248,9 +247,11 @@ __global__ void batch_init_kernel(const BatchMesh* __restrict__ meshes, int nrhs
 }
 
 template <int P, int NE, int NRB, typename TV, typename TD, typename TC>
-void launch_cfg(const BatchMesh* meshes, int nmesh, int nblocks, int kind, const double* tabB,
-                const double* tabG, int nrhs, hipStream_t st) {
+void launch_cfg(const BatchMesh* meshes, int nmesh, int nblocks, int kind, const void* tab,
+                int nrhs, hipStream_t st) {
   constexpr int Q = P + 2;
+  const TC* tabB = static_cast<const TC*>(tab);
+  const TC* tabG = tabB + Q * (P + 1);
   if (kind == PAFEM_DIFFUSION)
     hipLaunchKernelGGL((pa_apply_mrhs_kernel<P, Q, NE, NRB, PAFEM_DIFFUSION, TV, TD, TC>),
                        dim3(nblocks), dim3(NE * Q * Q * NRB), 0, st, meshes, nmesh, tabB, tabG,
@@ -265,30 +266,30 @@ void launch_cfg(const BatchMesh* meshes, int nmesh, int nblocks, int kind, const
 // by 1024 threads per workgroup and the LDS of the FP64 diffusion variant.
 template <int P, typename TV, typename TD, typename TC>
 bool launch_tile(int cand, const BatchMesh* meshes, int nmesh, int nblocks, int kind,
-                 const double* tabB, const double* tabG, int nrhs, hipStream_t st) {
+                 const void* tab, int nrhs, hipStream_t st) {
   if (cand == 0) {
-    launch_cfg<P, 1, 4, TV, TD, TC>(meshes, nmesh, nblocks, kind, tabB, tabG, nrhs, st);
+    launch_cfg<P, 1, 4, TV, TD, TC>(meshes, nmesh, nblocks, kind, tab, nrhs, st);
     return true;
   }
   if (cand == 4) {
-    launch_cfg<P, 1, 2, TV, TD, TC>(meshes, nmesh, nblocks, kind, tabB, tabG, nrhs, st);
+    launch_cfg<P, 1, 2, TV, TD, TC>(meshes, nmesh, nblocks, kind, tab, nrhs, st);
     return true;
   }
   if constexpr (P <= 5) {
     if (cand == 1) {
-      launch_cfg<P, 1, 8, TV, TD, TC>(meshes, nmesh, nblocks, kind, tabB, tabG, nrhs, st);
+      launch_cfg<P, 1, 8, TV, TD, TC>(meshes, nmesh, nblocks, kind, tab, nrhs, st);
       return true;
     }
   }
   if constexpr (P <= 3) {
     if (cand == 2) {
-      launch_cfg<P, 1, 16, TV, TD, TC>(meshes, nmesh, nblocks, kind, tabB, tabG, nrhs, st);
+      launch_cfg<P, 1, 16, TV, TD, TC>(meshes, nmesh, nblocks, kind, tab, nrhs, st);
       return true;
     }
   }
   if constexpr (P <= 3) {
     if (cand == 3) {
-      launch_cfg<P, 2, 8, TV, TD, TC>(meshes, nmesh, nblocks, kind, tabB, tabG, nrhs, st);
+      launch_cfg<P, 2, 8, TV, TD, TC>(meshes, nmesh, nblocks, kind, tab, nrhs, st);
       return true;
     }
   }
@@ -315,17 +316,17 @@ int batch_tile_rhs(int cand) {
 }
 
 bool launch_batch_apply(int p, int cand, int vdtype, int qdtype, int kind,
-                        const BatchMesh* meshes, int nmesh, int nblocks, const double* tabB,
-                        const double* tabG, int nrhs, hipStream_t st) {
+                        const BatchMesh* meshes, int nmesh, int nblocks, const void* tab,
+                        int nrhs, hipStream_t st) {
   bool ok = false;
 #define PAFEM_BATCH_ORDER(PP)                                                                   \
   case PP:                                                                                      \
     if (vdtype == PAFEM_F64 && qdtype == PAFEM_F64)                                             \
-      ok = launch_tile<PP, double, double, double>(cand, meshes, nmesh, nblocks, kind, tabB,    \
-                                                   tabG, nrhs, st);                             \
+      ok = launch_tile<PP, double, double, double>(cand, meshes, nmesh, nblocks, kind, tab,     \
+                                                   nrhs, st);                                   \
     else if (vdtype == PAFEM_F32 && qdtype == PAFEM_F32)                                        \
-      ok = launch_tile<PP, float, float, float>(cand, meshes, nmesh, nblocks, kind, tabB, tabG, \
-                                                nrhs, st);                                      \
+      ok = launch_tile<PP, float, float, float>(cand, meshes, nmesh, nblocks, kind, tab, nrhs,  \
+                                                st);                                            \
     break;
   switch (p) {
     PAFEM_BATCH_ORDER(1)

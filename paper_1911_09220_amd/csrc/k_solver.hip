@@ -341,17 +341,13 @@ __global__ void __launch_bounds__(kCGThreads)
   }
 }
 
-__global__ void __launch_bounds__(kCGThreads)
-    ir_correct_kernel(double* __restrict__ x, const float* __restrict__ dx, double scale,
-                      int64_t n) {
-  GRID_LOOP(i, n) x[i] += scale * double(dx[i]);
-}
 
 // ---- inner PCG of iterative refinement --------------------------------------
 // The inner solve of A_lo d = r / s keeps its residual r, the preconditioned
-// residual z and all dot products in FP64; only what the reduced-precision apply
-// reads and writes is FP32: the direction d, its image q = A_lo d and the
-// correction dx accumulated since the last FP64 residual.  dinv is the Jacobi
+// residual z, all dot products and the solution x in FP64 (x += s alpha d
+// directly, so the FP64 residual b - A x that replaces r carries no rounding of
+// an intermediate correction); only what the reduced-precision apply reads and
+// writes is FP32: the direction d and its image q = A_lo d.  dinv is the Jacobi
 // preconditioner 1/diag rounded to FP32 (a preconditioner, not part of the
 // answer); null for none.  Essential rows: q_b = d_b for a constrained operator.
 
@@ -359,12 +355,11 @@ __device__ __forceinline__ double ir_z(const double* r, const float* dinv, int64
   return dinv ? r[i] * double(dinv[i]) : r[i];
 }
 
-// r *= inv_s (r holds the FP64 residual), d = z, dx = 0, q = apply init of d;
+// r *= inv_s (r holds the FP64 residual), d = z, q = apply init of d;
 // rz, rr, bb = rr, tol2 = inner_rel_tol^2 rr, iter = 0, done
 __global__ void __launch_bounds__(kCGThreads)
     ir_start_kernel(CGState* st, double* partials, double* __restrict__ r, double inv_s,
-                    const float* __restrict__ dinv, float* __restrict__ d,
-                    float* __restrict__ dx, float* __restrict__ q,
+                    const float* __restrict__ dinv, float* __restrict__ d, float* __restrict__ q,
                     const uint8_t* __restrict__ ess, double inner_rel_tol, int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   double rz = 0.0, rr = 0.0;
@@ -374,7 +369,6 @@ __global__ void __launch_bounds__(kCGThreads)
     const double zi = dinv ? ri * double(dinv[i]) : ri;
     const float di = float(zi);
     d[i] = di;
-    dx[i] = 0.0f;
     q[i] = (ess && ess[i]) ? di : 0.0f;
     rz += ri * zi;
     rr += ri * ri;
@@ -401,18 +395,18 @@ __global__ void __launch_bounds__(kCGThreads)
   }
 }
 
-// dx += alpha d; r -= alpha q (FP64); rz, rr, beta = rz / rz_old, iter, convergence
+// x += (s alpha) d; r -= alpha q (FP64); rz, rr, beta = rz / rz_old, iter, convergence
 __global__ void __launch_bounds__(kCGThreads)
-    ir_update_kernel(CGState* st, double* partials, float* __restrict__ dx,
+    ir_update_kernel(CGState* st, double* partials, double* __restrict__ x, double s,
                      double* __restrict__ r, const float* __restrict__ d,
                      const float* __restrict__ q, const float* __restrict__ dinv, int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   if (state_done(st)) return;
   const double alpha = st->alpha;
-  const float alpha_f = float(alpha);
+  const double xstep = s * alpha;
   double rz = 0.0, rr = 0.0;
   GRID_LOOP(i, n) {
-    dx[i] += alpha_f * d[i];
+    x[i] += xstep * double(d[i]);
     const double ri = r[i] - alpha * double(q[i]);
     r[i] = ri;
     const double zi = dinv ? ri * double(dinv[i]) : ri;
@@ -456,8 +450,8 @@ __global__ void __launch_bounds__(kCGThreads)
   }
 }
 
-// Residual replacement: r holds the FP64 residual b - A_hi x; scale it by 1/s_new,
-// restart dx, and continue the recurrence with the kept direction d.  The next
+// Residual replacement: r holds the FP64 residual b - A_hi x; scale it by 1/s_new
+// and continue the recurrence with the kept direction d.  The next
 // direction d' = z + beta d is made A_lo-conjugate to d using q = A_lo d of the
 // last step: beta = -(z . q) / (d . q).  Without rounding and operator mismatch this
 // is the usual beta in the new scaling (times s_old / s_new for the kept direction);
@@ -465,14 +459,12 @@ __global__ void __launch_bounds__(kCGThreads)
 __global__ void __launch_bounds__(kCGThreads)
     ir_replace_kernel(CGState* st, double* partials, double* __restrict__ r, double inv_s_new,
                       const float* __restrict__ dinv, const float* __restrict__ d,
-                      const float* __restrict__ q, float* __restrict__ dx,
-                      double inner_rel_tol, int64_t n) {
+                      const float* __restrict__ q, double inner_rel_tol, int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   double rz = 0.0, rr = 0.0, zq = 0.0, dq = 0.0;
   GRID_LOOP(i, n) {
     const double ri = r[i] * inv_s_new;
     r[i] = ri;
-    dx[i] = 0.0f;
     const double zi = dinv ? ri * double(dinv[i]) : ri;
     const double qi = double(q[i]);
     rz += ri * zi;
@@ -633,24 +625,20 @@ void launch_residual(CGState* st, double* partials, const double* b, const doubl
   check_launch("residual");
 }
 
-void launch_ir_correct(double* x, const float* dx, double scale, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(ir_correct_kernel, dim3(vec_grid(n)), dim3(kCGThreads), 0, s, x, dx, scale,
-                     n);
-  check_launch("ir_correct");
-}
 
 void launch_ir_start(CGState* st, double* partials, double* r, double s, const float* dinv,
-                     float* d, float* dx, float* q, const uint8_t* ess, double inner_rel_tol,
-                     int64_t n, hipStream_t stream) {
+                     float* d, float* q, const uint8_t* ess, double inner_rel_tol, int64_t n,
+                     hipStream_t stream) {
   hipLaunchKernelGGL(ir_start_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, stream, st, partials,
-                     r, 1.0 / s, dinv, d, dx, q, ess, inner_rel_tol, n);
+                     r, 1.0 / s, dinv, d, q, ess, inner_rel_tol, n);
   check_launch("ir_start");
 }
 
-void launch_ir_update(CGState* st, double* partials, float* dx, double* r, const float* d,
-                      const float* q, const float* dinv, int64_t n, hipStream_t stream) {
+void launch_ir_update(CGState* st, double* partials, double* x, double s, double* r,
+                      const float* d, const float* q, const float* dinv, int64_t n,
+                      hipStream_t stream) {
   hipLaunchKernelGGL(ir_update_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, stream, st,
-                     partials, dx, r, d, q, dinv, n);
+                     partials, x, s, r, d, q, dinv, n);
   check_launch("ir_update");
 }
 
@@ -662,10 +650,10 @@ void launch_ir_direction(CGState* st, const double* r, const float* dinv, float*
 }
 
 void launch_ir_replace(CGState* st, double* partials, double* r, double s_new, const float* dinv,
-                       const float* d, const float* q, float* dx, double inner_rel_tol, int64_t n,
+                       const float* d, const float* q, double inner_rel_tol, int64_t n,
                        hipStream_t stream) {
   hipLaunchKernelGGL(ir_replace_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, stream, st,
-                     partials, r, 1.0 / s_new, dinv, d, q, dx, inner_rel_tol, n);
+                     partials, r, 1.0 / s_new, dinv, d, q, inner_rel_tol, n);
   check_launch("ir_replace");
 }
 

@@ -67,28 +67,27 @@ void launch_fcg_direction(CGState* st, const double* z, double* p, int64_t n, hi
 // res2 = ||b - q||^2 and, if r is not null, r = b - q (always runs, ignores `done`)
 void launch_residual(CGState* st, double* partials, const double* b, const double* q, double* r,
                      int64_t n, hipStream_t s);
-// x += scale * dx (f64 += f32)
-void launch_ir_correct(double* x, const float* dx, double scale, int64_t n, hipStream_t s);
-// Inner PCG of iterative refinement: residual, preconditioned residual and dots in
-// FP64; direction d, its image q = A_lo d and the correction dx in FP32; dinv =
-// 1/diag in FP32 (null: no preconditioner); ess = essential mask of a constrained
-// operator (q_b = d_b) or null.  Every kernel that sets the next direction also
-// writes q's apply init, so the apply runs without its own init pass.
-// r (FP64 residual) *= 1/s; d = z; dx = 0; state restarted with tol2 = tol^2 rr
+// Inner PCG of iterative refinement: residual, preconditioned residual, dots and the
+// solution x in FP64; direction d and its image q = A_lo d in FP32; dinv = 1/diag in
+// FP32 (null: no preconditioner); ess = essential mask of a constrained operator
+// (q_b = d_b) or null.  Every kernel that sets the next direction also writes q's
+// apply init, so the apply runs without its own init pass.
+// r (FP64 residual) *= 1/s; d = z; state restarted with tol2 = tol^2 rr
 void launch_ir_start(CGState* st, double* partials, double* r, double s, const float* dinv,
-                     float* d, float* dx, float* q, const uint8_t* ess, double inner_rel_tol,
-                     int64_t n, hipStream_t stream);
-// dx += alpha d; r -= alpha q; rz, rr, beta, iter, convergence
-void launch_ir_update(CGState* st, double* partials, float* dx, double* r, const float* d,
-                      const float* q, const float* dinv, int64_t n, hipStream_t stream);
+                     float* d, float* q, const uint8_t* ess, double inner_rel_tol, int64_t n,
+                     hipStream_t stream);
+// x += (s alpha) d; r -= alpha q; rz, rr, beta, iter, convergence
+void launch_ir_update(CGState* st, double* partials, double* x, double s, double* r,
+                      const float* d, const float* q, const float* dinv, int64_t n,
+                      hipStream_t stream);
 // d = z + beta d; q = apply init of d
 void launch_ir_direction(CGState* st, const double* r, const float* dinv, float* d, float* q,
                          const uint8_t* ess, int64_t n, hipStream_t stream);
 // Reliable update after a residual replacement: r (the FP64 residual) *= 1/s_new,
-// dx = 0, beta = -(z.q)/(d.q) so that launch_ir_direction continues with a direction
+// beta = -(z.q)/(d.q) so that launch_ir_direction continues with a direction
 // conjugate to the kept one (done = 2 on breakdown).  partials: 4 * kCGBlocks.
 void launch_ir_replace(CGState* st, double* partials, double* r, double s_new, const float* dinv,
-                       const float* d, const float* q, float* dx, double inner_rel_tol, int64_t n,
+                       const float* d, const float* q, double inner_rel_tol, int64_t n,
                        hipStream_t stream);
 // dinv = 1/diag rounded to FP32
 void launch_ir_dinv(const double* diag, float* dinv, int64_t n, hipStream_t stream);

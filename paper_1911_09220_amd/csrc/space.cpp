@@ -397,6 +397,7 @@ void space_device_layout(const Space& s, size_t* off, size_t* total) {
       sizeof(int32_t) * s.tile_off.size(),         // 8 tile offsets
       sizeof(int32_t) * s.tile_dofs.size(),        // 9 tile dof lists
       sizeof(uint16_t) * s.tile_slot.size(),       // 10 tile slot maps
+      sizeof(float) * s.tables.size(),             // 11 1D tables in FP32
   };
   for (int i = 0; i < kSpaceSegments; ++i) {
     off[i] = o;
