@@ -104,13 +104,15 @@ struct LowRankShape {
 };
 
 // z += sum_E R_E^t V diag(c_E idb_E) V^t R_E r over the non-essential dofs (z holds
-// the Jacobi part on entry).  One workgroup per apply tile.
+// the Jacobi part on entry).  Persistent: each workgroup loads V into LDS once and
+// walks one contiguous range of apply tiles (ranges of the workgroups of one XCD
+// are adjacent, so tiles that share dofs share an L2).
 template <int P, int K>
 __global__ void __launch_bounds__(256)
     lowrank_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
                          const uint16_t* __restrict__ tile_slot, const float* __restrict__ V,
                          const float* __restrict__ c, const float* __restrict__ idb,
-                         const double* __restrict__ r, double* __restrict__ z, int ne) {
+                         const double* __restrict__ r, double* __restrict__ z, int ne, int ntiles) {
   using S = LowRankShape<P, K>;
   constexpr int DDD = S::DDD, NE = S::NE;
   __shared__ float sV[DDD * K];    // [i][k]
@@ -120,48 +122,53 @@ __global__ void __launch_bounds__(256)
   __shared__ float sT[NE * K];
   __shared__ uint16_t sSlot[NE * DDD];
   const int tid = threadIdx.x;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int e0 = tile * NE;
-  const int nel = min(NE, ne - e0);
-  const int u0 = tile_off[tile];
-  const int nu = tile_off[tile + 1] - u0;
   for (int j = tid; j < DDD * K; j += 256) {
     const float v = V[j];
     sV[j] = v;
     sVt[(j % K) * DDD + j / K] = v;
   }
-  for (int s = tid; s < nu; s += 256) {
-    const int g = tile_dofs[u0 + s];
-    sU[s] = g < 0 ? 0.f : float(r[g]);
-  }
-  for (int j = tid; j < nel * DDD; j += 256) sSlot[j] = tile_slot[size_t(e0) * DDD + j];
-  __syncthreads();
-  for (int j = tid; j < nel * DDD; j += 256) sRE[j] = sU[sSlot[j]];
-  __syncthreads();
-  for (int s = tid; s < nu; s += 256) sU[s] = 0.f;
-  // t = V^t r_E, scaled by c_E / dbar_E
-  for (int j = tid; j < nel * K; j += 256) {
-    const int el = j / K, k = j - el * K;
-    const float* re = sRE + el * DDD;
-    float acc = 0.f;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int t0 = b * per, t1 = min(ntiles, t0 + per);
+  for (int tile = t0; tile < t1; ++tile) {
+    const int e0 = tile * NE;
+    const int nel = min(NE, ne - e0);
+    const int u0 = tile_off[tile];
+    const int nu = tile_off[tile + 1] - u0;
+    __syncthreads();  // V is in place; the previous tile's outputs are out
+    for (int s = tid; s < nu; s += 256) {
+      const int g = tile_dofs[u0 + s];
+      sU[s] = g < 0 ? 0.f : float(r[g]);
+    }
+    for (int j = tid; j < nel * DDD; j += 256) sSlot[j] = tile_slot[size_t(e0) * DDD + j];
+    __syncthreads();
+    for (int j = tid; j < nel * DDD; j += 256) sRE[j] = sU[sSlot[j]];
+    __syncthreads();
+    for (int s = tid; s < nu; s += 256) sU[s] = 0.f;
+    // t = V^t r_E, scaled by c_E / dbar_E
+    for (int j = tid; j < nel * K; j += 256) {
+      const int el = j / K, k = j - el * K;
+      const float* re = sRE + el * DDD;
+      float acc = 0.f;
 #pragma unroll 8
-    for (int i = 0; i < DDD; ++i) acc += sV[i * K + k] * re[i];
-    sT[j] = acc * c[size_t(e0 + el) * K + k] * idb[e0 + el];
-  }
-  __syncthreads();
-  // y_E = V t, summed per unique dof
-  for (int j = tid; j < nel * DDD; j += 256) {
-    const int el = j / DDD, i = j - el * DDD;
-    const float* t = sT + el * K;
-    float acc = 0.f;
+      for (int i = 0; i < DDD; ++i) acc += sV[i * K + k] * re[i];
+      sT[j] = acc * c[size_t(e0 + el) * K + k] * idb[e0 + el];
+    }
+    __syncthreads();
+    // y_E = V t, summed per unique dof
+    for (int j = tid; j < nel * DDD; j += 256) {
+      const int el = j / DDD, i = j - el * DDD;
+      const float* t = sT + el * K;
+      float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc += sVt[k * DDD + i] * t[k];
-    atomicAdd(&sU[sSlot[j]], acc);
-  }
-  __syncthreads();
-  for (int s = tid; s < nu; s += 256) {
-    const int g = tile_dofs[u0 + s];
-    if (g >= 0) unsafeAtomicAdd(&z[g], double(sU[s]));
+      for (int k = 0; k < K; ++k) acc += sVt[k * DDD + i] * t[k];
+      atomicAdd(&sU[sSlot[j]], acc);
+    }
+    __syncthreads();
+    for (int s = tid; s < nu; s += 256) {
+      const int g = tile_dofs[u0 + s];
+      if (g >= 0) unsafeAtomicAdd(&z[g], double(sU[s]));
+    }
   }
 }
 
@@ -318,8 +325,10 @@ void lowrank_apply_p(const DevSpace& sp, const float* V, const float* c, const f
                      const double* r, double* z, hipStream_t st) {
   if (sp.tile_ne != LowRankShape<P, kLowRank>::NE)
     throw Error(PAFEM_EINVAL, "low-rank apply: tile size differs from the apply tiles");
-  hipLaunchKernelGGL((lowrank_apply_kernel<P, kLowRank>), dim3(ntiles_of(sp)), dim3(256), 0, st,
-                     sp.tile_off, sp.tile_dofs, sp.tile_slot, V, c, idb, r, z, int(sp.ne));
+  const int nt = ntiles_of(sp);
+  hipLaunchKernelGGL((lowrank_apply_kernel<P, kLowRank>), dim3(std::min(nt, kLowRankApplyBlocks)),
+                     dim3(256), 0, st, sp.tile_off, sp.tile_dofs, sp.tile_slot, V, c, idb, r, z,
+                     int(sp.ne), nt);
 }
 
 template <int P>

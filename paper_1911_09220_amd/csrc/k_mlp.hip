@@ -154,15 +154,29 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// grad[i] = sum over blocks of part[blk][i] (fixed order)
-__global__ void reduce_parts_kernel(const float* __restrict__ part, float* __restrict__ grad,
-                                    int nblk, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[size_t(b) * n + i];
-    grad[i] = s;
+// grad[i] = sum over blocks of part[blk][i], in a fixed order: a workgroup takes
+// kRedEntries consecutive entries; lane group j (kRedLanes of them) sums the blocks
+// b = j, j + kRedLanes, ... and the groups' sums are added in index order.
+constexpr int kRedEntries = 32, kRedLanes = 8;  // kRedEntries * kRedLanes = 256 threads
+__global__ void __launch_bounds__(256)
+    reduce_parts_kernel(const float* __restrict__ part, float* __restrict__ grad, int nblk,
+                        int n) {
+  __shared__ float sp[kRedLanes][kRedEntries];
+  const int e = threadIdx.x % kRedEntries, j = threadIdx.x / kRedEntries;
+  const int i = blockIdx.x * kRedEntries + e;
+  float s = 0.f;
+  if (i < n)
+    for (int b = j; b < nblk; b += kRedLanes) s += part[size_t(b) * n + i];
+  sp[j][e] = s;
+  __syncthreads();
+  if (j == 0 && i < n) {
+    float t = sp[0][e];
+    for (int k = 1; k < kRedLanes; ++k) t += sp[k][e];
+    grad[i] = t;
   }
 }
+
+int reduce_grid(int n) { return (n + kRedEntries - 1) / kRedEntries; }
 
 // Adam on the FP32 master parameters, then refresh the bf16 copies (weights and
 // the transposed weights used by the input-gradient GEMMs).
@@ -238,14 +252,16 @@ void launch_gemm_wgrad(const uint16_t* Z, const uint16_t* X, float* part, float*
   const size_t lds = sizeof(uint16_t) * size_t(kWgradRows) * (N + K);
   hipLaunchKernelGGL(gemm_wgrad_kernel, dim3(nblk), dim3(256), lds, st, Z, X, part, partb, M, N, K);
   check("gemm_wgrad");
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid1d(N * K)), dim3(256), 0, st, part, gW, nblk,
-                     N * K);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, partb, gb, nblk, N);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(reduce_grid(N * K)), dim3(256), 0, st, part, gW,
+                     nblk, N * K);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(reduce_grid(N)), dim3(256), 0, st, partb, gb, nblk,
+                     N);
   check("reduce_parts");
 }
 
 void launch_reduce_parts(const float* part, float* out, int nblk, int n, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid1d(n)), dim3(256), 0, st, part, out, nblk, n);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(reduce_grid(n)), dim3(256), 0, st, part, out, nblk,
+                     n);
   check("reduce_parts");
 }
 

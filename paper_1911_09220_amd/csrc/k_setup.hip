@@ -251,12 +251,53 @@ __global__ void evec_gather_kernel(const int32_t* __restrict__ toff,
 
 template <typename T>
 __global__ void scatter_init_kernel(const uint8_t* __restrict__ bmask, const T* __restrict__ x,
-                                    int constrained, T* __restrict__ y, int64_t n) {
+                                    int constrained, T* __restrict__ y, int64_t begin, int64_t n) {
 #pragma unroll 4
-  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n;
+  for (int64_t g = begin + blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < n;
        g += int64_t(gridDim.x) * blockDim.x)
     y[g] = (constrained && bmask[g]) ? x[g] : T(0);
 }
+
+// Four dofs per thread: one 4-byte mask load and 16-byte stores (vectors aligned to
+// 16 bytes, mask to 4).  Covers [0, 4 * n4).
+__global__ void scatter_init_f64x4_kernel(const uint32_t* __restrict__ mask4,
+                                          const double2* __restrict__ x2, int constrained,
+                                          double2* __restrict__ y2, int64_t n4) {
+  for (int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; w < n4;
+       w += int64_t(gridDim.x) * blockDim.x) {
+    const uint32_t m = constrained ? mask4[w] : 0u;
+    double2 lo = {0.0, 0.0}, hi = {0.0, 0.0};
+    if (m) {
+      const double2 xl = x2[2 * w], xh = x2[2 * w + 1];
+      lo.x = (m & 0xffu) ? xl.x : 0.0;
+      lo.y = (m & 0xff00u) ? xl.y : 0.0;
+      hi.x = (m & 0xff0000u) ? xh.x : 0.0;
+      hi.y = (m & 0xff000000u) ? xh.y : 0.0;
+    }
+    y2[2 * w] = lo;
+    y2[2 * w + 1] = hi;
+  }
+}
+
+__global__ void scatter_init_f32x4_kernel(const uint32_t* __restrict__ mask4,
+                                          const float4* __restrict__ x4, int constrained,
+                                          float4* __restrict__ y4, int64_t n4) {
+  for (int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; w < n4;
+       w += int64_t(gridDim.x) * blockDim.x) {
+    const uint32_t m = constrained ? mask4[w] : 0u;
+    float4 v = {0.f, 0.f, 0.f, 0.f};
+    if (m) {
+      const float4 xv = x4[w];
+      v.x = (m & 0xffu) ? xv.x : 0.f;
+      v.y = (m & 0xff00u) ? xv.y : 0.f;
+      v.z = (m & 0xff0000u) ? xv.z : 0.f;
+      v.w = (m & 0xff000000u) ? xv.w : 0.f;
+    }
+    y4[w] = v;
+  }
+}
+
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
 int grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
@@ -314,15 +355,39 @@ void launch_evec_gather_f32(const DevSpace& sp, const float* ye, const float* x,
 
 void launch_scatter_init(const DevSpace& sp, const double* x, bool constrained, double* y,
                          hipStream_t st) {
-  hipLaunchKernelGGL(scatter_init_kernel<double>, dim3(grid_for(sp.ndofs, 256)), dim3(256), 0, st,
-                     sp.bmask, x, int(constrained), y, sp.ndofs);
+  const int64_t n = sp.ndofs;
+  int64_t done = 0;
+  if (aligned(x, 16) && aligned(y, 16) && aligned(sp.bmask, 4)) {
+    const int64_t n4 = n / 4;
+    if (n4 > 0)
+      hipLaunchKernelGGL(scatter_init_f64x4_kernel, dim3(grid_for(n4, 256)), dim3(256), 0, st,
+                         reinterpret_cast<const uint32_t*>(sp.bmask),
+                         reinterpret_cast<const double2*>(x), int(constrained),
+                         reinterpret_cast<double2*>(y), n4);
+    done = 4 * n4;
+  }
+  if (done < n)
+    hipLaunchKernelGGL(scatter_init_kernel<double>, dim3(grid_for(n - done, 256)), dim3(256), 0,
+                       st, sp.bmask, x, int(constrained), y, done, n);
   HIP_LAUNCH_CHECK();
 }
 
 void launch_scatter_init_f32(const DevSpace& sp, const float* x, bool constrained, float* y,
                              hipStream_t st) {
-  hipLaunchKernelGGL(scatter_init_kernel<float>, dim3(grid_for(sp.ndofs, 256)), dim3(256), 0, st,
-                     sp.bmask, x, int(constrained), y, sp.ndofs);
+  const int64_t n = sp.ndofs;
+  int64_t done = 0;
+  if (aligned(x, 16) && aligned(y, 16) && aligned(sp.bmask, 4)) {
+    const int64_t n4 = n / 4;
+    if (n4 > 0)
+      hipLaunchKernelGGL(scatter_init_f32x4_kernel, dim3(grid_for(n4, 256)), dim3(256), 0, st,
+                         reinterpret_cast<const uint32_t*>(sp.bmask),
+                         reinterpret_cast<const float4*>(x), int(constrained),
+                         reinterpret_cast<float4*>(y), n4);
+    done = 4 * n4;
+  }
+  if (done < n)
+    hipLaunchKernelGGL(scatter_init_kernel<float>, dim3(grid_for(n - done, 256)), dim3(256), 0,
+                       st, sp.bmask, x, int(constrained), y, done, n);
   HIP_LAUNCH_CHECK();
 }
 

@@ -250,11 +250,14 @@ __global__ void __launch_bounds__(kCGThreads)
   }
 }
 
-// x += alpha p; r -= alpha q; rr, iteration count, history, convergence
+// x += alpha p; r -= alpha q; zj = r / diag (0 on essential dofs: the Jacobi part of
+// the next preconditioned residual); rr, iteration count, history, convergence
 __global__ void __launch_bounds__(kCGThreads)
     fcg_update_kernel(CGState* st, double* partials, double* __restrict__ x,
                       double* __restrict__ r, const double* __restrict__ p,
-                      const double* __restrict__ q, double* hist, int64_t n) {
+                      const double* __restrict__ q, const double* __restrict__ diag,
+                      const uint8_t* __restrict__ bmask, double* __restrict__ zj, double* hist,
+                      int64_t n) {
   __shared__ double scratch[kCGThreads / kWave];
   if (state_done(st)) return;
   const double alpha = st->alpha;
@@ -263,6 +266,7 @@ __global__ void __launch_bounds__(kCGThreads)
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
+    zj[i] = bmask[i] ? 0.0 : ri / diag[i];
     rr += ri * ri;
   }
   rr = block_sum(rr, scratch);
@@ -602,9 +606,10 @@ void launch_fcg_start(CGState* st, double* partials, const double* r, const doub
   check_launch("fcg_start");
 }
 void launch_fcg_update(CGState* st, double* partials, double* x, double* r, const double* p,
-                       const double* q, double* hist, int64_t n, hipStream_t s) {
+                       const double* q, const double* diag, const uint8_t* bmask, double* zj,
+                       double* hist, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fcg_update_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, partials, x,
-                     r, p, q, hist, n);
+                     r, p, q, diag, bmask, zj, hist, n);
   check_launch("fcg_update");
 }
 void launch_fcg_beta(CGState* st, double* partials, const double* r, const double* z,

@@ -202,13 +202,19 @@ void learned_setup(const Net& net, const Op& op, const float* feats, const doubl
                         reinterpret_cast<float*>(work + W.idb), st);
 }
 
+// z += the low-rank correction of r, with the element weights of the last learned_setup
+void learned_correct(const Net& net, const Op& op, const double* r, double* z, char* work,
+                     const LearnedLayout& W, hipStream_t st) {
+  launch_lowrank_apply(op.space->dev, net.params() + net.d.oV,
+                       reinterpret_cast<const float*>(work + W.c),
+                       reinterpret_cast<const float*>(work + W.idb), r, z, st);
+}
+
 // z = M(r) with the element weights of the last learned_setup
 void learned_apply(const Net& net, const Op& op, const double* diag, const double* r, double* z,
                    char* work, const LearnedLayout& W, hipStream_t st) {
-  const DevSpace& sp = op.space->dev;
-  launch_jacobi(sp, r, diag, z, st);
-  launch_lowrank_apply(sp, net.params() + net.d.oV, reinterpret_cast<const float*>(work + W.c),
-                       reinterpret_cast<const float*>(work + W.idb), r, z, st);
+  launch_jacobi(op.space->dev, r, diag, z, st);
+  learned_correct(net, op, r, z, work, W, st);
 }
 
 }  // namespace
@@ -489,8 +495,9 @@ pafem_status fcg_solve(const Op& op, Net* net, const float* feats, const double*
     for (int k = 0; k < batch; ++k) {
       apply_op(op, p, q, lw + LW.opwork, st, dotp);
       launch_cg_alpha<double>(state, partials, dotp, nap, ess, p, n, st);
-      launch_fcg_update(state, partials, x, r, p, q, hist, n, st);
-      precond(r, zold);  // new z into the spare buffer
+      // new z into the spare buffer: the update writes its Jacobi part
+      launch_fcg_update(state, partials, x, r, p, q, diag, sp.bmask, zold, hist, n, st);
+      if (use_net) learned_correct(*net, op, r, zold, lw, LW, st);
       launch_fcg_beta(state, partials, r, zold, z, n, st);
       launch_fcg_direction(state, zold, p, n, st);
       std::swap(z, zold);

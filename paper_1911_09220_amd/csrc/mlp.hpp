@@ -33,6 +33,7 @@ void launch_reduce_parts(const float* part, float* out, int nblk, int n, hipStre
 // ---- learned preconditioner (k_learned.hip) ----
 constexpr int kLowRank = 16;            // columns of the learned element basis V
 constexpr int kLowRankGradBlocks = 256;  // workgroups of the basis-gradient reduction
+constexpr int kLowRankApplyBlocks = 2048;  // persistent workgroups of the per-iteration apply
 
 // feats[e] = {kbar_e, 8 octant log-ratios} per device element, from kappa [E][Q^3]
 // in caller element order (NULL: kbar = 1, ratios 0).

@@ -59,8 +59,11 @@ void launch_fcg_init(CGState* st, double* partials, const double* b, const doubl
                      hipStream_t s);
 void launch_fcg_start(CGState* st, double* partials, const double* r, const double* z, double* p,
                       int64_t n, hipStream_t s);
+// x += alpha p; r -= alpha q; zj = r / diag (0 where bmask): the Jacobi part of the
+// next preconditioned residual
 void launch_fcg_update(CGState* st, double* partials, double* x, double* r, const double* p,
-                       const double* q, double* hist, int64_t n, hipStream_t s);
+                       const double* q, const double* diag, const uint8_t* bmask, double* zj,
+                       double* hist, int64_t n, hipStream_t s);
 void launch_fcg_beta(CGState* st, double* partials, const double* r, const double* z,
                      const double* zold, int64_t n, hipStream_t s);
 void launch_fcg_direction(CGState* st, const double* z, double* p, int64_t n, hipStream_t s);

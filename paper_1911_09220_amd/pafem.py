@@ -404,10 +404,14 @@ class Operator:
         flags = (OP_CONSTRAINED if constrained else 0) | (OP_SCATTER_EVEC if scatter == "evec" else 0)
         self.handle = pafem_op_create(space.handle, kind, self.q1d, qdata, qdata_dtype, flags)
         self.work = _device_bytes(pafem_op_workspace_bytes(self.handle), space.device)
+        self.vec_dtype = "float64" if qdata_dtype == F64 else "float32"
 
-    def _check_vec(self, v, name):
-        if v.numel() != self.space.ndofs or not v.is_contiguous() or not v.is_cuda:
-            raise ValueError(f"{name} must be a contiguous device vector of {self.space.ndofs}")
+    def _check_vec(self, v, name, dtype=None):
+        want = self.vec_dtype if dtype is None else dtype
+        if (v.numel() != self.space.ndofs or not v.is_contiguous() or not v.is_cuda
+                or str(v.dtype) != "torch." + want):
+            raise ValueError(f"{name} must be a contiguous {want} device vector of "
+                             f"{self.space.ndofs}")
 
     def apply(self, x, y=None):
         import torch
