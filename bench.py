@@ -29,8 +29,9 @@ FP64_PEAK_TFLOPS = 78.6
 METRIC = "PA diffusion apply GDOF/s (p=1–8); CG time-to-1e-8, chosen vs plain FP64"
 
 
-APPLY_SOURCES = ("paper_1911_09220_amd/csrc/k_apply.hip", "paper_1911_09220_amd/csrc/device.hpp",
-                 "paper_1911_09220_amd/csrc/internal.hpp", "paper_1911_09220_amd/csrc/space.cpp")
+APPLY_SOURCES = ("paper_1911_09220_amd/csrc/k_apply.hip", "paper_1911_09220_amd/csrc/k_setup.hip",
+                 "paper_1911_09220_amd/csrc/device.hpp", "paper_1911_09220_amd/csrc/internal.hpp",
+                 "paper_1911_09220_amd/csrc/space.cpp")
 
 
 def log(msg: str) -> None:
