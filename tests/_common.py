@@ -6,6 +6,7 @@ matching dofs by their node coordinates (each H1 dof has a distinct node).
 import numpy as np
 
 import oracle
+import synth
 from oracle import forms
 from oracle.forms import assemble_vector
 
@@ -44,3 +45,42 @@ class OracleProblem:
 def rel_err(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _patch(n, c):
+    """Element ids of the 3x3x3 block around element c of an n^3 lattice, and c's position."""
+    cx, cy, cz = c % n, (c // n) % n, c // (n * n)
+    ids = [ix + n * (iy + n * iz)
+           for iz in range(max(cz - 1, 0), min(cz + 2, n))
+           for iy in range(max(cy - 1, 0), min(cy + 2, n))
+           for ix in range(max(cx - 1, 0), min(cx + 2, n))]
+    return ids, ids.index(c)
+
+
+def on_boundary(X):
+    """Nodes on the faces of the unit cube (the essential set)."""
+    return np.any((np.abs(X) < 1e-12) | (np.abs(X - 1.0) < 1e-12), axis=1)
+
+
+def patch_rows(mesh, kappa, p, c, kind, seed):
+    """Oracle (A x) of the constrained operator at the dofs of element c of a lattice,
+    from the 3x3x3 element block around c alone, and those dofs' coordinates.
+
+    x = synth.hash_normal(node positions, seed); essential dofs are the nodes on the
+    cube's faces: y_b = x_b there, free rows ignore essential columns."""
+    n = mesh["n"][0]
+    ids, pos = _patch(n, c)
+    sub = synth.sub_mesh(mesh, ids)
+    space = oracle.H1Space(sub, p)
+    if kind == "diffusion":
+        Ae = forms.element_stiffness(sub, p, p + 2, kappa[ids])
+    else:
+        Ae = forms.element_mass(sub, p, p + 2, kappa[ids])
+    A = oracle.assemble(space, Ae).tocsr()
+    X = space.dof_coordinates()
+    ess = on_boundary(X)
+    x = synth.hash_normal(X, seed=seed)
+    y = A @ np.where(ess, 0.0, x)
+    y = np.where(ess, x, y)
+    dofs = space.elem_dofs[pos]
+    return y[dofs], X[dofs]

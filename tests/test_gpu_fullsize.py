@@ -1,0 +1,80 @@
+"""Parity at the scale-sweep sizes: ~1e7 dofs per order p = 1..8 on the benchmark's
+lattices (5% jitter, lognormal coefficient per quadrature point), in the launch
+configuration the benchmark times (constrained operator, atomic scatter).
+
+The oracle cannot assemble 1e7-dof matrices, so it recomputes sampled outputs one
+by one: for a few centre elements (random ones and two corners) it assembles the
+3x3x3 block of elements around the centre from scratch.  Every element that
+touches a dof of the centre element lies in that block, so the block's
+(unconstrained) rows of those dofs are complete.  The essential set comes from
+the node positions (dofs on the cube's faces), independent of the library:
+y_b = x_b there, and free rows ignore essential columns (symmetric elimination).
+Inputs are position-keyed on both sides; results are matched by node position.
+Bar: essential outputs exact; free outputs within 1e-12 relative (2-norm over the
+sampled free dofs, which are measured apart: their values are O(h) (diffusion) and
+O(h^3) (mass) smaller than the O(1) essential ones).
+"""
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import synth
+from tests._common import on_boundary, patch_rows, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1911_09220_amd import pafem as P  # noqa: E402
+
+TARGET_DOFS = 1e7
+TOL = 1e-12
+
+
+def _lattice_n(p):
+    return max(1, int(round((TARGET_DOFS ** (1.0 / 3.0) - 1.0) / p)))
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_bench_size_applies_on_sampled_rows(p):
+    n = _lattice_n(p)
+    mesh = synth.hex_lattice(n, 0.05, seed=2)
+    E = mesh["hex"].shape[0]
+    kappa = synth.lognormal_iid(E, p + 2, 1.0, seed=3)
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    assert 0.9e7 < S.ndofs < 1.1e7
+    Xlib = S.dof_coords()
+    seed = 50 + p
+    x = torch.as_tensor(synth.hash_normal(Xlib, seed=seed), device="cuda")
+    kc = torch.as_tensor(kappa, device="cuda")
+    rng = np.random.default_rng(60 + p)
+    centres = [0, E - 1] + [int(c) for c in rng.integers(0, E, size=6)]
+    print(f"p={p}: n={n}, {E} elements, {S.ndofs} dofs", flush=True)
+    picks = {}
+    for kind in (P.DIFFUSION, P.MASS):
+        op = P.Operator(S, kind, S.qdata(kind, coeff=kc))
+        y = op.apply(x).cpu().numpy()
+        got, want, ess = [], [], []
+        for c in centres:
+            yo, Xo = patch_rows(mesh, kappa, p, c, "diffusion" if kind == P.DIFFUSION else "mass",
+                                seed)
+            if c not in picks:
+                # library dofs near the centre element, matched by position
+                lo, hi = Xo.min(axis=0) - 1e-9, Xo.max(axis=0) + 1e-9
+                cand = np.flatnonzero(np.all((Xlib >= lo) & (Xlib <= hi), axis=1))
+                dist, idx = cKDTree(Xlib[cand]).query(Xo)
+                assert dist.max() < 1e-10, "node positions do not match"
+                picks[c] = cand[idx]
+            got.append(y[picks[c]])
+            want.append(yo)
+            ess.append(on_boundary(Xo))
+        got, want, ess = np.concatenate(got), np.concatenate(want), np.concatenate(ess)
+        err = rel_err(got[~ess], want[~ess])
+        name = "diffusion" if kind == P.DIFFUSION else "mass"
+        print(f"p={p} {name}: sampled {len(got)} outputs ({int(ess.sum())} essential), "
+              f"free rel err {err:.2e}", flush=True)
+        assert np.array_equal(got[ess], want[ess])
+        assert (~ess).sum() > 0 and err <= TOL
+        del op

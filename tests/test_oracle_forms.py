@@ -232,3 +232,23 @@ def test_mutant_short_quadrature_fails():
     Ke = forms.element_stiffness(_single_element(), 3, 2)[0]
     expected_K = _kron3(K1, M1, M1) + _kron3(M1, K1, M1) + _kron3(M1, M1, K1)
     assert np.abs(Ke - expected_K).max() > 1e-6
+
+
+def test_patch_rows_equal_whole_mesh_rows():
+    """The sampled-row oracle of the full-size parity tests: rows of the constrained
+    operator from a 3x3x3 element block equal the rows of the whole-mesh matrix
+    (interior, face, edge and corner elements; diffusion and mass)."""
+    from tests._common import OracleProblem, patch_rows
+    n, p = 5, 2
+    mesh = synth.hex_lattice(n, 0.08, seed=7)
+    E = mesh["hex"].shape[0]
+    kappa = synth.lognormal_iid(E, p + 2, 1.0, seed=8)
+    ref = OracleProblem(mesh, p, coeff=kappa, rho=kappa)
+    x = synth.hash_normal(ref.coords, seed=9)
+    for kind, A in (("diffusion", ref.Kc), ("mass", ref.Mc)):
+        y = A @ x
+        for c in (0, E - 1, 12, 62, 2 + n * (2 + n * 2)):
+            yo, Xo = patch_rows(mesh, kappa, p, c, kind, seed=9)
+            idx = [int(np.argmin(np.abs(ref.coords - xo).sum(axis=1))) for xo in Xo]
+            assert np.abs(ref.coords[idx] - Xo).max() < 1e-12
+            np.testing.assert_allclose(yo, y[idx], rtol=1e-12, atol=1e-12 * np.abs(y).max())
