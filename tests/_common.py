@@ -63,7 +63,8 @@ def on_boundary(X):
 
 
 def patch_rows(mesh, kappa, p, c, kind, seed):
-    """Oracle (A x) of the constrained operator at the dofs of element c of a lattice,
+    """Oracle (A x) of the constrained operator at the dofs of element c of a lattice
+    (kappa [E, Q^3] or None for 1),
     from the 3x3x3 element block around c alone, and those dofs' coordinates.
 
     x = synth.hash_normal(node positions, seed); essential dofs are the nodes on the
@@ -72,10 +73,11 @@ def patch_rows(mesh, kappa, p, c, kind, seed):
     ids, pos = _patch(n, c)
     sub = synth.sub_mesh(mesh, ids)
     space = oracle.H1Space(sub, p)
+    coeff = None if kappa is None else kappa[ids]
     if kind == "diffusion":
-        Ae = forms.element_stiffness(sub, p, p + 2, kappa[ids])
+        Ae = forms.element_stiffness(sub, p, p + 2, coeff)
     else:
-        Ae = forms.element_mass(sub, p, p + 2, kappa[ids])
+        Ae = forms.element_mass(sub, p, p + 2, coeff)
     A = oracle.assemble(space, Ae).tocsr()
     X = space.dof_coordinates()
     ess = on_boundary(X)

@@ -78,3 +78,89 @@ def test_bench_size_applies_on_sampled_rows(p):
         assert np.array_equal(got[ess], want[ess])
         assert (~ess).sum() > 0 and err <= TOL
         del op
+
+
+def _sample(Xlib, y, mesh, kappa, p, centres, kind, seed, picks):
+    got, want, ess = [], [], []
+    for c in centres:
+        yo, Xo = patch_rows(mesh, kappa, p, c, kind, seed)
+        if c not in picks:
+            lo, hi = Xo.min(axis=0) - 1e-9, Xo.max(axis=0) + 1e-9
+            cand = np.flatnonzero(np.all((Xlib >= lo) & (Xlib <= hi), axis=1))
+            dist, idx = cKDTree(Xlib[cand]).query(Xo)
+            assert dist.max() < 1e-10, "node positions do not match"
+            picks[c] = cand[idx]
+        got.append(y[picks[c]])
+        want.append(yo)
+        ess.append(on_boundary(Xo))
+    return np.concatenate(got), np.concatenate(want), np.concatenate(ess)
+
+
+def test_mixed_precision_config_applies_on_sampled_rows():
+    """The refinement benchmark's mesh: quadratic geometry warped by 0.05 sin sin sin,
+    45^3 elements, p = 6 (19.9M dofs), coefficient 1.  The FP64, FP32 and BF16-D applies
+    against the oracle's rows (bars as at small size: 1e-12, 1e-5, 1e-2)."""
+    p, n = 6, 45
+    mesh = synth.q2_warped_lattice(n, 0.05)
+    E = mesh["hex"].shape[0]
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    Xlib = S.dof_coords()
+    seed = 71
+    x = torch.as_tensor(synth.hash_normal(Xlib, seed=seed), device="cuda")
+    qd = S.qdata(P.DIFFUSION)
+    rng = np.random.default_rng(72)
+    centres = [0, E - 1] + [int(c) for c in rng.integers(0, E, size=4)]
+    print(f"mixed config: {E} elements, {S.ndofs} dofs", flush=True)
+    picks = {}
+    for name, dt, tol in (("f64", P.F64, 1e-12), ("f32", P.F32, 1e-5), ("bf16", P.BF16, 1e-2)):
+        if dt == P.F64:
+            op = P.Operator(S, P.DIFFUSION, qd)
+            y = op.apply(x)
+        else:
+            op = P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, dt), qdata_dtype=dt)
+            y = op.apply(x.float())
+        got, want, ess = _sample(Xlib, y.double().cpu().numpy(), mesh, None, p, centres,
+                                 "diffusion", seed, picks)
+        err = rel_err(got[~ess], want[~ess])
+        print(f"mixed config {name}: {len(got)} sampled outputs, free rel err {err:.2e}", flush=True)
+        assert err <= tol
+        ess_tol = 0.0 if dt == P.F64 else 1e-7
+        assert np.all(np.abs(got[ess] - want[ess]) <= ess_tol * np.abs(want[ess]))
+        del op, y
+
+
+def test_batched_config_columns_match_single_applies():
+    """The batched benchmark's 32 uneven meshes (1e4..1e6 dofs, p = 2..6) with 16
+    right-hand sides each, in one batch launch: every column equals the single-vector
+    FP64 apply of its mesh (FP64 batch to 1e-12, FP32 batch to 1e-5)."""
+    nrhs = 16
+    specs = synth.uneven_mesh_list(32)
+    spaces, qds = [], []
+    for sp in specs:
+        S = P.Space(P.Mesh.from_dict(synth.hex_lattice(sp["n"], 0.05, seed=sp["mesh_seed"])), sp["p"])
+        spaces.append(S)
+        qds.append(S.qdata(P.DIFFUSION))
+    for dt, tol in ((P.F64, 1e-12), (P.F32, 1e-5)):
+        ops, xs, ys, ops64 = [], [], [], []
+        for i, (S, qd) in enumerate(zip(spaces, qds)):
+            ops64.append(P.Operator(S, P.DIFFUSION, qd))
+            if dt == P.F64:
+                ops.append(ops64[-1])
+            else:
+                ops.append(P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, dt), qdata_dtype=dt))
+            g = torch.Generator(device="cuda")
+            g.manual_seed(5000 + i)
+            x = torch.randn(S.ndofs, nrhs, dtype=torch.float64, device="cuda", generator=g)
+            xs.append(x if dt == P.F64 else x.float())
+            ys.append(torch.empty_like(xs[-1]))
+        B = P.Batch(ops, nrhs)
+        B.apply(xs, ys)
+        worst = 0.0
+        for op64, x, y in zip(ops64, xs, ys):
+            for r in range(nrhs):
+                ref = op64.apply(x[:, r].double().contiguous())
+                worst = max(worst, float((y[:, r].double() - ref).norm() / ref.norm()))
+        print(f"batched config {'f64' if dt == P.F64 else 'f32'}: worst column rel err {worst:.2e}",
+              flush=True)
+        assert worst <= tol
+        del B
