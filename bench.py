@@ -72,6 +72,13 @@ def algorithmic_bytes(kind: str, p: int, ne: int, ndofs: int) -> int:
     return 8 * ndofs + 8 * ndofs + d_bytes + 4 * ne * (p + 1) ** 3
 
 
+def geom_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
+    """Recomputed-geometry diffusion: x + y + w*kappa per point + 8 corner nodes per
+    element + int32 element->dof map, per apply."""
+    q = p + 2
+    return 8 * ndofs + 8 * ndofs + 8 * ne * q ** 3 + 192 * ne + 4 * ne * (p + 1) ** 3
+
+
 def algorithmic_flops(kind: str, p: int, ne: int) -> int:
     D, Q = p + 1, p + 2
     if kind == "diffusion":
@@ -91,6 +98,7 @@ def setup_problem(P, torch, p, target, scatter):
     del mesh
     qd = S.qdata(P.DIFFUSION, coeff=kappa)
     qm = S.qdata(P.MASS, coeff=kappa)
+    qg = S.qdata(P.DIFFUSION_GEOM, coeff=kappa)
     del kappa
     gen = torch.Generator(device="cuda")
     gen.manual_seed(100 + p)
@@ -99,6 +107,7 @@ def setup_problem(P, torch, p, target, scatter):
         "p": p, "n": n, "space": S, "ne": S.nelem, "ndofs": S.ndofs,
         "diff": P.Operator(S, P.DIFFUSION, qd, scatter=scatter),
         "mass": P.Operator(S, P.MASS, qm, scatter=scatter),
+        "geom": P.Operator(S, P.DIFFUSION_GEOM, qg, scatter=scatter),
         "x": x, "y": torch.empty_like(x),
     }
 
@@ -319,6 +328,8 @@ def main():
     ap.add_argument("--cg-orders", default="3", help="orders for the Jacobi-PCG solve ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mass", action="store_true")
+    ap.add_argument("--no-geom", action="store_true",
+                    help="skip the recomputed-geometry diffusion variant")
     ap.add_argument("--forms", default="mixed,batched,learned",
                     help="solver forms to measure beside the sweep ('' = none)")
     ap.add_argument("--learned-fields", type=int, default=20)
@@ -366,6 +377,15 @@ def main():
             mass[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
                                   "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
 
+    geom = {}
+    if not args.no_geom:
+        gper, _ = time_applies(torch, probs, "geom", max(3, args.steps // 2), 1)
+        for pr, t, td in zip(probs, gper, per):
+            by = geom_algorithmic_bytes(pr["p"], pr["ne"], pr["ndofs"])
+            geom[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
+                                  "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4),
+                                  "speedup_vs_stored": round(td / t, 3)}
+
     # dominant kernel: the order whose apply takes the longest
     k = max(range(len(probs)), key=lambda i: per[i])
     dom = probs[k]
@@ -394,6 +414,15 @@ def main():
                       "seconds": round(info["seconds"], 4), "status": info["status"],
                       "true_rel_res": info["true_rel_res"], "diag_seconds": round(t_diag, 4),
                       "ms_per_iter": round(1e3 * info["seconds"] / max(1, info["iters"]), 4)}
+        if not args.no_geom:
+            # same solve with the recomputed-geometry operator (diagonal of the stored one)
+            xg, gi = pr["geom"].pcg(b, diag=diag, rel_tol=1e-8, max_iter=20000, history=False)
+            cg[str(p)]["recomputed_geometry"] = {
+                "iters": gi["iters"], "seconds": round(gi["seconds"], 4), "status": gi["status"],
+                "true_rel_res": gi["true_rel_res"],
+                "ms_per_iter": round(1e3 * gi["seconds"] / max(1, gi["iters"]), 4),
+                "rel_diff_vs_stored": float((xg - xs).norm() / xs.norm())}
+            del xg
         del xs, b, diag
 
     out = {
@@ -405,7 +434,7 @@ def main():
                                f"dofs for p={args.orders}, 5% vertex jitter, lognormal kappa "
                                f"(sigma=1) per quadrature point, q1d=p+2, Dirichlet boundary",
                    "orders": orders, "scatter": args.scatter, "per_p": per_p,
-                   "mass_apply": mass, "setup_seconds": round(t_setup, 1),
+                   "mass_apply": mass, "recomputed_geometry_apply": geom, "setup_seconds": round(t_setup, 1),
                    "timed_wall_seconds": round(wall, 4)},
         "roofline": roofline,
         "cg_time_to_1e-8": cg,

@@ -59,6 +59,13 @@ typedef int32_t pafem_status;
  * Abstractions": diffusion). */
 #define PAFEM_MASS 0
 #define PAFEM_DIFFUSION 1
+/* The diffusion operator storing only a portion of D ("High-Order Partial
+ * Assembly" lets PA store portions of D and recompute the rest): qdata holds
+ * alpha_q kappa_q per point, and the apply recomputes J, det J and J^{-1} J^{-T}
+ * from the element's trilinear geometry nodes.  Same operator as
+ * PAFEM_DIFFUSION up to rounding; FP64, trilinear meshes only; the diagonal is
+ * taken from a PAFEM_DIFFUSION operator of the same space and coefficient. */
+#define PAFEM_DIFFUSION_GEOM 2
 
 /* Storage types. */
 #define PAFEM_F64 0
@@ -152,6 +159,8 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
  *   diffusion: E * 6 * Q^3   D_q = alpha_q kappa_q det J_q J_q^{-1} J_q^{-T},
  *                            symmetric, components (00,01,02,11,12,22),
  *                            layout [E][6][Q^3].
+ *   diffusion with recomputed geometry (PAFEM_DIFFUSION_GEOM): E * Q^3 values
+ *                            alpha_q kappa_q.
  * Errors: EUNSUPPORTED if q1d is not one of the built rules (q1d = p+2). */
 pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int64_t* nvalues);
 
@@ -184,7 +193,8 @@ pafem_status pafem_op_apply(pafem_op op, const double* x, double* y, void* work,
                             size_t work_bytes, void* stream);
 
 /* diag[ndofs] = diagonal of the operator (1 on essential dofs if constrained),
- * by sum factorization with products of the 1D tables.  Asynchronous. */
+ * by sum factorization with products of the 1D tables.  Asynchronous.
+ * EUNSUPPORTED for PAFEM_DIFFUSION_GEOM (use the PAFEM_DIFFUSION operator). */
 pafem_status pafem_op_diagonal(pafem_op op, double* diag, void* work, size_t work_bytes,
                                void* stream);
 

@@ -255,7 +255,8 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
 pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int64_t* nvalues) {
   return guarded([&] {
     require(space && space->s && nvalues, PAFEM_EINVAL, "null pointer argument");
-    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, PAFEM_EINVAL, "unknown operator kind");
+    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM,
+            PAFEM_EINVAL, "unknown operator kind");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
     *nvalues = qdata_values(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 6 : 1);
   });
@@ -267,7 +268,8 @@ pafem_status pafem_qdata_assemble(pafem_space space, int32_t kind, int32_t q1d,
   return guarded([&] {
     const Space& s = uploaded_space(space);
     require(qdata != nullptr, PAFEM_EINVAL, "null qdata");
-    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, PAFEM_EINVAL, "unknown operator kind");
+    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM,
+            PAFEM_EINVAL, "unknown operator kind");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
     auto st = static_cast<hipStream_t>(stream);
     hip_check(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(s.dev.status), INT_MAX, 1, st),
@@ -286,7 +288,12 @@ pafem_status pafem_op_create(pafem_space space, int32_t kind, int32_t q1d, const
   return guarded([&] {
     const Space& s = uploaded_space(space);
     require(out && qdata, PAFEM_EINVAL, "null pointer argument");
-    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, PAFEM_EINVAL, "unknown operator kind");
+    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM,
+            PAFEM_EINVAL, "unknown operator kind");
+    if (kind == PAFEM_DIFFUSION_GEOM) {
+      require(s.ng == 2, PAFEM_EUNSUPPORTED, "recomputed geometry needs trilinear elements");
+      require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "recomputed geometry is FP64");
+    }
     require(dtype_size(qdata_dtype) != 0, PAFEM_EINVAL, "unknown qdata dtype");
     require(q1d == s.p + 2, PAFEM_EUNSUPPORTED,
             "the fused apply is built for q1d = p + 2 only");
@@ -328,6 +335,8 @@ pafem_status pafem_op_diagonal(pafem_op op, double* diag, void* work, size_t wor
   return guarded([&] {
     require(op && diag, PAFEM_EINVAL, "null pointer argument");
     require(op->op.qdtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "diagonal needs f64 qdata");
+    require(op->op.kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
+            "diagonal: use the PAFEM_DIFFUSION operator of the same space and coefficient");
     require(work && work_bytes >= op_work_bytes(op->op), PAFEM_ESHAPE, "workspace too small");
     const Op& o = op->op;
     const Space& s = *o.space;

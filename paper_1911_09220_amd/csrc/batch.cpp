@@ -60,6 +60,8 @@ Batch::Batch(const std::vector<const Op*>& ops_in, int nrhs_in, void* work, size
   if (nrhs < 2 || nrhs % 2) throw Error(PAFEM_EINVAL, "nrhs must be a positive even number");
   qdtype = ops[0]->qdtype;
   kind = ops[0]->kind;
+  if (kind != PAFEM_MASS && kind != PAFEM_DIFFUSION)
+    throw Error(PAFEM_EUNSUPPORTED, "batched apply: mass or diffusion operators with stored D");
   for (const Op* o : ops) {
     if (o->qdtype != qdtype || o->kind != kind)
       throw Error(PAFEM_EINVAL, "all operators of a batch need the same kind and qdata dtype");

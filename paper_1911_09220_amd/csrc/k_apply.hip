@@ -45,11 +45,14 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
                     const uint16_t* __restrict__ tile_slot, const TC* __restrict__ tabB,
                     const TC* __restrict__ tabG, const TD* __restrict__ qd,
                     const TV* __restrict__ x, TV* __restrict__ y, double* __restrict__ dotp,
-                    int ne, int constrained) {
+                    const double* __restrict__ gnodes, const TC* __restrict__ tabBg,
+                    const TC* __restrict__ tabGg, int ne, int constrained) {
   constexpr int D = P + 1, DD = D * D, QQ = Q * Q, QQQ = Q * Q * Q, DDD = D * D * D;
   constexpr int NE = elems_per_block<Q>();
-  constexpr bool DIFF = (KIND == PAFEM_DIFFUSION);
-  constexpr int NC = DIFF ? 6 : 1;   // stored values per quadrature point
+  // GEOM: diffusion storing alpha kappa per point; J recomputed from the 8 corners
+  constexpr bool GEOM = (KIND == PAFEM_DIFFUSION_GEOM);
+  constexpr bool DIFF = (KIND == PAFEM_DIFFUSION) || GEOM;
+  constexpr int NC = (DIFF && !GEOM) ? 6 : 1;   // stored values per quadrature point
   constexpr int NA = DIFF ? 2 : 1;   // arrays after the x-lines (B and G along x)
   constexpr int NCC = DIFF ? 3 : 1;  // arrays after the y-lines (one per derivative)
   // Line stride: odd, so that threads walking consecutive lines hit distinct banks.
@@ -179,6 +182,32 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   double energy = 0.0;  // sum of u . D u over this thread's points (DOT)
   if (act) {
     const int zy = r / Q, zx = r - (r / Q) * Q;
+    // GEOM: the corners contracted over this thread's (qx, qy), per z-corner k and
+    // coordinate a: value, x-derivative and y-derivative parts of J
+    TC gv[3][2], gx[3][2], gy[3][2];
+    if constexpr (GEOM) {
+      const double* X = gnodes + size_t(e) * 24;  // [k3][k2][k1][a], k1 fastest
+      const TC b1[2] = {tabBg[zx * 2], tabBg[zx * 2 + 1]}, g1[2] = {tabGg[zx * 2], tabGg[zx * 2 + 1]};
+      const TC b2[2] = {tabBg[zy * 2], tabBg[zy * 2 + 1]}, g2[2] = {tabGg[zy * 2], tabGg[zy * 2 + 1]};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k3 = 0; k3 < 2; ++k3) {
+          TC v = TC(0), dx = TC(0), dy = TC(0);
+#pragma unroll
+          for (int k2 = 0; k2 < 2; ++k2)
+#pragma unroll
+            for (int k1 = 0; k1 < 2; ++k1) {
+              const TC xa = X[3 * (k1 + 2 * (k2 + 2 * k3)) + a];
+              v += xa * (b1[k1] * b2[k2]);
+              dx += xa * (g1[k1] * b2[k2]);
+              dy += xa * (b1[k1] * g2[k2]);
+            }
+          gv[a][k3] = v;
+          gx[a][k3] = dx;
+          gy[a][k3] = dy;
+        }
+    }
     TC c0[D], c1[D], c2[D];
 #pragma unroll
     for (int dz = 0; dz < D; ++dz) {
@@ -193,7 +222,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
     for (int dz = 0; dz < D; ++dz) t0[dz] = t1[dz] = t2[dz] = TC(0);
 #pragma unroll
     for (int qz = 0; qz < Q; ++qz) {
-      if (DIFF) {
+      if constexpr (DIFF) {
         TC ux = TC(0), uy = TC(0), uz = TC(0);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
@@ -201,9 +230,44 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
           uy += bB(qz, dz) * c1[dz];
           uz += bG(qz, dz) * c2[dz];
         }
-        const TC vx = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
-        const TC vy = dq[qz][1] * ux + dq[qz][3] * uy + dq[qz][4] * uz;
-        const TC vz = dq[qz][2] * ux + dq[qz][4] * uy + dq[qz][5] * uz;
+        TC d00, d01, d02, d11, d12, d22;
+        if constexpr (GEOM) {
+          // J[a][b] = dx_a / dxi_b at (qx, qy, qz); D = w kappa adj(J) adj(J)^t / det J
+          TC J[3][3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            J[a][0] = gx[a][0] * tabBg[qz * 2] + gx[a][1] * tabBg[qz * 2 + 1];
+            J[a][1] = gy[a][0] * tabBg[qz * 2] + gy[a][1] * tabBg[qz * 2 + 1];
+            J[a][2] = gv[a][0] * tabGg[qz * 2] + gv[a][1] * tabGg[qz * 2 + 1];
+          }
+          const TC A00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+          const TC A01 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+          const TC A02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+          const TC A10 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+          const TC A11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+          const TC A12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+          const TC A20 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+          const TC A21 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+          const TC A22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+          const TC det = J[0][0] * A00 + J[0][1] * A10 + J[0][2] * A20;
+          const TC f = dq[qz][0] / det;
+          d00 = f * (A00 * A00 + A01 * A01 + A02 * A02);
+          d01 = f * (A00 * A10 + A01 * A11 + A02 * A12);
+          d02 = f * (A00 * A20 + A01 * A21 + A02 * A22);
+          d11 = f * (A10 * A10 + A11 * A11 + A12 * A12);
+          d12 = f * (A10 * A20 + A11 * A21 + A12 * A22);
+          d22 = f * (A20 * A20 + A21 * A21 + A22 * A22);
+        } else {
+          d00 = dq[qz][0];
+          d01 = dq[qz][1];
+          d02 = dq[qz][2];
+          d11 = dq[qz][3];
+          d12 = dq[qz][4];
+          d22 = dq[qz][5];
+        }
+        const TC vx = d00 * ux + d01 * uy + d02 * uz;
+        const TC vy = d01 * ux + d11 * uy + d12 * uz;
+        const TC vz = d02 * ux + d12 * uy + d22 * uz;
         if (DOT) energy += double(ux) * double(vx) + double(uy) * double(vy) + double(uz) * double(vz);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
@@ -318,10 +382,14 @@ void launch_one(const DevSpace& sp, bool constrained, const void* qd, const void
   const int nblk = int((sp.ne + NE - 1) / NE);
   const TC* tabB = table_block<TC>(sp, Q) + 2 * Q;
   const TC* tabG = tabB + Q * (P + 1);
+  // geometry tables (Bg, Gg of the ng-node geometry basis) follow B and G
+  const TC* tabBg = tabG + Q * (P + 1);
+  const TC* tabGg = tabBg + Q * sp.ng;
   hipLaunchKernelGGL((pa_apply_kernel<P, Q, KIND, EVEC, DOT, TV, TD, TC>), dim3(nblk),
                      dim3(NE * Q * Q), 0, st, sp.tile_off, sp.tile_dofs, sp.tile_slot, tabB, tabG,
                      static_cast<const TD*>(qd), static_cast<const TV*>(x),
-                     static_cast<TV*>(out), dotp, int(sp.ne), int(constrained));
+                     static_cast<TV*>(out), dotp, sp.gnodes, tabBg, tabGg, int(sp.ne),
+                     int(constrained));
 }
 
 template <int P, int KIND, typename TV, typename TD, typename TC>
@@ -345,6 +413,12 @@ bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, bool con
                   bool evec, const void* qd, const void* x, void* out, double* dotp,
                   hipStream_t st) {
   const bool diff = kind == PAFEM_DIFFUSION;
+  if (kind == PAFEM_DIFFUSION_GEOM) {
+    if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || sp.ng != 2) return false;
+    launch_mode<P, PAFEM_DIFFUSION_GEOM, double, double, double>(sp, constrained, evec, qd, x, out,
+                                                                 dotp, st);
+    return true;
+  }
   if (vdtype == PAFEM_F64 && qdtype == PAFEM_F64) {
     if (diff)
       launch_mode<P, PAFEM_DIFFUSION, double, double, double>(sp, constrained, evec, qd, x, out, dotp, st);

@@ -99,6 +99,8 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* _
     const double c = scale * (coeff ? coeff[size_t(orig[e]) * QQQ + q] : 1.0);
     if (kind == PAFEM_MASS) {
       qd[qdata_index(e, 0, q, Q, 1)] = w * c * det;
+    } else if (kind == PAFEM_DIFFUSION_GEOM) {
+      qd[qdata_index(e, 0, q, Q, 1)] = w * c;  // the apply recomputes the geometric part
     } else {
       // alpha kappa det J J^{-1} J^{-T} = alpha kappa A A^T / det J
       const double f = w * c / det;

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpafem.so")
 
-MASS, DIFFUSION = 0, 1
+MASS, DIFFUSION, DIFFUSION_GEOM = 0, 1, 2
 F64, F32, BF16 = 0, 1, 2
 SPACE_RENUMBER = 1
 OP_CONSTRAINED, OP_SCATTER_EVEC = 1, 2

@@ -233,3 +233,67 @@ def test_apply_on_offset_views_matches_aligned(dtype):
     op.apply(big_x[1:], big_y[1:])
     tol = 1e-14 if dtype == "f64" else 1e-6
     assert float((big_y[1:] - y).norm() / y.norm()) <= tol and float(big_y[0]) == 7.0
+
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_diffusion_with_recomputed_geometry(p):
+    """The variant that stores only w*kappa per quadrature point and rebuilds the
+    trilinear Jacobian inside the apply: the oracle's operator to 1e-12 on rotated,
+    jittered elements with a lognormal coefficient, in both scatter modes, and the
+    stored-D apply on the same input."""
+    mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=50 + p, rotate_seed=150 + p)
+    E = mesh["hex"].shape[0]
+    kappa = synth.lognormal_iid(E, p + 2, 1.0, seed=51 + p)
+    S, X, kc = _setup(mesh, p, kappa)
+    qg = S.qdata(P.DIFFUSION_GEOM, coeff=kc)
+    qd = S.qdata(P.DIFFUSION, coeff=kc)
+    assert qg.numel() * 6 == qd.numel()
+    x = _cuda(synth.hash_normal(X, seed=52 + p))
+    stored = P.Operator(S, P.DIFFUSION, qd).apply(x)
+    ref = OracleProblem(mesh, p, coeff=kappa)
+    y_ref = ref.Kc @ synth.hash_normal(ref.coords, seed=52 + p)
+    perm = match_by_coords(X, ref.coords)
+    for scatter in ("atomic", "evec"):
+        y = P.Operator(S, P.DIFFUSION_GEOM, qg, scatter=scatter).apply(x)
+        err = rel_err(y.cpu().numpy(), y_ref[perm])
+        print(f"recomputed geometry p={p} {scatter}: rel err {err:.2e}")
+        assert err <= TOL
+        assert float((y - stored).norm() / stored.norm()) <= TOL
+
+
+def test_recomputed_geometry_limits():
+    """Quadratic geometry and the diagonal are refused with an error, and so is a
+    batch of such operators."""
+    S2 = P.Space(P.Mesh.from_dict(synth.q2_warped_lattice(2, 0.05)), 2)
+    with pytest.raises(P.PafemError):
+        P.Operator(S2, P.DIFFUSION_GEOM, S2.qdata(P.DIFFUSION_GEOM))
+    S1 = P.Space(P.Mesh.from_dict(synth.hex_lattice(2, 0.1, seed=1)), 2)
+    op = P.Operator(S1, P.DIFFUSION_GEOM, S1.qdata(P.DIFFUSION_GEOM))
+    with pytest.raises(P.PafemError):
+        op.diagonal()
+    with pytest.raises(P.PafemError):
+        P.Batch([op], 2)
+
+
+def test_pcg_with_recomputed_geometry():
+    """Jacobi-PCG on the recomputed-geometry operator (diagonal taken from the
+    stored-D operator) reaches the direct solution of the oracle's system, with the
+    oracle PCG's iteration count."""
+    mesh = synth.hex_lattice(6, 0.1, seed=3, rotate_seed=4)
+    S, X, _ = _setup(mesh, 3)
+    diag = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION)).diagonal()
+    op = P.Operator(S, P.DIFFUSION_GEOM, S.qdata(P.DIFFUSION_GEOM))
+    b = S.linear_form(P.SOURCE_SINE)
+    x, info = op.pcg(b, diag=diag, rel_tol=1e-12, max_iter=2000)
+    assert info["status"] == "OK" and info["converged"]
+    ref = OracleProblem(mesh, 3)
+    perm = match_by_coords(X, ref.coords)
+    bref = ref.load(synth.sine_source)
+    import scipy.sparse.linalg as spla
+    xd = spla.spsolve(ref.Kc.tocsc(), bref)
+    err = rel_err(x.cpu().numpy(), xd[perm])
+    print(f"recomputed-geometry pcg: iters {info['iters']} rel err vs direct {err:.2e}")
+    assert err < 1e-10
+    r = oracle.pcg(ref.Kc, bref, ref.Kc.diagonal(), tol=1e-12)
+    assert abs(r["iters"] - info["iters"]) <= 2
