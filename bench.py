@@ -214,6 +214,81 @@ def bench_mixed(P, torch, n=45, p=6, tol=1e-8):
     return out
 
 
+def bench_pmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20,
+              configs=((2, 10, "arithmetic"), (1, 10, "arithmetic"), (2, 5, "arithmetic"),
+                       (2, 20, "arithmetic"), (2, 10, "geometric"))):
+    """Order multigrid on the sweep's p-order problem (5% jitter, lognormal kappa per
+    point): flexible CG with one V-cycle per iteration against FP64 Jacobi-PCG."""
+    import synth
+    n = lattice_size(p, target)
+    mesh = synth.hex_lattice(n, 0.05, seed=2)
+    ne = mesh["hex"].shape[0]
+    kappa = torch.as_tensor(synth.lognormal_iid(ne, p + 2, 1.0, seed=3), device="cuda")
+    M = P.Mesh.from_dict(mesh)
+    del mesh
+    orders = [p]
+    while orders[-1] > 1:
+        orders.append(max(1, orders[-1] // 2))
+    means = {"arithmetic": P.MEAN_ARITHMETIC, "geometric": P.MEAN_GEOMETRIC,
+             "harmonic": P.MEAN_HARMONIC}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(77)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    spaces = [P.Space(M, q) for q in orders]
+    torch.cuda.synchronize()
+    t_spaces = time.perf_counter() - t0
+    fine = P.Operator(spaces[0], P.DIFFUSION, spaces[0].qdata(P.DIFFUSION, coeff=kappa))
+    b = spaces[0].linear_form(P.SOURCE_SINE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dfine = fine.diagonal()
+    torch.cuda.synchronize()
+    t_diag = time.perf_counter() - t0
+    xj, ij = fine.pcg(b, diag=dfine, rel_tol=tol, max_iter=20000, history=False)
+    out = {"order": p, "orders": orders, "ndofs": spaces[0].ndofs,
+           "coarse_ndofs": [S.ndofs for S in spaces[1:]], "elements": spaces[0].nelem,
+           "tol": tol, "space_setup_seconds": round(t_spaces, 3),
+           "jacobi_pcg": {"iters": ij["iters"], "seconds": round(ij["seconds"], 4),
+                          "diag_seconds": round(t_diag, 4), "true_rel_res": ij["true_rel_res"]},
+           "runs": []}
+    log(f"pmg: Jacobi-PCG {ij['iters']} its {ij['seconds']:.3f} s")
+    levels = {}
+    for degree, coarse_iters, mean in configs:
+        if mean not in levels:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ops, diags, lmax = [fine], [dfine], []
+            for l, S in enumerate(spaces):
+                if l > 0:
+                    c = S.coeff_mean(kappa, q1d_in=p + 2, q1d_out=S.p + 2, kind=means[mean])
+                    ops.append(P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=c)))
+                    diags.append(ops[-1].diagonal())
+                v = torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=gen)
+                lmax.append(ops[l].lambda_max(diags[l], v, power_iters))
+            torch.cuda.synchronize()
+            levels[mean] = (ops, diags, lmax, time.perf_counter() - t0)
+        ops, diags, lmax, t_levels = levels[mean]
+        G = P.PMG(ops, diags, lmax, degree=degree, coarse_iters=coarse_iters)
+        G.fcg(b, rel_tol=1e-2, max_iter=2, history=False)  # warm-up (workspace, kernels)
+        x, info = G.fcg(b, rel_tol=tol, max_iter=1000, history=False)
+        run = {"degree": degree, "coarse_iters": coarse_iters, "coarse_coefficient": mean,
+               "iters": info["iters"], "seconds": round(info["seconds"], 4),
+               "status": info["status"], "true_rel_res": info["true_rel_res"],
+               "ms_per_iter": round(1e3 * info["seconds"] / max(1, info["iters"]), 3),
+               "speedup_vs_jacobi": round(ij["seconds"] / info["seconds"], 3),
+               "level_setup_seconds": round(t_levels, 3),
+               "lmax": [round(v, 5) for v in lmax],
+               "solution_rel_diff_vs_jacobi": float((x - xj).norm() / xj.norm())}
+        out["runs"].append(run)
+        log(f"pmg: degree {degree} coarse {coarse_iters} {mean}: {info['iters']} its "
+            f"{info['seconds']:.3f} s ({run['speedup_vs_jacobi']}x)")
+        del G, x
+    best = min(out["runs"], key=lambda r: r["seconds"] if r["status"] == "OK" else 1e9)
+    out["best"] = best
+    return out
+
+
 def bench_batched(P, torch, nrhs=16, reps=20, tune_cache=None):
     """32 uneven meshes (1e4..1e6 dofs, p = 2..6), nrhs right-hand sides, one graph launch."""
     import synth
@@ -330,8 +405,10 @@ def main():
     ap.add_argument("--no-mass", action="store_true")
     ap.add_argument("--no-geom", action="store_true",
                     help="skip the recomputed-geometry diffusion variant")
-    ap.add_argument("--forms", default="mixed,batched,learned",
+    ap.add_argument("--forms", default="mixed,batched,learned,pmg",
                     help="solver forms to measure beside the sweep ('' = none)")
+    ap.add_argument("--pmg-orders", default="3,6",
+                    help="orders of the sweep problems solved with order multigrid")
     ap.add_argument("--learned-fields", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=1500)
     args = ap.parse_args()
@@ -451,6 +528,11 @@ def main():
     if "batched" in forms:
         log("batched")
         out["batched"] = bench_batched(P, torch)
+    if "pmg" in forms:
+        out["pmg"] = {}
+        for p in [int(v) for v in args.pmg_orders.split(",") if v]:
+            log(f"pmg p={p}")
+            out["pmg"][str(p)] = bench_pmg(P, torch, p=p, target=args.target_dofs)
     if "learned" in forms:
         log("learned")
         out["learned"] = bench_learned(P, torch, fields=args.learned_fields,

@@ -411,6 +411,98 @@ pafem_status pafem_fcg_solve(pafem_op op, pafem_net net, const float* feats, con
                              const pafem_solve_opts* opts, pafem_fcg_result* result,
                              void* stream);
 
+/* ---------------------------------------------------- order multigrid --- */
+/* Matrix-free preconditioning of PA operators by multigrid in the polynomial
+ * order ("Scalable Linear Solvers" names it without fixing an algorithm; the
+ * definitions below are this library's).  Levels are H1 spaces of orders
+ * p_0 >= p_1 >= ... on ONE mesh object (the spaces share the device element
+ * order), each with its constrained diffusion operator and diagonal. */
+
+#define PAFEM_MEAN_ARITHMETIC 0
+#define PAFEM_MEAN_GEOMETRIC 1
+#define PAFEM_MEAN_HARMONIC 2
+
+/* out[e][q'] = mean over q of coeff[e][q], for every q' < q1d_out^3: the
+ * per-element mean (PAFEM_MEAN_*) of a coefficient given per quadrature point
+ * (q1d_in^3 values per element, caller element order) spread over the points
+ * of another rule; the coarse-level coefficient of the multigrid.  Device f64
+ * arrays.  Asynchronous.  Errors: EINVAL (kind, sizes). */
+pafem_status pafem_coeff_element_mean(pafem_space space, int32_t kind, const double* coeff,
+                                      int32_t q1d_in, int32_t q1d_out, double* out,
+                                      void* stream);
+
+/* Prolongation from the order-pc space `coarse` to the order-pf space `fine`
+ * (pc <= pf, same mesh): yf[i] = sum_j phi^c_j(x_i) xc[j] over free coarse dofs
+ * j, for free fine dofs i (the coarse function evaluated at the fine node);
+ * essential fine entries are set to 0, or left unchanged when add != 0, in
+ * which case the result is added to yf.  Device f64 vectors.  Asynchronous.
+ * Deterministic (each fine dof is written by one element).
+ * Errors: EINVAL (different meshes, pc > pf, order above 8). */
+pafem_status pafem_prolongate(pafem_space coarse, pafem_space fine, const double* xc, double* yf,
+                              int32_t add, void* stream);
+
+/* Restriction, the transpose of the prolongation on free dofs:
+ * rc = P^T (bf - yf) (yf may be NULL), 0 on essential coarse dofs.  Sums with
+ * device atomics (order not fixed).  Asynchronous. */
+pafem_status pafem_restrict(pafem_space fine, pafem_space coarse, const double* bf,
+                            const double* yf, double* rc, void* stream);
+
+/* Workspace of pafem_op_lambda_max and pafem_chebyshev_smooth on op. */
+pafem_status pafem_smoother_workspace_bytes(pafem_op op, size_t* nbytes);
+
+/* Power iteration for the largest eigenvalue of D^-1 A (D = diag(diag)):
+ * v (device f64 [ndofs], the start vector, overwritten) is zeroed on essential
+ * dofs and normalised in the D-norm; then `iters` times w = A v,
+ * lambda = v . w, v = D^-1 w / ||D^-1 w||_D.  *lambda (host) is the last
+ * estimate, a lower bound of the largest eigenvalue.  SYNCHRONOUS. */
+pafem_status pafem_op_lambda_max(pafem_op op, const double* diag, double* v, int32_t iters,
+                                 void* work, size_t work_bytes, double* lambda, void* stream);
+
+/* `degree` steps of Chebyshev iteration with the Jacobi preconditioner on
+ * A x = b (Saad, Iterative Methods for Sparse Linear Systems, Chebyshev
+ * acceleration): eigenvalue interval [lo*lmax, hi*lmax] of D^-1 A, centre
+ * theta, half width delta, sigma = theta/delta; r = b - A x, rho = 1/sigma,
+ * d = D^-1 r / theta; repeat: x += d, and before each further step
+ * r -= A d, rho' = 1/(2 sigma - rho), d = rho' rho d + (2 rho'/delta) D^-1 r.
+ * zero_guess: x_0 = 0 (saves one apply).  Asynchronous. */
+pafem_status pafem_chebyshev_smooth(pafem_op op, const double* diag, double lmax, double lo,
+                                    double hi, int32_t degree, const double* b, double* x,
+                                    int32_t zero_guess, void* work, size_t work_bytes,
+                                    void* stream);
+
+typedef struct pafem_pmg_s* pafem_pmg;
+
+typedef struct {
+  int32_t degree;        /* Chebyshev steps before and after the coarse correction */
+  double lo, hi;         /* Chebyshev interval [lo*lmax, hi*lmax] */
+  int32_t coarse_iters;  /* Jacobi-PCG iterations on the coarsest level (from zero) */
+} pafem_pmg_opts;
+
+/* A V-cycle hierarchy over nlevels >= 1 levels, finest first: ops[l] an f64
+ * constrained diffusion operator (PAFEM_DIFFUSION or PAFEM_DIFFUSION_GEOM) of
+ * order p_l (non-increasing), all on one mesh object; diags[l] its diagonal
+ * (device f64, caller-owned, kept by pointer); lmax[l] the largest-eigenvalue
+ * estimate of diags[l]^-1 ops[l] (pafem_op_lambda_max).  The operators and
+ * diagonals must outlive the hierarchy.  Orders up to 8. */
+pafem_status pafem_pmg_create(int32_t nlevels, const pafem_op* ops, const double* const* diags,
+                              const double* lmax, const pafem_pmg_opts* opts, pafem_pmg* out);
+void pafem_pmg_destroy(pafem_pmg pmg);
+/* Workspace bytes of pafem_pmg_vcycle (max_iter < 0) or of pafem_pmg_fcg_solve
+ * with at most max_iter iterations. */
+pafem_status pafem_pmg_workspace_bytes(pafem_pmg pmg, int32_t max_iter, size_t* nbytes);
+/* z = V(r), one V-cycle from a zero guess: pre-smoothing, residual,
+ * restriction, recursion (coarsest: opts.coarse_iters Jacobi-PCG iterations),
+ * prolongation added, post-smoothing.  Device f64 [ndofs of level 0].
+ * Asynchronous. */
+pafem_status pafem_pmg_vcycle(pafem_pmg pmg, const double* r, double* z, void* work,
+                              size_t work_bytes, void* stream);
+/* Flexible CG on ops[0] preconditioned by one V-cycle per iteration (the
+ * coarse PCG makes the cycle a nonlinear map).  opts->precond is ignored.
+ * SYNCHRONOUS.  Returns ENOTCONV / EBREAKDOWN with the result filled in. */
+pafem_status pafem_pmg_fcg_solve(pafem_pmg pmg, const double* b, double* x, void* work,
+                                 size_t work_bytes, const pafem_solve_opts* opts,
+                                 pafem_solve_result* result, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,7 +100,7 @@ extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 200; }
+int32_t pafem_version(void) { return 210; }
 
 pafem_status pafem_mesh_create_hex(int64_t nv, const double* xyz, int64_t ne, const int64_t* hex8,
                                    int32_t geom_order, const double* geom_nodes,

@@ -22,6 +22,7 @@ SPACE_RENUMBER = 1
 OP_CONSTRAINED, OP_SCATTER_EVEC = 1, 2
 SOURCE_ARRAY, SOURCE_CONST, SOURCE_SINE = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
+MEAN_ARITHMETIC, MEAN_GEOMETRIC, MEAN_HARMONIC = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EUNSUPPORTED", -4: "EHIP",
           -5: "ENOTCONV", -6: "EBREAKDOWN"}
 
@@ -55,13 +56,18 @@ class IRResult(C.Structure):
                 ("rel_res", C.c_double), ("seconds", C.c_double)]
 
 
+class PMGOpts(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
+                ("coarse_iters", C.c_int32)]
+
+
 class FCGResult(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("fell_back", C.c_int32),
                 ("fallback_iter", C.c_int32), ("rel_res", C.c_double),
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 200  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 210  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -120,6 +126,18 @@ def _load():
         "pafem_fcg_workspace_bytes": (I32, [P, I32, C.POINTER(SZ)]),
         "pafem_fcg_solve": (I32, [P, P, P, P, P, P, P, SZ, C.POINTER(SolveOpts),
                                   C.POINTER(FCGResult), P]),
+        "pafem_coeff_element_mean": (I32, [P, I32, P, I32, I32, P, P]),
+        "pafem_prolongate": (I32, [P, P, P, P, I32, P]),
+        "pafem_restrict": (I32, [P, P, P, P, P, P]),
+        "pafem_smoother_workspace_bytes": (I32, [P, C.POINTER(SZ)]),
+        "pafem_op_lambda_max": (I32, [P, P, P, I32, P, SZ, C.POINTER(D), P]),
+        "pafem_chebyshev_smooth": (I32, [P, P, D, D, D, I32, P, P, I32, P, SZ, P]),
+        "pafem_pmg_create": (I32, [I32, P, P, P, C.POINTER(PMGOpts), C.POINTER(P)]),
+        "pafem_pmg_destroy": (None, [P]),
+        "pafem_pmg_workspace_bytes": (I32, [P, I32, C.POINTER(SZ)]),
+        "pafem_pmg_vcycle": (I32, [P, P, P, P, SZ, P]),
+        "pafem_pmg_fcg_solve": (I32, [P, P, P, P, SZ, C.POINTER(SolveOpts),
+                                      C.POINTER(SolveResult), P]),
         "pafem_ir_workspace_bytes": (I32, [P, P, C.POINTER(SZ)]),
         "pafem_ir_solve": (I32, [P, P, P, P, P, P, SZ, C.POINTER(IROpts), C.POINTER(IRResult), P]),
     }
@@ -309,6 +327,65 @@ def pafem_batch_describe(batch):
     return buf.value.decode()
 
 
+def pafem_coeff_element_mean(space, kind, coeff, q1d_in, q1d_out, out):
+    _check(lib.pafem_coeff_element_mean(space, int(kind), _ptr(coeff), int(q1d_in), int(q1d_out),
+                                        _ptr(out), _stream()))
+
+
+def pafem_prolongate(coarse, fine, xc, yf, add=False):
+    _check(lib.pafem_prolongate(coarse, fine, _ptr(xc), _ptr(yf), int(bool(add)), _stream()))
+
+
+def pafem_restrict(fine, coarse, bf, yf, rc):
+    _check(lib.pafem_restrict(fine, coarse, _ptr(bf), _ptr(yf), _ptr(rc), _stream()))
+
+
+def pafem_smoother_workspace_bytes(op):
+    n = C.c_size_t()
+    _check(lib.pafem_smoother_workspace_bytes(op, C.byref(n)))
+    return n.value
+
+
+def pafem_op_lambda_max(op, diag, v, iters, work):
+    lam = C.c_double()
+    _check(lib.pafem_op_lambda_max(op, _ptr(diag), _ptr(v), int(iters), _ptr(work), work.numel(),
+                                   C.byref(lam), _stream()))
+    return lam.value
+
+
+def pafem_chebyshev_smooth(op, diag, lmax, lo, hi, degree, b, x, zero_guess, work):
+    _check(lib.pafem_chebyshev_smooth(op, _ptr(diag), float(lmax), float(lo), float(hi),
+                                      int(degree), _ptr(b), _ptr(x), int(bool(zero_guess)),
+                                      _ptr(work), work.numel(), _stream()))
+
+
+def pafem_pmg_create(ops, diags, lmax, opts: PMGOpts):
+    n = len(ops)
+    oh = (C.c_void_p * n)(*[o.value for o in ops])
+    dh = _ptr_array(diags)
+    lm = (C.c_double * n)(*[float(v) for v in lmax])
+    out = C.c_void_p()
+    _check(lib.pafem_pmg_create(n, oh, dh, lm, C.byref(opts), C.byref(out)))
+    return out
+
+
+def pafem_pmg_workspace_bytes(pmg, max_iter):
+    n = C.c_size_t()
+    _check(lib.pafem_pmg_workspace_bytes(pmg, int(max_iter), C.byref(n)))
+    return n.value
+
+
+def pafem_pmg_vcycle(pmg, r, z, work):
+    _check(lib.pafem_pmg_vcycle(pmg, _ptr(r), _ptr(z), _ptr(work), work.numel(), _stream()))
+
+
+def pafem_pmg_fcg_solve(pmg, b, x, work, opts: SolveOpts):
+    res = SolveResult()
+    rc = lib.pafem_pmg_fcg_solve(pmg, _ptr(b), _ptr(x), _ptr(work), work.numel(), C.byref(opts),
+                                 C.byref(res), _stream())
+    return rc, res
+
+
 def lowered_qdata(qdata, dtype):
     """Reduced-precision copy (F32 or BF16 bits) of f64 quadrature data, on the device."""
     import torch
@@ -378,6 +455,16 @@ class Space:
                          device=self.device)
         pafem_qdata_assemble(self.handle, kind, q1d, coeff, scale, qd)
         return qd
+
+    def coeff_mean(self, coeff, q1d_in=None, q1d_out=None, kind=MEAN_ARITHMETIC):
+        """Per-element mean of a per-point coefficient, spread over another rule."""
+        import torch
+        q1d_in = self.p + 2 if q1d_in is None else q1d_in
+        q1d_out = self.p + 2 if q1d_out is None else q1d_out
+        self._check_qp_array(coeff, q1d_in, "coeff")
+        out = torch.empty(self.nelem * q1d_out ** 3, dtype=torch.float64, device=self.device)
+        pafem_coeff_element_mean(self.handle, kind, coeff, q1d_in, q1d_out, out)
+        return out
 
     def linear_form(self, source=SOURCE_SINE, q1d=None, f_qp=None, scale=1.0):
         import torch
@@ -453,6 +540,26 @@ class Operator:
             info["history"] = hist[: res.iters + 1].copy()
         return x, info
 
+    def lambda_max(self, diag, v, iters=20):
+        """Power-iteration estimate of the largest eigenvalue of diag^-1 A (v: start
+        vector, overwritten)."""
+        self._check_vec(v, "v")
+        self._check_vec(diag, "diag")
+        work = _device_bytes(pafem_smoother_workspace_bytes(self.handle), self.space.device)
+        return pafem_op_lambda_max(self.handle, diag, v, iters, work)
+
+    def chebyshev(self, diag, lmax, b, x=None, degree=2, lo=0.3, hi=1.1):
+        """degree Chebyshev-Jacobi steps on A x = b (x None: from zero)."""
+        import torch
+        zero = x is None
+        if zero:
+            x = torch.empty_like(b)
+        for v, nm in ((b, "b"), (x, "x"), (diag, "diag")):
+            self._check_vec(v, nm)
+        work = _device_bytes(pafem_smoother_workspace_bytes(self.handle), self.space.device)
+        pafem_chebyshev_smooth(self.handle, diag, lmax, lo, hi, degree, b, x, zero, work)
+        return x
+
     def ir_solve(self, lo, b, diag=None, rel_tol=1e-10, inner_rel_tol=1e-2, max_outer=50,
                  max_inner=5000, check_every=8, precond=PRECOND_JACOBI, keep_direction=True):
         """Iterative refinement with `lo` (same operator on F32/BF16 qdata) as inner solver.
@@ -480,6 +587,85 @@ class Operator:
     def __del__(self):
         if getattr(self, "handle", None):
             lib.pafem_op_destroy(self.handle)
+            self.handle = None
+
+
+def prolongate(coarse: Space, fine: Space, xc, yf=None, add=False):
+    """yf (+)= P xc: the coarse function at the fine nodes (free dofs)."""
+    import torch
+    if yf is None:
+        yf = torch.empty(fine.ndofs, dtype=torch.float64, device=fine.device)
+    for v, S, nm in ((xc, coarse, "xc"), (yf, fine, "yf")):
+        if v.numel() != S.ndofs or v.dtype != torch.float64 or not v.is_contiguous() or not v.is_cuda:
+            raise ValueError(f"{nm} must be a contiguous float64 device vector of {S.ndofs}")
+    pafem_prolongate(coarse.handle, fine.handle, xc, yf, add)
+    return yf
+
+
+def restrict(fine: Space, coarse: Space, bf, yf=None, rc=None):
+    """rc = P^T (bf - yf) on free dofs."""
+    import torch
+    if rc is None:
+        rc = torch.empty(coarse.ndofs, dtype=torch.float64, device=coarse.device)
+    for v, S, nm in ((bf, fine, "bf"), (yf, fine, "yf"), (rc, coarse, "rc")):
+        if v is None:
+            continue
+        if v.numel() != S.ndofs or v.dtype != torch.float64 or not v.is_contiguous() or not v.is_cuda:
+            raise ValueError(f"{nm} must be a contiguous float64 device vector of {S.ndofs}")
+    pafem_restrict(fine.handle, coarse.handle, bf, yf, rc)
+    return rc
+
+
+class PMG:
+    """Order-multigrid V-cycle over constrained diffusion operators (finest first) on
+    spaces of one Mesh; diagonals and largest-eigenvalue estimates per level."""
+
+    def __init__(self, ops, diags, lmax, degree=2, lo=0.3, hi=1.1, coarse_iters=20):
+        self.ops, self.diags = list(ops), list(diags)  # kept alive: the library holds pointers
+        for o, d in zip(self.ops, self.diags):
+            o._check_vec(d, "diag")
+        self.lmax = [float(v) for v in lmax]
+        self.opts = PMGOpts(int(degree), float(lo), float(hi), int(coarse_iters))
+        self.handle = pafem_pmg_create([o.handle for o in self.ops], self.diags, self.lmax,
+                                       self.opts)
+        self.device = self.ops[0].space.device
+        self._vwork = None
+
+    def vcycle(self, r, z=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        self.ops[0]._check_vec(r, "r")
+        self.ops[0]._check_vec(z, "z")
+        if self._vwork is None:
+            self._vwork = _device_bytes(pafem_pmg_workspace_bytes(self.handle, -1), self.device)
+        pafem_pmg_vcycle(self.handle, r, z, self._vwork)
+        return z
+
+    def fcg(self, b, x=None, rel_tol=1e-8, max_iter=500, check_every=4, history=True):
+        import torch
+        zero = x is None
+        if x is None:
+            x = torch.zeros_like(b)
+        self.ops[0]._check_vec(b, "b")
+        self.ops[0]._check_vec(x, "x")
+        work = _device_bytes(pafem_pmg_workspace_bytes(self.handle, max_iter), self.device)
+        hist = np.zeros(max_iter + 1) if history else None
+        opts = SolveOpts(float(rel_tol), int(max_iter), PRECOND_NONE, int(check_every), int(zero),
+                         None if hist is None else hist.ctypes.data_as(C.POINTER(C.c_double)),
+                         0 if hist is None else hist.size)
+        rc, res = pafem_pmg_fcg_solve(self.handle, b, x, work, opts)
+        if rc not in (0, -5, -6):
+            _check(rc)
+        info = {"status": STATUS.get(rc, rc), "iters": res.iters, "converged": bool(res.converged),
+                "rel_res": res.rel_res, "true_rel_res": res.true_rel_res, "seconds": res.seconds}
+        if hist is not None:
+            info["history"] = hist[: res.iters + 1].copy()
+        return x, info
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.pafem_pmg_destroy(self.handle)
             self.handle = None
 
 

@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 from scipy.spatial import cKDTree
 
+import oracle
 import synth
 from tests._common import on_boundary, patch_rows, rel_err
 
@@ -164,3 +165,88 @@ def test_batched_config_columns_match_single_applies():
               flush=True)
         assert worst <= tol
         del B
+
+
+def _element_prolongation(mesh, pc, pf, c, seed):
+    """Oracle prolongation restricted to element c alone: the coarse function built
+    from position-keyed values at c's coarse nodes (0 on the cube's faces), evaluated
+    at c's fine nodes (0 on the cube's faces), and those fine nodes' coordinates."""
+    from oracle import pmg
+    sub = synth.sub_mesh(mesh, [c])
+    Pl = pmg.interpolation(sub, pc, pf, free_only=False)
+    Xc = oracle.H1Space(sub, pc).dof_coordinates()
+    Xf = oracle.H1Space(sub, pf).dof_coordinates()
+    xc = np.where(on_boundary(Xc), 0.0, synth.hash_normal(Xc, seed=seed))
+    y = Pl @ xc
+    return np.where(on_boundary(Xf), 0.0, y), Xf
+
+
+@pytest.mark.parametrize("pf", [3, 6])
+def test_order_multigrid_at_bench_size(pf):
+    """The multigrid benchmark's problems (~1e7 dofs, orders pf -> pf/2 -> ... -> 1):
+    prolongation on sampled elements against the oracle's element-local definition
+    (1e-12); restriction is its adjoint, <P a, b> = <a, P^T b> (1e-12); a V-cycle
+    without coarse iterations (a linear map) is symmetric (1e-10); flexible CG with
+    the V-cycle reaches the Jacobi-PCG solution."""
+    n = _lattice_n(pf)
+    mesh = synth.hex_lattice(n, 0.05, seed=2)
+    E = mesh["hex"].shape[0]
+    kappa = synth.lognormal_iid(E, pf + 2, 1.0, seed=3)
+    kc = torch.as_tensor(kappa.reshape(-1), device="cuda")
+    M = P.Mesh.from_dict(mesh)
+    orders = [pf]
+    while orders[-1] > 1:
+        orders.append(orders[-1] // 2)
+    spaces = [P.Space(M, q) for q in orders]
+    print(f"multigrid p={pf}: orders {orders}, dofs {[S.ndofs for S in spaces]}", flush=True)
+    # prolongation on sampled elements
+    Sf, Sc = spaces[0], spaces[1]
+    Xf, Xc = Sf.dof_coords(), Sc.dof_coords()
+    y = P.prolongate(Sc, Sf, torch.as_tensor(synth.hash_normal(Xc, seed=5), device="cuda"))
+    y = y.cpu().numpy()
+    rng = np.random.default_rng(8)
+    got, want = [], []
+    for c in [0, E - 1] + [int(v) for v in rng.integers(0, E, size=6)]:
+        yo, Xo = _element_prolongation(mesh, orders[1], pf, c, 5)
+        lo_, hi_ = Xo.min(axis=0) - 1e-9, Xo.max(axis=0) + 1e-9
+        cand = np.flatnonzero(np.all((Xf >= lo_) & (Xf <= hi_), axis=1))
+        dist, idx = cKDTree(Xf[cand]).query(Xo)
+        assert dist.max() < 1e-10
+        got.append(y[cand[idx]])
+        want.append(yo)
+    err = rel_err(np.concatenate(got), np.concatenate(want))
+    print(f"multigrid p={pf}: sampled prolongation rel err {err:.2e}", flush=True)
+    assert err <= 1e-12
+    # restriction is the adjoint of prolongation
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    a = torch.randn(Sc.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    bf = torch.randn(Sf.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    lhs = float(torch.dot(P.prolongate(Sc, Sf, a), bf))
+    rhs = float(torch.dot(a, P.restrict(Sf, Sc, bf)))
+    print(f"multigrid p={pf}: <Pa,b> {lhs:.15e} <a,P^T b> {rhs:.15e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
+    # hierarchy
+    ops, diags, lmax = [], [], []
+    for l, S in enumerate(spaces):
+        c = kc if l == 0 else S.coeff_mean(kc, q1d_in=pf + 2, q1d_out=S.p + 2)
+        ops.append(P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=c)))
+        diags.append(ops[-1].diagonal())
+        v = torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=g)
+        lmax.append(ops[-1].lambda_max(diags[-1], v, 20))
+    lin = P.PMG(ops, diags, lmax, degree=2, coarse_iters=0)
+    u = torch.randn(Sf.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    w = torch.randn(Sf.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    s1, s2 = float(torch.dot(lin.vcycle(u), w)), float(torch.dot(u, lin.vcycle(w)))
+    print(f"multigrid p={pf}: <V u, w> {s1:.15e} <u, V w> {s2:.15e}", flush=True)
+    assert abs(s1 - s2) <= 1e-10 * (abs(s1) + abs(s2))
+    del lin
+    G = P.PMG(ops, diags, lmax, degree=2, coarse_iters=10)
+    b = Sf.linear_form(P.SOURCE_SINE)
+    x, info = G.fcg(b, rel_tol=1e-8, max_iter=300, history=False)
+    xj, ij = ops[0].pcg(b, diag=diags[0], rel_tol=1e-8, max_iter=20000, history=False)
+    diff = float((x - xj).norm() / xj.norm())
+    print(f"multigrid p={pf}: fcg {info['iters']} its (true rel res {info['true_rel_res']:.2e}), "
+          f"jacobi {ij['iters']} its, solutions differ by {diff:.2e}", flush=True)
+    assert info["converged"] and info["true_rel_res"] <= 1.5e-8
+    assert diff <= 1e-6
