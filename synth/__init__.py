@@ -1,8 +1,8 @@
 """Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
 
-This module only *generates inputs*: hexahedral lattice meshes (optionally jittered,
-warped or with rotated element vertex lists), coefficient fields and right-hand-side
-vectors.  It holds none of the finite element arithmetic (no basis, no quadrature
+This module only *generates inputs*: hexahedral and quadrilateral lattice meshes
+(optionally jittered, warped or with rotated element vertex lists), coefficient fields
+and right-hand-side vectors.  It holds none of the finite element arithmetic (no basis, no quadrature
 operator, no assembly); both the CPU oracle and the HIP library consume its arrays.
 
 Conventions fixed here and used by both sides:
@@ -92,9 +92,56 @@ def hex_lattice(n, jitter: float = 0.0, seed: int = 0,
             "geom_nodes": None}
 
 
+# Corner coordinates of the reference square in quadrilateral vertex order
+# (counter-clockwise from the origin).
+QUAD_CORNERS = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], dtype=np.int64)
+
+
+def quad_lattice(n, jitter: float = 0.0, seed: int = 0,
+                 rotate_seed: int | None = None) -> dict:
+    """Unit-square lattice of nx*ny quadrilaterals (n is an int or a 2-tuple).
+
+    Interior vertices are displaced by ``jitter * h * u`` with ``u`` uniform in the
+    unit disc (h = 1/max(n)), using ``numpy.random.default_rng(seed)``.  With
+    ``rotate_seed`` every element's vertex list is cyclically shifted by a random
+    amount (a proper rotation of the square: same geometry, other local frame).
+    Elements are numbered lexicographically (x fastest).
+    """
+    nx, ny = (int(n),) * 2 if np.isscalar(n) else tuple(int(v) for v in n)
+    mx, my = nx + 1, ny + 1
+    vy, vx = np.meshgrid(np.arange(my) / ny, np.arange(mx) / nx, indexing="ij")
+    verts = np.stack([vx.ravel(), vy.ravel()], axis=1)
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        nv = verts.shape[0]
+        d = rng.normal(size=(nv, 2))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        r = np.sqrt(rng.uniform(size=(nv, 1)))
+        disp = jitter * (1.0 / max(nx, ny)) * r * d
+        ix = np.arange(nv)
+        i0, i1 = ix % mx, ix // mx
+        interior = (i0 > 0) & (i0 < nx) & (i1 > 0) & (i1 < ny)
+        verts[interior] += disp[interior]
+    ey, ex = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    ex, ey = ex.ravel(), ey.ravel()
+    quads = np.empty((nx * ny, 4), dtype=np.int64)
+    for s, (cx, cy) in enumerate(QUAD_CORNERS):
+        quads[:, s] = (ex + cx) + mx * (ey + cy)
+    if rotate_seed is not None:
+        rng = np.random.default_rng(rotate_seed)
+        shift = rng.integers(0, 4, size=quads.shape[0])
+        idx = (np.arange(4)[None, :] + shift[:, None]) % 4
+        quads = np.take_along_axis(quads, idx, axis=1)
+    return {"vertices": verts, "quad": quads, "n": (nx, ny), "geom_order": 1,
+            "geom_nodes": None}
+
+
 def sub_mesh(mesh: dict, elems) -> dict:
     """The mesh restricted to the listed elements (vertex array kept whole)."""
     out = dict(mesh)
+    if "quad" in mesh:
+        out["quad"] = mesh["quad"][elems]
+        return out
     out["hex"] = mesh["hex"][elems]
     if mesh.get("geom_nodes") is not None:
         out["geom_nodes"] = mesh["geom_nodes"][elems]
@@ -128,10 +175,12 @@ def q2_warped_lattice(n: int, amp: float = 0.05) -> dict:
     return mesh
 
 
-def lognormal_iid(num_elems: int, q1d: int, sigma: float = 1.0, seed: int = 0) -> np.ndarray:
-    """kappa[e, q] = exp(Z), Z ~ N(0, sigma^2) i.i.d. per element and quadrature point."""
+def lognormal_iid(num_elems: int, q1d: int, sigma: float = 1.0, seed: int = 0,
+                  dim: int = 3) -> np.ndarray:
+    """kappa[e, q] = exp(Z), Z ~ N(0, sigma^2) i.i.d. per element and quadrature point
+    (q1d^dim points per element)."""
     rng = np.random.default_rng(seed)
-    return np.exp(sigma * rng.normal(size=(num_elems, q1d ** 3)))
+    return np.exp(sigma * rng.normal(size=(num_elems, q1d ** dim)))
 
 
 def lattice_quadrature_points(n: int, q1d: int) -> np.ndarray:
@@ -201,7 +250,7 @@ def hash_normal(points: np.ndarray, seed: int = 0) -> np.ndarray:
         q = np.round(np.asarray(points, dtype=np.float64) * (1 << 24)).astype(np.int64)
         q = q.view(np.uint64)
         h = _splitmix64(np.full(q.shape[:-1], np.uint64(seed), dtype=np.uint64))
-        for d in range(3):
+        for d in range(q.shape[-1]):
             h = _splitmix64(h ^ q[..., d])
         h2 = _splitmix64(h)
     u1 = ((h >> np.uint64(11)).astype(np.float64) + 0.5) / float(1 << 53)
@@ -215,8 +264,8 @@ def sine_solution(points: np.ndarray) -> np.ndarray:
 
 
 def sine_source(points: np.ndarray) -> np.ndarray:
-    """f = -Laplace(u) = 3 pi^2 u for the sine solution."""
-    return 3.0 * np.pi ** 2 * sine_solution(points)
+    """f = -Laplace(u) = d pi^2 u for the sine solution in d = points.shape[-1] dimensions."""
+    return np.asarray(points).shape[-1] * np.pi ** 2 * sine_solution(points)
 
 
 def linear_patch(points: np.ndarray) -> np.ndarray:
