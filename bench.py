@@ -289,6 +289,64 @@ def bench_pmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20,
     return out
 
 
+# The paper's table of 200 partially assembled CG iterations (2D Poisson, ~1.3M dofs),
+# read as seconds: best GPU backend (CEED-CUDA, Quadro GV100) and the 16-core MPI run.
+PAPER_2D_SECONDS = {"ceed_cuda_gv100": {1: 0.19, 2: 0.15, 4: 0.12, 8: 0.12},
+                    "mpi_16core_xeon6130": {1: 2.72, 2: 1.66, 4: 1.45, 8: 1.44}}
+
+
+def bench_paper2d(P, torch, orders=(1, 2, 4, 8), ndofs=1.3e6, iters=200, reps=3, applies=20):
+    """The paper's experiment shape: 2D Poisson on quadrilaterals, ~1.3M dofs, 200
+    unpreconditioned CG iterations with the partially assembled operator, p = 1, 2, 4, 8
+    (unit square, 5% jitter, sine right-hand side)."""
+    import math
+    import synth
+    out = {"ndofs_target": ndofs, "iterations": iters, "per_p": {},
+           "paper_seconds": PAPER_2D_SECONDS}
+    for p in orders:
+        n = max(1, int(round((math.sqrt(ndofs) - 1.0) / p)))
+        mesh = synth.quad_lattice(n, 0.05, seed=2)
+        S = P.Space(P.Mesh.from_dict(mesh), p)
+        del mesh
+        op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION))
+        b = S.linear_form(P.SOURCE_SINE)
+        best = None
+        for _ in range(reps + 1):  # first call warms up
+            x, info = op.pcg(b, rel_tol=0.0, max_iter=iters, precond=P.PRECOND_NONE,
+                             check_every=iters, history=False)
+            assert info["iters"] == iters
+            if best is not None or _ > 0:
+                best = info["seconds"] if best is None else min(best, info["seconds"])
+        xj, ij = op.pcg(b, rel_tol=0.0, max_iter=iters, check_every=iters, history=False)
+        xs = torch.randn(S.ndofs, dtype=torch.float64, device="cuda")
+        ys = torch.empty_like(xs)
+        op.apply(xs, ys)
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(applies):
+            op.apply(xs, ys)
+        e.record()
+        torch.cuda.synchronize()
+        t_apply = a.elapsed_time(e) / applies / 1e3
+        Q = p + 2
+        by = 8 * S.ndofs * 2 + 24 * S.nelem * Q * Q + 4 * S.nelem * (p + 1) ** 2
+        row = {"n": n, "ndofs": S.ndofs, "elements": S.nelem,
+               "cg200_seconds": round(best, 5),
+               "gdof_it_per_s": round(S.ndofs * iters / best / 1e9, 3),
+               "cg200_jacobi_seconds": round(ij["seconds"], 5),
+               "rel_res_after_200": info["rel_res"],
+               "apply_ms": round(t_apply * 1e3, 4),
+               "apply_gdofs": round(S.ndofs / t_apply / 1e9, 3),
+               "apply_hbm_frac": round(by / t_apply / 1e9 / HBM_PEAK_GBS, 4),
+               "speedup_vs_paper_ceed_cuda": round(PAPER_2D_SECONDS["ceed_cuda_gv100"][p] / best, 1)}
+        out["per_p"][str(p)] = row
+        log(f"paper2d p={p}: {S.ndofs} dofs, 200 CG its {best * 1e3:.2f} ms "
+            f"(paper CEED-CUDA {PAPER_2D_SECONDS['ceed_cuda_gv100'][p]} s), apply {t_apply * 1e3:.3f} ms")
+        del op, S, b, x, xj, xs, ys
+    return out
+
+
 def bench_batched(P, torch, nrhs=16, reps=20, tune_cache=None):
     """32 uneven meshes (1e4..1e6 dofs, p = 2..6), nrhs right-hand sides, one graph launch."""
     import synth
@@ -405,7 +463,7 @@ def main():
     ap.add_argument("--no-mass", action="store_true")
     ap.add_argument("--no-geom", action="store_true",
                     help="skip the recomputed-geometry diffusion variant")
-    ap.add_argument("--forms", default="mixed,batched,learned,pmg",
+    ap.add_argument("--forms", default="mixed,batched,learned,pmg,paper2d",
                     help="solver forms to measure beside the sweep ('' = none)")
     ap.add_argument("--pmg-orders", default="3,6",
                     help="orders of the sweep problems solved with order multigrid")
@@ -533,6 +591,9 @@ def main():
         for p in [int(v) for v in args.pmg_orders.split(",") if v]:
             log(f"pmg p={p}")
             out["pmg"][str(p)] = bench_pmg(P, torch, p=p, target=args.target_dofs)
+    if "paper2d" in forms:
+        log("paper2d")
+        out["paper_2d_cg200"] = bench_paper2d(P, torch)
     if "learned" in forms:
         log("learned")
         out["learned"] = bench_learned(P, torch, fields=args.learned_fields,

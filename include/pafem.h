@@ -116,6 +116,17 @@ int32_t pafem_version(void);
 pafem_status pafem_mesh_create_hex(int64_t nv, const double* xyz, int64_t ne,
                                    const int64_t* hex8, int32_t geom_order,
                                    const double* geom_nodes, pafem_mesh* out);
+
+/* A conforming quadrilateral mesh ("Meshes", 2D): nv vertices xy[nv][2], ne
+ * elements quad4[ne][4] listing each element's vertices counter-clockwise from
+ * its reference origin ((0,0), (1,0), (1,1), (0,1)); bilinear geometry.  Spaces
+ * on it are 2D: (p+1)^2 dofs per element, Q^2 quadrature points per element,
+ * diffusion qdata holds the symmetric 2x2 operator (3 values per point).  2D
+ * operators are FP64 with the atomic scatter; the mixed-precision, batched,
+ * learned and multigrid entry points return EUNSUPPORTED for them.
+ * Errors: EINVAL (index out of range, repeated vertex). */
+pafem_status pafem_mesh_create_quad(int64_t nv, const double* xy, int64_t ne, const int64_t* quad4,
+                                    pafem_mesh* out);
 void pafem_mesh_destroy(pafem_mesh mesh);
 
 /* --------------------------------------------------------------- space --- */
@@ -136,8 +147,10 @@ void pafem_space_destroy(pafem_space space);
 pafem_status pafem_space_info(pafem_space space, int64_t* ndofs, int64_t* nelem,
                               int32_t* dofs_per_elem, int64_t* nbdr);
 
-/* Host copies: dof node coordinates [ndofs][3] f64; essential dof indices
- * [nbdr] int32 ascending; element->dof map [nelem][(p+1)^3] int32. */
+/* Spatial dimension of the space's mesh (3 hexahedra, 2 quadrilaterals). */
+pafem_status pafem_space_dim(pafem_space space, int32_t* dim);
+/* Host copies: dof node coordinates [ndofs][dim] f64; essential dof indices
+ * [nbdr] int32 ascending; element->dof map [nelem][(p+1)^dim] int32. */
 pafem_status pafem_space_dof_coords(pafem_space space, double* xyz);
 pafem_status pafem_space_boundary_dofs(pafem_space space, int32_t* idx);
 pafem_status pafem_space_elem_dofs(pafem_space space, int32_t* gmap);

@@ -100,7 +100,7 @@ extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 210; }
+int32_t pafem_version(void) { return 220; }
 
 pafem_status pafem_mesh_create_hex(int64_t nv, const double* xyz, int64_t ne, const int64_t* hex8,
                                    int32_t geom_order, const double* geom_nodes,
@@ -128,6 +128,33 @@ pafem_status pafem_mesh_create_hex(int64_t nv, const double* xyz, int64_t ne, co
     m->m.hex.assign(hex8, hex8 + ne * 8);
     m->m.geom_order = geom_order;
     if (geom_order == 2) m->m.gnodes.assign(geom_nodes, geom_nodes + ne * 27 * 3);
+    *out = m;
+  });
+}
+
+pafem_status pafem_mesh_create_quad(int64_t nv, const double* xy, int64_t ne, const int64_t* quad4,
+                                    pafem_mesh* out) {
+  return guarded([&] {
+    require(out && xy && quad4, PAFEM_EINVAL, "null pointer argument");
+    require(nv > 0 && ne > 0, PAFEM_EINVAL, "mesh needs vertices and elements");
+    for (int64_t e = 0; e < ne; ++e) {
+      const int64_t* q = quad4 + e * 4;
+      for (int k = 0; k < 4; ++k) {
+        if (q[k] < 0 || q[k] >= nv)
+          throw Error(PAFEM_EINVAL,
+                      "element " + std::to_string(e) + " has a vertex index out of range");
+        for (int j = 0; j < k; ++j)
+          if (q[j] == q[k])
+            throw Error(PAFEM_EINVAL, "element " + std::to_string(e) + " repeats a vertex");
+      }
+    }
+    auto* m = new pafem_mesh_s();
+    m->m.dim = 2;
+    m->m.nv = nv;
+    m->m.ne = ne;
+    m->m.xyz.assign(xy, xy + nv * 2);
+    m->m.quad.assign(quad4, quad4 + ne * 4);
+    m->m.geom_order = 1;
     *out = m;
   });
 }
@@ -164,6 +191,13 @@ pafem_status pafem_space_info(pafem_space space, int64_t* ndofs, int64_t* nelem,
     if (nelem) *nelem = s.ne;
     if (dofs_per_elem) *dofs_per_elem = s.dpe;
     if (nbdr) *nbdr = int64_t(s.bdr.size());
+  });
+}
+
+pafem_status pafem_space_dim(pafem_space space, int32_t* dim) {
+  return guarded([&] {
+    require(space && space->s && dim, PAFEM_EINVAL, "null pointer argument");
+    *dim = space->s->dim;
   });
 }
 
@@ -248,6 +282,7 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     s.dev.p = s.p;
     s.dev.ng = s.ng;
     s.dev.tile_ne = s.tile_ne;
+    s.dev.dim = s.dim;
     s.uploaded = true;
   });
 }
@@ -258,7 +293,13 @@ pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int6
     require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM,
             PAFEM_EINVAL, "unknown operator kind");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
-    *nvalues = qdata_values(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 6 : 1);
+    if (space->s->dim == 2) {
+      require(kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
+              "recomputed geometry is built for hexahedra only");
+      *nvalues = qdata_values_2d(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 3 : 1);
+    } else {
+      *nvalues = qdata_values(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 6 : 1);
+    }
   });
 }
 
@@ -271,6 +312,8 @@ pafem_status pafem_qdata_assemble(pafem_space space, int32_t kind, int32_t q1d,
     require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM,
             PAFEM_EINVAL, "unknown operator kind");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
+    require(s.dim == 3 || kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
+            "recomputed geometry is built for hexahedra only");
     auto st = static_cast<hipStream_t>(stream);
     hip_check(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(s.dev.status), INT_MAX, 1, st),
               "status init");
@@ -290,6 +333,13 @@ pafem_status pafem_op_create(pafem_space space, int32_t kind, int32_t q1d, const
     require(out && qdata, PAFEM_EINVAL, "null pointer argument");
     require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM,
             PAFEM_EINVAL, "unknown operator kind");
+    if (s.dim == 2) {
+      require(kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
+              "recomputed geometry is built for hexahedra only");
+      require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "quadrilateral operators are FP64");
+      require(!(flags & PAFEM_OP_SCATTER_EVEC), PAFEM_EUNSUPPORTED,
+              "quadrilateral operators use the atomic scatter");
+    }
     if (kind == PAFEM_DIFFUSION_GEOM) {
       require(s.ng == 2, PAFEM_EUNSUPPORTED, "recomputed geometry needs trilinear elements");
       require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "recomputed geometry is FP64");

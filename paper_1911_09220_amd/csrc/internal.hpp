@@ -37,6 +37,20 @@ constexpr size_t qdata_index(int64_t e, int c, int q, int Q, int nc) {
   const int qz = q / qq, r = q - qz * qq;
   return ((size_t(tile) * nc + c) * Q + qz) * size_t(nt * qq) + size_t(el) * qq + r;
 }
+// Quadrilaterals: tiles of qdata_tile_2d(Q) elements (Q threads per element in the
+// apply), within a tile [component][qy][element in tile][qx].
+constexpr int qdata_tile_2d(int Q) { return (256 / Q) > 0 ? (256 / Q) : 1; }
+constexpr size_t qdata_index_2d(int64_t e, int c, int q, int Q, int nc) {
+  const int nt = qdata_tile_2d(Q);
+  const int64_t tile = e / nt;
+  const int el = int(e - tile * nt);
+  const int qy = q / Q, qx = q - qy * Q;
+  return ((size_t(tile) * nc + c) * Q + qy) * size_t(nt * Q) + size_t(el) * Q + qx;
+}
+inline int64_t qdata_values_2d(int64_t ne, int Q, int nc) {
+  const int nt = qdata_tile_2d(Q);
+  return ((ne + nt - 1) / nt) * nt * int64_t(nc) * Q * Q;
+}
 inline int64_t qdata_values(int64_t ne, int Q, int nc) {
   const int nt = qdata_tile(Q);
   return ((ne + nt - 1) / nt) * nt * int64_t(nc) * Q * Q * Q;
@@ -83,23 +97,27 @@ struct DevSpace {
   const uint16_t* tile_slot = nullptr; // [ntiles*tile_ne*D^3] node -> index in its tile's list
   int64_t ne = 0, ndofs = 0;
   int p = 0, ng = 0, tile_ne = 0;
+  int dim = 3;                         // 3: hexahedra, 2: quadrilaterals
 };
 
 struct Mesh {
+  int dim = 3;                 // 3: hexahedra, 2: quadrilaterals
   int64_t nv = 0, ne = 0;
-  std::vector<double> xyz;     // [nv][3]
-  std::vector<int64_t> hex;    // [ne][8]
+  std::vector<double> xyz;     // [nv][dim]
+  std::vector<int64_t> hex;    // [ne][8] (dim 3)
+  std::vector<int64_t> quad;   // [ne][4] counter-clockwise (dim 2)
   int geom_order = 1;
   std::vector<double> gnodes;  // [ne][27][3] for geom_order 2
 };
 
 struct Space {
   const Mesh* mesh = nullptr;
+  int dim = 3;
   int p = 0, D1 = 0, dpe = 0, ng = 0;
   int64_t ne = 0, ndofs = 0;
   std::vector<int32_t> gmap;      // [ne][dpe] dof ids, caller element order
   std::vector<int32_t> dev_order; // device element position -> caller element id
-  int tile_ne = 0;                // elements per apply tile (qdata_tile(p + 2))
+  int tile_ne = 0;                // elements per apply tile (qdata_tile(p + 2), 2D: qdata_tile_2d)
   std::vector<int32_t> tile_off, tile_dofs;
   std::vector<uint16_t> tile_slot;
   std::vector<uint8_t> bmask;     // [ndofs]

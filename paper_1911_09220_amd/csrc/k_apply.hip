@@ -446,6 +446,7 @@ bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, bool con
 }  // namespace
 
 int pa_apply_blocks(const DevSpace& sp) {
+  if (sp.dim == 2) return pa_apply2d_blocks(sp);
   return int((sp.ne + qdata_tile(sp.p + 2) - 1) / qdata_tile(sp.p + 2));
 }
 
@@ -454,6 +455,19 @@ bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool con
                      hipStream_t st, double* dotp) {
   if (q1d != sp.p + 2) return false;
   bool ok = false;
+  if (sp.dim == 2) {
+    if (evec || qdtype != PAFEM_F64 || vdtype != PAFEM_F64 ||
+        (kind != PAFEM_DIFFUSION && kind != PAFEM_MASS))
+      return false;
+    ok = launch_pa_apply_2d(sp, kind, constrained, static_cast<const double*>(qd),
+                            static_cast<const double*>(x), static_cast<double*>(out), st, dotp);
+    if (ok) {
+      hipError_t err = hipGetLastError();
+      if (err != hipSuccess)
+        throw Error(PAFEM_EHIP, std::string("apply launch: ") + hipGetErrorString(err));
+    }
+    return ok;
+  }
 #define PAFEM_ORDER_CASE(P_)                                                                   \
   case P_:                                                                                     \
     ok = launch_order<P_>(sp, kind, qdtype, vdtype, constrained, evec, qd, x, out, dotp, st); \

@@ -311,6 +311,11 @@ int grid_for(int64_t n, int block) {
 
 void launch_qdata(const DevSpace& sp, int kind, int q1d, const double* coeff, double scale,
                   double* qd, hipStream_t st) {
+  if (sp.dim == 2) {
+    launch_qdata_2d(sp, kind, q1d, coeff, scale, qd, st);
+    HIP_LAUNCH_CHECK();
+    return;
+  }
   const TabView tv = tab_view(sp, q1d);
   const int NN = sp.ng * sp.ng * sp.ng;
   const size_t lds = sizeof(double) * (3 * NN + 2 * q1d * sp.ng);
@@ -321,6 +326,11 @@ void launch_qdata(const DevSpace& sp, int kind, int q1d, const double* coeff, do
 
 void launch_linear_form_evec(const DevSpace& sp, int q1d, int source, const double* fqp,
                              double scale, double* ye, hipStream_t st) {
+  if (sp.dim == 2) {
+    launch_linear_form_evec_2d(sp, q1d, source, fqp, scale, ye, st);
+    HIP_LAUNCH_CHECK();
+    return;
+  }
   const TabView tv = tab_view(sp, q1d);
   const int NN = sp.ng * sp.ng * sp.ng, Q = q1d, D = sp.p + 1;
   const size_t lds = sizeof(double) * (3 * NN + 2 * Q * sp.ng + Q * D + Q * Q * Q + Q * Q * D +
@@ -332,6 +342,11 @@ void launch_linear_form_evec(const DevSpace& sp, int q1d, int source, const doub
 
 void launch_diagonal_evec(const DevSpace& sp, int kind, int q1d, const double* qd, double* ye,
                           hipStream_t st) {
+  if (sp.dim == 2) {
+    launch_diagonal_evec_2d(sp, kind, q1d, qd, ye, st);
+    HIP_LAUNCH_CHECK();
+    return;
+  }
   const TabView tv = tab_view(sp, q1d);
   const int Q = q1d, D = sp.p + 1;
   const size_t lds =

@@ -40,4 +40,16 @@ bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool con
                      hipStream_t st, double* dotp = nullptr);
 int pa_apply_blocks(const DevSpace& sp);
 
+// ---- quadrilaterals (k_2d.hip); the launchers above dispatch to these when sp.dim == 2 ----
+void launch_qdata_2d(const DevSpace& sp, int kind, int q1d, const double* coeff, double scale,
+                     double* qd, hipStream_t st);
+void launch_linear_form_evec_2d(const DevSpace& sp, int q1d, int source, const double* fqp,
+                                double scale, double* ye, hipStream_t st);
+void launch_diagonal_evec_2d(const DevSpace& sp, int kind, int q1d, const double* qd, double* ye,
+                             hipStream_t st);
+int pa_apply2d_blocks(const DevSpace& sp);
+// FP64, atomic scatter only
+bool launch_pa_apply_2d(const DevSpace& sp, int kind, bool constrained, const double* qd,
+                        const double* x, double* y, hipStream_t st, double* dotp);
+
 }  // namespace pafem

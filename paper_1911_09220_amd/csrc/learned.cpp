@@ -186,6 +186,7 @@ LearnedLayout learned_layout(const Op& op) {
 }
 
 void check_net_op(const Net& net, const Op& op) {
+  require(op.space->dim == 3, PAFEM_EUNSUPPORTED, "the learned preconditioner is built for hexahedra");
   require(op.qdtype == PAFEM_F64, PAFEM_EINVAL, "learned preconditioner needs an FP64 operator");
   require(op.space->p == net.d.p, PAFEM_EINVAL, "network order differs from the space order");
   require(op.space->ne <= net.rows, PAFEM_ESHAPE, "mesh has more elements than the network rows");
@@ -531,6 +532,7 @@ pafem_status pafem_learned_features(pafem_space space, const double* kappa, int3
   return guarded([&] {
     require(space && space->s && feats, PAFEM_EINVAL, "null pointer argument");
     require(space->s->uploaded, PAFEM_EINVAL, "space has no device image");
+    require(space->s->dim == 3, PAFEM_EUNSUPPORTED, "element features are built for hexahedra");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
     launch_patch_features(space->s->dev, kappa, q1d, feats, static_cast<hipStream_t>(stream));
   });

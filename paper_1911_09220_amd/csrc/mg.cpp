@@ -50,6 +50,7 @@ Interp1D make_interp(int pc, int pf) {
 }
 
 void check_pair(const Space& c, const Space& f) {
+  require(c.dim == 3 && f.dim == 3, PAFEM_EUNSUPPORTED, "order transfers are built for hexahedra");
   require(c.mesh == f.mesh, PAFEM_EINVAL, "transfer spaces must be built on the same mesh object");
   require(c.p <= f.p, PAFEM_EINVAL, "coarse order above fine order");
 }
@@ -263,6 +264,7 @@ pafem_status pafem_coeff_element_mean(pafem_space space, int32_t kind, const dou
   return guarded([&] {
     const Space& s = uploaded(space);
     require(coeff && out, PAFEM_EINVAL, "null pointer argument");
+    require(s.dim == 3, PAFEM_EUNSUPPORTED, "element means are built for hexahedra");
     require(kind == PAFEM_MEAN_ARITHMETIC || kind == PAFEM_MEAN_GEOMETRIC ||
                 kind == PAFEM_MEAN_HARMONIC,
             PAFEM_EINVAL, "unknown mean");
@@ -371,6 +373,7 @@ pafem_status pafem_pmg_create(int32_t nlevels, const pafem_op* ops, const double
                   (o.kind == PAFEM_DIFFUSION || o.kind == PAFEM_DIFFUSION_GEOM),
               PAFEM_EUNSUPPORTED, "levels must be f64 diffusion operators");
       require(o.flags & PAFEM_OP_CONSTRAINED, PAFEM_EINVAL, "levels must be constrained");
+      require(o.space->dim == 3, PAFEM_EUNSUPPORTED, "order multigrid is built for hexahedra");
       require(std::isfinite(lmax[l]) && lmax[l] > 0.0, PAFEM_EINVAL, "lmax must be positive");
       g.ops.push_back(&o);
       g.diag.push_back(diags[l]);

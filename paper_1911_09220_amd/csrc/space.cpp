@@ -116,28 +116,43 @@ uint64_t spread3(uint64_t v) {
   return v;
 }
 
+// spread the low 31 bits of v so that bit i lands at bit 2i
+uint64_t spread2(uint64_t v) {
+  v &= 0x7fffffff;
+  v = (v | (v << 16)) & 0x0000ffff0000ffffULL;
+  v = (v | (v << 8)) & 0x00ff00ff00ff00ffULL;
+  v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0fULL;
+  v = (v | (v << 2)) & 0x3333333333333333ULL;
+  v = (v | (v << 1)) & 0x5555555555555555ULL;
+  return v;
+}
+
 // Device element order: Morton (Z-curve) order of element centroids.
 std::vector<int32_t> morton_order(const Mesh& m) {
   const int64_t ne = m.ne;
+  const int dim = m.dim, nvert = dim == 2 ? 4 : 8;
+  const std::vector<int64_t>& conn = dim == 2 ? m.quad : m.hex;
   std::vector<double> c(static_cast<size_t>(ne) * 3, 0.0);
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t e = 0; e < ne; ++e) {
-    for (int k = 0; k < 8; ++k)
-      for (int a = 0; a < 3; ++a) c[size_t(e) * 3 + a] += m.xyz[size_t(m.hex[size_t(e) * 8 + k]) * 3 + a];
-    for (int a = 0; a < 3; ++a) {
-      c[size_t(e) * 3 + a] *= 0.125;
+    for (int k = 0; k < nvert; ++k)
+      for (int a = 0; a < dim; ++a)
+        c[size_t(e) * 3 + a] += m.xyz[size_t(conn[size_t(e) * nvert + k]) * dim + a];
+    for (int a = 0; a < dim; ++a) {
+      c[size_t(e) * 3 + a] /= nvert;
       lo[a] = std::min(lo[a], c[size_t(e) * 3 + a]);
       hi[a] = std::max(hi[a], c[size_t(e) * 3 + a]);
     }
   }
   std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(ne));
+  const int bits = dim == 2 ? 31 : 21;
   for (int64_t e = 0; e < ne; ++e) {
     uint64_t code = 0;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < dim; ++a) {
       const double span = hi[a] - lo[a];
       const double t = span > 0 ? (c[size_t(e) * 3 + a] - lo[a]) / span : 0.0;
-      const uint64_t qv = uint64_t(std::min(std::max(t, 0.0), 1.0) * double((1 << 21) - 1));
-      code |= spread3(qv) << a;
+      const uint64_t qv = uint64_t(std::min(std::max(t, 0.0), 1.0) * double((uint64_t(1) << bits) - 1));
+      code |= (dim == 2 ? spread2(qv) : spread3(qv)) << a;
     }
     key[size_t(e)] = {code, int32_t(e)};
   }
@@ -147,11 +162,155 @@ std::vector<int32_t> morton_order(const Mesh& m) {
   return order;
 }
 
+// Device element order, optional renumbering, apply tiles, the essential list and
+// the 1D tables: the same for every dimension once gmap and bmask are set.
+void finish_space(Space* s, const Mesh& m, int flags) {
+  const int p = s->p, dpe = s->dpe;
+  const int64_t ne = s->ne, ndofs = s->ndofs;
+  s->dev_order = morton_order(m);
+  if (flags & PAFEM_SPACE_RENUMBER) {
+    // first touch while walking the elements in device order
+    std::vector<int32_t> perm(size_t(ndofs), -1);
+    int32_t nn = 0;
+    for (int64_t k = 0; k < ne; ++k) {
+      const int32_t* g = s->gmap.data() + size_t(s->dev_order[size_t(k)]) * dpe;
+      for (int i = 0; i < dpe; ++i)
+        if (perm[size_t(g[i])] < 0) perm[size_t(g[i])] = nn++;
+    }
+    for (auto& d : s->gmap) d = perm[size_t(d)];
+    std::vector<uint8_t> bm(static_cast<size_t>(ndofs), 0);
+    for (int64_t d = 0; d < ndofs; ++d) bm[size_t(perm[d])] = s->bmask[size_t(d)];
+    s->bmask.swap(bm);
+  }
+  // apply tiles: tile_ne consecutive device elements share one list of unique dofs
+  s->tile_ne = s->dim == 2 ? qdata_tile_2d(p + 2) : qdata_tile(p + 2);
+  const int64_t ntiles = (ne + s->tile_ne - 1) / s->tile_ne;
+  s->tile_off.assign(size_t(ntiles) + 1, 0);
+  s->tile_slot.assign(size_t(ntiles) * s->tile_ne * dpe, 0);
+  s->tile_dofs.reserve(size_t(ne) * dpe / 2);
+  std::vector<int32_t> buf;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int64_t e0 = t * s->tile_ne, e1 = std::min(ne, e0 + s->tile_ne);
+    buf.clear();
+    for (int64_t k = e0; k < e1; ++k) {
+      const int32_t* g = s->gmap.data() + size_t(s->dev_order[size_t(k)]) * dpe;
+      buf.insert(buf.end(), g, g + dpe);
+    }
+    std::sort(buf.begin(), buf.end());
+    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    for (int64_t k = e0; k < e1; ++k) {
+      const int32_t* g = s->gmap.data() + size_t(s->dev_order[size_t(k)]) * dpe;
+      uint16_t* sl = s->tile_slot.data() + size_t(k) * dpe;
+      for (int i = 0; i < dpe; ++i)
+        sl[i] = uint16_t(std::lower_bound(buf.begin(), buf.end(), g[i]) - buf.begin());
+    }
+    for (int32_t d : buf) s->tile_dofs.push_back(s->bmask[size_t(d)] ? ~d : d);
+    s->tile_off[size_t(t) + 1] = int32_t(s->tile_dofs.size());
+  }
+  for (int64_t d = 0; d < ndofs; ++d)
+    if (s->bmask[size_t(d)]) s->bdr.push_back(int32_t(d));
+  s->tables = build_tables(p, s->ng);
+}
+
+// lexicographic corner c = cx + 2 cy -> slot in the counter-clockwise quad order
+constexpr int kLexToSlot2[4] = {0, 1, 3, 2};
+
+// Quadrilaterals: vertex dofs, edge dofs (each edge run from its smaller to its
+// larger vertex id), interiors; every dof on an edge of one element only is essential.
+Space* build_space_2d(const Mesh* mesh, int order, int flags) {
+  const Mesh& m = *mesh;
+  const int p = order, D1 = p + 1, dpe = D1 * D1;
+  const int64_t ne = m.ne;
+  auto* s = new Space();
+  s->mesh = mesh;
+  s->dim = 2;
+  s->p = p;
+  s->D1 = D1;
+  s->dpe = dpe;
+  s->ne = ne;
+  s->ng = 2;
+  s->ref_nodes.resize(D1);
+  gauss_lobatto_01(D1, s->ref_nodes.data());
+  auto corner = [&](int64_t e, int c) { return m.quad[size_t(e) * 4 + kLexToSlot2[c]]; };
+  // 4 edges as (axis, low corner) with bit `axis` of the corner clear
+  const int eaxis[4] = {0, 0, 1, 1}, ec0[4] = {0, 2, 0, 1};
+  int edge_slot_of[2][4] = {{0, 0, 1, 0}, {2, 3, 0, 0}};
+  std::vector<std::array<int64_t, 2>> ekeys(size_t(ne) * 4);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int k = 0; k < 4; ++k) {
+      const int64_t a = corner(e, ec0[k]), b = corner(e, ec0[k] | (1 << eaxis[k]));
+      ekeys[size_t(e) * 4 + k] = {std::min(a, b), std::max(a, b)};
+    }
+  std::vector<int64_t> erep;
+  std::vector<int32_t> emult;
+  match_keys<2>(ekeys, m.nv, erep, emult);
+  for (size_t i = 0; i < emult.size(); ++i)
+    if (emult[i] > 2) {
+      delete s;
+      throw Error(PAFEM_EINVAL, "non-conforming mesh: edge shared by more than two elements "
+                                "(element " + std::to_string(i / 4) + ")");
+    }
+  std::vector<int32_t> vdof(size_t(m.nv), -1);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int k = 0; k < 4; ++k) vdof[size_t(m.quad[size_t(e) * 4 + k])] = 0;
+  int64_t next = 0;
+  for (int64_t v = 0; v < m.nv; ++v)
+    if (vdof[size_t(v)] == 0) vdof[size_t(v)] = int32_t(next++);
+  std::vector<int32_t> eid(erep.size(), -1);
+  int64_t n_edges = 0;
+  for (size_t i = 0; i < erep.size(); ++i)
+    eid[i] = (erep[i] == int64_t(i)) ? int32_t(n_edges++) : eid[size_t(erep[i])];
+  const int64_t ebase = next;
+  const int64_t ibase = ebase + n_edges * (p - 1);
+  const int64_t ndofs = ibase + ne * int64_t(p - 1) * (p - 1);
+  if (ndofs >= (int64_t(1) << 31) - 1 || ne * int64_t(dpe) >= (int64_t(1) << 31) - 1) {
+    delete s;
+    throw Error(PAFEM_EINVAL, "problem too large for 32-bit dof indices");
+  }
+  s->ndofs = ndofs;
+  s->gmap.assign(size_t(ne) * dpe, 0);
+  s->bmask.assign(size_t(ndofs), 0);
+  for (int64_t e = 0; e < ne; ++e) {
+    int32_t* g = s->gmap.data() + size_t(e) * dpe;
+    for (int i2 = 0; i2 < D1; ++i2)
+      for (int i1 = 0; i1 < D1; ++i1) {
+        const int idx[2] = {i1, i2};
+        const bool b1 = (i1 == 0 || i1 == p), b2 = (i2 == 0 || i2 == p);
+        int64_t dof;
+        if (b1 && b2) {
+          dof = vdof[size_t(corner(e, (i1 == p) | ((i2 == p) << 1)))];
+        } else if (b1 || b2) {
+          const int a = b1 ? 1 : 0, o = 1 - a;  // a: the axis along the edge
+          const int c0 = (idx[o] == p) ? (1 << o) : 0;
+          const int k = edge_slot_of[a][c0];
+          const int64_t va = corner(e, c0), vb = corner(e, c0 | (1 << a));
+          const int tc = (va < vb) ? idx[a] : p - idx[a];
+          dof = ebase + int64_t(eid[size_t(e) * 4 + k]) * (p - 1) + (tc - 1);
+        } else {
+          dof = ibase + e * int64_t(p - 1) * (p - 1) + (i1 - 1) + int64_t(p - 1) * (i2 - 1);
+        }
+        g[i1 + D1 * i2] = int32_t(dof);
+      }
+    for (int k = 0; k < 4; ++k) {
+      if (emult[size_t(e) * 4 + k] != 1) continue;
+      const int a = eaxis[k], o = 1 - a;
+      const int v = ((ec0[k] >> o) & 1) ? p : 0;
+      for (int t = 0; t < D1; ++t) {
+        const int i1 = a == 0 ? t : v, i2 = a == 0 ? v : t;
+        s->bmask[size_t(g[i1 + D1 * i2])] = 1;
+      }
+    }
+  }
+  finish_space(s, m, flags);
+  return s;
+}
+
 }  // namespace
 
 Space* build_space(const Mesh* mesh, int order, int flags) {
   if (order < 1 || order > kMaxOrder)
     throw Error(PAFEM_EUNSUPPORTED, "order must be in 1..8, got " + std::to_string(order));
+  if (mesh->dim == 2) return build_space_2d(mesh, order, flags);
   const Mesh& m = *mesh;
   const int p = order, D1 = p + 1, dpe = D1 * D1 * D1;
   const int64_t ne = m.ne;
@@ -300,55 +459,35 @@ Space* build_space(const Mesh* mesh, int order, int flags) {
     }
   }
 
-  s->dev_order = morton_order(m);
-  if (flags & PAFEM_SPACE_RENUMBER) {
-    // first touch while walking the elements in device order
-    std::vector<int32_t> perm(size_t(ndofs), -1);
-    int32_t nn = 0;
-    for (int64_t k = 0; k < ne; ++k) {
-      const int32_t* g = s->gmap.data() + size_t(s->dev_order[size_t(k)]) * dpe;
-      for (int i = 0; i < dpe; ++i)
-        if (perm[size_t(g[i])] < 0) perm[size_t(g[i])] = nn++;
-    }
-    for (auto& d : s->gmap) d = perm[size_t(d)];
-    std::vector<uint8_t> bm(static_cast<size_t>(ndofs), 0);
-    for (int64_t d = 0; d < ndofs; ++d) bm[size_t(perm[d])] = s->bmask[size_t(d)];
-    s->bmask.swap(bm);
-  }
-  // apply tiles: tile_ne consecutive device elements share one list of unique dofs
-  s->tile_ne = qdata_tile(p + 2);
-  const int64_t ntiles = (ne + s->tile_ne - 1) / s->tile_ne;
-  s->tile_off.assign(size_t(ntiles) + 1, 0);
-  s->tile_slot.assign(size_t(ntiles) * s->tile_ne * dpe, 0);
-  s->tile_dofs.reserve(size_t(ne) * dpe / 2);
-  std::vector<int32_t> buf;
-  for (int64_t t = 0; t < ntiles; ++t) {
-    const int64_t e0 = t * s->tile_ne, e1 = std::min(ne, e0 + s->tile_ne);
-    buf.clear();
-    for (int64_t k = e0; k < e1; ++k) {
-      const int32_t* g = s->gmap.data() + size_t(s->dev_order[size_t(k)]) * dpe;
-      buf.insert(buf.end(), g, g + dpe);
-    }
-    std::sort(buf.begin(), buf.end());
-    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
-    for (int64_t k = e0; k < e1; ++k) {
-      const int32_t* g = s->gmap.data() + size_t(s->dev_order[size_t(k)]) * dpe;
-      uint16_t* sl = s->tile_slot.data() + size_t(k) * dpe;
-      for (int i = 0; i < dpe; ++i)
-        sl[i] = uint16_t(std::lower_bound(buf.begin(), buf.end(), g[i]) - buf.begin());
-    }
-    for (int32_t d : buf) s->tile_dofs.push_back(s->bmask[size_t(d)] ? ~d : d);
-    s->tile_off[size_t(t) + 1] = int32_t(s->tile_dofs.size());
-  }
-  for (int64_t d = 0; d < ndofs; ++d)
-    if (s->bmask[size_t(d)]) s->bdr.push_back(int32_t(d));
-  s->tables = build_tables(p, s->ng);
+  finish_space(s, m, flags);
   return s;
 }
 
 void space_dof_coords(const Space& s, double* xyz) {
   const Mesh& m = *s.mesh;
   const int D1 = s.D1, ng = s.ng;
+  if (s.dim == 2) {
+    std::vector<double> gn = {0.0, 1.0}, Bg(size_t(D1) * 2), Gg(size_t(D1) * 2);
+    lagrange_tables(2, gn.data(), D1, s.ref_nodes.data(), Bg.data(), Gg.data());
+    for (int64_t e = 0; e < s.ne; ++e) {
+      double X[4][2];
+      for (int k = 0; k < 4; ++k)
+        for (int a = 0; a < 2; ++a)
+          X[k][a] = m.xyz[size_t(m.quad[size_t(e) * 4 + kLexToSlot2[k]]) * 2 + a];
+      const int32_t* g = s.gmap.data() + size_t(e) * s.dpe;
+      for (int i2 = 0; i2 < D1; ++i2)
+        for (int i1 = 0; i1 < D1; ++i1) {
+          double x[2] = {0, 0};
+          for (int k2 = 0; k2 < 2; ++k2)
+            for (int k1 = 0; k1 < 2; ++k1)
+              for (int a = 0; a < 2; ++a) x[a] += Bg[i1 * 2 + k1] * Bg[i2 * 2 + k2] * X[k1 + 2 * k2][a];
+          const int32_t d = g[i1 + D1 * i2];
+          xyz[size_t(d) * 2] = x[0];
+          xyz[size_t(d) * 2 + 1] = x[1];
+        }
+    }
+    return;
+  }
   // geometry basis (linear or quadratic Lagrange on equispaced nodes) at the
   // Gauss-Lobatto nodes
   std::vector<double> gn(ng), Bg(size_t(D1) * ng), Gg(size_t(D1) * ng);
@@ -383,11 +522,11 @@ void space_dof_coords(const Space& s, double* xyz) {
 }
 
 void space_device_layout(const Space& s, size_t* off, size_t* total) {
-  const size_t nn = size_t(s.ng) * s.ng * s.ng;
+  const size_t nn = s.dim == 2 ? size_t(s.ng) * s.ng : size_t(s.ng) * s.ng * s.ng;
   size_t o = 0;
   const size_t sizes[kSpaceSegments] = {
       sizeof(int32_t) * size_t(s.ne) * s.dpe,      // 0 gmap (device order)
-      sizeof(double) * size_t(s.ne) * nn * 3,      // 1 geometry nodes (device order)
+      sizeof(double) * size_t(s.ne) * nn * s.dim,  // 1 geometry nodes (device order)
       size_t(s.ndofs),                             // 2 boundary mask
       sizeof(int32_t) * size_t(s.ndofs + 1),       // 3 transposed offsets
       sizeof(int32_t) * size_t(s.ne) * s.dpe,      // 4 transposed entries
@@ -417,9 +556,19 @@ void space_pack(const Space& s, std::vector<int32_t>& gmap_enc, std::vector<doub
     for (int i = 0; i < s.dpe; ++i)
       gmap_enc[size_t(k) * s.dpe + i] = s.bmask[size_t(g[i])] ? ~g[i] : g[i];
   }
+  if (s.dim == 2) {
+    // [element][lexicographic corner][x, y]
+    gnodes.resize(size_t(s.ne) * 8);
+    for (int64_t k = 0; k < s.ne; ++k) {
+      const int64_t e = s.dev_order[size_t(k)];
+      for (int c = 0; c < 4; ++c)
+        for (int a = 0; a < 2; ++a)
+          gnodes[size_t(k) * 8 + c * 2 + a] = m.xyz[size_t(m.quad[size_t(e) * 4 + kLexToSlot2[c]]) * 2 + a];
+    }
+  }
   const int nn = s.ng * s.ng * s.ng;
-  gnodes.resize(size_t(s.ne) * nn * 3);
-  for (int64_t k = 0; k < s.ne; ++k) {
+  if (s.dim == 3) gnodes.resize(size_t(s.ne) * nn * 3);
+  for (int64_t k = 0; k < s.ne && s.dim == 3; ++k) {
     const int64_t e = s.dev_order[size_t(k)];
     double* X = gnodes.data() + size_t(k) * nn * 3;
     if (m.geom_order == 2) {

@@ -67,7 +67,7 @@ class FCGResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 210  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 220  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -79,7 +79,9 @@ def _load():
         "pafem_last_error": (C.c_char_p, []),
         "pafem_version": (I32, []),
         "pafem_mesh_create_hex": (I32, [I64, P, I64, P, I32, P, C.POINTER(P)]),
+        "pafem_mesh_create_quad": (I32, [I64, P, I64, P, C.POINTER(P)]),
         "pafem_mesh_destroy": (None, [P]),
+        "pafem_space_dim": (I32, [P, C.POINTER(I32)]),
         "pafem_space_create_h1": (I32, [P, I32, I32, C.POINTER(P)]),
         "pafem_space_destroy": (None, [P]),
         "pafem_space_info": (I32, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32),
@@ -193,6 +195,20 @@ def pafem_mesh_create_hex(vertices, hexes, geom_order=1, geom_nodes=None):
                                      int(geom_order), None if g is None else _np_ptr(g),
                                      C.byref(out)))
     return out
+
+
+def pafem_mesh_create_quad(vertices, quads):
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    q = np.ascontiguousarray(quads, dtype=np.int64)
+    out = C.c_void_p()
+    _check(lib.pafem_mesh_create_quad(v.shape[0], _np_ptr(v), q.shape[0], _np_ptr(q), C.byref(out)))
+    return out
+
+
+def pafem_space_dim(space):
+    d = C.c_int32()
+    _check(lib.pafem_space_dim(space, C.byref(d)))
+    return d.value
 
 
 def pafem_space_create_h1(mesh, order, flags=0):
@@ -398,11 +414,20 @@ def lowered_qdata(qdata, dtype):
 # ---- handle-owning conveniences -----------------------------------------------------
 
 class Mesh:
-    def __init__(self, vertices, hexes, geom_order=1, geom_nodes=None):
-        self.handle = pafem_mesh_create_hex(vertices, hexes, geom_order, geom_nodes)
+    """Hexahedral mesh, or quadrilateral with ``quads`` (2D vertices) instead of hexes."""
+
+    def __init__(self, vertices, hexes=None, geom_order=1, geom_nodes=None, quads=None):
+        if quads is not None:
+            self.dim = 2
+            self.handle = pafem_mesh_create_quad(vertices, quads)
+        else:
+            self.dim = 3
+            self.handle = pafem_mesh_create_hex(vertices, hexes, geom_order, geom_nodes)
 
     @classmethod
     def from_dict(cls, m):
+        if "quad" in m:
+            return cls(m["vertices"], quads=m["quad"])
         return cls(m["vertices"], m["hex"], m.get("geom_order", 1), m.get("geom_nodes"))
 
     def __del__(self):
@@ -419,6 +444,7 @@ class Space:
         self.p = int(order)
         self.handle = pafem_space_create_h1(mesh.handle, order, SPACE_RENUMBER if renumber else 0)
         self.ndofs, self.nelem, self.dofs_per_elem, self.nbdr = pafem_space_info(self.handle)
+        self.dim = pafem_space_dim(self.handle)
         self.device = device
         self.buf = None
         if device is not None:
@@ -426,7 +452,7 @@ class Space:
             pafem_space_upload(self.handle, self.buf)
 
     def dof_coords(self):
-        out = np.empty((self.ndofs, 3))
+        out = np.empty((self.ndofs, self.dim))
         _check(lib.pafem_space_dof_coords(self.handle, _np_ptr(out)))
         return out
 
@@ -443,7 +469,7 @@ class Space:
     def _check_qp_array(self, a, q1d, name):
         if a is None:
             return
-        need = self.nelem * q1d ** 3
+        need = self.nelem * q1d ** self.dim
         if a.numel() != need or a.dtype != __import__("torch").float64 or not a.is_contiguous():
             raise ValueError(f"{name} must be a contiguous float64 array of {need} values")
 

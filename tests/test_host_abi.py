@@ -90,3 +90,24 @@ def test_bad_inputs():
     assert ei.value.code == -1
     with pytest.raises(pafem.PafemError):
         pafem.Mesh(mesh["vertices"], mesh["hex"], geom_order=2)   # nodes missing
+
+
+@pytest.mark.parametrize("p,rotate,renumber", [(1, False, False), (2, True, False), (3, True, True),
+                                                (4, False, False), (8, True, False)])
+def test_quad_element_dof_map_matches_oracle(p, rotate, renumber):
+    from oracle import twod
+    mesh = synth.quad_lattice((4, 3), 0.1, seed=5, rotate_seed=9 if rotate else None)
+    sp = pafem.Space(pafem.Mesh.from_dict(mesh), p, renumber=renumber, device=None)
+    ref = twod.H1Space2D(mesh, p)
+    assert sp.dim == 2 and sp.ndofs == ref.ndofs and sp.dofs_per_elem == (p + 1) ** 2
+    X = sp.dof_coords()
+    assert X.shape == (sp.ndofs, 2)
+    perm = match_by_coords(X, ref.dof_coordinates())
+    assert len(np.unique(perm)) == sp.ndofs
+    np.testing.assert_array_equal(perm[sp.elem_dofs()], ref.elem_dofs)
+    bd = np.zeros(sp.ndofs, dtype=bool)
+    bd[sp.boundary_dofs()] = True
+    np.testing.assert_array_equal(bd, ref.boundary[perm])
+    if not renumber:
+        cls = ref.dof_class[perm]          # vertices, then edges, then interiors
+        assert np.all(np.diff(cls) >= 0)
