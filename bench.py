@@ -189,6 +189,21 @@ def bench_mixed(P, torch, n=45, p=6, tol=1e-8):
     b = S.linear_form(P.SOURCE_SINE)
     diag = hi.diagonal()
     out = {"ndofs": S.ndofs, "elements": S.nelem, "order": p, "tol": tol}
+    # the refinement configuration's own tolerance, 1e-10: FP64 PCG against FP32 refinement
+    x10, i10 = hi.pcg(b, diag=diag, rel_tol=1e-10, max_iter=20000, history=False)
+    lo32 = P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, P.F32), qdata_dtype=P.F32)
+    xr, ir = hi.ir_solve(lo32, b, diag=diag, rel_tol=1e-10, inner_rel_tol=1e-2, max_outer=40,
+                         max_inner=20000, keep_direction=True)
+    out["tol_1e-10"] = {
+        "fp64_pcg": {"seconds": round(i10["seconds"], 4), "iters": i10["iters"],
+                     "true_rel_res": i10["true_rel_res"]},
+        "ir_fp32": {"seconds": round(ir["seconds"], 4), "outer": ir["outer"],
+                    "inner_iters": ir["inner_total"], "rel_res": ir["rel_res"],
+                    "solution_rel_diff_vs_fp64_pcg": float((xr - x10).norm() / x10.norm()),
+                    "speedup_vs_fp64": round(i10["seconds"] / ir["seconds"], 3)}}
+    log(f"mixed 1e-10: FP64 PCG {i10['iters']} its {i10['seconds']:.3f} s, FP32 IR "
+        f"{ir['inner_total']} inner {ir['seconds']:.3f} s")
+    del x10, xr, lo32
     x64, i64 = hi.pcg(b, diag=diag, rel_tol=tol, max_iter=20000, history=False)
     out["fp64_pcg"] = {"seconds": round(i64["seconds"], 4), "iters": i64["iters"],
                        "true_rel_res": i64["true_rel_res"]}

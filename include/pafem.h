@@ -424,6 +424,13 @@ pafem_status pafem_fcg_solve(pafem_op op, pafem_net net, const float* feats, con
                              const pafem_solve_opts* opts, pafem_fcg_result* result,
                              void* stream);
 
+/* Solver iterations (pafem_pcg_solve batches, pafem_pmg_fcg_solve pairs of
+ * iterations) are captured once per solve into a HIP graph (kernels only) and
+ * replayed on the caller's stream.  mode 0 launches every kernel directly
+ * instead; process-wide, returns the previous mode.  Results are the same up to
+ * the order of atomic sums. */
+int32_t pafem_set_graph_mode(int32_t mode);
+
 /* ---------------------------------------------------- order multigrid --- */
 /* Matrix-free preconditioning of PA operators by multigrid in the polynomial
  * order ("Scalable Linear Solvers" names it without fixing an algorithm; the

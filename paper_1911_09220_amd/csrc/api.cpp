@@ -12,6 +12,7 @@
 #include "internal.hpp"
 #include "batch_host.hpp"
 #include "capi.hpp"
+#include "graph.hpp"
 #include "launch.hpp"
 #include "solver.hpp"
 
@@ -94,13 +95,21 @@ void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st, 
 
 namespace pafem {
 thread_local std::string g_last_error;
+std::atomic<int>& graph_mode_flag() {
+  static std::atomic<int> flag{1};
+  return flag;
+}
 }
 
 extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 220; }
+int32_t pafem_version(void) { return 230; }
+
+int32_t pafem_set_graph_mode(int32_t mode) {
+  return graph_mode_flag().exchange(mode != 0 ? 1 : 0);
+}
 
 pafem_status pafem_mesh_create_hex(int64_t nv, const double* xyz, int64_t ne, const int64_t* hex8,
                                    int32_t geom_order, const double* geom_nodes,
@@ -476,6 +485,21 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
     if (!opts->zero_guess) apply_op(o, x, q, opwork, st);
     launch_cg_init<double, double>(state, partials, b, 1.0, opts->zero_guess ? nullptr : q, dg,
                                    x, r, d, opts->zero_guess, opts->rel_tol, hist, n, st);
+    // the atomic scatter's y-init of each apply is written by the preceding kernel
+    const bool evec = o.flags & PAFEM_OP_SCATTER_EVEC;
+    if (!evec) launch_scatter_init(s.dev, d, ess != nullptr, q, st);
+    auto iterations = [&](hipStream_t s2, int count) {
+      for (int k = 0; k < count; ++k) {
+        apply_op(o, d, q, opwork, s2, dotp, !evec);
+        launch_cg_alpha(state, partials, dotp, nap, ess, d, n, s2);
+        launch_cg_update(state, partials, x, r, d, q, dg, hist, n, s2);
+        if (evec)
+          launch_cg_direction(state, r, dg, d, n, s2);
+        else
+          launch_cg_direction_init(state, r, dg, d, q, ess, n, s2);
+      }
+    };
+    CapturedGraph graph;
     CGState host{};
     int launched = 0;
     while (true) {
@@ -484,11 +508,11 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
       hip_check(hipStreamSynchronize(st), "solver sync");
       if (host.done || launched >= opts->max_iter) break;
       const int batch = std::min(check, opts->max_iter - launched);
-      for (int k = 0; k < batch; ++k) {
-        apply_op(o, d, q, opwork, st, dotp);
-        launch_cg_alpha(state, partials, dotp, nap, ess, d, n, st);
-        launch_cg_update(state, partials, x, r, d, q, dg, hist, n, st);
-        launch_cg_direction(state, r, dg, d, n, st);
+      if (graphs_enabled() && batch == check && check >= 2) {
+        if (!graph.ready()) graph.capture([&](hipStream_t cs) { iterations(cs, check); });
+        graph.launch(st);
+      } else {
+        iterations(st, batch);
       }
       launched += batch;
     }

@@ -3,7 +3,8 @@
 // run on the device because they are written with Vector operations, "GPU
 // Acceleration").
 //
-// Each kernel is a fixed grid of kCGBlocks x kCGThreads threads striding over
+// Each kernel is a fixed grid of kCGBlocks x kCGThreads threads (one workgroup per
+// compute unit, so the last-block ticket sees few same-address atomics) striding over
 // the vectors.  Dot products: wave64 butterfly -> per-wave LDS -> per-block
 // partial; the last block to arrive (atomic ticket) sums the partials in index
 // order and updates the scalars, so results do not depend on scheduling.
@@ -187,6 +188,23 @@ __global__ void __launch_bounds__(kCGThreads)
   GRID_LOOP(i, n) {
     const TV zi = diag ? r[i] / diag[i] : r[i];
     d[i] = zi + beta * d[i];
+  }
+}
+
+// d = r / diag + beta d, and q = the next apply's init: d on essential dofs of a
+// constrained operator (bmask non-null), 0 elsewhere
+__global__ void __launch_bounds__(kCGThreads)
+    cg_direction_init_kernel(const CGState* st, const double* __restrict__ r,
+                             const double* __restrict__ diag, double* __restrict__ d,
+                             double* __restrict__ q, const uint8_t* __restrict__ bmask,
+                             int64_t n) {
+  if (state_done(st)) return;
+  const double beta = st->beta;
+  GRID_LOOP(i, n) {
+    const double zi = diag ? r[i] / diag[i] : r[i];
+    const double di = zi + beta * d[i];
+    d[i] = di;
+    q[i] = (bmask && bmask[i]) ? di : 0.0;
   }
 }
 
@@ -618,6 +636,13 @@ void launch_fcg_beta(CGState* st, double* partials, const double* r, const doubl
                      zold, n);
   check_launch("fcg_beta");
 }
+void launch_cg_direction_init(CGState* st, const double* r, const double* diag, double* d,
+                              double* q, const uint8_t* bmask, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(cg_direction_init_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, r,
+                     diag, d, q, bmask, n);
+  check_launch("cg_direction_init");
+}
+
 void launch_fcg_direction(CGState* st, const double* z, double* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fcg_direction_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, s, st, z, p, n);
   check_launch("fcg_direction");

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "capi.hpp"
+#include "graph.hpp"
 #include "internal.hpp"
 #include "launch.hpp"
 #include "mg.hpp"
@@ -447,7 +448,19 @@ pafem_status pafem_pmg_fcg_solve(pafem_pmg pmg, const double* b, double* x, void
                     opts->rel_tol, hist, n, st);
     vcycle(g, 0, r, z, B, st);
     launch_fcg_start(state, partials, r, z, p, n, st);
-    const int check = std::max(1, opts->check_every);
+    // one iteration: the new preconditioned residual goes to zn, zc holds the current one
+    auto iteration = [&](hipStream_t s2, double* zc, double* zn) {
+      apply_op(op, p, q, B.opwork, s2, dotp);
+      launch_cg_alpha<double>(state, partials, dotp, nap, ess, p, n, s2);
+      launch_fcg_update(state, partials, x, r, p, q, g.diag[0], ess, zn, hist, n, s2);
+      vcycle(g, 0, r, zn, B, s2);
+      launch_fcg_beta(state, partials, r, zn, zc, n, s2);
+      launch_fcg_direction(state, zn, p, n, s2);
+    };
+    const bool graphs = graphs_enabled();
+    int check = std::max(1, opts->check_every);
+    if (graphs) check += check & 1;  // whole pairs of iterations per host check
+    CapturedGraph pair;               // two iterations, z -> zold -> z
     int launched = 0;
     CGState h{};
     while (true) {
@@ -455,13 +468,17 @@ pafem_status pafem_pmg_fcg_solve(pafem_pmg pmg, const double* b, double* x, void
       hip_check(hipStreamSynchronize(st), "fcg sync");
       if (h.done != 0 || launched >= opts->max_iter || h.iter >= opts->max_iter) break;
       const int batch = std::min(check, opts->max_iter - launched);
-      for (int k = 0; k < batch; ++k) {
-        apply_op(op, p, q, B.opwork, st, dotp);
-        launch_cg_alpha<double>(state, partials, dotp, nap, ess, p, n, st);
-        launch_fcg_update(state, partials, x, r, p, q, g.diag[0], ess, zold, hist, n, st);
-        vcycle(g, 0, r, zold, B, st);
-        launch_fcg_beta(state, partials, r, zold, z, n, st);
-        launch_fcg_direction(state, zold, p, n, st);
+      int k = 0;
+      if (graphs && batch >= 2) {
+        if (!pair.ready())
+          pair.capture([&](hipStream_t cs) {
+            iteration(cs, z, zold);
+            iteration(cs, zold, z);
+          });
+        for (; k + 2 <= batch; k += 2) pair.launch(st);
+      }
+      for (; k < batch; ++k) {  // only the last batch can be odd
+        iteration(st, z, zold);
         std::swap(z, zold);
       }
       launched += batch;

@@ -24,8 +24,8 @@ struct CGState {
   uint32_t ticket[8];  // arrival counters of the last-block reductions
 };
 
-constexpr int kCGBlocks = 1024;  // fixed grid of the vector kernels = number of partials
-constexpr int kCGThreads = 256;
+constexpr int kCGBlocks = 256;  // fixed grid of the vector kernels = number of partials
+constexpr int kCGThreads = 1024;
 
 // zero the state and tickets; hist holds max_hist entries
 void launch_cg_reset(CGState* st, int32_t max_hist, hipStream_t s);
@@ -53,6 +53,10 @@ void launch_cg_update(CGState* st, double* partials, TV* x, TV* r, const TV* d, 
 template <typename TV>
 void launch_cg_direction(CGState* st, const TV* r, const TV* diag, TV* d, int64_t n,
                          hipStream_t s);
+// d = r / diag + beta d (FP64) and q = the apply init of the new d (d on the
+// essential dofs given by bmask, 0 elsewhere; bmask null: 0 everywhere)
+void launch_cg_direction_init(CGState* st, const double* r, const double* diag, double* d,
+                              double* q, const uint8_t* bmask, int64_t n, hipStream_t s);
 // Flexible CG (done = 3: the preconditioner returned r.z <= 0)
 void launch_fcg_init(CGState* st, double* partials, const double* b, const double* q, double* x,
                      double* r, int zero_guess, double rel_tol, double* hist, int64_t n,

@@ -67,7 +67,7 @@ class FCGResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 220  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 230  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -78,6 +78,7 @@ def _load():
     sig = {
         "pafem_last_error": (C.c_char_p, []),
         "pafem_version": (I32, []),
+        "pafem_set_graph_mode": (I32, [I32]),
         "pafem_mesh_create_hex": (I32, [I64, P, I64, P, I32, P, C.POINTER(P)]),
         "pafem_mesh_create_quad": (I32, [I64, P, I64, P, C.POINTER(P)]),
         "pafem_mesh_destroy": (None, [P]),
@@ -184,6 +185,12 @@ def _device_bytes(nbytes, device="cuda"):
 
 def pafem_version():
     return lib.pafem_version()
+
+
+def pafem_set_graph_mode(mode):
+    """1: replay solver iterations from HIP graphs (default); 0: direct launches.
+    Returns the previous mode."""
+    return lib.pafem_set_graph_mode(int(mode))
 
 
 def pafem_mesh_create_hex(vertices, hexes, geom_order=1, geom_nodes=None):
