@@ -14,6 +14,8 @@ Definitions followed:
 * Mass M_E = B^t D_E B, (D_E)_kk = alpha_k det J(xhat_k) rho(Phi(xhat_k)) --
   "High-Order Partial Assembly", mass-matrix equations.
 * Load b_i = int f phi_i -- eq. (abstract forms), the b_i definition.
+* Convection C_E[i, j] = sum_k alpha_k det J_k phi_i (beta . J_k^{-T} ghat_j), the
+  form int (beta . grad u) v with J^{-1} again from numpy.linalg.inv.
 * Global operator A = sum_E G_E^t A_E G_E (dense element matrices scattered into
   a sparse matrix; "Operator Decomposition" with P = identity).
 * Essential BC: the "further modifications" of FormLinearSystem ("Finite Element
@@ -105,6 +107,28 @@ def element_load(mesh, p, q1d, f):
     val, _ = tensor_basis(gauss_lobatto(p + 1), pts)
     fq = f(x) if callable(f) else np.asarray(f)
     return np.einsum("qi,eq->ei", val, w[None, :] * det * fq)
+
+
+def element_convection(mesh, p, q1d, velocity):
+    """Dense element convection matrices [E, D^3, D^3] for a(u, v) = int (beta . grad u) v.
+
+    C_E[i, j] = sum_k alpha_k det J_k phi_i(xhat_k) beta_k . (J_k^{-T} ghat_j(xhat_k))
+    ("Finite Element Abstractions", the bilinear form; the convection integrator is
+    one of the partially assembled integrators listed in "GPU Acceleration").
+    ``velocity`` is a callable on physical points [E, Q^3, 3], a 3-vector, or an
+    array [E, Q^3, 3].
+    """
+    pts, w, x, J, det = _jacobians(mesh, q1d)
+    val, grad = tensor_basis(gauss_lobatto(p + 1), pts)               # [Q^3, D^3], [3, Q^3, D^3]
+    if callable(velocity):
+        beta = velocity(x)
+    else:
+        beta = np.broadcast_to(np.asarray(velocity, dtype=np.float64), x.shape)
+    Jinv = np.linalg.inv(J)                                            # [E, Q^3, 3, 3]
+    # beta . J^{-T} g = (J^{-1} beta) . g
+    c = np.einsum("eqba,eqa->eqb", Jinv, beta) * (w[None, :] * det)[..., None]   # [E, Q^3, 3]
+    dphi = np.einsum("eqb,bqj->eqj", c, grad)                          # [E, Q^3, D^3]
+    return np.einsum("qi,eqj->eij", val, dphi)
 
 
 def assemble(space, elmats):

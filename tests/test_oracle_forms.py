@@ -252,3 +252,43 @@ def test_patch_rows_equal_whole_mesh_rows():
             idx = [int(np.argmin(np.abs(ref.coords - xo).sum(axis=1))) for xo in Xo]
             assert np.abs(ref.coords[idx] - Xo).max() < 1e-12
             np.testing.assert_allclose(yo, y[idx], rtol=1e-12, atol=1e-12 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_convection_affine_element_exact(p):
+    """Affine map x = A xhat, constant beta: C_E = det A sum_b (A^-1 beta)_b S_b with
+    S_b the tensor product of exact 1D integrals (C^T along axis b, M elsewhere)."""
+    rng = np.random.default_rng(11 + p)
+    A = np.eye(3) + 0.3 * rng.normal(size=(3, 3))
+    if np.linalg.det(A) < 0:
+        A[:, 0] *= -1
+    beta = np.array([0.7, -1.3, 0.4])
+    M1, _, C1 = _exact_1d(p)
+    g = np.linalg.solve(A, beta)
+    # C1[i, j] = int phi_i' phi_j, so int phi_i phi_j' = C1[j, i]
+    S = [_kron3(C1.T, M1, M1), _kron3(M1, C1.T, M1), _kron3(M1, M1, C1.T)]
+    want = np.linalg.det(A) * sum(g[b] * S[b] for b in range(3))
+    got = forms.element_convection(_single_element(A), p, p + 2, beta)[0]
+    np.testing.assert_allclose(got, want, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_convection_constants_and_skew_symmetry(p):
+    """C 1 = 0; for a divergence-free velocity C + C^T vanishes on functions that are
+    zero on the boundary (integration by parts), on jittered, rotated meshes."""
+    mesh = synth.hex_lattice(3, 0.1, seed=4, rotate_seed=5)
+    S = oracle.H1Space(mesh, p)
+    vel = lambda x: np.stack([x[..., 1] - 0.5, 0.5 - x[..., 0], 0.3 + 0.0 * x[..., 2]], axis=-1)
+    C = oracle.assemble(S, forms.element_convection(mesh, p, p + 2, vel)).toarray()
+    assert np.abs(C @ np.ones(S.ndofs)).max() < 1e-12 * np.abs(C).max()
+    free = ~S.boundary
+    Cf = C[np.ix_(free, free)]
+    # the velocity is linear, so every rule of q1d = p + 2 integrates it exactly on
+    # affine maps only; jittered trilinear maps leave a quadrature error
+    assert np.abs(Cf + Cf.T).max() < 5e-3 * np.abs(Cf).max()
+    flat = synth.hex_lattice(3, 0.0, rotate_seed=5)
+    S0 = oracle.H1Space(flat, p)
+    C0 = oracle.assemble(S0, forms.element_convection(flat, p, p + 2, vel)).toarray()
+    f0 = ~S0.boundary
+    C0f = C0[np.ix_(f0, f0)]
+    assert np.abs(C0f + C0f.T).max() < 1e-12 * np.abs(C0f).max()
