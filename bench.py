@@ -72,6 +72,12 @@ def algorithmic_bytes(kind: str, p: int, ne: int, ndofs: int) -> int:
     return 8 * ndofs + 8 * ndofs + d_bytes + 4 * ne * (p + 1) ** 3
 
 
+def conv_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
+    """Convection: x + y + 3 values of alpha adj(J) beta per point + element->dof map."""
+    q = p + 2
+    return 8 * ndofs + 8 * ndofs + 24 * ne * q ** 3 + 4 * ne * (p + 1) ** 3
+
+
 def geom_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
     """Recomputed-geometry diffusion: x + y + w*kappa per point + 8 corner nodes per
     element + int32 element->dof map, per apply."""
@@ -100,6 +106,10 @@ def setup_problem(P, torch, p, target, scatter):
     qm = S.qdata(P.MASS, coeff=kappa)
     qg = S.qdata(P.DIFFUSION_GEOM, coeff=kappa)
     del kappa
+    # convection with the constant velocity (1, 1/2, 1/4)
+    beta = torch.tensor([1.0, 0.5, 0.25], dtype=torch.float64, device="cuda").repeat(ne * (p + 2) ** 3)
+    qc = S.qdata(P.CONVECTION, coeff=beta)
+    del beta
     gen = torch.Generator(device="cuda")
     gen.manual_seed(100 + p)
     x = torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=gen)
@@ -108,6 +118,7 @@ def setup_problem(P, torch, p, target, scatter):
         "diff": P.Operator(S, P.DIFFUSION, qd, scatter=scatter),
         "mass": P.Operator(S, P.MASS, qm, scatter=scatter),
         "geom": P.Operator(S, P.DIFFUSION_GEOM, qg, scatter=scatter),
+        "conv": P.Operator(S, P.CONVECTION, qc, scatter=scatter),
         "x": x, "y": torch.empty_like(x),
     }
 
@@ -478,6 +489,7 @@ def main():
     ap.add_argument("--no-mass", action="store_true")
     ap.add_argument("--no-geom", action="store_true",
                     help="skip the recomputed-geometry diffusion variant")
+    ap.add_argument("--no-conv", action="store_true", help="skip the convection operator")
     ap.add_argument("--forms", default="mixed,batched,learned,pmg,paper2d",
                     help="solver forms to measure beside the sweep ('' = none)")
     ap.add_argument("--pmg-orders", default="3,6",
@@ -536,6 +548,14 @@ def main():
                                   "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4),
                                   "speedup_vs_stored": round(td / t, 3)}
 
+    conv = {}
+    if not args.no_conv:
+        cper, _ = time_applies(torch, probs, "conv", max(3, args.steps // 2), 1)
+        for pr, t in zip(probs, cper):
+            by = conv_algorithmic_bytes(pr["p"], pr["ne"], pr["ndofs"])
+            conv[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
+                                  "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
+
     # dominant kernel: the order whose apply takes the longest
     k = max(range(len(probs)), key=lambda i: per[i])
     dom = probs[k]
@@ -584,7 +604,8 @@ def main():
                                f"dofs for p={args.orders}, 5% vertex jitter, lognormal kappa "
                                f"(sigma=1) per quadrature point, q1d=p+2, Dirichlet boundary",
                    "orders": orders, "scatter": args.scatter, "per_p": per_p,
-                   "mass_apply": mass, "recomputed_geometry_apply": geom, "setup_seconds": round(t_setup, 1),
+                   "mass_apply": mass, "recomputed_geometry_apply": geom,
+                   "convection_apply": conv, "setup_seconds": round(t_setup, 1),
                    "timed_wall_seconds": round(wall, 4)},
         "roofline": roofline,
         "cg_time_to_1e-8": cg,

@@ -66,6 +66,11 @@ typedef int32_t pafem_status;
  * PAFEM_DIFFUSION up to rounding; FP64, trilinear meshes only; the diagonal is
  * taken from a PAFEM_DIFFUSION operator of the same space and coefficient. */
 #define PAFEM_DIFFUSION_GEOM 2
+/* Convection a(u, v) = int (beta . grad u) v, one of the integrators the paper
+ * lists among its partially assembled kernels ("GPU Acceleration"): D_q =
+ * alpha_q det J_q J_q^{-1} beta_q (3 values per point), applied as
+ * B^t (D . (B G u)).  Not symmetric: no diagonal, no CG.  FP64, hexahedra. */
+#define PAFEM_CONVECTION 3
 
 /* Storage types. */
 #define PAFEM_F64 0
@@ -174,12 +179,16 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
  *                            layout [E][6][Q^3].
  *   diffusion with recomputed geometry (PAFEM_DIFFUSION_GEOM): E * Q^3 values
  *                            alpha_q kappa_q.
+ *   convection: E * 3 * Q^3  D_q = alpha_q det J_q J_q^{-1} beta_q.
+ * Quadrilateral spaces: Q^2 points per element, diffusion 3 components
+ * (00, 01, 11), mass 1.  All layouts are padded to whole apply tiles.
  * Errors: EUNSUPPORTED if q1d is not one of the built rules (q1d = p+2). */
 pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int64_t* nvalues);
 
 /* PA setup: geometric factors (Jacobian of the element map at every
  * quadrature point) and D, written as f64 to device `qdata`.
- *  coeff: device [E][Q^3] f64 coefficient (kappa or rho) or NULL for 1.
+ *  coeff: device [E][Q^3] f64 coefficient (kappa or rho) or NULL for 1; for
+ *         PAFEM_CONVECTION the velocity [E][Q^3][3] (required).
  *  coeff_scale: multiplies the coefficient.
  * SYNCHRONOUS: returns EINVAL naming the first element with det J <= 0. */
 pafem_status pafem_qdata_assemble(pafem_space space, int32_t kind, int32_t q1d,

@@ -105,7 +105,7 @@ extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 230; }
+int32_t pafem_version(void) { return 240; }
 
 int32_t pafem_set_graph_mode(int32_t mode) {
   return graph_mode_flag().exchange(mode != 0 ? 1 : 0);
@@ -299,15 +299,17 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
 pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int64_t* nvalues) {
   return guarded([&] {
     require(space && space->s && nvalues, PAFEM_EINVAL, "null pointer argument");
-    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM,
+    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM ||
+                kind == PAFEM_CONVECTION,
             PAFEM_EINVAL, "unknown operator kind");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
     if (space->s->dim == 2) {
-      require(kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
-              "recomputed geometry is built for hexahedra only");
+      require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, PAFEM_EUNSUPPORTED,
+              "quadrilaterals support the mass and diffusion operators");
       *nvalues = qdata_values_2d(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 3 : 1);
     } else {
-      *nvalues = qdata_values(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 6 : 1);
+      const int nc = kind == PAFEM_DIFFUSION ? 6 : kind == PAFEM_CONVECTION ? 3 : 1;
+      *nvalues = qdata_values(space->s->ne, q1d, nc);
     }
   });
 }
@@ -318,11 +320,14 @@ pafem_status pafem_qdata_assemble(pafem_space space, int32_t kind, int32_t q1d,
   return guarded([&] {
     const Space& s = uploaded_space(space);
     require(qdata != nullptr, PAFEM_EINVAL, "null qdata");
-    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM,
+    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM ||
+                kind == PAFEM_CONVECTION,
             PAFEM_EINVAL, "unknown operator kind");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
-    require(s.dim == 3 || kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
-            "recomputed geometry is built for hexahedra only");
+    require(s.dim == 3 || kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, PAFEM_EUNSUPPORTED,
+            "quadrilaterals support the mass and diffusion operators");
+    require(kind != PAFEM_CONVECTION || coeff, PAFEM_EINVAL,
+            "the convection operator needs the velocity field");
     auto st = static_cast<hipStream_t>(stream);
     hip_check(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(s.dev.status), INT_MAX, 1, st),
               "status init");
@@ -340,8 +345,13 @@ pafem_status pafem_op_create(pafem_space space, int32_t kind, int32_t q1d, const
   return guarded([&] {
     const Space& s = uploaded_space(space);
     require(out && qdata, PAFEM_EINVAL, "null pointer argument");
-    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM,
+    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM ||
+                kind == PAFEM_CONVECTION,
             PAFEM_EINVAL, "unknown operator kind");
+    if (kind == PAFEM_CONVECTION) {
+      require(s.dim == 3, PAFEM_EUNSUPPORTED, "the convection operator is built for hexahedra");
+      require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "the convection operator is FP64");
+    }
     if (s.dim == 2) {
       require(kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
               "recomputed geometry is built for hexahedra only");
@@ -396,6 +406,8 @@ pafem_status pafem_op_diagonal(pafem_op op, double* diag, void* work, size_t wor
     require(op->op.qdtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "diagonal needs f64 qdata");
     require(op->op.kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
             "diagonal: use the PAFEM_DIFFUSION operator of the same space and coefficient");
+    require(op->op.kind != PAFEM_CONVECTION, PAFEM_EUNSUPPORTED,
+            "diagonal of the convection operator is not built");
     require(work && work_bytes >= op_work_bytes(op->op), PAFEM_ESHAPE, "workspace too small");
     const Op& o = op->op;
     const Space& s = *o.space;
@@ -448,6 +460,7 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
     require(op && b && x && work && opts && result, PAFEM_EINVAL, "null pointer argument");
     const Op& o = op->op;
     require(o.qdtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "PCG needs an f64 operator");
+    require(o.kind != PAFEM_CONVECTION, PAFEM_EINVAL, "CG needs a symmetric operator");
     require(opts->precond == PAFEM_PRECOND_NONE || opts->precond == PAFEM_PRECOND_JACOBI,
             PAFEM_EINVAL, "unknown preconditioner");
     require(opts->precond == PAFEM_PRECOND_NONE || diag, PAFEM_EINVAL,

@@ -51,10 +51,14 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   constexpr int NE = elems_per_block<Q>();
   // GEOM: diffusion storing alpha kappa per point; J recomputed from the 8 corners
   constexpr bool GEOM = (KIND == PAFEM_DIFFUSION_GEOM);
-  constexpr bool DIFF = (KIND == PAFEM_DIFFUSION) || GEOM;
-  constexpr int NC = (DIFF && !GEOM) ? 6 : 1;   // stored values per quadrature point
-  constexpr int NA = DIFF ? 2 : 1;   // arrays after the x-lines (B and G along x)
-  constexpr int NCC = DIFF ? 3 : 1;  // arrays after the y-lines (one per derivative)
+  constexpr bool DIFF = (KIND == PAFEM_DIFFUSION) || GEOM;  // gradient in, gradient out
+  // CONV: convection, gradient in, value out (the back contractions are the mass ones)
+  constexpr bool CONV = (KIND == PAFEM_CONVECTION);
+  constexpr bool GRAD = DIFF || CONV;  // the forward contractions produce the gradient
+  constexpr int NC = GEOM ? 1 : DIFF ? 6 : CONV ? 3 : 1;  // stored values per point
+  constexpr int NA = GRAD ? 2 : 1;   // arrays after the x-lines (B and G along x)
+  constexpr int NCC = GRAD ? 3 : 1;  // arrays after the y-lines (one per derivative)
+  static_assert(!(CONV && DOT), "the convection operator has no energy");
   // Line stride: odd, so that threads walking consecutive lines hit distinct banks.
   constexpr int LC = D | 1;
   constexpr int ELEM = NCC * QQ * LC;
@@ -134,10 +138,10 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll
       for (int dx = 0; dx < D; ++dx) {
         b += bB(qx, dx) * u[dx];
-        if (DIFF) g += bG(qx, dx) * u[dx];
+        if (GRAD) g += bG(qx, dx) * u[dx];
       }
       at(xy / Q, xy % Q, qx, xz) = b;
-      if (DIFF) at((D + xy) / Q, (D + xy) % Q, qx, xz) = g;
+      if (GRAD) at((D + xy) / Q, (D + xy) % Q, qx, xz) = g;
     }
   }
   __syncthreads();
@@ -154,7 +158,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll
     for (int dy = 0; dy < D; ++dy) {
       aB[dy] = at(dy / Q, dy % Q, yx, yz);
-      if (DIFF) aG[dy] = at((D + dy) / Q, (D + dy) % Q, yx, yz);
+      if (GRAD) aG[dy] = at((D + dy) / Q, (D + dy) % Q, yx, yz);
     }
 #pragma unroll
     for (int qy = 0; qy < Q; ++qy) {
@@ -162,12 +166,12 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll
       for (int dy = 0; dy < D; ++dy) {
         bb += bB(qy, dy) * aB[dy];
-        if (DIFF) {
+        if (GRAD) {
           gb += bB(qy, dy) * aG[dy];
           bg += bG(qy, dy) * aB[dy];
         }
       }
-      if (DIFF) {
+      if (GRAD) {
         at(0, qy, yx, yz) = gb;
         at(1, qy, yx, yz) = bg;
         at(2, qy, yx, yz) = bb;
@@ -212,7 +216,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll
     for (int dz = 0; dz < D; ++dz) {
       c0[dz] = at(0, zy, zx, dz);
-      if (DIFF) {
+      if (GRAD) {
         c1[dz] = at(1, zy, zx, dz);
         c2[dz] = at(2, zy, zx, dz);
       }
@@ -275,6 +279,18 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
           t1[dz] += bB(qz, dz) * vy;
           t2[dz] += bG(qz, dz) * vz;
         }
+      } else if constexpr (CONV) {
+        // (beta . grad u) at the point: w adj(J) beta . (reference gradient)
+        TC ux = TC(0), uy = TC(0), uz = TC(0);
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) {
+          ux += bB(qz, dz) * c0[dz];
+          uy += bB(qz, dz) * c1[dz];
+          uz += bG(qz, dz) * c2[dz];
+        }
+        const TC v = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * v;
       } else {
         TC u = TC(0);
 #pragma unroll
@@ -413,6 +429,16 @@ bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, bool con
                   bool evec, const void* qd, const void* x, void* out, double* dotp,
                   hipStream_t st) {
   const bool diff = kind == PAFEM_DIFFUSION;
+  if (kind == PAFEM_CONVECTION) {
+    if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp) return false;
+    if (evec)
+      launch_one<P, PAFEM_CONVECTION, true, false, double, double, double>(sp, constrained, qd, x,
+                                                                            out, nullptr, st);
+    else
+      launch_one<P, PAFEM_CONVECTION, false, false, double, double, double>(sp, constrained, qd, x,
+                                                                             out, nullptr, st);
+    return true;
+  }
   if (kind == PAFEM_DIFFUSION_GEOM) {
     if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || sp.ng != 2) return false;
     launch_mode<P, PAFEM_DIFFUSION_GEOM, double, double, double>(sp, constrained, evec, qd, x, out,

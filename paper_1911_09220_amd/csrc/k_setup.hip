@@ -99,6 +99,13 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* _
     const double c = scale * (coeff ? coeff[size_t(orig[e]) * QQQ + q] : 1.0);
     if (kind == PAFEM_MASS) {
       qd[qdata_index(e, 0, q, Q, 1)] = w * c * det;
+    } else if (kind == PAFEM_CONVECTION) {
+      // alpha det J J^{-1} beta = alpha adj(J) beta, beta = scale * velocity at the point
+      const double* v = coeff + (size_t(orig[e]) * QQQ + q) * 3;
+      const double b0 = scale * v[0], b1 = scale * v[1], b2 = scale * v[2];
+      qd[qdata_index(e, 0, q, Q, 3)] = w * (A00 * b0 + A01 * b1 + A02 * b2);
+      qd[qdata_index(e, 1, q, Q, 3)] = w * (A10 * b0 + A11 * b1 + A12 * b2);
+      qd[qdata_index(e, 2, q, Q, 3)] = w * (A20 * b0 + A21 * b1 + A22 * b2);
     } else if (kind == PAFEM_DIFFUSION_GEOM) {
       qd[qdata_index(e, 0, q, Q, 1)] = w * c;  // the apply recomputes the geometric part
     } else {

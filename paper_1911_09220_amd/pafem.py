@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpafem.so")
 
-MASS, DIFFUSION, DIFFUSION_GEOM = 0, 1, 2
+MASS, DIFFUSION, DIFFUSION_GEOM, CONVECTION = 0, 1, 2, 3
 F64, F32, BF16 = 0, 1, 2
 SPACE_RENUMBER = 1
 OP_CONSTRAINED, OP_SCATTER_EVEC = 1, 2
@@ -67,7 +67,7 @@ class FCGResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 230  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 240  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -481,9 +481,15 @@ class Space:
             raise ValueError(f"{name} must be a contiguous float64 array of {need} values")
 
     def qdata(self, kind, q1d=None, coeff=None, scale=1.0):
+        """Quadrature data of an operator kind; coeff per point [E*Q^dim] (for
+        CONVECTION the velocity, [E*Q^3*3])."""
         import torch
         q1d = self.p + 2 if q1d is None else q1d
-        self._check_qp_array(coeff, q1d, "coeff")
+        if kind == CONVECTION:
+            if coeff is None or coeff.numel() != self.nelem * q1d ** 3 * 3 or not coeff.is_contiguous():
+                raise ValueError("convection needs a contiguous velocity [E][Q^3][3]")
+        else:
+            self._check_qp_array(coeff, q1d, "coeff")
         qd = torch.empty(pafem_qdata_size(self.handle, kind, q1d), dtype=torch.float64,
                          device=self.device)
         pafem_qdata_assemble(self.handle, kind, q1d, coeff, scale, qd)

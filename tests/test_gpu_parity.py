@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import forms
 import synth
 from tests._common import OracleProblem, match_by_coords, rel_err
 
@@ -297,3 +298,47 @@ def test_pcg_with_recomputed_geometry():
     assert err < 1e-10
     r = oracle.pcg(ref.Kc, bref, ref.Kc.diagonal(), tol=1e-12)
     assert abs(r["iters"] - info["iters"]) <= 2
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_convection_apply(p):
+    """int (beta . grad u) v with a seeded random velocity per quadrature point, on
+    rotated jittered elements: the oracle's constrained matrix to 1e-12 in both scatter
+    modes; unconstrained, constants are annihilated."""
+    mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=60 + p, rotate_seed=160 + p)
+    E = mesh["hex"].shape[0]
+    Q = p + 2
+    beta = np.random.default_rng(61 + p).normal(size=(E, Q ** 3, 3))
+    S, X, _ = _setup(mesh, p)
+    qd = S.qdata(P.CONVECTION, coeff=_cuda(beta.reshape(-1)))
+    ref = oracle.H1Space(mesh, p)
+    C = oracle.assemble(ref, forms.element_convection(mesh, p, Q, beta))
+    Cc, _ = oracle.constrain(C, np.zeros(ref.ndofs), ref.boundary)
+    perm = match_by_coords(X, ref.dof_coordinates())
+    want = (Cc @ synth.hash_normal(ref.dof_coordinates(), seed=62 + p))[perm]
+    x = _cuda(synth.hash_normal(X, seed=62 + p))
+    for scatter in ("atomic", "evec"):
+        y = P.Operator(S, P.CONVECTION, qd, scatter=scatter).apply(x).cpu().numpy()
+        err = rel_err(y, want)
+        print(f"convection p={p} {scatter}: rel err {err:.2e}")
+        assert err <= TOL
+    free = P.Operator(S, P.CONVECTION, qd, constrained=False)
+    one = torch.ones(S.ndofs, dtype=torch.float64, device="cuda")
+    scale = float(free.apply(x).abs().max())
+    assert float(free.apply(one).abs().max()) <= 1e-12 * scale
+
+
+def test_convection_limits():
+    S = P.Space(P.Mesh.from_dict(synth.hex_lattice(2, 0.1, seed=1)), 2)
+    beta = torch.ones(S.nelem * 64 * 3, dtype=torch.float64, device="cuda")
+    qd = S.qdata(P.CONVECTION, coeff=beta)
+    op = P.Operator(S, P.CONVECTION, qd)
+    with pytest.raises(P.PafemError):
+        op.diagonal()
+    with pytest.raises(P.PafemError):
+        op.pcg(torch.ones(S.ndofs, dtype=torch.float64, device="cuda"),
+               diag=torch.ones(S.ndofs, dtype=torch.float64, device="cuda"))
+    with pytest.raises(P.PafemError):
+        P.Operator(S, P.CONVECTION, P.lowered_qdata(qd, P.F32), qdata_dtype=P.F32)
+    with pytest.raises(ValueError):
+        S.qdata(P.CONVECTION)
