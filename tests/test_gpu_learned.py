@@ -112,8 +112,8 @@ def test_zero_basis_is_jacobi():
     assert float((z - jac).abs().max()) == 0.0
 
 
-def test_preconditioner_and_loss_gradients_vs_oracle():
-    p = 2
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_preconditioner_and_loss_gradients_vs_oracle(p):
     mesh, kappa, S, op, diag, feats, ref = _small_problem(p)
     net = P.Net(p, hidden=32, max_rows=S.nelem, max_train_rows=S.nelem)
     params = _params(net, 8)
