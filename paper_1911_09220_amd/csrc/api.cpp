@@ -252,7 +252,8 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
             "device buffer too small: need " + std::to_string(total) + " bytes");
     std::vector<int32_t> gmap_enc, toff, tidx;
     std::vector<double> gnodes;
-    space_pack(s, gmap_enc, gnodes, toff, tidx);
+    std::vector<uint32_t> owner;
+    space_pack(s, gmap_enc, gnodes, toff, tidx, owner);
     auto st = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(device_buf);
     auto up = [&](int seg, const void* src, size_t bytes, const char* what) {
@@ -271,6 +272,7 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     up(10, s.tile_slot.data(), s.tile_slot.size() * 2, "upload tile slots");
     const std::vector<float> tables32(s.tables.begin(), s.tables.end());
     up(11, tables32.data(), tables32.size() * 4, "upload FP32 tables");
+    up(12, owner.data(), owner.size() * 4, "upload owner bits");
     hip_check(hipStreamSynchronize(st), "upload sync");
     s.dev_buf = device_buf;
     s.dev_bytes = nbytes;
@@ -286,6 +288,7 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     s.dev.tile_dofs = reinterpret_cast<const int32_t*>(base + off[9]);
     s.dev.tile_slot = reinterpret_cast<const uint16_t*>(base + off[10]);
     s.dev.tables32 = reinterpret_cast<const float*>(base + off[11]);
+    s.dev.owner = reinterpret_cast<const uint32_t*>(base + off[12]);
     s.dev.ne = s.ne;
     s.dev.ndofs = s.ndofs;
     s.dev.p = s.p;

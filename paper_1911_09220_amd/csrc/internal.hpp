@@ -95,6 +95,7 @@ struct DevSpace {
   const int32_t* tile_off = nullptr;   // [ntiles+1] offsets into tile_dofs
   const int32_t* tile_dofs = nullptr;  // unique dofs of each apply tile (~g if essential)
   const uint16_t* tile_slot = nullptr; // [ntiles*tile_ne*D^3] node -> index in its tile's list
+  const uint32_t* owner = nullptr;     // [ne][owner_words(D^dim)] first-occurrence bits
   int64_t ne = 0, ndofs = 0;
   int p = 0, ng = 0, tile_ne = 0;
   int dim = 3;                         // 3: hexahedra, 2: quadrilaterals
@@ -134,11 +135,15 @@ struct Space {
 // space.cpp
 Space* build_space(const Mesh* mesh, int order, int flags);
 void space_dof_coords(const Space& s, double* xyz);
-constexpr int kSpaceSegments = 12;
+constexpr int kSpaceSegments = 13;
+// words of the per-element owner bitmask (bit i of element k: node i is the first
+// occurrence of its dof in device element order)
+inline int owner_words(int dpe) { return (dpe + 31) / 32; }
 void space_device_layout(const Space& s, size_t* offsets /*[kSpaceSegments+1]*/, size_t* total);
 // host copies of every device array, in upload order
 void space_pack(const Space& s, std::vector<int32_t>& gmap_enc, std::vector<double>& gnodes,
-                std::vector<int32_t>& toff, std::vector<int32_t>& tidx);
+                std::vector<int32_t>& toff, std::vector<int32_t>& tidx,
+                std::vector<uint32_t>& owner);
 
 struct Op {
   const Space* space = nullptr;

@@ -6,8 +6,9 @@
 //   order (a Morton order of the mesh's elements), so element k of one is element k of
 //   the other.  Prolongation evaluates the coarse function at the fine nodes of each
 //   element by three one-axis contractions with the 1D table I[xf][xc] = phi^c_xc at
-//   fine node xf; each fine dof is written by one element only, its owner (the first
-//   entry of its transposed-map list).  Restriction is the exact transpose: every fine
+//   fine node xf (sizes fixed at compile time per pair of orders); each fine dof is
+//   written by one element only, its owner (the first entry of its transposed-map list,
+//   marked in a per-element bitmask of the space image).  Restriction is the exact transpose: every fine
 //   value enters once (through its owner), contracted with I^T, and added into the
 //   coarse vector with one atomic per element node.
 // * Chebyshev-Jacobi smoothing and power-iteration vector kernels.
@@ -23,66 +24,78 @@ namespace pafem {
 namespace {
 
 constexpr int kMgThreads = 256;
-constexpr int kMgLdsDoubles = 4096;  // 32 KB of LDS per workgroup
 
+// grid-stride loop, unrolled so each thread keeps several independent loads in flight
 #define GRID_LOOP(i, n)                                                     \
+  _Pragma("unroll 4")                                                       \
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < (n); \
        i += int64_t(gridDim.x) * blockDim.x)
 
 struct TransferArgs {
   const int32_t* gmap_c;  // coarse element->dof map (~g on essential dofs)
   const int32_t* gmap_f;  // fine element->dof map
-  const int32_t* toff_f;  // fine transposed-map offsets
-  const int32_t* tidx_f;  // fine transposed-map entries (element-vector positions, ascending)
+  const uint32_t* own_f;  // fine owner bits: node is the first occurrence of its dof
   int64_t ne;
-  int dc, df;             // 1D nodes of the coarse / fine order
-  int nel;                // elements per workgroup
 };
 
-// true if element-vector position `pos` is the first occurrence of dof g
-__device__ __forceinline__ bool owns(const TransferArgs& a, int32_t g, int64_t pos) {
-  return int64_t(a.tidx_f[a.toff_f[g]]) == pos;
+template <int DC, int DF>
+struct TransferShape {
+  static constexpr int DC3 = DC * DC * DC, DF3 = DF * DF * DF;
+  static constexpr int W = (DF3 + 31) / 32;  // owner words per element
+  // elements per workgroup: as many as fit 32 KB of LDS (at most 64)
+  static constexpr int fit(int per) { return (4096 / per) < 1 ? 1 : (4096 / per) > 64 ? 64 : (4096 / per); }
+  static constexpr int NELP = fit(DC3 + DC * DC * DF + DC * DF * DF);  // prolongation
+  static constexpr int NELR = fit(DF3 + DC * DF * DF + DC * DC * DF);  // restriction
+};
+
+__device__ __forceinline__ bool owns(const uint32_t* own, int W, int64_t e, int l) {
+  return (own[e * W + (l >> 5)] >> (l & 31)) & 1u;
 }
 
+static_assert(TransferShape<9, 9>::NELR * (729 * 3) * 8 <= 32768, "transfer LDS");
+
+template <int DC, int DF>
 __global__ void __launch_bounds__(kMgThreads)
     prolong_kernel(TransferArgs a, Interp1D I, const double* __restrict__ xc,
                    double* __restrict__ out, int add) {
-  extern __shared__ double lds[];
-  const int dc = a.dc, df = a.df;
-  const int dc3 = dc * dc * dc, df3 = df * df * df;
-  const int64_t e0 = int64_t(blockIdx.x) * a.nel;
-  const int nel = int(min(int64_t(a.nel), a.ne - e0));
-  double* u = lds;                          // [nel][dc][dc][dc]
-  double* t1 = u + a.nel * dc3;             // [nel][zc][yc][xf]
-  double* t2 = t1 + a.nel * dc * dc * df;   // [nel][zc][yf][xf]
-  for (int i = threadIdx.x; i < nel * dc3; i += blockDim.x) {
-    const int32_t g = a.gmap_c[e0 * dc3 + i];
+  using S = TransferShape<DC, DF>;
+  constexpr int NEL = S::NELP, DC3 = S::DC3, DF3 = S::DF3;
+  __shared__ double u[NEL * DC3];             // [el][zc][yc][xc]
+  __shared__ double t1[NEL * DC * DC * DF];   // [el][zc][yc][xf]
+  __shared__ double t2[NEL * DC * DF * DF];   // [el][zc][yf][xf]
+  const int64_t e0 = int64_t(blockIdx.x) * NEL;
+  const int nel = int(min(int64_t(NEL), a.ne - e0));
+  for (int i = threadIdx.x; i < nel * DC3; i += kMgThreads) {
+    const int32_t g = a.gmap_c[e0 * DC3 + i];
     u[i] = g >= 0 ? xc[g] : 0.0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nel * dc * dc * df; i += blockDim.x) {
-    const int xf = i % df, line = i / df;  // line = (e, zc, yc)
+  for (int i = threadIdx.x; i < nel * DC * DC * DF; i += kMgThreads) {
+    const int xf = i % DF, line = i / DF;  // line = (el, zc, yc)
     double s = 0.0;
-    for (int k = 0; k < dc; ++k) s += I.v[xf * dc + k] * u[line * dc + k];
+#pragma unroll
+    for (int k = 0; k < DC; ++k) s += I.v[xf * DC + k] * u[line * DC + k];
     t1[i] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nel * dc * df * df; i += blockDim.x) {
-    const int xf = i % df, yf = (i / df) % df, ez = i / (df * df);  // ez = (e, zc)
+  for (int i = threadIdx.x; i < nel * DC * DF * DF; i += kMgThreads) {
+    const int xf = i % DF, yf = (i / DF) % DF, ez = i / (DF * DF);  // ez = (el, zc)
     double s = 0.0;
-    for (int k = 0; k < dc; ++k) s += I.v[yf * dc + k] * t1[(ez * dc + k) * df + xf];
+#pragma unroll
+    for (int k = 0; k < DC; ++k) s += I.v[yf * DC + k] * t1[(ez * DC + k) * DF + xf];
     t2[i] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nel * df3; i += blockDim.x) {
-    const int l = i % df3, e = i / df3;
-    const int xf = l % df, yf = (l / df) % df, zf = l / (df * df);
+  for (int i = threadIdx.x; i < nel * DF3; i += kMgThreads) {
+    const int l = i % DF3, el = i / DF3;
+    const int xf = l % DF, yf = (l / DF) % DF, zf = l / (DF * DF);
+    const int64_t e = e0 + el;
+    if (!owns(a.own_f, S::W, e, l)) continue;
     double s = 0.0;
-    for (int k = 0; k < dc; ++k) s += I.v[zf * dc + k] * t2[((e * dc + k) * df + yf) * df + xf];
-    const int64_t pos = (e0 + e) * df3 + l;
-    const int32_t g = a.gmap_f[pos];
+#pragma unroll
+    for (int k = 0; k < DC; ++k) s += I.v[zf * DC + k] * t2[((el * DC + k) * DF + yf) * DF + xf];
+    const int32_t g = a.gmap_f[e * DF3 + l];
     const int32_t gi = g >= 0 ? g : ~g;
-    if (!owns(a, gi, pos)) continue;
     const double v = g >= 0 ? s : 0.0;  // free rows only
     if (add)
       out[gi] += v;
@@ -91,45 +104,47 @@ __global__ void __launch_bounds__(kMgThreads)
   }
 }
 
+template <int DC, int DF>
 __global__ void __launch_bounds__(kMgThreads)
     restrict_kernel(TransferArgs a, Interp1D I, const double* __restrict__ bf,
                     const double* __restrict__ yf, double* __restrict__ rc) {
-  extern __shared__ double lds[];
-  const int dc = a.dc, df = a.df;
-  const int df3 = df * df * df;
-  const int64_t e0 = int64_t(blockIdx.x) * a.nel;
-  const int nel = int(min(int64_t(a.nel), a.ne - e0));
-  double* rf = lds;                          // [nel][zf][yf][xf]
-  double* t2 = rf + a.nel * df3;             // [nel][zc][yf][xf]
-  double* t1 = t2 + a.nel * dc * df * df;    // [nel][zc][yc][xf]
-  for (int i = threadIdx.x; i < nel * df3; i += blockDim.x) {
-    const int64_t pos = e0 * df3 + i;
-    const int32_t g = a.gmap_f[pos];
+  using S = TransferShape<DC, DF>;
+  constexpr int NEL = S::NELR, DC3 = S::DC3, DF3 = S::DF3;
+  __shared__ double rf[NEL * DF3];            // [el][zf][yf][xf]
+  __shared__ double t2[NEL * DC * DF * DF];   // [el][zc][yf][xf]
+  __shared__ double t1[NEL * DC * DC * DF];   // [el][zc][yc][xf]
+  const int64_t e0 = int64_t(blockIdx.x) * NEL;
+  const int nel = int(min(int64_t(NEL), a.ne - e0));
+  for (int i = threadIdx.x; i < nel * DF3; i += kMgThreads) {
+    const int el = i / DF3, l = i - el * DF3;
+    const int32_t g = a.gmap_f[e0 * DF3 + i];
     double v = 0.0;
-    if (g >= 0 && owns(a, g, pos)) v = yf ? bf[g] - yf[g] : bf[g];
+    if (g >= 0 && owns(a.own_f, S::W, e0 + el, l)) v = yf ? bf[g] - yf[g] : bf[g];
     rf[i] = v;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nel * dc * df * df; i += blockDim.x) {
-    const int xf = i % df, yfi = (i / df) % df, zc = (i / (df * df)) % dc, e = i / (dc * df * df);
+  for (int i = threadIdx.x; i < nel * DC * DF * DF; i += kMgThreads) {
+    const int xf = i % DF, yfi = (i / DF) % DF, zc = (i / (DF * DF)) % DC, el = i / (DC * DF * DF);
     double s = 0.0;
-    for (int k = 0; k < df; ++k) s += I.v[k * dc + zc] * rf[((e * df + k) * df + yfi) * df + xf];
+#pragma unroll
+    for (int k = 0; k < DF; ++k) s += I.v[k * DC + zc] * rf[((el * DF + k) * DF + yfi) * DF + xf];
     t2[i] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nel * dc * dc * df; i += blockDim.x) {
-    const int xf = i % df, yc = (i / df) % dc, ez = i / (df * dc);  // ez = (e, zc)
+  for (int i = threadIdx.x; i < nel * DC * DC * DF; i += kMgThreads) {
+    const int xf = i % DF, yc = (i / DF) % DC, ez = i / (DF * DC);  // ez = (el, zc)
     double s = 0.0;
-    for (int k = 0; k < df; ++k) s += I.v[k * dc + yc] * t2[(ez * df + k) * df + xf];
+#pragma unroll
+    for (int k = 0; k < DF; ++k) s += I.v[k * DC + yc] * t2[(ez * DF + k) * DF + xf];
     t1[i] = s;
   }
   __syncthreads();
-  const int dc3 = dc * dc * dc;
-  for (int i = threadIdx.x; i < nel * dc3; i += blockDim.x) {
-    const int xc = i % dc, line = i / dc;  // line = (e, zc, yc)
+  for (int i = threadIdx.x; i < nel * DC3; i += kMgThreads) {
+    const int xc = i % DC, line = i / DC;  // line = (el, zc, yc)
     double s = 0.0;
-    for (int k = 0; k < df; ++k) s += I.v[k * dc + xc] * t1[line * df + k];
-    const int32_t g = a.gmap_c[e0 * dc3 + i];
+#pragma unroll
+    for (int k = 0; k < DF; ++k) s += I.v[k * DC + xc] * t1[line * DF + k];
+    const int32_t g = a.gmap_c[e0 * DC3 + i];
     if (g >= 0) atomicAdd(&rc[g], s);
   }
 }
@@ -143,12 +158,22 @@ __global__ void cheb_start_kernel(const double* __restrict__ b, const double* __
                                   const double* __restrict__ diag, double* __restrict__ r,
                                   double* __restrict__ d, double* __restrict__ x, double c0,
                                   int zero_guess, int64_t n) {
-  GRID_LOOP(i, n) {
-    const double ri = y ? b[i] - y[i] : b[i];
-    const double di = c0 * (ri / diag[i]);
-    r[i] = ri;
-    d[i] = di;
-    x[i] = zero_guess ? di : x[i] + di;
+  if (zero_guess) {
+    GRID_LOOP(i, n) {
+      const double ri = b[i];
+      const double di = c0 * (ri / diag[i]);
+      r[i] = ri;
+      d[i] = di;
+      x[i] = di;
+    }
+  } else {
+    GRID_LOOP(i, n) {
+      const double ri = y ? b[i] - y[i] : b[i];
+      const double di = c0 * (ri / diag[i]);
+      r[i] = ri;
+      d[i] = di;
+      x[i] += di;
+    }
   }
 }
 
@@ -249,68 +274,91 @@ __global__ void coeff_mean_kernel(const double* __restrict__ coeff, int64_t ne, 
   for (int q = lane; q < nout; q += kWave) out[e * nout + q] = m;
 }
 
+// streaming kernels: the CG grid (one workgroup of kCGThreads per compute unit)
+constexpr int kVecThreads = kCGThreads;
 int vec_blocks(int64_t n) {
-  return int(std::min<int64_t>(kCGBlocks, std::max<int64_t>(1, (n + 255) / 256)));
+  return int(std::min<int64_t>(kCGBlocks, std::max<int64_t>(1, (n + kVecThreads - 1) / kVecThreads)));
 }
 
-TransferArgs transfer_args(const DevSpace& c, const DevSpace& f, int* lds_bytes, bool prolong) {
+template <int DC, int DF>
+void prolong_t(const TransferArgs& a, const Interp1D& I, const double* xc, double* yf, bool add,
+               hipStream_t st) {
+  constexpr int NEL = TransferShape<DC, DF>::NELP;
+  const int64_t nblk = (a.ne + NEL - 1) / NEL;
+  if (nblk > 0)
+    hipLaunchKernelGGL((prolong_kernel<DC, DF>), dim3(unsigned(nblk)), dim3(kMgThreads), 0, st, a,
+                       I, xc, yf, add ? 1 : 0);
+}
+
+template <int DC, int DF>
+void restrict_t(const TransferArgs& a, const Interp1D& I, const double* bf, const double* yf,
+                double* rc, hipStream_t st) {
+  constexpr int NEL = TransferShape<DC, DF>::NELR;
+  const int64_t nblk = (a.ne + NEL - 1) / NEL;
+  if (nblk > 0)
+    hipLaunchKernelGGL((restrict_kernel<DC, DF>), dim3(unsigned(nblk)), dim3(kMgThreads), 0, st, a,
+                       I, bf, yf, rc);
+}
+
+TransferArgs transfer_args(const DevSpace& c, const DevSpace& f) {
   TransferArgs a{};
   a.gmap_c = c.gmap;
   a.gmap_f = f.gmap;
-  a.toff_f = f.toff;
-  a.tidx_f = f.tidx;
+  a.own_f = f.owner;
   a.ne = f.ne;
-  a.dc = c.p + 1;
-  a.df = f.p + 1;
-  const int dc = a.dc, df = a.df;
-  const int per = prolong ? dc * dc * dc + dc * dc * df + dc * df * df
-                          : df * df * df + dc * df * df + dc * dc * df;
-  a.nel = std::max(1, std::min(64, kMgLdsDoubles / per));
-  *lds_bytes = a.nel * per * int(sizeof(double));
   return a;
 }
+
+// every (coarse, fine) pair of orders 1 <= pc <= pf <= 8, as 1D node counts
+#define PAFEM_TRANSFER_PAIRS(X)                                                              \
+  X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(2, 7) X(2, 8) X(2, 9) X(3, 3) X(3, 4) X(3, 5)     \
+  X(3, 6) X(3, 7) X(3, 8) X(3, 9) X(4, 4) X(4, 5) X(4, 6) X(4, 7) X(4, 8) X(4, 9) X(5, 5)     \
+  X(5, 6) X(5, 7) X(5, 8) X(5, 9) X(6, 6) X(6, 7) X(6, 8) X(6, 9) X(7, 7) X(7, 8) X(7, 9)     \
+  X(8, 8) X(8, 9) X(9, 9)
 
 }  // namespace
 
 void launch_prolongate(const DevSpace& coarse, const DevSpace& fine, const Interp1D& I,
                        const double* xc, double* yf, bool add, hipStream_t st) {
-  int lds = 0;
-  const TransferArgs a = transfer_args(coarse, fine, &lds, true);
-  const int64_t nblk = (a.ne + a.nel - 1) / a.nel;
-  if (nblk == 0) return;
-  hipLaunchKernelGGL(prolong_kernel, dim3(unsigned(nblk)), dim3(kMgThreads), lds, st, a, I, xc,
-                     yf, add ? 1 : 0);
+  const TransferArgs a = transfer_args(coarse, fine);
+  const int dc = coarse.p + 1, df = fine.p + 1;
+#define PAFEM_PROLONG_CASE(C, F) \
+  if (dc == C && df == F) return prolong_t<C, F>(a, I, xc, yf, add, st);
+  PAFEM_TRANSFER_PAIRS(PAFEM_PROLONG_CASE)
+#undef PAFEM_PROLONG_CASE
+  throw Error(PAFEM_EUNSUPPORTED, "transfer between these orders is not built");
 }
 
 void launch_restrict(const DevSpace& fine, const DevSpace& coarse, const Interp1D& I,
                      const double* bf, const double* yf, double* rc, hipStream_t st) {
-  hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(coarse.ndofs)), dim3(256), 0, st, rc, 0.0,
+  hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(coarse.ndofs)), dim3(kVecThreads), 0, st, rc, 0.0,
                      int64_t(coarse.ndofs));
-  int lds = 0;
-  const TransferArgs a = transfer_args(coarse, fine, &lds, false);
-  const int64_t nblk = (a.ne + a.nel - 1) / a.nel;
-  if (nblk == 0) return;
-  hipLaunchKernelGGL(restrict_kernel, dim3(unsigned(nblk)), dim3(kMgThreads), lds, st, a, I, bf,
-                     yf, rc);
+  const TransferArgs a = transfer_args(coarse, fine);
+  const int dc = coarse.p + 1, df = fine.p + 1;
+#define PAFEM_RESTRICT_CASE(C, F) \
+  if (dc == C && df == F) return restrict_t<C, F>(a, I, bf, yf, rc, st);
+  PAFEM_TRANSFER_PAIRS(PAFEM_RESTRICT_CASE)
+#undef PAFEM_RESTRICT_CASE
+  throw Error(PAFEM_EUNSUPPORTED, "transfer between these orders is not built");
 }
 
 void launch_fill(double* y, double v, int64_t n, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(n)), dim3(256), 0, st, y, v, n);
+  hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, y, v, n);
 }
 
 void launch_cheb_start(const double* b, const double* y, const double* diag, double* r,
                        double* d, double* x, double c0, bool zero_guess, int64_t n,
                        hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(cheb_start_kernel, dim3(vec_blocks(n)), dim3(256), 0, st, b, y, diag, r, d,
+  hipLaunchKernelGGL(cheb_start_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, b, y, diag, r, d,
                      x, c0, zero_guess ? 1 : 0, n);
 }
 
 void launch_cheb_step(const double* y, const double* diag, double* r, double* d, double* x,
                       double c1, double c2, int64_t n, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(cheb_step_kernel, dim3(vec_blocks(n)), dim3(256), 0, st, y, diag, r, d, x,
+  hipLaunchKernelGGL(cheb_step_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, y, diag, r, d, x,
                      c1, c2, n);
 }
 
@@ -318,7 +366,7 @@ void launch_power_norm(double* v, const double* diag, const uint8_t* bmask, doub
                        uint32_t* ticket, double* scal, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(power_norm_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, st, v, diag, bmask,
                      partials, ticket, scal, n);
-  hipLaunchKernelGGL(power_scale_kernel, dim3(vec_blocks(n)), dim3(256), 0, st, v,
+  hipLaunchKernelGGL(power_scale_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, v,
                      static_cast<const double*>(scal), n);
 }
 
@@ -326,7 +374,7 @@ void launch_power_step(double* v, const double* w, const double* diag, double* p
                        uint32_t* ticket, double* scal, double* lam, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(power_dots_kernel, dim3(kCGBlocks), dim3(kCGThreads), 0, st, v, w, diag,
                      partials, ticket, scal, lam, n);
-  hipLaunchKernelGGL(power_update_kernel, dim3(vec_blocks(n)), dim3(256), 0, st, v, w, diag,
+  hipLaunchKernelGGL(power_update_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, st, v, w, diag,
                      static_cast<const double*>(scal), n);
 }
 

@@ -537,6 +537,7 @@ void space_device_layout(const Space& s, size_t* off, size_t* total) {
       sizeof(int32_t) * s.tile_dofs.size(),        // 9 tile dof lists
       sizeof(uint16_t) * s.tile_slot.size(),       // 10 tile slot maps
       sizeof(float) * s.tables.size(),             // 11 1D tables in FP32
+      sizeof(uint32_t) * size_t(s.ne) * owner_words(s.dpe),  // 12 owner bits
   };
   for (int i = 0; i < kSpaceSegments; ++i) {
     off[i] = o;
@@ -547,7 +548,8 @@ void space_device_layout(const Space& s, size_t* off, size_t* total) {
 }
 
 void space_pack(const Space& s, std::vector<int32_t>& gmap_enc, std::vector<double>& gnodes,
-                std::vector<int32_t>& toff, std::vector<int32_t>& tidx) {
+                std::vector<int32_t>& toff, std::vector<int32_t>& tidx,
+                std::vector<uint32_t>& owner) {
   const Mesh& m = *s.mesh;
   const size_t n = size_t(s.ne) * s.dpe;
   gmap_enc.resize(n);
@@ -587,6 +589,14 @@ void space_pack(const Space& s, std::vector<int32_t>& gmap_enc, std::vector<doub
   tidx.resize(n);
   std::vector<int32_t> fill(toff.begin(), toff.end() - 1);
   for (size_t i = 0; i < n; ++i) tidx[size_t(fill[size_t(dof_of(i))]++)] = int32_t(i);
+  // owner bits: the first element-vector position of each dof
+  const int W = owner_words(s.dpe);
+  owner.assign(size_t(s.ne) * W, 0u);
+  for (int64_t d = 0; d < s.ndofs; ++d) {
+    const int64_t pos = tidx[size_t(toff[size_t(d)])];
+    const int64_t k = pos / s.dpe, i = pos - k * s.dpe;
+    owner[size_t(k) * W + size_t(i / 32)] |= 1u << (i % 32);
+  }
 }
 
 }  // namespace pafem
