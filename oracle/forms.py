@@ -16,6 +16,8 @@ Definitions followed:
 * Load b_i = int f phi_i -- eq. (abstract forms), the b_i definition.
 * Convection C_E[i, j] = sum_k alpha_k det J_k phi_i (beta . J_k^{-T} ghat_j), the
   form int (beta . grad u) v with J^{-1} again from numpy.linalg.inv.
+* Gradient G_E[c, i, j] = sum_k alpha_k kappa_k det J_k phi_i (J_k^{-T} ghat_j)_c, the
+  mixed form (grad u, v) with v vector-valued in the same space.
 * Global operator A = sum_E G_E^t A_E G_E (dense element matrices scattered into
   a sparse matrix; "Operator Decomposition" with P = identity).
 * Essential BC: the "further modifications" of FormLinearSystem ("Finite Element
@@ -129,6 +131,25 @@ def element_convection(mesh, p, q1d, velocity):
     c = np.einsum("eqba,eqa->eqb", Jinv, beta) * (w[None, :] * det)[..., None]   # [E, Q^3, 3]
     dphi = np.einsum("eqb,bqj->eqj", c, grad)                          # [E, Q^3, D^3]
     return np.einsum("qi,eqj->eij", val, dphi)
+
+
+def element_gradient(mesh, p, q1d, coeff=None):
+    """Dense element gradient matrices [E, 3, D^3, D^3] of the mixed form
+    (grad u, v) with u and each component of v in the same H1 space:
+
+        G_E[c, i, j] = sum_k alpha_k kappa_k det J_k phi_i(xhat_k) (J_k^{-T} ghat_j)_c,
+
+    the gradient integrator among the paper's partially assembled kernels ("GPU
+    Acceleration"); coeff None, scalar or [E, Q^3].
+    """
+    pts, w, _, J, det = _jacobians(mesh, q1d)
+    val, grad = tensor_basis(gauss_lobatto(p + 1), pts)               # [Q^3, D^3], [3, Q^3, D^3]
+    c = 1.0 if coeff is None else np.asarray(coeff)
+    Jinv = np.linalg.inv(J)                                            # [E, Q^3, 3, 3]
+    scale = (w[None, :] * det) * c                                     # [E, Q^3]
+    # (J^{-T} g)_c = sum_b Jinv[b, c] g_b
+    phys = np.einsum("eqbc,bqj->ecqj", Jinv, grad)                     # [E, 3, Q^3, D^3]
+    return np.einsum("qi,eq,ecqj->ecij", val, scale, phys)
 
 
 def assemble(space, elmats):

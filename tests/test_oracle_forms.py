@@ -292,3 +292,42 @@ def test_convection_constants_and_skew_symmetry(p):
     f0 = ~S0.boundary
     C0f = C0[np.ix_(f0, f0)]
     assert np.abs(C0f + C0f.T).max() < 1e-12 * np.abs(C0f).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_gradient_of_linear_functions_and_convection(p):
+    """grad of a + b.x is b everywhere: G_c u = b_c M 1 exactly (the same rule as the
+    mass matrix); sum_c beta_c G_c is the convection matrix of a constant beta."""
+    mesh = synth.hex_lattice(3, 0.15, seed=6, rotate_seed=7)
+    S = oracle.H1Space(mesh, p)
+    kappa = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 1.0, seed=8)
+    Ge = forms.element_gradient(mesh, p, p + 2, kappa)
+    G = [oracle.assemble(S, Ge[:, c]) for c in range(3)]
+    M = oracle.assemble(S, forms.element_mass(mesh, p, p + 2, kappa))
+    X = S.dof_coordinates()
+    bvec = np.array([0.7, -1.2, 2.0])
+    u = 0.3 + X @ bvec
+    m1 = M @ np.ones(S.ndofs)
+    for c in range(3):
+        np.testing.assert_allclose(G[c] @ u, bvec[c] * m1, atol=1e-12 * np.abs(m1).max())
+    beta = np.array([0.4, 1.1, -0.6])
+    Gu = forms.element_gradient(mesh, p, p + 2)
+    C = oracle.assemble(S, forms.element_convection(mesh, p, p + 2, beta)).toarray()
+    Gb = sum(beta[c] * oracle.assemble(S, Gu[:, c]).toarray() for c in range(3))
+    assert np.abs(Gb - C).max() <= 1e-12 * np.abs(C).max()
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_gradient_affine_element_exact(p):
+    """Affine map, constant coefficient: G_c = det A sum_b (A^-1)_bc S_b (exact 1D integrals)."""
+    rng = np.random.default_rng(21 + p)
+    A = np.eye(3) + 0.3 * rng.normal(size=(3, 3))
+    if np.linalg.det(A) < 0:
+        A[:, 0] *= -1
+    M1, _, C1 = _exact_1d(p)
+    S = [_kron3(C1.T, M1, M1), _kron3(M1, C1.T, M1), _kron3(M1, M1, C1.T)]
+    Ainv = np.linalg.inv(A)
+    got = forms.element_gradient(_single_element(A), p, p + 2)[0]
+    for c in range(3):
+        want = np.linalg.det(A) * sum(Ainv[b, c] * S[b] for b in range(3))
+        np.testing.assert_allclose(got[c], want, atol=1e-12 * np.abs(want).max())
