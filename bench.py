@@ -78,6 +78,12 @@ def conv_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
     return 8 * ndofs + 8 * ndofs + 24 * ne * q ** 3 + 4 * ne * (p + 1) ** 3
 
 
+def grad_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
+    """Gradient: x + 3 output components + 9 values of w kappa adj(J)^t per point + map."""
+    q = p + 2
+    return 8 * ndofs + 24 * ndofs + 72 * ne * q ** 3 + 4 * ne * (p + 1) ** 3
+
+
 def geom_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
     """Recomputed-geometry diffusion: x + y + w*kappa per point + 8 corner nodes per
     element + int32 element->dof map, per apply."""
@@ -105,6 +111,7 @@ def setup_problem(P, torch, p, target, scatter):
     qd = S.qdata(P.DIFFUSION, coeff=kappa)
     qm = S.qdata(P.MASS, coeff=kappa)
     qg = S.qdata(P.DIFFUSION_GEOM, coeff=kappa)
+    qgr = S.qdata(P.GRADIENT, coeff=kappa) if p <= 4 else None
     del kappa
     # convection with the constant velocity (1, 1/2, 1/4)
     beta = torch.tensor([1.0, 0.5, 0.25], dtype=torch.float64, device="cuda").repeat(ne * (p + 2) ** 3)
@@ -113,7 +120,12 @@ def setup_problem(P, torch, p, target, scatter):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(100 + p)
     x = torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=gen)
+    extra = {}
+    if qgr is not None:
+        extra = {"grad": P.Operator(S, P.GRADIENT, qgr, constrained=False),
+                 "grad_y": torch.empty(3 * S.ndofs, dtype=torch.float64, device="cuda")}
     return {
+        **extra,
         "p": p, "n": n, "space": S, "ne": S.nelem, "ndofs": S.ndofs,
         "diff": P.Operator(S, P.DIFFUSION, qd, scatter=scatter),
         "mass": P.Operator(S, P.MASS, qm, scatter=scatter),
@@ -128,7 +140,7 @@ def time_applies(torch, probs, kind, steps, warmup):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         for pr in probs:
-            pr[kind].apply(pr["x"], pr["y"])
+            pr[kind].apply(pr["x"], pr.get(kind + "_y", pr["y"]))
     torch.cuda.synchronize()
     evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in probs] for _ in range(steps)]
@@ -136,7 +148,7 @@ def time_applies(torch, probs, kind, steps, warmup):
     for s in range(steps):
         for i, pr in enumerate(probs):
             evs[s][i][0].record(stream)
-            pr[kind].apply(pr["x"], pr["y"])
+            pr[kind].apply(pr["x"], pr.get(kind + "_y", pr["y"]))
             evs[s][i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -489,7 +501,8 @@ def main():
     ap.add_argument("--no-mass", action="store_true")
     ap.add_argument("--no-geom", action="store_true",
                     help="skip the recomputed-geometry diffusion variant")
-    ap.add_argument("--no-conv", action="store_true", help="skip the convection operator")
+    ap.add_argument("--no-conv", action="store_true",
+                    help="skip the convection and gradient operators")
     ap.add_argument("--forms", default="mixed,batched,learned,pmg,paper2d",
                     help="solver forms to measure beside the sweep ('' = none)")
     ap.add_argument("--pmg-orders", default="3,6",
@@ -556,6 +569,15 @@ def main():
             conv[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
                                   "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
 
+    grad = {}
+    gprobs = [pr for pr in probs if "grad" in pr]
+    if not args.no_conv and gprobs:
+        gper2, _ = time_applies(torch, gprobs, "grad", max(3, args.steps // 2), 1)
+        for pr, t in zip(gprobs, gper2):
+            by = grad_algorithmic_bytes(pr["p"], pr["ne"], pr["ndofs"])
+            grad[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
+                                  "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
+
     # dominant kernel: the order whose apply takes the longest
     k = max(range(len(probs)), key=lambda i: per[i])
     dom = probs[k]
@@ -605,7 +627,7 @@ def main():
                                f"(sigma=1) per quadrature point, q1d=p+2, Dirichlet boundary",
                    "orders": orders, "scatter": args.scatter, "per_p": per_p,
                    "mass_apply": mass, "recomputed_geometry_apply": geom,
-                   "convection_apply": conv, "setup_seconds": round(t_setup, 1),
+                   "convection_apply": conv, "gradient_apply": grad, "setup_seconds": round(t_setup, 1),
                    "timed_wall_seconds": round(wall, 4)},
         "roofline": roofline,
         "cg_time_to_1e-8": cg,

@@ -71,6 +71,13 @@ typedef int32_t pafem_status;
  * alpha_q det J_q J_q^{-1} beta_q (3 values per point), applied as
  * B^t (D . (B G u)).  Not symmetric: no diagonal, no CG.  FP64, hexahedra. */
 #define PAFEM_CONVECTION 3
+/* Gradient, the mixed form (grad u, v) with v vector-valued in the same H1
+ * space (the gradient integrator of "GPU Acceleration"): D_q = alpha_q kappa_q
+ * det J_q J_q^{-T} (9 values per point), applied as three value contractions
+ * B^t (D (B G u))_c.  The output has 3 * ndofs values, component-major
+ * (y[c * ndofs + i]).  Unconstrained (flags 0), atomic scatter, FP64,
+ * hexahedra, orders 1..4. */
+#define PAFEM_GRADIENT 4
 
 /* Storage types. */
 #define PAFEM_F64 0
@@ -180,6 +187,8 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
  *   diffusion with recomputed geometry (PAFEM_DIFFUSION_GEOM): E * Q^3 values
  *                            alpha_q kappa_q.
  *   convection: E * 3 * Q^3  D_q = alpha_q det J_q J_q^{-1} beta_q.
+ *   gradient:   E * 9 * Q^3  D_q = alpha_q kappa_q det J_q J_q^{-T}, [c][b] with c the
+ *                            output component and b the reference derivative.
  * Quadrilateral spaces: Q^2 points per element, diffusion 3 components
  * (00, 01, 11), mass 1.  All layouts are padded to whole apply tiles.
  * Errors: EUNSUPPORTED if q1d is not one of the built rules (q1d = p+2). */

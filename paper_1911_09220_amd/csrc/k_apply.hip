@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
                     const TC* __restrict__ tabG, const TD* __restrict__ qd,
                     const TV* __restrict__ x, TV* __restrict__ y, double* __restrict__ dotp,
                     const double* __restrict__ gnodes, const TC* __restrict__ tabBg,
-                    const TC* __restrict__ tabGg, int ne, int constrained) {
+                    const TC* __restrict__ tabGg, int ne, int constrained, int64_t ystride) {
   constexpr int D = P + 1, DD = D * D, QQ = Q * Q, QQQ = Q * Q * Q, DDD = D * D * D;
   constexpr int NE = elems_per_block<Q>();
   // GEOM: diffusion storing alpha kappa per point; J recomputed from the 8 corners
@@ -54,11 +54,18 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   constexpr bool DIFF = (KIND == PAFEM_DIFFUSION) || GEOM;  // gradient in, gradient out
   // CONV: convection, gradient in, value out (the back contractions are the mass ones)
   constexpr bool CONV = (KIND == PAFEM_CONVECTION);
-  constexpr bool GRAD = DIFF || CONV;  // the forward contractions produce the gradient
-  constexpr int NC = GEOM ? 1 : DIFF ? 6 : CONV ? 3 : 1;  // stored values per point
+  // GRADV: gradient into a vector-valued output, gradient in, 3 values out (each
+  // contracted back with B only), output component c at y + c * ystride
+  constexpr bool GRADV = (KIND == PAFEM_GRADIENT);
+  constexpr bool GRAD = DIFF || CONV || GRADV;  // the forward contractions produce the gradient
+  constexpr bool BACK3 = DIFF || GRADV;         // three arrays in the back contractions
+  constexpr int NC = GEOM ? 1 : DIFF ? 6 : CONV ? 3 : GRADV ? 9 : 1;  // stored values per point
   constexpr int NA = GRAD ? 2 : 1;   // arrays after the x-lines (B and G along x)
   constexpr int NCC = GRAD ? 3 : 1;  // arrays after the y-lines (one per derivative)
-  static_assert(!(CONV && DOT), "the convection operator has no energy");
+  constexpr int NOUT = GRADV ? 3 : 1;  // output components
+  static_assert(!((CONV || GRADV) && DOT), "the convection and gradient operators have no energy");
+  static_assert(!(GRADV && EVEC), "the gradient operator uses the atomic scatter");
+  static_assert(NOUT * D <= NCC * Q, "back x-line arrays must fit the element region");
   // Line stride: odd, so that threads walking consecutive lines hit distinct banks.
   constexpr int LC = D | 1;
   constexpr int ELEM = NCC * QQ * LC;
@@ -67,7 +74,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   __shared__ TC sW[NE * ELEM];
   // The tile's unique dofs: x gathered once per unique dof, later the element
   // outputs summed per unique dof before one global atomic each.
-  __shared__ TC sX[NE * DDD];
+  __shared__ TC sX[NOUT * NE * DDD];
 
   const int tid = threadIdx.x;
   const int el = tid / QQ;
@@ -148,7 +155,9 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 
   // sX is dead from here on: clear the per-unique-dof accumulators it now holds
   if (!EVEC)
-    for (int s = tid; s < nu; s += NE * QQ) sX[s] = TC(0);
+    for (int s = tid; s < nu; s += NE * QQ)
+#pragma unroll
+      for (int oc = 0; oc < NOUT; ++oc) sX[oc * NE * DDD + s] = TC(0);
 
   // B along y: thread (dz, qx) = r < D*Q
   const bool yline = act && r < D * Q;
@@ -279,6 +288,24 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
           t1[dz] += bB(qz, dz) * vy;
           t2[dz] += bG(qz, dz) * vz;
         }
+      } else if constexpr (GRADV) {
+        // w kappa adj(J)^t (reference gradient): the physical gradient times w det J
+        TC ux = TC(0), uy = TC(0), uz = TC(0);
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) {
+          ux += bB(qz, dz) * c0[dz];
+          uy += bB(qz, dz) * c1[dz];
+          uz += bG(qz, dz) * c2[dz];
+        }
+        const TC v0 = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
+        const TC v1 = dq[qz][3] * ux + dq[qz][4] * uy + dq[qz][5] * uz;
+        const TC v2 = dq[qz][6] * ux + dq[qz][7] * uy + dq[qz][8] * uz;
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) {
+          t0[dz] += bB(qz, dz) * v0;
+          t1[dz] += bB(qz, dz) * v1;
+          t2[dz] += bB(qz, dz) * v2;
+        }
       } else if constexpr (CONV) {
         // (beta . grad u) at the point: w adj(J) beta . (reference gradient)
         TC ux = TC(0), uy = TC(0), uz = TC(0);
@@ -304,7 +331,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll
     for (int dz = 0; dz < D; ++dz) {
       at(0, zy, zx, dz) = t0[dz];
-      if (DIFF) {
+      if (BACK3) {
         at(1, zy, zx, dz) = t1[dz];
         at(2, zy, zx, dz) = t2[dz];
       }
@@ -318,31 +345,71 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll
     for (int qy = 0; qy < Q; ++qy) {
       v0[qy] = at(0, qy, yx, yz);
-      if (DIFF) {
+      if (BACK3) {
         v1[qy] = at(1, qy, yx, yz);
         v2[qy] = at(2, qy, yx, yz);
       }
     }
+    if constexpr (GRADV) {
+      // three value contractions: component c of the output to x-line array c
 #pragma unroll
-    for (int dy = 0; dy < D; ++dy) {
-      TC b = TC(0), g = TC(0);
+      for (int dy = 0; dy < D; ++dy) {
+        TC o0 = TC(0), o1 = TC(0), o2 = TC(0);
 #pragma unroll
-      for (int qy = 0; qy < Q; ++qy) {
-        if (DIFF) {
-          g += bB(qy, dy) * v0[qy];
-          b += bG(qy, dy) * v1[qy] + bB(qy, dy) * v2[qy];
-        } else {
-          b += bB(qy, dy) * v0[qy];
+        for (int qy = 0; qy < Q; ++qy) {
+          o0 += bB(qy, dy) * v0[qy];
+          o1 += bB(qy, dy) * v1[qy];
+          o2 += bB(qy, dy) * v2[qy];
         }
+        at(dy / Q, dy % Q, yx, yz) = o0;
+        at((D + dy) / Q, (D + dy) % Q, yx, yz) = o1;
+        at((2 * D + dy) / Q, (2 * D + dy) % Q, yx, yz) = o2;
       }
-      at(dy / Q, dy % Q, yx, yz) = b;
-      if (DIFF) at((D + dy) / Q, (D + dy) % Q, yx, yz) = g;
+    } else {
+#pragma unroll
+      for (int dy = 0; dy < D; ++dy) {
+        TC b = TC(0), g = TC(0);
+#pragma unroll
+        for (int qy = 0; qy < Q; ++qy) {
+          if (DIFF) {
+            g += bB(qy, dy) * v0[qy];
+            b += bG(qy, dy) * v1[qy] + bB(qy, dy) * v2[qy];
+          } else {
+            b += bB(qy, dy) * v0[qy];
+          }
+        }
+        at(dy / Q, dy % Q, yx, yz) = b;
+        if (DIFF) at((D + dy) / Q, (D + dy) % Q, yx, yz) = g;
+      }
     }
   }
   __syncthreads();
 
   // B^t along x and G^t: thread (dz, dy)
-  if (xline) {
+  if constexpr (GRADV) {
+   if (xline) {
+    TC w0[Q], w1[Q], w2[Q];
+#pragma unroll
+    for (int qx = 0; qx < Q; ++qx) {
+      w0[qx] = at(xy / Q, xy % Q, qx, xz);
+      w1[qx] = at((D + xy) / Q, (D + xy) % Q, qx, xz);
+      w2[qx] = at((2 * D + xy) / Q, (2 * D + xy) % Q, qx, xz);
+    }
+#pragma unroll
+    for (int dx = 0; dx < D; ++dx) {
+      TC a0 = TC(0), a1 = TC(0), a2 = TC(0);
+#pragma unroll
+      for (int qx = 0; qx < Q; ++qx) {
+        a0 += bB(qx, dx) * w0[qx];
+        a1 += bB(qx, dx) * w1[qx];
+        a2 += bB(qx, dx) * w2[qx];
+      }
+      atomicAdd(&sX[slot[dx]], a0);
+      atomicAdd(&sX[NE * DDD + slot[dx]], a1);
+      atomicAdd(&sX[2 * NE * DDD + slot[dx]], a2);
+    }
+   }
+  } else if (xline) {
     TC wB[Q], wG[Q];
 #pragma unroll
     for (int qx = 0; qx < Q; ++qx) {
@@ -374,7 +441,10 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll 4
   for (int s = tid; s < nu; s += NE * QQ) {
     const int g = tile_dofs[u0 + s];
-    if (!(constrained && g < 0)) unsafeAtomicAdd(&y[g < 0 ? ~g : g], TV(sX[s]));
+    if (!(constrained && g < 0))
+#pragma unroll
+      for (int oc = 0; oc < NOUT; ++oc)
+        unsafeAtomicAdd(&y[oc * ystride + (g < 0 ? ~g : g)], TV(sX[oc * NE * DDD + s]));
   }
 }
 
@@ -405,7 +475,7 @@ void launch_one(const DevSpace& sp, bool constrained, const void* qd, const void
                      dim3(NE * Q * Q), 0, st, sp.tile_off, sp.tile_dofs, sp.tile_slot, tabB, tabG,
                      static_cast<const TD*>(qd), static_cast<const TV*>(x),
                      static_cast<TV*>(out), dotp, sp.gnodes, tabBg, tabGg, int(sp.ne),
-                     int(constrained));
+                     int(constrained), int64_t(sp.ndofs));
 }
 
 template <int P, int KIND, typename TV, typename TD, typename TC>
@@ -429,6 +499,16 @@ bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, bool con
                   bool evec, const void* qd, const void* x, void* out, double* dotp,
                   hipStream_t st) {
   const bool diff = kind == PAFEM_DIFFUSION;
+  if (kind == PAFEM_GRADIENT) {
+    // three output accumulators in LDS: built up to p = 4 (51 KB of LDS per workgroup)
+    if constexpr (P <= 4) {
+      if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp || evec) return false;
+      launch_one<P, PAFEM_GRADIENT, false, false, double, double, double>(sp, constrained, qd, x,
+                                                                           out, nullptr, st);
+      return true;
+    }
+    return false;
+  }
   if (kind == PAFEM_CONVECTION) {
     if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp) return false;
     if (evec)

@@ -99,6 +99,19 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* _
     const double c = scale * (coeff ? coeff[size_t(orig[e]) * QQQ + q] : 1.0);
     if (kind == PAFEM_MASS) {
       qd[qdata_index(e, 0, q, Q, 1)] = w * c * det;
+    } else if (kind == PAFEM_GRADIENT) {
+      // w kappa det J J^{-T} as D[c][b] = w kappa adj(J)[b][c]: output component c,
+      // reference derivative b
+      const double f = w * c;
+      qd[qdata_index(e, 0, q, Q, 9)] = f * A00;
+      qd[qdata_index(e, 1, q, Q, 9)] = f * A10;
+      qd[qdata_index(e, 2, q, Q, 9)] = f * A20;
+      qd[qdata_index(e, 3, q, Q, 9)] = f * A01;
+      qd[qdata_index(e, 4, q, Q, 9)] = f * A11;
+      qd[qdata_index(e, 5, q, Q, 9)] = f * A21;
+      qd[qdata_index(e, 6, q, Q, 9)] = f * A02;
+      qd[qdata_index(e, 7, q, Q, 9)] = f * A12;
+      qd[qdata_index(e, 8, q, Q, 9)] = f * A22;
     } else if (kind == PAFEM_CONVECTION) {
       // alpha det J J^{-1} beta = alpha adj(J) beta, beta = scale * velocity at the point
       const double* v = coeff + (size_t(orig[e]) * QQQ + q) * 3;

@@ -82,7 +82,7 @@ SmootherLayout smoother_layout(const Op& op) {
 void check_smoother_op(const Op& op) {
   require(op.qdtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "smoothers need an f64 operator");
   require(op.kind == PAFEM_DIFFUSION || op.kind == PAFEM_DIFFUSION_GEOM || op.kind == PAFEM_MASS,
-          PAFEM_EINVAL, "unknown operator kind");
+          PAFEM_EINVAL, "smoothers need a mass or diffusion operator");
 }
 
 // degree steps of Chebyshev-Jacobi on A x = b; r, d, y: scratch vectors of n

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpafem.so")
 
-MASS, DIFFUSION, DIFFUSION_GEOM, CONVECTION = 0, 1, 2, 3
+MASS, DIFFUSION, DIFFUSION_GEOM, CONVECTION, GRADIENT = 0, 1, 2, 3, 4
 F64, F32, BF16 = 0, 1, 2
 SPACE_RENUMBER = 1
 OP_CONSTRAINED, OP_SCATTER_EVEC = 1, 2
@@ -67,7 +67,7 @@ class FCGResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 240  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 250  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -540,11 +540,17 @@ class Operator:
                              f"{self.space.ndofs}")
 
     def apply(self, x, y=None):
+        """y = A x; for GRADIENT y has 3 * ndofs values (component-major)."""
         import torch
+        nout = 3 if self.kind == GRADIENT else 1
         if y is None:
-            y = torch.empty_like(x)
+            y = torch.empty(nout * x.numel(), dtype=x.dtype, device=x.device)
         self._check_vec(x, "x")
-        self._check_vec(y, "y")
+        if nout == 1:
+            self._check_vec(y, "y")
+        elif (y.numel() != 3 * self.space.ndofs or not y.is_contiguous() or not y.is_cuda
+              or y.dtype != x.dtype):
+            raise ValueError(f"y must be a contiguous device vector of {3 * self.space.ndofs}")
         pafem_op_apply(self.handle, x, y, self.work)
         return y
 

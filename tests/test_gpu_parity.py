@@ -342,3 +342,39 @@ def test_convection_limits():
         P.Operator(S, P.CONVECTION, P.lowered_qdata(qd, P.F32), qdata_dtype=P.F32)
     with pytest.raises(ValueError):
         S.qdata(P.CONVECTION)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_gradient_apply(p):
+    """(grad u, v) into a vector-valued output, lognormal coefficient, rotated jittered
+    elements: every component against the oracle's unconstrained matrices to 1e-12."""
+    mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=70 + p, rotate_seed=170 + p)
+    E = mesh["hex"].shape[0]
+    kappa = synth.lognormal_iid(E, p + 2, 1.0, seed=71 + p)
+    S, X, kc = _setup(mesh, p, kappa, renumber=(p % 2 == 1))
+    op = P.Operator(S, P.GRADIENT, S.qdata(P.GRADIENT, coeff=kc), constrained=False)
+    y = op.apply(_cuda(synth.hash_normal(X, seed=72 + p))).cpu().numpy().reshape(3, -1)
+    ref = oracle.H1Space(mesh, p)
+    Ge = forms.element_gradient(mesh, p, p + 2, kappa)
+    xo = synth.hash_normal(ref.dof_coordinates(), seed=72 + p)
+    perm = match_by_coords(X, ref.dof_coordinates())
+    for c in range(3):
+        want = (oracle.assemble(ref, Ge[:, c]) @ xo)[perm]
+        err = rel_err(y[c], want)
+        print(f"gradient p={p} component {c}: rel err {err:.2e}")
+        assert err <= TOL
+
+
+def test_gradient_limits():
+    S = P.Space(P.Mesh.from_dict(synth.hex_lattice(2, 0.1, seed=1)), 2)
+    qd = S.qdata(P.GRADIENT)
+    with pytest.raises(P.PafemError):
+        P.Operator(S, P.GRADIENT, qd)                      # constrained is not defined
+    with pytest.raises(P.PafemError):
+        P.Operator(S, P.GRADIENT, qd, constrained=False, scatter="evec")
+    op = P.Operator(S, P.GRADIENT, qd, constrained=False)
+    with pytest.raises(P.PafemError):
+        op.diagonal()
+    S5 = P.Space(P.Mesh.from_dict(synth.hex_lattice(1, 0.0)), 5)
+    with pytest.raises(P.PafemError):
+        P.Operator(S5, P.GRADIENT, S5.qdata(P.GRADIENT), constrained=False)
