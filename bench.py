@@ -131,6 +131,8 @@ def setup_problem(P, torch, p, target, scatter):
         "mass": P.Operator(S, P.MASS, qm, scatter=scatter),
         "geom": P.Operator(S, P.DIFFUSION_GEOM, qg, scatter=scatter),
         "conv": P.Operator(S, P.CONVECTION, qc, scatter=scatter),
+        "vec3": P.Operator(S, P.DIFFUSION, qd, vector=True),
+        "vec3_y": torch.empty(3 * S.ndofs, dtype=torch.float64, device="cuda"),
         "x": x, "y": torch.empty_like(x),
     }
 
@@ -138,9 +140,13 @@ def setup_problem(P, torch, p, target, scatter):
 def time_applies(torch, probs, kind, steps, warmup):
     """Per-order mean apply time (s) from HIP events on the launch stream."""
     stream = torch.cuda.current_stream()
+    for pr in probs:
+        if kind + "_x" not in pr and kind + "_y" in pr and pr[kind + "_y"].numel() == 3 * pr["ndofs"] \
+                and kind == "vec3":
+            pr["vec3_x"] = pr["x"].repeat(3)
     for _ in range(warmup):
         for pr in probs:
-            pr[kind].apply(pr["x"], pr.get(kind + "_y", pr["y"]))
+            pr[kind].apply(pr.get(kind + "_x", pr["x"]), pr.get(kind + "_y", pr["y"]))
     torch.cuda.synchronize()
     evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in probs] for _ in range(steps)]
@@ -148,7 +154,7 @@ def time_applies(torch, probs, kind, steps, warmup):
     for s in range(steps):
         for i, pr in enumerate(probs):
             evs[s][i][0].record(stream)
-            pr[kind].apply(pr["x"], pr.get(kind + "_y", pr["y"]))
+            pr[kind].apply(pr.get(kind + "_x", pr["x"]), pr.get(kind + "_y", pr["y"]))
             evs[s][i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -569,6 +575,16 @@ def main():
             conv[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
                                   "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
 
+    vec3 = {}
+    if not args.no_conv:
+        vper, _ = time_applies(torch, probs, "vec3", max(3, args.steps // 2), 1)
+        for pr, t, td in zip(probs, vper, per):
+            vec3[str(pr["p"])] = {"ms": round(t * 1e3, 4),
+                                  "gdofs_per_component": round(3 * pr["ndofs"] / t / 1e9, 3),
+                                  "speedup_vs_3_scalar_applies": round(3 * td / t, 3)}
+        for pr in probs:
+            pr.pop("vec3_x", None)
+
     grad = {}
     gprobs = [pr for pr in probs if "grad" in pr]
     if not args.no_conv and gprobs:
@@ -627,7 +643,8 @@ def main():
                                f"(sigma=1) per quadrature point, q1d=p+2, Dirichlet boundary",
                    "orders": orders, "scatter": args.scatter, "per_p": per_p,
                    "mass_apply": mass, "recomputed_geometry_apply": geom,
-                   "convection_apply": conv, "gradient_apply": grad, "setup_seconds": round(t_setup, 1),
+                   "convection_apply": conv, "gradient_apply": grad,
+                   "vector_diffusion_apply": vec3, "setup_seconds": round(t_setup, 1),
                    "timed_wall_seconds": round(wall, 4)},
         "roofline": roofline,
         "cg_time_to_1e-8": cg,

@@ -94,6 +94,12 @@ typedef int32_t pafem_status;
 #define PAFEM_OP_SCATTER_EVEC 2 /* G^t by writing element vectors and gathering them per dof
                                    through the transposed element->dof map: deterministic,
                                    needs a workspace.  Default: hardware FP atomics. */
+#define PAFEM_OP_VECTOR3 4      /* the operator on each component of a vector-valued H1
+                                   function (vector mass / vector diffusion): x and y hold
+                                   3 * ndofs values, component-major; D is read once for the
+                                   three components.  Mass or diffusion, FP64, hexahedra,
+                                   atomic scatter; no diagonal or solvers (use the scalar
+                                   operator per component). */
 
 /* Built-in sources for pafem_linear_form. */
 #define PAFEM_SOURCE_ARRAY 0 /* f given at quadrature points, device [E][Q^3] f64 */

@@ -82,6 +82,10 @@ void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st, 
       // the caller already set y = x on essential dofs (constrained) and 0 elsewhere
     } else if (op.kind == PAFEM_GRADIENT) {
       launch_fill(static_cast<double*>(y), 0.0, 3 * s.ndofs, st);  // three output components
+    } else if (op.flags & PAFEM_OP_VECTOR3) {
+      for (int c = 0; c < 3; ++c)
+        launch_scatter_init(s.dev, static_cast<const double*>(x) + c * s.ndofs, constrained,
+                            static_cast<double*>(y) + c * s.ndofs, st);
     } else if (vdt == PAFEM_F64) {
       launch_scatter_init(s.dev, static_cast<const double*>(x), constrained,
                           static_cast<double*>(y), st);
@@ -89,7 +93,8 @@ void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st, 
       launch_scatter_init_f32(s.dev, static_cast<const float*>(x), constrained,
                               static_cast<float*>(y), st);
     }
-    require(launch_pa_apply(s.dev, op.kind, op.q1d, op.qdtype, constrained, false, op.qdata, x,
+    const int kkind = (op.flags & PAFEM_OP_VECTOR3) ? kVectorKind + op.kind : op.kind;
+    require(launch_pa_apply(s.dev, kkind, op.q1d, op.qdtype, constrained, false, op.qdata, x,
                             y, vdt, st, dotp),
             PAFEM_EUNSUPPORTED, "apply kernel not built for this order/q1d/dtype");
   }
@@ -108,7 +113,7 @@ extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 250; }
+int32_t pafem_version(void) { return 260; }
 
 int32_t pafem_set_graph_mode(int32_t mode) {
   return graph_mode_flag().exchange(mode != 0 ? 1 : 0);
@@ -380,8 +385,14 @@ pafem_status pafem_op_create(pafem_space space, int32_t kind, int32_t q1d, const
     require(dtype_size(qdata_dtype) != 0, PAFEM_EINVAL, "unknown qdata dtype");
     require(q1d == s.p + 2, PAFEM_EUNSUPPORTED,
             "the fused apply is built for q1d = p + 2 only");
-    require((flags & ~(PAFEM_OP_CONSTRAINED | PAFEM_OP_SCATTER_EVEC)) == 0, PAFEM_EINVAL,
-            "unknown operator flags");
+    require((flags & ~(PAFEM_OP_CONSTRAINED | PAFEM_OP_SCATTER_EVEC | PAFEM_OP_VECTOR3)) == 0,
+            PAFEM_EINVAL, "unknown operator flags");
+    if (flags & PAFEM_OP_VECTOR3) {
+      require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, PAFEM_EUNSUPPORTED,
+              "vector operators: mass or diffusion");
+      require(s.dim == 3 && qdata_dtype == PAFEM_F64 && !(flags & PAFEM_OP_SCATTER_EVEC),
+              PAFEM_EUNSUPPORTED, "vector operators are FP64, hexahedra, atomic scatter");
+    }
     auto* o = new pafem_op_s();
     o->op.space = &s;
     o->op.kind = kind;
@@ -422,6 +433,8 @@ pafem_status pafem_op_diagonal(pafem_op op, double* diag, void* work, size_t wor
             "diagonal: use the PAFEM_DIFFUSION operator of the same space and coefficient");
     require(op->op.kind != PAFEM_CONVECTION && op->op.kind != PAFEM_GRADIENT, PAFEM_EUNSUPPORTED,
             "diagonal of the convection and gradient operators is not built");
+    require(!(op->op.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED,
+            "vector operator: every component has the scalar operator's diagonal");
     require(work && work_bytes >= op_work_bytes(op->op), PAFEM_ESHAPE, "workspace too small");
     const Op& o = op->op;
     const Space& s = *o.space;
@@ -476,6 +489,8 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
     require(o.qdtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "PCG needs an f64 operator");
     require(o.kind != PAFEM_CONVECTION && o.kind != PAFEM_GRADIENT, PAFEM_EINVAL,
             "CG needs a symmetric operator");
+    require(!(o.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED,
+            "CG on vector operators: solve each component with the scalar operator");
     require(opts->precond == PAFEM_PRECOND_NONE || opts->precond == PAFEM_PRECOND_JACOBI,
             PAFEM_EINVAL, "unknown preconditioner");
     require(opts->precond == PAFEM_PRECOND_NONE || diag, PAFEM_EINVAL,
@@ -633,6 +648,8 @@ pafem_status pafem_ir_solve(pafem_op a_hi, pafem_op a_lo, const double* diag, co
   pafem_status rc = guarded([&] {
     require(a_hi && a_lo && b && x && work && opts && result, PAFEM_EINVAL,
             "null pointer argument");
+    require(!((a_hi->op.flags | a_lo->op.flags) & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED,
+            "refinement needs scalar operators");
     const Op& hi = a_hi->op;
     const Op& lo = a_lo->op;
     check_ir_pair(hi, lo);

@@ -66,6 +66,7 @@ Batch::Batch(const std::vector<const Op*>& ops_in, int nrhs_in, void* work, size
     if (o->qdtype != qdtype || o->kind != kind)
       throw Error(PAFEM_EINVAL, "all operators of a batch need the same kind and qdata dtype");
     if (o->space->dim != 3) throw Error(PAFEM_EUNSUPPORTED, "batched apply is built for hexahedra");
+    if (o->flags & PAFEM_OP_VECTOR3) throw Error(PAFEM_EUNSUPPORTED, "batched apply of vector operators");
     if (o->space->p > 6) throw Error(PAFEM_EUNSUPPORTED, "batched apply is built for orders 1..6");
     if (o->q1d != o->space->p + 2) throw Error(PAFEM_EUNSUPPORTED, "batched apply needs q1d = p+2");
   }

@@ -13,6 +13,9 @@
 namespace pafem {
 
 constexpr int kMaxOrder = 8;
+// kernel-internal operator kinds: kVectorKind + kind applies `kind` to each of three
+// components (PAFEM_OP_VECTOR3)
+constexpr int kVectorKind = 16;
 constexpr int kMaxQ1d = 12;  // 1D tables are built for every q1d in [1, kMaxQ1d]
 
 // Thrown inside the library and turned into a status at the C boundary.

@@ -50,13 +50,17 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   constexpr int D = P + 1, DD = D * D, QQ = Q * Q, QQQ = Q * Q * Q, DDD = D * D * D;
   constexpr int NE = elems_per_block<Q>();
   // GEOM: diffusion storing alpha kappa per point; J recomputed from the 8 corners
-  constexpr bool GEOM = (KIND == PAFEM_DIFFUSION_GEOM);
-  constexpr bool DIFF = (KIND == PAFEM_DIFFUSION) || GEOM;  // gradient in, gradient out
+  // kinds from kVectorKind on: the same operator on each of 3 components (x and y hold
+  // 3 vectors at stride ystride), D read once and kept in registers for all three
+  constexpr int NV = KIND >= kVectorKind ? 3 : 1;
+  constexpr int K0 = KIND >= kVectorKind ? KIND - kVectorKind : KIND;
+  constexpr bool GEOM = (K0 == PAFEM_DIFFUSION_GEOM);
+  constexpr bool DIFF = (K0 == PAFEM_DIFFUSION) || GEOM;  // gradient in, gradient out
   // CONV: convection, gradient in, value out (the back contractions are the mass ones)
-  constexpr bool CONV = (KIND == PAFEM_CONVECTION);
+  constexpr bool CONV = (K0 == PAFEM_CONVECTION);
   // GRADV: gradient into a vector-valued output, gradient in, 3 values out (each
   // contracted back with B only), output component c at y + c * ystride
-  constexpr bool GRADV = (KIND == PAFEM_GRADIENT);
+  constexpr bool GRADV = (K0 == PAFEM_GRADIENT);
   constexpr bool GRAD = DIFF || CONV || GRADV;  // the forward contractions produce the gradient
   constexpr bool BACK3 = DIFF || GRADV;         // three arrays in the back contractions
   constexpr int NC = GEOM ? 1 : DIFF ? 6 : CONV ? 3 : GRADV ? 9 : 1;  // stored values per point
@@ -66,6 +70,8 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   static_assert(!((CONV || GRADV) && DOT), "the convection and gradient operators have no energy");
   static_assert(!(GRADV && EVEC), "the gradient operator uses the atomic scatter");
   static_assert(NOUT * D <= NCC * Q, "back x-line arrays must fit the element region");
+  static_assert(NV == 1 || (!DOT && !EVEC && (K0 == PAFEM_MASS || K0 == PAFEM_DIFFUSION)),
+                "vector operators: stored-D mass or diffusion, atomic scatter, no energy");
   // Line stride: odd, so that threads walking consecutive lines hit distinct banks.
   constexpr int LC = D | 1;
   constexpr int ELEM = NCC * QQ * LC;
@@ -104,6 +110,8 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
         dq[qz][c] = load_value<TC, TD>(qe + (c * Q + qz) * (NE * QQ));
   }
 
+  for (int comp = 0; comp < NV; ++comp) {
+  const TV* const xv_in = x + comp * ystride;
   // G: gather the tile's unique dofs; four per thread per step keep several
   // gathers in flight
   for (int s0 = tid; s0 < nu; s0 += 4 * NE * QQ) {
@@ -117,7 +125,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int g = gg[k];
-      xv[k] = (s0 + k * NE * QQ < nu && !(constrained && g < 0)) ? TC(x[g < 0 ? ~g : g]) : TC(0);
+      xv[k] = (s0 + k * NE * QQ < nu && !(constrained && g < 0)) ? TC(xv_in[g < 0 ? ~g : g]) : TC(0);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -444,7 +452,9 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
     if (!(constrained && g < 0))
 #pragma unroll
       for (int oc = 0; oc < NOUT; ++oc)
-        unsafeAtomicAdd(&y[oc * ystride + (g < 0 ? ~g : g)], TV(sX[oc * NE * DDD + s]));
+        unsafeAtomicAdd(&y[(comp + oc) * ystride + (g < 0 ? ~g : g)], TV(sX[oc * NE * DDD + s]));
+  }
+  if (NV > 1) __syncthreads();  // sX is gathered again for the next component
   }
 }
 
@@ -499,6 +509,31 @@ bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, bool con
                   bool evec, const void* qd, const void* x, void* out, double* dotp,
                   hipStream_t st) {
   const bool diff = kind == PAFEM_DIFFUSION;
+  if (kind == kVectorKind + PAFEM_DIFFUSION || kind == kVectorKind + PAFEM_MASS) {
+    if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp || evec) return false;
+    if constexpr (P >= 7) {
+      // the three-component kernel runs out of registers at p >= 7: one scalar apply per
+      // component (measured faster there)
+      for (int c = 0; c < 3; ++c) {
+        const double* xc = static_cast<const double*>(x) + c * sp.ndofs;
+        double* yc = static_cast<double*>(out) + c * sp.ndofs;
+        if (kind == kVectorKind + PAFEM_DIFFUSION)
+          launch_one<P, PAFEM_DIFFUSION, false, false, double, double, double>(sp, constrained, qd,
+                                                                                xc, yc, nullptr, st);
+        else
+          launch_one<P, PAFEM_MASS, false, false, double, double, double>(sp, constrained, qd, xc,
+                                                                           yc, nullptr, st);
+      }
+      return true;
+    }
+    if (kind == kVectorKind + PAFEM_DIFFUSION)
+      launch_one<P, kVectorKind + PAFEM_DIFFUSION, false, false, double, double, double>(
+          sp, constrained, qd, x, out, nullptr, st);
+    else
+      launch_one<P, kVectorKind + PAFEM_MASS, false, false, double, double, double>(
+          sp, constrained, qd, x, out, nullptr, st);
+    return true;
+  }
   if (kind == PAFEM_GRADIENT) {
     // three output accumulators in LDS: built up to p = 4 (51 KB of LDS per workgroup)
     if constexpr (P <= 4) {

@@ -186,6 +186,7 @@ LearnedLayout learned_layout(const Op& op) {
 }
 
 void check_net_op(const Net& net, const Op& op) {
+  require(!(op.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED, "the learned preconditioner needs a scalar operator");
   require(op.space->dim == 3, PAFEM_EUNSUPPORTED, "the learned preconditioner is built for hexahedra");
   require(op.qdtype == PAFEM_F64, PAFEM_EINVAL, "learned preconditioner needs an FP64 operator");
   require(op.space->p == net.d.p, PAFEM_EINVAL, "network order differs from the space order");
@@ -427,6 +428,7 @@ pafem_status fcg_solve(const Op& op, Net* net, const float* feats, const double*
   require(op.qdtype == PAFEM_F64, PAFEM_EINVAL, "FCG needs an FP64 operator");
   require(op.kind != PAFEM_CONVECTION && op.kind != PAFEM_GRADIENT, PAFEM_EINVAL,
           "CG needs a symmetric operator");
+  require(!(op.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED, "FCG needs a scalar operator");
   require(diag != nullptr, PAFEM_EINVAL, "FCG needs the operator diagonal");
   if (net) {
     check_net_op(*net, op);

@@ -80,6 +80,7 @@ SmootherLayout smoother_layout(const Op& op) {
 }
 
 void check_smoother_op(const Op& op) {
+  require(!(op.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED, "smoothers need a scalar operator");
   require(op.qdtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "smoothers need an f64 operator");
   require(op.kind == PAFEM_DIFFUSION || op.kind == PAFEM_DIFFUSION_GEOM || op.kind == PAFEM_MASS,
           PAFEM_EINVAL, "smoothers need a mass or diffusion operator");
@@ -374,6 +375,7 @@ pafem_status pafem_pmg_create(int32_t nlevels, const pafem_op* ops, const double
                   (o.kind == PAFEM_DIFFUSION || o.kind == PAFEM_DIFFUSION_GEOM),
               PAFEM_EUNSUPPORTED, "levels must be f64 diffusion operators");
       require(o.flags & PAFEM_OP_CONSTRAINED, PAFEM_EINVAL, "levels must be constrained");
+      require(!(o.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED, "levels must be scalar operators");
       require(o.space->dim == 3, PAFEM_EUNSUPPORTED, "order multigrid is built for hexahedra");
       require(std::isfinite(lmax[l]) && lmax[l] > 0.0, PAFEM_EINVAL, "lmax must be positive");
       g.ops.push_back(&o);

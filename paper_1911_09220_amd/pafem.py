@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpafem.so")
 MASS, DIFFUSION, DIFFUSION_GEOM, CONVECTION, GRADIENT = 0, 1, 2, 3, 4
 F64, F32, BF16 = 0, 1, 2
 SPACE_RENUMBER = 1
-OP_CONSTRAINED, OP_SCATTER_EVEC = 1, 2
+OP_CONSTRAINED, OP_SCATTER_EVEC, OP_VECTOR3 = 1, 2, 4
 SOURCE_ARRAY, SOURCE_CONST, SOURCE_SINE = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 MEAN_ARITHMETIC, MEAN_GEOMETRIC, MEAN_HARMONIC = 0, 1, 2
@@ -67,7 +67,7 @@ class FCGResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 250  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 260  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -524,10 +524,13 @@ class Operator:
     """y = A x for the PA mass or diffusion operator on a Space."""
 
     def __init__(self, space: Space, kind, qdata, q1d=None, constrained=True,
-                 scatter="atomic", qdata_dtype=F64):
+                 scatter="atomic", qdata_dtype=F64, vector=False):
+        """vector=True: the operator on each of 3 components (vectors of 3 * ndofs)."""
         self.space, self.kind, self.qdata = space, kind, qdata
         self.q1d = space.p + 2 if q1d is None else q1d
-        flags = (OP_CONSTRAINED if constrained else 0) | (OP_SCATTER_EVEC if scatter == "evec" else 0)
+        self.vector = bool(vector)
+        flags = ((OP_CONSTRAINED if constrained else 0) | (OP_SCATTER_EVEC if scatter == "evec" else 0)
+                 | (OP_VECTOR3 if vector else 0))
         self.handle = pafem_op_create(space.handle, kind, self.q1d, qdata, qdata_dtype, flags)
         self.work = _device_bytes(pafem_op_workspace_bytes(self.handle), space.device)
         self.vec_dtype = "float64" if qdata_dtype == F64 else "float32"
@@ -545,6 +548,12 @@ class Operator:
         nout = 3 if self.kind == GRADIENT else 1
         if y is None:
             y = torch.empty(nout * x.numel(), dtype=x.dtype, device=x.device)
+        if self.vector:
+            for v, nm in ((x, "x"), (y, "y")):
+                if v.numel() != 3 * self.space.ndofs or not v.is_contiguous() or not v.is_cuda:
+                    raise ValueError(f"{nm} must be a contiguous device vector of {3 * self.space.ndofs}")
+            pafem_op_apply(self.handle, x, y, self.work)
+            return y
         self._check_vec(x, "x")
         if nout == 1:
             self._check_vec(y, "y")
