@@ -171,7 +171,8 @@ __global__ void __launch_bounds__(k2dThreads)
   constexpr bool DIFF = (KIND == PAFEM_DIFFUSION);
   constexpr int NC = DIFF ? 3 : 1;  // stored values per point
   constexpr int NA = DIFF ? 2 : 1;  // arrays between the stages
-  constexpr int LQ = Q | 1;         // odd row stride
+  // row stride: odd (no bank conflicts between rows) while the tile fits 3 workgroups per CU
+  constexpr int LQ = (Q | 1) * NA * D * NE * 8 + NE * DD * 8 <= 52 * 1024 ? (Q | 1) : Q;
   constexpr int ELEM = NA * D * LQ;
 
   __shared__ double sW[NE * ELEM];
