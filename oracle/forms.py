@@ -18,6 +18,9 @@ Definitions followed:
   form int (beta . grad u) v with J^{-1} again from numpy.linalg.inv.
 * Gradient G_E[c, i, j] = sum_k alpha_k kappa_k det J_k phi_i (J_k^{-T} ghat_j)_c, the
   mixed form (grad u, v) with v vector-valued in the same space.
+* Divergence V_E[c, i, j] = sum_k alpha_k kappa_k det J_k phi_i (d phi_j / d x_c)(x_k),
+  the mixed form (div u, q) with u vector-valued; the physical gradient here comes
+  from solving J^T g = ghat (numpy.linalg.solve), not from an inverse.
 * Global operator A = sum_E G_E^t A_E G_E (dense element matrices scattered into
   a sparse matrix; "Operator Decomposition" with P = identity).
 * Essential BC: the "further modifications" of FormLinearSystem ("Finite Element
@@ -26,7 +29,8 @@ Definitions followed:
 
 Pins (tests/test_oracle_forms.py): closed-form 1D element matrices on affine
 cubes, volume = 1^T M 1, K 1 = 0, SPD with nullity 1 before BC, the paper's 2D
-setup formula, linear patch test, O(h^{p+1}) L2 convergence.
+setup formula, linear patch test, O(h^{p+1}) L2 convergence; divergence of linear
+vector fields, integration by parts against the gradient matrices, affine closed form.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -150,6 +154,29 @@ def element_gradient(mesh, p, q1d, coeff=None):
     # (J^{-T} g)_c = sum_b Jinv[b, c] g_b
     phys = np.einsum("eqbc,bqj->ecqj", Jinv, grad)                     # [E, 3, Q^3, D^3]
     return np.einsum("qi,eq,ecqj->ecij", val, scale, phys)
+
+
+def element_divergence(mesh, p, q1d, coeff=None):
+    """Dense element divergence matrices [E, 3, D^3, D^3] of the mixed form
+    (div u, q) with each component of u and the scalar q in the same H1 space (the
+    divergence integrator among the paper's partially assembled kernels, "GPU
+    Acceleration"):
+
+        V_E[c, i, j] = sum_k alpha_k kappa_k det J_k phi_i(xhat_k) (d phi_j / d x_c)(x_k),
+
+    so that (V u)_i = sum_c sum_j V[c, i, j] u_c[j] is the load of div u against
+    phi_i.  The physical gradient is obtained by solving J^T g = ghat at each point;
+    coeff None, scalar or [E, Q^3].
+    """
+    pts, w, _, J, det = _jacobians(mesh, q1d)
+    val, grad = tensor_basis(gauss_lobatto(p + 1), pts)               # [Q^3, D^3], [3, Q^3, D^3]
+    c = 1.0 if coeff is None else np.asarray(coeff)
+    E, nq = det.shape
+    Jt = np.broadcast_to(np.swapaxes(J, -1, -2)[:, :, None], (E, nq, grad.shape[2], 3, 3))
+    rhs = np.broadcast_to(np.moveaxis(grad, 0, -1)[None], (E, nq, grad.shape[2], 3))
+    phys = np.linalg.solve(Jt, rhs[..., None])[..., 0]                # [E, Q^3, D^3, 3]
+    scale = (w[None, :] * det) * c                                     # [E, Q^3]
+    return np.einsum("qi,eq,eqjc->ecij", val, scale, phys)
 
 
 def assemble(space, elmats):

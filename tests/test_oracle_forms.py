@@ -331,3 +331,60 @@ def test_gradient_affine_element_exact(p):
     for c in range(3):
         want = np.linalg.det(A) * sum(Ainv[b, c] * S[b] for b in range(3))
         np.testing.assert_allclose(got[c], want, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_divergence_of_linear_vector_fields(p):
+    """u = A x + b lies in the space and div u = tr A, so sum_c V_c u_c = tr(A) M 1
+    exactly (M the kappa-weighted mass matrix, the same rule)."""
+    mesh = synth.hex_lattice(3, 0.15, seed=16, rotate_seed=17)
+    S = oracle.H1Space(mesh, p)
+    kappa = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 1.0, seed=18)
+    Ve = forms.element_divergence(mesh, p, p + 2, kappa)
+    V = [oracle.assemble(S, Ve[:, c]) for c in range(3)]
+    M = oracle.assemble(S, forms.element_mass(mesh, p, p + 2, kappa))
+    X = S.dof_coordinates()
+    A = np.array([[0.3, -1.1, 0.4], [0.9, 1.7, -0.2], [0.5, 0.8, -2.3]])
+    u = X @ A.T + np.array([0.2, -0.7, 1.3])
+    m1 = M @ np.ones(S.ndofs)
+    got = sum(V[c] @ u[:, c] for c in range(3))
+    np.testing.assert_allclose(got, np.trace(A) * m1, atol=1e-12 * np.abs(m1).max())
+    # a field with zero divergence, u = (y, -x, 0) (rotation), gives zero
+    rot = np.stack([X[:, 1], -X[:, 0], np.zeros(S.ndofs)], axis=1)
+    assert np.abs(sum(V[c] @ rot[:, c] for c in range(3))).max() < 1e-12 * np.abs(m1).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_divergence_integration_by_parts(p):
+    """For u vanishing on the boundary, (div u, q) = -(u, grad q).  On trilinear
+    elements the integrand of int d(u_c q)/dx_c is a polynomial of degree <= 2p + 2
+    per reference direction, which the (p + 2)-point rule integrates exactly: the
+    divergence matrices equal minus the transposed gradient matrices on columns of
+    interior dofs, on jittered meshes too."""
+    mesh = synth.hex_lattice(3, 0.15, seed=26, rotate_seed=27)
+    S = oracle.H1Space(mesh, p)
+    Ve = forms.element_divergence(mesh, p, p + 2)
+    Ge = forms.element_gradient(mesh, p, p + 2)
+    free = ~S.boundary
+    for c in range(3):
+        V = oracle.assemble(S, Ve[:, c]).toarray()
+        G = oracle.assemble(S, Ge[:, c]).toarray()
+        lhs = V[:, free]
+        rhs = -G.T[:, free]
+        assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(lhs).max()
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_divergence_affine_element_exact(p):
+    """Affine map, constant coefficient: V_c = det A sum_b (A^-1)_bc S_b (exact 1D integrals)."""
+    rng = np.random.default_rng(41 + p)
+    A = np.eye(3) + 0.3 * rng.normal(size=(3, 3))
+    if np.linalg.det(A) < 0:
+        A[:, 0] *= -1
+    M1, _, C1 = _exact_1d(p)
+    S = [_kron3(C1.T, M1, M1), _kron3(M1, C1.T, M1), _kron3(M1, M1, C1.T)]
+    Ainv = np.linalg.inv(A)
+    got = forms.element_divergence(_single_element(A), p, p + 2)[0]
+    for c in range(3):
+        want = np.linalg.det(A) * sum(Ainv[b, c] * S[b] for b in range(3))
+        np.testing.assert_allclose(got[c], want, atol=1e-12 * np.abs(want).max())
