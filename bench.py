@@ -79,7 +79,8 @@ def conv_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
 
 
 def grad_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
-    """Gradient: x + 3 output components + 9 values of w kappa adj(J)^t per point + map."""
+    """Gradient: x + 3 output components + 9 values of w kappa adj(J)^t per point + map
+    (divergence: 3 input components + y, the same count)."""
     q = p + 2
     return 8 * ndofs + 24 * ndofs + 72 * ne * q ** 3 + 4 * ne * (p + 1) ** 3
 
@@ -112,6 +113,7 @@ def setup_problem(P, torch, p, target, scatter):
     qm = S.qdata(P.MASS, coeff=kappa)
     qg = S.qdata(P.DIFFUSION_GEOM, coeff=kappa)
     qgr = S.qdata(P.GRADIENT, coeff=kappa) if p <= 4 else None
+    qdv = qgr if qgr is not None else S.qdata(P.DIVERGENCE, coeff=kappa)
     del kappa
     # convection with the constant velocity (1, 1/2, 1/4)
     beta = torch.tensor([1.0, 0.5, 0.25], dtype=torch.float64, device="cuda").repeat(ne * (p + 2) ** 3)
@@ -124,6 +126,9 @@ def setup_problem(P, torch, p, target, scatter):
     if qgr is not None:
         extra = {"grad": P.Operator(S, P.GRADIENT, qgr, constrained=False),
                  "grad_y": torch.empty(3 * S.ndofs, dtype=torch.float64, device="cuda")}
+    # divergence: the gradient's quadrature data (9 values per point) serve both kinds
+    extra["div"] = P.Operator(S, P.DIVERGENCE, qdv, constrained=False)
+    extra["div_x"] = x.repeat(3)
     return {
         **extra,
         "p": p, "n": n, "space": S, "ne": S.nelem, "ndofs": S.ndofs,
@@ -508,7 +513,7 @@ def main():
     ap.add_argument("--no-geom", action="store_true",
                     help="skip the recomputed-geometry diffusion variant")
     ap.add_argument("--no-conv", action="store_true",
-                    help="skip the convection and gradient operators")
+                    help="skip the convection, gradient and divergence operators")
     ap.add_argument("--forms", default="mixed,batched,learned,pmg,paper2d",
                     help="solver forms to measure beside the sweep ('' = none)")
     ap.add_argument("--pmg-orders", default="3,6",
@@ -594,6 +599,14 @@ def main():
             grad[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
                                   "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
 
+    div = {}
+    if not args.no_conv:
+        dper, _ = time_applies(torch, probs, "div", max(3, args.steps // 2), 1)
+        for pr, t in zip(probs, dper):
+            by = grad_algorithmic_bytes(pr["p"], pr["ne"], pr["ndofs"])
+            div[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
+                                 "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
+
     # dominant kernel: the order whose apply takes the longest
     k = max(range(len(probs)), key=lambda i: per[i])
     dom = probs[k]
@@ -644,6 +657,7 @@ def main():
                    "orders": orders, "scatter": args.scatter, "per_p": per_p,
                    "mass_apply": mass, "recomputed_geometry_apply": geom,
                    "convection_apply": conv, "gradient_apply": grad,
+                   "divergence_apply": div,
                    "vector_diffusion_apply": vec3, "setup_seconds": round(t_setup, 1),
                    "timed_wall_seconds": round(wall, 4)},
         "roofline": roofline,

@@ -78,6 +78,13 @@ typedef int32_t pafem_status;
  * (y[c * ndofs + i]).  Unconstrained (flags 0), atomic scatter, FP64,
  * hexahedra, orders 1..4. */
 #define PAFEM_GRADIENT 4
+/* Divergence, the mixed form (div u, q) with u vector-valued in the same H1
+ * space as the scalar test function q (the divergence integrator of "GPU
+ * Acceleration"): the same D_q as PAFEM_GRADIENT (the qdata of either kind
+ * serves both), applied as B^t (sum_c (D (B G u_c))_c).  The input has
+ * 3 * ndofs values, component-major (x[c * ndofs + i]), the output ndofs.
+ * Unconstrained (flags 0), atomic scatter, FP64, hexahedra. */
+#define PAFEM_DIVERGENCE 5
 
 /* Storage types. */
 #define PAFEM_F64 0
@@ -195,6 +202,7 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
  *   convection: E * 3 * Q^3  D_q = alpha_q det J_q J_q^{-1} beta_q.
  *   gradient:   E * 9 * Q^3  D_q = alpha_q kappa_q det J_q J_q^{-T}, [c][b] with c the
  *                            output component and b the reference derivative.
+ *   divergence: the gradient's layout and values (c the input component).
  * Quadrilateral spaces: Q^2 points per element, diffusion 3 components
  * (00, 01, 11), mass 1.  All layouts are padded to whole apply tiles.
  * Errors: EUNSUPPORTED if q1d is not one of the built rules (q1d = p+2). */

@@ -82,6 +82,8 @@ void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st, 
       // the caller already set y = x on essential dofs (constrained) and 0 elsewhere
     } else if (op.kind == PAFEM_GRADIENT) {
       launch_fill(static_cast<double*>(y), 0.0, 3 * s.ndofs, st);  // three output components
+    } else if (op.kind == PAFEM_DIVERGENCE) {
+      launch_fill(static_cast<double*>(y), 0.0, s.ndofs, st);
     } else if (op.flags & PAFEM_OP_VECTOR3) {
       for (int c = 0; c < 3; ++c)
         launch_scatter_init(s.dev, static_cast<const double*>(x) + c * s.ndofs, constrained,
@@ -113,7 +115,7 @@ extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 260; }
+int32_t pafem_version(void) { return 270; }
 
 int32_t pafem_set_graph_mode(int32_t mode) {
   return graph_mode_flag().exchange(mode != 0 ? 1 : 0);
@@ -310,9 +312,7 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
 pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int64_t* nvalues) {
   return guarded([&] {
     require(space && space->s && nvalues, PAFEM_EINVAL, "null pointer argument");
-    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM ||
-                kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT,
-            PAFEM_EINVAL, "unknown operator kind");
+    require(known_kind(kind), PAFEM_EINVAL, "unknown operator kind");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
     if (space->s->dim == 2) {
       require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, PAFEM_EUNSUPPORTED,
@@ -320,7 +320,7 @@ pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int6
       *nvalues = qdata_values_2d(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 3 : 1);
     } else {
       const int nc = kind == PAFEM_DIFFUSION ? 6 : kind == PAFEM_CONVECTION ? 3
-                     : kind == PAFEM_GRADIENT ? 9 : 1;
+                     : (kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE) ? 9 : 1;
       *nvalues = qdata_values(space->s->ne, q1d, nc);
     }
   });
@@ -332,9 +332,7 @@ pafem_status pafem_qdata_assemble(pafem_space space, int32_t kind, int32_t q1d,
   return guarded([&] {
     const Space& s = uploaded_space(space);
     require(qdata != nullptr, PAFEM_EINVAL, "null qdata");
-    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM ||
-                kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT,
-            PAFEM_EINVAL, "unknown operator kind");
+    require(known_kind(kind), PAFEM_EINVAL, "unknown operator kind");
     require(q1d >= 1 && q1d <= kMaxQ1d, PAFEM_EUNSUPPORTED, "q1d out of range");
     require(s.dim == 3 || kind == PAFEM_MASS || kind == PAFEM_DIFFUSION, PAFEM_EUNSUPPORTED,
             "quadrilaterals support the mass and diffusion operators");
@@ -357,15 +355,19 @@ pafem_status pafem_op_create(pafem_space space, int32_t kind, int32_t q1d, const
   return guarded([&] {
     const Space& s = uploaded_space(space);
     require(out && qdata, PAFEM_EINVAL, "null pointer argument");
-    require(kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM ||
-                kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT,
-            PAFEM_EINVAL, "unknown operator kind");
+    require(known_kind(kind), PAFEM_EINVAL, "unknown operator kind");
     if (kind == PAFEM_GRADIENT) {
       require(s.dim == 3, PAFEM_EUNSUPPORTED, "the gradient operator is built for hexahedra");
       require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "the gradient operator is FP64");
       require(flags == 0, PAFEM_EUNSUPPORTED,
               "the gradient operator is unconstrained with the atomic scatter");
       require(s.p <= 4, PAFEM_EUNSUPPORTED, "the gradient operator is built for orders 1..4");
+    }
+    if (kind == PAFEM_DIVERGENCE) {
+      require(s.dim == 3, PAFEM_EUNSUPPORTED, "the divergence operator is built for hexahedra");
+      require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "the divergence operator is FP64");
+      require(flags == 0, PAFEM_EUNSUPPORTED,
+              "the divergence operator is unconstrained with the atomic scatter");
     }
     if (kind == PAFEM_CONVECTION) {
       require(s.dim == 3, PAFEM_EUNSUPPORTED, "the convection operator is built for hexahedra");
@@ -431,8 +433,8 @@ pafem_status pafem_op_diagonal(pafem_op op, double* diag, void* work, size_t wor
     require(op->op.qdtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "diagonal needs f64 qdata");
     require(op->op.kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
             "diagonal: use the PAFEM_DIFFUSION operator of the same space and coefficient");
-    require(op->op.kind != PAFEM_CONVECTION && op->op.kind != PAFEM_GRADIENT, PAFEM_EUNSUPPORTED,
-            "diagonal of the convection and gradient operators is not built");
+    require(!mixed_or_nonsymmetric(op->op.kind), PAFEM_EUNSUPPORTED,
+            "diagonal of the convection, gradient and divergence operators is not built");
     require(!(op->op.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED,
             "vector operator: every component has the scalar operator's diagonal");
     require(work && work_bytes >= op_work_bytes(op->op), PAFEM_ESHAPE, "workspace too small");
@@ -487,8 +489,7 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
     require(op && b && x && work && opts && result, PAFEM_EINVAL, "null pointer argument");
     const Op& o = op->op;
     require(o.qdtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "PCG needs an f64 operator");
-    require(o.kind != PAFEM_CONVECTION && o.kind != PAFEM_GRADIENT, PAFEM_EINVAL,
-            "CG needs a symmetric operator");
+    require(!mixed_or_nonsymmetric(o.kind), PAFEM_EINVAL, "CG needs a symmetric operator");
     require(!(o.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED,
             "CG on vector operators: solve each component with the scalar operator");
     require(opts->precond == PAFEM_PRECOND_NONE || opts->precond == PAFEM_PRECOND_JACOBI,

@@ -18,6 +18,15 @@ constexpr int kMaxOrder = 8;
 constexpr int kVectorKind = 16;
 constexpr int kMaxQ1d = 12;  // 1D tables are built for every q1d in [1, kMaxQ1d]
 
+inline bool known_kind(int kind) {
+  return kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM ||
+         kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE;
+}
+// operators that are not symmetric positive definite on one space: no diagonal, no CG
+inline bool mixed_or_nonsymmetric(int kind) {
+  return kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE;
+}
+
 // Thrown inside the library and turned into a status at the C boundary.
 struct Error : std::runtime_error {
   pafem_status code;

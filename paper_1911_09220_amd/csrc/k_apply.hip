@@ -52,8 +52,12 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   // GEOM: diffusion storing alpha kappa per point; J recomputed from the 8 corners
   // kinds from kVectorKind on: the same operator on each of 3 components (x and y hold
   // 3 vectors at stride ystride), D read once and kept in registers for all three
-  constexpr int NV = KIND >= kVectorKind ? 3 : 1;
   constexpr int K0 = KIND >= kVectorKind ? KIND - kVectorKind : KIND;
+  // DIVV: divergence of a vector-valued input into a scalar output: the three input
+  // components pass the forward contractions one after the other, their point values
+  // summed in registers, then one back contraction of values
+  constexpr bool DIVV = (K0 == PAFEM_DIVERGENCE);
+  constexpr int NV = (KIND >= kVectorKind || DIVV) ? 3 : 1;
   constexpr bool GEOM = (K0 == PAFEM_DIFFUSION_GEOM);
   constexpr bool DIFF = (K0 == PAFEM_DIFFUSION) || GEOM;  // gradient in, gradient out
   // CONV: convection, gradient in, value out (the back contractions are the mass ones)
@@ -61,16 +65,18 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   // GRADV: gradient into a vector-valued output, gradient in, 3 values out (each
   // contracted back with B only), output component c at y + c * ystride
   constexpr bool GRADV = (K0 == PAFEM_GRADIENT);
-  constexpr bool GRAD = DIFF || CONV || GRADV;  // the forward contractions produce the gradient
+  constexpr bool GRAD = DIFF || CONV || GRADV || DIVV;  // the forward contractions produce the gradient
   constexpr bool BACK3 = DIFF || GRADV;         // three arrays in the back contractions
-  constexpr int NC = GEOM ? 1 : DIFF ? 6 : CONV ? 3 : GRADV ? 9 : 1;  // stored values per point
+  // values per point in registers; DIVV stores 9 and reads those of one input component
+  constexpr int NC = GEOM ? 1 : DIFF ? 6 : (CONV || DIVV) ? 3 : GRADV ? 9 : 1;
+  constexpr int NCT = DIVV ? 9 : NC;  // stored values per point
   constexpr int NA = GRAD ? 2 : 1;   // arrays after the x-lines (B and G along x)
   constexpr int NCC = GRAD ? 3 : 1;  // arrays after the y-lines (one per derivative)
   constexpr int NOUT = GRADV ? 3 : 1;  // output components
-  static_assert(!((CONV || GRADV) && DOT), "the convection and gradient operators have no energy");
-  static_assert(!(GRADV && EVEC), "the gradient operator uses the atomic scatter");
+  static_assert(!((CONV || GRADV || DIVV) && DOT), "the convection, gradient and divergence operators have no energy");
+  static_assert(!((GRADV || DIVV) && EVEC), "the gradient and divergence operators use the atomic scatter");
   static_assert(NOUT * D <= NCC * Q, "back x-line arrays must fit the element region");
-  static_assert(NV == 1 || (!DOT && !EVEC && (K0 == PAFEM_MASS || K0 == PAFEM_DIFFUSION)),
+  static_assert(NV == 1 || DIVV || (!DOT && !EVEC && (K0 == PAFEM_MASS || K0 == PAFEM_DIFFUSION)),
                 "vector operators: stored-D mass or diffusion, atomic scatter, no energy");
   // Line stride: odd, so that threads walking consecutive lines hit distinct banks.
   constexpr int LC = D | 1;
@@ -101,17 +107,24 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   // overlaps the gather and the forward contractions (tile-interleaved: for each
   // (c, qz) the workgroup reads one contiguous run)
   TC dq[Q][NC];
-  if (act) {
-    const TD* qe = qd + size_t(tile) * NC * QQQ * NE + tid;
+  auto load_dq = [&](int cbase) {
+    if (act) {
+      const TD* qe = qd + size_t(tile) * NCT * QQQ * NE + tid;
 #pragma unroll
-    for (int qz = 0; qz < Q; ++qz)
+      for (int qz = 0; qz < Q; ++qz)
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        dq[qz][c] = load_value<TC, TD>(qe + (c * Q + qz) * (NE * QQ));
-  }
+        for (int c = 0; c < NC; ++c)
+          dq[qz][c] = load_value<TC, TD>(qe + ((cbase + c) * Q + qz) * (NE * QQ));
+    }
+  };
+  if (!DIVV) load_dq(0);
+  TC sdiv[DIVV ? Q : 1];  // DIVV: the divergence at this thread's points, summed over components
+#pragma unroll
+  for (int qz = 0; qz < (DIVV ? Q : 1); ++qz) sdiv[qz] = TC(0);
 
   for (int comp = 0; comp < NV; ++comp) {
   const TV* const xv_in = x + comp * ystride;
+  if (DIVV) load_dq(3 * comp);  // w kappa adj(J)[b][comp], b = 0..2
   // G: gather the tile's unique dofs; four per thread per step keep several
   // gathers in flight
   for (int s0 = tid; s0 < nu; s0 += 4 * NE * QQ) {
@@ -314,6 +327,20 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
           t1[dz] += bB(qz, dz) * v1;
           t2[dz] += bB(qz, dz) * v2;
         }
+      } else if constexpr (DIVV) {
+        // d u_comp / d x_comp times w kappa det J: sum_b w kappa adj(J)[b][comp] d_b u_comp
+        TC ux = TC(0), uy = TC(0), uz = TC(0);
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) {
+          ux += bB(qz, dz) * c0[dz];
+          uy += bB(qz, dz) * c1[dz];
+          uz += bG(qz, dz) * c2[dz];
+        }
+        sdiv[qz] += dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
+        if (comp == NV - 1) {
+#pragma unroll
+          for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * sdiv[qz];
+        }
       } else if constexpr (CONV) {
         // (beta . grad u) at the point: w adj(J) beta . (reference gradient)
         TC ux = TC(0), uy = TC(0), uz = TC(0);
@@ -336,15 +363,21 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
         for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * v;
       }
     }
+    if (!DIVV || comp == NV - 1) {
 #pragma unroll
-    for (int dz = 0; dz < D; ++dz) {
-      at(0, zy, zx, dz) = t0[dz];
-      if (BACK3) {
-        at(1, zy, zx, dz) = t1[dz];
-        at(2, zy, zx, dz) = t2[dz];
+      for (int dz = 0; dz < D; ++dz) {
+        at(0, zy, zx, dz) = t0[dz];
+        if (BACK3) {
+          at(1, zy, zx, dz) = t1[dz];
+          at(2, zy, zx, dz) = t2[dz];
+        }
       }
     }
   }
+  // DIVV: the next component's gather writes only sX, which no thread reads after the
+  // x-lines, and its x-lines write the element regions only after the barrier that
+  // follows the gather, which every thread reaches after its z-line
+  if (DIVV && comp < NV - 1) continue;
   __syncthreads();
 
   // B^t along y: thread (dz, qx)
@@ -452,7 +485,8 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
     if (!(constrained && g < 0))
 #pragma unroll
       for (int oc = 0; oc < NOUT; ++oc)
-        unsafeAtomicAdd(&y[(comp + oc) * ystride + (g < 0 ? ~g : g)], TV(sX[oc * NE * DDD + s]));
+        unsafeAtomicAdd(&y[(DIVV ? 0 : comp + oc) * ystride + (g < 0 ? ~g : g)],
+                        TV(sX[oc * NE * DDD + s]));
   }
   if (NV > 1) __syncthreads();  // sX is gathered again for the next component
   }
@@ -543,6 +577,12 @@ bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, bool con
       return true;
     }
     return false;
+  }
+  if (kind == PAFEM_DIVERGENCE) {
+    if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp || evec) return false;
+    launch_one<P, PAFEM_DIVERGENCE, false, false, double, double, double>(sp, constrained, qd, x,
+                                                                           out, nullptr, st);
+    return true;
   }
   if (kind == PAFEM_CONVECTION) {
     if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp) return false;

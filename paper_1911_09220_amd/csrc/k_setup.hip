@@ -99,8 +99,9 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* _
     const double c = scale * (coeff ? coeff[size_t(orig[e]) * QQQ + q] : 1.0);
     if (kind == PAFEM_MASS) {
       qd[qdata_index(e, 0, q, Q, 1)] = w * c * det;
-    } else if (kind == PAFEM_GRADIENT) {
-      // w kappa det J J^{-T} as D[c][b] = w kappa adj(J)[b][c]: output component c,
+    } else if (kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE) {
+      // w kappa det J J^{-T} as D[c][b] = w kappa adj(J)[b][c]: physical derivative c
+      // (the gradient's output component, the divergence's input component),
       // reference derivative b
       const double f = w * c;
       qd[qdata_index(e, 0, q, Q, 9)] = f * A00;

@@ -426,7 +426,7 @@ pafem_status fcg_solve(const Op& op, Net* net, const float* feats, const double*
                        const double* b, double* x, void* work, size_t work_bytes,
                        const pafem_solve_opts& opts, pafem_fcg_result& res, hipStream_t st) {
   require(op.qdtype == PAFEM_F64, PAFEM_EINVAL, "FCG needs an FP64 operator");
-  require(op.kind != PAFEM_CONVECTION && op.kind != PAFEM_GRADIENT, PAFEM_EINVAL,
+  require(!mixed_or_nonsymmetric(op.kind), PAFEM_EINVAL,
           "CG needs a symmetric operator");
   require(!(op.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED, "FCG needs a scalar operator");
   require(diag != nullptr, PAFEM_EINVAL, "FCG needs the operator diagonal");

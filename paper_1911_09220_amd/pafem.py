@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpafem.so")
 
-MASS, DIFFUSION, DIFFUSION_GEOM, CONVECTION, GRADIENT = 0, 1, 2, 3, 4
+MASS, DIFFUSION, DIFFUSION_GEOM, CONVECTION, GRADIENT, DIVERGENCE = 0, 1, 2, 3, 4, 5
 F64, F32, BF16 = 0, 1, 2
 SPACE_RENUMBER = 1
 OP_CONSTRAINED, OP_SCATTER_EVEC, OP_VECTOR3 = 1, 2, 4
@@ -67,7 +67,7 @@ class FCGResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 260  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 270  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -543,9 +543,19 @@ class Operator:
                              f"{self.space.ndofs}")
 
     def apply(self, x, y=None):
-        """y = A x; for GRADIENT y has 3 * ndofs values (component-major)."""
+        """y = A x; GRADIENT writes and DIVERGENCE reads 3 * ndofs values
+        (component-major)."""
         import torch
         nout = 3 if self.kind == GRADIENT else 1
+        if self.kind == DIVERGENCE:
+            n3 = 3 * self.space.ndofs
+            if x.numel() != n3 or not x.is_contiguous() or not x.is_cuda or x.dtype != torch.float64:
+                raise ValueError(f"x must be a contiguous float64 device vector of {n3}")
+            if y is None:
+                y = torch.empty(self.space.ndofs, dtype=x.dtype, device=x.device)
+            self._check_vec(y, "y")
+            pafem_op_apply(self.handle, x, y, self.work)
+            return y
         if y is None:
             y = torch.empty(nout * x.numel(), dtype=x.dtype, device=x.device)
         if self.vector:
