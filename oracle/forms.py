@@ -21,6 +21,9 @@ Definitions followed:
 * Divergence V_E[c, i, j] = sum_k alpha_k kappa_k det J_k phi_i (d phi_j / d x_c)(x_k),
   the mixed form (div u, q) with u vector-valued; the physical gradient here comes
   from solving J^T g = ghat (numpy.linalg.solve), not from an inverse.
+* Linear elasticity K_E[c, i, d, j] = sum_k alpha_k det J_k [lambda d_c phi_i d_d phi_j +
+  mu (delta_cd grad phi_i . grad phi_j + d_d phi_i d_c phi_j)], the bilinear form
+  int lambda div u div v + 2 mu eps(u):eps(v) on the vector H1 space (component-major).
 * Global operator A = sum_E G_E^t A_E G_E (dense element matrices scattered into
   a sparse matrix; "Operator Decomposition" with P = identity).
 * Essential BC: the "further modifications" of FormLinearSystem ("Finite Element
@@ -30,7 +33,9 @@ Definitions followed:
 Pins (tests/test_oracle_forms.py): closed-form 1D element matrices on affine
 cubes, volume = 1^T M 1, K 1 = 0, SPD with nullity 1 before BC, the paper's 2D
 setup formula, linear patch test, O(h^{p+1}) L2 convergence; divergence of linear
-vector fields, integration by parts against the gradient matrices, affine closed form.
+vector fields, integration by parts against the gradient matrices, affine closed form;
+elasticity rigid-body null space, linear patch test, lambda and mu parts against the
+gradient and diffusion matrices, affine closed form.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -177,6 +182,44 @@ def element_divergence(mesh, p, q1d, coeff=None):
     phys = np.linalg.solve(Jt, rhs[..., None])[..., 0]                # [E, Q^3, D^3, 3]
     scale = (w[None, :] * det) * c                                     # [E, Q^3]
     return np.einsum("qi,eq,eqjc->ecij", val, scale, phys)
+
+
+def element_elasticity(mesh, p, q1d, lam, mu):
+    """Dense element matrices [E, 3, D^3, 3, D^3] of isotropic linear elasticity on the
+    vector H1 space (each displacement component in the scalar space):
+
+        a(u, v) = int lambda (div u)(div v) + 2 mu eps(u) : eps(v),  eps(u) = (grad u + grad u^T)/2,
+
+    which for u = phi_j e_d, v = phi_i e_c gives
+
+        K_E[c, i, d, j] = sum_k alpha_k det J_k [ lambda_k d_c phi_i d_d phi_j
+                          + mu_k (delta_cd grad phi_i . grad phi_j + d_d phi_i d_c phi_j) ],
+
+    d_c the physical derivative (J^{-T} ghat)_c; lam and mu scalars or [E, Q^3].
+    """
+    pts, w, _, J, det = _jacobians(mesh, q1d)
+    _, grad = tensor_basis(gauss_lobatto(p + 1), pts)                 # [3, Q^3, D^3]
+    Jinv = np.linalg.inv(J)                                            # [E, Q^3, 3, 3]
+    phys = np.einsum("eqbc,bqj->eqjc", Jinv, grad)                     # [E, Q^3, D^3, 3]
+    wd = w[None, :] * det
+    lw = wd * np.asarray(lam)                                          # [E, Q^3]
+    mw = wd * np.asarray(mu)
+    K = np.einsum("eq,eqic,eqjd->ecidj", lw, phys, phys)
+    K += np.einsum("eq,eqid,eqjc->ecidj", mw, phys, phys)
+    lap = np.einsum("eq,eqia,eqja->eij", mw, phys, phys)
+    for c in range(3):
+        K[:, c, :, c, :] += lap
+    return K
+
+
+def vector_space(space):
+    """The three-component space of `space`, component-major global index c * N + i,
+    as the (elem_dofs, ndofs, boundary) triple that :func:`assemble` and
+    :func:`constrain` take."""
+    from types import SimpleNamespace
+    n = space.ndofs
+    ed = np.concatenate([space.elem_dofs + c * n for c in range(3)], axis=1)
+    return SimpleNamespace(elem_dofs=ed, ndofs=3 * n, boundary=np.tile(space.boundary, 3))
 
 
 def assemble(space, elmats):

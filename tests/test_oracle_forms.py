@@ -388,3 +388,111 @@ def test_divergence_affine_element_exact(p):
     for c in range(3):
         want = np.linalg.det(A) * sum(Ainv[b, c] * S[b] for b in range(3))
         np.testing.assert_allclose(got[c], want, atol=1e-12 * np.abs(want).max())
+
+
+def _elasticity_global(mesh, p, lam, mu):
+    S = oracle.H1Space(mesh, p)
+    Ke = forms.element_elasticity(mesh, p, p + 2, lam, mu)
+    E, nd = Ke.shape[0], Ke.shape[2]
+    V = forms.vector_space(S)
+    return S, V, oracle.assemble(V, Ke.reshape(E, 3 * nd, 3 * nd))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_elasticity_rigid_modes_and_patch(p):
+    """The six rigid-body fields (translations, infinitesimal rotations w x X) have zero
+    strain and lie in the space: K u = 0 exactly for point-varying lambda, mu.  For a
+    linear field and constant lambda, mu the stress is constant and K u vanishes on
+    interior rows (the integrand of int sigma : grad v has degree <= p + 2 per reference
+    direction on trilinear elements)."""
+    mesh = synth.hex_lattice(3, 0.15, seed=31, rotate_seed=32)
+    E = mesh["hex"].shape[0]
+    lam = synth.lognormal_iid(E, p + 2, 0.5, seed=33)
+    mu = synth.lognormal_iid(E, p + 2, 0.5, seed=34)
+    S, V, K = _elasticity_global(mesh, p, lam, mu)
+    X = S.dof_coordinates()
+    scale = np.abs(K).max()
+    modes = [np.tile(e, (S.ndofs, 1)) for e in np.eye(3)]
+    for w in np.eye(3):
+        modes.append(np.cross(w, X))
+    for u in modes:
+        assert np.abs(K @ u.T.ravel()).max() <= 1e-11 * scale
+    S1, V1, K1 = _elasticity_global(mesh, p, 1.7, 0.6)
+    A = np.array([[0.3, -1.1, 0.4], [0.9, 1.7, -0.2], [0.5, 0.8, -2.3]])
+    u = (X @ A.T + 0.3).T.ravel()
+    r = K1 @ u
+    assert np.abs(r[~V1.boundary]).max() <= 1e-11 * np.abs(K1).max()
+    assert np.abs(r[V1.boundary]).max() > 1e-3 * np.abs(K1).max()
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_elasticity_parts_against_gradient_and_diffusion(p):
+    """lambda part (mu = 0): for u = A x + b the load is tr(A) int d_c phi_i = tr(A)
+    (G_c^T 1)_i with the gradient matrices.  mu part (lambda = 0): the diagonal blocks
+    sum to 4 times the diffusion stiffness (sum_c (delta_cc grad.grad + d_c d_c) = 3 L + L)."""
+    mesh = synth.hex_lattice(2, 0.15, seed=36, rotate_seed=37)
+    E = mesh["hex"].shape[0]
+    kap = synth.lognormal_iid(E, p + 2, 0.5, seed=38)
+    S = oracle.H1Space(mesh, p)
+    X = S.dof_coordinates()
+    A = np.array([[0.3, -1.1, 0.4], [0.9, 1.7, -0.2], [0.5, 0.8, -2.3]])
+    u = (X @ A.T + np.array([0.1, 0.2, -0.3])).T.ravel()
+    _, _, Kl = _elasticity_global(mesh, p, kap, 0.0)
+    Ge = forms.element_gradient(mesh, p, p + 2, kap)
+    ones = np.ones(S.ndofs)
+    want = np.concatenate([np.trace(A) * (oracle.assemble(S, Ge[:, c]).T @ ones) for c in range(3)])
+    np.testing.assert_allclose(Kl @ u, want, atol=1e-12 * np.abs(want).max())
+    Km = forms.element_elasticity(mesh, p, p + 2, 0.0, kap)
+    L = forms.element_stiffness(mesh, p, p + 2, kap)
+    np.testing.assert_allclose(sum(Km[:, c, :, c, :] for c in range(3)), 4.0 * L,
+                               atol=1e-12 * np.abs(L).max())
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_elasticity_affine_element_exact(p):
+    """Affine map x = A xhat, constant lambda, mu: with S_ab[i, j] = int dhat_a phi_i dhat_b phi_j
+    (Kronecker products of exact 1D integrals) and Ai = A^-1,
+    K[c,i,d,j] = det A sum_ab S_ab [lambda Ai_ac Ai_bd + mu (delta_cd (Ai Ai^T)_ab + Ai_ad Ai_bc)]."""
+    rng = np.random.default_rng(51 + p)
+    A = np.eye(3) + 0.3 * rng.normal(size=(3, 3))
+    if np.linalg.det(A) < 0:
+        A[:, 0] *= -1
+    lam, mu = 1.3, 0.7
+    M1, K1, C1 = _exact_1d(p)
+    Sab = {}
+    for a in range(3):
+        for b in range(3):
+            t = []
+            for d in range(3):
+                if d == a and d == b:
+                    t.append(K1)
+                elif d == a:
+                    t.append(C1)
+                elif d == b:
+                    t.append(C1.T)
+                else:
+                    t.append(M1)
+            Sab[a, b] = _kron3(*t)
+    Ai = np.linalg.inv(A)
+    G = Ai @ Ai.T
+    got = forms.element_elasticity(_single_element(A, [0.1, 0.0, -0.2]), p, p + 2, lam, mu)[0]
+    for c in range(3):
+        for d in range(3):
+            want = np.linalg.det(A) * sum(
+                Sab[a, b] * (lam * Ai[a, c] * Ai[b, d]
+                             + mu * ((c == d) * G[a, b] + Ai[a, d] * Ai[b, c]))
+                for a in range(3) for b in range(3))
+            np.testing.assert_allclose(got[c, :, d, :], want, atol=1e-12 * np.abs(want).max())
+
+
+def test_elasticity_null_space_dimension():
+    """Symmetric positive semidefinite with exactly the six rigid-body modes as kernel."""
+    mesh = synth.hex_lattice(2, 0.15, seed=41, rotate_seed=42)
+    E = mesh["hex"].shape[0]
+    _, _, K = _elasticity_global(mesh, 1, synth.lognormal_iid(E, 3, 0.5, seed=43),
+                                 synth.lognormal_iid(E, 3, 0.5, seed=44))
+    K = K.toarray()
+    assert np.abs(K - K.T).max() <= 1e-13 * np.abs(K).max()
+    ev = np.linalg.eigvalsh(K)
+    tol = 1e-10 * ev[-1]
+    assert ev[0] > -tol and int((np.abs(ev) <= tol).sum()) == 6
