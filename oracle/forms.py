@@ -204,9 +204,16 @@ def element_elasticity(mesh, p, q1d, lam, mu):
     wd = w[None, :] * det
     lw = wd * np.asarray(lam)                                          # [E, Q^3]
     mw = wd * np.asarray(mu)
-    K = np.einsum("eq,eqic,eqjd->ecidj", lw, phys, phys)
-    K += np.einsum("eq,eqid,eqjc->ecidj", mw, phys, phys)
-    lap = np.einsum("eq,eqia,eqja->eij", mw, phys, phys)
+    E, nq, nd, _ = phys.shape
+    Pm = phys.reshape(E, nq, nd * 3)                                   # column (j, c)
+
+    def gram(wq):
+        # [e, i, a, j, b] = sum_q wq d_a phi_i d_b phi_j, as one matrix product per element
+        return np.matmul(np.swapaxes(Pm * wq[:, :, None], 1, 2), Pm).reshape(E, nd, 3, nd, 3)
+
+    L, M = gram(lw), gram(mw)
+    K = L.transpose(0, 2, 1, 4, 3) + M.transpose(0, 4, 1, 2, 3)       # lambda and d_d phi_i d_c phi_j
+    lap = np.einsum("eiaja->eij", M)                                   # mu grad phi_i . grad phi_j
     for c in range(3):
         K[:, c, :, c, :] += lap
     return K
