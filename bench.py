@@ -85,6 +85,13 @@ def grad_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
     return 8 * ndofs + 24 * ndofs + 72 * ne * q ** 3 + 4 * ne * (p + 1) ** 3
 
 
+def elas_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
+    """Elasticity: 3 input and 3 output components + 11 values per point (J^-1, w det J
+    lambda, w det J mu) + element->dof map."""
+    q = p + 2
+    return 24 * ndofs + 24 * ndofs + 88 * ne * q ** 3 + 4 * ne * (p + 1) ** 3
+
+
 def geom_algorithmic_bytes(p: int, ne: int, ndofs: int) -> int:
     """Recomputed-geometry diffusion: x + y + w*kappa per point + 8 corner nodes per
     element + int32 element->dof map, per apply."""
@@ -114,7 +121,10 @@ def setup_problem(P, torch, p, target, scatter):
     qg = S.qdata(P.DIFFUSION_GEOM, coeff=kappa)
     qgr = S.qdata(P.GRADIENT, coeff=kappa) if p <= 4 else None
     qdv = qgr if qgr is not None else S.qdata(P.DIVERGENCE, coeff=kappa)
-    del kappa
+    # linear elasticity with (lambda, mu) = (kappa, kappa / 2) per point
+    lm = torch.stack([kappa, 0.5 * kappa], dim=-1).contiguous()
+    qel = S.qdata(P.ELASTICITY, coeff=lm)
+    del kappa, lm
     # convection with the constant velocity (1, 1/2, 1/4)
     beta = torch.tensor([1.0, 0.5, 0.25], dtype=torch.float64, device="cuda").repeat(ne * (p + 2) ** 3)
     qc = S.qdata(P.CONVECTION, coeff=beta)
@@ -129,6 +139,9 @@ def setup_problem(P, torch, p, target, scatter):
     # divergence: the gradient's quadrature data (9 values per point) serve both kinds
     extra["div"] = P.Operator(S, P.DIVERGENCE, qdv, constrained=False)
     extra["div_x"] = x.repeat(3)
+    extra["elas"] = P.Operator(S, P.ELASTICITY, qel)
+    extra["elas_x"] = extra["div_x"]
+    extra["elas_y"] = torch.empty(3 * S.ndofs, dtype=torch.float64, device="cuda")
     return {
         **extra,
         "p": p, "n": n, "space": S, "ne": S.nelem, "ndofs": S.ndofs,
@@ -513,7 +526,7 @@ def main():
     ap.add_argument("--no-geom", action="store_true",
                     help="skip the recomputed-geometry diffusion variant")
     ap.add_argument("--no-conv", action="store_true",
-                    help="skip the convection, gradient and divergence operators")
+                    help="skip the convection, gradient, divergence and elasticity operators")
     ap.add_argument("--forms", default="mixed,batched,learned,pmg,paper2d",
                     help="solver forms to measure beside the sweep ('' = none)")
     ap.add_argument("--pmg-orders", default="3,6",
@@ -607,6 +620,15 @@ def main():
             div[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
                                  "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
 
+    elas = {}
+    if not args.no_conv:
+        eper, _ = time_applies(torch, probs, "elas", max(3, args.steps // 2), 1)
+        for pr, t in zip(probs, eper):
+            by = elas_algorithmic_bytes(pr["p"], pr["ne"], pr["ndofs"])
+            elas[str(pr["p"])] = {"ms": round(t * 1e3, 4),
+                                  "gdofs": round(3 * pr["ndofs"] / t / 1e9, 3),
+                                  "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
+
     # dominant kernel: the order whose apply takes the longest
     k = max(range(len(probs)), key=lambda i: per[i])
     dom = probs[k]
@@ -657,7 +679,7 @@ def main():
                    "orders": orders, "scatter": args.scatter, "per_p": per_p,
                    "mass_apply": mass, "recomputed_geometry_apply": geom,
                    "convection_apply": conv, "gradient_apply": grad,
-                   "divergence_apply": div,
+                   "divergence_apply": div, "elasticity_apply": elas,
                    "vector_diffusion_apply": vec3, "setup_seconds": round(t_setup, 1),
                    "timed_wall_seconds": round(wall, 4)},
         "roofline": roofline,

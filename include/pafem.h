@@ -85,6 +85,15 @@ typedef int32_t pafem_status;
  * 3 * ndofs values, component-major (x[c * ndofs + i]), the output ndofs.
  * Unconstrained (flags 0), atomic scatter, FP64, hexahedra. */
 #define PAFEM_DIVERGENCE 5
+/* Isotropic linear elasticity on the vector H1 space, a(u, v) = int lambda
+ * (div u)(div v) + 2 mu eps(u) : eps(v) with eps(u) = (grad u + grad u^T)/2 (the
+ * vector-valued integrators of "GPU Acceleration"): qdata per point J^{-1} (9
+ * values), alpha det J lambda and alpha det J mu, from a coefficient array of
+ * (lambda, mu) pairs per point, [E][Q^3][2].  x and y have 3 * ndofs values,
+ * component-major; PAFEM_OP_CONSTRAINED eliminates the essential dofs of every
+ * component (y_c = x_c there).  Atomic scatter, FP64, hexahedra, orders 1..8; no
+ * diagonal or CG on it. */
+#define PAFEM_ELASTICITY 6
 
 /* Storage types. */
 #define PAFEM_F64 0
@@ -203,6 +212,7 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
  *   gradient:   E * 9 * Q^3  D_q = alpha_q kappa_q det J_q J_q^{-T}, [c][b] with c the
  *                            output component and b the reference derivative.
  *   divergence: the gradient's layout and values (c the input component).
+ *   elasticity: E * 11 * Q^3  J^{-1} as [b][d] (9), alpha det J lambda, alpha det J mu.
  * Quadrilateral spaces: Q^2 points per element, diffusion 3 components
  * (00, 01, 11), mass 1.  All layouts are padded to whole apply tiles.
  * Errors: EUNSUPPORTED if q1d is not one of the built rules (q1d = p+2). */

@@ -84,7 +84,7 @@ void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st, 
       launch_fill(static_cast<double*>(y), 0.0, 3 * s.ndofs, st);  // three output components
     } else if (op.kind == PAFEM_DIVERGENCE) {
       launch_fill(static_cast<double*>(y), 0.0, s.ndofs, st);
-    } else if (op.flags & PAFEM_OP_VECTOR3) {
+    } else if ((op.flags & PAFEM_OP_VECTOR3) || op.kind == PAFEM_ELASTICITY) {
       for (int c = 0; c < 3; ++c)
         launch_scatter_init(s.dev, static_cast<const double*>(x) + c * s.ndofs, constrained,
                             static_cast<double*>(y) + c * s.ndofs, st);
@@ -320,7 +320,8 @@ pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int6
       *nvalues = qdata_values_2d(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 3 : 1);
     } else {
       const int nc = kind == PAFEM_DIFFUSION ? 6 : kind == PAFEM_CONVECTION ? 3
-                     : (kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE) ? 9 : 1;
+                     : (kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE) ? 9
+                     : kind == PAFEM_ELASTICITY ? 11 : 1;
       *nvalues = qdata_values(space->s->ne, q1d, nc);
     }
   });
@@ -338,6 +339,8 @@ pafem_status pafem_qdata_assemble(pafem_space space, int32_t kind, int32_t q1d,
             "quadrilaterals support the mass and diffusion operators");
     require(kind != PAFEM_CONVECTION || coeff, PAFEM_EINVAL,
             "the convection operator needs the velocity field");
+    require(kind != PAFEM_ELASTICITY || coeff, PAFEM_EINVAL,
+            "the elasticity operator needs the (lambda, mu) pairs");
     auto st = static_cast<hipStream_t>(stream);
     hip_check(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(s.dev.status), INT_MAX, 1, st),
               "status init");
@@ -362,6 +365,12 @@ pafem_status pafem_op_create(pafem_space space, int32_t kind, int32_t q1d, const
       require(flags == 0, PAFEM_EUNSUPPORTED,
               "the gradient operator is unconstrained with the atomic scatter");
       require(s.p <= 4, PAFEM_EUNSUPPORTED, "the gradient operator is built for orders 1..4");
+    }
+    if (kind == PAFEM_ELASTICITY) {
+      require(s.dim == 3, PAFEM_EUNSUPPORTED, "the elasticity operator is built for hexahedra");
+      require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "the elasticity operator is FP64");
+      require((flags & ~PAFEM_OP_CONSTRAINED) == 0, PAFEM_EUNSUPPORTED,
+              "the elasticity operator is vector-valued by itself, with the atomic scatter");
     }
     if (kind == PAFEM_DIVERGENCE) {
       require(s.dim == 3, PAFEM_EUNSUPPORTED, "the divergence operator is built for hexahedra");
@@ -434,7 +443,7 @@ pafem_status pafem_op_diagonal(pafem_op op, double* diag, void* work, size_t wor
     require(op->op.kind != PAFEM_DIFFUSION_GEOM, PAFEM_EUNSUPPORTED,
             "diagonal: use the PAFEM_DIFFUSION operator of the same space and coefficient");
     require(!mixed_or_nonsymmetric(op->op.kind), PAFEM_EUNSUPPORTED,
-            "diagonal of the convection, gradient and divergence operators is not built");
+            "diagonal of the convection, gradient, divergence and elasticity operators is not built");
     require(!(op->op.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED,
             "vector operator: every component has the scalar operator's diagonal");
     require(work && work_bytes >= op_work_bytes(op->op), PAFEM_ESHAPE, "workspace too small");
@@ -489,7 +498,8 @@ pafem_status pafem_pcg_solve(pafem_op op, const double* diag, const double* b, d
     require(op && b && x && work && opts && result, PAFEM_EINVAL, "null pointer argument");
     const Op& o = op->op;
     require(o.qdtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "PCG needs an f64 operator");
-    require(!mixed_or_nonsymmetric(o.kind), PAFEM_EINVAL, "CG needs a symmetric operator");
+    require(!mixed_or_nonsymmetric(o.kind), PAFEM_EINVAL,
+            "CG needs a symmetric operator on a scalar space");
     require(!(o.flags & PAFEM_OP_VECTOR3), PAFEM_EUNSUPPORTED,
             "CG on vector operators: solve each component with the scalar operator");
     require(opts->precond == PAFEM_PRECOND_NONE || opts->precond == PAFEM_PRECOND_JACOBI,

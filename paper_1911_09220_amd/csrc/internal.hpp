@@ -20,11 +20,14 @@ constexpr int kMaxQ1d = 12;  // 1D tables are built for every q1d in [1, kMaxQ1d
 
 inline bool known_kind(int kind) {
   return kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM ||
-         kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE;
+         kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE ||
+         kind == PAFEM_ELASTICITY;
 }
-// operators that are not symmetric positive definite on one space: no diagonal, no CG
+// operators that are not symmetric positive definite on one scalar space (mixed,
+// non-symmetric or vector-valued): no diagonal, no CG
 inline bool mixed_or_nonsymmetric(int kind) {
-  return kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE;
+  return kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE ||
+         kind == PAFEM_ELASTICITY;
 }
 
 // Thrown inside the library and turned into a status at the C boundary.

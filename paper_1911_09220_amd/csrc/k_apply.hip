@@ -649,6 +649,11 @@ bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool con
     }
     return ok;
   }
+  if (kind == PAFEM_ELASTICITY) {
+    if (evec || dotp || qdtype != PAFEM_F64 || vdtype != PAFEM_F64) return false;
+    ok = launch_elasticity(sp, constrained, static_cast<const double*>(qd),
+                           static_cast<const double*>(x), static_cast<double*>(out), st);
+  } else {
 #define PAFEM_ORDER_CASE(P_)                                                                   \
   case P_:                                                                                     \
     ok = launch_order<P_>(sp, kind, qdtype, vdtype, constrained, evec, qd, x, out, dotp, st); \
@@ -665,6 +670,7 @@ bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool con
     default: ok = false;
   }
 #undef PAFEM_ORDER_CASE
+  }
   if (ok) {
     hipError_t err = hipGetLastError();
     if (err != hipSuccess)

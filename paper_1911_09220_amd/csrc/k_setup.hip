@@ -96,7 +96,10 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* _
     if (!(det > 0.0)) atomicMin(&status[0], orig[e]);
     const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
     const double w = tv.wts[q1] * tv.wts[q2] * tv.wts[q3];
-    const double c = scale * (coeff ? coeff[size_t(orig[e]) * QQQ + q] : 1.0);
+    // scalar coefficient per point (convection and elasticity read theirs below)
+    const double c = (kind == PAFEM_CONVECTION || kind == PAFEM_ELASTICITY)
+                         ? 0.0
+                         : scale * (coeff ? coeff[size_t(orig[e]) * QQQ + q] : 1.0);
     if (kind == PAFEM_MASS) {
       qd[qdata_index(e, 0, q, Q, 1)] = w * c * det;
     } else if (kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE) {
@@ -113,6 +116,15 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* _
       qd[qdata_index(e, 6, q, Q, 9)] = f * A02;
       qd[qdata_index(e, 7, q, Q, 9)] = f * A12;
       qd[qdata_index(e, 8, q, Q, 9)] = f * A22;
+    } else if (kind == PAFEM_ELASTICITY) {
+      // J^{-1} = A / det J as [b][d] = d xhat_b / d x_d, then w det J lambda and
+      // w det J mu, lambda and mu from the point's coefficient pair
+      const double* lm = coeff + (size_t(orig[e]) * QQQ + q) * 2;
+      const double id = 1.0 / det, wd = scale * w * det;
+      const double Kinv[9] = {A00, A01, A02, A10, A11, A12, A20, A21, A22};
+      for (int k = 0; k < 9; ++k) qd[qdata_index(e, k, q, Q, 11)] = Kinv[k] * id;
+      qd[qdata_index(e, 9, q, Q, 11)] = wd * lm[0];
+      qd[qdata_index(e, 10, q, Q, 11)] = wd * lm[1];
     } else if (kind == PAFEM_CONVECTION) {
       // alpha det J J^{-1} beta = alpha adj(J) beta, beta = scale * velocity at the point
       const double* v = coeff + (size_t(orig[e]) * QQQ + q) * 3;

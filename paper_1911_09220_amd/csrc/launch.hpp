@@ -35,6 +35,10 @@ void launch_scatter_init_f32(const DevSpace& sp, const float* x, bool constraine
 // null): receives pa_apply_blocks(sp) partial sums of the element energies
 // u_E . A_E u_E (essential inputs 0 when constrained), one per workgroup.
 // Returns false if (p, q1d, dtype) is not instantiated.
+// isotropic linear elasticity on the vector space (k_elastic.hip); false when the order
+// is not built
+bool launch_elasticity(const DevSpace& sp, bool constrained, const double* qd, const double* x,
+                       double* y, hipStream_t st);
 bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool constrained,
                      bool evec, const void* qd, const void* x, void* out, int vdtype,
                      hipStream_t st, double* dotp = nullptr);

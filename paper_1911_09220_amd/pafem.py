@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpafem.so")
 
-MASS, DIFFUSION, DIFFUSION_GEOM, CONVECTION, GRADIENT, DIVERGENCE = 0, 1, 2, 3, 4, 5
+MASS, DIFFUSION, DIFFUSION_GEOM, CONVECTION, GRADIENT, DIVERGENCE, ELASTICITY = 0, 1, 2, 3, 4, 5, 6
 F64, F32, BF16 = 0, 1, 2
 SPACE_RENUMBER = 1
 OP_CONSTRAINED, OP_SCATTER_EVEC, OP_VECTOR3 = 1, 2, 4
@@ -482,12 +482,16 @@ class Space:
 
     def qdata(self, kind, q1d=None, coeff=None, scale=1.0):
         """Quadrature data of an operator kind; coeff per point [E*Q^dim] (for
-        CONVECTION the velocity, [E*Q^3*3])."""
+        CONVECTION the velocity, [E*Q^3*3]; for ELASTICITY (lambda, mu) pairs, [E*Q^3*2])."""
         import torch
         q1d = self.p + 2 if q1d is None else q1d
         if kind == CONVECTION:
             if coeff is None or coeff.numel() != self.nelem * q1d ** 3 * 3 or not coeff.is_contiguous():
                 raise ValueError("convection needs a contiguous velocity [E][Q^3][3]")
+        elif kind == ELASTICITY:
+            if (coeff is None or coeff.numel() != self.nelem * q1d ** 3 * 2 or not coeff.is_contiguous()
+                    or coeff.dtype != torch.float64):
+                raise ValueError("elasticity needs contiguous float64 (lambda, mu) pairs [E][Q^3][2]")
         else:
             self._check_qp_array(coeff, q1d, "coeff")
         qd = torch.empty(pafem_qdata_size(self.handle, kind, q1d), dtype=torch.float64,
@@ -543,8 +547,8 @@ class Operator:
                              f"{self.space.ndofs}")
 
     def apply(self, x, y=None):
-        """y = A x; GRADIENT writes and DIVERGENCE reads 3 * ndofs values
-        (component-major)."""
+        """y = A x; GRADIENT writes, DIVERGENCE reads, ELASTICITY and vector operators
+        read and write 3 * ndofs values (component-major)."""
         import torch
         nout = 3 if self.kind == GRADIENT else 1
         if self.kind == DIVERGENCE:
@@ -558,10 +562,12 @@ class Operator:
             return y
         if y is None:
             y = torch.empty(nout * x.numel(), dtype=x.dtype, device=x.device)
-        if self.vector:
+        if self.vector or self.kind == ELASTICITY:
             for v, nm in ((x, "x"), (y, "y")):
-                if v.numel() != 3 * self.space.ndofs or not v.is_contiguous() or not v.is_cuda:
-                    raise ValueError(f"{nm} must be a contiguous device vector of {3 * self.space.ndofs}")
+                if (v.numel() != 3 * self.space.ndofs or not v.is_contiguous() or not v.is_cuda
+                        or v.dtype != torch.float64):
+                    raise ValueError(f"{nm} must be a contiguous float64 device vector of "
+                                     f"{3 * self.space.ndofs}")
             pafem_op_apply(self.handle, x, y, self.work)
             return y
         self._check_vec(x, "x")

@@ -476,3 +476,86 @@ def test_divergence_limits():
     with pytest.raises(P.PafemError):
         P.Operator(S, P.DIVERGENCE, P.lowered_qdata(qd, P.F32), qdata_dtype=P.F32,
                    constrained=False)
+
+
+def _lame_pairs(E, p, seed):
+    lam = synth.lognormal_iid(E, p + 2, 0.5, seed=seed)
+    mu = synth.lognormal_iid(E, p + 2, 0.5, seed=seed + 1)
+    pairs = np.stack([np.reshape(lam, (E, -1)), np.reshape(mu, (E, -1))], axis=-1)
+    return lam, mu, _cuda(pairs.ravel())
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_elasticity_apply(p):
+    """Linear elasticity with lognormal lambda and mu per point on rotated jittered
+    elements, three-component input: against the oracle's assembled vector operator,
+    unconstrained and with every component's essential dofs eliminated, to 1e-12."""
+    mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=130 + p, rotate_seed=230 + p)
+    E = mesh["hex"].shape[0]
+    lam, mu, lm = _lame_pairs(E, p, 131 + p)
+    S, X, _ = _setup(mesh, p, renumber=(p % 2 == 1))
+    qd = S.qdata(P.ELASTICITY, coeff=lm)
+    ref = oracle.H1Space(mesh, p)
+    Ke = forms.element_elasticity(mesh, p, p + 2, lam, mu)
+    nd = Ke.shape[2]
+    V = forms.vector_space(ref)
+    K = oracle.assemble(V, Ke.reshape(E, 3 * nd, 3 * nd))
+    Xo = ref.dof_coordinates()
+    perm = match_by_coords(X, Xo)
+    x3 = _cuda(np.concatenate([synth.hash_normal(X, seed=140 + c) for c in range(3)]))
+    xo = np.concatenate([synth.hash_normal(Xo, seed=140 + c) for c in range(3)])
+    for constrained in (False, True):
+        op = P.Operator(S, P.ELASTICITY, qd, constrained=constrained)
+        y = op.apply(x3).cpu().numpy().reshape(3, -1)
+        A = oracle.constrain(K, np.zeros(V.ndofs), V.boundary)[0] if constrained else K
+        want = (A @ xo).reshape(3, -1)[:, perm]
+        err = rel_err(y.ravel(), want.ravel())
+        print(f"elasticity p={p} constrained={constrained}: rel err {err:.2e}")
+        assert err <= TOL
+
+
+@pytest.mark.parametrize("p", [2, 3, 6])
+def test_elasticity_properties_many_tiles(p):
+    """At ~1e5 dofs: the six rigid-body fields give K u = 0 (unconstrained, point-varying
+    lambda and mu), and the operator is symmetric, <v, K u> = <u, K v>."""
+    n = {2: 24, 3: 16, 6: 8}[p]
+    mesh = synth.hex_lattice(n, 0.1, seed=150 + p, rotate_seed=250 + p)
+    E = mesh["hex"].shape[0]
+    _, _, lm = _lame_pairs(E, p, 151 + p)
+    S, X, _ = _setup(mesh, p)
+    op = P.Operator(S, P.ELASTICITY, S.qdata(P.ELASTICITY, coeff=lm), constrained=False)
+    u = _cuda(np.concatenate([synth.hash_normal(X, seed=160 + c) for c in range(3)]))
+    Ku = op.apply(u)
+    scale = float(Ku.abs().max())
+    modes = [np.tile(e_, (S.ndofs, 1)) for e_ in np.eye(3)]
+    modes += [np.cross(w, X) for w in np.eye(3)]
+    for m in modes:
+        r = op.apply(_cuda(m.T.ravel()))
+        assert float(r.abs().max()) <= 1e-12 * scale * max(1.0, float(np.abs(m).max()))
+    v = _cuda(np.concatenate([synth.hash_normal(X, seed=170 + c) for c in range(3)]))
+    a, b = float(v @ Ku), float(u @ op.apply(v))
+    assert abs(a - b) <= 1e-12 * float((v.abs() @ Ku.abs()))
+
+
+def test_elasticity_limits():
+    S = P.Space(P.Mesh.from_dict(synth.hex_lattice(2, 0.1, seed=1)), 2)
+    E = S.nelem
+    _, _, lm = _lame_pairs(E, 2, 5)
+    qd = S.qdata(P.ELASTICITY, coeff=lm)
+    with pytest.raises(ValueError):
+        S.qdata(P.ELASTICITY)                               # needs (lambda, mu)
+    with pytest.raises(P.PafemError):
+        P.Operator(S, P.ELASTICITY, qd, scatter="evec")
+    with pytest.raises(P.PafemError):
+        P.Operator(S, P.ELASTICITY, qd, vector=True)        # vector-valued by itself
+    op = P.Operator(S, P.ELASTICITY, qd)
+    with pytest.raises(P.PafemError):
+        op.diagonal()
+    with pytest.raises(ValueError):
+        op.apply(torch.zeros(S.ndofs, dtype=torch.float64, device="cuda"))  # needs 3 * ndofs
+    n3 = 3 * S.ndofs
+    with pytest.raises(P.PafemError):
+        op.pcg(torch.ones(S.ndofs, dtype=torch.float64, device="cuda"),
+               diag=torch.ones(S.ndofs, dtype=torch.float64, device="cuda"))
+    y = op.apply(torch.zeros(n3, dtype=torch.float64, device="cuda"))
+    assert float(y.abs().max()) == 0.0
