@@ -111,3 +111,29 @@ def test_quad_element_dof_map_matches_oracle(p, rotate, renumber):
     if not renumber:
         cls = ref.dof_class[perm]          # vertices, then edges, then interiors
         assert np.all(np.diff(cls) >= 0)
+
+
+def test_empty_mesh_rejected():
+    with pytest.raises(pafem.PafemError) as ei:
+        pafem.Mesh(np.zeros((8, 3)), np.zeros((0, 8), dtype=np.int64))
+    assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("p", [1, 3, 8])
+def test_qdata_sizes_per_kind(p):
+    """Values per point of every operator kind, padded to whole apply tiles of
+    floor(256 / Q^2) elements; unknown kinds and q1d outside the tables are refused."""
+    mesh = synth.hex_lattice((3, 2, 2), 0.1, seed=4)
+    S = pafem.Space(pafem.Mesh.from_dict(mesh), p, device=None)
+    Q = p + 2
+    nt = max(1, 256 // (Q * Q))
+    tiles = -(-S.nelem // nt)
+    per_point = {pafem.MASS: 1, pafem.DIFFUSION: 6, pafem.DIFFUSION_GEOM: 1, pafem.CONVECTION: 3,
+                 pafem.GRADIENT: 9, pafem.DIVERGENCE: 9, pafem.ELASTICITY: 11}
+    for kind, nc in per_point.items():
+        assert pafem.pafem_qdata_size(S.handle, kind, Q) == tiles * nt * nc * Q ** 3
+    for bad_kind in (-1, 7, 16, 17):
+        with pytest.raises(pafem.PafemError):
+            pafem.pafem_qdata_size(S.handle, bad_kind, Q)
+    with pytest.raises(pafem.PafemError):
+        pafem.pafem_qdata_size(S.handle, pafem.DIFFUSION, 13)
