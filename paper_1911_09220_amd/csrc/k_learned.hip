@@ -106,7 +106,10 @@ struct LowRankShape {
 // z += sum_E R_E^t V diag(c_E idb_E) V^t R_E r over the non-essential dofs (z holds
 // the Jacobi part on entry).  Persistent: each workgroup loads V into LDS once and
 // walks one contiguous range of apply tiles (ranges of the workgroups of one XCD
-// are adjacent, so tiles that share dofs share an L2).
+// are adjacent, so tiles that share dofs share an L2).  Per tile every global load
+// (unique dofs, r, slot map, coefficients) is issued before the first barrier, and
+// each thread keeps the unique dofs it gathered for its scatter, so a tile waits on
+// one round of memory latency.
 template <int P, int K>
 __global__ void __launch_bounds__(256)
     lowrank_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
@@ -115,11 +118,13 @@ __global__ void __launch_bounds__(256)
                          const double* __restrict__ r, double* __restrict__ z, int ne, int ntiles) {
   using S = LowRankShape<P, K>;
   constexpr int DDD = S::DDD, NE = S::NE;
+  constexpr int MU = (NE * DDD + 255) / 256;  // unique dofs per thread (at most)
   __shared__ float sV[DDD * K];    // [i][k]
   __shared__ float sVt[K * DDD];   // [k][i]
   __shared__ float sU[NE * DDD];   // the tile's unique dofs: r, later the summed outputs
   __shared__ float sRE[NE * DDD];  // element node values
   __shared__ float sT[NE * K];
+  __shared__ float sC[NE * K];     // c_E idb_E per element and column
   __shared__ uint16_t sSlot[NE * DDD];
   const int tid = threadIdx.x;
   for (int j = tid; j < DDD * K; j += 256) {
@@ -135,12 +140,38 @@ __global__ void __launch_bounds__(256)
     const int nel = min(NE, ne - e0);
     const int u0 = tile_off[tile];
     const int nu = tile_off[tile + 1] - u0;
-    __syncthreads();  // V is in place; the previous tile's outputs are out
-    for (int s = tid; s < nu; s += 256) {
-      const int g = tile_dofs[u0 + s];
-      sU[s] = g < 0 ? 0.f : float(r[g]);
+    int gk[MU];
+#pragma unroll
+    for (int m = 0; m < MU; ++m) {
+      const int s = tid + 256 * m;
+      gk[m] = s < nu ? tile_dofs[u0 + s] : -1;
     }
-    for (int j = tid; j < nel * DDD; j += 256) sSlot[j] = tile_slot[size_t(e0) * DDD + j];
+    float rv[MU];
+#pragma unroll
+    for (int m = 0; m < MU; ++m) rv[m] = gk[m] < 0 ? 0.f : float(r[gk[m]]);
+    uint16_t sl[MU];  // slot map entries j = tid + 256 m < nel * DDD
+#pragma unroll
+    for (int m = 0; m < MU; ++m) {
+      const int j = tid + 256 * m;
+      sl[m] = j < nel * DDD ? tile_slot[size_t(e0) * DDD + j] : uint16_t(0);
+    }
+    constexpr int MC = (NE * K + 255) / 256;
+    float cv[MC];
+#pragma unroll
+    for (int m = 0; m < MC; ++m) {
+      const int j = tid + 256 * m;
+      cv[m] = j < nel * K ? c[size_t(e0) * K + j] * idb[e0 + j / K] : 0.f;
+    }
+    __syncthreads();  // V is in place; the previous tile's outputs are out
+#pragma unroll
+    for (int m = 0; m < MU; ++m) {
+      const int j = tid + 256 * m;
+      if (j < nu) sU[j] = rv[m];
+      if (j < nel * DDD) sSlot[j] = sl[m];
+    }
+#pragma unroll
+    for (int m = 0; m < MC; ++m)
+      if (tid + 256 * m < nel * K) sC[tid + 256 * m] = cv[m];
     __syncthreads();
     for (int j = tid; j < nel * DDD; j += 256) sRE[j] = sU[sSlot[j]];
     __syncthreads();
@@ -152,7 +183,7 @@ __global__ void __launch_bounds__(256)
       float acc = 0.f;
 #pragma unroll 8
       for (int i = 0; i < DDD; ++i) acc += sV[i * K + k] * re[i];
-      sT[j] = acc * c[size_t(e0 + el) * K + k] * idb[e0 + el];
+      sT[j] = acc * sC[j];
     }
     __syncthreads();
     // y_E = V t, summed per unique dof
@@ -165,10 +196,9 @@ __global__ void __launch_bounds__(256)
       atomicAdd(&sU[sSlot[j]], acc);
     }
     __syncthreads();
-    for (int s = tid; s < nu; s += 256) {
-      const int g = tile_dofs[u0 + s];
-      if (g >= 0) unsafeAtomicAdd(&z[g], double(sU[s]));
-    }
+#pragma unroll
+    for (int m = 0; m < MU; ++m)
+      if (gk[m] >= 0) unsafeAtomicAdd(&z[gk[m]], double(sU[tid + 256 * m]));
   }
 }
 
