@@ -438,7 +438,8 @@ class Mesh:
         return cls(m["vertices"], m["hex"], m.get("geom_order", 1), m.get("geom_nodes"))
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module's globals may already be cleared
+        if getattr(self, "handle", None) and lib is not None:
             lib.pafem_mesh_destroy(self.handle)
             self.handle = None
 
@@ -519,7 +520,8 @@ class Space:
         return b
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module's globals may already be cleared
+        if getattr(self, "handle", None) and lib is not None:
             lib.pafem_space_destroy(self.handle)
             self.handle = None
 
@@ -655,7 +657,8 @@ class Operator:
                    "seconds": res.seconds, "history": hist[: res.outer + 1].copy()}
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module's globals may already be cleared
+        if getattr(self, "handle", None) and lib is not None:
             lib.pafem_op_destroy(self.handle)
             self.handle = None
 
@@ -734,7 +737,8 @@ class PMG:
         return x, info
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module's globals may already be cleared
+        if getattr(self, "handle", None) and lib is not None:
             lib.pafem_pmg_destroy(self.handle)
             self.handle = None
 
@@ -774,7 +778,8 @@ class Batch:
         return json.loads(pafem_batch_describe(self.handle))
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module's globals may already be cleared
+        if getattr(self, "handle", None) and lib is not None:
             lib.pafem_batch_destroy(self.handle)
             self.handle = None
 
@@ -845,7 +850,8 @@ class Net:
         _check(lib.pafem_net_adam_step(self.handle, float(lr), _stream()))
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module's globals may already be cleared
+        if getattr(self, "handle", None) and lib is not None:
             lib.pafem_net_destroy(self.handle)
             self.handle = None
 
