@@ -250,3 +250,74 @@ def test_order_multigrid_at_bench_size(pf):
           f"jacobi {ij['iters']} its, solutions differ by {diff:.2e}", flush=True)
     assert info["converged"] and info["true_rel_res"] <= 1.5e-8
     assert diff <= 1e-6
+
+
+@pytest.mark.parametrize("p", [1, 3, 6, 8])
+def test_bench_size_integrator_properties(p):
+    """The further integrators at the sweep sizes, in the configuration the benchmark
+    times, through identities that hold exactly (up to rounding) at any size.  With the
+    linear field u_c = sum_d A[c, d] x_d + b_c (in the space): divergence sum_c V_c u_c =
+    tr(A) M_kappa 1; gradient of u_0, component c: A[0, c] M_kappa 1; convection of u_0
+    with constant beta: (beta . A[0]) M_1 1.  Elasticity annihilates the six rigid-body
+    fields, and its constrained form returns x on the essential dofs."""
+    n = _lattice_n(p)
+    mesh = synth.hex_lattice(n, 0.05, seed=2)
+    E = mesh["hex"].shape[0]
+    kappa = synth.lognormal_iid(E, p + 2, 1.0, seed=3)
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    del mesh
+    X = S.dof_coords()
+    kc = torch.as_tensor(kappa, device="cuda")
+    N = S.ndofs
+    print(f"p={p}: {E} elements, {N} dofs", flush=True)
+    A = np.array([[0.3, -1.1, 0.4], [0.9, 1.7, -0.2], [0.5, 0.8, -2.3]])
+    u = X @ A.T + np.array([0.2, -0.7, 1.3])          # u_c = sum_d A[c, d] x_d + b_c
+    ones = torch.ones(N, dtype=torch.float64, device="cuda")
+    mk1 = P.Operator(S, P.MASS, S.qdata(P.MASS, coeff=kc), constrained=False).apply(ones)
+    mk1 = mk1.cpu().numpy()
+    u3 = torch.as_tensor(np.ascontiguousarray(u.T).ravel(), device="cuda")
+    # divergence: div u = tr(A)
+    qg = S.qdata(P.DIVERGENCE, coeff=kc)
+    y = P.Operator(S, P.DIVERGENCE, qg, constrained=False).apply(u3).cpu().numpy()
+    err = rel_err(y, np.trace(A) * mk1)
+    print(f"p={p} divergence: rel err {err:.2e}", flush=True)
+    assert err <= TOL
+    # gradient of the scalar u_0 = A[0] . x + b_0: component c is A[0, c] M_kappa 1
+    if p <= 4:
+        y = P.Operator(S, P.GRADIENT, qg, constrained=False).apply(u3[:N].contiguous())
+        y = y.cpu().numpy().reshape(3, -1)
+        err = max(rel_err(y[c], A[0, c] * mk1) for c in range(3))
+        print(f"p={p} gradient: rel err {err:.2e}", flush=True)
+        assert err <= TOL
+    del qg
+    # convection of u_0 with constant beta: beta . grad u_0 = beta . A[0]
+    beta = np.array([1.0, 0.5, 0.25])
+    bq = torch.tensor(beta, dtype=torch.float64, device="cuda").repeat(E * (p + 2) ** 3)
+    conv = P.Operator(S, P.CONVECTION, S.qdata(P.CONVECTION, coeff=bq), constrained=False)
+    del bq
+    m1 = P.Operator(S, P.MASS, S.qdata(P.MASS), constrained=False).apply(ones).cpu().numpy()
+    y = conv.apply(u3[:N].contiguous()).cpu().numpy()
+    err = rel_err(y, float(beta @ A[0]) * m1)
+    print(f"p={p} convection: rel err {err:.2e}", flush=True)
+    assert err <= TOL
+    del conv
+    # elasticity: rigid-body fields, and the constrained form's essential rows
+    lm = torch.stack([kc, 0.5 * kc], dim=-1).contiguous()
+    qe = S.qdata(P.ELASTICITY, coeff=lm)
+    del lm
+    el = P.Operator(S, P.ELASTICITY, qe, constrained=False)
+    w = torch.as_tensor(np.concatenate([synth.hash_normal(X, seed=70 + c) for c in range(3)]),
+                        device="cuda")
+    scale = float(el.apply(w).abs().max())
+    worst = 0.0
+    modes = [np.tile(e_, (N, 1)) for e_ in np.eye(3)] + [np.cross(v, X) for v in np.eye(3)]
+    for m in modes:
+        r = el.apply(torch.as_tensor(np.ascontiguousarray(m.T).ravel(), device="cuda"))
+        worst = max(worst, float(r.abs().max()) / scale)
+    print(f"p={p} elasticity: rigid-body residual {worst:.2e} of max|K w|", flush=True)
+    assert worst <= 1e-12
+    elc = P.Operator(S, P.ELASTICITY, qe, constrained=True)
+    yc = elc.apply(w).cpu().numpy().reshape(3, -1)
+    bd = S.boundary_dofs()
+    wn = w.cpu().numpy().reshape(3, -1)
+    assert np.array_equal(yc[:, bd], wn[:, bd])
