@@ -106,15 +106,21 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
   // D for this thread's z-line (qx, qy) = r: issued first so the HBM stream
   // overlaps the gather and the forward contractions (tile-interleaved: for each
   // (c, qz) the workgroup reads one contiguous run)
+  // At p = 5 (stored-D scalar FP64 diffusion) only the first PD planes are loaded here
+  // and each later plane one z-iteration ahead of its use: the registers of the other
+  // planes lift the occupancy from 2 to 3 waves per SIMD (0.434 -> 0.383 ms at 1e7 dofs).
+  // At p = 6..8 the LDS of a tile or the contraction registers still allow only 2, and
+  // streaming there only exposes the load latency (1-2% slower).
+  constexpr int PD = (P == 5 && K0 == PAFEM_DIFFUSION && NV == 1 && sizeof(TC) == 8) ? 2 : Q;
   TC dq[Q][NC];
+  const TD* const qe0 = qd + size_t(tile) * NCT * QQQ * NE + tid;
   auto load_dq = [&](int cbase) {
     if (act) {
-      const TD* qe = qd + size_t(tile) * NCT * QQQ * NE + tid;
 #pragma unroll
-      for (int qz = 0; qz < Q; ++qz)
+      for (int qz = 0; qz < PD; ++qz)
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-          dq[qz][c] = load_value<TC, TD>(qe + ((cbase + c) * Q + qz) * (NE * QQ));
+          dq[qz][c] = load_value<TC, TD>(qe0 + ((cbase + c) * Q + qz) * (NE * QQ));
     }
   };
   if (!DIVV) load_dq(0);
@@ -256,6 +262,14 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q)
     for (int dz = 0; dz < D; ++dz) t0[dz] = t1[dz] = t2[dz] = TC(0);
 #pragma unroll
     for (int qz = 0; qz < Q; ++qz) {
+      if constexpr (PD < Q) {
+        if (qz + PD < Q) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            dq[qz + PD][c] = load_value<TC, TD>(qe0 + (c * Q + qz + PD) * (NE * QQ));
+        }
+        __asm__ volatile("" ::: "memory");  // keep the next plane's loads in this iteration
+      }
       if constexpr (DIFF) {
         TC ux = TC(0), uy = TC(0), uz = TC(0);
 #pragma unroll
