@@ -40,7 +40,7 @@ constexpr int elems_per_block() {
 }
 
 template <int P, int Q, int KIND, bool EVEC, bool DOT, typename TV, typename TD, typename TC>
-__global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, (P == 6 && KIND == PAFEM_DIFFUSION && sizeof(TC) == 4) ? 5 : 1)
+__global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DIFFUSION ? 1 : sizeof(TC) == 4 ? (P == 6 ? 5 : 1) : P == 4 ? 4 : 1)
     pa_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
                     const uint16_t* __restrict__ tile_slot, const TC* __restrict__ tabB,
                     const TC* __restrict__ tabG, const TD* __restrict__ qd,
@@ -106,15 +106,16 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, (P == 6 && KIND 
   // D for this thread's z-line (qx, qy) = r: issued first so the HBM stream
   // overlaps the gather and the forward contractions (tile-interleaved: for each
   // (c, qz) the workgroup reads one contiguous run)
-  // Stored-D scalar diffusion at p = 5, and at p = 6 in FP32 (the refinement's inner
-  // operator): only the first PD planes are loaded here and each later plane one
-  // z-iteration ahead of its use.  The registers of the other planes lift the occupancy
-  // from 2 to 3 waves per SIMD (FP64, p = 5: 0.434 -> 0.383 ms at 1e7 dofs) and, with the
-  // launch bound's request for 5 waves, from 4 to 5 (FP32, p = 6: 0.462 -> 0.445 ms at
-  // 2e7 dofs).  At p = 6..8 in FP64 a tile's LDS or the contraction registers still allow
-  // only 2 waves, and streaming there only exposes the load latency (1-2% slower).
+  // Stored-D scalar diffusion at p = 4, 5 in FP64 and at p = 6 in FP32 (the refinement's
+  // inner operator): only the first PD planes are loaded here and each later plane one
+  // z-iteration ahead of its use.  The registers of the other planes lift the occupancy,
+  // with the launch bound's request where needed: FP64 p = 4 from 3 to 4 waves per SIMD
+  // (0.431 -> 0.419 ms at 1e7 dofs), p = 5 from 2 to 3 (0.434 -> 0.383 ms), FP32 p = 6
+  // from 4 to 5 (0.462 -> 0.445 ms at 2e7 dofs).  Measured and not kept: p = 2 at 6 waves
+  // (spills, 5% slower), p = 3 at 5 waves (spills, 4% slower), FP64 p = 6..8 streamed at
+  // the 2 waves their LDS or contraction registers allow (1-2% slower).
   constexpr int PD =
-      (K0 == PAFEM_DIFFUSION && NV == 1 && sizeof(TC) == (P == 5 ? 8 : P == 6 ? 4 : 0)) ? 2 : Q;
+      (K0 == PAFEM_DIFFUSION && NV == 1 && sizeof(TC) == ((P == 4 || P == 5) ? 8 : P == 6 ? 4 : 0)) ? 2 : Q;
   TC dq[Q][NC];
   const TD* const qe0 = qd + size_t(tile) * NCT * QQQ * NE + tid;
   auto load_dq = [&](int cbase) {
