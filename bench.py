@@ -10,7 +10,7 @@ sweep; `value` = sum_p ndofs_p / sum_p t_p in GDOF/s (every dof, boundary
 included).  The mass apply and Jacobi-PCG time-to-1e-8 are reported beside it.
 All inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build targets one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the benchmark measures one GPU (the sharded path is a design only).
 """
 from __future__ import annotations
 
@@ -536,7 +536,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; the multi-GPU path is not built, so --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
