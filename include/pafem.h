@@ -241,9 +241,15 @@ void pafem_op_destroy(pafem_op op);
 /* Workspace bytes needed by pafem_op_apply / pafem_op_diagonal (0 if none). */
 pafem_status pafem_op_workspace_bytes(pafem_op op, size_t* nbytes);
 
-/* y = A x on device vectors of length ndofs (f64).  x and y must not alias.
- * With PAFEM_OP_CONSTRAINED, y_b = x_b on essential dofs and the essential
- * columns are dropped.  Asynchronous. */
+/* y = A x on device vectors (f64; f32 for an operator on f32 or bf16 qdata).
+ * Lengths: ndofs, except 3 * ndofs (component-major) for y of PAFEM_GRADIENT,
+ * x of PAFEM_DIVERGENCE, and x and y of PAFEM_ELASTICITY and of operators
+ * created with PAFEM_OP_VECTOR3; the library cannot check lengths.  x and y
+ * must not alias.  With PAFEM_OP_CONSTRAINED, y_b = x_b on essential dofs and
+ * the essential columns are dropped (per component for vector operators).
+ * Asynchronous.  Errors: EINVAL (null or aliased pointers), ESHAPE (workspace
+ * too small for the deterministic scatter), EUNSUPPORTED (no kernel built for
+ * the order, q1d or dtype). */
 pafem_status pafem_op_apply(pafem_op op, const double* x, double* y, void* work,
                             size_t work_bytes, void* stream);
 
