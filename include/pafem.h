@@ -269,7 +269,7 @@ pafem_status pafem_linear_form(pafem_space space, int32_t q1d, int32_t source,
 /* -------------------------------------------------------------- solver --- */
 
 typedef struct {
-  double rel_tol;       /* stop when ||r_k||_2 <= rel_tol * ||b||_2 (recursive residual) */
+  double rel_tol;       /* stop when ||r_k||_2 <= rel_tol * ||b||_2 (recursive residual); for b = 0, relative to ||r_0||_2 */
   int32_t max_iter;     /* iteration cap (the paper's ex1p uses 2000) */
   int32_t precond;      /* PAFEM_PRECOND_* */
   int32_t check_every;  /* host reads the convergence flag every this many iterations */

@@ -76,13 +76,16 @@ __global__ void __launch_bounds__(kCGThreads)
   if (threadIdx.x == 0) {
     st->rz = trz;
     st->rr = trr;
-    st->bb = tbb;
-    st->tol2 = rel_tol * rel_tol * tbb;
+    // reference of the relative stop: ||b||^2, or ||r_0||^2 when b = 0 (the answer is
+    // then x = 0 and the iteration reduces the initial residual; both 0: done)
+    const double ref = tbb > 0.0 ? tbb : trr;
+    st->bb = ref;
+    st->tol2 = rel_tol * rel_tol * ref;
     st->iter = 0;
     st->alpha = st->beta = 0.0;
     st->res2 = 0.0;
-    const int conv = (trr <= st->tol2) || (tbb == 0.0);
-    if (hist && st->max_hist > 0) hist[0] = tbb > 0.0 ? sqrt(trr / tbb) : 0.0;
+    const int conv = trr <= st->tol2;
+    if (hist && st->max_hist > 0) hist[0] = ref > 0.0 ? sqrt(trr / ref) : 0.0;
     __hip_atomic_store(&st->done, conv ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&st->ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -235,10 +238,11 @@ __global__ void __launch_bounds__(kCGThreads)
   const double tbb = sum_partials(partials + kCGBlocks, scratch);
   if (threadIdx.x == 0) {
     st->rr = trr;
-    st->bb = tbb;
-    st->tol2 = rel_tol * rel_tol * tbb;
-    const int conv = (trr <= st->tol2) || (tbb == 0.0);
-    if (hist && st->max_hist > 0) hist[0] = tbb > 0.0 ? sqrt(trr / tbb) : 0.0;
+    const double ref = tbb > 0.0 ? tbb : trr;  // as in cg_init_kernel
+    st->bb = ref;
+    st->tol2 = rel_tol * rel_tol * ref;
+    const int conv = trr <= st->tol2;
+    if (hist && st->max_hist > 0) hist[0] = ref > 0.0 ? sqrt(trr / ref) : 0.0;
     __hip_atomic_store(&st->done, conv ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&st->ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }

@@ -559,3 +559,30 @@ def test_elasticity_limits():
                diag=torch.ones(S.ndofs, dtype=torch.float64, device="cuda"))
     y = op.apply(torch.zeros(n3, dtype=torch.float64, device="cuda"))
     assert float(y.abs().max()) == 0.0
+
+
+def test_degenerate_solves():
+    """One p = 1 element (every dof essential): the constrained operator is the identity,
+    its diagonal is 1 and CG returns b after one iteration.  A zero right-hand side from a
+    zero start is solved with no iteration; from a random start the stop is relative to the
+    initial residual and the iterate goes to zero."""
+    S1 = P.Space(P.Mesh.from_dict(synth.hex_lattice(1, 0.0)), 1)
+    op1 = P.Operator(S1, P.DIFFUSION, S1.qdata(P.DIFFUSION))
+    v = _cuda(np.arange(S1.ndofs, dtype=np.float64) + 1.0)
+    assert torch.equal(op1.apply(v), v)
+    assert torch.equal(op1.diagonal(), torch.ones_like(v))
+    x, info = op1.pcg(v, rel_tol=1e-12)
+    assert info["status"] == "OK" and info["iters"] <= 1
+    assert float((x - v).abs().max()) <= 1e-15 * float(v.abs().max())
+
+    S = P.Space(P.Mesh.from_dict(synth.hex_lattice(4, 0.1, seed=9)), 2)
+    op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION))
+    zero = torch.zeros(S.ndofs, dtype=torch.float64, device="cuda")
+    x, info = op.pcg(zero, rel_tol=1e-10)
+    assert info["status"] == "OK" and info["iters"] == 0 and float(x.abs().max()) == 0.0
+    x0 = _cuda(synth.hash_normal(S.dof_coords(), seed=3))
+    x, info = op.pcg(zero, x=x0.clone(), rel_tol=1e-10, max_iter=5000)
+    print(f"zero rhs from a random start: {info['iters']} its, rel res {info['rel_res']:.1e}, "
+          f"|x|/|x0| {float(x.norm() / x0.norm()):.1e}")
+    assert info["status"] == "OK" and info["iters"] > 0 and info["rel_res"] <= 1e-10
+    assert float(x.norm()) <= 1e-6 * float(x0.norm())
