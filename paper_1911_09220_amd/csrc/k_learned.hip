@@ -356,7 +356,24 @@ void lowrank_apply_p(const DevSpace& sp, const float* V, const float* c, const f
   if (sp.tile_ne != LowRankShape<P, kLowRank>::NE)
     throw Error(PAFEM_EINVAL, "low-rank apply: tile size differs from the apply tiles");
   const int nt = ntiles_of(sp);
-  hipLaunchKernelGGL((lowrank_apply_kernel<P, kLowRank>), dim3(std::min(nt, kLowRankApplyBlocks)),
+  // persistent grid: at most as many workgroups as are resident at once on this device
+  // (a second, partial wave of workgroups would double the time of its tiles)
+  static int resident[64] = {0};
+  auto ok = [](hipError_t e, const char* what) {
+    if (e != hipSuccess) throw Error(PAFEM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  int dev = 0;
+  ok(hipGetDevice(&dev), "device");
+  if (dev < 0 || dev >= 64) dev = 0;
+  if (resident[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lowrank_apply_kernel<P, kLowRank>,
+                                                    256, 0),
+       "occupancy");
+    ok(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CUs");
+    resident[dev] = std::max(1, std::min(kLowRankApplyBlocks, per_cu * cus));
+  }
+  hipLaunchKernelGGL((lowrank_apply_kernel<P, kLowRank>), dim3(std::min(nt, resident[dev])),
                      dim3(256), 0, st, sp.tile_off, sp.tile_dofs, sp.tile_slot, V, c, idb, r, z,
                      int(sp.ne), nt);
 }
