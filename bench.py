@@ -119,8 +119,9 @@ def setup_problem(P, torch, p, target, scatter):
     qd = S.qdata(P.DIFFUSION, coeff=kappa)
     qm = S.qdata(P.MASS, coeff=kappa)
     qg = S.qdata(P.DIFFUSION_GEOM, coeff=kappa)
-    qgr = S.qdata(P.GRADIENT, coeff=kappa) if p <= 4 else None
-    qdv = qgr if qgr is not None else S.qdata(P.DIVERGENCE, coeff=kappa)
+    # gradient and divergence share their quadrature data (9 values per point)
+    qgr = S.qdata(P.GRADIENT, coeff=kappa)
+    qdv = qgr
     # linear elasticity with (lambda, mu) = (kappa, kappa / 2) per point
     lm = torch.stack([kappa, 0.5 * kappa], dim=-1).contiguous()
     qel = S.qdata(P.ELASTICITY, coeff=lm)
@@ -132,11 +133,8 @@ def setup_problem(P, torch, p, target, scatter):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(100 + p)
     x = torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=gen)
-    extra = {}
-    if qgr is not None:
-        extra = {"grad": P.Operator(S, P.GRADIENT, qgr, constrained=False),
-                 "grad_y": torch.empty(3 * S.ndofs, dtype=torch.float64, device="cuda")}
-    # divergence: the gradient's quadrature data (9 values per point) serve both kinds
+    extra = {"grad": P.Operator(S, P.GRADIENT, qgr, constrained=False),
+             "grad_y": torch.empty(3 * S.ndofs, dtype=torch.float64, device="cuda")}
     extra["div"] = P.Operator(S, P.DIVERGENCE, qdv, constrained=False)
     extra["div_x"] = x.repeat(3)
     extra["elas"] = P.Operator(S, P.ELASTICITY, qel)

@@ -76,7 +76,7 @@ typedef int32_t pafem_status;
  * det J_q J_q^{-T} (9 values per point), applied as three value contractions
  * B^t (D (B G u))_c.  The output has 3 * ndofs values, component-major
  * (y[c * ndofs + i]).  Unconstrained (flags 0), atomic scatter, FP64,
- * hexahedra, orders 1..4. */
+ * hexahedra, orders 1..8 (from p = 5 on, one pass per output component). */
 #define PAFEM_GRADIENT 4
 /* Divergence, the mixed form (div u, q) with u vector-valued in the same H1
  * space as the scalar test function q (the divergence integrator of "GPU

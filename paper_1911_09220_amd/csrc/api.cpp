@@ -364,7 +364,6 @@ pafem_status pafem_op_create(pafem_space space, int32_t kind, int32_t q1d, const
       require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "the gradient operator is FP64");
       require(flags == 0, PAFEM_EUNSUPPORTED,
               "the gradient operator is unconstrained with the atomic scatter");
-      require(s.p <= 4, PAFEM_EUNSUPPORTED, "the gradient operator is built for orders 1..4");
     }
     if (kind == PAFEM_ELASTICITY) {
       require(s.dim == 3, PAFEM_EUNSUPPORTED, "the elasticity operator is built for hexahedra");

@@ -16,6 +16,9 @@ constexpr int kMaxOrder = 8;
 // kernel-internal operator kinds: kVectorKind + kind applies `kind` to each of three
 // components (PAFEM_OP_VECTOR3)
 constexpr int kVectorKind = 16;
+// kernel-internal: kGradCompKind + c is output component c of PAFEM_GRADIENT alone
+// (its one-accumulator form, used from p = 5 on)
+constexpr int kGradCompKind = 32;
 constexpr int kMaxQ1d = 12;  // 1D tables are built for every q1d in [1, kMaxQ1d]
 
 inline bool known_kind(int kind) {

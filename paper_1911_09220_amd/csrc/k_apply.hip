@@ -52,12 +52,17 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   // GEOM: diffusion storing alpha kappa per point; J recomputed from the 8 corners
   // kinds from kVectorKind on: the same operator on each of 3 components (x and y hold
   // 3 vectors at stride ystride), D read once and kept in registers for all three
-  constexpr int K0 = KIND >= kVectorKind ? KIND - kVectorKind : KIND;
+  // GRADC: output component GC of the gradient operator alone: the convection
+  // contractions with that component's row of the gradient's D (9 values stored per point)
+  constexpr bool GRADC = KIND >= kGradCompKind;
+  constexpr int GC = GRADC ? KIND - kGradCompKind : 0;
+  constexpr bool VEC3 = KIND >= kVectorKind && !GRADC;
+  constexpr int K0 = GRADC ? PAFEM_CONVECTION : VEC3 ? KIND - kVectorKind : KIND;
   // DIVV: divergence of a vector-valued input into a scalar output: the three input
   // components pass the forward contractions one after the other, their point values
   // summed in registers, then one back contraction of values
   constexpr bool DIVV = (K0 == PAFEM_DIVERGENCE);
-  constexpr int NV = (KIND >= kVectorKind || DIVV) ? 3 : 1;
+  constexpr int NV = (VEC3 || DIVV) ? 3 : 1;
   constexpr bool GEOM = (K0 == PAFEM_DIFFUSION_GEOM);
   constexpr bool DIFF = (K0 == PAFEM_DIFFUSION) || GEOM;  // gradient in, gradient out
   // CONV: convection, gradient in, value out (the back contractions are the mass ones)
@@ -69,7 +74,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   constexpr bool BACK3 = DIFF || GRADV;         // three arrays in the back contractions
   // values per point in registers; DIVV stores 9 and reads those of one input component
   constexpr int NC = GEOM ? 1 : DIFF ? 6 : (CONV || DIVV) ? 3 : GRADV ? 9 : 1;
-  constexpr int NCT = DIVV ? 9 : NC;  // stored values per point
+  constexpr int NCT = (DIVV || GRADC) ? 9 : NC;  // stored values per point
   constexpr int NA = GRAD ? 2 : 1;   // arrays after the x-lines (B and G along x)
   constexpr int NCC = GRAD ? 3 : 1;  // arrays after the y-lines (one per derivative)
   constexpr int NOUT = GRADV ? 3 : 1;  // output components
@@ -127,7 +132,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
           dq[qz][c] = load_value<TC, TD>(qe0 + ((cbase + c) * Q + qz) * (NE * QQ));
     }
   };
-  if (!DIVV) load_dq(0);
+  if (!DIVV) load_dq(GRADC ? 3 * GC : 0);
   TC sdiv[DIVV ? Q : 1];  // DIVV: the divergence at this thread's points, summed over components
 #pragma unroll
   for (int qz = 0; qz < (DIVV ? Q : 1); ++qz) sdiv[qz] = TC(0);
@@ -503,7 +508,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
     if (!(constrained && g < 0))
 #pragma unroll
       for (int oc = 0; oc < NOUT; ++oc)
-        unsafeAtomicAdd(&y[(DIVV ? 0 : comp + oc) * ystride + (g < 0 ? ~g : g)],
+        unsafeAtomicAdd(&y[(DIVV ? 0 : GRADC ? GC : comp + oc) * ystride + (g < 0 ? ~g : g)],
                         TV(sX[oc * NE * DDD + s]));
   }
   if (NV > 1) __syncthreads();  // sX is gathered again for the next component
@@ -587,14 +592,21 @@ bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, bool con
     return true;
   }
   if (kind == PAFEM_GRADIENT) {
-    // three output accumulators in LDS: built up to p = 4 (51 KB of LDS per workgroup)
+    if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp || evec) return false;
     if constexpr (P <= 4) {
-      if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp || evec) return false;
+      // all three output components at once: three accumulators in LDS (51 KB at p = 4)
       launch_one<P, PAFEM_GRADIENT, false, false, double, double, double>(sp, constrained, qd, x,
                                                                            out, nullptr, st);
-      return true;
+    } else {
+      // three accumulators no longer fit a workgroup's LDS: one pass per component
+      launch_one<P, kGradCompKind + 0, false, false, double, double, double>(sp, constrained, qd,
+                                                                             x, out, nullptr, st);
+      launch_one<P, kGradCompKind + 1, false, false, double, double, double>(sp, constrained, qd,
+                                                                             x, out, nullptr, st);
+      launch_one<P, kGradCompKind + 2, false, false, double, double, double>(sp, constrained, qd,
+                                                                             x, out, nullptr, st);
     }
-    return false;
+    return true;
   }
   if (kind == PAFEM_DIVERGENCE) {
     if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp || evec) return false;

@@ -344,10 +344,11 @@ def test_convection_limits():
         S.qdata(P.CONVECTION)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", range(1, 9))
 def test_gradient_apply(p):
     """(grad u, v) into a vector-valued output, lognormal coefficient, rotated jittered
-    elements: every component against the oracle's unconstrained matrices to 1e-12."""
+    elements: every component against the oracle's unconstrained matrices to 1e-12
+    (p <= 4: the three-accumulator kernel; p >= 5: one pass per component)."""
     mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=70 + p, rotate_seed=170 + p)
     E = mesh["hex"].shape[0]
     kappa = synth.lognormal_iid(E, p + 2, 1.0, seed=71 + p)
@@ -375,9 +376,9 @@ def test_gradient_limits():
     op = P.Operator(S, P.GRADIENT, qd, constrained=False)
     with pytest.raises(P.PafemError):
         op.diagonal()
-    S5 = P.Space(P.Mesh.from_dict(synth.hex_lattice(1, 0.0)), 5)
     with pytest.raises(P.PafemError):
-        P.Operator(S5, P.GRADIENT, S5.qdata(P.GRADIENT), constrained=False)
+        P.Operator(S, P.GRADIENT, P.lowered_qdata(qd, P.F32), qdata_dtype=P.F32,
+                   constrained=False)
 
 
 @pytest.mark.parametrize("p", range(1, 9))
@@ -448,17 +449,13 @@ def test_divergence_properties_many_tiles(p):
     uu[:, S.boundary_dofs()] = 0.0
     q = synth.hash_normal(X, seed=125)
     dq_ = div1.apply(_cuda(uu.ravel())).cpu().numpy()
-    if p <= 4:
-        # the gradient operator (orders 1..4) on the same quadrature data
-        grad1 = P.Operator(S, P.GRADIENT, qd1, constrained=False)
-        gq = grad1.apply(_cuda(q)).cpu().numpy().reshape(3, -1)
-        lhs, rhs = float(q @ dq_), -float(np.sum(uu * gq))
-        assert abs(lhs - rhs) <= 1e-12 * float(np.abs(q * dq_).sum())
-    else:
-        # p > 4: the same identity row by row against the oracle is covered by
-        # test_divergence_apply; here the divergence of a field vanishing on the boundary
-        # integrates to zero against q = 1
-        assert abs(float(dq_.sum())) <= 1e-12 * float(np.abs(dq_).sum())
+    # the gradient operator on the same quadrature data
+    grad1 = P.Operator(S, P.GRADIENT, qd1, constrained=False)
+    gq = grad1.apply(_cuda(q)).cpu().numpy().reshape(3, -1)
+    lhs, rhs = float(q @ dq_), -float(np.sum(uu * gq))
+    assert abs(lhs - rhs) <= 1e-12 * float(np.abs(q * dq_).sum())
+    # and the divergence of a field vanishing on the boundary integrates to zero
+    assert abs(float(dq_.sum())) <= 1e-12 * float(np.abs(dq_).sum())
 
 
 def test_divergence_limits():
