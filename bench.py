@@ -472,12 +472,21 @@ def bench_learned(P, torch, n=64, p=3, fields=20, heldout=3, steps=1500, tol=1e-
         op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kappa))
         return op, op.diagonal(), P.learned_features(S, kappa)
 
-    samples = []
     b = S.linear_form(P.SOURCE_SINE)
+    # up to 20 fields every operator stays resident; beyond, the compact store (FP32
+    # pairs, one shared operator re-assembled per drawn field) keeps 200 fields in memory
+    compact = fields > 20
+    samples = L.CompactFields(S) if compact else []
     for f in range(fields):
-        op, diag, feats = field(1000 + f)
-        for r, e in L.jacobi_pairs(op, b, diag, stops=stops):
-            samples.append((op, feats, diag, r, e))
+        if compact:
+            kappa = synth.grf_lognormal(pts, 0.1, 1e3, seed=1000 + f,
+                                        device="cuda").reshape(E, -1).contiguous()
+            samples.add_field(kappa, P.learned_features(S, kappa),
+                              lambda op, diag: L.jacobi_pairs(op, b, diag, stops=stops))
+        else:
+            op, diag, feats = field(1000 + f)
+            for r, e in L.jacobi_pairs(op, b, diag, stops=stops):
+                samples.append((op, feats, diag, r, e))
         log(f"learned: training field {f + 1}/{fields}, {len(samples)} pairs")
     t_pairs = time.perf_counter() - t0
     net = P.Net(p, hidden=64, max_rows=E, max_train_rows=E)

@@ -42,21 +42,66 @@ def jacobi_pairs(op, b, diag, stops=(2, 5, 10, 20, 40, 80), tight=1e-12, max_ite
     return pairs
 
 
+class CompactFields:
+    """Training data of many coefficient fields kept small: per field the coefficient,
+    the element features, the diagonal and its pairs in FP32; one quadrature-data buffer
+    and one operator are shared, and the buffer is re-assembled from the drawn field's
+    coefficient (a few ms) when a sample of another field is drawn.  For field counts
+    whose operators would not all fit in device memory (1.6 GB each at 64^3, p = 3)."""
+
+    def __init__(self, space, kind=P.DIFFUSION):
+        self.space, self.kind = space, kind
+        self.qd = space.qdata(kind)
+        self.op = P.Operator(space, kind, self.qd)
+        self.fields, self.samples, self.current = [], [], None
+
+    def use(self, f):
+        """The shared operator, its quadrature data set to field f."""
+        if self.current != f:
+            P.pafem_qdata_assemble(self.space.handle, self.kind, self.space.p + 2,
+                                   self.fields[f][0], 1.0, self.qd)
+            self.current = f
+        return self.op
+
+    def add_field(self, kappa, feats, make_pairs):
+        """Register a field; make_pairs(op, diag) yields its (r, e) pairs, computed
+        with the shared operator set to this field."""
+        self.fields.append((kappa, feats, None))
+        f = len(self.fields) - 1
+        op = self.use(f)
+        diag = op.diagonal()
+        self.fields[f] = (kappa, feats, diag)
+        for r, e in make_pairs(op, diag):
+            self.samples.append((f, r.float(), e.float()))
+
+    def __len__(self):
+        return len(self.samples)
+
+    def draw(self, i):
+        f, r, e = self.samples[i]
+        kappa, feats, diag = self.fields[f]
+        return self.use(f), feats, diag, r.double(), e.double()
+
+
 def train(net, samples, steps=500, lr=2e-3, lr_decay=0.5, decay_every=200, seed=0, log_every=0,
           log=print):
     """Adam on the loss of randomly drawn samples.
 
-    samples: list of (op, feats, diag, r, e).  Returns the per-step losses (host).
+    samples: list of (op, feats, diag, r, e), or a CompactFields.  Returns the per-step
+    losses (host).
     """
     import torch
     rng = np.random.default_rng(seed)
     works = {}
-    loss_dev = torch.zeros(steps, dtype=torch.float64, device=samples[0][3].device)
+    compact = isinstance(samples, CompactFields)
+    device = samples.qd.device if compact else samples[0][3].device
+    loss_dev = torch.zeros(steps, dtype=torch.float64, device=device)
     cur_lr = lr
     for t in range(steps):
         if decay_every and t and t % decay_every == 0:
             cur_lr *= lr_decay
-        op, feats, diag, r, e = samples[int(rng.integers(len(samples)))]
+        i = int(rng.integers(len(samples)))
+        op, feats, diag, r, e = samples.draw(i) if compact else samples[i]
         w = works.get(id(op))
         if w is None:
             w = works[id(op)] = P._learned_work(op)
