@@ -1,6 +1,9 @@
 // Fused partial-assembly operator action y = G^t B^t D B G x for H1 mass and
 // diffusion on hexahedra ("Operator Decomposition", "High-Order Partial
-// Assembly").
+// Assembly"), and on the same skeleton the other integrators of "GPU Acceleration":
+// diffusion with recomputed geometry, convection, gradient (vector output; from
+// p = 5 one pass per component), divergence (vector input) and the three-component
+// vector forms of mass and diffusion (elasticity has its own kernel, k_elastic.hip).
 //
 // One workgroup holds NE elements (one tile of the tile-interleaved quadrature
 // data); each element gets Q*Q threads.  Every contraction is done one 1D line per
@@ -14,6 +17,7 @@
 //   B    x-lines (dz, dy) -> y-lines (dz, qx) -> z-lines (qy, qx)
 //   D    pointwise on the z-line: 1 value (mass) or a symmetric 3x3 (diffusion) per
 //        point, streamed from HBM with non-temporal loads issued before the gather
+//        (at some orders only the first planes, the rest one z-iteration ahead)
 //   B^t  z-lines (in registers) -> y-lines -> x-lines
 //   G^t  either: sum the element outputs per unique dof of the tile in LDS, then one
 //        hardware FP atomic per unique dof into y (y pre-set by an init kernel); or
