@@ -13,6 +13,7 @@
 
 #include "capi.hpp"
 #include "launch.hpp"
+#include "mg.hpp"
 #include "mlp.hpp"
 #include "solver.hpp"
 
@@ -378,7 +379,8 @@ void learned_loss_grad(Net& net, const Op& op, const float* feats, const double*
   learned_apply(net, op, diag, r, z, w, W, st);
   launch_diff(e, z, t, sp.ndofs, st);
   apply_op(op, t, u, w + W.opwork, st);
-  hip_check(hipMemsetAsync(ticket, 0, 4, st), "loss ticket");
+  // cleared by a kernel, not a memset, so that a caller may capture this call in a graph
+  launch_fill(reinterpret_cast<double*>(ticket), 0.0, 1, st);
   launch_loss(sp, u, r, diag, v, partials, ticket, scal, st);
   apply_op(op, v, g, w + W.opwork, st);
   // dL/dz = scal[1] * g; the basis gradient goes straight into the gradient vector
