@@ -1,4 +1,5 @@
-"""Graph replay of solver iterations against direct launches.
+"""Graph replay of solver iterations against direct launches, and a caller's own
+graph capture of the operator apply.
 
 PCG batches and pairs of V-cycle FCG iterations are captured into HIP graphs once per
 solve and replayed many times, with the host's own synchronisations and copies between
@@ -86,3 +87,50 @@ def test_pmg_fcg_graph_replay_matches_direct_launches():
         assert i1["status"] == ie["status"] == i2["status"] == "OK"
         assert abs(i1["iters"] - ie["iters"]) <= 1 and abs(i2["iters"] - ie["iters"]) <= 1
         assert _close(x1, xe) and _close(x2, xe)
+
+
+@pytest.mark.parametrize("kind", ["diffusion", "mass_evec", "elasticity", "gradient"])
+def test_caller_captures_apply_in_a_graph(kind):
+    """A caller captures pafem_op_apply (its y-init is a kernel, not a memset) in a torch
+    CUDA graph; every replay, with eager work and synchronisations between the replays
+    (a new input written in place), equals the eager apply of the same input."""
+    mesh = synth.hex_lattice(5, 0.1, seed=11, rotate_seed=12)
+    S = P.Space(P.Mesh.from_dict(mesh), 3)
+    X = S.dof_coords()
+    if kind == "elasticity":
+        E = S.nelem
+        lm = torch.as_tensor(np.stack([np.full((E, 125), 1.5), np.full((E, 125), 0.7)], -1).ravel(),
+                             device="cuda")
+        op = P.Operator(S, P.ELASTICITY, S.qdata(P.ELASTICITY, coeff=lm))
+        ncomp_in = ncomp_out = 3
+    elif kind == "gradient":
+        op = P.Operator(S, P.GRADIENT, S.qdata(P.GRADIENT), constrained=False)
+        ncomp_in, ncomp_out = 1, 3
+    else:
+        k = P.DIFFUSION if kind == "diffusion" else P.MASS
+        op = P.Operator(S, k, S.qdata(k), scatter="evec" if "evec" in kind else "atomic")
+        ncomp_in = ncomp_out = 1
+
+    def field(seed):
+        v = np.concatenate([synth.hash_normal(X, seed=seed + c) for c in range(ncomp_in)])
+        return torch.as_tensor(v, device="cuda")
+
+    x = field(1)
+    y = torch.empty(ncomp_out * S.ndofs, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        op.apply(x, y)                      # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        op.apply(x, y)
+    for k in range(4):
+        x.copy_(field(10 * (k + 2)))        # eager work between the replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        want = op.apply(x)
+        torch.cuda.synchronize()
+        assert _close(y, want, tol=1e-14), f"replay {k}"
