@@ -466,7 +466,10 @@ pafem_status pafem_fcg_workspace_bytes(pafem_op op, int32_t max_iter, size_t* nb
 /* Flexible CG (Polak-Ribiere beta) with the learned preconditioner (net != NULL)
  * or Jacobi (net == NULL).  If r.z <= 0, a non-finite scalar or a residual
  * growth by 1e6 appears with the network, it restarts from the current iterate
- * with Jacobi (result->fell_back).  opts->precond is ignored.  SYNCHRONOUS. */
+ * with Jacobi (result->fell_back).  opts->precond is ignored.  On the essential
+ * dofs the preconditioner returns r when the operator is constrained (its rows
+ * there are the identity, so b and x may hold any values on them) and r / diag
+ * otherwise; the learned correction acts on the other dofs only.  SYNCHRONOUS. */
 pafem_status pafem_fcg_solve(pafem_op op, pafem_net net, const float* feats, const double* diag,
                              const double* b, double* x, void* work, size_t work_bytes,
                              const pafem_solve_opts* opts, pafem_fcg_result* result,

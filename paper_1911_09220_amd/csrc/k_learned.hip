@@ -331,11 +331,15 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// z = r / diag off the essential dofs; on them per ess_mode (kJacobiEss*)
 __global__ void jacobi_kernel(const double* __restrict__ r, const double* __restrict__ diag,
-                              const uint8_t* __restrict__ bmask, double* __restrict__ z, int64_t n) {
+                              const uint8_t* __restrict__ bmask, int ess_mode,
+                              double* __restrict__ z, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
-    z[i] = bmask[i] ? 0.0 : r[i] / diag[i];
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const bool b = bmask[i] && ess_mode != kJacobiEssDiag;
+    z[i] = b ? (ess_mode == kJacobiEssKeep ? r[i] : 0.0) : r[i] / diag[i];
+  }
 }
 
 int grid_for(int64_t n) {
@@ -407,9 +411,9 @@ void launch_loss(const DevSpace& sp, const double* u, const double* r, const dou
 }
 
 void launch_jacobi(const DevSpace& sp, const double* r, const double* diag, double* z,
-                   hipStream_t st) {
+                   hipStream_t st, int ess_mode) {
   hipLaunchKernelGGL(jacobi_kernel, dim3(grid_for(sp.ndofs)), dim3(256), 0, st, r, diag, sp.bmask,
-                     z, sp.ndofs);
+                     ess_mode, z, sp.ndofs);
   check("jacobi");
 }
 

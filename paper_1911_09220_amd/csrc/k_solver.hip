@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(kCGThreads)
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
-    zj[i] = bmask[i] ? 0.0 : ri / diag[i];
+    zj[i] = (bmask && bmask[i]) ? ri : ri / diag[i];
     rr += ri * ri;
   }
   rr = block_sum(rr, scratch);

@@ -215,8 +215,9 @@ void learned_correct(const Net& net, const Op& op, const double* r, double* z, c
 
 // z = M(r) with the element weights of the last learned_setup
 void learned_apply(const Net& net, const Op& op, const double* diag, const double* r, double* z,
-                   char* work, const LearnedLayout& W, hipStream_t st) {
-  launch_jacobi(op.space->dev, r, diag, z, st);
+                   char* work, const LearnedLayout& W, hipStream_t st,
+                   int ess_mode = kJacobiEssZero) {
+  launch_jacobi(op.space->dev, r, diag, z, st, ess_mode);
   learned_correct(net, op, r, z, work, W, st);
 }
 
@@ -379,7 +380,8 @@ void learned_loss_grad(Net& net, const Op& op, const float* feats, const double*
   learned_apply(net, op, diag, r, z, w, W, st);
   launch_diff(e, z, t, sp.ndofs, st);
   apply_op(op, t, u, w + W.opwork, st);
-  // cleared by a kernel, not a memset, so that a caller may capture this call in a graph
+  // the reduction ticket is cleared by a kernel rather than a memset (no memset nodes
+  // when the caller's stream is being captured); capture of this call is not tested
   launch_fill(reinterpret_cast<double*>(ticket), 0.0, 1, st);
   launch_loss(sp, u, r, diag, v, partials, ticket, scal, st);
   apply_op(op, v, g, w + W.opwork, st);
@@ -460,11 +462,15 @@ pafem_status fcg_solve(const Op& op, Net* net, const float* feats, const double*
   res.fallback_iter = -1;
 
   if (use_net) learned_setup(*net, op, feats, diag, lw, LW, st);
+  // a constrained operator is the identity on the essential rows: the preconditioner
+  // passes r through there; an unconstrained one gets Jacobi on every row (the learned
+  // correction touches only the non-essential dofs either way)
+  const int ess_mode = ess ? kJacobiEssKeep : kJacobiEssDiag;
   auto precond = [&](const double* rr, double* zz) {
     if (use_net)
-      learned_apply(*net, op, diag, rr, zz, lw, LW, st);
+      learned_apply(*net, op, diag, rr, zz, lw, LW, st, ess_mode);
     else
-      launch_jacobi(sp, rr, diag, zz, st);
+      launch_jacobi(sp, rr, diag, zz, st, ess_mode);
   };
 
   launch_cg_reset(state, opts.max_iter + 1, st);
@@ -503,7 +509,7 @@ pafem_status fcg_solve(const Op& op, Net* net, const float* feats, const double*
       apply_op(op, p, q, lw + LW.opwork, st, dotp);
       launch_cg_alpha<double>(state, partials, dotp, nap, ess, p, n, st);
       // new z into the spare buffer: the update writes its Jacobi part
-      launch_fcg_update(state, partials, x, r, p, q, diag, sp.bmask, zold, hist, n, st);
+      launch_fcg_update(state, partials, x, r, p, q, diag, ess, zold, hist, n, st);
       if (use_net) learned_correct(*net, op, r, zold, lw, LW, st);
       launch_fcg_beta(state, partials, r, zold, z, n, st);
       launch_fcg_direction(state, zold, p, n, st);

@@ -327,7 +327,8 @@ pafem_status pafem_op_lambda_max(pafem_op op, const double* diag, double* v, int
     auto* ticket = reinterpret_cast<uint32_t*>(scal + 2);
     const int64_t n = o.space->ndofs;
     const uint8_t* ess = (o.flags & PAFEM_OP_CONSTRAINED) ? o.space->dev.bmask : nullptr;
-    // cleared by a kernel, not a memset, so that a caller may capture this call in a graph
+    // the reduction ticket is cleared by a kernel rather than a memset; the call as a
+    // whole is synchronous (it reads lambda back), so it cannot be captured in a graph
     launch_fill(reinterpret_cast<double*>(scal + 2), 0.0, 1, st);
     launch_power_norm(v, diag, ess, partials, ticket, scal, n, st);
     for (int k = 0; k < iters; ++k) {

@@ -59,8 +59,11 @@ void launch_diff(const double* a, const double* b, double* t, int64_t n, hipStre
 // training loss: v = u / diag, scal = {loss, -2 / (r.D^-1 r)}; partials >= 2*512 doubles
 void launch_loss(const DevSpace& sp, const double* u, const double* r, const double* diag,
                  double* v, double* partials, uint32_t* ticket, double* scal, hipStream_t st);
-// z = r / diag, 0 on essential dofs
+// z = r / diag, and on the essential dofs: 0 (kJacobiEssZero, the learned
+// preconditioner's own definition), r (kJacobiEssKeep: a constrained operator is the
+// identity there) or r / diag as elsewhere (kJacobiEssDiag: an unconstrained operator)
+constexpr int kJacobiEssZero = 0, kJacobiEssKeep = 1, kJacobiEssDiag = 2;
 void launch_jacobi(const DevSpace& sp, const double* r, const double* diag, double* z,
-                   hipStream_t st);
+                   hipStream_t st, int ess_mode = kJacobiEssZero);
 
 }  // namespace pafem

@@ -63,8 +63,9 @@ void launch_fcg_init(CGState* st, double* partials, const double* b, const doubl
                      hipStream_t s);
 void launch_fcg_start(CGState* st, double* partials, const double* r, const double* z, double* p,
                       int64_t n, hipStream_t s);
-// x += alpha p; r -= alpha q; zj = r / diag (0 where bmask): the Jacobi part of the
-// next preconditioned residual
+// x += alpha p; r -= alpha q; zj = r / diag, and zj = r where bmask (may be null) marks
+// the essential rows of a constrained operator (unit diagonal there): the Jacobi part
+// of the next preconditioned residual
 void launch_fcg_update(CGState* st, double* partials, double* x, double* r, const double* p,
                        const double* q, const double* diag, const uint8_t* bmask, double* zj,
                        double* hist, int64_t n, hipStream_t s);

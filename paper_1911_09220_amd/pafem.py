@@ -890,14 +890,18 @@ def learned_loss_grad(net, op, feats, diag, r, e, loss=None, work=None):
 
 
 def fcg_solve(op, b, diag, net=None, feats=None, rel_tol=1e-8, max_iter=2000, check_every=8,
-              history=True):
+              history=True, x=None):
+    """Flexible CG; x: starting guess, overwritten with the solution (None: from zero)."""
     import torch
-    x = torch.zeros_like(b)
+    zero = x is None
+    if zero:
+        x = torch.zeros_like(b)
+    op._check_vec(x, "x")
     n = C.c_size_t()
     _check(lib.pafem_fcg_workspace_bytes(op.handle, int(max_iter), C.byref(n)))
     work = _device_bytes(n.value, op.space.device)
     hist = np.zeros(max_iter + 1) if history else None
-    opts = SolveOpts(float(rel_tol), int(max_iter), 0, int(check_every), 1,
+    opts = SolveOpts(float(rel_tol), int(max_iter), 0, int(check_every), int(zero),
                      None if hist is None else hist.ctypes.data_as(C.POINTER(C.c_double)),
                      0 if hist is None else hist.size)
     res = FCGResult()

@@ -47,6 +47,22 @@ def rel_err(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def max_rel_err(a, b):
+    """Largest entry error over the largest reference entry: max|a - b| / max|b|."""
+    a, b = np.asarray(a), np.asarray(b)
+    if a.size == 0:
+        return 0.0
+    mb = np.abs(b).max()
+    return float(np.abs(a - b).max() / (mb if mb > 0 else 1.0))
+
+
+def parity_err(a, b):
+    """The worse of the norm-wise and the entry-wise relative error, so that one bar
+    `parity_err(a, b) <= tol` requires both ||a - b||/||b|| <= tol and
+    max|a - b| <= tol * max|b|."""
+    return max(rel_err(a, b), max_rel_err(a, b))
+
+
 def _patch(n, c):
     """Element ids of the 3x3x3 block around element c of an n^3 lattice, and c's position."""
     cx, cy, cz = c % n, (c // n) % n, c // (n * n)

@@ -5,11 +5,11 @@ with its gain over Jacobi on a held-out coefficient field.
 
 Bars (BF16 weights and activations, FP32 accumulation): forward outputs and loss
 within 3e-2 relative of the FP64 oracle on the same bf16-rounded weights and
-inputs; gradients with cosine >= 0.999 and relative error <= 5e-2.  The gradient
+inputs; gradients with cosine >= 0.999 and relative error <= 3e-2.  The gradient
 bar follows from the arithmetic: the first-layer gradient passes through three
 bf16 roundings (the output gradient and the two back-propagated activations,
-2^-8 relative each) and through ReLU masks whose near-zero pre-activations can
-flip sign between BF16/FP32 and FP64 evaluation.
+2^-8 relative each, about 1.2e-2 together) and through ReLU masks whose near-zero
+pre-activations can flip sign between BF16/FP32 and FP64 evaluation.
 """
 import numpy as np
 import pytest
@@ -80,7 +80,7 @@ def test_network_forward_backward_vs_oracle():
     for k in pr:
         c, e = _cos(g[k], gr[k]), rel_err(g[k], gr[k])
         print(f"{k}: cosine {c:.5f} rel {e:.2e}")
-        assert c >= 0.999 and e <= 5e-2, k
+        assert c >= 0.999 and e <= 3e-2, k
 
 
 def _small_problem(p=2, n=(3, 3, 2), seed=5):
@@ -150,7 +150,7 @@ def test_preconditioner_and_loss_gradients_vs_oracle(p):
     for k in net.NAMES:
         c, er = _cos(g[k], G_or[k]), rel_err(g[k], G_or[k])
         print(f"{k}: cosine {c:.5f} rel {er:.2e}")
-        assert c >= 0.999 and er <= 5e-2, k
+        assert c >= 0.999 and er <= 3e-2, k
 
 
 def test_fcg_with_jacobi_matches_pcg():
@@ -217,3 +217,81 @@ def test_training_gains_over_jacobi():
     perm = match_by_coords(S.dof_coords(), ref.coords)
     xd = spla.spsolve(ref.Kc.tocsc(), ref.load(synth.sine_source))
     assert rel_err(x.cpu().numpy(), xd[perm]) < 1e-6
+
+
+def test_fcg_with_essential_values_and_a_start_guess():
+    """Right-hand side and starting guess nonzero on the essential dofs: the constrained
+    operator is the identity there, so the solution takes b's values on them and the
+    rest solves the eliminated system.  Flexible CG with Jacobi and with a (random,
+    untrained) network both reach Jacobi-PCG's solution."""
+    mesh, kappa, S, op, diag, feats, ref = _small_problem(2, (5, 5, 4))
+    X = S.dof_coords()
+    bd = torch.as_tensor(S.boundary_dofs(), device="cuda").long()
+    b = S.linear_form(P.SOURCE_SINE)
+    b[bd] = torch.as_tensor(synth.hash_normal(X, seed=21), device="cuda")[bd]
+    x0 = torch.as_tensor(synth.hash_normal(X, seed=22), device="cuda")
+    xp, ip = op.pcg(b, x=x0.clone(), diag=diag, rel_tol=1e-10)
+    assert ip["status"] == "OK"
+    # x_B reaches b_B as the residual falls (rows of the identity), to the tolerance
+    gap = float((xp[bd] - b[bd]).abs().max()) / float(b[bd].abs().max())
+    assert gap < 1e-9, gap
+    net = P.Net(2, hidden=32, max_rows=S.nelem, max_train_rows=0)
+    net.set_params(_params(net, 23))
+    for nt in (None, net):
+        x, info = P.fcg_solve(op, b, diag, net=nt, feats=None if nt is None else feats,
+                              rel_tol=1e-10, x=x0.clone())
+        err = float((x - xp).norm() / xp.norm())
+        print(f"fcg net={nt is not None}: {info['status']} {info['iters']} its "
+              f"(pcg {ip['iters']}), rel diff {err:.2e}")
+        assert info["converged"] and info["true_rel_res"] < 1e-9 and not info["fell_back"]
+        assert err < 1e-8
+
+
+def test_fcg_on_unconstrained_mass():
+    """No essential rows: Jacobi acts on every dof, and flexible CG matches PCG."""
+    mesh = synth.hex_lattice((4, 3, 3), 0.1, seed=24)
+    S = P.Space(P.Mesh.from_dict(mesh), 3)
+    op = P.Operator(S, P.MASS, S.qdata(P.MASS), constrained=False)
+    diag = op.diagonal()
+    b = torch.as_tensor(synth.hash_normal(S.dof_coords(), seed=25), device="cuda")
+    xp, ip = op.pcg(b, diag=diag, rel_tol=1e-11)
+    x, info = P.fcg_solve(op, b, diag, rel_tol=1e-11)
+    err = float((x - xp).norm() / xp.norm())
+    print(f"mass: pcg {ip['iters']} its, fcg {info['iters']} its, rel diff {err:.2e}")
+    assert ip["status"] == "OK" and info["converged"] and abs(ip["iters"] - info["iters"]) <= 1
+    assert err < 1e-9
+    r = b - op.apply(x)
+    assert float(r.norm() / b.norm()) < 1e-10
+
+
+def test_compact_field_store_trains_like_the_list():
+    """The compact training store (one shared operator re-assembled per drawn field,
+    pairs kept in FP32) gives the same loss sequence as the list of per-field operators
+    on the same FP32-rounded pairs, drawn with the same seed."""
+    p, n = 2, 4
+    mesh = synth.hex_lattice(n, 0.05, seed=31)
+    E = mesh["hex"].shape[0]
+    S = P.Space(P.Mesh.from_dict(mesh), p)
+    pts = synth.lattice_quadrature_points(n, p + 2)
+    b = S.linear_form(P.SOURCE_SINE)
+    store = L.CompactFields(S)
+    listed = []
+    for f in range(3):
+        kappa = synth.grf_lognormal(pts, 0.1, 1e3, seed=1100 + f, device="cuda").reshape(E, -1)
+        kappa = kappa.contiguous()
+        feats = P.learned_features(S, kappa)
+        op = P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=kappa))
+        diag = op.diagonal()
+        pairs = L.jacobi_pairs(op, b, diag, stops=(2, 5, 10))
+        assert len(pairs) == 3
+        listed += [(op, feats, diag, r.float().double(), e.float().double()) for r, e in pairs]
+        store.add_field(kappa, feats, lambda o, d: L.jacobi_pairs(o, b, d, stops=(2, 5, 10)))
+    assert len(store) == len(listed) == 9
+    losses = []
+    for samples in (listed, store):
+        net = P.Net(p, hidden=32, max_rows=E, max_train_rows=E)
+        net.set_params(L.initial_params(net, seed=32))
+        losses.append(L.train(net, samples, steps=40, lr=2e-3, seed=33))
+    print("list", losses[0][:5], "compact", losses[1][:5])
+    assert np.all(np.isfinite(losses[0]))
+    assert np.allclose(losses[0], losses[1], rtol=1e-6, atol=0.0)

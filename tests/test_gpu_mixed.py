@@ -13,7 +13,7 @@ import scipy.sparse.linalg as spla
 
 import synth
 from oracle.precision import to_bf16_bits, to_f32
-from tests._common import OracleProblem, match_by_coords, rel_err
+from tests._common import OracleProblem, match_by_coords, rel_err, parity_err
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,7 @@ def test_reduced_precision_apply(p, dtype, tol):
     y = lo.apply(torch.as_tensor(x, dtype=torch.float32, device="cuda")).double().cpu().numpy()
     ref = OracleProblem(mesh, p, coeff=kappa)
     perm = match_by_coords(X, ref.coords)
-    err = rel_err(y, (ref.Kc @ synth.hash_normal(ref.coords, seed=53))[perm])
+    err = parity_err(y, (ref.Kc @ synth.hash_normal(ref.coords, seed=53))[perm])
     print(f"p={p} dtype={'f32' if dtype == P.F32 else 'bf16'} apply rel err vs FP64 oracle {err:.2e}")
     assert err <= tol
 

@@ -3,8 +3,9 @@
 Inputs are seeded synthetic meshes; input vectors are pseudo-random values keyed
 by dof position (``synth.hash_normal``), so each side evaluates them on its own
 dof coordinates and no input crosses from the GPU path to the oracle.  Results
-are compared after matching dofs by position.  Bar: FP64 relative error
-<= 1e-12 (norm-wise) for applies, diagonals and load vectors.
+are compared after matching dofs by position.  Bar for applies, diagonals and
+load vectors in FP64: ||got - want|| <= 1e-12 ||want|| and, entry by entry,
+max|got - want| <= 1e-12 max|want|.
 """
 import numpy as np
 import pytest
@@ -12,7 +13,7 @@ import pytest
 import oracle
 from oracle import forms
 import synth
-from tests._common import OracleProblem, match_by_coords, rel_err
+from tests._common import OracleProblem, match_by_coords, rel_err, parity_err
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +51,7 @@ def test_diffusion_apply(p, scatter):
     ref = OracleProblem(mesh, p, coeff=kappa)
     y_ref = ref.Kc @ synth.hash_normal(ref.coords, seed=p)
     perm = match_by_coords(X, ref.coords)
-    err = rel_err(y, y_ref[perm])
+    err = parity_err(y, y_ref[perm])
     print(f"diffusion p={p} {scatter}: rel err {err:.2e}")
     assert err <= TOL
 
@@ -66,7 +67,7 @@ def test_mass_apply(p):
         ref = OracleProblem(mesh, p, rho=rho)
         y_ref = ref.Mc @ synth.hash_normal(ref.coords, seed=3)
         perm = match_by_coords(X, ref.coords)
-        assert rel_err(y, y_ref[perm]) <= TOL
+        assert parity_err(y, y_ref[perm]) <= TOL
 
 
 @pytest.mark.parametrize("kind", [P.DIFFUSION, P.MASS])
@@ -99,10 +100,10 @@ def test_quadratic_geometry(p):
     y = op.apply(_cuda(synth.hash_normal(X, seed=11))).cpu().numpy()
     ref = OracleProblem(mesh, p)
     perm = match_by_coords(X, ref.coords)
-    assert rel_err(y, (ref.Kc @ synth.hash_normal(ref.coords, seed=11))[perm]) <= TOL
+    assert parity_err(y, (ref.Kc @ synth.hash_normal(ref.coords, seed=11))[perm]) <= TOL
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("p", range(1, 9))
 def test_diagonal(p):
     mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=30 + p, rotate_seed=31)
     kappa = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 1.0, seed=9)
@@ -112,22 +113,22 @@ def test_diagonal(p):
     for kind, A in ((P.DIFFUSION, ref.Kc), (P.MASS, ref.Mc)):
         op = P.Operator(S, kind, S.qdata(kind, coeff=kc))
         d = op.diagonal().cpu().numpy()
-        assert rel_err(d, A.diagonal()[perm]) <= TOL
+        assert parity_err(d, A.diagonal()[perm]) <= TOL
 
 
-@pytest.mark.parametrize("p", [1, 3, 6])
+@pytest.mark.parametrize("p", range(1, 9))
 def test_linear_form(p):
     mesh = synth.hex_lattice(SHAPES[p], 0.1, seed=40 + p)
     S, X, _ = _setup(mesh, p)
     ref = OracleProblem(mesh, p)
     perm = match_by_coords(X, ref.coords)
     b = S.linear_form(P.SOURCE_SINE).cpu().numpy()
-    assert rel_err(b, ref.load(synth.sine_source)[perm]) <= TOL
+    assert parity_err(b, ref.load(synth.sine_source)[perm]) <= TOL
     b1 = S.linear_form(P.SOURCE_CONST, scale=2.5).cpu().numpy()
-    assert rel_err(b1, ref.load(lambda x: np.full(x.shape[:-1], 2.5))[perm]) <= TOL
+    assert parity_err(b1, ref.load(lambda x: np.full(x.shape[:-1], 2.5))[perm]) <= TOL
     fq = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 0.5, seed=12)
     b2 = S.linear_form(P.SOURCE_ARRAY, f_qp=_cuda(fq)).cpu().numpy()
-    assert rel_err(b2, ref.load(fq)[perm]) <= TOL
+    assert parity_err(b2, ref.load(fq)[perm]) <= TOL
 
 
 def test_unconstrained_invariants():
@@ -173,7 +174,7 @@ def test_small_poisson_solve():
     ref = OracleProblem(mesh, 2)
     perm = match_by_coords(X, ref.coords)
     bref = ref.load(synth.sine_source)
-    assert rel_err(b.cpu().numpy(), bref[perm]) <= TOL
+    assert parity_err(b.cpu().numpy(), bref[perm]) <= TOL
     import scipy.sparse.linalg as spla
     xd = spla.spsolve(ref.Kc.tocsc(), bref)
     err = rel_err(x.cpu().numpy(), xd[perm])
@@ -257,7 +258,7 @@ def test_diffusion_with_recomputed_geometry(p):
     perm = match_by_coords(X, ref.coords)
     for scatter in ("atomic", "evec"):
         y = P.Operator(S, P.DIFFUSION_GEOM, qg, scatter=scatter).apply(x)
-        err = rel_err(y.cpu().numpy(), y_ref[perm])
+        err = parity_err(y.cpu().numpy(), y_ref[perm])
         print(f"recomputed geometry p={p} {scatter}: rel err {err:.2e}")
         assert err <= TOL
         assert float((y - stored).norm() / stored.norm()) <= TOL
@@ -319,7 +320,7 @@ def test_convection_apply(p):
     x = _cuda(synth.hash_normal(X, seed=62 + p))
     for scatter in ("atomic", "evec"):
         y = P.Operator(S, P.CONVECTION, qd, scatter=scatter).apply(x).cpu().numpy()
-        err = rel_err(y, want)
+        err = parity_err(y, want)
         print(f"convection p={p} {scatter}: rel err {err:.2e}")
         assert err <= TOL
     free = P.Operator(S, P.CONVECTION, qd, constrained=False)
@@ -361,7 +362,7 @@ def test_gradient_apply(p):
     perm = match_by_coords(X, ref.dof_coordinates())
     for c in range(3):
         want = (oracle.assemble(ref, Ge[:, c]) @ xo)[perm]
-        err = rel_err(y[c], want)
+        err = parity_err(y[c], want)
         print(f"gradient p={p} component {c}: rel err {err:.2e}")
         assert err <= TOL
 
@@ -400,8 +401,8 @@ def test_vector_operator_applies_per_component(p):
         sc = P.Operator(S, kind, qd)
         for c in range(3):
             ys = sc.apply(_cuda(xs[c])).cpu().numpy()
-            assert rel_err(vec[c], ys) <= 1e-14
-            assert rel_err(vec[c], (A @ xo[c])[perm]) <= TOL
+            assert parity_err(vec[c], ys) <= 1e-14
+            assert parity_err(vec[c], (A @ xo[c])[perm]) <= TOL
 
 
 @pytest.mark.parametrize("p", range(1, 9))
@@ -420,7 +421,7 @@ def test_divergence_apply(p):
     Xo = ref.dof_coordinates()
     want = sum(oracle.assemble(ref, Ve[:, c]) @ synth.hash_normal(Xo, seed=102 + c)
                for c in range(3))
-    err = rel_err(y, want[match_by_coords(X, Xo)])
+    err = parity_err(y, want[match_by_coords(X, Xo)])
     print(f"divergence p={p}: rel err {err:.2e}")
     assert err <= TOL
 
@@ -442,7 +443,7 @@ def test_divergence_properties_many_tiles(p):
     u = X @ A.T + np.array([0.2, -0.7, 1.3])
     y = div.apply(_cuda(np.ascontiguousarray(u.T).ravel())).cpu().numpy()
     m1 = mass.apply(torch.ones(S.ndofs, dtype=torch.float64, device="cuda")).cpu().numpy()
-    assert rel_err(y, np.trace(A) * m1) <= 1e-12
+    assert parity_err(y, np.trace(A) * m1) <= 1e-12
     qd1 = S.qdata(P.DIVERGENCE)
     div1 = P.Operator(S, P.DIVERGENCE, qd1, constrained=False)
     uu = np.stack([synth.hash_normal(X, seed=120 + c) for c in range(3)])
@@ -506,7 +507,7 @@ def test_elasticity_apply(p):
         y = op.apply(x3).cpu().numpy().reshape(3, -1)
         A = oracle.constrain(K, np.zeros(V.ndofs), V.boundary)[0] if constrained else K
         want = (A @ xo).reshape(3, -1)[:, perm]
-        err = rel_err(y.ravel(), want.ravel())
+        err = parity_err(y.ravel(), want.ravel())
         print(f"elasticity p={p} constrained={constrained}: rel err {err:.2e}")
         assert err <= TOL
 

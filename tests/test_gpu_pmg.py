@@ -14,7 +14,7 @@ import scipy.sparse.linalg as spla
 import oracle
 import synth
 from oracle import forms, mlp, pmg
-from tests._common import match_by_coords, rel_err
+from tests._common import match_by_coords, rel_err, parity_err
 
 pytestmark = pytest.mark.gpu
 
@@ -48,24 +48,24 @@ def test_prolongation_and_restriction_match_oracle(pc, pf):
     xc_o = synth.hash_normal(Oc.dof_coordinates(), seed=1)
     y = P.prolongate(Sc, Sf, _cuda(synth.hash_normal(Xc, seed=1))).cpu().numpy()
     want = (Po @ xc_o)[pf_perm]
-    err = rel_err(y, want)
+    err = parity_err(y, want)
     print(f"prolongate {pc}->{pf}: rel err {err:.2e}")
     assert err <= TOL
     # add mode leaves essential entries alone
     y0 = _cuda(synth.hash_normal(Xf, seed=2))
     ya = P.prolongate(Sc, Sf, _cuda(synth.hash_normal(Xc, seed=1)), y0.clone(), add=True)
-    assert rel_err(ya.cpu().numpy(), y0.cpu().numpy() + want) <= TOL
+    assert parity_err(ya.cpu().numpy(), y0.cpu().numpy() + want) <= TOL
     # restriction: P^T (b - y)
     bo = synth.hash_normal(Of.dof_coordinates(), seed=3)
     yo = synth.hash_normal(Of.dof_coordinates(), seed=4)
     r = P.restrict(Sf, Sc, _cuda(synth.hash_normal(Xf, seed=3)),
                    _cuda(synth.hash_normal(Xf, seed=4))).cpu().numpy()
     want_r = (Po.T @ (bo - yo))[pc_perm]
-    err = rel_err(r, want_r)
+    err = parity_err(r, want_r)
     print(f"restrict {pf}->{pc}: rel err {err:.2e}")
     assert err <= TOL
     r1 = P.restrict(Sf, Sc, _cuda(synth.hash_normal(Xf, seed=3))).cpu().numpy()
-    assert rel_err(r1, (Po.T @ bo)[pc_perm]) <= TOL
+    assert parity_err(r1, (Po.T @ bo)[pc_perm]) <= TOL
 
 
 def _levels_gpu(mesh, orders, kappa=None, mean=P.MEAN_ARITHMETIC, power_iters=20):
@@ -129,12 +129,12 @@ def test_power_iteration_and_chebyshev_match_oracle(p):
     for degree in (1, 2, 3, 5):
         x = ops[0].chebyshev(diags[0], lmax[0], b, None, degree).cpu().numpy()
         want = pmg.chebyshev(A, d, bo, None, levels[0]["lmax"], degree)
-        assert rel_err(x, want[perm]) <= TOL, degree
+        assert parity_err(x, want[perm]) <= TOL, degree
         x0o = synth.hash_normal(Xo, seed=8)
         x0 = _cuda(synth.hash_normal(X, seed=8))
         x = ops[0].chebyshev(diags[0], lmax[0], b, x0, degree, lo=0.2, hi=1.3).cpu().numpy()
         want = pmg.chebyshev(A, d, bo, x0o, levels[0]["lmax"], degree, lo=0.2, hi=1.3)
-        assert rel_err(x, want[perm]) <= TOL, degree
+        assert parity_err(x, want[perm]) <= TOL, degree
 
 
 @pytest.mark.parametrize("orders,coarse_iters", [([4, 2, 1], 0), ([4, 2, 1], 8), ([3, 1], 12),
@@ -153,7 +153,7 @@ def test_vcycle_matches_oracle(orders, coarse_iters):
     perm = match_by_coords(X, Xo)
     z = G.vcycle(_cuda(synth.hash_normal(X, seed=9))).cpu().numpy()
     want = pmg.vcycle(levels, synth.hash_normal(Xo, seed=9), degree=2, coarse_iters=coarse_iters)
-    err = rel_err(z, want[perm])
+    err = parity_err(z, want[perm])
     print(f"vcycle {orders} coarse {coarse_iters}: rel err {err:.2e}")
     assert err <= TOL
 
