@@ -24,7 +24,8 @@
  *  - "device" pointers are HIP device memory owned by the caller (typically
  *    torch tensors); the library never frees caller memory and never
  *    allocates device memory itself.  Scratch memory comes from caller
- *    workspaces whose size is queried first.
+ *    workspaces whose size is queried first (pafem_op_apply_noalloc instead
+ *    uses one fixed device array of the library, loaded with its code).
  *  - stream is a hipStream_t (NULL = default stream).  Calls are asynchronous
  *    on that stream unless marked SYNCHRONOUS.  An asynchronous HIP failure is
  *    reported as PAFEM_EHIP by a later synchronous call.
@@ -252,6 +253,20 @@ pafem_status pafem_op_workspace_bytes(pafem_op op, size_t* nbytes);
  * the order, q1d or dtype). */
 pafem_status pafem_op_apply(pafem_op op, const double* x, double* y, void* work,
                             size_t work_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops and harnesses that forbid hipMalloc): pafem_op_apply without a
+ * workspace.  The element vectors of the deterministic scatter
+ * (PAFEM_OP_SCATTER_EVEC) go to a library-held device buffer of
+ * PAFEM_NOALLOC_SCRATCH_BYTES on each GPU, set up on the first call on that GPU
+ * and held until the process ends; operators with the atomic scatter need none.
+ * Same vectors, semantics and results as pafem_op_apply (bitwise, for the
+ * deterministic scatter).  Calls whose executions overlap on one GPU share that
+ * GPU's buffer and race: serialize them (one stream, or events).  Allocates
+ * nothing.  Asynchronous.  Errors: as pafem_op_apply, and ESHAPE when the element
+ * vectors (8 bytes per element dof: ne * (p+1)^dim * 8) exceed the buffer. */
+#define PAFEM_NOALLOC_SCRATCH_BYTES (64u << 20)
+pafem_status pafem_op_apply_noalloc(pafem_op op, const double* x, double* y, void* stream);
 
 /* diag[ndofs] = diagonal of the operator (1 on essential dofs if constrained),
  * by sum factorization with products of the 1D tables.  Asynchronous.

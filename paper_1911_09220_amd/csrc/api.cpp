@@ -115,7 +115,7 @@ extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 270; }
+int32_t pafem_version(void) { return 271; }
 
 int32_t pafem_set_graph_mode(int32_t mode) {
   return graph_mode_flag().exchange(mode != 0 ? 1 : 0);

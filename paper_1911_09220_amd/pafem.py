@@ -67,7 +67,7 @@ class FCGResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 270  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 271  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -98,6 +98,7 @@ def _load():
         "pafem_op_destroy": (None, [P]),
         "pafem_op_workspace_bytes": (I32, [P, C.POINTER(SZ)]),
         "pafem_op_apply": (I32, [P, P, P, P, SZ, P]),
+        "pafem_op_apply_noalloc": (I32, [P, P, P, P]),
         "pafem_op_diagonal": (I32, [P, P, P, SZ, P]),
         "pafem_linear_form": (I32, [P, I32, I32, P, D, P, P, SZ, P]),
         "pafem_pcg_workspace_bytes": (I32, [P, I32, C.POINTER(SZ)]),
@@ -268,6 +269,10 @@ def pafem_op_workspace_bytes(op):
 def pafem_op_apply(op, x, y, work):
     _check(lib.pafem_op_apply(op, _ptr(x), _ptr(y), _ptr(work),
                               0 if work is None else work.numel(), _stream()))
+
+
+def pafem_op_apply_noalloc(op, x, y):
+    _check(lib.pafem_op_apply_noalloc(op, _ptr(x), _ptr(y), _stream()))
 
 
 def pafem_op_diagonal(op, diag, work):
@@ -579,6 +584,16 @@ class Operator:
               or y.dtype != x.dtype):
             raise ValueError(f"y must be a contiguous device vector of {3 * self.space.ndofs}")
         pafem_op_apply(self.handle, x, y, self.work)
+        return y
+
+    def apply_noalloc(self, x, y):
+        """y = A x through pafem_op_apply_noalloc: no workspace and no allocation (the
+        caller passes y).  Scalar operators only."""
+        if self.vector or self.kind in (GRADIENT, DIVERGENCE, ELASTICITY):
+            raise ValueError("apply_noalloc: scalar operators only")
+        self._check_vec(x, "x")
+        self._check_vec(y, "y")
+        pafem_op_apply_noalloc(self.handle, x, y)
         return y
 
     def diagonal(self):
