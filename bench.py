@@ -179,48 +179,183 @@ def time_applies(torch, probs, kind, steps, warmup):
     return per, wall
 
 
-def cpu_baseline(orders, budget_s=20.0):
-    """The oracle's apply (assembled CSR matvec) on reduced meshes of the same recipe."""
+def copy_bandwidth(torch, nbytes=4 << 30, reps=10):
+    """Device-to-device copy of nbytes (one hipMemcpyAsync per rep through torch's copy_),
+    timed with HIP events: the achievable streaming rate of this GPU beside the nominal
+    8 TB/s.  Bandwidth counts the bytes read plus the bytes written."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_each_way": nbytes, "ms": round(t * 1e3, 4),
+            "GBps_read_plus_write": round(2 * nbytes / t / 1e9, 1), "reps": reps}
+
+
+def cpu_baseline(orders):
+    """The oracle on the host cores: its assembled CSR diffusion matrix (constrained),
+    applied by the oracle's C/OpenMP timing variant on reduced lattices of the sweep's
+    recipe for p <= 3 (the CSR of higher orders outgrows a bounded sample), and its
+    Jacobi-PCG to 1e-8 at p = 3 with the sine load."""
     import numpy as np
 
     import oracle
     import synth
-    from oracle import forms
+    from oracle import csr_host, forms
+    from oracle.forms import assemble_vector
     t_start = time.perf_counter()
-    sizes = {p: (1e5 if p <= 2 else 5e4 if p <= 4 else 2e4) for p in orders}
+    sizes = {1: 1.25e5, 2: 2.5e5, 3: 2.5e5}
     tot_n, tot_t, parts, t_asm = 0.0, 0.0, [], 0.0
-    per_order_budget = budget_s / max(1, len(orders))
-    for p in orders:
+    pcg = None
+    for p in [q for q in orders if q in sizes]:
         n = lattice_size(p, sizes[p])
         mesh = synth.hex_lattice(n, 0.05, seed=2)
         kappa = synth.lognormal_iid(mesh["hex"].shape[0], p + 2, 1.0, seed=3)
         ta = time.perf_counter()
         sp = oracle.H1Space(mesh, p)
         K = oracle.assemble(sp, forms.element_stiffness(mesh, p, p + 2, kappa))
-        Kc, _ = oracle.constrain(K, np.zeros(sp.ndofs), sp.boundary)
+        b = assemble_vector(sp, forms.element_load(mesh, p, p + 2, synth.sine_source))
+        Kc, bc = oracle.constrain(K, b, sp.boundary)
         t_asm += time.perf_counter() - ta
+        H = csr_host.HostCSR(Kc)
         x = np.random.default_rng(p).normal(size=sp.ndofs)
-        y = Kc @ x
+        y = np.empty(sp.ndofs)
+        H.matvec(x, y)
         reps, t0 = 0, time.perf_counter()
         while True:
-            y = Kc @ x
+            H.matvec(x, y)
             reps += 1
             el = time.perf_counter() - t0
-            if el > min(1.0, per_order_budget / 4) and reps >= 3:
+            if el > 1.0 and reps >= 5:
                 break
         t_apply = el / reps
         tot_n += sp.ndofs
         tot_t += t_apply
         parts.append(f"p{p}:{sp.ndofs}dofs:{sp.ndofs / t_apply / 1e9:.4f}GDOF/s")
-        del y
-    return {
-        "value": round(tot_n / tot_t / 1e9, 5), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-        "sample": ("oracle CSR matvec (scipy, single thread) of the assembled constrained "
-                   "diffusion matrix, one apply per order, on reduced lattices of the same "
-                   "recipe: " + ", ".join(parts) +
+        if p == 3:
+            t0 = time.perf_counter()
+            _, its, rel = H.pcg_jacobi(bc, Kc.diagonal(), tol=1e-8)
+            pcg = {"order": 3, "ndofs": int(sp.ndofs), "iters": its, "rel_res": rel,
+                   "seconds": round(time.perf_counter() - t0, 3)}
+        del K, Kc, H
+    out = {
+        "value": round(tot_n / tot_t / 1e9, 5), "unit": "GDOF/s", "cores": csr_host.threads(),
+        "kind": "oracle",
+        "sample": ("oracle CSR matvec of the assembled constrained diffusion matrix (C/OpenMP "
+                   "timing variant, rows split over the threads), one apply per order, on "
+                   "reduced lattices of the sweep's recipe, p <= 3 only: " + ", ".join(parts) +
                    f"; oracle assembly {t_asm:.1f}s; leg total "
-                   f"{time.perf_counter() - t_start:.1f}s on {os.cpu_count()} host cpus"),
+                   f"{time.perf_counter() - t_start:.1f}s"),
     }
+    if pcg is not None:
+        out["jacobi_pcg_time_to_1e-8"] = pcg
+    return out
+
+
+def hcurl_algorithmic_bytes(p: int, ne: int, ndofs: int, nc: int) -> int:
+    """H(curl) apply: x + y + nc values per point + the element->dof map with one sign
+    byte per element dof (4 + 1 bytes)."""
+    q = p + 2
+    return 16 * ndofs + 8 * nc * ne * q ** 3 + 5 * ne * 3 * p * (p + 1) ** 2
+
+
+def bench_hcurl(P, torch, orders, target, steps=10, warmup=2):
+    """Definite Maxwell operator (alpha curl-curl + beta mass, lognormal (alpha, beta) per
+    quadrature point, tangential essential dofs eliminated) on Nedelec spaces of ~target
+    dofs, 5% jitter: apply time per order from HIP events (with its y-init)."""
+    import synth
+    out = {}
+    for p in orders:
+        n = max(1, int(round((target / (3.0 * p ** 3)) ** (1.0 / 3.0))))
+        mesh = synth.hex_lattice(n, 0.05, seed=2)
+        ne = mesh["hex"].shape[0]
+        S = P.Space(P.Mesh.from_dict(mesh), p, family="nd")
+        del mesh
+        q = p + 2
+        ab = torch.stack([torch.as_tensor(synth.lognormal_iid(ne, q, 1.0, seed=4), device="cuda"),
+                          torch.as_tensor(synth.lognormal_iid(ne, q, 1.0, seed=5), device="cuda")],
+                         dim=-1).contiguous()
+        op = P.Operator(S, P.HCURL_MAXWELL, S.qdata(P.HCURL_MAXWELL, coeff=ab))
+        del ab
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(200 + p)
+        x = torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=gen)
+        y = torch.empty_like(x)
+        for _ in range(warmup):
+            op.apply(x, y)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            op.apply(x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / steps
+        by = hcurl_algorithmic_bytes(p, S.nelem, S.ndofs, 12)
+        out[str(p)] = {"ndofs": S.ndofs, "elements": S.nelem, "ms": round(t * 1e3, 4),
+                       "gdofs": round(S.ndofs / t / 1e9, 3),
+                       "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"hcurl p={p}: {out[str(p)]}")
+        del op, x, y, S
+        torch.cuda.empty_cache()
+    return out
+
+
+def dg_algorithmic_bytes(p: int, ne: int, ndofs: int, nfaces: int, nbfaces: int) -> int:
+    """DG convection: x + y + 3 values per volume point + one value per face point + the
+    face records (3 ints per interior face, 2 per boundary face)."""
+    q = p + 2
+    return 16 * ndofs + 24 * ne * q ** 3 + 8 * (nfaces + nbfaces) * q * q + 12 * nfaces + 8 * nbfaces
+
+
+def bench_dg(P, torch, orders, target, steps=10, warmup=2):
+    """Upwind DG convection (constant velocity (1, 1/2, 1/4)) on discontinuous spaces of
+    ~target dofs, 5% jitter: apply time per order (volume kernel + face kernel + y-init)."""
+    import synth
+    out = {}
+    beta = torch.tensor([1.0, 0.5, 0.25], dtype=torch.float64, device="cuda")
+    for p in orders:
+        n = max(1, int(round(target ** (1.0 / 3.0) / (p + 1))))
+        mesh = synth.hex_lattice(n, 0.05, seed=2)
+        S = P.Space(P.Mesh.from_dict(mesh), p, family="l2")
+        del mesh
+        op = P.Operator(S, P.DG_CONVECTION, S.qdata(P.DG_CONVECTION, coeff=beta), constrained=False)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(300 + p)
+        x = torch.randn(S.ndofs, dtype=torch.float64, device="cuda", generator=gen)
+        y = torch.empty_like(x)
+        for _ in range(warmup):
+            op.apply(x, y)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            op.apply(x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / steps
+        nf = 3 * n * n * (n - 1)
+        nb = 6 * n * n
+        by = dg_algorithmic_bytes(p, S.nelem, S.ndofs, nf, nb)
+        out[str(p)] = {"ndofs": S.ndofs, "elements": S.nelem, "ms": round(t * 1e3, 4),
+                       "gdofs": round(S.ndofs / t / 1e9, 3),
+                       "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"dg p={p}: {out[str(p)]}")
+        del op, x, y, S
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_mixed(P, torch, n=45, p=6, tol=1e-8):
@@ -527,14 +662,19 @@ def main():
     ap.add_argument("--orders", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--target-dofs", type=float, default=1e7)
     ap.add_argument("--scatter", choices=["atomic", "evec"], default="atomic")
-    ap.add_argument("--cg-orders", default="3", help="orders for the Jacobi-PCG solve ('' = none)")
+    ap.add_argument("--cg-orders", default="1,2,3,4,5,6,7,8",
+                    help="orders for the Jacobi-PCG solve ('' = none)")
+    ap.add_argument("--geom-cg-orders", default="3",
+                    help="orders also solved with the recomputed-geometry operator")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time the device-to-device copy (for counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mass", action="store_true")
     ap.add_argument("--no-geom", action="store_true",
                     help="skip the recomputed-geometry diffusion variant")
     ap.add_argument("--no-conv", action="store_true",
                     help="skip the convection, gradient, divergence and elasticity operators")
-    ap.add_argument("--forms", default="mixed,batched,learned,pmg,paper2d",
+    ap.add_argument("--forms", default="mixed,batched,learned,pmg,paper2d,hcurl,dg",
                     help="solver forms to measure beside the sweep ('' = none)")
     ap.add_argument("--pmg-orders", default="3,6",
                     help="orders of the sweep problems solved with order multigrid")
@@ -551,6 +691,11 @@ def main():
 
     from paper_1911_09220_amd import pafem as P
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        print(json.dumps({"copy": copy_bandwidth(torch)}), flush=True)
+        return
+    copy = copy_bandwidth(torch)
+    log(f"device copy {copy['GBps_read_plus_write']} GB/s (read + write)")
     orders = [int(v) for v in args.orders.split(",") if v]
     t_setup = time.perf_counter()
     probs = []
@@ -646,7 +791,9 @@ def main():
                 "traffic": recorded_traffic(dom["p"]), "source_hash": apply_source_hash(),
                 "kernel": f"pa_apply_kernel diffusion p={dom['p']} q1d={dom['p'] + 2} f64 "
                           f"({args.scatter} scatter, with its y-init kernel)",
-                "bytes_per_launch": by}
+                "bytes_per_launch": by,
+                "measured_copy_GBps": copy["GBps_read_plus_write"],
+                "frac_of_measured_copy": round(achieved / copy["GBps_read_plus_write"], 4)}
 
     cg = {}
     for p in [int(v) for v in args.cg_orders.split(",") if v]:
@@ -664,7 +811,7 @@ def main():
                       "seconds": round(info["seconds"], 4), "status": info["status"],
                       "true_rel_res": info["true_rel_res"], "diag_seconds": round(t_diag, 4),
                       "ms_per_iter": round(1e3 * info["seconds"] / max(1, info["iters"]), 4)}
-        if not args.no_geom:
+        if not args.no_geom and str(p) in args.geom_cg_orders.split(","):
             # same solve with the recomputed-geometry operator (diagonal of the stored one)
             xg, gi = pr["geom"].pcg(b, diag=diag, rel_tol=1e-8, max_iter=20000, history=False)
             cg[str(p)]["recomputed_geometry"] = {
@@ -690,6 +837,11 @@ def main():
                    "vector_diffusion_apply": vec3, "setup_seconds": round(t_setup, 1),
                    "timed_wall_seconds": round(wall, 4)},
         "roofline": roofline,
+        "diffusion_hbm_frac_by_p": {k: v["hbm_frac"] for k, v in per_p.items()},
+        "diffusion_frac_of_copy_by_p": {
+            k: round(v["hbm_frac"] * HBM_PEAK_GBS / copy["GBps_read_plus_write"], 4)
+            for k, v in per_p.items()},
+        "device_copy": copy,
         "cg_time_to_1e-8": cg,
     }
     forms = [f for f in args.forms.split(",") if f]
@@ -709,6 +861,12 @@ def main():
         for p in [int(v) for v in args.pmg_orders.split(",") if v]:
             log(f"pmg p={p}")
             out["pmg"][str(p)] = bench_pmg(P, torch, p=p, target=args.target_dofs)
+    if "hcurl" in forms:
+        log("hcurl")
+        out["hcurl_maxwell_apply"] = bench_hcurl(P, torch, orders, args.target_dofs)
+    if "dg" in forms:
+        log("dg")
+        out["dg_convection_apply"] = bench_dg(P, torch, orders, args.target_dofs)
     if "paper2d" in forms:
         log("paper2d")
         out["paper_2d_cg200"] = bench_paper2d(P, torch)

@@ -96,6 +96,38 @@ typedef int32_t pafem_status;
  * diagonal or CG on it. */
 #define PAFEM_ELASTICITY 6
 
+/* Nedelec (H(curl)) operators, on a space from pafem_space_create_nd: the forms of
+ * the definite Maxwell problem of the paper's Example 3 ("Discrete de Rham
+ * Complex"; the H(curl) integrators of "GPU Acceleration").  With the covariant
+ * map u = J^{-T} uhat and curl u = J curlhat uhat / det J:
+ *   PAFEM_HCURL_MASS      (beta u, v):           D_q = w beta det J J^{-1} J^{-T}
+ *                          (the same 6 values per point as PAFEM_DIFFUSION)
+ *   PAFEM_HCURL_CURLCURL  (alpha curl u, curl v): D_q = w alpha J^T J / det J (6 values)
+ *   PAFEM_HCURL_MAXWELL   the sum of both, coefficients as (alpha, beta) pairs per
+ *                          point [E][Q^3][2] (12 values per point)
+ * Constrained (tangential essential dofs eliminated) or not; atomic scatter; FP64. */
+#define PAFEM_HCURL_MASS 7
+#define PAFEM_HCURL_CURLCURL 8
+#define PAFEM_HCURL_MAXWELL 9
+
+/* Upwind DG convection on a space from pafem_space_create_l2 (convection "including
+ * DG" among the partially assembled integrators of "GPU Acceleration"): the steady
+ * transport term div(beta u) with a constant velocity beta, zero inflow data,
+ *   a(u, v) = -sum_K int_K u beta . grad v + sum_F int_F (beta . n) u_up (v^- - v^+)
+ *             + int_{outflow} (beta . n) u v,
+ * n from the face's "-" element to its "+" element, u_up the trace on the side the
+ * flow leaves.  qdata: per volume point w adj(J) beta (3 values, the layout of
+ * PAFEM_CONVECTION), then per interior face and per boundary face the Q^2 values
+ * w (beta . N) at the face's Gauss points (N the area-weighted normal, outward from
+ * the face's "-" element); coeff of pafem_qdata_assemble: device beta[3].
+ * Unconstrained, atomic scatter, FP64, not symmetric (no diagonal or CG). */
+#define PAFEM_DG_CONVECTION 10
+
+/* Space families (pafem_space_family). */
+#define PAFEM_SPACE_H1 0
+#define PAFEM_SPACE_ND 1
+#define PAFEM_SPACE_L2 2
+
 /* Storage types. */
 #define PAFEM_F64 0
 #define PAFEM_F32 1
@@ -177,6 +209,38 @@ void pafem_mesh_destroy(pafem_mesh mesh);
 pafem_status pafem_space_create_h1(pafem_mesh mesh, int32_t order, int32_t flags,
                                    pafem_space* out);
 void pafem_space_destroy(pafem_space space);
+
+/* Nedelec (H(curl)-conforming) space of order 1..8 on a hexahedral mesh
+ * ("Discrete de Rham Complex"; vector dofs as in "Finite Elements": the dof of a
+ * basis function is its dot product with a fixed vector at its node).  Local dof
+ * (a, i0, i1, i2), component-major, first index fastest: component a is the
+ * product of the open basis (Lagrange on the p Gauss-Legendre points) along axis
+ * a and the closed basis (Lagrange on the p+1 Gauss-Lobatto points) along the
+ * other two; 3 p (p+1)^2 dofs per element.  Global numbering: edge dofs (p per
+ * edge, from its smaller to its larger vertex id), face dofs (2 p (p-1) per face),
+ * interiors.  Orientation: the global basis function along local axis a is the
+ * local one when the smallest vertex id among the dof entity's corners with c_a = 1
+ * exceeds the smallest among those with c_a = 0, else its negative (interior dofs
+ * are never negated); pafem_space_elem_signs returns these signs.  Essential dofs:
+ * every dof on a boundary face (the tangential trace).  The other pafem_space_*
+ * calls work as for H1 spaces (dof coordinates are the dof nodes).  Host call.
+ * Errors: EINVAL (bad mesh), EUNSUPPORTED (order, quadrilateral mesh). */
+pafem_status pafem_space_create_nd(pafem_mesh mesh, int32_t order, int32_t flags,
+                                   pafem_space* out);
+/* Discontinuous (L2) space of order 1..8 on a hexahedral mesh ("Discrete de Rham
+ * Complex"; nodal Lagrange basis on the (p+1)^3 Gauss-Lobatto points of every
+ * element, no continuity): element e of the caller's numbering owns dofs
+ * e * (p+1)^3 + i, i lexicographic; no essential dofs.  The space also records its
+ * interior faces (with the orientation between the two sides) and boundary faces
+ * for the face terms of PAFEM_DG_CONVECTION.  Host call.  Errors as
+ * pafem_space_create_h1. */
+pafem_status pafem_space_create_l2(pafem_mesh mesh, int32_t order, int32_t flags,
+                                   pafem_space* out);
+/* PAFEM_SPACE_H1, PAFEM_SPACE_ND or PAFEM_SPACE_L2. */
+pafem_status pafem_space_family(pafem_space space, int32_t* family);
+/* signs[ne * dofs_per_elem] (+1 / -1) of each element's local dofs in the global
+ * basis, caller element order; all +1 for an H1 space.  Host call. */
+pafem_status pafem_space_elem_signs(pafem_space space, int8_t* signs);
 
 /* Sizes: global dofs, elements, dofs per element ((p+1)^3), essential dofs. */
 pafem_status pafem_space_info(pafem_space space, int64_t* ndofs, int64_t* nelem,

@@ -67,6 +67,26 @@ void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st, 
   const bool constrained = op.flags & PAFEM_OP_CONSTRAINED;
   const bool evec = op.flags & PAFEM_OP_SCATTER_EVEC;
   const int vdt = vector_dtype(op.qdtype);
+  if (op.kind == PAFEM_DG_CONVECTION) {
+    const double* qd = static_cast<const double*>(op.qdata);
+    launch_fill(static_cast<double*>(y), 0.0, s.ndofs, st);
+    require(launch_pa_apply(s.dev, op.kind, op.q1d, PAFEM_F64, false, false, qd, x, y,
+                            PAFEM_F64, st, nullptr),
+            PAFEM_EUNSUPPORTED, "DG volume kernel not built for this order/q1d");
+    launch_dg_faces(s.dev, op.q1d, qd + qdata_values(s.ne, op.q1d, 3),
+                    static_cast<const double*>(x), static_cast<double*>(y), st);
+    return;
+  }
+  if (nd_kind(op.kind)) {
+    if (!y_ready)
+      launch_scatter_init(s.dev, static_cast<const double*>(x), constrained,
+                          static_cast<double*>(y), st);
+    require(launch_nd_apply(s.dev, op.kind, op.q1d, constrained,
+                            static_cast<const double*>(op.qdata), static_cast<const double*>(x),
+                            static_cast<double*>(y), st, dotp),
+            PAFEM_EUNSUPPORTED, "H(curl) apply not built for this order/q1d");
+    return;
+  }
   if (evec) {
     require(launch_pa_apply(s.dev, op.kind, op.q1d, op.qdtype, constrained, true, op.qdata, x,
                             work, vdt, st, dotp),
@@ -115,7 +135,7 @@ extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 271; }
+int32_t pafem_version(void) { return 273; }
 
 int32_t pafem_set_graph_mode(int32_t mode) {
   return graph_mode_flag().exchange(mode != 0 ? 1 : 0);
@@ -192,6 +212,55 @@ pafem_status pafem_space_create_h1(pafem_mesh mesh, int32_t order, int32_t flags
       throw;
     }
     *out = s;
+  });
+}
+
+pafem_status pafem_space_create_nd(pafem_mesh mesh, int32_t order, int32_t flags,
+                                   pafem_space* out) {
+  return guarded([&] {
+    require(mesh && out, PAFEM_EINVAL, "null pointer argument");
+    auto* s = new pafem_space_s();
+    try {
+      s->s = build_nd_space(&mesh->m, order, flags);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
+}
+
+pafem_status pafem_space_create_l2(pafem_mesh mesh, int32_t order, int32_t flags,
+                                   pafem_space* out) {
+  return guarded([&] {
+    require(mesh && out, PAFEM_EINVAL, "null pointer argument");
+    auto* s = new pafem_space_s();
+    try {
+      s->s = build_l2_space(&mesh->m, order, flags);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
+}
+
+pafem_status pafem_space_family(pafem_space space, int32_t* family) {
+  return guarded([&] {
+    require(space && space->s && family, PAFEM_EINVAL, "null pointer argument");
+    const int f = space->s->family;
+    *family = f == kFamilyND ? PAFEM_SPACE_ND : f == kFamilyL2 ? PAFEM_SPACE_L2 : PAFEM_SPACE_H1;
+  });
+}
+
+pafem_status pafem_space_elem_signs(pafem_space space, int8_t* signs) {
+  return guarded([&] {
+    require(space && space->s && signs, PAFEM_EINVAL, "null pointer argument");
+    const Space& s = *space->s;
+    if (s.family == kFamilyND)
+      std::copy(s.gsign.begin(), s.gsign.end(), signs);
+    else
+      std::fill(signs, signs + size_t(s.ne) * s.dpe, int8_t(1));
   });
 }
 
@@ -283,6 +352,14 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     const std::vector<float> tables32(s.tables.begin(), s.tables.end());
     up(11, tables32.data(), tables32.size() * 4, "upload FP32 tables");
     up(12, owner.data(), owner.size() * 4, "upload owner bits");
+    std::vector<int8_t> sign_dev(s.gsign.size());
+    for (int64_t k = 0; k < s.ne && !s.gsign.empty(); ++k)
+      std::copy_n(s.gsign.data() + size_t(s.dev_order[size_t(k)]) * s.dpe, s.dpe,
+                  sign_dev.data() + size_t(k) * s.dpe);
+    up(13, sign_dev.data(), sign_dev.size(), "upload dof signs");
+    up(14, s.tables_open.data(), s.tables_open.size() * 8, "upload open-basis tables");
+    up(15, s.faces.data(), s.faces.size() * 4, "upload faces");
+    up(16, s.bfaces.data(), s.bfaces.size() * 4, "upload boundary faces");
     hip_check(hipStreamSynchronize(st), "upload sync");
     s.dev_buf = device_buf;
     s.dev_bytes = nbytes;
@@ -299,6 +376,14 @@ pafem_status pafem_space_upload(pafem_space space, void* device_buf, size_t nbyt
     s.dev.tile_slot = reinterpret_cast<const uint16_t*>(base + off[10]);
     s.dev.tables32 = reinterpret_cast<const float*>(base + off[11]);
     s.dev.owner = reinterpret_cast<const uint32_t*>(base + off[12]);
+    s.dev.sign = s.gsign.empty() ? nullptr : reinterpret_cast<const int8_t*>(base + off[13]);
+    s.dev.tables_open =
+        s.tables_open.empty() ? nullptr : reinterpret_cast<const double*>(base + off[14]);
+    s.dev.family = s.family;
+    s.dev.faces = s.faces.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + off[15]);
+    s.dev.bfaces = s.bfaces.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + off[16]);
+    s.dev.nfaces = int64_t(s.faces.size() / kFaceInts);
+    s.dev.nbfaces = int64_t(s.bfaces.size() / 2);
     s.dev.ne = s.ne;
     s.dev.ndofs = s.ndofs;
     s.dev.p = s.p;
@@ -319,10 +404,12 @@ pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int6
               "quadrilaterals support the mass and diffusion operators");
       *nvalues = qdata_values_2d(space->s->ne, q1d, kind == PAFEM_DIFFUSION ? 3 : 1);
     } else {
-      const int nc = kind == PAFEM_DIFFUSION ? 6 : kind == PAFEM_CONVECTION ? 3
-                     : (kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE) ? 9
-                     : kind == PAFEM_ELASTICITY ? 11 : 1;
-      *nvalues = qdata_values(space->s->ne, q1d, nc);
+      require(kind_family(kind) == space->s->family, PAFEM_EUNSUPPORTED,
+              "operator kind and space family do not match (H1, Nedelec or L2)");
+      *nvalues = qdata_values(space->s->ne, q1d, qdata_components(kind));
+      if (kind == PAFEM_DG_CONVECTION)
+        *nvalues += int64_t(space->s->faces.size() / kFaceInts + space->s->bfaces.size() / 2) *
+                    q1d * q1d;
     }
   });
 }
@@ -341,10 +428,19 @@ pafem_status pafem_qdata_assemble(pafem_space space, int32_t kind, int32_t q1d,
             "the convection operator needs the velocity field");
     require(kind != PAFEM_ELASTICITY || coeff, PAFEM_EINVAL,
             "the elasticity operator needs the (lambda, mu) pairs");
+    require(kind != PAFEM_HCURL_MAXWELL || coeff, PAFEM_EINVAL,
+            "the definite Maxwell operator needs the (alpha, beta) pairs");
+    require(kind_family(kind) == s.family, PAFEM_EUNSUPPORTED,
+            "operator kind and space family do not match (H1, Nedelec or L2)");
+    require(kind != PAFEM_DG_CONVECTION || coeff, PAFEM_EINVAL,
+            "the DG convection operator needs the velocity (3 values)");
     auto st = static_cast<hipStream_t>(stream);
     hip_check(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(s.dev.status), INT_MAX, 1, st),
               "status init");
     launch_qdata(s.dev, kind, q1d, coeff, coeff_scale, qdata, st);
+    if (kind == PAFEM_DG_CONVECTION)
+      launch_dg_face_qdata(s.dev, q1d, coeff, coeff_scale,
+                           qdata + qdata_values(s.ne, q1d, qdata_components(kind)), st);
     int32_t bad = INT_MAX;
     hip_check(hipMemcpyAsync(&bad, s.dev.status, 4, hipMemcpyDeviceToHost, st), "status read");
     hip_check(hipStreamSynchronize(st), "qdata sync");
@@ -359,6 +455,18 @@ pafem_status pafem_op_create(pafem_space space, int32_t kind, int32_t q1d, const
     const Space& s = uploaded_space(space);
     require(out && qdata, PAFEM_EINVAL, "null pointer argument");
     require(known_kind(kind), PAFEM_EINVAL, "unknown operator kind");
+    require(kind_family(kind) == s.family, PAFEM_EUNSUPPORTED,
+            "operator kind and space family do not match (H1, Nedelec or L2)");
+    if (kind == PAFEM_DG_CONVECTION) {
+      require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "the DG convection operator is FP64");
+      require(flags == 0, PAFEM_EUNSUPPORTED,
+              "the DG convection operator is unconstrained with the atomic scatter");
+    }
+    if (nd_kind(kind)) {
+      require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "the H(curl) operators are FP64");
+      require((flags & ~PAFEM_OP_CONSTRAINED) == 0, PAFEM_EUNSUPPORTED,
+              "the H(curl) operators use the atomic scatter");
+    }
     if (kind == PAFEM_GRADIENT) {
       require(s.dim == 3, PAFEM_EUNSUPPORTED, "the gradient operator is built for hexahedra");
       require(qdata_dtype == PAFEM_F64, PAFEM_EUNSUPPORTED, "the gradient operator is FP64");

@@ -42,6 +42,31 @@ __device__ __forceinline__ float load_value<float, bf16>(const bf16* p) {
   return bf16_to_float(bf16{raw});
 }
 
+// Two adjacent stored values (components 2k and 2k+1 of one quadrature point in the
+// paired diffusion layout) with one non-temporal load: 16 bytes per lane in FP64.
+typedef double pafem_d2 __attribute__((ext_vector_type(2)));
+typedef float pafem_f2 __attribute__((ext_vector_type(2)));
+template <typename TC, typename TD>
+__device__ __forceinline__ void load_pair(const TD* p, TC& a, TC& b);
+template <>
+__device__ __forceinline__ void load_pair<double, double>(const double* p, double& a, double& b) {
+  const pafem_d2 v = __builtin_nontemporal_load(reinterpret_cast<const pafem_d2*>(p));
+  a = v.x;
+  b = v.y;
+}
+template <>
+__device__ __forceinline__ void load_pair<float, float>(const float* p, float& a, float& b) {
+  const pafem_f2 v = __builtin_nontemporal_load(reinterpret_cast<const pafem_f2*>(p));
+  a = v.x;
+  b = v.y;
+}
+template <>
+__device__ __forceinline__ void load_pair<float, bf16>(const bf16* p, float& a, float& b) {
+  const uint32_t raw = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+  a = bf16_to_float(bf16{uint16_t(raw & 0xffffu)});
+  b = bf16_to_float(bf16{uint16_t(raw >> 16)});
+}
+
 // Sum over the 64 lanes of a wave (butterfly: every lane ends with the total,
 // fixed association order, so results are reproducible run to run).
 __device__ __forceinline__ double wave_sum(double v) {

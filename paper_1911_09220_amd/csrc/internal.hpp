@@ -24,7 +24,27 @@ constexpr int kMaxQ1d = 12;  // 1D tables are built for every q1d in [1, kMaxQ1d
 inline bool known_kind(int kind) {
   return kind == PAFEM_MASS || kind == PAFEM_DIFFUSION || kind == PAFEM_DIFFUSION_GEOM ||
          kind == PAFEM_CONVECTION || kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE ||
-         kind == PAFEM_ELASTICITY;
+         kind == PAFEM_ELASTICITY || kind == PAFEM_HCURL_MASS || kind == PAFEM_HCURL_CURLCURL ||
+         kind == PAFEM_HCURL_MAXWELL || kind == PAFEM_DG_CONVECTION;
+}
+// operators on L2 spaces
+inline bool l2_kind(int kind) { return kind == PAFEM_DG_CONVECTION; }
+
+// operators on Nedelec spaces
+inline bool nd_kind(int kind) {
+  return kind == PAFEM_HCURL_MASS || kind == PAFEM_HCURL_CURLCURL || kind == PAFEM_HCURL_MAXWELL;
+}
+// stored values per quadrature point of each operator kind (hexahedra)
+inline int qdata_components(int kind) {
+  switch (kind) {
+    case PAFEM_DIFFUSION: case PAFEM_HCURL_MASS: case PAFEM_HCURL_CURLCURL: return 6;
+    case PAFEM_HCURL_MAXWELL: return 12;
+    case PAFEM_DG_CONVECTION: return 3;
+    case PAFEM_CONVECTION: return 3;
+    case PAFEM_GRADIENT: case PAFEM_DIVERGENCE: return 9;
+    case PAFEM_ELASTICITY: return 11;
+    default: return 1;
+  }
 }
 // operators that are not symmetric positive definite on one scalar space (mixed,
 // non-symmetric or vector-valued): no diagonal, no CG
@@ -43,16 +63,23 @@ inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 // Quadrature data is stored tile-interleaved: elements are grouped in tiles of
 // qdata_tile(Q) consecutive elements, and within a tile the values are ordered
-// [component][qz][element in tile][qy][qx].  One load instruction of the fused
+// [component][qz][element in tile][qy][qx] (the diffusion D in component pairs, below).  One load instruction of the fused
 // apply (all threads of a tile reading component c at plane qz) is then one
 // contiguous run.  The last tile is padded.
 constexpr int qdata_tile(int Q) { return (256 / (Q * Q)) > 0 ? (256 / (Q * Q)) : 1; }
 // Offset of value (e, component c, point q = qz*Q*Q + r) with nc components.
+// The six values of the diffusion D (and the twelve of the definite Maxwell form)
+// are stored in pairs: components 2k and 2k+1 of a point are adjacent ([pair][qz][element in tile][qy][qx][2]), so the apply reads a
+// pair with one 16-byte load per thread (FP64) and a workgroup's pair plane is still
+// one contiguous run.
 constexpr size_t qdata_index(int64_t e, int c, int q, int Q, int nc) {
   const int nt = qdata_tile(Q), qq = Q * Q;
   const int64_t tile = e / nt;
   const int el = int(e - tile * nt);
   const int qz = q / qq, r = q - qz * qq;
+  if (nc == 6 || nc == 12)
+    return ((size_t(tile) * (nc / 2) + c / 2) * Q + qz) * size_t(nt * qq) * 2 +
+           (size_t(el) * qq + r) * 2 + (c & 1);
   return ((size_t(tile) * nc + c) * Q + qz) * size_t(nt * qq) + size_t(el) * qq + r;
 }
 // Quadrilaterals: tiles of qdata_tile_2d(Q) elements (Q threads per element in the
@@ -101,7 +128,7 @@ std::vector<double> build_tables(int p, int ng);
 // of element centroids, so consecutive elements -- and each apply tile -- are
 // spatially compact); elem_orig maps back to the caller's element numbering.
 struct DevSpace {
-  const int32_t* gmap = nullptr;       // [ne][D^3], essential dofs stored as ~g
+  const int32_t* gmap = nullptr;       // [ne][dpe], essential dofs stored as ~g
   const double* gnodes = nullptr;      // [ne][NG^3][3]
   const uint8_t* bmask = nullptr;      // [ndofs] 1 on essential dofs
   const int32_t* toff = nullptr;       // [ndofs+1] transposed map offsets
@@ -114,9 +141,15 @@ struct DevSpace {
   const int32_t* tile_dofs = nullptr;  // unique dofs of each apply tile (~g if essential)
   const uint16_t* tile_slot = nullptr; // [ntiles*tile_ne*D^3] node -> index in its tile's list
   const uint32_t* owner = nullptr;     // [ne][owner_words(D^dim)] first-occurrence bits
+  const int8_t* sign = nullptr;        // Nedelec: [ne][dpe] orientation sign of each local dof
+  const double* tables_open = nullptr; // Nedelec: open-basis tables for q1d = 1..kMaxQ1d
+  const int32_t* faces = nullptr;      // L2: interior faces [nfaces][kFaceInts]
+  const int32_t* bfaces = nullptr;     // L2: boundary faces [nbfaces][2]
+  int64_t nfaces = 0, nbfaces = 0;
   int64_t ne = 0, ndofs = 0;
   int p = 0, ng = 0, tile_ne = 0;
   int dim = 3;                         // 3: hexahedra, 2: quadrilaterals
+  int family = 0;                      // kFamilyH1 or kFamilyND
 };
 
 struct Mesh {
@@ -129,8 +162,28 @@ struct Mesh {
   std::vector<double> gnodes;  // [ne][27][3] for geom_order 2
 };
 
+// space families: nodal H1 (Gauss-Lobatto nodes) and Nedelec H(curl)
+constexpr int kFamilyH1 = 0;
+constexpr int kFamilyND = 1;
+constexpr int kFamilyL2 = 2;
+// interior face of an L2 space: device elements of its two sides and
+// code = f_minus | f_plus << 3 | orientation << 6 (f = 2 * axis + side; orientation:
+// bit 0 swap, bit 1 reverse u, bit 2 reverse v, mapping the "-" side's face indices
+// (s, t) to the "+" side's (u, v); s, u along the lower tangential axis)
+constexpr int kFaceInts = 3;
+// the family an operator kind needs
+inline int kind_family(int kind) {
+  return nd_kind(kind) ? kFamilyND : l2_kind(kind) ? kFamilyL2 : kFamilyH1;
+}
+
+// Open-basis (Gauss-Legendre nodes, p of them) value table B_o[q][k] for each q1d,
+// stored one block after another: block Q starts at nd_open_offset(Q, p) doubles.
+inline size_t nd_open_offset(int Q, int p) { return size_t(p) * size_t(Q - 1) * size_t(Q) / 2; }
+std::vector<double> build_open_tables(int p);
+
 struct Space {
   const Mesh* mesh = nullptr;
+  int family = kFamilyH1;
   int dim = 3;
   int p = 0, D1 = 0, dpe = 0, ng = 0;
   int64_t ne = 0, ndofs = 0;
@@ -143,6 +196,10 @@ struct Space {
   std::vector<int32_t> bdr;       // essential dofs ascending
   std::vector<double> ref_nodes;  // Gauss-Lobatto nodes [D1]
   std::vector<double> tables;     // build_tables(p, ng)
+  std::vector<int8_t> gsign;      // Nedelec: [ne][dpe] dof signs, caller element order
+  std::vector<int32_t> faces;     // L2: [nfaces][kFaceInts] interior faces (device elements)
+  std::vector<int32_t> bfaces;    // L2: [nbfaces][2] boundary faces (device element, face)
+  std::vector<double> tables_open;  // Nedelec: build_open_tables(p)
   // device image (caller-owned buffer)
   void* dev_buf = nullptr;
   size_t dev_bytes = 0;
@@ -152,8 +209,16 @@ struct Space {
 
 // space.cpp
 Space* build_space(const Mesh* mesh, int order, int flags);
+// Nedelec space of order p on hexahedra: local dof (a, i0, i1, i2) component-major,
+// lexicographic (first index fastest), open index along a, closed along the others
+Space* build_nd_space(const Mesh* mesh, int order, int flags);
+inline int nd_dofs_per_elem(int p) { return 3 * p * (p + 1) * (p + 1); }
+// Discontinuous nodal space of order p on hexahedra: element e (caller order) owns dofs
+// e * (p+1)^3 + i, i lexicographic on the Gauss-Lobatto nodes; interior and boundary
+// face lists for the face terms
+Space* build_l2_space(const Mesh* mesh, int order, int flags);
 void space_dof_coords(const Space& s, double* xyz);
-constexpr int kSpaceSegments = 13;
+constexpr int kSpaceSegments = 17;
 // words of the per-element owner bitmask (bit i of element k: node i is the first
 // occurrence of its dof in device element order)
 inline int owner_words(int dpe) { return (dpe + 31) / 32; }

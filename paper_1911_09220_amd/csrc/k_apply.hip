@@ -71,18 +71,23 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   constexpr bool DIFF = (K0 == PAFEM_DIFFUSION) || GEOM;  // gradient in, gradient out
   // CONV: convection, gradient in, value out (the back contractions are the mass ones)
   constexpr bool CONV = (K0 == PAFEM_CONVECTION);
+  // DGV: volume term of the DG convection, -(u, beta . grad v): value in, gradient out
+  // (the forward contractions are the mass ones, the back ones the diffusion ones)
+  constexpr bool DGV = (K0 == PAFEM_DG_CONVECTION);
   // GRADV: gradient into a vector-valued output, gradient in, 3 values out (each
   // contracted back with B only), output component c at y + c * ystride
   constexpr bool GRADV = (K0 == PAFEM_GRADIENT);
   constexpr bool GRAD = DIFF || CONV || GRADV || DIVV;  // the forward contractions produce the gradient
-  constexpr bool BACK3 = DIFF || GRADV;         // three arrays in the back contractions
+  constexpr bool BACK3 = DIFF || GRADV || DGV;  // three arrays in the back contractions
+  constexpr bool BACKD = DIFF || DGV;           // gradient back contractions
   // values per point in registers; DIVV stores 9 and reads those of one input component
-  constexpr int NC = GEOM ? 1 : DIFF ? 6 : (CONV || DIVV) ? 3 : GRADV ? 9 : 1;
+  constexpr int NC = GEOM ? 1 : DIFF ? 6 : (CONV || DIVV || DGV) ? 3 : GRADV ? 9 : 1;
   constexpr int NCT = (DIVV || GRADC) ? 9 : NC;  // stored values per point
   constexpr int NA = GRAD ? 2 : 1;   // arrays after the x-lines (B and G along x)
-  constexpr int NCC = GRAD ? 3 : 1;  // arrays after the y-lines (one per derivative)
+  constexpr int NCC = (GRAD || DGV) ? 3 : 1;  // arrays after the y-lines (one per derivative)
   constexpr int NOUT = GRADV ? 3 : 1;  // output components
-  static_assert(!((CONV || GRADV || DIVV) && DOT), "the convection, gradient and divergence operators have no energy");
+  static_assert(!((CONV || GRADV || DIVV || DGV) && DOT), "the convection, gradient and divergence operators have no energy");
+  static_assert(!(DGV && EVEC), "the DG volume term uses the atomic scatter");
   static_assert(!((GRADV || DIVV) && EVEC), "the gradient and divergence operators use the atomic scatter");
   static_assert(NOUT * D <= NCC * Q, "back x-line arrays must fit the element region");
   static_assert(NV == 1 || DIVV || (!DOT && !EVEC && (K0 == PAFEM_MASS || K0 == PAFEM_DIFFUSION)),
@@ -126,14 +131,24 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   constexpr int PD =
       (K0 == PAFEM_DIFFUSION && NV == 1 && sizeof(TC) == ((P == 4 || P == 5) ? 8 : P == 6 ? 4 : 0)) ? 2 : Q;
   TC dq[Q][NC];
-  const TD* const qe0 = qd + size_t(tile) * NCT * QQQ * NE + tid;
+  // stored diffusion D: components in pairs per point, one load per pair
+  constexpr bool PAIRS = (NCT == 6);
+  const TD* const qe0 = qd + size_t(tile) * NCT * QQQ * NE + (PAIRS ? 2 * tid : tid);
+  auto load_plane = [&](int qz, int cbase) {
+    if constexpr (PAIRS) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        load_pair<TC, TD>(qe0 + 2 * ((k * Q + qz) * (NE * QQ)), dq[qz][2 * k], dq[qz][2 * k + 1]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        dq[qz][c] = load_value<TC, TD>(qe0 + ((cbase + c) * Q + qz) * (NE * QQ));
+    }
+  };
   auto load_dq = [&](int cbase) {
     if (act) {
 #pragma unroll
-      for (int qz = 0; qz < PD; ++qz)
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          dq[qz][c] = load_value<TC, TD>(qe0 + ((cbase + c) * Q + qz) * (NE * QQ));
+      for (int qz = 0; qz < PD; ++qz) load_plane(qz, cbase);
     }
   };
   if (!DIVV) load_dq(GRADC ? 3 * GC : 0);
@@ -276,11 +291,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
 #pragma unroll
     for (int qz = 0; qz < Q; ++qz) {
       if constexpr (PD < Q) {
-        if (qz + PD < Q) {
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-            dq[qz + PD][c] = load_value<TC, TD>(qe0 + (c * Q + qz + PD) * (NE * QQ));
-        }
+        if (qz + PD < Q) load_plane(qz + PD, 0);
         __asm__ volatile("" ::: "memory");  // keep the next plane's loads in this iteration
       }
       if constexpr (DIFF) {
@@ -368,6 +379,19 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
 #pragma unroll
           for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * sdiv[qz];
         }
+      } else if constexpr (DGV) {
+        // -u (w adj(J) beta) . grad_ref v: the value at the point times minus the stored
+        // vector, contracted back against the reference gradient
+        TC u = TC(0);
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) u += bB(qz, dz) * c0[dz];
+        const TC vx = -dq[qz][0] * u, vy = -dq[qz][1] * u, vz = -dq[qz][2] * u;
+#pragma unroll
+        for (int dz = 0; dz < D; ++dz) {
+          t0[dz] += bB(qz, dz) * vx;
+          t1[dz] += bB(qz, dz) * vy;
+          t2[dz] += bG(qz, dz) * vz;
+        }
       } else if constexpr (CONV) {
         // (beta . grad u) at the point: w adj(J) beta . (reference gradient)
         TC ux = TC(0), uy = TC(0), uz = TC(0);
@@ -439,7 +463,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
         TC b = TC(0), g = TC(0);
 #pragma unroll
         for (int qy = 0; qy < Q; ++qy) {
-          if (DIFF) {
+          if (BACKD) {
             g += bB(qy, dy) * v0[qy];
             b += bG(qy, dy) * v1[qy] + bB(qy, dy) * v2[qy];
           } else {
@@ -447,7 +471,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
           }
         }
         at(dy / Q, dy % Q, yx, yz) = b;
-        if (DIFF) at((D + dy) / Q, (D + dy) % Q, yx, yz) = g;
+        if (BACKD) at((D + dy) / Q, (D + dy) % Q, yx, yz) = g;
       }
     }
   }
@@ -482,7 +506,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
 #pragma unroll
     for (int qx = 0; qx < Q; ++qx) {
       wB[qx] = at(xy / Q, xy % Q, qx, xz);
-      if (DIFF) wG[qx] = at((D + xy) / Q, (D + xy) % Q, qx, xz);
+      if (BACKD) wG[qx] = at((D + xy) / Q, (D + xy) % Q, qx, xz);
     }
 #pragma unroll
     for (int dx = 0; dx < D; ++dx) {
@@ -490,7 +514,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
 #pragma unroll
       for (int qx = 0; qx < Q; ++qx) {
         acc += bB(qx, dx) * wB[qx];
-        if (DIFF) acc += bG(qx, dx) * wG[qx];
+        if (BACKD) acc += bG(qx, dx) * wG[qx];
       }
       if (EVEC)
         y[size_t(e) * DDD + r * D + dx] = TV(acc);
@@ -616,6 +640,12 @@ bool launch_order(const DevSpace& sp, int kind, int qdtype, int vdtype, bool con
     if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp || evec) return false;
     launch_one<P, PAFEM_DIVERGENCE, false, false, double, double, double>(sp, constrained, qd, x,
                                                                            out, nullptr, st);
+    return true;
+  }
+  if (kind == PAFEM_DG_CONVECTION) {
+    if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || dotp || evec) return false;
+    launch_one<P, PAFEM_DG_CONVECTION, false, false, double, double, double>(sp, false, qd, x,
+                                                                              out, nullptr, st);
     return true;
   }
   if (kind == PAFEM_CONVECTION) {

@@ -96,11 +96,43 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* _
     if (!(det > 0.0)) atomicMin(&status[0], orig[e]);
     const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
     const double w = tv.wts[q1] * tv.wts[q2] * tv.wts[q3];
-    // scalar coefficient per point (convection and elasticity read theirs below)
-    const double c = (kind == PAFEM_CONVECTION || kind == PAFEM_ELASTICITY)
+    // scalar coefficient per point (convection, elasticity and the definite Maxwell
+    // form read theirs below)
+    const double c = (kind == PAFEM_CONVECTION || kind == PAFEM_ELASTICITY ||
+                      kind == PAFEM_HCURL_MAXWELL || kind == PAFEM_DG_CONVECTION)
                          ? 0.0
                          : scale * (coeff ? coeff[size_t(orig[e]) * QQQ + q] : 1.0);
-    if (kind == PAFEM_MASS) {
+    if (kind == PAFEM_HCURL_CURLCURL || kind == PAFEM_HCURL_MAXWELL) {
+      // curl-curl: w alpha J^T J / det J (the reference curl maps with J / det J);
+      // Maxwell: that with alpha, then the mass part w beta A A^T / det J with beta,
+      // (alpha, beta) the point's coefficient pair
+      const int nc = kind == PAFEM_HCURL_MAXWELL ? 12 : 6;
+      double ca = c, cb = 0.0;
+      if (kind == PAFEM_HCURL_MAXWELL) {
+        const double* ab = coeff + (size_t(orig[e]) * QQQ + q) * 2;
+        ca = scale * ab[0];
+        cb = scale * ab[1];
+      }
+      const double f = w * ca / det;
+      double T[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) T[a][b] = J[0][a] * J[0][b] + J[1][a] * J[1][b] + J[2][a] * J[2][b];
+      qd[qdata_index(e, 0, q, Q, nc)] = f * T[0][0];
+      qd[qdata_index(e, 1, q, Q, nc)] = f * T[0][1];
+      qd[qdata_index(e, 2, q, Q, nc)] = f * T[0][2];
+      qd[qdata_index(e, 3, q, Q, nc)] = f * T[1][1];
+      qd[qdata_index(e, 4, q, Q, nc)] = f * T[1][2];
+      qd[qdata_index(e, 5, q, Q, nc)] = f * T[2][2];
+      if (kind == PAFEM_HCURL_MAXWELL) {
+        const double g = w * cb / det;
+        qd[qdata_index(e, 6, q, Q, 12)] = g * (A00 * A00 + A01 * A01 + A02 * A02);
+        qd[qdata_index(e, 7, q, Q, 12)] = g * (A00 * A10 + A01 * A11 + A02 * A12);
+        qd[qdata_index(e, 8, q, Q, 12)] = g * (A00 * A20 + A01 * A21 + A02 * A22);
+        qd[qdata_index(e, 9, q, Q, 12)] = g * (A10 * A10 + A11 * A11 + A12 * A12);
+        qd[qdata_index(e, 10, q, Q, 12)] = g * (A10 * A20 + A11 * A21 + A12 * A22);
+        qd[qdata_index(e, 11, q, Q, 12)] = g * (A20 * A20 + A21 * A21 + A22 * A22);
+      }
+    } else if (kind == PAFEM_MASS) {
       qd[qdata_index(e, 0, q, Q, 1)] = w * c * det;
     } else if (kind == PAFEM_GRADIENT || kind == PAFEM_DIVERGENCE) {
       // w kappa det J J^{-T} as D[c][b] = w kappa adj(J)[b][c]: physical derivative c
@@ -125,9 +157,11 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* _
       for (int k = 0; k < 9; ++k) qd[qdata_index(e, k, q, Q, 11)] = Kinv[k] * id;
       qd[qdata_index(e, 9, q, Q, 11)] = wd * lm[0];
       qd[qdata_index(e, 10, q, Q, 11)] = wd * lm[1];
-    } else if (kind == PAFEM_CONVECTION) {
+    } else if (kind == PAFEM_CONVECTION || kind == PAFEM_DG_CONVECTION) {
       // alpha det J J^{-1} beta = alpha adj(J) beta, beta = scale * velocity at the point
-      const double* v = coeff + (size_t(orig[e]) * QQQ + q) * 3;
+      // (the DG convection: one constant velocity)
+      const double* v =
+          kind == PAFEM_DG_CONVECTION ? coeff : coeff + (size_t(orig[e]) * QQQ + q) * 3;
       const double b0 = scale * v[0], b1 = scale * v[1], b2 = scale * v[2];
       qd[qdata_index(e, 0, q, Q, 3)] = w * (A00 * b0 + A01 * b1 + A02 * b2);
       qd[qdata_index(e, 1, q, Q, 3)] = w * (A10 * b0 + A11 * b1 + A12 * b2);
@@ -135,7 +169,8 @@ __global__ void qdata_kernel(const double* __restrict__ gnodes, const int32_t* _
     } else if (kind == PAFEM_DIFFUSION_GEOM) {
       qd[qdata_index(e, 0, q, Q, 1)] = w * c;  // the apply recomputes the geometric part
     } else {
-      // alpha kappa det J J^{-1} J^{-T} = alpha kappa A A^T / det J
+      // diffusion and the H(curl) mass: alpha kappa det J J^{-1} J^{-T} = alpha kappa
+      // A A^T / det J
       const double f = w * c / det;
       qd[qdata_index(e, 0, q, Q, 6)] = f * (A00 * A00 + A01 * A01 + A02 * A02);
       qd[qdata_index(e, 1, q, Q, 6)] = f * (A00 * A10 + A01 * A11 + A02 * A12);

@@ -43,6 +43,17 @@ bool launch_pa_apply(const DevSpace& sp, int kind, int q1d, int qdtype, bool con
                      bool evec, const void* qd, const void* x, void* out, int vdtype,
                      hipStream_t st, double* dotp = nullptr);
 int pa_apply_blocks(const DevSpace& sp);
+// DG convection (k_dg.hip): the face values w (beta . N) of every interior face, then of
+// every boundary face, Q^2 per face (beta = scale * beta3[0..2], device)
+void launch_dg_face_qdata(const DevSpace& sp, int q1d, const double* beta3, double scale,
+                          double* fq, hipStream_t st);
+// adds the upwind face terms of the DG convection to y
+void launch_dg_faces(const DevSpace& sp, int q1d, const double* fq, const double* x, double* y,
+                     hipStream_t st);
+// H(curl) mass / curl-curl / definite Maxwell apply on a Nedelec space (k_hcurl.hip);
+// false when the order, q1d or kind is not built
+bool launch_nd_apply(const DevSpace& sp, int kind, int q1d, bool constrained, const double* qd,
+                     const double* x, double* y, hipStream_t st, double* dotp = nullptr);
 
 // ---- quadrilaterals (k_2d.hip); the launchers above dispatch to these when sp.dim == 2 ----
 void launch_qdata_2d(const DevSpace& sp, int kind, int q1d, const double* coeff, double scale,

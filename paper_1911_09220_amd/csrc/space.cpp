@@ -463,7 +463,350 @@ Space* build_space(const Mesh* mesh, int order, int flags) {
   return s;
 }
 
+// Nedelec space.  Local dof (a, i0, i1, i2): the basis function of component a, open
+// (Gauss-Legendre) index i_a in [0, p), closed (Gauss-Lobatto) indices i_b in [0, p]
+// for b != a.  A dof with both closed indices on the element's boundary lies on an
+// edge along a, one on a face, none in the interior.  Global numbering: edge dofs
+// (p per edge, running from the edge's smaller to its larger vertex id), face dofs
+// (2p(p-1) per face, in the face frame of the H1 space: first the dofs along its
+// first axis, then along its second), interiors.  Orientation: the global basis
+// function along local axis a is the local one when the smallest vertex id among
+// the entity's corners with c_a = 1 exceeds the smallest among those with c_a = 0,
+// else its negative; interior dofs are never negated.  Every dof on a boundary face
+// is essential (tangential trace).
+Space* build_nd_space(const Mesh* mesh, int order, int flags) {
+  if (order < 1 || order > kMaxOrder)
+    throw Error(PAFEM_EUNSUPPORTED, "order must be in 1..8, got " + std::to_string(order));
+  if (mesh->dim != 3) throw Error(PAFEM_EUNSUPPORTED, "Nedelec spaces are built on hexahedra");
+  const Mesh& m = *mesh;
+  const int p = order, D1 = p + 1, dpe = nd_dofs_per_elem(p);
+  const int64_t ne = m.ne;
+  auto* s = new Space();
+  s->mesh = mesh;
+  s->family = kFamilyND;
+  s->p = p;
+  s->D1 = D1;
+  s->dpe = dpe;
+  s->ne = ne;
+  s->ng = (m.geom_order == 2) ? 3 : 2;
+  s->ref_nodes.resize(D1);
+  gauss_lobatto_01(D1, s->ref_nodes.data());
+
+  const auto fs = face_slots();
+  const auto es = edge_slots();
+  std::vector<std::array<int64_t, 4>> fkeys(size_t(ne) * 6);
+  std::vector<std::array<int64_t, 2>> ekeys(size_t(ne) * 12);
+  for (int64_t e = 0; e < ne; ++e) {
+    const ElemCorners c = corners_of(m, e);
+    for (int f = 0; f < 6; ++f) {
+      std::array<int64_t, 4> k = {c.v[fs[f].c[0]], c.v[fs[f].c[1]], c.v[fs[f].c[2]],
+                                  c.v[fs[f].c[3]]};
+      std::sort(k.begin(), k.end());
+      fkeys[size_t(e) * 6 + f] = k;
+    }
+    for (int k = 0; k < 12; ++k) {
+      const int64_t a = c.v[es[k].c0], b = c.v[es[k].c0 | (1 << es[k].axis)];
+      ekeys[size_t(e) * 12 + k] = {std::min(a, b), std::max(a, b)};
+    }
+  }
+  std::vector<int64_t> frep, erep;
+  std::vector<int32_t> fmult, emult;
+  match_keys<4>(fkeys, m.nv, frep, fmult);
+  match_keys<2>(ekeys, m.nv, erep, emult);
+  fkeys.clear();
+  fkeys.shrink_to_fit();
+  ekeys.clear();
+  ekeys.shrink_to_fit();
+  for (size_t i = 0; i < fmult.size(); ++i)
+    if (fmult[i] > 2) {
+      delete s;
+      throw Error(PAFEM_EINVAL, "non-conforming mesh: face shared by more than two elements "
+                                "(element " + std::to_string(i / 6) + ")");
+    }
+  std::vector<int32_t> eid(erep.size(), -1), fid(frep.size(), -1);
+  int64_t n_edges = 0, n_faces = 0;
+  for (size_t i = 0; i < erep.size(); ++i)
+    eid[i] = (erep[i] == int64_t(i)) ? int32_t(n_edges++) : eid[size_t(erep[i])];
+  for (size_t i = 0; i < frep.size(); ++i)
+    fid[i] = (frep[i] == int64_t(i)) ? int32_t(n_faces++) : fid[size_t(frep[i])];
+  const int64_t per_face = 2 * int64_t(p) * (p - 1), per_int = 3 * int64_t(p) * (p - 1) * (p - 1);
+  const int64_t fbase = n_edges * p;
+  const int64_t ibase = fbase + n_faces * per_face;
+  const int64_t ndofs = ibase + ne * per_int;
+  if (ndofs >= (int64_t(1) << 31) - 1 || ne * int64_t(dpe) >= (int64_t(1) << 31) - 1) {
+    delete s;
+    throw Error(PAFEM_EINVAL, "problem too large for 32-bit dof indices");
+  }
+  s->ndofs = ndofs;
+  int edge_slot_of[3][8];
+  for (int k = 0; k < 12; ++k) edge_slot_of[es[k].axis][es[k].c0] = k;
+
+  s->gmap.assign(size_t(ne) * dpe, 0);
+  s->gsign.assign(size_t(ne) * dpe, 1);
+  s->bmask.assign(size_t(ndofs), 0);
+  for (int64_t e = 0; e < ne; ++e) {
+    const ElemCorners c = corners_of(m, e);
+    int32_t* g = s->gmap.data() + size_t(e) * dpe;
+    int8_t* sg = s->gsign.data() + size_t(e) * dpe;
+    int j = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int n0 = a == 0 ? p : D1, n1 = a == 1 ? p : D1, n2 = a == 2 ? p : D1;
+      for (int i2 = 0; i2 < n2; ++i2)
+        for (int i1 = 0; i1 < n1; ++i1)
+          for (int i0 = 0; i0 < n0; ++i0, ++j) {
+            const int idx[3] = {i0, i1, i2};
+            // doubled lattice: closed i -> 2i, open k -> 2k + 1
+            int mm[3];
+            for (int b = 0; b < 3; ++b) mm[b] = (b == a) ? 2 * idx[b] + 1 : 2 * idx[b];
+            int nb = 0, nrm = -1;
+            for (int b = 0; b < 3; ++b)
+              if (b != a && (idx[b] == 0 || idx[b] == p)) {
+                ++nb;
+                nrm = b;
+              }
+            int64_t dof;
+            int sgn = 1;
+            if (nb == 2) {
+              int c0 = 0;
+              for (int b = 0; b < 3; ++b)
+                if (b != a && idx[b] == p) c0 |= (1 << b);
+              const int k = edge_slot_of[a][c0];
+              const int64_t va = c.v[c0], vb = c.v[c0 | (1 << a)];
+              const int kc = (va < vb) ? idx[a] : p - 1 - idx[a];
+              sgn = (vb > va) ? 1 : -1;
+              dof = int64_t(eid[size_t(e) * 12 + k]) * p + kc;
+            } else if (nb == 1) {
+              const int f = 2 * nrm + (idx[nrm] == p);
+              const int b0 = (nrm == 0) ? 1 : 0, b1 = (nrm == 2) ? 1 : 2;
+              int O = fs[f].c[0];
+              for (int q = 1; q < 4; ++q)
+                if (c.v[fs[f].c[q]] < c.v[O]) O = fs[f].c[q];
+              const int nb0 = O ^ (1 << b0), nb1 = O ^ (1 << b1);
+              const int au = (c.v[nb0] < c.v[nb1]) ? b0 : b1, av = (au == b0) ? b1 : b0;
+              const int mu = ((O >> au) & 1) ? 2 * p - mm[au] : mm[au];
+              const int mv = ((O >> av) & 1) ? 2 * p - mm[av] : mm[av];
+              int64_t loc;
+              if (a == au)
+                loc = int64_t(mv / 2 - 1) * p + (mu - 1) / 2;
+              else
+                loc = int64_t(p) * (p - 1) + int64_t((mv - 1) / 2) * (p - 1) + (mu / 2 - 1);
+              int64_t lo0 = INT64_MAX, lo1 = INT64_MAX;
+              for (int q = 0; q < 4; ++q) {
+                const int cc = fs[f].c[q];
+                if ((cc >> a) & 1)
+                  lo1 = std::min(lo1, c.v[cc]);
+                else
+                  lo0 = std::min(lo0, c.v[cc]);
+              }
+              sgn = (lo1 > lo0) ? 1 : -1;
+              dof = fbase + int64_t(fid[size_t(e) * 6 + f]) * per_face + loc;
+            } else {
+              // interior: component a block, open index along a, closed interior indices
+              int m0 = a == 0 ? p : p - 1, m1 = a == 1 ? p : p - 1;
+              const int j0 = a == 0 ? i0 : i0 - 1, j1 = a == 1 ? i1 : i1 - 1,
+                        j2 = a == 2 ? i2 : i2 - 1;
+              dof = ibase + e * per_int + int64_t(a) * p * (p - 1) * (p - 1) + j0 +
+                    int64_t(m0) * (j1 + int64_t(m1) * j2);
+            }
+            g[j] = int32_t(dof);
+            sg[j] = int8_t(sgn);
+          }
+    }
+    // essential dofs: the nodes on faces that belong to this element only
+    for (int f = 0; f < 6; ++f) {
+      if (fmult[size_t(e) * 6 + f] != 1) continue;
+      const int nrm = fs[f].axis, v = fs[f].side ? p : 0;
+      int jj = 0;
+      for (int a = 0; a < 3; ++a) {
+        const int n0 = a == 0 ? p : D1, n1 = a == 1 ? p : D1, n2 = a == 2 ? p : D1;
+        for (int i2 = 0; i2 < n2; ++i2)
+          for (int i1 = 0; i1 < n1; ++i1)
+            for (int i0 = 0; i0 < n0; ++i0, ++jj) {
+              const int idx[3] = {i0, i1, i2};
+              if (a != nrm && idx[nrm] == v) s->bmask[size_t(g[jj])] = 1;
+            }
+      }
+    }
+  }
+  finish_space(s, m, flags);
+  s->tables_open = build_open_tables(p);
+  return s;
+}
+
+// Discontinuous space: no shared dofs; the faces give the coupling.  Each interior
+// face records its two device elements, local faces and the orientation that carries
+// the "-" side's face indices to the "+" side's, found from the shared corner ids.
+Space* build_l2_space(const Mesh* mesh, int order, int flags) {
+  if (order < 1 || order > kMaxOrder)
+    throw Error(PAFEM_EUNSUPPORTED, "order must be in 1..8, got " + std::to_string(order));
+  if (mesh->dim != 3) throw Error(PAFEM_EUNSUPPORTED, "L2 spaces are built on hexahedra");
+  const Mesh& m = *mesh;
+  const int p = order, D1 = p + 1, dpe = D1 * D1 * D1;
+  const int64_t ne = m.ne;
+  if (ne * int64_t(dpe) >= (int64_t(1) << 31) - 1)
+    throw Error(PAFEM_EINVAL, "problem too large for 32-bit dof indices");
+  auto* s = new Space();
+  s->mesh = mesh;
+  s->family = kFamilyL2;
+  s->p = p;
+  s->D1 = D1;
+  s->dpe = dpe;
+  s->ne = ne;
+  s->ng = (m.geom_order == 2) ? 3 : 2;
+  s->ref_nodes.resize(D1);
+  gauss_lobatto_01(D1, s->ref_nodes.data());
+  s->ndofs = ne * dpe;
+  s->gmap.resize(size_t(ne) * dpe);
+  for (size_t i = 0; i < s->gmap.size(); ++i) s->gmap[i] = int32_t(i);
+  s->bmask.assign(size_t(s->ndofs), 0);
+
+  const auto fs = face_slots();
+  std::vector<std::array<int64_t, 4>> fkeys(size_t(ne) * 6);
+  for (int64_t e = 0; e < ne; ++e) {
+    const ElemCorners c = corners_of(m, e);
+    for (int f = 0; f < 6; ++f) {
+      std::array<int64_t, 4> k = {c.v[fs[f].c[0]], c.v[fs[f].c[1]], c.v[fs[f].c[2]],
+                                  c.v[fs[f].c[3]]};
+      std::sort(k.begin(), k.end());
+      fkeys[size_t(e) * 6 + f] = k;
+    }
+  }
+  std::vector<int64_t> frep;
+  std::vector<int32_t> fmult;
+  match_keys<4>(fkeys, m.nv, frep, fmult);
+  fkeys.clear();
+  fkeys.shrink_to_fit();
+  for (size_t i = 0; i < fmult.size(); ++i)
+    if (fmult[i] > 2) {
+      delete s;
+      throw Error(PAFEM_EINVAL, "non-conforming mesh: face shared by more than two elements "
+                                "(element " + std::to_string(i / 6) + ")");
+    }
+  finish_space(s, m, flags);
+  std::vector<int32_t> dev_of(static_cast<size_t>(ne));
+  for (int64_t k = 0; k < ne; ++k) dev_of[size_t(s->dev_order[size_t(k)])] = int32_t(k);
+  // face-local coordinates (u, v) in {0,1}^2 of corner cc of face f: bits of the two
+  // tangential axes in increasing order
+  auto uv_of = [&](int f, int cc, int& u, int& v) {
+    const int a = f / 2, b = (a == 0) ? 1 : 0, c2 = (a == 2) ? 1 : 2;
+    u = (cc >> b) & 1;
+    v = (cc >> c2) & 1;
+  };
+  struct FaceRec {
+    int32_t key, em, ep, code;
+  };
+  std::vector<FaceRec> recs;
+  std::vector<std::array<int32_t, 3>> brecs;
+  for (size_t i = 0; i < frep.size(); ++i) {
+    const int64_t e = int64_t(i) / 6;
+    const int f = int(i % 6);
+    if (fmult[i] == 1) {
+      brecs.push_back({dev_of[size_t(e)], dev_of[size_t(e)], f});
+      continue;
+    }
+    if (frep[i] == int64_t(i)) continue;  // the "-" side is the representative
+    const int64_t em = frep[i] / 6, ep = e;
+    const int fm = int(frep[i] % 6), fp = f;
+    const ElemCorners cm = corners_of(m, em), cp = corners_of(m, ep);
+    // corners of the "-" face at (s, t) = (0,0), (1,0), (0,1) -> "+" face (u, v)
+    int U[3], V[3];
+    const int st[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+    for (int k = 0; k < 3; ++k) {
+      int cc = -1;
+      for (int q = 0; q < 4; ++q) {
+        int uu, vv;
+        uv_of(fm, fs[fm].c[q], uu, vv);
+        if (uu == st[k][0] && vv == st[k][1]) cc = fs[fm].c[q];
+      }
+      const int64_t vid = cm.v[cc];
+      U[k] = V[k] = -1;
+      for (int q = 0; q < 4; ++q)
+        if (cp.v[fs[fp].c[q]] == vid) uv_of(fp, fs[fp].c[q], U[k], V[k]);
+      if (U[k] < 0) {
+        delete s;
+        throw Error(PAFEM_EINVAL, "faces of elements " + std::to_string(em) + " and " +
+                                      std::to_string(ep) + " do not share their corners");
+      }
+    }
+    const int dsu = U[1] - U[0], dsv = V[1] - V[0], dtu = U[2] - U[0], dtv = V[2] - V[0];
+    int orient;
+    if (dsu != 0)  // s runs along u, t along v
+      orient = (dsu < 0 ? 2 : 0) | (dtv < 0 ? 4 : 0);
+    else           // s runs along v, t along u
+      orient = 1 | (dtu < 0 ? 2 : 0) | (dsv < 0 ? 4 : 0);
+    const int32_t a = dev_of[size_t(em)], b = dev_of[size_t(ep)];
+    recs.push_back({std::min(a, b), a, b, fm | (fp << 3) | (orient << 6)});
+  }
+  std::sort(recs.begin(), recs.end(),
+            [](const FaceRec& x, const FaceRec& y) { return x.key < y.key || (x.key == y.key && x.ep < y.ep); });
+  s->faces.reserve(recs.size() * kFaceInts);
+  for (const auto& r : recs) {
+    s->faces.push_back(r.em);
+    s->faces.push_back(r.ep);
+    s->faces.push_back(r.code);
+  }
+  std::sort(brecs.begin(), brecs.end());
+  s->bfaces.reserve(brecs.size() * 2);
+  for (const auto& r : brecs) {
+    s->bfaces.push_back(r[1]);
+    s->bfaces.push_back(r[2]);
+  }
+  return s;
+}
+
+namespace {
+// Nedelec dofs: the physical node of each dof (open index on the Gauss-Legendre
+// points along its component's axis, closed indices on the Gauss-Lobatto points)
+void nd_dof_coords(const Space& s, double* xyz) {
+  const Mesh& m = *s.mesh;
+  const int p = s.p, D1 = s.D1, ng = s.ng;
+  std::vector<double> onodes(p), ow(p);
+  gauss_legendre_01(p, onodes.data(), ow.data());
+  std::vector<double> gn(ng), Bc(size_t(D1) * ng), Gc(size_t(D1) * ng), Bo(size_t(p) * ng),
+      Go(size_t(p) * ng);
+  for (int i = 0; i < ng; ++i) gn[i] = double(i) / (ng - 1);
+  lagrange_tables(ng, gn.data(), D1, s.ref_nodes.data(), Bc.data(), Gc.data());
+  lagrange_tables(ng, gn.data(), p, onodes.data(), Bo.data(), Go.data());
+  const int nn = ng * ng * ng;
+  std::vector<double> X(size_t(nn) * 3);
+  for (int64_t e = 0; e < s.ne; ++e) {
+    if (m.geom_order == 2) {
+      std::memcpy(X.data(), m.gnodes.data() + size_t(e) * 27 * 3, sizeof(double) * 81);
+    } else {
+      const ElemCorners c = corners_of(m, e);
+      for (int k = 0; k < 8; ++k)
+        for (int a = 0; a < 3; ++a) X[k * 3 + a] = m.xyz[size_t(c.v[k]) * 3 + a];
+    }
+    const int32_t* g = s.gmap.data() + size_t(e) * s.dpe;
+    int j = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int n0 = a == 0 ? p : D1, n1 = a == 1 ? p : D1, n2 = a == 2 ? p : D1;
+      const double* T0 = a == 0 ? Bo.data() : Bc.data();
+      const double* T1 = a == 1 ? Bo.data() : Bc.data();
+      const double* T2 = a == 2 ? Bo.data() : Bc.data();
+      for (int i2 = 0; i2 < n2; ++i2)
+        for (int i1 = 0; i1 < n1; ++i1)
+          for (int i0 = 0; i0 < n0; ++i0, ++j) {
+            double x[3] = {0, 0, 0};
+            for (int k3 = 0; k3 < ng; ++k3)
+              for (int k2 = 0; k2 < ng; ++k2)
+                for (int k1 = 0; k1 < ng; ++k1) {
+                  const double w = T0[i0 * ng + k1] * T1[i1 * ng + k2] * T2[i2 * ng + k3];
+                  const int k = k1 + ng * (k2 + ng * k3);
+                  for (int b = 0; b < 3; ++b) x[b] += w * X[k * 3 + b];
+                }
+            for (int b = 0; b < 3; ++b) xyz[size_t(g[j]) * 3 + b] = x[b];
+          }
+    }
+  }
+}
+}  // namespace
+
 void space_dof_coords(const Space& s, double* xyz) {
+  if (s.family == kFamilyND) {
+    nd_dof_coords(s, xyz);
+    return;
+  }
   const Mesh& m = *s.mesh;
   const int D1 = s.D1, ng = s.ng;
   if (s.dim == 2) {
@@ -538,6 +881,10 @@ void space_device_layout(const Space& s, size_t* off, size_t* total) {
       sizeof(uint16_t) * s.tile_slot.size(),       // 10 tile slot maps
       sizeof(float) * s.tables.size(),             // 11 1D tables in FP32
       sizeof(uint32_t) * size_t(s.ne) * owner_words(s.dpe),  // 12 owner bits
+      s.gsign.size(),                              // 13 Nedelec dof signs (device order)
+      sizeof(double) * s.tables_open.size(),       // 14 Nedelec open-basis tables
+      sizeof(int32_t) * s.faces.size(),            // 15 L2 interior faces
+      sizeof(int32_t) * s.bfaces.size(),           // 16 L2 boundary faces
   };
   for (int i = 0; i < kSpaceSegments; ++i) {
     off[i] = o;

@@ -143,4 +143,18 @@ std::vector<double> build_tables(int p, int ng) {
   return out;
 }
 
+// Value tables of the open basis of a Nedelec space (Lagrange polynomials on the p
+// Gauss-Legendre points) at the Gauss-Legendre quadrature points, for every q1d.
+std::vector<double> build_open_tables(int p) {
+  std::vector<double> nodes(p), wdummy(p);
+  gauss_legendre_01(p, nodes.data(), wdummy.data());
+  std::vector<double> out(nd_open_offset(kMaxQ1d + 1, p), 0.0);
+  for (int Q = 1; Q <= kMaxQ1d; ++Q) {
+    std::vector<double> pts(Q), wts(Q), G(size_t(Q) * p);
+    gauss_legendre_01(Q, pts.data(), wts.data());
+    lagrange_tables(p, nodes.data(), Q, pts.data(), out.data() + nd_open_offset(Q, p), G.data());
+  }
+  return out;
+}
+
 }  // namespace pafem

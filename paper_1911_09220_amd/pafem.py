@@ -17,6 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpafem.so")
 
 MASS, DIFFUSION, DIFFUSION_GEOM, CONVECTION, GRADIENT, DIVERGENCE, ELASTICITY = 0, 1, 2, 3, 4, 5, 6
+HCURL_MASS, HCURL_CURLCURL, HCURL_MAXWELL = 7, 8, 9
+DG_CONVECTION = 10
+SPACE_H1, SPACE_ND, SPACE_L2 = 0, 1, 2
 F64, F32, BF16 = 0, 1, 2
 SPACE_RENUMBER = 1
 OP_CONSTRAINED, OP_SCATTER_EVEC, OP_VECTOR3 = 1, 2, 4
@@ -67,12 +70,15 @@ class FCGResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 271  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 273  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # torch first: the library then binds to the HIP runtime torch already loaded, so
+    # both share one runtime (two runtimes in one process do not see the same device)
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I32, I64, D, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
     sig = {
@@ -90,6 +96,10 @@ def _load():
         "pafem_space_dof_coords": (I32, [P, P]),
         "pafem_space_boundary_dofs": (I32, [P, P]),
         "pafem_space_elem_dofs": (I32, [P, P]),
+        "pafem_space_create_nd": (I32, [P, I32, I32, C.POINTER(P)]),
+        "pafem_space_create_l2": (I32, [P, I32, I32, C.POINTER(P)]),
+        "pafem_space_family": (I32, [P, C.POINTER(I32)]),
+        "pafem_space_elem_signs": (I32, [P, P]),
         "pafem_space_device_bytes": (I32, [P, C.POINTER(SZ)]),
         "pafem_space_upload": (I32, [P, P, SZ, P]),
         "pafem_qdata_size": (I32, [P, I32, I32, C.POINTER(I64)]),
@@ -222,6 +232,18 @@ def pafem_space_dim(space):
 def pafem_space_create_h1(mesh, order, flags=0):
     out = C.c_void_p()
     _check(lib.pafem_space_create_h1(mesh, int(order), int(flags), C.byref(out)))
+    return out
+
+
+def pafem_space_create_nd(mesh, order, flags=0):
+    out = C.c_void_p()
+    _check(lib.pafem_space_create_nd(mesh, int(order), int(flags), C.byref(out)))
+    return out
+
+
+def pafem_space_create_l2(mesh, order, flags=0):
+    out = C.c_void_p()
+    _check(lib.pafem_space_create_l2(mesh, int(order), int(flags), C.byref(out)))
     return out
 
 
@@ -452,10 +474,19 @@ class Mesh:
 class Space:
     """H1 space of order p; uploads its device image on construction."""
 
-    def __init__(self, mesh: Mesh, order: int, renumber: bool = False, device="cuda"):
+    def __init__(self, mesh: Mesh, order: int, renumber: bool = False, device="cuda",
+                 family="h1"):
+        """family "h1" (nodal Gauss-Lobatto), "nd" (Nedelec, H(curl)) or "l2"
+        (discontinuous nodal Gauss-Lobatto)."""
         self.mesh = mesh  # keeps the mesh alive
         self.p = int(order)
-        self.handle = pafem_space_create_h1(mesh.handle, order, SPACE_RENUMBER if renumber else 0)
+        creators = {"h1": pafem_space_create_h1, "nd": pafem_space_create_nd,
+                    "l2": pafem_space_create_l2}
+        if family not in creators:
+            raise ValueError("family must be 'h1', 'nd' or 'l2'")
+        self.family = family
+        create = creators[family]
+        self.handle = create(mesh.handle, order, SPACE_RENUMBER if renumber else 0)
         self.ndofs, self.nelem, self.dofs_per_elem, self.nbdr = pafem_space_info(self.handle)
         self.dim = pafem_space_dim(self.handle)
         self.device = device
@@ -479,6 +510,12 @@ class Space:
         _check(lib.pafem_space_elem_dofs(self.handle, _np_ptr(out)))
         return out
 
+    def elem_signs(self):
+        """Orientation sign (+1 / -1) of every element's local dofs in the global basis."""
+        out = np.empty((self.nelem, self.dofs_per_elem), dtype=np.int8)
+        _check(lib.pafem_space_elem_signs(self.handle, _np_ptr(out)))
+        return out
+
     def _check_qp_array(self, a, q1d, name):
         if a is None:
             return
@@ -494,10 +531,15 @@ class Space:
         if kind == CONVECTION:
             if coeff is None or coeff.numel() != self.nelem * q1d ** 3 * 3 or not coeff.is_contiguous():
                 raise ValueError("convection needs a contiguous velocity [E][Q^3][3]")
-        elif kind == ELASTICITY:
+        elif kind == DG_CONVECTION:
+            if coeff is None or coeff.numel() != 3 or coeff.dtype != torch.float64 or not coeff.is_cuda:
+                raise ValueError("DG convection needs the constant velocity as a float64 device "
+                                 "tensor of 3 values")
+        elif kind in (ELASTICITY, HCURL_MAXWELL):
             if (coeff is None or coeff.numel() != self.nelem * q1d ** 3 * 2 or not coeff.is_contiguous()
                     or coeff.dtype != torch.float64):
-                raise ValueError("elasticity needs contiguous float64 (lambda, mu) pairs [E][Q^3][2]")
+                raise ValueError("this operator needs contiguous float64 coefficient pairs "
+                                 "[E][Q^3][2]")
         else:
             self._check_qp_array(coeff, q1d, "coeff")
         qd = torch.empty(pafem_qdata_size(self.handle, kind, q1d), dtype=torch.float64,

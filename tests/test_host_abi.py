@@ -137,3 +137,30 @@ def test_qdata_sizes_per_kind(p):
             pafem.pafem_qdata_size(S.handle, bad_kind, Q)
     with pytest.raises(pafem.PafemError):
         pafem.pafem_qdata_size(S.handle, pafem.DIFFUSION, 13)
+
+
+@pytest.mark.parametrize("case", [
+    ("lattice", 1, False), ("lattice", 2, False), ("rotated", 2, False), ("rotated", 3, True),
+    ("rotated", 4, False), ("q2", 2, False), ("q2", 3, True), ("rotated", 6, False)])
+def test_nedelec_numbering_and_signs_match_oracle(case):
+    """The library's Nedelec space against the oracle's (oracle/hcurl.py): same dofs
+    (matched by node position), same element maps, the same orientation sign of every
+    element-local dof and the same essential set."""
+    from oracle import hcurl
+    kind, p, renumber = case
+    if kind == "lattice":
+        mesh = synth.hex_lattice((3, 2, 2), 0.1, seed=3)
+    elif kind == "rotated":
+        mesh = synth.hex_lattice((2, 3, 2), 0.1, seed=4, rotate_seed=17)
+    else:
+        mesh = synth.q2_warped_lattice(2)
+    sp = pafem.Space(pafem.Mesh.from_dict(mesh), p, renumber=renumber, device=None, family="nd")
+    ref = hcurl.NDSpace(mesh, p)
+    assert sp.ndofs == ref.ndofs and sp.dofs_per_elem == 3 * p * (p + 1) ** 2
+    perm = match_by_coords(sp.dof_coords(), ref.dof_coordinates())
+    assert len(np.unique(perm)) == sp.ndofs
+    np.testing.assert_array_equal(perm[sp.elem_dofs()], ref.elem_dofs)
+    np.testing.assert_array_equal(sp.elem_signs(), ref.elem_signs.astype(np.int8))
+    bd = np.zeros(sp.ndofs, dtype=bool)
+    bd[sp.boundary_dofs()] = True
+    np.testing.assert_array_equal(bd, ref.boundary[perm])

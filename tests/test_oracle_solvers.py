@@ -46,3 +46,22 @@ def test_small_poisson_configuration_converges():
     assert res["history"][-1] <= 1e-10
     err = oracle.l2_error(s, res["x"], synth.sine_solution)
     assert err < 1e-3
+
+
+def test_host_csr_timing_variant_matches_scipy_and_python_pcg():
+    """The C/OpenMP timing variant (oracle/csr_host.c) against scipy's product and the
+    Python PCG on a constrained p = 2 diffusion problem."""
+    from oracle import csr_host
+    csr_host.build_library()
+    mesh = synth.hex_lattice(4, 0.1, seed=1)
+    sp = oracle.H1Space(mesh, 2)
+    K = oracle.assemble(sp, forms.element_stiffness(mesh, 2, 4))
+    bv = assemble_vector(sp, forms.element_load(mesh, 2, 4, synth.sine_source))
+    Kc, bc = oracle.constrain(K, bv, sp.boundary)
+    H = csr_host.HostCSR(Kc)
+    x = np.random.default_rng(0).normal(size=sp.ndofs)
+    assert np.abs(H.matvec(x) - Kc @ x).max() < 1e-13 * np.abs(Kc @ x).max()
+    xs, its, rel = H.pcg_jacobi(bc, Kc.diagonal(), tol=1e-10)
+    ref = oracle.pcg(Kc, bc, Kc.diagonal(), tol=1e-10)
+    assert rel <= 1e-10 and abs(its - ref["iters"]) <= 1
+    assert np.linalg.norm(xs - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
