@@ -202,15 +202,26 @@ class NDSpace:
         return out
 
 
+def _gram(phys, scale):
+    """sum_q scale[e, q] phys[e, q, i, :] . phys[e, q, j, :] for every element, as one
+    matrix product per element (rows i against columns j over the (q, component) pairs)."""
+    E, nq, nd, _ = phys.shape
+    out = np.empty((E, nd, nd))
+    for e in range(E):
+        F = np.transpose(phys[e], (1, 0, 2)).reshape(nd, 3 * nq)        # [nd, (q, a)]
+        out[e] = (F * np.repeat(scale[e], 3)[None, :]) @ F.T
+    return out
+
+
 def element_nd_mass(mesh, p, q1d, coeff=None):
     """Dense element H(curl) mass matrices [E, nd, nd], coefficient None, scalar or [E, Q^3]."""
     pts, w, _, J, det = _jacobians(mesh, q1d)
     N, _ = nd_reference_basis(p, pts)                                     # [Q^3, nd, 3]
     Jinv = np.linalg.inv(J)                                               # [E, Q^3, 3, 3]
     c = 1.0 if coeff is None else np.asarray(coeff)
-    scale = w[None, :] * det * c                                          # [E, Q^3]
+    scale = np.broadcast_to(w[None, :] * det * c, det.shape)              # [E, Q^3]
     phys = np.einsum("eqba,qjb->eqja", Jinv, N)                           # J^{-T} N
-    return np.einsum("eq,eqia,eqja->eij", scale, phys, phys)
+    return _gram(phys, scale)
 
 
 def element_nd_curlcurl(mesh, p, q1d, coeff=None):
@@ -218,9 +229,9 @@ def element_nd_curlcurl(mesh, p, q1d, coeff=None):
     pts, w, _, J, det = _jacobians(mesh, q1d)
     _, C = nd_reference_basis(p, pts)
     c = 1.0 if coeff is None else np.asarray(coeff)
-    scale = w[None, :] * c / det
+    scale = np.broadcast_to(w[None, :] * c / det, det.shape)
     phys = np.einsum("eqab,qjb->eqja", J, C)                              # J C
-    return np.einsum("eq,eqia,eqja->eij", scale, phys, phys)
+    return _gram(phys, scale)
 
 
 def assemble_nd(space: NDSpace, Ae):
