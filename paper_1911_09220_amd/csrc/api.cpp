@@ -298,7 +298,8 @@ pafem_status pafem_space_dof_coords(pafem_space space, double* xyz) {
 
 pafem_status pafem_space_boundary_dofs(pafem_space space, int32_t* idx) {
   return guarded([&] {
-    require(space && space->s && idx, PAFEM_EINVAL, "null pointer argument");
+    require(space && space->s, PAFEM_EINVAL, "null pointer argument");
+    require(idx || space->s->bdr.empty(), PAFEM_EINVAL, "null pointer argument");
     std::copy(space->s->bdr.begin(), space->s->bdr.end(), idx);
   });
 }
