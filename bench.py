@@ -358,54 +358,57 @@ def bench_dg(P, torch, orders, target, steps=10, warmup=2):
     return out
 
 
-def bench_mixed(P, torch, n=45, p=6, tol=1e-8):
-    """Quadratic warped mesh, p = 6: FP64 Jacobi-PCG vs FP32/BF16-inner refinement."""
+def bench_mixed(P, torch, n=45, p=6, tol=1e-8, tol_hi=1e-10):
+    """Quadratic warped mesh: FP64 Jacobi-PCG vs FP32/BF16-inner refinement, at tol and at
+    the refinement configuration's own tol_hi; every solution's nodal error against the
+    exact solution sin(pi x) sin(pi y) sin(pi z) beside its difference to FP64 PCG."""
+    import numpy as np
+
     import synth
     mesh = synth.q2_warped_lattice(n, 0.05)
     S = P.Space(P.Mesh.from_dict(mesh), p)
     del mesh
+    u_exact = torch.as_tensor(synth.sine_solution(S.dof_coords()), device="cuda")
     qd = S.qdata(P.DIFFUSION)
     hi = P.Operator(S, P.DIFFUSION, qd)
     b = S.linear_form(P.SOURCE_SINE)
     diag = hi.diagonal()
-    out = {"ndofs": S.ndofs, "elements": S.nelem, "order": p, "tol": tol}
-    # the refinement configuration's own tolerance, 1e-10: FP64 PCG against FP32 refinement
-    x10, i10 = hi.pcg(b, diag=diag, rel_tol=1e-10, max_iter=20000, history=False)
-    lo32 = P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, P.F32), qdata_dtype=P.F32)
-    xr, ir = hi.ir_solve(lo32, b, diag=diag, rel_tol=1e-10, inner_rel_tol=1e-2, max_outer=40,
-                         max_inner=20000, keep_direction=True)
-    out["tol_1e-10"] = {
-        "fp64_pcg": {"seconds": round(i10["seconds"], 4), "iters": i10["iters"],
-                     "true_rel_res": i10["true_rel_res"]},
-        "ir_fp32": {"seconds": round(ir["seconds"], 4), "outer": ir["outer"],
-                    "inner_iters": ir["inner_total"], "rel_res": ir["rel_res"],
-                    "solution_rel_diff_vs_fp64_pcg": float((xr - x10).norm() / x10.norm()),
-                    "speedup_vs_fp64": round(i10["seconds"] / ir["seconds"], 3)}}
-    log(f"mixed 1e-10: FP64 PCG {i10['iters']} its {i10['seconds']:.3f} s, FP32 IR "
-        f"{ir['inner_total']} inner {ir['seconds']:.3f} s")
-    del x10, xr, lo32
-    x64, i64 = hi.pcg(b, diag=diag, rel_tol=tol, max_iter=20000, history=False)
-    out["fp64_pcg"] = {"seconds": round(i64["seconds"], 4), "iters": i64["iters"],
-                       "true_rel_res": i64["true_rel_res"]}
-    log(f"mixed: FP64 PCG {i64['iters']} its {i64['seconds']:.3f} s")
-    for name, dt in (("fp32", P.F32), ("bf16", P.BF16)):
-        lo = P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, dt), qdata_dtype=dt)
-        # reduced-precision apply error on one vector, against the FP64 apply
-        v = b / b.norm()
-        ea = float((lo.apply(v.float()).double() - hi.apply(v)).norm() / hi.apply(v).norm())
-        for mode, keep in (("", True), ("_restart", False)):
-            x, info = hi.ir_solve(lo, b, diag=diag, rel_tol=tol, inner_rel_tol=1e-2, max_outer=40,
-                                  max_inner=20000, keep_direction=keep)
-            err = float((x - x64).norm() / x64.norm())
-            out[f"ir_{name}{mode}"] = {
-                "seconds": round(info["seconds"], 4), "outer": info["outer"],
-                "inner_iters": info["inner_total"], "rel_res": info["rel_res"],
-                "solution_rel_diff_vs_fp64_pcg": err, "apply_rel_err": ea,
-                "speedup_vs_fp64": round(i64["seconds"] / info["seconds"], 3)}
-            log(f"mixed: IR {name}{mode} {info['outer']} outer {info['inner_total']} inner "
-                f"{info['seconds']:.3f} s")
-            del x
-        del lo
+    lows = {"fp32": P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, P.F32), qdata_dtype=P.F32),
+            "bf16": P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, P.BF16), qdata_dtype=P.BF16)}
+    v = b / b.norm()
+    hv = hi.apply(v)
+    apply_err = {k: float((lo.apply(v.float()).double() - hv).norm() / hv.norm())
+                 for k, lo in lows.items()}
+    out = {"ndofs": S.ndofs, "elements": S.nelem, "order": p, "mesh": n,
+           "apply_rel_err_vs_fp64_apply": apply_err}
+
+    def nodal_err(x):
+        return float((x - u_exact).abs().max())
+
+    for t, key in ((tol, "tol_%.0e" % tol), (tol_hi, "tol_%.0e" % tol_hi)):
+        x64, i64 = hi.pcg(b, diag=diag, rel_tol=t, max_iter=40000, history=False)
+        res = {"fp64_pcg": {"seconds": round(i64["seconds"], 4), "iters": i64["iters"],
+                            "true_rel_res": i64["true_rel_res"],
+                            "max_nodal_err_vs_exact": nodal_err(x64)}}
+        log(f"mixed p={p} {key}: FP64 PCG {i64['iters']} its {i64['seconds']:.3f} s")
+        for name, lo in lows.items():
+            modes = (("", True), ("_restart", False)) if t == tol else (("", True),)
+            for mode, keep in modes:
+                x, info = hi.ir_solve(lo, b, diag=diag, rel_tol=t, inner_rel_tol=1e-2,
+                                      max_outer=60, max_inner=40000, keep_direction=keep)
+                res[f"ir_{name}{mode}"] = {
+                    "seconds": round(info["seconds"], 4), "outer": info["outer"],
+                    "inner_iters": info["inner_total"], "rel_res": info["rel_res"],
+                    "solution_rel_diff_vs_fp64_pcg": float((x - x64).norm() / x64.norm()),
+                    "max_nodal_err_vs_exact": nodal_err(x),
+                    "speedup_vs_fp64": round(i64["seconds"] / info["seconds"], 3)}
+                log(f"mixed p={p} {key}: IR {name}{mode} {info['outer']} outer "
+                    f"{info['inner_total']} inner {info['seconds']:.3f} s")
+                del x
+        out[key] = res
+        del x64
+    del lows, hi, qd
+    torch.cuda.empty_cache()
     return out
 
 
@@ -564,6 +567,8 @@ def bench_batched(P, torch, nrhs=16, reps=20, tune_cache=None):
         y32.append(torch.empty_like(x32[-1]))
         total += S.ndofs
     out["total_dofs"] = total
+    flops = sum(algorithmic_flops("diffusion", o.space.p, o.space.nelem) for o in ops64) * nrhs
+    out["algorithmic_flops"] = flops
     for name, ops, xs, ys in (("f64", ops64, x64, y64), ("f32", ops32, x32, y32)):
         B = P.Batch(ops, nrhs)
         res = {}
@@ -580,13 +585,19 @@ def bench_batched(P, torch, nrhs=16, reps=20, tune_cache=None):
             torch.cuda.synchronize()
             t = a.elapsed_time(b) / reps / 1e3
             res[mode] = {"ms": round(t * 1e3, 4), "gdofs_rhs": round(total * nrhs / t / 1e9, 3)}
-        res["tiles"] = B.describe()["groups"]
+        desc = B.describe()
+        res["tiles"] = desc["groups"]
+        # per order and candidate (5 = FP64 matrix cores), ms of that order's launch
+        res["tuning_ms"] = desc["tuning"]
+        peak = FP64_PEAK_TFLOPS if name == "f64" else 157.3
+        res["vector_or_matrix_peak_frac"] = round(
+            flops / (res["autotuned"]["ms"] / 1e3) / 1e12 / peak, 4)
         out[name] = res
         log(f"batched: {name} {res['default']['ms']} ms default, {res['autotuned']['ms']} ms tuned")
     return out
 
 
-def bench_learned(P, torch, n=64, p=3, fields=20, heldout=3, steps=1500, tol=1e-8,
+def bench_learned(P, torch, n=64, p=3, fields=20, heldout=10, steps=1500, tol=1e-8,
                   stops=(2, 5, 10, 20, 40, 80, 160, 320, 640)):
     """64^3 p = 3 lattice, GRF lognormal coefficient (contrast 1e3, correlation 0.1): the
     learned element preconditioner is trained on pairs from Jacobi-PCG runs on seeded
@@ -631,11 +642,30 @@ def bench_learned(P, torch, n=64, p=3, fields=20, heldout=3, steps=1500, tol=1e-
                      log_every=max(1, steps // 5), log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
+    # ablation: the same basis training with the element features zeroed, so the
+    # network's output (the element weights) is one constant vector for every element
+    ablation = None
+    if not compact:
+        zero = torch.zeros_like(samples[0][1])
+        abl_samples = [(o, zero, d, r, e) for (o, _, d, r, e) in samples]
+        net0 = P.Net(p, hidden=64, max_rows=E, max_train_rows=E)
+        net0.set_params(L.initial_params(net0, seed=23))
+        t2 = time.perf_counter()
+        losses0 = L.train(net0, abl_samples, steps=steps, lr=2e-3, decay_every=max(1, steps // 3))
+        torch.cuda.synchronize()
+        ablation = {"net": net0, "zero": zero, "train_seconds": round(time.perf_counter() - t2, 2),
+                    "loss_last": float(losses0[-50:].mean())}
+        del abl_samples
     del samples
     out = {"order": p, "mesh": n, "ndofs": S.ndofs, "train_fields": fields,
            "pair_stops": list(stops), "train_steps": steps, "pair_seconds": round(t_pairs, 2),
            "train_seconds": round(t_train, 2), "loss_first": float(losses[:50].mean()),
            "loss_last": float(losses[-50:].mean()), "tol": tol, "heldout": []}
+    if ablation is not None:
+        out["constant_weights"] = {
+            "what": "same basis training with the element features zeroed (one weight vector "
+                    "for every element: the network adds nothing)",
+            "train_seconds": ablation["train_seconds"], "loss_last": ablation["loss_last"]}
     for f in range(heldout):
         op, diag, feats = field(2000 + f)
         _, ij = op.pcg(b, diag=diag, rel_tol=tol, max_iter=20000, history=False)
@@ -650,6 +680,14 @@ def bench_learned(P, torch, n=64, p=3, fields=20, heldout=3, steps=1500, tol=1e-
                             "true_rel_res": il["true_rel_res"], "fell_back": il["fell_back"]},
             "speedup": round(ij["seconds"] / il["seconds"], 3)})
         log(f"learned: held-out field {f}: FCG {il['iters']} its {il['seconds']:.3f} s")
+        if ablation is not None:
+            _, ia = P.fcg_solve(op, b, diag, net=ablation["net"], feats=ablation["zero"],
+                                rel_tol=tol, max_iter=20000, history=False)
+            out["heldout"][-1]["constant_weights_fcg"] = {
+                "seconds": round(ia["seconds"], 4), "iters": ia["iters"],
+                "true_rel_res": ia["true_rel_res"], "fell_back": ia["fell_back"]}
+            log(f"learned: held-out field {f}: constant-weight FCG {ia['iters']} its "
+                f"{ia['seconds']:.3f} s")
         del op, diag, feats
     return out
 
@@ -853,6 +891,8 @@ def main():
     if "mixed" in forms:
         log("mixed precision")
         out["mixed_precision"] = bench_mixed(P, torch)
+        # the same refinement where the apply is bound by HBM: p = 3, ~2e7 dofs
+        out["mixed_precision_p3"] = bench_mixed(P, torch, n=90, p=3)
     if "batched" in forms:
         log("batched")
         out["batched"] = bench_batched(P, torch)

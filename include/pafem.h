@@ -466,7 +466,12 @@ pafem_status pafem_batch_apply(pafem_batch batch, const void* const* x, void* co
 pafem_status pafem_batch_autotune(pafem_batch batch, const void* const* x, void* const* y,
                                   const char* cache_path, int32_t reps, void* stream);
 
-/* Force the tile candidate (0..4, -1 = default) for the meshes of one order. */
+/* Force the tile candidate (-1 = default) for the meshes of one order.  0..4: vector-unit
+ * tiles of 4, 8, 16, 2x8 (two elements) and 2 right-hand sides; 5: FP64 matrix cores
+ * (v_mfma_f64_16x16x4f64, the sum-factorization contractions as dense products over 16
+ * right-hand sides; one element per workgroup), FP64 batches of orders 1..4 with nrhs a
+ * multiple of 16 ("High-Order Partial Assembly").  EINVAL for a candidate the order,
+ * dtype or nrhs does not allow. */
 pafem_status pafem_batch_set_tile(pafem_batch batch, int32_t order, int32_t candidate);
 
 /* JSON description of the groups, chosen tiles and tuning timings into buf. */

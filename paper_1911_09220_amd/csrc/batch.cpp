@@ -25,9 +25,10 @@ void hipc(hipError_t err, const char* what) {
 }
 
 // largest right-hand-side chunk first: the default before tuning
-bool candidate_ok(int p, int cand, int nrhs) {
+bool candidate_ok(int p, int cand, int nrhs, int vdtype) {
   if (cand < 0 || cand >= kBatchCandidates) return false;
   if (nrhs % batch_tile_rhs(cand)) return false;
+  if (cand == kBatchMfmaCandidate) return vdtype == PAFEM_F64 && p <= 4;
   // tiles built per order (k_batch.hip): larger ones would exceed the registers
   if (cand == 1 && p > 5) return false;
   if (cand == 2 && p > 3) return false;
@@ -35,10 +36,10 @@ bool candidate_ok(int p, int cand, int nrhs) {
   return true;
 }
 
-int default_candidate(int p, int nrhs) {
+int default_candidate(int p, int nrhs, int vdtype) {
   const int order_pref[] = {2, 1, 0, 4};
   for (int c : order_pref)
-    if (candidate_ok(p, c, nrhs)) return c;
+    if (candidate_ok(p, c, nrhs, vdtype)) return c;
   return -1;
 }
 
@@ -91,7 +92,7 @@ Batch::Batch(const std::vector<const Op*>& ops_in, int nrhs_in, void* work, size
       g.p = p;
       g.first = int(k);
       g.count = 0;
-      g.cand = default_candidate(p, nrhs);
+      g.cand = default_candidate(p, nrhs, vdtype);
       if (g.cand < 0) throw Error(PAFEM_EINVAL, "no tile shape divides nrhs");
       groups.push_back(g);
     }
@@ -203,8 +204,8 @@ void Batch::apply(const void* const* x, void* const* y, hipStream_t st) {
 void Batch::set_candidate(int p, int cand) {
   for (Group& g : groups)
     if (g.p == p) {
-      const int c = cand < 0 ? default_candidate(p, nrhs) : cand;
-      if (!candidate_ok(p, c, nrhs))
+      const int c = cand < 0 ? default_candidate(p, nrhs, vdtype) : cand;
+      if (!candidate_ok(p, c, nrhs, vdtype))
         throw Error(PAFEM_EINVAL, "tile candidate " + std::to_string(cand) +
                                       " not available for order " + std::to_string(p));
       g.cand = c;
@@ -230,7 +231,7 @@ void Batch::autotune(const void* const* x, void* const* y, const char* cache_pat
   for (Group& g : groups) {
     const auto key = std::make_tuple(arch, kind, vdtype, nrhs, g.p);
     const auto hit = cache.find(key);
-    if (hit != cache.end() && candidate_ok(g.p, hit->second, nrhs)) {
+    if (hit != cache.end() && candidate_ok(g.p, hit->second, nrhs, vdtype)) {
       g.cand = hit->second;
       continue;
     }
@@ -240,7 +241,7 @@ void Batch::autotune(const void* const* x, void* const* y, const char* cache_pat
     hipc(hipEventCreate(&a), "event");
     hipc(hipEventCreate(&b), "event");
     for (int c = 0; c < kBatchCandidates; ++c) {
-      if (!candidate_ok(g.p, c, nrhs)) continue;
+      if (!candidate_ok(g.p, c, nrhs, vdtype)) continue;
       g.cand = c;
       build_descriptors(x, y);
       upload(st);

@@ -21,7 +21,10 @@ struct BatchMesh {
   int32_t constrained;
 };
 
-constexpr int kBatchCandidates = 5;
+// candidates 0..4: vector-unit tiles (k_batch.hip); 5: FP64 matrix cores, one element x
+// 16 right-hand sides per workgroup (k_batch_mfma.hip), orders 1..4
+constexpr int kBatchCandidates = 6;
+constexpr int kBatchMfmaCandidate = 5;
 int batch_tile_elems(int cand);
 int batch_tile_rhs(int cand);
 // Launches the multi-rhs apply of one order group; false if the (order,
@@ -31,5 +34,8 @@ bool launch_batch_apply(int p, int cand, int vdtype, int qdtype, int kind,
                         const BatchMesh* meshes, int nmesh, int nblocks, const void* tabB,
                         int nrhs, hipStream_t st);
 void launch_batch_init(int vdtype, const BatchMesh* meshes, int nmesh, int nrhs, hipStream_t st);
+// the matrix-core variant (FP64, orders 1..4, nrhs a multiple of 16); false otherwise
+bool launch_batch_apply_mfma(int p, int kind, const BatchMesh* meshes, int nmesh, int nblocks,
+                             const double* tabB, int nrhs, hipStream_t st);
 
 }  // namespace pafem

@@ -311,6 +311,7 @@ int batch_tile_rhs(int cand) {
     case 2: return 16;
     case 3: return 8;
     case 4: return 2;
+    case kBatchMfmaCandidate: return 16;
     default: return 0;
   }
 }
@@ -318,6 +319,11 @@ int batch_tile_rhs(int cand) {
 bool launch_batch_apply(int p, int cand, int vdtype, int qdtype, int kind,
                         const BatchMesh* meshes, int nmesh, int nblocks, const void* tab,
                         int nrhs, hipStream_t st) {
+  if (cand == kBatchMfmaCandidate) {
+    if (vdtype != PAFEM_F64 || qdtype != PAFEM_F64 || nrhs % 16) return false;
+    return launch_batch_apply_mfma(p, kind, meshes, nmesh, nblocks,
+                                   static_cast<const double*>(tab), nrhs, st);
+  }
   bool ok = false;
 #define PAFEM_BATCH_ORDER(PP)                                                                   \
   case PP:                                                                                      \

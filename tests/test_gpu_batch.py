@@ -23,18 +23,18 @@ from paper_1911_09220_amd import pafem as P  # noqa: E402
 NRHS = 16
 
 
-def _problem(shapes_orders, dtype=P.F64, seed=0):
+def _problem(shapes_orders, dtype=P.F64, seed=0, kind=P.DIFFUSION):
     ops64, ops, xs, ys, spaces = [], [], [], [], []
     for i, (shape, p) in enumerate(shapes_orders):
         mesh = synth.hex_lattice(shape, 0.05, seed=seed + i, rotate_seed=seed + 100 + i)
         S = P.Space(P.Mesh.from_dict(mesh), p, renumber=bool(i % 2))
-        qd = S.qdata(P.DIFFUSION)
-        op64 = P.Operator(S, P.DIFFUSION, qd)
+        qd = S.qdata(kind)
+        op64 = P.Operator(S, kind, qd)
         ops64.append(op64)
         if dtype == P.F64:
             ops.append(op64)
         else:
-            ops.append(P.Operator(S, P.DIFFUSION, P.lowered_qdata(qd, dtype), qdata_dtype=dtype))
+            ops.append(P.Operator(S, kind, P.lowered_qdata(qd, dtype), qdata_dtype=dtype))
         g = torch.Generator(device="cuda")
         g.manual_seed(1000 + i)
         x = torch.randn(S.ndofs, NRHS, dtype=torch.float64, device="cuda", generator=g)
@@ -73,7 +73,7 @@ def test_every_tile_candidate_agrees():
     B.apply(xs, ys)
     ref = [y.clone() for y in ys]
     orders = sorted({o.space.p for o in ops})
-    for cand in range(5):
+    for cand in range(6):
         for p in orders:
             try:
                 B.set_tile(p, cand)
@@ -82,6 +82,38 @@ def test_every_tile_candidate_agrees():
         B.apply(xs, ys)
         for a, b in zip(ys, ref):
             assert float((a - b).norm() / b.norm()) <= 1e-13
+
+
+MFMA = 5  # the FP64 matrix-core candidate (orders 1..4, 16 right-hand sides per workgroup)
+
+
+@pytest.mark.parametrize("kind", [P.DIFFUSION, P.MASS])
+def test_matrix_core_candidate_matches_single_applies(kind):
+    """Every column of the matrix-core batch against the single FP64 apply of its mesh,
+    orders 1..4, several element counts, constrained operators."""
+    shapes = [s for s in SHAPES if s[1] <= 4]
+    ops64, ops, xs, ys, _ = _problem(shapes, seed=3, kind=kind)
+    B = P.Batch(ops, NRHS)
+    for p in sorted({o.space.p for o in ops}):
+        B.set_tile(p, MFMA)
+    assert all(t["candidate"] == MFMA for t in B.describe()["groups"])
+    B.apply(xs, ys)
+    torch.cuda.synchronize()
+    for op64, x, y in zip(ops64, xs, ys):
+        ref = _single_columns(op64, x)
+        err = parity_err(y.cpu().numpy(), ref.cpu().numpy())
+        assert err <= 1e-12, (op64.space.p, err)
+
+
+def test_matrix_core_candidate_refused_where_not_built():
+    ops64, ops, xs, ys, _ = _problem([((2, 2, 2), 5)])
+    B = P.Batch(ops, NRHS)
+    with pytest.raises(P.PafemError):
+        B.set_tile(5, MFMA)
+    ops64, ops, xs, ys, _ = _problem([((2, 2, 2), 3)], dtype=P.F32)
+    B = P.Batch(ops, NRHS)
+    with pytest.raises(P.PafemError):
+        B.set_tile(3, MFMA)
 
 
 def test_graph_replays_match_eager(tmp_path):

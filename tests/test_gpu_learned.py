@@ -213,6 +213,17 @@ def test_training_gains_over_jacobi():
           f"learned FCG {il['iters']} its")
     assert il["converged"] and not il["fell_back"] and il["true_rel_res"] < 1e-7
     assert il["iters"] <= 0.85 * ij["iters"]
+    # ablation: the same training with the element features zeroed (one constant weight
+    # vector for every element); the features must not make the preconditioner worse
+    zero = torch.zeros_like(feats)
+    net0 = P.Net(p, hidden=64, max_rows=E, max_train_rows=E)
+    net0.set_params(L.initial_params(net0, seed=12))
+    L.train(net0, [(o, torch.zeros_like(f), d, r, e) for (o, f, d, r, e) in samples],
+            steps=800, lr=2e-3, decay_every=300)
+    _, ia = P.fcg_solve(op, b, diag, net=net0, feats=zero, rel_tol=1e-8)
+    print(f"constant-weight ablation: {ia['iters']} its")
+    assert ia["converged"] and not ia["fell_back"]
+    assert il["iters"] <= 1.1 * ia["iters"]
     ref = OracleProblem(mesh, p, coeff=kappa.cpu().numpy())
     perm = match_by_coords(S.dof_coords(), ref.coords)
     xd = spla.spsolve(ref.Kc.tocsc(), ref.load(synth.sine_source))
