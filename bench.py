@@ -144,6 +144,8 @@ def setup_problem(P, torch, p, target, scatter):
         **extra,
         "p": p, "n": n, "space": S, "ne": S.nelem, "ndofs": S.ndofs,
         "diff": P.Operator(S, P.DIFFUSION, qd, scatter=scatter),
+        # the deterministic scatter (element vectors, then a fixed-order gather per dof)
+        "diff_evec": P.Operator(S, P.DIFFUSION, qd, scatter="evec"),
         "mass": P.Operator(S, P.MASS, qm, scatter=scatter),
         "geom": P.Operator(S, P.DIFFUSION_GEOM, qg, scatter=scatter),
         "conv": P.Operator(S, P.CONVECTION, qc, scatter=scatter),
@@ -668,6 +670,12 @@ def bench_learned(P, torch, n=64, p=3, fields=20, heldout=10, steps=1500, tol=1e
             "train_seconds": ablation["train_seconds"], "loss_last": ablation["loss_last"]}
     for f in range(heldout):
         op, diag, feats = field(2000 + f)
+        if f == 0:
+            # spread of the network's inputs (the 8 octant log-ratios) over the elements:
+            # near zero means the coefficient is nearly constant inside an element
+            lr = feats[:, 1:9]
+            out["feature_spread"] = {"octant_log_ratio_std": float(lr.std()),
+                                     "octant_log_ratio_max_abs": float(lr.abs().max())}
         _, ij = op.pcg(b, diag=diag, rel_tol=tol, max_iter=20000, history=False)
         log(f"learned: held-out field {f}: Jacobi-PCG {ij['iters']} its {ij['seconds']:.3f} s")
         _, il = P.fcg_solve(op, b, diag, net=net, feats=feats, rel_tol=tol, max_iter=20000,
@@ -765,6 +773,13 @@ def main():
             by = algorithmic_bytes("mass", pr["p"], pr["ne"], pr["ndofs"])
             mass[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
                                   "hbm_frac": round(by / t / 1e9 / HBM_PEAK_GBS, 4)}
+
+    evec = {}
+    if not args.no_mass:
+        eper, _ = time_applies(torch, probs, "diff_evec", max(3, args.steps // 2), 1)
+        for pr, t, ta in zip(probs, eper, per):
+            evec[str(pr["p"])] = {"ms": round(t * 1e3, 4), "gdofs": round(pr["ndofs"] / t / 1e9, 3),
+                                  "time_vs_atomic": round(t / ta, 3)}
 
     geom = {}
     if not args.no_geom:
@@ -869,7 +884,8 @@ def main():
                                f"dofs for p={args.orders}, 5% vertex jitter, lognormal kappa "
                                f"(sigma=1) per quadrature point, q1d=p+2, Dirichlet boundary",
                    "orders": orders, "scatter": args.scatter, "per_p": per_p,
-                   "mass_apply": mass, "recomputed_geometry_apply": geom,
+                   "mass_apply": mass, "deterministic_scatter_apply": evec,
+                   "recomputed_geometry_apply": geom,
                    "convection_apply": conv, "gradient_apply": grad,
                    "divergence_apply": div, "elasticity_apply": elas,
                    "vector_diffusion_apply": vec3, "setup_seconds": round(t_setup, 1),

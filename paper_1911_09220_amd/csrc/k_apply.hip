@@ -13,7 +13,9 @@
 // intermediate value passes through LDS once.  Per element:
 //   G    gather the tile's unique dofs once into LDS (essential dofs read as 0 when
 //        constrained); a thread owning the x-line (dz, dy) picks its D values
-//        through the tile slot map
+//        through the tile slot map.  The index lists are read once per apply and
+//        loaded non-temporally; at p <= 4 every thread keeps the dof ids it gathered
+//        for the scatter instead of reading the list again
 //   B    x-lines (dz, dy) -> y-lines (dz, qx) -> z-lines (qy, qx)
 //   D    pointwise on the z-line: 1 value (mass) or a symmetric 3x3 (diffusion) per
 //        point, streamed from HBM with non-temporal loads issued before the gather
@@ -161,12 +163,17 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   if (DIVV) load_dq(3 * comp);  // w kappa adj(J)[b][comp], b = 0..2
   // G: gather the tile's unique dofs; four per thread per step keep several
   // gathers in flight
+  // at p <= 4 a tile's unique dofs fit one pass of four per thread: the dof ids stay
+  // in registers for the scatter
+  constexpr bool ONEPASS = DDD <= 4 * QQ;
+  int gkeep[4] = {0, 0, 0, 0};
   for (int s0 = tid; s0 < nu; s0 += 4 * NE * QQ) {
     int gg[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int s = s0 + k * NE * QQ;
-      gg[k] = s < nu ? tile_dofs[u0 + s] : 0;
+      gg[k] = s < nu ? __builtin_nontemporal_load(tile_dofs + u0 + s) : 0;
+      gkeep[k] = gg[k];
     }
     TC xv[4];
 #pragma unroll
@@ -185,7 +192,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   if (xline) {
     const uint16_t* sl = tile_slot + size_t(e) * DDD + r * D;
 #pragma unroll
-    for (int dx = 0; dx < D; ++dx) slot[dx] = sl[dx];
+    for (int dx = 0; dx < D; ++dx) slot[dx] = __builtin_nontemporal_load(sl + dx);
   }
   __syncthreads();
 
@@ -530,14 +537,27 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   if (EVEC) return;
   __syncthreads();
   // G^t: one global atomic per unique dof of the tile
-#pragma unroll 4
-  for (int s = tid; s < nu; s += NE * QQ) {
-    const int g = tile_dofs[u0 + s];
-    if (!(constrained && g < 0))
+  if constexpr (ONEPASS && NV == 1) {
 #pragma unroll
-      for (int oc = 0; oc < NOUT; ++oc)
-        unsafeAtomicAdd(&y[(DIVV ? 0 : GRADC ? GC : comp + oc) * ystride + (g < 0 ? ~g : g)],
-                        TV(sX[oc * NE * DDD + s]));
+    for (int k = 0; k < 4; ++k) {
+      const int s = tid + k * NE * QQ;
+      const int g = gkeep[k];
+      if (s < nu && !(constrained && g < 0))
+#pragma unroll
+        for (int oc = 0; oc < NOUT; ++oc)
+          unsafeAtomicAdd(&y[(DIVV ? 0 : GRADC ? GC : comp + oc) * ystride + (g < 0 ? ~g : g)],
+                          TV(sX[oc * NE * DDD + s]));
+    }
+  } else {
+#pragma unroll 4
+    for (int s = tid; s < nu; s += NE * QQ) {
+      const int g = tile_dofs[u0 + s];
+      if (!(constrained && g < 0))
+#pragma unroll
+        for (int oc = 0; oc < NOUT; ++oc)
+          unsafeAtomicAdd(&y[(DIVV ? 0 : GRADC ? GC : comp + oc) * ystride + (g < 0 ? ~g : g)],
+                          TV(sX[oc * NE * DDD + s]));
+    }
   }
   if (NV > 1) __syncthreads();  // sX is gathered again for the next component
   }
