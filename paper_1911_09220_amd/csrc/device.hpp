@@ -19,6 +19,25 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return xcd * base + min(xcd, rem) + idx;
 }
 
+// p itself, but opaque to the optimizer: loads through the result are issued after
+// this point and are not merged with loads through other copies of p.  Applied per loop
+// iteration to a uniform table pointer, it keeps the iteration's table entries in
+// scalar registers for that iteration only, instead of every entry of an unrolled loop
+// nest being loaded up front and spilled (p >= 6 tables exceed the scalar registers).
+// The result points into the constant address space (read-only for the kernel's
+// lifetime), so the loads stay scalar.
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ const_ptr<T> opaque_ptr(const T* p) {
+  // the address is uniform; readfirstlane states so where the compiler cannot see it
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+  uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+  __asm__ volatile("" : "+s"(lo), "+s"(hi));
+  return reinterpret_cast<const_ptr<T>>((uint64_t(hi) << 32) | lo);
+}
+
 // bfloat16 storage as raw 16-bit patterns (round-to-nearest-even on conversion).
 struct bf16 {
   uint16_t bits;

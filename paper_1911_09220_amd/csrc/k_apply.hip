@@ -46,7 +46,7 @@ constexpr int elems_per_block() {
 }
 
 template <int P, int Q, int KIND, bool EVEC, bool DOT, typename TV, typename TD, typename TC>
-__global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DIFFUSION ? 1 : sizeof(TC) == 4 ? (P == 6 ? 5 : 1) : P == 4 ? 4 : 1)
+__global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DIFFUSION ? 1 : sizeof(TC) == 4 ? (P == 6 ? 5 : 1) : P == 4 ? 4 : P >= 6 ? 3 : 1)
     pa_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
                     const uint16_t* __restrict__ tile_slot, const TC* __restrict__ tabB,
                     const TC* __restrict__ tabG, const TD* __restrict__ qd,
@@ -98,11 +98,23 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   constexpr int LC = D | 1;
   constexpr int ELEM = NCC * QQ * LC;
   static_assert(NA * D <= NCC * Q, "x-line outputs must fit the element region");
+  // XTAIL (scalar FP64 diffusion, p >= 6): the rows (c*Q + qy) of the element region
+  // from NA*D on are dead from the back y-lines until the forward y-lines, while the
+  // tile's unique-dof array is live exactly then (gather to forward x-lines, back
+  // x-lines to the scatter).  Those rows of all elements of the tile are one
+  // contiguous block after the leading rows, and the unique-dof array lives in it:
+  // 11-12 KB less LDS per tile, three tiles per CU instead of two (one more barrier,
+  // to clear the accumulators once the back y-lines have read the rows).
+  constexpr bool XTAIL = DIFF && NV == 1 && P >= 6 && sizeof(TC) == 8;
+  constexpr int HR = XTAIL ? NA * D : NCC * Q;  // leading rows of an element
+  constexpr int HEAD = HR * Q * LC, TAIL = ELEM - HEAD;
+  static_assert(!XTAIL || NE * TAIL >= NE * DDD, "the unique dofs must fit the region tails");
 
   __shared__ TC sW[NE * ELEM];
   // The tile's unique dofs: x gathered once per unique dof, later the element
   // outputs summed per unique dof before one global atomic each.
-  __shared__ TC sX[NOUT * NE * DDD];
+  __shared__ TC sXa[XTAIL ? 1 : NOUT * NE * DDD];
+  TC* const sX = XTAIL ? sW + NE * HEAD : sXa;
 
   const int tid = threadIdx.x;
   const int el = tid / QQ;
@@ -112,26 +124,50 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   const bool act = e < ne;
   const int u0 = tile_off[tile];
   const int nu = tile_off[tile + 1] - u0;
-  TC* const W = sW + el * ELEM;
+  TC* const W = sW + el * HEAD;
+  TC* const WT = sW + NE * HEAD + el * TAIL;
   // entry (c, qy, qx, dz) of the element region; the x-line outputs (a, dz, dy, qx)
   // live at c*Q + qy = a*D + dy
-  auto at = [&](int c, int qy, int qx, int dz) -> TC& { return W[((c * Q + qy) * Q + qx) * LC + dz]; };
-  auto bB = [&](int q, int d) -> TC { return tabB[q * D + d]; };
-  auto bG = [&](int q, int d) -> TC { return tabG[q * D + d]; };
+  auto at = [&](int c, int qy, int qx, int dz) -> TC& {
+    const int row = c * Q + qy;
+    if constexpr (XTAIL)
+      return row < HR ? W[(row * Q + qx) * LC + dz] : WT[((row - HR) * Q + qx) * LC + dz];
+    else
+      return W[(row * Q + qx) * LC + dz];
+  };
+  // Row q (forward stages) or column d (back stages) of a 1D table.  At p = 8 loaded per
+  // loop iteration (opaque_ptr): the 180 FP64 table entries outgrow the scalar registers
+  // and the compiler, loading them all up front, spilled them through VGPR lanes (1674
+  // lane reads per wave; 0.483 -> 0.363 ms at 1e7 dofs with the changes below).  At
+  // p = 6, 7 its up-front loads spill far less and are 2-4% faster than the per-iteration ones.
+  constexpr bool OPQ = P >= 8;
+  auto tab = [&](const TC* t) {
+    if constexpr (OPQ)
+      return opaque_ptr(t);
+    else
+      return t;
+  };
+  auto rowB = [&](int q) { return tab(tabB + q * D); };
+  auto rowG = [&](int q) { return tab(tabG + q * D); };
+  auto colB = [&](int d) { return tab(tabB + d); };
+  auto colG = [&](int d) { return tab(tabG + d); };
 
   // D for this thread's z-line (qx, qy) = r: issued first so the HBM stream
   // overlaps the gather and the forward contractions (tile-interleaved: for each
   // (c, qz) the workgroup reads one contiguous run)
-  // Stored-D scalar diffusion at p = 4, 5 in FP64 and at p = 6 in FP32 (the refinement's
-  // inner operator): only the first PD planes are loaded here and each later plane one
-  // z-iteration ahead of its use.  The registers of the other planes lift the occupancy,
+  // Stored-D scalar diffusion at p >= 4 in FP64 and at p = 6 in FP32 (the refinement's
+  // inner operator): only the first PD planes are loaded here and each later plane PD
+  // z-iterations ahead of its use.  The registers of the other planes lift the occupancy,
   // with the launch bound's request where needed: FP64 p = 4 from 3 to 4 waves per SIMD
   // (0.431 -> 0.419 ms at 1e7 dofs), p = 5 from 2 to 3 (0.434 -> 0.383 ms), FP32 p = 6
-  // from 4 to 5 (0.462 -> 0.445 ms at 2e7 dofs).  Measured and not kept: p = 2 at 6 waves
-  // (spills, 5% slower), p = 3 at 5 waves (spills, 4% slower), FP64 p = 6..8 streamed at
-  // the 2 waves their LDS or contraction registers allow (1-2% slower).
-  constexpr int PD =
-      (K0 == PAFEM_DIFFUSION && NV == 1 && sizeof(TC) == ((P == 4 || P == 5) ? 8 : P == 6 ? 4 : 0)) ? 2 : Q;
+  // from 4 to 5 (0.462 -> 0.445 ms at 2e7 dofs), and FP64 p = 6..8 from 2 to 3 together
+  // with the smaller LDS footprint of XTAIL (p = 6 0.382 -> 0.326 ms, p = 7 0.377 ->
+  // 0.342 ms; p = 8 one plane ahead, fewer spills).  Measured and not kept: p = 2 at 6
+  // waves (spills, 5% slower), p = 3 at 5 waves (spills, 4% slower), FP64 p = 6..8
+  // streamed at 2 waves (1-2% slower).
+  constexpr int PD = (K0 == PAFEM_DIFFUSION && NV == 1 && (sizeof(TC) == 8 ? P >= 4 : P == 6))
+                         ? (P == 8 ? 1 : 2)
+                         : Q;
   TC dq[Q][NC];
   // stored diffusion D: components in pairs per point, one load per pair
   constexpr bool PAIRS = (NCT == 6);
@@ -203,11 +239,13 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
     for (int dx = 0; dx < D; ++dx) u[dx] = sX[slot[dx]];
 #pragma unroll
     for (int qx = 0; qx < Q; ++qx) {
+      const auto rb = rowB(qx);
+      const auto rg = rowG(qx);
       TC b = TC(0), g = TC(0);
 #pragma unroll
       for (int dx = 0; dx < D; ++dx) {
-        b += bB(qx, dx) * u[dx];
-        if (GRAD) g += bG(qx, dx) * u[dx];
+        b += rb[dx] * u[dx];
+        if (GRAD) g += rg[dx] * u[dx];
       }
       at(xy / Q, xy % Q, qx, xz) = b;
       if (GRAD) at((D + xy) / Q, (D + xy) % Q, qx, xz) = g;
@@ -216,7 +254,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   __syncthreads();
 
   // sX is dead from here on: clear the per-unique-dof accumulators it now holds
-  if (!EVEC)
+  if (!EVEC && !XTAIL)
     for (int s = tid; s < nu; s += NE * QQ)
 #pragma unroll
       for (int oc = 0; oc < NOUT; ++oc) sX[oc * NE * DDD + s] = TC(0);
@@ -233,13 +271,15 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
     }
 #pragma unroll
     for (int qy = 0; qy < Q; ++qy) {
+      const auto rb = rowB(qy);
+      const auto rg = rowG(qy);
       TC gb = TC(0), bg = TC(0), bb = TC(0);
 #pragma unroll
       for (int dy = 0; dy < D; ++dy) {
-        bb += bB(qy, dy) * aB[dy];
+        bb += rb[dy] * aB[dy];
         if (GRAD) {
-          gb += bB(qy, dy) * aG[dy];
-          bg += bG(qy, dy) * aB[dy];
+          gb += rb[dy] * aG[dy];
+          bg += rg[dy] * aB[dy];
         }
       }
       if (GRAD) {
@@ -297,6 +337,8 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
     for (int dz = 0; dz < D; ++dz) t0[dz] = t1[dz] = t2[dz] = TC(0);
 #pragma unroll
     for (int qz = 0; qz < Q; ++qz) {
+      const auto rb = rowB(qz);
+      const auto rg = rowG(qz);
       if constexpr (PD < Q) {
         if (qz + PD < Q) load_plane(qz + PD, 0);
         __asm__ volatile("" ::: "memory");  // keep the next plane's loads in this iteration
@@ -305,9 +347,9 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
         TC ux = TC(0), uy = TC(0), uz = TC(0);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
-          ux += bB(qz, dz) * c0[dz];
-          uy += bB(qz, dz) * c1[dz];
-          uz += bG(qz, dz) * c2[dz];
+          ux += rb[dz] * c0[dz];
+          uy += rb[dz] * c1[dz];
+          uz += rg[dz] * c2[dz];
         }
         TC d00, d01, d02, d11, d12, d22;
         if constexpr (GEOM) {
@@ -350,75 +392,75 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
         if (DOT) energy += double(ux) * double(vx) + double(uy) * double(vy) + double(uz) * double(vz);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
-          t0[dz] += bB(qz, dz) * vx;
-          t1[dz] += bB(qz, dz) * vy;
-          t2[dz] += bG(qz, dz) * vz;
+          t0[dz] += rb[dz] * vx;
+          t1[dz] += rb[dz] * vy;
+          t2[dz] += rg[dz] * vz;
         }
       } else if constexpr (GRADV) {
         // w kappa adj(J)^t (reference gradient): the physical gradient times w det J
         TC ux = TC(0), uy = TC(0), uz = TC(0);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
-          ux += bB(qz, dz) * c0[dz];
-          uy += bB(qz, dz) * c1[dz];
-          uz += bG(qz, dz) * c2[dz];
+          ux += rb[dz] * c0[dz];
+          uy += rb[dz] * c1[dz];
+          uz += rg[dz] * c2[dz];
         }
         const TC v0 = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
         const TC v1 = dq[qz][3] * ux + dq[qz][4] * uy + dq[qz][5] * uz;
         const TC v2 = dq[qz][6] * ux + dq[qz][7] * uy + dq[qz][8] * uz;
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
-          t0[dz] += bB(qz, dz) * v0;
-          t1[dz] += bB(qz, dz) * v1;
-          t2[dz] += bB(qz, dz) * v2;
+          t0[dz] += rb[dz] * v0;
+          t1[dz] += rb[dz] * v1;
+          t2[dz] += rb[dz] * v2;
         }
       } else if constexpr (DIVV) {
         // d u_comp / d x_comp times w kappa det J: sum_b w kappa adj(J)[b][comp] d_b u_comp
         TC ux = TC(0), uy = TC(0), uz = TC(0);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
-          ux += bB(qz, dz) * c0[dz];
-          uy += bB(qz, dz) * c1[dz];
-          uz += bG(qz, dz) * c2[dz];
+          ux += rb[dz] * c0[dz];
+          uy += rb[dz] * c1[dz];
+          uz += rg[dz] * c2[dz];
         }
         sdiv[qz] += dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
         if (comp == NV - 1) {
 #pragma unroll
-          for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * sdiv[qz];
+          for (int dz = 0; dz < D; ++dz) t0[dz] += rb[dz] * sdiv[qz];
         }
       } else if constexpr (DGV) {
         // -u (w adj(J) beta) . grad_ref v: the value at the point times minus the stored
         // vector, contracted back against the reference gradient
         TC u = TC(0);
 #pragma unroll
-        for (int dz = 0; dz < D; ++dz) u += bB(qz, dz) * c0[dz];
+        for (int dz = 0; dz < D; ++dz) u += rb[dz] * c0[dz];
         const TC vx = -dq[qz][0] * u, vy = -dq[qz][1] * u, vz = -dq[qz][2] * u;
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
-          t0[dz] += bB(qz, dz) * vx;
-          t1[dz] += bB(qz, dz) * vy;
-          t2[dz] += bG(qz, dz) * vz;
+          t0[dz] += rb[dz] * vx;
+          t1[dz] += rb[dz] * vy;
+          t2[dz] += rg[dz] * vz;
         }
       } else if constexpr (CONV) {
         // (beta . grad u) at the point: w adj(J) beta . (reference gradient)
         TC ux = TC(0), uy = TC(0), uz = TC(0);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
-          ux += bB(qz, dz) * c0[dz];
-          uy += bB(qz, dz) * c1[dz];
-          uz += bG(qz, dz) * c2[dz];
+          ux += rb[dz] * c0[dz];
+          uy += rb[dz] * c1[dz];
+          uz += rg[dz] * c2[dz];
         }
         const TC v = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
 #pragma unroll
-        for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * v;
+        for (int dz = 0; dz < D; ++dz) t0[dz] += rb[dz] * v;
       } else {
         TC u = TC(0);
 #pragma unroll
-        for (int dz = 0; dz < D; ++dz) u += bB(qz, dz) * c0[dz];
+        for (int dz = 0; dz < D; ++dz) u += rb[dz] * c0[dz];
         const TC v = dq[qz][0] * u;
         if (DOT) energy += double(u) * double(v);
 #pragma unroll
-        for (int dz = 0; dz < D; ++dz) t0[dz] += bB(qz, dz) * v;
+        for (int dz = 0; dz < D; ++dz) t0[dz] += rb[dz] * v;
       }
     }
     if (!DIVV || comp == NV - 1) {
@@ -453,12 +495,13 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
       // three value contractions: component c of the output to x-line array c
 #pragma unroll
       for (int dy = 0; dy < D; ++dy) {
+        const auto cb = colB(dy);
         TC o0 = TC(0), o1 = TC(0), o2 = TC(0);
 #pragma unroll
         for (int qy = 0; qy < Q; ++qy) {
-          o0 += bB(qy, dy) * v0[qy];
-          o1 += bB(qy, dy) * v1[qy];
-          o2 += bB(qy, dy) * v2[qy];
+          o0 += cb[qy * D] * v0[qy];
+          o1 += cb[qy * D] * v1[qy];
+          o2 += cb[qy * D] * v2[qy];
         }
         at(dy / Q, dy % Q, yx, yz) = o0;
         at((D + dy) / Q, (D + dy) % Q, yx, yz) = o1;
@@ -467,14 +510,16 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
     } else {
 #pragma unroll
       for (int dy = 0; dy < D; ++dy) {
+        const auto cb = colB(dy);
+        const auto cg = colG(dy);
         TC b = TC(0), g = TC(0);
 #pragma unroll
         for (int qy = 0; qy < Q; ++qy) {
           if (BACKD) {
-            g += bB(qy, dy) * v0[qy];
-            b += bG(qy, dy) * v1[qy] + bB(qy, dy) * v2[qy];
+            g += cb[qy * D] * v0[qy];
+            b += cg[qy * D] * v1[qy] + cb[qy * D] * v2[qy];
           } else {
-            b += bB(qy, dy) * v0[qy];
+            b += cb[qy * D] * v0[qy];
           }
         }
         at(dy / Q, dy % Q, yx, yz) = b;
@@ -483,6 +528,11 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
     }
   }
   __syncthreads();
+  if constexpr (XTAIL && !EVEC) {
+    // the region tails are dead now: clear the per-unique-dof accumulators there
+    for (int s = tid; s < nu; s += NE * QQ) sX[s] = TC(0);
+    __syncthreads();
+  }
 
   // B^t along x and G^t: thread (dz, dy)
   if constexpr (GRADV) {
@@ -496,12 +546,13 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
     }
 #pragma unroll
     for (int dx = 0; dx < D; ++dx) {
+      const auto cb = colB(dx);
       TC a0 = TC(0), a1 = TC(0), a2 = TC(0);
 #pragma unroll
       for (int qx = 0; qx < Q; ++qx) {
-        a0 += bB(qx, dx) * w0[qx];
-        a1 += bB(qx, dx) * w1[qx];
-        a2 += bB(qx, dx) * w2[qx];
+        a0 += cb[qx * D] * w0[qx];
+        a1 += cb[qx * D] * w1[qx];
+        a2 += cb[qx * D] * w2[qx];
       }
       atomicAdd(&sX[slot[dx]], a0);
       atomicAdd(&sX[NE * DDD + slot[dx]], a1);
@@ -517,11 +568,13 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
     }
 #pragma unroll
     for (int dx = 0; dx < D; ++dx) {
+      const auto cb = colB(dx);
+      const auto cg = colG(dx);
       TC acc = TC(0);
 #pragma unroll
       for (int qx = 0; qx < Q; ++qx) {
-        acc += bB(qx, dx) * wB[qx];
-        if (BACKD) acc += bG(qx, dx) * wG[qx];
+        acc += cb[qx * D] * wB[qx];
+        if (BACKD) acc += cg[qx * D] * wG[qx];
       }
       if (EVEC)
         y[size_t(e) * DDD + r * D + dx] = TV(acc);

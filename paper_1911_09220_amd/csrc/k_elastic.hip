@@ -55,8 +55,21 @@ __global__ void __launch_bounds__(qdata_tile(Q) * Q * Q)
   auto at = [&](int c, int qy, int qx, int dz) -> double& {
     return W[((c * Q + qy) * Q + qx) * LC + dz];
   };
-  auto bB = [&](int q, int d) -> double { return tabB[q * D + d]; };
-  auto bG = [&](int q, int d) -> double { return tabG[q * D + d]; };
+  // Row q (forward stages) or column d (back stages) of a 1D table.  At p = 8 loaded per
+  // loop iteration (opaque_ptr): loading every entry of the unrolled stages up front
+  // overflowed the scalar registers (1784 spilled through VGPR lanes; 2.98 -> 1.42 ms at
+  // 1e7 dofs).  At p = 5..7, where 56-312 spill, the per-iteration loads were 1-6% slower.
+  constexpr bool OPQ = P >= 8;
+  auto tab = [&](const double* t) {
+    if constexpr (OPQ)
+      return opaque_ptr(t);
+    else
+      return t;
+  };
+  auto rowB = [&](int q) { return tab(tabB + q * D); };
+  auto rowG = [&](int q) { return tab(tabG + q * D); };
+  auto colB = [&](int d) { return tab(tabB + d); };
+  auto colG = [&](int d) { return tab(tabG + d); };
 
   const bool xline = act && r < DD;  // x-line (dz, dy)
   const int xz = r / D, xy = r - (r / D) * D;
@@ -88,11 +101,13 @@ __global__ void __launch_bounds__(qdata_tile(Q) * Q * Q)
       for (int dx = 0; dx < D; ++dx) u[dx] = sX[slot[dx]];
 #pragma unroll
       for (int qx = 0; qx < Q; ++qx) {
+        const auto rb = rowB(qx);
+        const auto rg = rowG(qx);
         double b = 0.0, gg = 0.0;
 #pragma unroll
         for (int dx = 0; dx < D; ++dx) {
-          b += bB(qx, dx) * u[dx];
-          gg += bG(qx, dx) * u[dx];
+          b += rb[dx] * u[dx];
+          gg += rg[dx] * u[dx];
         }
         at(xy / Q, xy % Q, qx, xz) = b;
         at((D + xy) / Q, (D + xy) % Q, qx, xz) = gg;
@@ -108,12 +123,14 @@ __global__ void __launch_bounds__(qdata_tile(Q) * Q * Q)
       }
 #pragma unroll
       for (int qy = 0; qy < Q; ++qy) {
+        const auto rb = rowB(qy);
+        const auto rg = rowG(qy);
         double gb = 0.0, bgv = 0.0, bb = 0.0;
 #pragma unroll
         for (int dy = 0; dy < D; ++dy) {
-          gb += bB(qy, dy) * aG[dy];
-          bgv += bG(qy, dy) * aB[dy];
-          bb += bB(qy, dy) * aB[dy];
+          gb += rb[dy] * aG[dy];
+          bgv += rg[dy] * aB[dy];
+          bb += rb[dy] * aB[dy];
         }
         at(0, qy, yx, yz) = gb;
         at(1, qy, yx, yz) = bgv;
@@ -131,12 +148,14 @@ __global__ void __launch_bounds__(qdata_tile(Q) * Q * Q)
       }
 #pragma unroll
       for (int qz = 0; qz < Q; ++qz) {
+        const auto rb = rowB(qz);
+        const auto rg = rowG(qz);
         double ux = 0.0, uy = 0.0, uz = 0.0;
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
-          ux += bB(qz, dz) * c0[dz];
-          uy += bB(qz, dz) * c1[dz];
-          uz += bG(qz, dz) * c2[dz];
+          ux += rb[dz] * c0[dz];
+          uy += rb[dz] * c1[dz];
+          uz += rg[dz] * c2[dz];
         }
         g[comp][qz][0] = ux;
         g[comp][qz][1] = uy;
@@ -191,13 +210,16 @@ __global__ void __launch_bounds__(qdata_tile(Q) * Q * Q)
 #pragma unroll
       for (int dz = 0; dz < D; ++dz) t0[dz] = t1[dz] = t2[dz] = 0.0;
 #pragma unroll
-      for (int qz = 0; qz < Q; ++qz)
+      for (int qz = 0; qz < Q; ++qz) {
+        const auto rb = rowB(qz);
+        const auto rg = rowG(qz);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
-          t0[dz] += bB(qz, dz) * g[comp][qz][0];
-          t1[dz] += bB(qz, dz) * g[comp][qz][1];
-          t2[dz] += bG(qz, dz) * g[comp][qz][2];
+          t0[dz] += rb[dz] * g[comp][qz][0];
+          t1[dz] += rb[dz] * g[comp][qz][1];
+          t2[dz] += rg[dz] * g[comp][qz][2];
         }
+      }
 #pragma unroll
       for (int dz = 0; dz < D; ++dz) {
         at(0, zy, zx, dz) = t0[dz];
@@ -216,11 +238,13 @@ __global__ void __launch_bounds__(qdata_tile(Q) * Q * Q)
       }
 #pragma unroll
       for (int dy = 0; dy < D; ++dy) {
+        const auto cb = colB(dy);
+        const auto cg = colG(dy);
         double b = 0.0, gg = 0.0;
 #pragma unroll
         for (int qy = 0; qy < Q; ++qy) {
-          gg += bB(qy, dy) * v0[qy];
-          b += bG(qy, dy) * v1[qy] + bB(qy, dy) * v2[qy];
+          gg += cb[qy * D] * v0[qy];
+          b += cg[qy * D] * v1[qy] + cb[qy * D] * v2[qy];
         }
         at(dy / Q, dy % Q, yx, yz) = b;
         at((D + dy) / Q, (D + dy) % Q, yx, yz) = gg;
@@ -236,9 +260,11 @@ __global__ void __launch_bounds__(qdata_tile(Q) * Q * Q)
       }
 #pragma unroll
       for (int dx = 0; dx < D; ++dx) {
+        const auto cb = colB(dx);
+        const auto cg = colG(dx);
         double acc = 0.0;
 #pragma unroll
-        for (int qx = 0; qx < Q; ++qx) acc += bB(qx, dx) * wB[qx] + bG(qx, dx) * wG[qx];
+        for (int qx = 0; qx < Q; ++qx) acc += cb[qx * D] * wB[qx] + cg[qx * D] * wG[qx];
         atomicAdd(&sX[slot[dx]], acc);
       }
     }

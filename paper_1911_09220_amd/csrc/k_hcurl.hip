@@ -72,9 +72,24 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
   double* const W2 = sW2 + el * W2N;
   const uint16_t* const slots = tile_slot + size_t(e) * NDE;
   const int8_t* const signs = esign + size_t(e) * NDE;
-  auto bB = [&](int q, int d) { return tabB[q * DC + d]; };
-  auto bG = [&](int q, int d) { return tabG[q * DC + d]; };
-  auto bO = [&](int q, int d) { return tabO[q * DO + d]; };
+  // Row q (forward stages, transposed z) or column d (transposed y and x) of a 1D
+  // table.  At p = 8 loaded per loop iteration (opaque_ptr): loading every entry of the
+  // unrolled stages up front overflows the scalar registers (spilled through VGPR lanes;
+  // 0.797 -> 0.614 ms at 1e7 dofs).  At p = 3..7 the spills are smaller and the
+  // per-iteration loads were 1-12% slower.
+  constexpr int OPQ_MIN = 8;
+  auto tab = [&](const double* t) {
+    if constexpr (P >= OPQ_MIN)
+      return opaque_ptr(t);
+    else
+      return t;
+  };
+  auto rowB = [&](int q) { return tab(tabB + q * DC); };
+  auto rowG = [&](int q) { return tab(tabG + q * DC); };
+  auto rowO = [&](int q) { return tab(tabO + q * DO); };
+  auto colB = [&](int d) { return tab(tabB + d); };  // entry q at [q * DC]
+  auto colG = [&](int d) { return tab(tabG + d); };
+  auto colO = [&](int d) { return tab(tabO + d); };  // entry q at [q * DO]
 
   // G: the tile's unique dofs, essential ones read as 0 when constrained
   for (int s0 = tid; s0 < nu; s0 += 4 * NE * QQ) {
@@ -120,14 +135,17 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
       }
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
+        const auto ro = rowO(q);
+        const auto rb = rowB(q);
+        const auto rg = rowG(q);
         double v = 0.0, d = 0.0;
 #pragma unroll
         for (int i0 = 0; i0 < n0; ++i0) {
           if constexpr (A == 0) {
-            v += bO(q, i0) * in[i0];
+            v += ro[i0] * in[i0];
           } else {
-            v += bB(q, i0) * in[i0];
-            if constexpr (CURL) d += bG(q, i0) * in[i0];
+            v += rb[i0] * in[i0];
+            if constexpr (CURL) d += rg[i0] * in[i0];
           }
         }
         W1[(0 * n2 * n1 + i2 * n1 + i1) * Q + q] = v;
@@ -145,6 +163,9 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
         for (int i1 = 0; i1 < n1; ++i1) in[k][i1] = W1[(k * n2 * n1 + i2 * n1 + i1) * Q + q0];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
+        const auto ro = rowO(q);
+        const auto rb = rowB(q);
+        const auto rg = rowG(q);
         double out[NY];
 #pragma unroll
         for (int k = 0; k < NY; ++k) out[k] = 0.0;
@@ -152,11 +173,11 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
         for (int i1 = 0; i1 < n1; ++i1) {
           if constexpr (A == 1) {
 #pragma unroll
-            for (int k = 0; k < NX; ++k) out[k] += bO(q, i1) * in[k][i1];
+            for (int k = 0; k < NX; ++k) out[k] += ro[i1] * in[k][i1];
           } else {
 #pragma unroll
-            for (int k = 0; k < NX; ++k) out[k] += bB(q, i1) * in[k][i1];
-            if constexpr (CURL) out[NY - 1] += bG(q, i1) * in[0][i1];
+            for (int k = 0; k < NX; ++k) out[k] += rb[i1] * in[k][i1];
+            if constexpr (CURL) out[NY - 1] += rg[i1] * in[0][i1];
           }
         }
 #pragma unroll
@@ -174,6 +195,9 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
         for (int i2 = 0; i2 < n2; ++i2) in[k][i2] = W2[((k * n2 + i2) * Q + q1) * Q + q0];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
+        const auto ro = rowO(q);
+        const auto rb = rowB(q);
+        const auto rg = rowG(q);
         double out[NY + 1];
 #pragma unroll
         for (int k = 0; k <= NY; ++k) out[k] = 0.0;
@@ -181,11 +205,11 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
         for (int i2 = 0; i2 < n2; ++i2) {
           if constexpr (A == 2) {
 #pragma unroll
-            for (int k = 0; k < NY; ++k) out[k] += bO(q, i2) * in[k][i2];
+            for (int k = 0; k < NY; ++k) out[k] += ro[i2] * in[k][i2];
           } else {
 #pragma unroll
-            for (int k = 0; k < NY; ++k) out[k] += bB(q, i2) * in[k][i2];
-            if constexpr (CURL) out[NY] += bG(q, i2) * in[0][i2];
+            for (int k = 0; k < NY; ++k) out[k] += rb[i2] * in[k][i2];
+            if constexpr (CURL) out[NY] += rg[i2] * in[0][i2];
           }
         }
         if (MASS) uq[A][q] = out[0];
@@ -266,6 +290,9 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
         for (int i2 = 0; i2 < n2; ++i2) out[k][i2] = 0.0;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
+        const auto ro = rowO(q);
+        const auto rb = rowB(q);
+        const auto rg = rowG(q);
         const double V = MASS ? uq[A][q] : 0.0;
         double Wd[2];
 #pragma unroll
@@ -277,17 +304,17 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
 #pragma unroll
         for (int i2 = 0; i2 < n2; ++i2) {
           if constexpr (A == 2) {
-            out[0][i2] += bO(q, i2) * V;
+            out[0][i2] += ro[i2] * V;
             if constexpr (CURL) {
-              out[1][i2] += bO(q, i2) * Wd[0];
-              out[2][i2] += bO(q, i2) * Wd[1];
+              out[1][i2] += ro[i2] * Wd[0];
+              out[2][i2] += ro[i2] * Wd[1];
             }
           } else {
             // the derivative along z (the last of the two) merges into the value
-            out[0][i2] += bB(q, i2) * V;
+            out[0][i2] += rb[i2] * V;
             if constexpr (CURL) {
-              out[0][i2] += bG(q, i2) * Wd[1];
-              out[1][i2] += bB(q, i2) * Wd[0];
+              out[0][i2] += rg[i2] * Wd[1];
+              out[1][i2] += rb[i2] * Wd[0];
             }
           }
         }
@@ -308,6 +335,9 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
         for (int q = 0; q < Q; ++q) in[k][q] = W2[((k * n2 + i2) * Q + q) * Q + q0];
 #pragma unroll
       for (int i1 = 0; i1 < n1; ++i1) {
+        const auto co = colO(i1);
+        const auto cb = colB(i1);
+        const auto cg = colG(i1);
         double out[NYB];
 #pragma unroll
         for (int k = 0; k < NYB; ++k) out[k] = 0.0;
@@ -315,13 +345,13 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
         for (int q = 0; q < Q; ++q) {
           if constexpr (A == 1) {
 #pragma unroll
-            for (int k = 0; k < NYB; ++k) out[k] += bO(q, i1) * in[k][q];
+            for (int k = 0; k < NYB; ++k) out[k] += co[q * DO] * in[k][q];
           } else {
             // the derivative along y (the last array) merges into the value
-            out[0] += bB(q, i1) * in[0][q];
-            if constexpr (CURL) out[0] += bG(q, i1) * in[NZ - 1][q];
+            out[0] += cb[q * DC] * in[0][q];
+            if constexpr (CURL) out[0] += cg[q * DC] * in[NZ - 1][q];
 #pragma unroll
-            for (int k = 1; k < NYB; ++k) out[k] += bB(q, i1) * in[k][q];
+            for (int k = 1; k < NYB; ++k) out[k] += cb[q * DC] * in[k][q];
           }
         }
 #pragma unroll
@@ -339,14 +369,17 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
         for (int q = 0; q < Q; ++q) in[k][q] = W1[(k * n2 * n1 + i2 * n1 + i1) * Q + q];
 #pragma unroll
       for (int i0 = 0; i0 < n0; ++i0) {
+        const auto co = colO(i0);
+        const auto cb = colB(i0);
+        const auto cg = colG(i0);
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           if constexpr (A == 0) {
-            acc += bO(q, i0) * in[0][q];
+            acc += co[q * DO] * in[0][q];
           } else {
-            acc += bB(q, i0) * in[0][q];
-            if constexpr (CURL) acc += bG(q, i0) * in[NYB - 1][q];
+            acc += cb[q * DC] * in[0][q];
+            if constexpr (CURL) acc += cg[q * DC] * in[NYB - 1][q];
           }
         }
         const int j = A * CB + i0 + n0 * (i1 + n1 * i2);
