@@ -646,28 +646,29 @@ def bench_learned(P, torch, n=64, p=3, fields=20, heldout=10, steps=1500, tol=1e
     t_train = time.perf_counter() - t1
     # ablation: the same basis training with the element features zeroed, so the
     # network's output (the element weights) is one constant vector for every element
-    ablation = None
-    if not compact:
+    if compact:
+        zero = torch.zeros_like(samples.fields[0][1])
+        abl_samples = samples.without_features(zero)
+    else:
         zero = torch.zeros_like(samples[0][1])
         abl_samples = [(o, zero, d, r, e) for (o, _, d, r, e) in samples]
-        net0 = P.Net(p, hidden=64, max_rows=E, max_train_rows=E)
-        net0.set_params(L.initial_params(net0, seed=23))
-        t2 = time.perf_counter()
-        losses0 = L.train(net0, abl_samples, steps=steps, lr=2e-3, decay_every=max(1, steps // 3))
-        torch.cuda.synchronize()
-        ablation = {"net": net0, "zero": zero, "train_seconds": round(time.perf_counter() - t2, 2),
-                    "loss_last": float(losses0[-50:].mean())}
-        del abl_samples
+    net0 = P.Net(p, hidden=64, max_rows=E, max_train_rows=E)
+    net0.set_params(L.initial_params(net0, seed=23))
+    t2 = time.perf_counter()
+    losses0 = L.train(net0, abl_samples, steps=steps, lr=2e-3, decay_every=max(1, steps // 3))
+    torch.cuda.synchronize()
+    ablation = {"net": net0, "zero": zero, "train_seconds": round(time.perf_counter() - t2, 2),
+                "loss_last": float(losses0[-50:].mean())}
+    del abl_samples
     del samples
     out = {"order": p, "mesh": n, "ndofs": S.ndofs, "train_fields": fields,
            "pair_stops": list(stops), "train_steps": steps, "pair_seconds": round(t_pairs, 2),
            "train_seconds": round(t_train, 2), "loss_first": float(losses[:50].mean()),
            "loss_last": float(losses[-50:].mean()), "tol": tol, "heldout": []}
-    if ablation is not None:
-        out["constant_weights"] = {
-            "what": "same basis training with the element features zeroed (one weight vector "
-                    "for every element: the network adds nothing)",
-            "train_seconds": ablation["train_seconds"], "loss_last": ablation["loss_last"]}
+    out["constant_weights"] = {
+        "what": "same basis training with the element features zeroed (one weight vector "
+                "for every element: the network adds nothing)",
+        "train_seconds": ablation["train_seconds"], "loss_last": ablation["loss_last"]}
     for f in range(heldout):
         op, diag, feats = field(2000 + f)
         if f == 0:
@@ -688,14 +689,13 @@ def bench_learned(P, torch, n=64, p=3, fields=20, heldout=10, steps=1500, tol=1e
                             "true_rel_res": il["true_rel_res"], "fell_back": il["fell_back"]},
             "speedup": round(ij["seconds"] / il["seconds"], 3)})
         log(f"learned: held-out field {f}: FCG {il['iters']} its {il['seconds']:.3f} s")
-        if ablation is not None:
-            _, ia = P.fcg_solve(op, b, diag, net=ablation["net"], feats=ablation["zero"],
-                                rel_tol=tol, max_iter=20000, history=False)
-            out["heldout"][-1]["constant_weights_fcg"] = {
-                "seconds": round(ia["seconds"], 4), "iters": ia["iters"],
-                "true_rel_res": ia["true_rel_res"], "fell_back": ia["fell_back"]}
-            log(f"learned: held-out field {f}: constant-weight FCG {ia['iters']} its "
-                f"{ia['seconds']:.3f} s")
+        _, ia = P.fcg_solve(op, b, diag, net=ablation["net"], feats=ablation["zero"],
+                            rel_tol=tol, max_iter=20000, history=False)
+        out["heldout"][-1]["constant_weights_fcg"] = {
+            "seconds": round(ia["seconds"], 4), "iters": ia["iters"],
+            "true_rel_res": ia["true_rel_res"], "fell_back": ia["fell_back"]}
+        log(f"learned: held-out field {f}: constant-weight FCG {ia['iters']} its "
+            f"{ia['seconds']:.3f} s")
         del op, diag, feats
     return out
 

@@ -82,18 +82,37 @@ class CompactFields:
         kappa, feats, diag = self.fields[f]
         return self.use(f), feats, diag, r.double(), e.double()
 
+    def without_features(self, zero):
+        """The same samples drawn with the element features replaced by `zero` (one
+        zeroed feature array): the network's output is then one weight vector for every
+        element, the ablation of the network."""
+        return _ZeroFeatures(self, zero)
+
+
+class _ZeroFeatures:
+    def __init__(self, store, zero):
+        self.store, self.zero, self.qd = store, zero, store.qd
+
+    def __len__(self):
+        return len(self.store)
+
+    def draw(self, i):
+        op, _, diag, r, e = self.store.draw(i)
+        return op, self.zero, diag, r, e
+
 
 def train(net, samples, steps=500, lr=2e-3, lr_decay=0.5, decay_every=200, seed=0, log_every=0,
           log=print):
     """Adam on the loss of randomly drawn samples.
 
-    samples: list of (op, feats, diag, r, e), or a CompactFields.  Returns the per-step
+    samples: list of (op, feats, diag, r, e), a CompactFields or its without_features()
+    view.  Returns the per-step
     losses (host).
     """
     import torch
     rng = np.random.default_rng(seed)
     works = {}
-    compact = isinstance(samples, CompactFields)
+    compact = isinstance(samples, (CompactFields, _ZeroFeatures))
     device = samples.qd.device if compact else samples[0][3].device
     loss_dev = torch.zeros(steps, dtype=torch.float64, device=device)
     cur_lr = lr

@@ -306,3 +306,14 @@ def test_compact_field_store_trains_like_the_list():
     print("list", losses[0][:5], "compact", losses[1][:5])
     assert np.all(np.isfinite(losses[0]))
     assert np.allclose(losses[0], losses[1], rtol=1e-6, atol=0.0)
+    # the ablation view of the store (features zeroed) trains like the list with zeroed
+    # features, and differs from the run with the features
+    zero = torch.zeros_like(listed[0][1])
+    losses0 = []
+    for samples in ([(o, zero, d, r, e) for (o, _, d, r, e) in listed],
+                    store.without_features(zero)):
+        net = P.Net(p, hidden=32, max_rows=E, max_train_rows=E)
+        net.set_params(L.initial_params(net, seed=32))
+        losses0.append(L.train(net, samples, steps=40, lr=2e-3, seed=33))
+    assert np.allclose(losses0[0], losses0[1], rtol=1e-6, atol=0.0)
+    assert not np.allclose(losses0[0], losses[0], rtol=1e-6, atol=0.0)
