@@ -108,13 +108,13 @@ def algorithmic_flops(kind: str, p: int, ne: int) -> int:
     return per * ne
 
 
-def setup_problem(P, torch, p, target, scatter):
+def setup_problem(P, torch, p, target, scatter, renumber=False):
     import synth
     n = lattice_size(p, target)
     mesh = synth.hex_lattice(n, 0.05, seed=2)
     ne = mesh["hex"].shape[0]
     kappa = torch.as_tensor(synth.lognormal_iid(ne, p + 2, 1.0, seed=3), device="cuda")
-    S = P.Space(P.Mesh.from_dict(mesh), p)
+    S = P.Space(P.Mesh.from_dict(mesh), p, renumber=renumber)
     del mesh
     qd = S.qdata(P.DIFFUSION, coeff=kappa)
     qm = S.qdata(P.MASS, coeff=kappa)
@@ -708,6 +708,9 @@ def main():
     ap.add_argument("--orders", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--target-dofs", type=float, default=1e7)
     ap.add_argument("--scatter", choices=["atomic", "evec"], default="atomic")
+    ap.add_argument("--renumber", action="store_true",
+                    help="sweep spaces number their dofs by first touch in the device element "
+                         "order (PAFEM_SPACE_RENUMBER) instead of vertices, edges, faces, interiors")
     ap.add_argument("--cg-orders", default="1,2,3,4,5,6,7,8",
                     help="orders for the Jacobi-PCG solve ('' = none)")
     ap.add_argument("--geom-cg-orders", default="3",
@@ -746,7 +749,7 @@ def main():
     t_setup = time.perf_counter()
     probs = []
     for p in orders:
-        probs.append(setup_problem(P, torch, p, args.target_dofs, args.scatter))
+        probs.append(setup_problem(P, torch, p, args.target_dofs, args.scatter, args.renumber))
         print(f"# setup p={p}: {probs[-1]['ndofs']} dofs, {probs[-1]['ne']} elements",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -883,7 +886,9 @@ def main():
         "config": {"workload": f"scale sweep: unit-cube hex lattices of ~{args.target_dofs:.0e} "
                                f"dofs for p={args.orders}, 5% vertex jitter, lognormal kappa "
                                f"(sigma=1) per quadrature point, q1d=p+2, Dirichlet boundary",
-                   "orders": orders, "scatter": args.scatter, "per_p": per_p,
+                   "orders": orders, "scatter": args.scatter,
+                   "dof_numbering": "first touch in Morton element order" if args.renumber
+                   else "vertices, edges, faces, interiors", "per_p": per_p,
                    "mass_apply": mass, "deterministic_scatter_apply": evec,
                    "recomputed_geometry_apply": geom,
                    "convection_apply": conv, "gradient_apply": grad,
