@@ -36,7 +36,7 @@ __host__ __device__ constexpr int eps3(int c, int b, int a) {
 __host__ __device__ constexpr int other_axis(int a, int k) { return k < a ? k : k + 1; }
 
 template <int P, int KIND, bool DOT>
-__global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
+__global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2), P >= 5 ? 2 : 1)
     nd_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
                     const uint16_t* __restrict__ tile_slot, const int8_t* __restrict__ esign,
                     const double* __restrict__ tabB, const double* __restrict__ tabG,
@@ -53,11 +53,19 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
   constexpr int NCT = KIND == PAFEM_HCURL_MAXWELL ? 12 : 6;
   constexpr int CP0 = 0;                 // first pair of the curl D
   constexpr int MP0 = KIND == PAFEM_HCURL_MAXWELL ? 3 : 0;  // first pair of the mass D
-  constexpr int W1N = 2 * Q * DC * DC;   // after the x contraction: <= 2 arrays
-  constexpr int W2N = 3 * Q * Q * DC;    // after the y contraction: <= 3 arrays
+  // One LDS region per element holds every intermediate of a component's contractions:
+  // Q x DC columns (q, i2), each of RS rows.  The x contraction of line (i1, i2) writes
+  // row k*n1 + i1 of columns (q, i2); the y contraction of line (q0, i2) reads those rows
+  // of its own column and writes rows k*Q + q of the same column; the z contraction of
+  // line (q0, q1) reads (and on the way back writes) row k*Q + q1 of the columns (q0, i2).
+  // Every y-line thread reads all its inputs before writing, so the stages work in place
+  // (LDS per element 3Q^2 DC instead of 2Q DC^2 + 3Q^2 DC: twice the workgroups per CU
+  // at p >= 6).  RS is odd, so that y-line threads walking their columns hit distinct banks.
+  constexpr int RS = (3 * Q) | 1;
+  constexpr int REG = Q * DC * RS;
+  static_assert(2 * DC <= RS && 3 * Q <= RS, "rows of a column");
 
-  __shared__ double sW1[NE * W1N];
-  __shared__ double sW2[NE * W2N];
+  __shared__ double sR[NE * REG];
   __shared__ double sX[NE * NDE];
 
   const int tid = threadIdx.x;
@@ -68,8 +76,8 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
   const bool act = e < ne;
   const int u0 = tile_off[tile];
   const int nu = tile_off[tile + 1] - u0;
-  double* const W1 = sW1 + el * W1N;
-  double* const W2 = sW2 + el * W2N;
+  double* const R = sR + el * REG;
+  auto at = [&](int col_q, int col_i2, int row) -> double& { return R[(col_i2 * Q + col_q) * RS + row]; };
   const uint16_t* const slots = tile_slot + size_t(e) * NDE;
   const int8_t* const signs = esign + size_t(e) * NDE;
   // Row q (forward stages, transposed z) or column d (transposed y and x) of a 1D
@@ -124,6 +132,8 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
     constexpr int n0 = A == 0 ? DO : DC, n1 = A == 1 ? DO : DC, n2 = A == 2 ? DO : DC;
     constexpr int NX = 1 + ((CURL && A != 0) ? 1 : 0);  // arrays after the x contraction
     constexpr int NY = NX + ((CURL && A != 1) ? 1 : 0);  // after the y contraction
+    // the previous component's z contraction has read the region
+    if constexpr (A > 0) __syncthreads();
     // x contraction: line (i1, i2)
     if (act && r < n1 * n2) {
       const int i1 = r % n1, i2 = r / n1;
@@ -148,8 +158,8 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
             if constexpr (CURL) d += rg[i0] * in[i0];
           }
         }
-        W1[(0 * n2 * n1 + i2 * n1 + i1) * Q + q] = v;
-        if constexpr (NX == 2) W1[(1 * n2 * n1 + i2 * n1 + i1) * Q + q] = d;
+        at(q, i2, i1) = v;
+        if constexpr (NX == 2) at(q, i2, n1 + i1) = d;
       }
     }
     __syncthreads();
@@ -160,7 +170,7 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
 #pragma unroll
       for (int k = 0; k < NX; ++k)
 #pragma unroll
-        for (int i1 = 0; i1 < n1; ++i1) in[k][i1] = W1[(k * n2 * n1 + i2 * n1 + i1) * Q + q0];
+        for (int i1 = 0; i1 < n1; ++i1) in[k][i1] = at(q0, i2, k * n1 + i1);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const auto ro = rowO(q);
@@ -181,7 +191,7 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
           }
         }
 #pragma unroll
-        for (int k = 0; k < NY; ++k) W2[((k * n2 + i2) * Q + q) * Q + q0] = out[k];
+        for (int k = 0; k < NY; ++k) at(q0, i2, k * Q + q) = out[k];
       }
     }
     __syncthreads();
@@ -192,7 +202,7 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
 #pragma unroll
       for (int k = 0; k < NY; ++k)
 #pragma unroll
-        for (int i2 = 0; i2 < n2; ++i2) in[k][i2] = W2[((k * n2 + i2) * Q + q1) * Q + q0];
+        for (int i2 = 0; i2 < n2; ++i2) in[k][i2] = at(q0, i2, k * Q + q1);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const auto ro = rowO(q);
@@ -280,6 +290,8 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
     // the axes below 2 other than A; after the y one: those below 1
     constexpr int NZ = 1 + (CURL ? ((A == 2) ? 2 : 1) : 0);
     constexpr int NYB = 1 + (CURL ? ((A == 0) ? 0 : 1) : 0);
+    // the previous component's transposed x contraction has read the region
+    if constexpr (A > 0) __syncthreads();
     // z: thread (q0, q1); coefficients of the value and of d/d(axis b) at the points
     if (act) {
       const int q0 = r % Q, q1 = r / Q;
@@ -322,7 +334,7 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
 #pragma unroll
       for (int k = 0; k < NZ; ++k)
 #pragma unroll
-        for (int i2 = 0; i2 < n2; ++i2) W2[((k * n2 + i2) * Q + q1) * Q + q0] = out[k][i2];
+        for (int i2 = 0; i2 < n2; ++i2) at(q0, i2, k * Q + q1) = out[k][i2];
     }
     __syncthreads();
     // y: line (q0, i2)
@@ -332,7 +344,7 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
 #pragma unroll
       for (int k = 0; k < NZ; ++k)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) in[k][q] = W2[((k * n2 + i2) * Q + q) * Q + q0];
+        for (int q = 0; q < Q; ++q) in[k][q] = at(q0, i2, k * Q + q);
 #pragma unroll
       for (int i1 = 0; i1 < n1; ++i1) {
         const auto co = colO(i1);
@@ -355,7 +367,7 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
           }
         }
 #pragma unroll
-        for (int k = 0; k < NYB; ++k) W1[(k * n2 * n1 + i2 * n1 + i1) * Q + q0] = out[k];
+        for (int k = 0; k < NYB; ++k) at(q0, i2, k * n1 + i1) = out[k];
       }
     }
     __syncthreads();
@@ -366,7 +378,7 @@ __global__ void __launch_bounds__(qdata_tile(P + 2) * (P + 2) * (P + 2))
 #pragma unroll
       for (int k = 0; k < NYB; ++k)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) in[k][q] = W1[(k * n2 * n1 + i2 * n1 + i1) * Q + q];
+        for (int q = 0; q < Q; ++q) in[k][q] = at(q, i2, k * n1 + i1);
 #pragma unroll
       for (int i0 = 0; i0 < n0; ++i0) {
         const auto co = colO(i0);
