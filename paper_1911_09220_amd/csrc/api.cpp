@@ -69,7 +69,7 @@ void apply_op(const Op& op, const void* x, void* y, void* work, hipStream_t st, 
   const int vdt = vector_dtype(op.qdtype);
   if (op.kind == PAFEM_DG_CONVECTION) {
     const double* qd = static_cast<const double*>(op.qdata);
-    launch_fill(static_cast<double*>(y), 0.0, s.ndofs, st);
+    // the volume kernel stores every dof (each belongs to one element); the faces add
     require(launch_pa_apply(s.dev, op.kind, op.q1d, PAFEM_F64, false, false, qd, x, y,
                             PAFEM_F64, st, nullptr),
             PAFEM_EUNSUPPORTED, "DG volume kernel not built for this order/q1d");

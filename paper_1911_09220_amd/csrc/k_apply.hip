@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   constexpr int NCC = (GRAD || DGV) ? 3 : 1;  // arrays after the y-lines (one per derivative)
   constexpr int NOUT = GRADV ? 3 : 1;  // output components
   static_assert(!((CONV || GRADV || DIVV || DGV) && DOT), "the convection, gradient and divergence operators have no energy");
-  static_assert(!(DGV && EVEC), "the DG volume term uses the atomic scatter");
+  static_assert(!(DGV && EVEC), "the DG volume term stores through the tile lists");
   static_assert(!((GRADV || DIVV) && EVEC), "the gradient and divergence operators use the atomic scatter");
   static_assert(NOUT * D <= NCC * Q, "back x-line arrays must fit the element region");
   static_assert(NV == 1 || DIVV || (!DOT && !EVEC && (K0 == PAFEM_MASS || K0 == PAFEM_DIFFUSION)),
@@ -589,7 +589,15 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   }
   if (EVEC) return;
   __syncthreads();
-  // G^t: one global atomic per unique dof of the tile
+  // G^t: one global atomic per unique dof of the tile.  The DG volume term's dofs belong
+  // to one element each (no dof is shared between tiles), so it stores instead, and the
+  // call needs no y-init (the face kernel adds its atomics afterwards).
+  auto put = [&](TV* dst, TV v) {
+    if constexpr (DGV)
+      *dst = v;
+    else
+      unsafeAtomicAdd(dst, v);
+  };
   if constexpr (ONEPASS && NV == 1) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -598,8 +606,8 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
       if (s < nu && !(constrained && g < 0))
 #pragma unroll
         for (int oc = 0; oc < NOUT; ++oc)
-          unsafeAtomicAdd(&y[(DIVV ? 0 : GRADC ? GC : comp + oc) * ystride + (g < 0 ? ~g : g)],
-                          TV(sX[oc * NE * DDD + s]));
+          put(&y[(DIVV ? 0 : GRADC ? GC : comp + oc) * ystride + (g < 0 ? ~g : g)],
+              TV(sX[oc * NE * DDD + s]));
     }
   } else {
 #pragma unroll 4
@@ -608,8 +616,8 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
       if (!(constrained && g < 0))
 #pragma unroll
         for (int oc = 0; oc < NOUT; ++oc)
-          unsafeAtomicAdd(&y[(DIVV ? 0 : GRADC ? GC : comp + oc) * ystride + (g < 0 ? ~g : g)],
-                          TV(sX[oc * NE * DDD + s]));
+          put(&y[(DIVV ? 0 : GRADC ? GC : comp + oc) * ystride + (g < 0 ? ~g : g)],
+              TV(sX[oc * NE * DDD + s]));
     }
   }
   if (NV > 1) __syncthreads();  // sX is gathered again for the next component
