@@ -46,7 +46,7 @@ constexpr int elems_per_block() {
 }
 
 template <int P, int Q, int KIND, bool EVEC, bool DOT, typename TV, typename TD, typename TC>
-__global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DIFFUSION ? 1 : sizeof(TC) == 4 ? (P == 6 ? 5 : 1) : P == 4 ? 4 : P >= 6 ? 3 : 1)
+__global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DIFFUSION ? 1 : sizeof(TC) == 4 ? (P == 6 ? 5 : 1) : (P == 4 || P == 5) ? 4 : P >= 6 ? 3 : 1)
     pa_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
                     const uint16_t* __restrict__ tile_slot, const TC* __restrict__ tabB,
                     const TC* __restrict__ tabG, const TD* __restrict__ qd,
@@ -95,17 +95,22 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   static_assert(NV == 1 || DIVV || (!DOT && !EVEC && (K0 == PAFEM_MASS || K0 == PAFEM_DIFFUSION)),
                 "vector operators: stored-D mass or diffusion, atomic scatter, no energy");
   // Line stride: odd, so that threads walking consecutive lines hit distinct banks.
-  constexpr int LC = D | 1;
+  // Stored-D scalar FP64 diffusion at p = 5 keeps the even stride D instead: the 1029 ->
+  // 882 values per element region are what lets four tiles share a CU (four waves per
+  // SIMD, with the unique dofs in the region tails below), which outweighs the conflicts
+  // (0.401 -> 0.386 ms at 1e7 dofs).
+  constexpr int LC =
+      (P == 5 && KIND == PAFEM_DIFFUSION && sizeof(TC) == 8) ? D : (D | 1);
   constexpr int ELEM = NCC * QQ * LC;
   static_assert(NA * D <= NCC * Q, "x-line outputs must fit the element region");
-  // XTAIL (scalar FP64 diffusion, p >= 6): the rows (c*Q + qy) of the element region
+  // XTAIL (scalar FP64 diffusion, p >= 5): the rows (c*Q + qy) of the element region
   // from NA*D on are dead from the back y-lines until the forward y-lines, while the
   // tile's unique-dof array is live exactly then (gather to forward x-lines, back
   // x-lines to the scatter).  Those rows of all elements of the tile are one
   // contiguous block after the leading rows, and the unique-dof array lives in it:
   // 11-12 KB less LDS per tile, three tiles per CU instead of two (one more barrier,
   // to clear the accumulators once the back y-lines have read the rows).
-  constexpr bool XTAIL = DIFF && NV == 1 && P >= 6 && sizeof(TC) == 8;
+  constexpr bool XTAIL = DIFF && NV == 1 && P >= 5 && sizeof(TC) == 8;
   constexpr int HR = XTAIL ? NA * D : NCC * Q;  // leading rows of an element
   constexpr int HEAD = HR * Q * LC, TAIL = ELEM - HEAD;
   static_assert(!XTAIL || NE * TAIL >= NE * DDD, "the unique dofs must fit the region tails");
@@ -162,11 +167,12 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   // (0.431 -> 0.419 ms at 1e7 dofs), p = 5 from 2 to 3 (0.434 -> 0.383 ms), FP32 p = 6
   // from 4 to 5 (0.462 -> 0.445 ms at 2e7 dofs), and FP64 p = 6..8 from 2 to 3 together
   // with the smaller LDS footprint of XTAIL (p = 6 0.382 -> 0.326 ms, p = 7 0.377 ->
-  // 0.342 ms; p = 8 one plane ahead, fewer spills).  Measured and not kept: p = 2 at 6
+  // 0.342 ms; p = 8 one plane ahead, fewer spills), and p = 5 from 3 to 4 with XTAIL,
+  // the even line stride and one plane ahead.  Measured and not kept: p = 2 at 6
   // waves (spills, 5% slower), p = 3 at 5 waves (spills, 4% slower), FP64 p = 6..8
   // streamed at 2 waves (1-2% slower).
   constexpr int PD = (K0 == PAFEM_DIFFUSION && NV == 1 && (sizeof(TC) == 8 ? P >= 4 : P == 6))
-                         ? (P == 8 ? 1 : 2)
+                         ? ((P == 5 || P == 8) ? 1 : 2)
                          : Q;
   TC dq[Q][NC];
   // stored diffusion D: components in pairs per point, one load per pair
