@@ -27,7 +27,7 @@ namespace {
 constexpr int kElasticValues = 11;
 
 template <int P, int Q>
-__global__ void __launch_bounds__(qdata_tile(Q) * Q * Q)
+__global__ void __launch_bounds__(qdata_tile(Q) * Q * Q, P == 7 ? 2 : 1)
     elasticity_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
                       const uint16_t* __restrict__ tile_slot, const double* __restrict__ tabB,
                       const double* __restrict__ tabG, const double* __restrict__ qd,
@@ -55,11 +55,13 @@ __global__ void __launch_bounds__(qdata_tile(Q) * Q * Q)
   auto at = [&](int c, int qy, int qx, int dz) -> double& {
     return W[((c * Q + qy) * Q + qx) * LC + dz];
   };
-  // Row q (forward stages) or column d (back stages) of a 1D table.  At p = 8 loaded per
-  // loop iteration (opaque_ptr): loading every entry of the unrolled stages up front
-  // overflowed the scalar registers (1784 spilled through VGPR lanes; 2.98 -> 1.42 ms at
-  // 1e7 dofs).  At p = 5..7, where 56-312 spill, the per-iteration loads were 1-6% slower.
-  constexpr bool OPQ = P >= 8;
+  // Row q (forward stages) or column d (back stages) of a 1D table.  At p = 7, 8 loaded
+  // per loop iteration (opaque_ptr): loading every entry of the unrolled stages up front
+  // overflowed the scalar registers (312 and 1784 spilled through VGPR lanes; p = 8 2.98 ->
+  // 1.42 ms at 1e7 dofs; at p = 7 it also frees the registers for the two-wave launch
+  // bound, 1.99 -> 1.23 ms).  At p = 5, 6, where 56-148 spill, the per-iteration loads
+  // were 1-6% slower.
+  constexpr bool OPQ = P >= 7;
   auto tab = [&](const double* t) {
     if constexpr (OPQ)
       return opaque_ptr(t);
