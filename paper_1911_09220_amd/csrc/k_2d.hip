@@ -188,8 +188,20 @@ __global__ void __launch_bounds__(k2dThreads)
   const int nu = tile_off[tile + 1] - u0;
   double* const W = sW + (act ? el : 0) * ELEM;
   auto at = [&](int a, int dy, int qx) -> double& { return W[(a * D + dy) * LQ + qx]; };
-  auto bB = [&](int q, int d) -> double { return tabB[q * D + d]; };
-  auto bG = [&](int q, int d) -> double { return tabG[q * D + d]; };
+  // Row q (forward stages) or column d (back stage) of a 1D table.  At p = 8 loaded per
+  // loop iteration (opaque_ptr): up front, the compiler spilled the 180 entries through
+  // VGPR lanes (1248 lane reads per wave against 750 FMAs).
+  constexpr bool OPQ = P >= 8;
+  auto tab = [&](const double* t) {
+    if constexpr (OPQ)
+      return opaque_ptr(t);
+    else
+      return t;
+  };
+  auto rowB = [&](int q) { return tab(tabB + q * D); };
+  auto rowG = [&](int q) { return tab(tabG + q * D); };
+  auto colB = [&](int d) { return tab(tabB + d); };
+  auto colG = [&](int d) { return tab(tabG + d); };
 
   // D of this thread's column qx = r
   double dq[Q][NC];
@@ -235,11 +247,13 @@ __global__ void __launch_bounds__(k2dThreads)
     for (int dx = 0; dx < D; ++dx) u[dx] = sX[slot[dx]];
 #pragma unroll
     for (int qx = 0; qx < Q; ++qx) {
+      const auto rb = rowB(qx);
+      const auto rg = rowG(qx);
       double b = 0.0, g = 0.0;
 #pragma unroll
       for (int dx = 0; dx < D; ++dx) {
-        b += bB(qx, dx) * u[dx];
-        if (DIFF) g += bG(qx, dx) * u[dx];
+        b += rb[dx] * u[dx];
+        if (DIFF) g += rg[dx] * u[dx];
       }
       at(0, r, qx) = b;
       if (DIFF) at(1, r, qx) = g;
@@ -260,29 +274,31 @@ __global__ void __launch_bounds__(k2dThreads)
     }
 #pragma unroll
     for (int qy = 0; qy < Q; ++qy) {
+      const auto rb = rowB(qy);
+      const auto rg = rowG(qy);
       if constexpr (DIFF) {
         double ux = 0.0, uy = 0.0;
 #pragma unroll
         for (int dy = 0; dy < D; ++dy) {
-          ux += bB(qy, dy) * a1[dy];  // G along x, B along y
-          uy += bG(qy, dy) * a0[dy];  // B along x, G along y
+          ux += rb[dy] * a1[dy];  // G along x, B along y
+          uy += rg[dy] * a0[dy];  // B along x, G along y
         }
         const double vx = dq[qy][0] * ux + dq[qy][1] * uy;
         const double vy = dq[qy][1] * ux + dq[qy][2] * uy;
         if (DOT) energy += ux * vx + uy * vy;
 #pragma unroll
         for (int dy = 0; dy < D; ++dy) {
-          t1[dy] += bB(qy, dy) * vx;
-          t0[dy] += bG(qy, dy) * vy;
+          t1[dy] += rb[dy] * vx;
+          t0[dy] += rg[dy] * vy;
         }
       } else {
         double u = 0.0;
 #pragma unroll
-        for (int dy = 0; dy < D; ++dy) u += bB(qy, dy) * a0[dy];
+        for (int dy = 0; dy < D; ++dy) u += rb[dy] * a0[dy];
         const double v = dq[qy][0] * u;
         if (DOT) energy += u * v;
 #pragma unroll
-        for (int dy = 0; dy < D; ++dy) t0[dy] += bB(qy, dy) * v;
+        for (int dy = 0; dy < D; ++dy) t0[dy] += rb[dy] * v;
       }
     }
 #pragma unroll
@@ -303,11 +319,13 @@ __global__ void __launch_bounds__(k2dThreads)
     }
 #pragma unroll
     for (int dx = 0; dx < D; ++dx) {
+      const auto cb = colB(dx);
+      const auto cg = colG(dx);
       double acc = 0.0;
 #pragma unroll
       for (int qx = 0; qx < Q; ++qx) {
-        acc += bB(qx, dx) * w0[qx];
-        if (DIFF) acc += bG(qx, dx) * w1[qx];
+        acc += cb[qx * D] * w0[qx];
+        if (DIFF) acc += cg[qx * D] * w1[qx];
       }
       atomicAdd(&sX[slot[dx]], acc);
     }

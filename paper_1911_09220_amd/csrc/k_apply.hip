@@ -144,8 +144,11 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   // loop iteration (opaque_ptr): the 180 FP64 table entries outgrow the scalar registers
   // and the compiler, loading them all up front, spilled them through VGPR lanes (1674
   // lane reads per wave; 0.483 -> 0.363 ms at 1e7 dofs with the changes below).  At
-  // p = 6, 7 its up-front loads spill far less and are 2-4% faster than the per-iteration ones.
-  constexpr bool OPQ = P >= 8;
+  // p = 6, 7 its up-front loads spill far less and are 2-4% faster than the per-iteration
+  // ones, except in the FP64 variant with the fused energy (the CG apply), where they
+  // spilled 374 / 804 / 1464 lane reads at p = 5 / 6 / 7 (CG iteration at p = 7 0.594 ->
+  // 0.542 ms with the per-iteration loads).
+  constexpr bool OPQ = P >= 8 || (DOT && !EVEC && P >= 5 && sizeof(TC) == 8);
   auto tab = [&](const TC* t) {
     if constexpr (OPQ)
       return opaque_ptr(t);
