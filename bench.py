@@ -315,10 +315,10 @@ def bench_hcurl(P, torch, orders, target, steps=10, warmup=2):
 
 
 def dg_algorithmic_bytes(p: int, ne: int, ndofs: int, nfaces: int, nbfaces: int) -> int:
-    """DG convection: x + y + 3 values per volume point + one value per face point + the
-    face records (3 ints per interior face, 2 per boundary face)."""
+    """DG convection: x + y + 3 values per volume point + one value per face point + per
+    face its code word (4 bytes) and the slot with its two elements' indices (8 bytes)."""
     q = p + 2
-    return 16 * ndofs + 24 * ne * q ** 3 + 8 * (nfaces + nbfaces) * q * q + 12 * nfaces + 8 * nbfaces
+    return 16 * ndofs + 24 * ne * q ** 3 + 8 * (nfaces + nbfaces) * q * q + 12 * (nfaces + nbfaces)
 
 
 def bench_dg(P, torch, orders, target, steps=10, warmup=2):

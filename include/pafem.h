@@ -119,7 +119,9 @@ typedef int32_t pafem_status;
  * flow leaves.  qdata: per volume point w adj(J) beta (3 values, the layout of
  * PAFEM_CONVECTION), then per interior face and per boundary face the Q^2 values
  * w (beta . N) at the face's Gauss points (N the area-weighted normal, outward from
- * the face's "-" element); coeff of pafem_qdata_assemble: device beta[3].
+ * the face's "-" element), then per face one 8-byte slot holding its "-" and "+"
+ * elements' indices (caller order, int32 each; 0 for the "+" side of a boundary face);
+ * coeff of pafem_qdata_assemble: device beta[3].
  * Unconstrained, atomic scatter, FP64, not symmetric (no diagonal or CG). */
 #define PAFEM_DG_CONVECTION 10
 

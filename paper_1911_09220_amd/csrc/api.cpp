@@ -409,8 +409,9 @@ pafem_status pafem_qdata_size(pafem_space space, int32_t kind, int32_t q1d, int6
               "operator kind and space family do not match (H1, Nedelec or L2)");
       *nvalues = qdata_values(space->s->ne, q1d, qdata_components(kind));
       if (kind == PAFEM_DG_CONVECTION)
+        // per face the Q^2 weights and one slot with its two elements' caller indices
         *nvalues += int64_t(space->s->faces.size() / kFaceInts + space->s->bfaces.size() / 2) *
-                    q1d * q1d;
+                    (q1d * q1d + 1);
     }
   });
 }

@@ -63,9 +63,12 @@ __device__ inline void geom_basis(int NG, int j, double x, double& val, double& 
 }
 
 // w_s w_t scale (beta . N) at the Q x Q Gauss points of every face, N = T_b x T_c
-// oriented outward from the face's first element (the interior face's "-" side)
+// oriented outward from the face's first element (the interior face's "-" side); after
+// them, one 8-byte slot per face with its two elements' caller indices (the dof blocks
+// the face kernel reads and writes), so the apply needs no lookup through elem_orig
 __global__ void dg_face_qdata_kernel(const int32_t* __restrict__ faces,
                                      const int32_t* __restrict__ bfaces, int64_t nf, int64_t nb,
+                                     const int32_t* __restrict__ orig,
                                      const double* __restrict__ gnodes, int NG,
                                      const double* __restrict__ pts,
                                      const double* __restrict__ wts, int Q,
@@ -80,6 +83,12 @@ __global__ void dg_face_qdata_kernel(const int32_t* __restrict__ faces,
   } else {
     e = bfaces[(g - nf) * 2 + 0];
     f = bfaces[(g - nf) * 2 + 1];
+  }
+  if (threadIdx.x == 0) {
+    int2 o;
+    o.x = orig[e];
+    o.y = g < nf ? orig[faces[g * kFaceInts + 1]] : 0;
+    reinterpret_cast<int2*>(fq + (nf + nb) * Q * Q)[g] = o;
   }
   int a, b, c;
   face_axes(f, a, b, c);
@@ -127,8 +136,8 @@ constexpr int faces_per_block() {
 template <int P>
 __global__ void __launch_bounds__(faces_per_block<P>() * (P + 2) * (P + 2))
     dg_face_kernel(const int32_t* __restrict__ faces, const int32_t* __restrict__ bfaces,
-                   int64_t nf, int64_t nb, const int32_t* __restrict__ orig,
-                   const double* __restrict__ tabB, const double* __restrict__ fq,
+                   int64_t nf, int64_t nb, const double* __restrict__ tabB,
+                   const double* __restrict__ fq,
                    const double* __restrict__ x, double* __restrict__ y) {
   constexpr int Q = P + 2, D = P + 1, QQ = Q * Q, DD = D * D, DDD = D * D * D;
   constexpr int FPB = faces_per_block<P>();
@@ -150,17 +159,16 @@ __global__ void __launch_bounds__(faces_per_block<P>() * (P + 2) * (P + 2))
   double* sP = sM + Q * D;
   auto bB = [&](int q, int d) { return tabB[q * D + d]; };
 
-  int em = 0, ep = 0, fm = 0, fp = 0, orient = 0;
+  int fm = 0, fp = 0, orient = 0;
+  int2 eo = {0, 0};  // the two sides' caller element indices
   if (act) {
+    eo = reinterpret_cast<const int2*>(fq + (nf + nb) * QQ)[g];
     if (inner) {
-      em = faces[g * kFaceInts + 0];
-      ep = faces[g * kFaceInts + 1];
       const int code = faces[g * kFaceInts + 2];
       fm = code & 7;
       fp = (code >> 3) & 7;
       orient = code >> 6;
     } else {
-      em = bfaces[(g - nf) * 2 + 0];
       fm = bfaces[(g - nf) * 2 + 1];
     }
   }
@@ -174,8 +182,8 @@ __global__ void __launch_bounds__(faces_per_block<P>() * (P + 2) * (P + 2))
     idx[c] = j;
     return idx[0] + D * (idx[1] + D * idx[2]);
   };
-  const int64_t baseM = act ? int64_t(orig[em]) * DDD : 0;
-  const int64_t baseP = (act && inner) ? int64_t(orig[ep]) * DDD : 0;
+  const int64_t baseM = int64_t(eo.x) * DDD;
+  const int64_t baseP = inner ? int64_t(eo.y) * DDD : 0;
 
   if (act && r < DD) {
     const int i = r % D, j = r / D;
@@ -255,7 +263,7 @@ void launch_faces_p(const DevSpace& sp, const double* tabB, const double* fq, co
   if (total == 0) return;
   const unsigned nblk = unsigned((total + FPB - 1) / FPB);
   hipLaunchKernelGGL((dg_face_kernel<P>), dim3(nblk), dim3(FPB * Q * Q), 0, st, sp.faces,
-                     sp.bfaces, sp.nfaces, sp.nbfaces, sp.elem_orig, tabB, fq, x, y);
+                     sp.bfaces, sp.nfaces, sp.nbfaces, tabB, fq, x, y);
 }
 
 }  // namespace
@@ -266,8 +274,8 @@ void launch_dg_face_qdata(const DevSpace& sp, int q1d, const double* beta3, doub
   if (total == 0) return;
   const double* t = sp.tables + table_offset_doubles(q1d, sp.p + 1, sp.ng);
   hipLaunchKernelGGL(dg_face_qdata_kernel, dim3(unsigned(total)), dim3(128), 0, st, sp.faces,
-                     sp.bfaces, sp.nfaces, sp.nbfaces, sp.gnodes, sp.ng, t, t + q1d, q1d, beta3,
-                     scale, fq);
+                     sp.bfaces, sp.nfaces, sp.nbfaces, sp.elem_orig, sp.gnodes, sp.ng, t, t + q1d,
+                     q1d, beta3, scale, fq);
   HIP_LAUNCH_CHECK_DG();
 }
 
