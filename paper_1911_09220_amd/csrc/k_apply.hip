@@ -46,7 +46,7 @@ constexpr int elems_per_block() {
 }
 
 template <int P, int Q, int KIND, bool EVEC, bool DOT, typename TV, typename TD, typename TC>
-__global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DIFFUSION ? 1 : sizeof(TC) == 4 ? (P == 6 ? 5 : 1) : (P == 4 || P == 5) ? 4 : P >= 6 ? 3 : 1)
+__global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DIFFUSION ? 1 : sizeof(TC) == 4 ? (P == 6 ? 5 : 1) : (P == 4 || P == 5) ? 4 : P == 2 ? 5 : P >= 6 ? 3 : 1)
     pa_apply_kernel(const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_dofs,
                     const uint16_t* __restrict__ tile_slot, const TC* __restrict__ tabB,
                     const TC* __restrict__ tabG, const TD* __restrict__ qd,
@@ -163,20 +163,21 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
   // D for this thread's z-line (qx, qy) = r: issued first so the HBM stream
   // overlaps the gather and the forward contractions (tile-interleaved: for each
   // (c, qz) the workgroup reads one contiguous run)
-  // Stored-D scalar diffusion at p >= 4 in FP64 and at p = 6 in FP32 (the refinement's
-  // inner operator): only the first PD planes are loaded here and each later plane PD
-  // z-iterations ahead of its use.  The registers of the other planes lift the occupancy,
-  // with the launch bound's request where needed: FP64 p = 4 from 3 to 4 waves per SIMD
-  // (0.431 -> 0.419 ms at 1e7 dofs), p = 5 from 2 to 3 (0.434 -> 0.383 ms), FP32 p = 6
-  // from 4 to 5 (0.462 -> 0.445 ms at 2e7 dofs), and FP64 p = 6..8 from 2 to 3 together
-  // with the smaller LDS footprint of XTAIL (p = 6 0.382 -> 0.326 ms, p = 7 0.377 ->
-  // 0.342 ms; p = 8 one plane ahead, fewer spills), and p = 5 from 3 to 4 with XTAIL,
-  // the even line stride and one plane ahead.  Measured and not kept: p = 2 at 6
-  // waves (spills, 5% slower), p = 3 at 5 waves (spills, 4% slower), FP64 p = 6..8
-  // streamed at 2 waves (1-2% slower).
-  constexpr int PD = (K0 == PAFEM_DIFFUSION && NV == 1 && (sizeof(TC) == 8 ? P >= 4 : P == 6))
-                         ? ((P == 5 || P == 8) ? 1 : 2)
-                         : Q;
+  // Stored-D scalar diffusion at p = 2 and p >= 4 in FP64 and at p = 6 in FP32 (the
+  // refinement's inner operator): only the first PD planes are loaded here and each later
+  // plane PD z-iterations ahead of its use.  The registers of the other planes lift the
+  // occupancy, with the launch bound's request where needed: FP64 p = 4 from 3 to 4 waves
+  // per SIMD (0.431 -> 0.419 ms at 1e7 dofs), p = 5 from 2 to 3 (0.434 -> 0.383 ms), FP32
+  // p = 6 from 4 to 5 (0.462 -> 0.445 ms at 2e7 dofs), FP64 p = 6..8 from 2 to 3 together
+  // with the smaller LDS footprint of XTAIL (p = 6 0.382 -> 0.326 ms, p = 7 0.377 -> 0.342
+  // ms; p = 8 one plane ahead, fewer spills), p = 5 from 3 to 4 with XTAIL, the even line
+  // stride and one plane ahead, and p = 2 from 4 to 5 (0.777 -> 0.770 ms, its CG iteration
+  // 0.988 -> 0.968 ms).  Measured and not kept: p = 2 at 6 waves (spills, 12% slower), p = 3
+  // at 5 waves (spills, 4% slower), FP64 p = 6..8 streamed at 2 waves (1-2% slower), FP32
+  // p = 6 at 6 waves with XTAIL (spills; the refinement 8% slower).
+  constexpr bool STREAM_D =
+      K0 == PAFEM_DIFFUSION && NV == 1 && (sizeof(TC) == 8 ? (P == 2 || P >= 4) : P == 6);
+  constexpr int PD = STREAM_D ? ((P == 5 || P == 8) ? 1 : 2) : Q;
   TC dq[Q][NC];
   // stored diffusion D: components in pairs per point, one load per pair
   constexpr bool PAIRS = (NCT == 6);
