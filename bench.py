@@ -901,6 +901,8 @@ def main():
             k: round(v["hbm_frac"] * HBM_PEAK_GBS / copy["GBps_read_plus_write"], 4)
             for k, v in per_p.items()},
         "device_copy": copy,
+        "device": {"name": torch.cuda.get_device_name(0),
+                   "arch": getattr(torch.cuda.get_device_properties(0), "gcnArchName", None)},
         "cg_time_to_1e-8": cg,
     }
     forms = [f for f in args.forms.split(",") if f]

@@ -510,6 +510,17 @@ pafem_status pafem_net_set_params(pafem_net net, const float* host_params, void*
 pafem_status pafem_net_get_params(pafem_net net, float* host_params, void* stream);
 /* Gradients of the last backward pass (host FP32).  SYNCHRONOUS. */
 pafem_status pafem_net_get_grads(pafem_net net, float* host_grads, void* stream);
+/* Training state for checkpoint and resume.  host_state [3][nparams] f32: the
+ * parameters (same order as pafem_net_set_params), then Adam's first and second
+ * moment estimates; *step / step: the number of Adam steps taken, which sets the
+ * bias correction of the next one.  set_state clears the kept gradients; the
+ * next pafem_net_adam_step then continues as if training had not stopped.
+ * Host memory is the caller's.  EINVAL on a null pointer or a negative step.
+ * SYNCHRONOUS.  (Checkpoints of the state are an addition to the paper's
+ * data-collection output.) */
+pafem_status pafem_net_get_state(pafem_net net, float* host_state, int32_t* step, void* stream);
+pafem_status pafem_net_set_state(pafem_net net, const float* host_state, int32_t step,
+                                 void* stream);
 /* out [rows][out] f32 = N(x), x device bf16 [rows][in]. */
 pafem_status pafem_net_forward(pafem_net net, const uint16_t* x, float* out, int64_t rows,
                                void* stream);

@@ -314,6 +314,44 @@ pafem_status pafem_net_get_grads(pafem_net net, float* host_grads, void* stream)
   });
 }
 
+pafem_status pafem_net_get_state(pafem_net net, float* host_state, int32_t* step, void* stream) {
+  return guarded([&] {
+    require(net && host_state && step, PAFEM_EINVAL, "null pointer argument");
+    const Net& n = net->net;
+    auto st = static_cast<hipStream_t>(stream);
+    const size_t count = size_t(n.d.nparams);
+    hip_check(hipMemcpyAsync(host_state, n.params(), count * 4, hipMemcpyDeviceToHost, st),
+              "state params");
+    hip_check(hipMemcpyAsync(host_state + count, n.at<float>(n.L.m), count * 4,
+                             hipMemcpyDeviceToHost, st), "state adam m");
+    hip_check(hipMemcpyAsync(host_state + 2 * count, n.at<float>(n.L.v), count * 4,
+                             hipMemcpyDeviceToHost, st), "state adam v");
+    hip_check(hipStreamSynchronize(st), "state sync");
+    *step = n.step;
+  });
+}
+
+pafem_status pafem_net_set_state(pafem_net net, const float* host_state, int32_t step,
+                                 void* stream) {
+  return guarded([&] {
+    require(net && host_state, PAFEM_EINVAL, "null pointer argument");
+    require(step >= 0, PAFEM_EINVAL, "negative Adam step count");
+    Net& n = net->net;
+    auto st = static_cast<hipStream_t>(stream);
+    const size_t count = size_t(n.d.nparams);
+    hip_check(hipMemcpyAsync(n.params(), host_state, count * 4, hipMemcpyHostToDevice, st),
+              "state params");
+    hip_check(hipMemcpyAsync(n.at<float>(n.L.m), host_state + count, count * 4,
+                             hipMemcpyHostToDevice, st), "state adam m");
+    hip_check(hipMemcpyAsync(n.at<float>(n.L.v), host_state + 2 * count, count * 4,
+                             hipMemcpyHostToDevice, st), "state adam v");
+    hip_check(hipMemsetAsync(n.grads(), 0, count * 4, st), "grads");
+    n.step = step;
+    n.refresh_bf16(st);
+    hip_check(hipStreamSynchronize(st), "state sync");
+  });
+}
+
 pafem_status pafem_net_forward(pafem_net net, const uint16_t* x, float* out, int64_t rows,
                                void* stream) {
   return guarded([&] {

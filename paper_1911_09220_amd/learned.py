@@ -102,30 +102,42 @@ class _ZeroFeatures:
 
 
 def train(net, samples, steps=500, lr=2e-3, lr_decay=0.5, decay_every=200, seed=0, log_every=0,
-          log=print):
+          log=print, start=0, checkpoint=None, checkpoint_every=0):
     """Adam on the loss of randomly drawn samples.
 
     samples: list of (op, feats, diag, r, e), a CompactFields or its without_features()
-    view.  Returns the per-step
-    losses (host).
+    view.  start: the training step to begin at; the sample draws and learning-rate
+    decays of the steps before it are replayed without work, so a run resumed at a
+    checkpoint's train_step (network state restored with Net.set_state) draws the
+    same samples at the same rates as one that never stopped.  checkpoint: a path that
+    receives the training state (checkpoint.save_training) every checkpoint_every
+    steps and at the end.  Returns the losses of steps start .. start + steps - 1
+    (host).
     """
     import torch
+    from . import checkpoint as ckpt
     rng = np.random.default_rng(seed)
     works = {}
     compact = isinstance(samples, (CompactFields, _ZeroFeatures))
     device = samples.qd.device if compact else samples[0][3].device
     loss_dev = torch.zeros(steps, dtype=torch.float64, device=device)
     cur_lr = lr
-    for t in range(steps):
+    for t in range(start + steps):
         if decay_every and t and t % decay_every == 0:
             cur_lr *= lr_decay
         i = int(rng.integers(len(samples)))
+        if t < start:
+            continue
         op, feats, diag, r, e = samples.draw(i) if compact else samples[i]
         w = works.get(id(op))
         if w is None:
             w = works[id(op)] = P._learned_work(op)
-        P.learned_loss_grad(net, op, feats, diag, r, e, loss=loss_dev[t:t + 1], work=w)
+        P.learned_loss_grad(net, op, feats, diag, r, e, loss=loss_dev[t - start:t - start + 1],
+                            work=w)
         net.adam_step(cur_lr)
         if log_every and (t + 1) % log_every == 0:
-            log(f"train step {t + 1}: loss {float(loss_dev[t]):.4f}")
+            log(f"train step {t + 1}: loss {float(loss_dev[t - start]):.4f}")
+        if checkpoint is not None and (t + 1 == start + steps or
+                                       (checkpoint_every and (t + 1) % checkpoint_every == 0)):
+            ckpt.save_training(checkpoint, net.get_state(), t + 1, seed)
     return loss_dev.cpu().numpy()

@@ -133,6 +133,8 @@ def _load():
         "pafem_net_forward": (I32, [P, P, P, I64, P]),
         "pafem_net_backward": (I32, [P, P, P, I64, P]),
         "pafem_net_adam_step": (I32, [P, C.c_float, P]),
+        "pafem_net_get_state": (I32, [P, P, P, P]),
+        "pafem_net_set_state": (I32, [P, P, I32, P]),
         "pafem_learned_features": (I32, [P, P, I32, P, P]),
         "pafem_learned_workspace_bytes": (I32, [P, C.POINTER(SZ)]),
         "pafem_learned_precond": (I32, [P, P, P, P, P, P, P, SZ, P]),
@@ -892,6 +894,24 @@ class Net:
         flat = np.empty(self.nparams, dtype=np.float32)
         _check(lib.pafem_net_get_grads(self.handle, _np_ptr(flat), _stream()))
         return self.unflatten(flat)
+
+    def get_state(self):
+        """Training state: {"params", "adam_m", "adam_v"} (flat FP32) and "adam_step"."""
+        flat = np.empty(3 * self.nparams, dtype=np.float32)
+        step = C.c_int32()
+        _check(lib.pafem_net_get_state(self.handle, _np_ptr(flat), C.byref(step), _stream()))
+        n = self.nparams
+        return {"params": flat[:n], "adam_m": flat[n:2 * n], "adam_v": flat[2 * n:],
+                "adam_step": int(step.value)}
+
+    def set_state(self, state):
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(state[k], dtype=np.float32).ravel()
+                                                    for k in ("params", "adam_m", "adam_v")]))
+        if flat.size != 3 * self.nparams:
+            raise ValueError(f"state holds {flat.size // 3} parameters, the network "
+                             f"{self.nparams}")
+        _check(lib.pafem_net_set_state(self.handle, _np_ptr(flat), int(state["adam_step"]),
+                                       _stream()))
 
     def forward(self, x_bf16, rows):
         import torch
