@@ -25,6 +25,18 @@ this project's own, and the GPU library follows the same ones step for step:
   number of Jacobi-PCG iterations from zero (a fixed but nonlinear map, hence the
   flexible CG outside), or an exact solve.
 
+* Levels in the mesh size (h-multigrid, the paper names h- and p-multigrid together):
+  a mesh refined uniformly (:func:`refine`: every hexahedron split into 8 children that
+  cover the octants of its reference cube, axes kept) holds the coarse mesh's space,
+  because each child's map is the parent's map restricted to the octant.  The
+  prolongation from a coarse level on the parent mesh to a fine level on the refined
+  mesh is again interpolation: the coarse function on the parent evaluated at the
+  child's nodes, i.e. the coarse basis at the parent reference points (o + xhat) / 2
+  of octant o (:func:`h_interpolation`).  A level's coefficient is the mean of the
+  finest coefficient over every finest point inside the level's element
+  (:func:`level_coefficient`); children are numbered 8 e + o, so those points are
+  contiguous.  :func:`build_hp_levels` mixes both kinds of step.
+
 Pins (tests/test_oracle_pmg.py): interpolation reproduces functions of the coarse
 space exactly and sums to one per row; P^T K_f P equals the coarse stiffness (and
 mass) matrix on affine meshes with a constant coefficient (both are the exact
@@ -32,12 +44,17 @@ Galerkin matrices there); Chebyshev error equals the scaled Chebyshev polynomial
 per eigenvalue; the power iteration converges to the largest eigenvalue from below;
 a V-cycle whose coarse level is the fine space solved exactly returns A^-1 b; the
 cycle with an exact coarse solve is symmetric positive definite; closed-form means.
+Refinement (tests/test_oracle_hmg.py): child vertices and quadrature points are the
+parent's map at the octant's points, volumes add up, the refined mesh is conforming
+(its H1 space has the dof count of the lattice twice as fine); h-interpolation
+reproduces linear functions and, on affine meshes, P^T A_f P is the coarse matrix.
 """
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .basis import tensor_basis, tensor_points
+from .geometry import map_points
 from .quadrature import gauss_lobatto
 from .solvers import pcg
 from .space import H1Space
@@ -168,4 +185,112 @@ def build_levels(mesh, orders, coeff=None, mean="arithmetic", starts=None, power
         spaces.append(S)
     for l in range(len(orders) - 1):
         levels[l]["P"] = interpolation(mesh, orders[l + 1], orders[l])
+    return levels, spaces
+
+
+# reference corner of each slot of the usual hexahedron vertex order
+_SLOT_CORNER = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                         [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]])
+
+
+def _octant(o):
+    return np.array([o & 1, (o >> 1) & 1, (o >> 2) & 1], dtype=np.float64)
+
+
+def refine(mesh):
+    """Uniform refinement of a hexahedral mesh dict.
+
+    Child 8 e + o (o = ox + 2 oy + 4 oz) of element e covers the parent's reference
+    box [o/2, (o+1)/2] with its axes along the parent's.  The fine vertices are the
+    nodes of the parent mesh's order-2 H1 space (corners, edge midpoints, face and cell
+    centres of every reference cube), identified topologically by that space and placed
+    by the parent's map; a quadratic geometry gives each child the parent's map at its
+    27 nodes, so in both cases the child's map is the parent's on the octant."""
+    S2 = H1Space(mesh, 2)
+    X2, _ = map_points(mesh, tensor_points(np.array([0.0, 0.5, 1.0])))     # [E, 27, 3]
+    E = S2.elem_dofs.shape[0]
+    verts = np.empty((S2.ndofs, 3))
+    verts[S2.elem_dofs.ravel()] = X2.reshape(-1, 3)
+    hexes = np.empty((E, 8, 8), dtype=np.int64)
+    for o in range(8):
+        off = _octant(o).astype(np.int64)
+        for s, c in enumerate(_SLOT_CORNER):
+            i, j, k = off + c
+            hexes[:, o, s] = S2.elem_dofs[:, i + 3 * j + 9 * k]
+    out = {"vertices": verts, "hex": hexes.reshape(E * 8, 8)}
+    if mesh.get("geom_order", 1) == 2 and mesh.get("geom_nodes") is not None:
+        g = np.empty((E, 8, 27, 3))
+        ref = tensor_points(np.array([0.0, 0.5, 1.0]))
+        for o in range(8):
+            g[:, o], _ = map_points(mesh, (_octant(o) + ref) / 2.0)
+        out["geom_order"] = 2
+        out["geom_nodes"] = g.reshape(E * 8, 27, 3)
+    return out
+
+
+def h_interpolation(coarse_mesh, fine_mesh, pc, pf, free_only=True):
+    """CSR prolongation [ndof_f, ndof_c] from order pc on ``coarse_mesh`` to order pf
+    on ``fine_mesh = refine(coarse_mesh)``: P[i, j] = phi^c_j at fine node i, the
+    coarse basis of the parent evaluated at (o + xhat_i) / 2 for a child in octant o."""
+    Sc, Sf = H1Space(coarse_mesh, pc), H1Space(fine_mesh, pf)
+    Ec = Sc.elem_dofs.shape[0]
+    assert Sf.elem_dofs.shape[0] == 8 * Ec, "fine mesh is not a refinement of the coarse one"
+    xf = tensor_points(gauss_lobatto(pf + 1))
+    rows, cols, vals = [], [], []
+    for o in range(8):
+        PE, _ = tensor_basis(gauss_lobatto(pc + 1), (_octant(o) + xf) / 2.0)
+        child = 8 * np.arange(Ec) + o
+        rows.append(np.repeat(Sf.elem_dofs[child], PE.shape[1], axis=1).ravel())
+        cols.append(np.tile(Sc.elem_dofs, (1, PE.shape[0])).ravel())
+        vals.append(np.broadcast_to(PE.ravel()[None, :], (Ec, PE.size)).ravel())
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    key = rows.astype(np.int64) * Sc.ndofs + cols
+    _, first = np.unique(key, return_index=True)
+    P = sp.csr_matrix((vals[first], (rows[first], cols[first])), shape=(Sf.ndofs, Sc.ndofs))
+    if free_only:
+        P = sp.diags((~Sf.boundary).astype(float)) @ P @ sp.diags((~Sc.boundary).astype(float))
+    return P.tocsr()
+
+
+def level_coefficient(coeff, n_elements, q, kind="arithmetic"):
+    """Coefficient [n_elements, q^3] of a coarse level: the mean of the finest
+    coefficient [E_0, Q^3] over the finest points inside each of the level's elements
+    (a contiguous block of E_0 / n_elements finest elements), at every point."""
+    c = np.asarray(coeff, dtype=np.float64).reshape(n_elements, -1)
+    return np.repeat(element_mean(c, kind)[:, None], q ** 3, axis=1)
+
+
+def build_hp_levels(meshes, plan, coeff=None, mean="arithmetic", starts=None, power_iters=20):
+    """Levels for :func:`vcycle` in mesh size and order.  ``meshes[0]`` is the finest
+    mesh and ``meshes[k] = refine(meshes[k+1])``; ``plan`` lists (mesh index, order)
+    per level, finest first, each step either lowering the order on one mesh or moving
+    to the parent mesh (order not raised).  Same conventions as :func:`build_levels`."""
+    from .forms import assemble, constrain, element_stiffness
+    levels, spaces = [], []
+    for l, (m, p) in enumerate(plan):
+        mesh = meshes[m]
+        S = H1Space(mesh, p)
+        q = p + 2
+        if coeff is None:
+            c = None
+        elif l == 0:
+            c = coeff
+        else:
+            c = level_coefficient(coeff, S.elem_dofs.shape[0], q, mean)
+        K = assemble(S, element_stiffness(mesh, p, q, c))
+        Kc, _ = constrain(K, np.zeros(S.ndofs), S.boundary)
+        d = Kc.diagonal()
+        lv = {"A": Kc, "diag": d, "p": p, "mesh": m}
+        if starts is not None:
+            lv["lmax"] = power_lmax(Kc, d, np.where(S.boundary, 0.0, starts[l]), power_iters)
+        levels.append(lv)
+        spaces.append(S)
+    for l in range(len(plan) - 1):
+        (mf, pf), (mc, pc) = plan[l], plan[l + 1]
+        if mc == mf:
+            levels[l]["P"] = interpolation(meshes[mf], pc, pf)
+        elif mc == mf + 1:
+            levels[l]["P"] = h_interpolation(meshes[mc], meshes[mf], pc, pf)
+        else:
+            raise ValueError("a level step moves to the same mesh or its parent")
     return levels, spaces
