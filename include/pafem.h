@@ -196,6 +196,24 @@ pafem_status pafem_mesh_create_hex(int64_t nv, const double* xyz, int64_t ne,
  * Errors: EINVAL (index out of range, repeated vertex). */
 pafem_status pafem_mesh_create_quad(int64_t nv, const double* xy, int64_t ne, const int64_t* quad4,
                                     pafem_mesh* out);
+/* Uniform refinement of a hexahedral mesh ("Meshes"; the nested mesh hierarchy of
+ * multigrid in the mesh size, "Scalable Linear Solvers").  Child 8 e + o
+ * (o = ox + 2 oy + 4 oz) of element e covers the octant [o/2, (o+1)/2]^3 of e's
+ * reference cube with its axes along e's, so its map is e's map on the octant and the
+ * coarse mesh's spaces lie in the refined mesh's.  Vertices: the coarse ones keep
+ * their ids, then one per edge midpoint, face centre and element centre (placed by
+ * the parent's map); a quadratic geometry gives each child the parent's map at its 27
+ * nodes.  The refined mesh records its parent, for transfers between spaces of the
+ * two (pafem_prolongate); it does not reference the coarse object, which may be
+ * destroyed first.  Host call.  Errors: EUNSUPPORTED (quadrilateral mesh), ESHAPE
+ * (more than 2^27 coarse elements). */
+pafem_status pafem_mesh_refine(pafem_mesh coarse, pafem_mesh* fine);
+/* Vertex and element counts.  Host call. */
+pafem_status pafem_mesh_info(pafem_mesh mesh, int64_t* nv, int64_t* ne);
+/* Copies of the vertex coordinates (host [nv][dim] f64) and the connectivity (host
+ * [ne][8], or [ne][4] for quadrilaterals, int64); either pointer may be NULL.  Host
+ * call. */
+pafem_status pafem_mesh_vertices(pafem_mesh mesh, double* xyz, int64_t* elems);
 void pafem_mesh_destroy(pafem_mesh mesh);
 
 /* --------------------------------------------------------------- space --- */
@@ -600,14 +618,26 @@ pafem_status pafem_coeff_element_mean(pafem_space space, int32_t kind, const dou
                                       void* stream);
 
 /* Prolongation from the order-pc space `coarse` to the order-pf space `fine`
- * (pc <= pf, same mesh): yf[i] = sum_j phi^c_j(x_i) xc[j] over free coarse dofs
- * j, for free fine dofs i (the coarse function evaluated at the fine node);
- * essential fine entries are set to 0, or left unchanged when add != 0, in
- * which case the result is added to yf.  Device f64 vectors.  Asynchronous.
- * Deterministic (each fine dof is written by one element).
- * Errors: EINVAL (different meshes, pc > pf, order above 8). */
+ * (pc <= pf; both on one mesh, or `fine` on pafem_mesh_refine of `coarse`'s mesh):
+ * yf[i] = sum_j phi^c_j(x_i) xc[j] over free coarse dofs j, for free fine dofs i
+ * (the coarse function evaluated at the fine node; across a refinement, the parent's
+ * basis at the child's nodes mapped into the parent's octant); essential fine
+ * entries are set to 0, or left unchanged when add != 0, in which case the result
+ * is added to yf.  Device f64 vectors.  Asynchronous.  Deterministic (each fine dof
+ * is written by one element).
+ * Errors: EINVAL (unrelated meshes, pc > pf, order above 8). */
 pafem_status pafem_prolongate(pafem_space coarse, pafem_space fine, const double* xc, double* yf,
                               int32_t add, void* stream);
+
+/* coeff_parent_mean: out [Ec][q1d_out^3] f64 = the mean (kind as above) of the
+ * coefficient coeff [Ef][q1d_in^3] given on `fine` (a space on pafem_mesh_refine
+ * of `coarse`'s mesh) over the points of each coarse element's 8 children, at every
+ * point of the coarse element; caller element order (children 8 e .. 8 e + 7).  The
+ * coefficient of a multigrid level one refinement coarser.  Device arrays.
+ * Asynchronous.  Errors: EINVAL (kind, sizes, unrelated meshes). */
+pafem_status pafem_coeff_parent_mean(pafem_space fine, pafem_space coarse, int32_t kind,
+                                     const double* coeff, int32_t q1d_in, int32_t q1d_out,
+                                     double* out, void* stream);
 
 /* Restriction, the transpose of the prolongation on free dofs:
  * rc = P^T (bf - yf) (yf may be NULL), 0 on essential coarse dofs.  Sums with
@@ -648,7 +678,9 @@ typedef struct {
 
 /* A V-cycle hierarchy over nlevels >= 1 levels, finest first: ops[l] an f64
  * constrained diffusion operator (PAFEM_DIFFUSION or PAFEM_DIFFUSION_GEOM) of
- * order p_l (non-increasing), all on one mesh object; diags[l] its diagonal
+ * order p_l (non-increasing); each level's space is on the previous level's mesh
+ * (a step in the order) or on the mesh that one was refined from
+ * (pafem_mesh_refine: a step in the mesh size, h-multigrid); diags[l] its diagonal
  * (device f64, caller-owned, kept by pointer); lmax[l] the largest-eigenvalue
  * estimate of diags[l]^-1 ops[l] (pafem_op_lambda_max).  The operators and
  * diagonals must outlive the hierarchy.  Orders up to 8. */

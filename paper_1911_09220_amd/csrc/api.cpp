@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 
@@ -135,7 +136,7 @@ extern "C" {
 
 const char* pafem_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pafem_version(void) { return 273; }
+int32_t pafem_version(void) { return 274; }
 
 int32_t pafem_set_graph_mode(int32_t mode) {
   return graph_mode_flag().exchange(mode != 0 ? 1 : 0);
@@ -167,6 +168,7 @@ pafem_status pafem_mesh_create_hex(int64_t nv, const double* xyz, int64_t ne, co
     m->m.hex.assign(hex8, hex8 + ne * 8);
     m->m.geom_order = geom_order;
     if (geom_order == 2) m->m.gnodes.assign(geom_nodes, geom_nodes + ne * 27 * 3);
+    m->m.id = next_mesh_id();
     *out = m;
   });
 }
@@ -194,7 +196,37 @@ pafem_status pafem_mesh_create_quad(int64_t nv, const double* xy, int64_t ne, co
     m->m.xyz.assign(xy, xy + nv * 2);
     m->m.quad.assign(quad4, quad4 + ne * 4);
     m->m.geom_order = 1;
+    m->m.id = next_mesh_id();
     *out = m;
+  });
+}
+
+pafem_status pafem_mesh_refine(pafem_mesh coarse, pafem_mesh* fine) {
+  return guarded([&] {
+    require(coarse && fine, PAFEM_EINVAL, "null pointer argument");
+    auto m = std::make_unique<pafem_mesh_s>();
+    refine_mesh(coarse->m, m->m);
+    *fine = m.release();
+  });
+}
+
+pafem_status pafem_mesh_info(pafem_mesh mesh, int64_t* nv, int64_t* ne) {
+  return guarded([&] {
+    require(mesh, PAFEM_EINVAL, "null mesh");
+    if (nv) *nv = mesh->m.nv;
+    if (ne) *ne = mesh->m.ne;
+  });
+}
+
+pafem_status pafem_mesh_vertices(pafem_mesh mesh, double* xyz, int64_t* elems) {
+  return guarded([&] {
+    require(mesh, PAFEM_EINVAL, "null mesh");
+    const Mesh& m = mesh->m;
+    if (xyz) std::copy(m.xyz.begin(), m.xyz.end(), xyz);
+    if (elems) {
+      const std::vector<int64_t>& conn = m.dim == 2 ? m.quad : m.hex;
+      std::copy(conn.begin(), conn.end(), elems);
+    }
   });
 }
 

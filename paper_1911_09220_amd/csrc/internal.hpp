@@ -160,7 +160,23 @@ struct Mesh {
   std::vector<int64_t> quad;   // [ne][4] counter-clockwise (dim 2)
   int geom_order = 1;
   std::vector<double> gnodes;  // [ne][27][3] for geom_order 2
+  uint64_t id = 0;             // unique per mesh object (next_mesh_id)
+  uint64_t parent_id = 0;      // id of the mesh this one refines uniformly (0: none)
+  std::vector<int32_t> elem_order;  // device element order of a refined mesh (else Morton)
 };
+
+uint64_t next_mesh_id();
+// Device element order of the mesh: Morton order of the element centroids, or for a
+// refined mesh the children 8 e + 0..7 of each parent e in the parent's device order,
+// so that device element k of the refined mesh lies in device element k / 8 of its
+// parent, octant k % 8.
+std::vector<int32_t> mesh_element_order(const Mesh& m);
+// Uniform refinement of a hexahedral mesh: child 8 e + o (o = ox + 2 oy + 4 oz) of
+// element e covers the octant [o/2, (o+1)/2] of its reference cube, axes kept; new
+// vertices at the edge midpoints, face and cell centres of the parent's map (coarse
+// vertices keep their ids, then one vertex per edge, face and element); a quadratic
+// geometry gives each child the parent's map at its 27 nodes.
+void refine_mesh(const Mesh& c, Mesh& f);
 
 // space families: nodal H1 (Gauss-Lobatto nodes) and Nedelec H(curl)
 constexpr int kFamilyH1 = 0;

@@ -4,7 +4,9 @@
 //
 // * Transfers between two H1 spaces of one mesh: both spaces share the device element
 //   order (a Morton order of the mesh's elements), so element k of one is element k of
-//   the other.  Prolongation evaluates the coarse function at the fine nodes of each
+//   the other.  Across a uniform refinement (h-multigrid) fine element k is child k % 8
+//   of coarse element k / 8, and each axis takes the table of its half of the parent's
+//   interval.  Prolongation evaluates the coarse function at the fine nodes of each
 //   element by three one-axis contractions with the 1D table I[xf][xc] = phi^c_xc at
 //   fine node xf (sizes fixed at compile time per pair of orders); each fine dof is
 //   written by one element only, its owner (the first entry of its transposed-map list,
@@ -35,8 +37,17 @@ struct TransferArgs {
   const int32_t* gmap_c;  // coarse element->dof map (~g on essential dofs)
   const int32_t* gmap_f;  // fine element->dof map
   const uint32_t* own_f;  // fine owner bits: node is the first occurrence of its dof
-  int64_t ne;
+  int64_t ne;             // fine elements
+  int h;                  // 1: the fine mesh refines the coarse one
 };
+
+// coarse element of fine element e, and the table half of axis `axis`
+__device__ __forceinline__ int64_t parent_of(const TransferArgs& a, int64_t e) {
+  return a.h ? e >> 3 : e;
+}
+__device__ __forceinline__ int half_of(const TransferArgs& a, int64_t e, int axis) {
+  return a.h ? int((e >> axis) & 1) : 0;
+}
 
 template <int DC, int DF>
 struct TransferShape {
@@ -66,23 +77,26 @@ __global__ void __launch_bounds__(kMgThreads)
   const int64_t e0 = int64_t(blockIdx.x) * NEL;
   const int nel = int(min(int64_t(NEL), a.ne - e0));
   for (int i = threadIdx.x; i < nel * DC3; i += kMgThreads) {
-    const int32_t g = a.gmap_c[e0 * DC3 + i];
+    const int el = i / DC3, l = i - el * DC3;
+    const int32_t g = a.gmap_c[parent_of(a, e0 + el) * DC3 + l];
     u[i] = g >= 0 ? xc[g] : 0.0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nel * DC * DC * DF; i += kMgThreads) {
     const int xf = i % DF, line = i / DF;  // line = (el, zc, yc)
+    const double* T = I.v[half_of(a, e0 + line / (DC * DC), 0)];
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < DC; ++k) s += I.v[xf * DC + k] * u[line * DC + k];
+    for (int k = 0; k < DC; ++k) s += T[xf * DC + k] * u[line * DC + k];
     t1[i] = s;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nel * DC * DF * DF; i += kMgThreads) {
     const int xf = i % DF, yf = (i / DF) % DF, ez = i / (DF * DF);  // ez = (el, zc)
+    const double* T = I.v[half_of(a, e0 + ez / DC, 1)];
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < DC; ++k) s += I.v[yf * DC + k] * t1[(ez * DC + k) * DF + xf];
+    for (int k = 0; k < DC; ++k) s += T[yf * DC + k] * t1[(ez * DC + k) * DF + xf];
     t2[i] = s;
   }
   __syncthreads();
@@ -91,9 +105,10 @@ __global__ void __launch_bounds__(kMgThreads)
     const int xf = l % DF, yf = (l / DF) % DF, zf = l / (DF * DF);
     const int64_t e = e0 + el;
     if (!owns(a.own_f, S::W, e, l)) continue;
+    const double* T = I.v[half_of(a, e, 2)];
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < DC; ++k) s += I.v[zf * DC + k] * t2[((el * DC + k) * DF + yf) * DF + xf];
+    for (int k = 0; k < DC; ++k) s += T[zf * DC + k] * t2[((el * DC + k) * DF + yf) * DF + xf];
     const int32_t g = a.gmap_f[e * DF3 + l];
     const int32_t gi = g >= 0 ? g : ~g;
     const double v = g >= 0 ? s : 0.0;  // free rows only
@@ -125,26 +140,30 @@ __global__ void __launch_bounds__(kMgThreads)
   __syncthreads();
   for (int i = threadIdx.x; i < nel * DC * DF * DF; i += kMgThreads) {
     const int xf = i % DF, yfi = (i / DF) % DF, zc = (i / (DF * DF)) % DC, el = i / (DC * DF * DF);
+    const double* T = I.v[half_of(a, e0 + el, 2)];
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < DF; ++k) s += I.v[k * DC + zc] * rf[((el * DF + k) * DF + yfi) * DF + xf];
+    for (int k = 0; k < DF; ++k) s += T[k * DC + zc] * rf[((el * DF + k) * DF + yfi) * DF + xf];
     t2[i] = s;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nel * DC * DC * DF; i += kMgThreads) {
     const int xf = i % DF, yc = (i / DF) % DC, ez = i / (DF * DC);  // ez = (el, zc)
+    const double* T = I.v[half_of(a, e0 + ez / DC, 1)];
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < DF; ++k) s += I.v[k * DC + yc] * t2[(ez * DF + k) * DF + xf];
+    for (int k = 0; k < DF; ++k) s += T[k * DC + yc] * t2[(ez * DF + k) * DF + xf];
     t1[i] = s;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nel * DC3; i += kMgThreads) {
     const int xc = i % DC, line = i / DC;  // line = (el, zc, yc)
+    const int el = line / (DC * DC);
+    const double* T = I.v[half_of(a, e0 + el, 0)];
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < DF; ++k) s += I.v[k * DC + xc] * t1[line * DF + k];
-    const int32_t g = a.gmap_c[e0 * DC3 + i];
+    for (int k = 0; k < DF; ++k) s += T[k * DC + xc] * t1[line * DF + k];
+    const int32_t g = a.gmap_c[parent_of(a, e0 + el) * DC3 + (i - el * DC3)];
     if (g >= 0) atomicAdd(&rc[g], s);
   }
 }
@@ -300,12 +319,15 @@ void restrict_t(const TransferArgs& a, const Interp1D& I, const double* bf, cons
                        I, bf, yf, rc);
 }
 
-TransferArgs transfer_args(const DevSpace& c, const DevSpace& f) {
+TransferArgs transfer_args(const DevSpace& c, const DevSpace& f, const Interp1D& I) {
   TransferArgs a{};
   a.gmap_c = c.gmap;
   a.gmap_f = f.gmap;
   a.own_f = f.owner;
   a.ne = f.ne;
+  a.h = I.h ? 1 : 0;
+  if (a.h && f.ne != 8 * c.ne) throw Error(PAFEM_EINVAL, "fine mesh is not a refinement of the coarse one");
+  if (!a.h && f.ne != c.ne) throw Error(PAFEM_EINVAL, "transfer spaces differ in element count");
   return a;
 }
 
@@ -320,7 +342,7 @@ TransferArgs transfer_args(const DevSpace& c, const DevSpace& f) {
 
 void launch_prolongate(const DevSpace& coarse, const DevSpace& fine, const Interp1D& I,
                        const double* xc, double* yf, bool add, hipStream_t st) {
-  const TransferArgs a = transfer_args(coarse, fine);
+  const TransferArgs a = transfer_args(coarse, fine, I);
   const int dc = coarse.p + 1, df = fine.p + 1;
 #define PAFEM_PROLONG_CASE(C, F) \
   if (dc == C && df == F) return prolong_t<C, F>(a, I, xc, yf, add, st);
@@ -333,7 +355,7 @@ void launch_restrict(const DevSpace& fine, const DevSpace& coarse, const Interp1
                      const double* bf, const double* yf, double* rc, hipStream_t st) {
   hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(coarse.ndofs)), dim3(kVecThreads), 0, st, rc, 0.0,
                      int64_t(coarse.ndofs));
-  const TransferArgs a = transfer_args(coarse, fine);
+  const TransferArgs a = transfer_args(coarse, fine, I);
   const int dc = coarse.p + 1, df = fine.p + 1;
 #define PAFEM_RESTRICT_CASE(C, F) \
   if (dc == C && df == F) return restrict_t<C, F>(a, I, bf, yf, rc, st);

@@ -37,23 +37,36 @@ const Space& uploaded(pafem_space sp) {
   return *sp->s;
 }
 
-Interp1D make_interp(int pc, int pf) {
+// h: the fine space is on a uniform refinement of the coarse space's mesh; the fine
+// nodes are then mapped into each half of the parent's interval, (half + x) / 2
+Interp1D make_interp(int pc, int pf, bool h) {
   require(pc >= 1 && pc <= pf, PAFEM_EINVAL, "transfer needs 1 <= coarse order <= fine order");
   require(pf + 1 <= kMaxInterpNodes, PAFEM_EINVAL, "transfer orders above 8 are not built");
   const int dc = pc + 1, df = pf + 1;
-  std::vector<double> nc(dc), nf(df), B(size_t(df) * dc), G(size_t(df) * dc);
+  std::vector<double> nc(dc), nf(df), pts(df), B(size_t(df) * dc), G(size_t(df) * dc);
   gauss_lobatto_01(dc, nc.data());
   gauss_lobatto_01(df, nf.data());
-  lagrange_tables(dc, nc.data(), df, nf.data(), B.data(), G.data());
   Interp1D I{};
-  for (int k = 0; k < df * dc; ++k) I.v[k] = B[size_t(k)];
+  I.h = h ? 1 : 0;
+  for (int half = 0; half < (h ? 2 : 1); ++half) {
+    for (int k = 0; k < df; ++k) pts[size_t(k)] = h ? 0.5 * (half + nf[size_t(k)]) : nf[size_t(k)];
+    lagrange_tables(dc, nc.data(), df, pts.data(), B.data(), G.data());
+    for (int k = 0; k < df * dc; ++k) I.v[half][k] = B[size_t(k)];
+  }
   return I;
 }
 
-void check_pair(const Space& c, const Space& f) {
+// true when the fine space's mesh is a uniform refinement of the coarse space's mesh
+bool check_pair(const Space& c, const Space& f) {
   require(c.dim == 3 && f.dim == 3, PAFEM_EUNSUPPORTED, "order transfers are built for hexahedra");
-  require(c.mesh == f.mesh, PAFEM_EINVAL, "transfer spaces must be built on the same mesh object");
+  require(c.family == kFamilyH1 && f.family == kFamilyH1, PAFEM_EINVAL,
+          "transfers are built between H1 spaces");
+  const bool h = c.mesh != f.mesh;
+  require(!h || (f.mesh->parent_id != 0 && f.mesh->parent_id == c.mesh->id), PAFEM_EINVAL,
+          "transfer spaces must be built on one mesh object, or the fine one on a refinement "
+          "of the coarse one's mesh");
   require(c.p <= f.p, PAFEM_EINVAL, "coarse order above fine order");
+  return h;
 }
 
 struct SmootherLayout {
@@ -277,14 +290,35 @@ pafem_status pafem_coeff_element_mean(pafem_space space, int32_t kind, const dou
   });
 }
 
+pafem_status pafem_coeff_parent_mean(pafem_space fine, pafem_space coarse, int32_t kind,
+                                     const double* coeff, int32_t q1d_in, int32_t q1d_out,
+                                     double* out, void* stream) {
+  return guarded([&] {
+    const Space& f = uploaded(fine);
+    const Space& c = uploaded(coarse);
+    require(coeff && out, PAFEM_EINVAL, "null pointer argument");
+    require(c.dim == 3 && f.dim == 3, PAFEM_EUNSUPPORTED, "element means are built for hexahedra");
+    require(f.mesh->parent_id != 0 && f.mesh->parent_id == c.mesh->id, PAFEM_EINVAL,
+            "the fine space's mesh is not a refinement of the coarse space's mesh");
+    require(kind == PAFEM_MEAN_ARITHMETIC || kind == PAFEM_MEAN_GEOMETRIC ||
+                kind == PAFEM_MEAN_HARMONIC,
+            PAFEM_EINVAL, "unknown mean");
+    require(q1d_in >= 1 && q1d_in <= kMaxQ1d && q1d_out >= 1 && q1d_out <= kMaxQ1d, PAFEM_EINVAL,
+            "q1d out of range");
+    // children 8 e .. 8 e + 7 of coarse element e are contiguous in the caller order
+    launch_coeff_mean(coeff, c.ne, 8 * q1d_in * q1d_in * q1d_in, q1d_out * q1d_out * q1d_out,
+                      kind, out, static_cast<hipStream_t>(stream));
+  });
+}
+
 pafem_status pafem_prolongate(pafem_space coarse, pafem_space fine, const double* xc, double* yf,
                               int32_t add, void* stream) {
   return guarded([&] {
     const Space& c = uploaded(coarse);
     const Space& f = uploaded(fine);
     require(xc && yf, PAFEM_EINVAL, "null pointer argument");
-    check_pair(c, f);
-    launch_prolongate(c.dev, f.dev, make_interp(c.p, f.p), xc, yf, add != 0,
+    const bool h = check_pair(c, f);
+    launch_prolongate(c.dev, f.dev, make_interp(c.p, f.p, h), xc, yf, add != 0,
                       static_cast<hipStream_t>(stream));
   });
 }
@@ -295,8 +329,8 @@ pafem_status pafem_restrict(pafem_space fine, pafem_space coarse, const double* 
     const Space& c = uploaded(coarse);
     const Space& f = uploaded(fine);
     require(bf && rc, PAFEM_EINVAL, "null pointer argument");
-    check_pair(c, f);
-    launch_restrict(f.dev, c.dev, make_interp(c.p, f.p), bf, yf, rc,
+    const bool h = check_pair(c, f);
+    launch_restrict(f.dev, c.dev, make_interp(c.p, f.p, h), bf, yf, rc,
                     static_cast<hipStream_t>(stream));
   });
 }
@@ -384,8 +418,8 @@ pafem_status pafem_pmg_create(int32_t nlevels, const pafem_op* ops, const double
       g.diag.push_back(diags[l]);
       g.lmax.push_back(lmax[l]);
       if (l > 0) {
-        check_pair(*o.space, *g.ops[size_t(l - 1)]->space);
-        g.interp.push_back(make_interp(o.space->p, g.ops[size_t(l - 1)]->space->p));
+        const bool h = check_pair(*o.space, *g.ops[size_t(l - 1)]->space);
+        g.interp.push_back(make_interp(o.space->p, g.ops[size_t(l - 1)]->space->p, h));
       }
     }
     *out = new pafem_pmg_s{std::move(g)};

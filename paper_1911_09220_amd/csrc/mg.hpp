@@ -8,15 +8,21 @@
 
 namespace pafem {
 
-// 1D interpolation table passed by value: v[xf * dc + xc] = coarse Lagrange basis
+// 1D interpolation tables passed by value: v[half][xf * dc + xc] = coarse Lagrange basis
 // function xc (Gauss-Lobatto nodes of the coarse order) at fine Gauss-Lobatto node xf.
+// Within one mesh (h == 0) only half 0 is used, at the fine node itself.  Across a
+// uniform refinement (h == 1) the fine node is mapped into the lower (half 0) or upper
+// (half 1) half of the parent's interval, (half + xf) / 2; fine device element k then
+// lies in coarse device element k / 8, octant k % 8 (bit a: upper half along axis a).
 constexpr int kMaxInterpNodes = 9;  // orders up to 8
 struct Interp1D {
-  double v[kMaxInterpNodes * kMaxInterpNodes];
+  double v[2][kMaxInterpNodes * kMaxInterpNodes];
+  int32_t h;
 };
 
 // yf = P xc on free fine dofs (0 on essential ones), or yf += P xc when `add`;
-// coarse essential values are read as 0.  Both spaces on one mesh.
+// coarse essential values are read as 0.  Both spaces on one mesh (I.h == 0), or the
+// fine one on a uniform refinement of the coarse one's mesh (I.h == 1).
 void launch_prolongate(const DevSpace& coarse, const DevSpace& fine, const Interp1D& I,
                        const double* xc, double* yf, bool add, hipStream_t st);
 // rc = P^T (bf - yf) (yf may be null), 0 on essential coarse dofs

@@ -16,6 +16,7 @@
 // every dof on a boundary face is essential.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstring>
 #include <numeric>
 
@@ -167,7 +168,7 @@ std::vector<int32_t> morton_order(const Mesh& m) {
 void finish_space(Space* s, const Mesh& m, int flags) {
   const int p = s->p, dpe = s->dpe;
   const int64_t ne = s->ne, ndofs = s->ndofs;
-  s->dev_order = morton_order(m);
+  s->dev_order = mesh_element_order(m);
   if (flags & PAFEM_SPACE_RENUMBER) {
     // first touch while walking the elements in device order
     std::vector<int32_t> perm(size_t(ndofs), -1);
@@ -306,6 +307,146 @@ Space* build_space_2d(const Mesh* mesh, int order, int flags) {
 }
 
 }  // namespace
+
+uint64_t next_mesh_id() {
+  static std::atomic<uint64_t> counter{0};
+  return ++counter;
+}
+
+std::vector<int32_t> mesh_element_order(const Mesh& m) {
+  return m.elem_order.empty() ? morton_order(m) : m.elem_order;
+}
+
+void refine_mesh(const Mesh& c, Mesh& f) {
+  if (c.dim != 3) throw Error(PAFEM_EUNSUPPORTED, "refinement is built for hexahedra");
+  const int64_t ne = c.ne, nv = c.nv;
+  if (ne > (int64_t(1) << 27)) throw Error(PAFEM_ESHAPE, "refined mesh would exceed 2^30 elements");
+  const auto es = edge_slots();
+  const auto fs = face_slots();
+  int edge_of[3][8] = {};  // (axis, low corner) -> edge slot
+  for (int k = 0; k < 12; ++k) edge_of[es[size_t(k)].axis][es[size_t(k)].c0] = k;
+  // shared edges and faces of the coarse mesh, by sorted vertex keys
+  std::vector<std::array<int64_t, 2>> ek(size_t(ne) * 12);
+  std::vector<std::array<int64_t, 4>> fk(size_t(ne) * 6);
+  for (int64_t e = 0; e < ne; ++e) {
+    const ElemCorners cc = corners_of(c, e);
+    for (int k = 0; k < 12; ++k) {
+      const int64_t a = cc.v[es[size_t(k)].c0], b = cc.v[es[size_t(k)].c0 | (1 << es[size_t(k)].axis)];
+      ek[size_t(e) * 12 + size_t(k)] = {std::min(a, b), std::max(a, b)};
+    }
+    for (int k = 0; k < 6; ++k) {
+      std::array<int64_t, 4> key{};
+      for (int j = 0; j < 4; ++j) key[size_t(j)] = cc.v[fs[size_t(k)].c[j]];
+      std::sort(key.begin(), key.end());
+      fk[size_t(e) * 6 + size_t(k)] = key;
+    }
+  }
+  std::vector<int64_t> erep, frep;
+  std::vector<int32_t> mult;
+  match_keys<2>(ek, nv, erep, mult);
+  match_keys<4>(fk, nv, frep, mult);
+  // new vertex ids: coarse vertices keep theirs, then edges, faces, cells (rep <= item)
+  int64_t next = nv;
+  std::vector<int64_t> eid(ek.size()), fid(fk.size());
+  for (size_t i = 0; i < ek.size(); ++i) eid[i] = erep[i] == int64_t(i) ? next++ : eid[size_t(erep[i])];
+  for (size_t i = 0; i < fk.size(); ++i) fid[i] = frep[i] == int64_t(i) ? next++ : fid[size_t(frep[i])];
+  const int64_t cell0 = next, nvf = next + ne;
+
+  f = Mesh();
+  f.dim = 3;
+  f.nv = nvf;
+  f.ne = ne * 8;
+  f.geom_order = c.geom_order;
+  f.xyz.assign(size_t(nvf) * 3, 0.0);
+  std::copy(c.xyz.begin(), c.xyz.begin() + nv * 3, f.xyz.begin());
+  f.hex.resize(size_t(f.ne) * 8);
+  std::vector<uint8_t> placed(size_t(nvf), 0);
+  std::fill(placed.begin(), placed.begin() + nv, uint8_t(1));
+  // the parent's map at reference point t: trilinear from the corners, or the
+  // triquadratic map through the 27 nodes at {0, 1/2, 1}^3
+  auto quad1d = [](int m, double t) {
+    return m == 0 ? 2.0 * (t - 0.5) * (t - 1.0) : m == 1 ? 4.0 * t * (1.0 - t) : 2.0 * t * (t - 0.5);
+  };
+  auto parent_map = [&](int64_t e, const ElemCorners& cc, const double t[3], double x[3]) {
+    x[0] = x[1] = x[2] = 0.0;
+    if (c.geom_order == 2) {
+      const double* gn = c.gnodes.data() + size_t(e) * 81;
+      for (int m = 0; m < 27; ++m) {
+        const double w = quad1d(m % 3, t[0]) * quad1d((m / 3) % 3, t[1]) * quad1d(m / 9, t[2]);
+        for (int a = 0; a < 3; ++a) x[a] += w * gn[m * 3 + a];
+      }
+      return;
+    }
+    for (int k = 0; k < 8; ++k) {
+      double w = 1.0;
+      for (int a = 0; a < 3; ++a) w *= ((k >> a) & 1) ? t[a] : 1.0 - t[a];
+      for (int a = 0; a < 3; ++a) x[a] += w * c.xyz[size_t(cc.v[k]) * 3 + size_t(a)];
+    }
+  };
+  int64_t lat[27];  // fine vertex of each point of the parent's {0, 1/2, 1}^3 lattice
+  for (int64_t e = 0; e < ne; ++e) {
+    const ElemCorners cc = corners_of(c, e);
+    for (int n = 0; n < 27; ++n) {
+      const int ijk[3] = {n % 3, (n / 3) % 3, n / 9};
+      int odd = 0, axis = 0, other = 0;
+      for (int a = 0; a < 3; ++a) {
+        if (ijk[a] == 1) {
+          ++odd;
+          axis = a;
+        } else {
+          other = a;
+        }
+      }
+      int64_t id;
+      if (odd == 0) {
+        id = cc.v[(ijk[0] / 2) | ((ijk[1] / 2) << 1) | ((ijk[2] / 2) << 2)];
+      } else if (odd == 1) {
+        int c0 = 0;
+        for (int a = 0; a < 3; ++a)
+          if (a != axis) c0 |= (ijk[a] / 2) << a;
+        id = eid[size_t(e) * 12 + size_t(edge_of[axis][c0])];
+      } else if (odd == 2) {
+        id = fid[size_t(e) * 6 + size_t(2 * other + ijk[other] / 2)];
+      } else {
+        id = cell0 + e;
+      }
+      lat[n] = id;
+      if (!placed[size_t(id)]) {
+        const double t[3] = {0.5 * ijk[0], 0.5 * ijk[1], 0.5 * ijk[2]};
+        parent_map(e, cc, t, f.xyz.data() + size_t(id) * 3);
+        placed[size_t(id)] = 1;
+      }
+    }
+    for (int o = 0; o < 8; ++o) {
+      const int off[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+      int64_t* h = f.hex.data() + size_t(e * 8 + o) * 8;
+      for (int slot = 0; slot < 8; ++slot) {
+        const int lc = kLexToSlot[slot];  // the slot order is its own inverse
+        const int n = (off[0] + (lc & 1)) + 3 * (off[1] + ((lc >> 1) & 1)) + 9 * (off[2] + (lc >> 2));
+        h[slot] = lat[n];
+      }
+    }
+  }
+  if (c.geom_order == 2) {
+    f.gnodes.resize(size_t(f.ne) * 81);
+    for (int64_t e = 0; e < ne; ++e) {
+      const ElemCorners cc = corners_of(c, e);
+      for (int o = 0; o < 8; ++o)
+        for (int n = 0; n < 27; ++n) {
+          const double t[3] = {0.5 * ((o & 1) + 0.5 * (n % 3)),
+                               0.5 * (((o >> 1) & 1) + 0.5 * ((n / 3) % 3)),
+                               0.5 * ((o >> 2) + 0.5 * (n / 9))};
+          parent_map(e, cc, t, f.gnodes.data() + (size_t(e * 8 + o) * 27 + size_t(n)) * 3);
+        }
+    }
+  }
+  const std::vector<int32_t> corder = mesh_element_order(c);
+  f.elem_order.resize(size_t(f.ne));
+  for (int64_t k = 0; k < ne; ++k)
+    for (int o = 0; o < 8; ++o) f.elem_order[size_t(k * 8 + o)] = corder[size_t(k)] * 8 + o;
+  f.id = next_mesh_id();
+  f.parent_id = c.id;
+}
 
 Space* build_space(const Mesh* mesh, int order, int flags) {
   if (order < 1 || order > kMaxOrder)

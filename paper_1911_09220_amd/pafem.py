@@ -70,7 +70,7 @@ class FCGResult(C.Structure):
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
-ABI_VERSION = 273  # pafem_version() of the library whose structs are declared above
+ABI_VERSION = 274  # pafem_version() of the library whose structs are declared above
 
 
 def _load():
@@ -88,6 +88,9 @@ def _load():
         "pafem_mesh_create_hex": (I32, [I64, P, I64, P, I32, P, C.POINTER(P)]),
         "pafem_mesh_create_quad": (I32, [I64, P, I64, P, C.POINTER(P)]),
         "pafem_mesh_destroy": (None, [P]),
+        "pafem_mesh_refine": (I32, [P, C.POINTER(P)]),
+        "pafem_mesh_info": (I32, [P, C.POINTER(I64), C.POINTER(I64)]),
+        "pafem_mesh_vertices": (I32, [P, P, P]),
         "pafem_space_dim": (I32, [P, C.POINTER(I32)]),
         "pafem_space_create_h1": (I32, [P, I32, I32, C.POINTER(P)]),
         "pafem_space_destroy": (None, [P]),
@@ -143,6 +146,7 @@ def _load():
         "pafem_fcg_solve": (I32, [P, P, P, P, P, P, P, SZ, C.POINTER(SolveOpts),
                                   C.POINTER(FCGResult), P]),
         "pafem_coeff_element_mean": (I32, [P, I32, P, I32, I32, P, P]),
+        "pafem_coeff_parent_mean": (I32, [P, P, I32, P, I32, I32, P, P]),
         "pafem_prolongate": (I32, [P, P, P, P, I32, P]),
         "pafem_restrict": (I32, [P, P, P, P, P, P]),
         "pafem_smoother_workspace_bytes": (I32, [P, C.POINTER(SZ)]),
@@ -379,6 +383,11 @@ def pafem_batch_describe(batch):
     return buf.value.decode()
 
 
+def pafem_coeff_parent_mean(fine, coarse, kind, coeff, q1d_in, q1d_out, out):
+    _check(lib.pafem_coeff_parent_mean(fine, coarse, int(kind), _ptr(coeff), int(q1d_in),
+                                       int(q1d_out), _ptr(out), _stream()))
+
+
 def pafem_coeff_element_mean(space, kind, coeff, q1d_in, q1d_out, out):
     _check(lib.pafem_coeff_element_mean(space, int(kind), _ptr(coeff), int(q1d_in), int(q1d_out),
                                         _ptr(out), _stream()))
@@ -465,6 +474,29 @@ class Mesh:
         if "quad" in m:
             return cls(m["vertices"], quads=m["quad"])
         return cls(m["vertices"], m["hex"], m.get("geom_order", 1), m.get("geom_nodes"))
+
+    def refine(self):
+        """Uniform refinement (pafem_mesh_refine): child 8 e + o covers octant o of
+        element e's reference cube; spaces on the result take transfers from spaces on
+        this mesh."""
+        out = C.c_void_p()
+        _check(lib.pafem_mesh_refine(self.handle, C.byref(out)))
+        m = Mesh.__new__(Mesh)
+        m.dim, m.handle = self.dim, out
+        return m
+
+    def counts(self):
+        nv, ne = C.c_int64(), C.c_int64()
+        _check(lib.pafem_mesh_info(self.handle, C.byref(nv), C.byref(ne)))
+        return nv.value, ne.value
+
+    def arrays(self):
+        """(vertices [nv, dim], elements [ne, 8 or 4]) host copies."""
+        nv, ne = self.counts()
+        v = np.empty((nv, self.dim), dtype=np.float64)
+        e = np.empty((ne, 8 if self.dim == 3 else 4), dtype=np.int64)
+        _check(lib.pafem_mesh_vertices(self.handle, _np_ptr(v), _np_ptr(e)))
+        return v, e
 
     def __del__(self):
         # at interpreter exit the module's globals may already be cleared
@@ -557,6 +589,17 @@ class Space:
         self._check_qp_array(coeff, q1d_in, "coeff")
         out = torch.empty(self.nelem * q1d_out ** 3, dtype=torch.float64, device=self.device)
         pafem_coeff_element_mean(self.handle, kind, coeff, q1d_in, q1d_out, out)
+        return out
+
+    def coeff_parent_mean(self, coarse, coeff, q1d_in=None, q1d_out=None, kind=MEAN_ARITHMETIC):
+        """Mean of a per-point coefficient on this space's (refined) mesh over the 8
+        children of each element of ``coarse``'s mesh, spread over ``coarse``'s rule."""
+        import torch
+        q1d_in = self.p + 2 if q1d_in is None else q1d_in
+        q1d_out = coarse.p + 2 if q1d_out is None else q1d_out
+        self._check_qp_array(coeff, q1d_in, "coeff")
+        out = torch.empty(coarse.nelem * q1d_out ** 3, dtype=torch.float64, device=self.device)
+        pafem_coeff_parent_mean(self.handle, coarse.handle, kind, coeff, q1d_in, q1d_out, out)
         return out
 
     def linear_form(self, source=SOURCE_SINE, q1d=None, f_qp=None, scale=1.0):
@@ -749,8 +792,9 @@ def restrict(fine: Space, coarse: Space, bf, yf=None, rc=None):
 
 
 class PMG:
-    """Order-multigrid V-cycle over constrained diffusion operators (finest first) on
-    spaces of one Mesh; diagonals and largest-eigenvalue estimates per level."""
+    """Multigrid V-cycle over constrained diffusion operators (finest first): each
+    level on the previous level's Mesh (lower order) or on the Mesh it was refined from
+    (Mesh.refine; h-multigrid); diagonals and largest-eigenvalue estimates per level."""
 
     def __init__(self, ops, diags, lmax, degree=2, lo=0.3, hi=1.1, coarse_iters=20):
         self.ops, self.diags = list(ops), list(diags)  # kept alive: the library holds pointers
