@@ -489,6 +489,86 @@ def bench_pmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20,
     return out
 
 
+def bench_hpmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20, degree=2, coarse_iters=10):
+    """Multigrid in the mesh size and the order on a twice-refined mesh: a coarse
+    lattice (5% jitter) refined twice by the library, lognormal kappa per point on the
+    finest mesh, order p there.  Flexible CG with one V-cycle per iteration, levels
+    p -> .. -> 1 on the finest mesh and then one or two steps down in mesh size,
+    against the same order-only V-cycle and FP64 Jacobi-PCG on the same mesh."""
+    import synth
+    nc = max(1, int(round(lattice_size(p, target) / 4.0)))
+    M2 = P.Mesh.from_dict(synth.hex_lattice(nc, 0.05, seed=2))
+    M1 = M2.refine()
+    M0 = M1.refine()
+    meshes = [M0, M1, M2]
+    orders = [p]
+    while orders[-1] > 1:
+        orders.append(max(1, orders[-1] // 2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S0 = P.Space(M0, p)
+    ne = S0.nelem
+    kappa = torch.as_tensor(synth.lognormal_iid(ne, p + 2, 1.0, seed=3), device="cuda")
+    fine = P.Operator(S0, P.DIFFUSION, S0.qdata(P.DIFFUSION, coeff=kappa))
+    b = S0.linear_form(P.SOURCE_SINE)
+    dfine = fine.diagonal()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    xj, ij = fine.pcg(b, diag=dfine, rel_tol=tol, max_iter=20000, history=False)
+    log(f"hpmg p={p}: {S0.ndofs} dofs, Jacobi-PCG {ij['iters']} its {ij['seconds']:.3f} s")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(78)
+    # for p = 1 the order-only plan is one level: its V-cycle is the coarse PCG alone
+    plans = {"order_only": [(0, q) for q in orders],
+             "order_then_1_refinement": [(0, q) for q in orders] + [(1, 1)],
+             "order_then_2_refinements": [(0, q) for q in orders] + [(1, 1), (2, 1)]}
+    out = {"order": p, "ndofs": S0.ndofs, "elements": ne,
+           "mesh": f"{nc}^3 lattice (5% jitter) refined twice", "tol": tol,
+           "degree": degree, "coarse_iters": coarse_iters,
+           "setup_seconds": round(t_setup, 3),
+           "jacobi_pcg": {"iters": ij["iters"], "seconds": round(ij["seconds"], 4)}, "runs": {}}
+    for name, plan in plans.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        spaces, ops, diags, lmax, coeffs = [S0], [fine], [dfine], [], [kappa]
+        for l, (m, q) in enumerate(plan):
+            if l > 0:
+                S = P.Space(meshes[m], q)
+                prev = spaces[-1]
+                qin = plan[l - 1][1] + 2
+                if plan[l - 1][0] == m:
+                    c = prev.coeff_mean(coeffs[-1], q1d_in=qin, q1d_out=q + 2)
+                else:
+                    c = prev.coeff_parent_mean(S, coeffs[-1], q1d_in=qin, q1d_out=q + 2)
+                spaces.append(S)
+                coeffs.append(c)
+                ops.append(P.Operator(S, P.DIFFUSION, S.qdata(P.DIFFUSION, coeff=c)))
+                diags.append(ops[-1].diagonal())
+            v = torch.randn(spaces[l].ndofs, dtype=torch.float64, device="cuda", generator=gen)
+            lmax.append(ops[l].lambda_max(diags[l], v, power_iters))
+        torch.cuda.synchronize()
+        t_levels = time.perf_counter() - t0
+        G = P.PMG(ops, diags, lmax, degree=degree, coarse_iters=coarse_iters)
+        G.fcg(b, rel_tol=1e-2, max_iter=2, history=False)  # warm-up (workspace, kernels)
+        x, info = G.fcg(b, rel_tol=tol, max_iter=1000, history=False)
+        out["runs"][name] = {
+            "levels": [[["fine", "1 refinement coarser", "2 refinements coarser"][m], q]
+                       for m, q in plan],
+            "level_ndofs": [S.ndofs for S in spaces],
+            "iters": info["iters"], "seconds": round(info["seconds"], 4),
+            "status": info["status"], "true_rel_res": info["true_rel_res"],
+            "ms_per_iter": round(1e3 * info["seconds"] / max(1, info["iters"]), 3),
+            "speedup_vs_jacobi": round(ij["seconds"] / info["seconds"], 3),
+            "level_setup_seconds": round(t_levels, 3),
+            "solution_rel_diff_vs_jacobi": float((x - xj).norm() / xj.norm())}
+        log(f"hpmg p={p} {name}: {info['iters']} its {info['seconds']:.3f} s")
+        del G, x, spaces[1:], ops[1:], diags[1:], coeffs[1:]
+    base = out["runs"]["order_only"]["seconds"]
+    for r in out["runs"].values():
+        r["speedup_vs_order_only"] = round(base / r["seconds"], 3)
+    return out
+
+
 # The paper's table of 200 partially assembled CG iterations (2D Poisson, ~1.3M dofs),
 # read as seconds: best GPU backend (CEED-CUDA, Quadro GV100) and the 16-core MPI run.
 PAPER_2D_SECONDS = {"ceed_cuda_gv100": {1: 0.19, 2: 0.15, 4: 0.12, 8: 0.12},
@@ -723,10 +803,12 @@ def main():
                     help="skip the recomputed-geometry diffusion variant")
     ap.add_argument("--no-conv", action="store_true",
                     help="skip the convection, gradient, divergence and elasticity operators")
-    ap.add_argument("--forms", default="mixed,batched,learned,pmg,paper2d,hcurl,dg",
+    ap.add_argument("--forms", default="mixed,batched,learned,pmg,hpmg,paper2d,hcurl,dg",
                     help="solver forms to measure beside the sweep ('' = none)")
     ap.add_argument("--pmg-orders", default="3,6",
                     help="orders of the sweep problems solved with order multigrid")
+    ap.add_argument("--hpmg-orders", default="1,2,3,6",
+                    help="orders solved with multigrid in mesh size and order")
     ap.add_argument("--learned-fields", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=1500)
     args = ap.parse_args()
@@ -924,6 +1006,10 @@ def main():
         for p in [int(v) for v in args.pmg_orders.split(",") if v]:
             log(f"pmg p={p}")
             out["pmg"][str(p)] = bench_pmg(P, torch, p=p, target=args.target_dofs)
+    if "hpmg" in forms:
+        out["hpmg"] = {}
+        for p in [int(v) for v in args.hpmg_orders.split(",") if v]:
+            out["hpmg"][str(p)] = bench_hpmg(P, torch, p=p, target=args.target_dofs)
     if "hcurl" in forms:
         log("hcurl")
         out["hcurl_maxwell_apply"] = bench_hcurl(P, torch, orders, args.target_dofs)
