@@ -489,18 +489,21 @@ def bench_pmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20,
     return out
 
 
-def bench_hpmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20, degree=2, coarse_iters=10):
-    """Multigrid in the mesh size and the order on a twice-refined mesh: a coarse
-    lattice (5% jitter) refined twice by the library, lognormal kappa per point on the
-    finest mesh, order p there.  Flexible CG with one V-cycle per iteration, levels
-    p -> .. -> 1 on the finest mesh and then one or two steps down in mesh size,
-    against the same order-only V-cycle and FP64 Jacobi-PCG on the same mesh."""
+def bench_hpmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20, degree=2, coarse_iters=10,
+               only=None):
+    """Multigrid in the mesh size and the order on a refined mesh: a coarse lattice (5%
+    jitter) refined by the library three times (p <= 2) or twice (p >= 3, where the order
+    levels already end on a small problem), lognormal kappa per point on the finest
+    mesh, order p there.  Flexible CG with one V-cycle per iteration, levels p -> .. -> 1
+    on the finest mesh and then one step down in mesh size after another, against the
+    order-only V-cycle and FP64 Jacobi-PCG on the same mesh."""
     import synth
-    nc = max(1, int(round(lattice_size(p, target) / 4.0)))
-    M2 = P.Mesh.from_dict(synth.hex_lattice(nc, 0.05, seed=2))
-    M1 = M2.refine()
-    M0 = M1.refine()
-    meshes = [M0, M1, M2]
+    depth = 3 if p <= 2 else 2
+    nc = max(1, int(round(lattice_size(p, target) / 2 ** depth)))
+    meshes = [P.Mesh.from_dict(synth.hex_lattice(nc, 0.05, seed=2))]
+    for _ in range(depth):
+        meshes.insert(0, meshes[0].refine())
+    M0 = meshes[0]
     orders = [p]
     while orders[-1] > 1:
         orders.append(max(1, orders[-1] // 2))
@@ -519,14 +522,17 @@ def bench_hpmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20, degree=2, co
     gen = torch.Generator(device="cuda")
     gen.manual_seed(78)
     # for p = 1 the order-only plan is one level: its V-cycle is the coarse PCG alone
-    plans = {"order_only": [(0, q) for q in orders],
-             "order_then_1_refinement": [(0, q) for q in orders] + [(1, 1)],
-             "order_then_2_refinements": [(0, q) for q in orders] + [(1, 1), (2, 1)]}
+    plans = {"order_only": [(0, q) for q in orders]}
+    for k in range(1, depth + 1):
+        name = f"order_then_{k}_refinement" + ("s" if k > 1 else "")
+        plans[name] = [(0, q) for q in orders] + [(m, 1) for m in range(1, k + 1)]
     out = {"order": p, "ndofs": S0.ndofs, "elements": ne,
-           "mesh": f"{nc}^3 lattice (5% jitter) refined twice", "tol": tol,
+           "mesh": f"{nc}^3 lattice (5% jitter) refined {depth} times", "tol": tol,
            "degree": degree, "coarse_iters": coarse_iters,
            "setup_seconds": round(t_setup, 3),
            "jacobi_pcg": {"iters": ij["iters"], "seconds": round(ij["seconds"], 4)}, "runs": {}}
+    if only:
+        plans = {k: v for k, v in plans.items() if k in only}
     for name, plan in plans.items():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -552,8 +558,7 @@ def bench_hpmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20, degree=2, co
         G.fcg(b, rel_tol=1e-2, max_iter=2, history=False)  # warm-up (workspace, kernels)
         x, info = G.fcg(b, rel_tol=tol, max_iter=1000, history=False)
         out["runs"][name] = {
-            "levels": [[["fine", "1 refinement coarser", "2 refinements coarser"][m], q]
-                       for m, q in plan],
+            "levels": [["fine" if m == 0 else f"{m} refinement(s) coarser", q] for m, q in plan],
             "level_ndofs": [S.ndofs for S in spaces],
             "iters": info["iters"], "seconds": round(info["seconds"], 4),
             "status": info["status"], "true_rel_res": info["true_rel_res"],
@@ -563,9 +568,10 @@ def bench_hpmg(P, torch, p=3, target=1e7, tol=1e-8, power_iters=20, degree=2, co
             "solution_rel_diff_vs_jacobi": float((x - xj).norm() / xj.norm())}
         log(f"hpmg p={p} {name}: {info['iters']} its {info['seconds']:.3f} s")
         del G, x, spaces[1:], ops[1:], diags[1:], coeffs[1:]
-    base = out["runs"]["order_only"]["seconds"]
-    for r in out["runs"].values():
-        r["speedup_vs_order_only"] = round(base / r["seconds"], 3)
+    if "order_only" in out["runs"]:
+        base = out["runs"]["order_only"]["seconds"]
+        for r in out["runs"].values():
+            r["speedup_vs_order_only"] = round(base / r["seconds"], 3)
     return out
 
 
@@ -809,6 +815,9 @@ def main():
                     help="orders of the sweep problems solved with order multigrid")
     ap.add_argument("--hpmg-orders", default="1,2,3,6",
                     help="orders solved with multigrid in mesh size and order")
+    ap.add_argument("--hpmg-plans", default="",
+                    help="comma-separated subset of order_only, order_then_1_refinement, "
+                         "order_then_2_refinements, order_then_3_refinements ('' = all)")
     ap.add_argument("--learned-fields", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=1500)
     args = ap.parse_args()
@@ -1009,7 +1018,8 @@ def main():
     if "hpmg" in forms:
         out["hpmg"] = {}
         for p in [int(v) for v in args.hpmg_orders.split(",") if v]:
-            out["hpmg"][str(p)] = bench_hpmg(P, torch, p=p, target=args.target_dofs)
+            out["hpmg"][str(p)] = bench_hpmg(P, torch, p=p, target=args.target_dofs,
+                                             only=[v for v in args.hpmg_plans.split(",") if v])
     if "hcurl" in forms:
         log("hcurl")
         out["hcurl_maxwell_apply"] = bench_hcurl(P, torch, orders, args.target_dofs)
