@@ -55,8 +55,11 @@ struct TransferShape {
   static constexpr int W = (DF3 + 31) / 32;  // owner words per element
   // elements per workgroup: as many as fit 32 KB of LDS (at most 64)
   static constexpr int fit(int per) { return (4096 / per) < 1 ? 1 : (4096 / per) > 64 ? 64 : (4096 / per); }
+  // a multiple of 8 where 8 or more fit, so that a workgroup holds whole families of
+  // children (8 consecutive fine elements) across a refinement
+  static constexpr int fit8(int per) { return fit(per) >= 8 ? fit(per) & ~7 : fit(per); }
   static constexpr int NELP = fit(DC3 + DC * DC * DF + DC * DF * DF);  // prolongation
-  static constexpr int NELR = fit(DF3 + DC * DF * DF + DC * DC * DF);  // restriction
+  static constexpr int NELR = fit8(DF3 + DC * DF * DF + DC * DC * DF);  // restriction
 };
 
 __device__ __forceinline__ bool owns(const uint32_t* own, int W, int64_t e, int l) {
@@ -156,6 +159,10 @@ __global__ void __launch_bounds__(kMgThreads)
     t1[i] = s;
   }
   __syncthreads();
+  // Across a refinement with whole families in the workgroup, the 8 children of a parent
+  // are summed here first (their values go to rf, free since the z stage) and the parent
+  // adds once per node: the children's atomics would all hit the same 8 coarse nodes.
+  const bool family = NEL % 8 == 0 && a.h;
   for (int i = threadIdx.x; i < nel * DC3; i += kMgThreads) {
     const int xc = i % DC, line = i / DC;  // line = (el, zc, yc)
     const int el = line / (DC * DC);
@@ -163,8 +170,23 @@ __global__ void __launch_bounds__(kMgThreads)
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < DF; ++k) s += T[k * DC + xc] * t1[line * DF + k];
-    const int32_t g = a.gmap_c[parent_of(a, e0 + el) * DC3 + (i - el * DC3)];
-    if (g >= 0) atomicAdd(&rc[g], s);
+    if (family) {
+      rf[i] = s;
+    } else {
+      const int32_t g = a.gmap_c[parent_of(a, e0 + el) * DC3 + (i - el * DC3)];
+      if (g >= 0) atomicAdd(&rc[g], s);
+    }
+  }
+  if (family) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < (nel >> 3) * DC3; i += kMgThreads) {
+      const int pp = i / DC3, l = i - pp * DC3;
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) s += rf[(pp * 8 + c) * DC3 + l];
+      const int32_t g = a.gmap_c[((e0 >> 3) + pp) * DC3 + l];
+      if (g >= 0) atomicAdd(&rc[g], s);
+    }
   }
 }
 
