@@ -751,6 +751,11 @@ def bench_learned(P, torch, n=64, p=3, fields=20, heldout=10, steps=1500, tol=1e
            "pair_stops": list(stops), "train_steps": steps, "pair_seconds": round(t_pairs, 2),
            "train_seconds": round(t_train, 2), "loss_first": float(losses[:50].mean()),
            "loss_last": float(losses[-50:].mean()), "tol": tol, "heldout": []}
+    if fields < 200:
+        out["train_fields_note"] = (
+            f"the learned-preconditioner configuration names 200 training fields; this run "
+            f"trains on {fields} (pairs cost {t_pairs / max(1, fields):.2f} s per field); "
+            f"--learned-fields 200 runs the full count")
     out["constant_weights"] = {
         "what": "same basis training with the element features zeroed (one weight vector "
                 "for every element: the network adds nothing)",
