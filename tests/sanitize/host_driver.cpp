@@ -1,7 +1,8 @@
 // Host-side exercise of the library's C ABI for the sanitizer build (AddressSanitizer
-// and UndefinedBehaviorSanitizer on the host C++): meshes, H1 / Nedelec / L2 spaces at
-// several orders (numbering, signs, faces, coordinates, boundary lists), quadrature-data
-// sizes of every kind, and the refusal paths.  No device call is made.
+// and UndefinedBehaviorSanitizer on the host C++): meshes and their uniform refinement,
+// H1 / Nedelec / L2 spaces at several orders (numbering, signs, faces, coordinates,
+// boundary lists), quadrature-data sizes of every kind, and the refusal paths.  No device
+// call is made.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -90,6 +91,31 @@ int main() {
       CHECK(pafem_qdata_assemble(s, PAFEM_MASS, p + 2, nullptr, 1.0, nullptr, nullptr) != PAFEM_OK);
       pafem_space_destroy(s);
     }
+  // uniform refinement, twice, with the parent destroyed in between; spaces on the result
+  {
+    pafem_mesh f1 = nullptr, f2 = nullptr;
+    CHECK(pafem_mesh_refine(mesh, &f1) == PAFEM_OK);
+    CHECK(pafem_mesh_refine(f1, &f2) == PAFEM_OK);
+    pafem_mesh_destroy(f1);
+    int64_t fnv = 0, fne = 0;
+    CHECK(pafem_mesh_info(f2, &fnv, &fne) == PAFEM_OK);
+    CHECK(fne == 64 * ne && fnv == 13 * 13 * 13);
+    std::vector<double> fxyz(size_t(fnv) * 3);
+    std::vector<int64_t> fhex(size_t(fne) * 8);
+    CHECK(pafem_mesh_vertices(f2, fxyz.data(), fhex.data()) == PAFEM_OK);
+    for (int64_t v : fhex) CHECK(v >= 0 && v < fnv);
+    for (double v : fxyz) CHECK(v > -1e-9 && v < 1.0 + 1e-9);
+    for (int p = 1; p <= 3; ++p) {
+      pafem_space s = nullptr;
+      CHECK(pafem_space_create_h1(f2, p, 0, &s) == PAFEM_OK);
+      int64_t nd = 0, nel = 0, nb = 0;
+      int32_t dpe = 0;
+      CHECK(pafem_space_info(s, &nd, &nel, &dpe, &nb) == PAFEM_OK);
+      CHECK(nd == int64_t(12 * p + 1) * (12 * p + 1) * (12 * p + 1));
+      pafem_space_destroy(s);
+    }
+    pafem_mesh_destroy(f2);
+  }
   pafem_space bad = nullptr;
   CHECK(pafem_space_create_h1(mesh, 0, 0, &bad) == PAFEM_EUNSUPPORTED);
   CHECK(pafem_space_create_nd(mesh, 9, 0, &bad) == PAFEM_EUNSUPPORTED);
