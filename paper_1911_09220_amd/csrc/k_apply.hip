@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
           uy += rb[dz] * c1[dz];
           uz += rg[dz] * c2[dz];
         }
-        TC d00, d01, d02, d11, d12, d22;
+        TC vx, vy, vz;
         if constexpr (GEOM) {
           // J[a][b] = dx_a / dxi_b at (qx, qy, qz); D = w kappa adj(J) adj(J)^t / det J
           TC J[3][3];
@@ -382,23 +382,18 @@ __global__ void __launch_bounds__(elems_per_block<Q>() * Q * Q, KIND != PAFEM_DI
           const TC A22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
           const TC det = J[0][0] * A00 + J[0][1] * A10 + J[0][2] * A20;
           const TC f = dq[qz][0] / det;
-          d00 = f * (A00 * A00 + A01 * A01 + A02 * A02);
-          d01 = f * (A00 * A10 + A01 * A11 + A02 * A12);
-          d02 = f * (A00 * A20 + A01 * A21 + A02 * A22);
-          d11 = f * (A10 * A10 + A11 * A11 + A12 * A12);
-          d12 = f * (A10 * A20 + A11 * A21 + A12 * A22);
-          d22 = f * (A20 * A20 + A21 * A21 + A22 * A22);
+          // D u = f A (A^t u) without forming D (21 instead of 33 operations per point)
+          const TC w0 = f * (A00 * ux + A10 * uy + A20 * uz);
+          const TC w1 = f * (A01 * ux + A11 * uy + A21 * uz);
+          const TC w2 = f * (A02 * ux + A12 * uy + A22 * uz);
+          vx = A00 * w0 + A01 * w1 + A02 * w2;
+          vy = A10 * w0 + A11 * w1 + A12 * w2;
+          vz = A20 * w0 + A21 * w1 + A22 * w2;
         } else {
-          d00 = dq[qz][0];
-          d01 = dq[qz][1];
-          d02 = dq[qz][2];
-          d11 = dq[qz][3];
-          d12 = dq[qz][4];
-          d22 = dq[qz][5];
+          vx = dq[qz][0] * ux + dq[qz][1] * uy + dq[qz][2] * uz;
+          vy = dq[qz][1] * ux + dq[qz][3] * uy + dq[qz][4] * uz;
+          vz = dq[qz][2] * ux + dq[qz][4] * uy + dq[qz][5] * uz;
         }
-        const TC vx = d00 * ux + d01 * uy + d02 * uz;
-        const TC vy = d01 * ux + d11 * uy + d12 * uz;
-        const TC vz = d02 * ux + d12 * uy + d22 * uz;
         if (DOT) energy += double(ux) * double(vx) + double(uy) * double(vy) + double(uz) * double(vz);
 #pragma unroll
         for (int dz = 0; dz < D; ++dz) {
