@@ -69,3 +69,23 @@ def test_quadrilateral_refinement_is_refused():
     m = synth.quad_lattice(2, 0.0)
     with pytest.raises(pafem.PafemError):
         pafem.Mesh.from_dict(m).refine()
+
+
+def test_refinement_entry_points_refuse_null_arguments():
+    import ctypes as C
+    lib = pafem.lib
+    out = C.c_void_p()
+    assert lib.pafem_mesh_refine(None, C.byref(out)) == -1          # EINVAL
+    M = pafem.Mesh.from_dict(synth.hex_lattice(1))
+    assert lib.pafem_mesh_refine(M.handle, None) == -1
+    assert lib.pafem_mesh_info(None, None, None) == -1
+    assert lib.pafem_mesh_vertices(None, None, None) == -1
+    # either output may be omitted
+    nv = C.c_int64()
+    assert lib.pafem_mesh_info(M.handle, C.byref(nv), None) == 0 and nv.value == 8
+    assert lib.pafem_mesh_vertices(M.handle, None, None) == 0
+    # the coefficient mean across a refinement needs uploaded spaces on related meshes
+    F = M.refine()
+    Sc = pafem.Space(M, 1, device=None)
+    Sf = pafem.Space(F, 1, device=None)
+    assert lib.pafem_coeff_parent_mean(Sf.handle, Sc.handle, 0, None, 3, 3, None, None) != 0
