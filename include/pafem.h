@@ -208,11 +208,14 @@ pafem_status pafem_mesh_create_quad(int64_t nv, const double* xy, int64_t ne, co
  * destroyed first.  Host call.  Errors: EUNSUPPORTED (quadrilateral mesh), ESHAPE
  * (more than 2^27 coarse elements). */
 pafem_status pafem_mesh_refine(pafem_mesh coarse, pafem_mesh* fine);
-/* Vertex and element counts.  Host call. */
+/* Vertex and element counts of a mesh ("Meshes"), e.g. of a refined one.  Either
+ * pointer may be NULL.  Host call.  Errors: EINVAL (null mesh). */
 pafem_status pafem_mesh_info(pafem_mesh mesh, int64_t* nv, int64_t* ne);
 /* Copies of the vertex coordinates (host [nv][dim] f64) and the connectivity (host
- * [ne][8], or [ne][4] for quadrilaterals, int64); either pointer may be NULL.  Host
- * call. */
+ * [ne][8] in the usual hexahedron vertex order, or [ne][4] counter-clockwise for
+ * quadrilaterals, int64) of a mesh ("Meshes"), sized by pafem_mesh_info; either
+ * pointer may be NULL.  Caller-owned host memory.  Host call.  Errors: EINVAL (null
+ * mesh). */
 pafem_status pafem_mesh_vertices(pafem_mesh mesh, double* xyz, int64_t* elems);
 void pafem_mesh_destroy(pafem_mesh mesh);
 
